@@ -1,0 +1,135 @@
+"""Seeded synthetic input generators shared by the tests and the benchmark.
+
+This module only draws random numbers and lays them out as plain dicts; it
+holds none of the method's arithmetic (no kinematics, dynamics, costs or
+weighting).  Quantities that need the robot model (target poses from a goal
+configuration, wall placement, the initial gravity-compensating nominal and
+the arm acceptance test) are computed once by ``tests/golden/make_workloads.py``
+with the CPU oracle and stored in ``tests/golden/workloads.json``; ``load``
+reads that file.
+
+Arm family (a stand-in for the 7-DoF arm of the paper, whose parameters are
+not published): a serial chain of 7 revolute joints about local z; joint 1
+vertical, every later joint frame turned by Rx(+-pi/2); link lengths
+U[0.1, 0.4] m with a lateral offset U[-0.1, 0.1] m; masses U[0.5, 4] kg;
+CoM near the link axis at 0.3-0.7 of its length; inertia of a solid box
+(extents U[0.04, 0.1] x U[0.04, 0.1] x length) turned by a random rotation
+(positive definite and satisfying the triangle inequality by construction);
+armature U[0.02, 0.1] kg m^2; limits q in [-2.8, 2.8] rad, |qd| <= 2.5
+rad/s, |tau| <= 87 N m (joints 1-4) / 12 N m (joints 5-7).
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+from scipy.spatial.transform import Rotation
+
+NJ = 7
+TAU_MAX = [87.0, 87.0, 87.0, 87.0, 12.0, 12.0, 12.0]
+WORKLOADS_JSON = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                              "tests", "golden", "workloads.json")
+
+_RX_PLUS = [[1.0, 0.0, 0.0], [0.0, 0.0, -1.0], [0.0, 1.0, 0.0]]
+_RX_MINUS = [[1.0, 0.0, 0.0], [0.0, 0.0, 1.0], [0.0, -1.0, 0.0]]
+_EYE = [[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]
+
+
+def draw_arm(seed: int, n: int = NJ) -> dict:
+    """Random arm parameters (see module docstring)."""
+    rng = np.random.default_rng(seed)
+    lengths = rng.uniform(0.1, 0.4, size=n)
+    links = []
+    for i in range(n):
+        if i == 0:
+            R_parent = _EYE
+            r_parent = [0.0, 0.0, float(rng.uniform(0.1, 0.3))]
+        else:
+            R_parent = _RX_PLUS if rng.integers(0, 2) else _RX_MINUS
+            r_parent = [float(rng.uniform(-0.1, 0.1)), 0.0, float(lengths[i - 1])]
+        L = float(lengths[i])
+        m = float(rng.uniform(0.5, 4.0))
+        com = [float(rng.uniform(-0.02, 0.02)), float(rng.uniform(-0.02, 0.02)),
+               float(rng.uniform(0.3, 0.7) * L)]
+        bx, by = rng.uniform(0.04, 0.1, size=2)
+        principal = np.diag([m / 12.0 * (by * by + L * L),
+                             m / 12.0 * (bx * bx + L * L),
+                             m / 12.0 * (bx * bx + by * by)])
+        Rc = Rotation.random(random_state=rng).as_matrix()
+        I = Rc @ principal @ Rc.T
+        links.append({
+            "R_parent": [list(map(float, r)) for r in R_parent],
+            "r_parent": r_parent,
+            "mass": m,
+            "com": com,
+            "inertia": [float(I[0, 0]), float(I[1, 1]), float(I[2, 2]),
+                        float(I[0, 1]), float(I[0, 2]), float(I[1, 2])],
+            "armature": float(rng.uniform(0.02, 0.1)),
+            "q_min": -2.8, "q_max": 2.8, "qd_max": 2.5,
+            "tau_max": TAU_MAX[i] if n == NJ else 87.0,
+        })
+    return {"n": n, "links": links, "R_ee": _EYE, "r_ee": [0.0, 0.0, 0.1],
+            "gravity": [0.0, 0.0, -9.81]}
+
+
+def draw_state(seed: int, n: int = NJ):
+    """q0 ~ U[-1, 1]^n, qd0 = 0, goal configuration q0 + U[-0.5, 0.5]^n."""
+    rng = np.random.default_rng(seed)
+    q0 = rng.uniform(-1.0, 1.0, size=n)
+    q_goal = q0 + rng.uniform(-0.5, 0.5, size=n)
+    return q0.tolist(), [0.0] * n, q_goal.tolist()
+
+
+def draw_wall(seed: int):
+    """Wall normal among +-x, +-y and its standoff U[0.02, 0.05] m."""
+    rng = np.random.default_rng(seed)
+    axis = int(rng.integers(0, 2))
+    sign = 1.0 if rng.integers(0, 2) else -1.0
+    normal = [0.0, 0.0, 0.0]
+    normal[axis] = sign
+    return normal, axis, float(rng.uniform(0.02, 0.05))
+
+
+def draw_horizon(seed: int, count: int):
+    """Batched problems: K ~ U{512..8192}, T ~ U{10..50}."""
+    rng = np.random.default_rng(seed)
+    K = rng.integers(512, 8193, size=count)
+    T = rng.integers(10, 51, size=count)
+    return K.tolist(), T.tolist()
+
+
+def position_cost(K: int, T: int, dt: float = 0.01, lam: float = 1.0) -> dict:
+    """Plain position task: W_pos = 1e3 I, joint-limit (1e4) and
+    torque-limit (10) penalties, terminal weight 1, sigma = 2 N m."""
+    return {
+        "K": K, "T": T, "dt": dt, "lambda": lam, "sigma": [2.0] * NJ,
+        "W_pos": [1e3, 1e3, 1e3], "W_ori": [0.0] * 3,
+        "W_force": [0.0] * 6, "W_reg": [0.0] * 6,
+        "w_q": 1e4, "w_qd": 0.0, "w_tau": 10.0, "w_post": 0.0,
+        "q_rest": [0.0] * NJ, "w_terminal": 1.0, "force_mode": 0,
+        "ext_mode": 0, "F_ext": [0.0] * 6, "wall_n": [0.0, 0.0, 0.0],
+        "wall_d0": 0.0, "wall_k": 0.0, "wall_c": 0.0,
+    }
+
+
+def wall_cost(K: int, T: int, normal, axis: int, d0: float, dt: float = 0.01,
+              lam: float = 1.0) -> dict:
+    """Contact task against a planar wall: W_pos = 1e3 on the two axes
+    tangent to the wall, W_ori = 1e2, W_force = 0.1 on the normal force
+    axis, W_reg = W_force / 30 on all six, spring 2000 N/m, damper 20 N s/m."""
+    c = position_cost(K, T, dt, lam)
+    W_pos = [1e3, 1e3, 1e3]
+    W_pos[axis] = 0.0
+    W_force = [0.0] * 6
+    W_force[axis] = 0.1
+    c.update({"W_pos": W_pos, "W_ori": [1e2] * 3, "W_force": W_force,
+              "W_reg": [0.1 / 30.0] * 6, "ext_mode": 2, "wall_n": list(normal),
+              "wall_d0": float(d0), "wall_k": 2000.0, "wall_c": 20.0})
+    return c
+
+
+def load(path: str = WORKLOADS_JSON) -> dict:
+    """Stored workloads (written by tests/golden/make_workloads.py)."""
+    with open(path) as f:
+        return json.load(f)

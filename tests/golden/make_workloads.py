@@ -1,0 +1,96 @@
+"""Write tests/golden/workloads.json: the seeded synthetic workloads.
+
+Calls only the seeded generators (paper_2609_02020_amd.inputs) and the CPU
+oracle (oracle/).  Run from the repository root:
+
+    python tests/golden/make_workloads.py
+
+Recipe (all seeds fixed):
+  * arm i: draw_arm(1000 + i + 100000 a), state: draw_state(2000 + i +
+    100000 a) for the first attempt a that passes the acceptance test:
+    |g_j(q)| <= 0.6 tau_max,j at q0 and at the goal configuration and
+    sigma_min(J(q0)) >= 0.05 (no singular start).
+  * target pose = FK(q_goal); wall (contact cases): normal among +-x/+-y,
+    plane 0.02-0.05 m beyond the initial EE point along -n, desired force
+    10 N into the wall (F_des = -10 n).
+  * initial nominal U_nom[t] = g(q0) for every step (gravity compensation).
+  * Philox key = 3000 + case index (single updates) / episode.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+import numpy as np
+from scipy.spatial.transform import Rotation
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as ora  # noqa: E402
+from paper_2609_02020_amd import inputs  # noqa: E402
+
+
+def accepted_case(index: int, arm_base: int = 1000, state_base: int = 2000):
+    for attempt in range(50):
+        arm = inputs.draw_arm(arm_base + index + 100000 * attempt)
+        q0, qd0, qg = inputs.draw_state(state_base + index + 100000 * attempt)
+        lim = np.array([L["tau_max"] for L in arm["links"]])
+        g0 = ora.bias_jacobian(arm, q0, np.zeros(7))
+        g1 = ora.bias_jacobian(arm, qg, np.zeros(7))
+        smin = np.linalg.svd(ora.ee_jacobian(arm, q0), compute_uv=False).min()
+        if (np.abs(g0) <= 0.6 * lim).all() and (np.abs(g1) <= 0.6 * lim).all() and smin >= 0.05:
+            return arm, q0, qd0, qg
+    raise RuntimeError("no acceptable arm for case %d" % index)
+
+
+def target_of(arm, q_goal, F_des=None):
+    _, _, pe, Re = ora.fk(arm, q_goal)
+    x, y, z, w = Rotation.from_matrix(Re).as_quat()
+    return {"p_des": pe.tolist(), "quat_des": [float(w), float(x), float(y), float(z)],
+            "F_des": list(F_des) if F_des is not None else [0.0] * 6}
+
+
+def make_case(index, kind, K, T, dt, lam, seed, arm_base=1000, state_base=2000,
+              wall_seed=None):
+    arm, q0, qd0, qg = accepted_case(index, arm_base, state_base)
+    g0 = ora.bias_jacobian(arm, q0, np.zeros(7))
+    if kind == "position":
+        cost = inputs.position_cost(K, T, dt, lam)
+        target = target_of(arm, qg)
+    else:
+        normal, axis, standoff = inputs.draw_wall(wall_seed if wall_seed is not None else 7000 + index)
+        _, _, pe0, _ = ora.fk(arm, q0)
+        d0 = float(np.dot(normal, pe0) - standoff)
+        cost = inputs.wall_cost(K, T, normal, axis, d0, dt, lam)
+        F_des = [-10.0 * n for n in normal] + [0.0, 0.0, 0.0]
+        target = target_of(arm, qg, F_des)
+    U_nom = np.tile(g0, (T, 1))
+    return {"kind": kind, "robot": arm, "cost": cost, "target": target,
+            "q0": list(map(float, q0)), "qd0": list(map(float, qd0)),
+            "q_goal": list(map(float, qg)), "U_nom": U_nom.tolist(),
+            "seed": int(seed), "tick": 0}
+
+
+def main():
+    out = {"recipe": __doc__.strip().splitlines()[0]}
+    # single update, position cost, K=256, T=18, dt=0.01, lambda=1 (FP64 case)
+    out["single_k256"] = [make_case(i, "position", 256, 18, 0.01, 1.0, 3000 + i) for i in range(20)]
+    # closed loop with a wall, K=4096, T=18, dt=0.01, lambda=1 (FP32 case)
+    out["wall_k4096"] = [make_case(100 + e, "wall", 4096, 18, 0.01, 1.0, 3000 + e) for e in range(10)]
+    # precision study: K=16384, T=36, dt=0.005, lambda in {0.01, 0.1, 1}
+    out["precision_k16384"] = [make_case(100, "wall", 16384, 36, 0.005, lam, 3100 + i)
+                               for i, lam in enumerate((0.01, 0.1, 1.0))]
+    # batched: 64 problems, K ~ U{512..8192}, T ~ U{10..50}, half position / half wall
+    Ks, Ts = inputs.draw_horizon(4000, 64)
+    out["batch64"] = [make_case(200 + i, "position" if i % 2 == 0 else "wall", Ks[i], Ts[i],
+                                0.01, 1.0, 3200 + i) for i in range(64)]
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "workloads.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=None, separators=(",", ":"))
+    print("wrote", path, os.path.getsize(path), "bytes")
+
+
+if __name__ == "__main__":
+    main()

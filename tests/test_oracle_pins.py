@@ -1,0 +1,543 @@
+"""Pins of the FP64 CPU oracle against facts fixed outside it.
+
+Each test ties one part of the oracle to something it cannot agree with by
+construction: closed forms, a symbolic Lagrangian, an independent library,
+published known-answer vectors, invariants of Eq. (4), or a hand-written
+recurrence.  CPU only.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+from scipy import stats
+
+from paper_2609_02020_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+I3 = [[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]
+RX90 = [[1.0, 0.0, 0.0], [0.0, 0.0, -1.0], [0.0, 1.0, 0.0]]
+
+
+def link(R_parent, r_parent, mass, com, inertia, armature=0.0, tau_max=87.0):
+    return {"R_parent": R_parent, "r_parent": r_parent, "mass": mass, "com": com,
+            "inertia": inertia, "armature": armature, "q_min": -2.8, "q_max": 2.8,
+            "qd_max": 2.5, "tau_max": tau_max}
+
+
+def pendulum(m=1.7, com=(0.31, 0.05, 0.02), inertia=(0.02, 0.03, 0.04, 0.001, -0.002, 0.003),
+             armature=0.05, g=9.81):
+    """One link whose joint axis is horizontal (world -y)."""
+    return {"n": 1, "links": [link(RX90, [0.0, 0.0, 0.0], m, list(com), list(inertia), armature)],
+            "R_ee": I3, "r_ee": [0.5, 0.0, 0.0], "gravity": [0.0, 0.0, -g]}
+
+
+def planar2(l1=0.45, m=(2.0, 1.3), com1=(0.2, 0.03, 0.01), com2=(0.17, -0.02, 0.04),
+            I1=(0.05, 0.06, 0.07, 0.002, 0.003, -0.001), I2=(0.03, 0.02, 0.025, -0.001, 0.002, 0.001),
+            arm=(0.04, 0.02), g=9.81):
+    """Two parallel z joints, gravity in the plane of motion (-y)."""
+    return {"n": 2, "links": [link(I3, [0.0, 0.0, 0.0], m[0], list(com1), list(I1), arm[0]),
+                              link(I3, [l1, 0.0, 0.0], m[1], list(com2), list(I2), arm[1])],
+            "R_ee": I3, "r_ee": [0.3, 0.0, 0.0], "gravity": [0.0, -g, 0.0]}
+
+
+def arm7(i=0):
+    return inputs.draw_arm(1000 + i)
+
+
+# ---------------------------------------------------------------------------
+# noise: Philox4x32-10 and Box-Muller
+# ---------------------------------------------------------------------------
+def test_philox_known_answers(ora):
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        rows = [r.split() for r in f if r.strip() and not r.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        w = [int(x, 16) for x in r]
+        assert ora.philox4x32_10(w[0:4], w[4:6]) == w[6:10]
+
+
+def test_philox_matches_rocrand_host(ora, tmp_path):
+    hdr = "/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"
+    if not os.path.exists(hdr) or shutil.which("g++") is None:
+        pytest.skip("rocRAND header or g++ not available")
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "philox_rocrand.cpp")
+    exe = str(tmp_path / "philox_rocrand")
+    subprocess.run(["g++", "-O1", "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__", src, "-o", exe],
+                   check=True)
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        w = rng.integers(0, 2**32, size=6, dtype=np.uint64).tolist()
+        out = subprocess.run([exe] + ["%x" % x for x in w], check=True, capture_output=True,
+                             text=True).stdout.split()
+        assert ora.philox4x32_10(w[0:4], w[4:6]) == [int(x, 16) for x in out]
+
+
+def test_philox_avalanche(ora):
+    rng = np.random.default_rng(6)
+    flips = []
+    for _ in range(200):
+        ctr = rng.integers(0, 2**32, size=4, dtype=np.uint64).tolist()
+        key = rng.integers(0, 2**32, size=2, dtype=np.uint64).tolist()
+        a = ora.philox4x32_10(ctr, key)
+        bit = int(rng.integers(0, 128))
+        ctr2 = list(ctr)
+        ctr2[bit // 32] ^= 1 << (bit % 32)
+        b = ora.philox4x32_10(ctr2, key)
+        flips.append(sum(bin(x ^ y).count("1") for x, y in zip(a, b)))
+    assert abs(np.mean(flips) - 64) < 2.0
+
+
+def test_normals_box_muller_closed_form(ora):
+    seed, tick, k, t = 0x1234_5678_9ABC, 77, 5, 3
+    z = ora.normals(seed, tick, k, t)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for call in range(2):
+        x = ora.philox4x32_10([call, t, k, tick & 0xFFFFFFFF], key)
+        for pr in range(2):
+            ua = (x[2 * pr] + 1) / 2.0**32
+            ub = x[2 * pr + 1] / 2.0**32
+            r = math.sqrt(-2 * math.log(ua))
+            assert z[call * 4 + 2 * pr] == pytest.approx(r * math.cos(2 * math.pi * ub), abs=1e-14)
+            assert z[call * 4 + 2 * pr + 1] == pytest.approx(r * math.sin(2 * math.pi * ub), abs=1e-14)
+
+
+def test_normals_distribution(ora):
+    zs = np.concatenate([ora.normals(99, tick, k, t)
+                         for tick in range(2) for k in range(250) for t in range(40)])
+    assert zs.size == 160000
+    assert abs(zs.mean()) < 0.01
+    assert abs(zs.var() - 1) < 0.015
+    assert stats.kstest(zs, "norm").pvalue > 1e-3
+    # counters are distinct streams: different k, t, tick give different draws
+    assert not np.allclose(ora.normals(1, 0, 0, 0), ora.normals(1, 0, 1, 0))
+    assert not np.allclose(ora.normals(1, 0, 0, 0), ora.normals(1, 1, 0, 0))
+    assert not np.allclose(ora.normals(1, 0, 0, 0), ora.normals(2, 0, 0, 0))
+
+
+# ---------------------------------------------------------------------------
+# kinematics
+# ---------------------------------------------------------------------------
+def test_fk_planar_closed_form(ora):
+    rb = planar2()
+    for th in [(0.3, -0.7), (1.2, 2.0), (-2.5, 0.4)]:
+        _, p, pe, Re = ora.fk(rb, th)
+        l1, le = 0.45, 0.3
+        a, b = th[0], th[0] + th[1]
+        assert np.allclose(p[1], [l1 * math.cos(a), l1 * math.sin(a), 0], atol=1e-14)
+        assert np.allclose(pe, [l1 * math.cos(a) + le * math.cos(b),
+                                l1 * math.sin(a) + le * math.sin(b), 0], atol=1e-14)
+        assert np.allclose(Re, Rotation.from_euler("z", b).as_matrix(), atol=1e-14)
+
+
+def test_jacobian_matches_finite_differences(ora):
+    rb = arm7(3)
+    q = np.random.default_rng(1).uniform(-1, 1, 7)
+    J = ora.ee_jacobian(rb, q)
+    h = 1e-6
+    for j in range(7):
+        dq = np.zeros(7); dq[j] = h
+        _, _, pp, Rp = ora.fk(rb, q + dq)
+        _, _, pm, Rm = ora.fk(rb, q - dq)
+        assert np.allclose(J[:3, j], (pp - pm) / (2 * h), atol=1e-8)
+        # angular column: vee of dR R^T
+        dR = (Rp - Rm) / (2 * h)
+        _, _, _, R0 = ora.fk(rb, q)
+        W = dR @ R0.T
+        assert np.allclose(J[3:, j], [W[2, 1], W[0, 2], W[1, 0]], atol=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# mass matrix and bias
+# ---------------------------------------------------------------------------
+def test_mass_matrix_three_way_and_spd(ora):
+    for i in range(4):
+        rb = arm7(i)
+        q = np.random.default_rng(10 + i).uniform(-2, 2, 7)
+        M8 = ora.mass_jacobian_sum(rb, q)
+        Mc = ora.crba(rb, q)
+        z = np.zeros(7)
+        Mr = np.stack([ora.rnea(rb, q, z, e) - ora.rnea(rb, q, z, z) for e in np.eye(7)], axis=1)
+        assert np.abs(M8 - Mc).max() < 1e-10
+        assert np.abs(M8 - Mr).max() < 1e-10
+        assert np.abs(M8 - M8.T).max() < 1e-12
+        assert np.linalg.eigvalsh(M8).min() > 0
+
+
+def test_pendulum_closed_form(ora):
+    m, com, arm, g = 1.7, (0.31, 0.05, 0.02), 0.05, 9.81
+    Izz = 0.04
+    rb = pendulum()
+    for th in [0.0, 0.4, -1.3, 2.9]:
+        M = ora.mass_jacobian_sum(rb, [th])
+        assert M[0, 0] == pytest.approx(Izz + m * (com[0] ** 2 + com[1] ** 2) + arm, rel=1e-13)
+        h = ora.bias_jacobian(rb, [th], [0.7])  # no Coriolis for one joint
+        hc = m * g * (com[0] * math.cos(th) - com[1] * math.sin(th))
+        assert h[0] == pytest.approx(hc, rel=1e-12, abs=1e-13)
+        qdd = ora.aba(rb, [th], [0.7], [1.5])
+        assert qdd[0] == pytest.approx((1.5 - hc) / M[0, 0], rel=1e-12)
+
+
+def _planar2_sympy():
+    import sympy as sp
+    t1, t2, d1, d2 = sp.symbols("t1 t2 d1 d2")
+    l1, g = sp.Rational(45, 100), sp.Float(9.81)
+    m1, m2 = sp.Float(2.0), sp.Float(1.3)
+    c1 = sp.Matrix([0.2, 0.03, 0.01])
+    c2 = sp.Matrix([0.17, -0.02, 0.04])
+    Izz1, Izz2, a1, a2 = sp.Float(0.07), sp.Float(0.025), sp.Float(0.04), sp.Float(0.02)
+
+    def rz(a):
+        return sp.Matrix([[sp.cos(a), -sp.sin(a), 0], [sp.sin(a), sp.cos(a), 0], [0, 0, 1]])
+
+    q = sp.Matrix([t1, t2])
+    qd = sp.Matrix([d1, d2])
+    p1 = rz(t1) * c1
+    o2 = rz(t1) * sp.Matrix([l1, 0, 0])
+    p2 = o2 + rz(t1 + t2) * c2
+    v1 = p1.jacobian(q) * qd
+    v2 = p2.jacobian(q) * qd
+    T = (m1 * v1.dot(v1) + m2 * v2.dot(v2) + Izz1 * d1 ** 2 + Izz2 * (d1 + d2) ** 2
+         + a1 * d1 ** 2 + a2 * d2 ** 2) / 2
+    V = g * (m1 * p1[1] + m2 * p2[1])
+    L = T - V
+    pmom = sp.Matrix([sp.diff(L, d1), sp.diff(L, d2)])
+    M = pmom.jacobian(qd)
+    h = pmom.jacobian(q) * qd - sp.Matrix([sp.diff(L, t1), sp.diff(L, t2)])
+    return sp.lambdify((t1, t2, d1, d2), M), sp.lambdify((t1, t2, d1, d2), h)
+
+
+def test_two_link_matches_symbolic_lagrangian(ora):
+    Mf, hf = _planar2_sympy()
+    rb = planar2()
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        th = rng.uniform(-3, 3, 2)
+        thd = rng.uniform(-2, 2, 2)
+        Ms = np.array(Mf(*th, *thd), dtype=float)
+        hs = np.array(hf(*th, *thd), dtype=float).ravel()
+        assert np.allclose(ora.mass_jacobian_sum(rb, th), Ms, atol=1e-12)
+        assert np.allclose(ora.bias_jacobian(rb, th, thd), hs, atol=1e-12)
+        assert np.allclose(ora.crba(rb, th), Ms, atol=1e-12)
+        assert np.allclose(ora.rnea(rb, th, thd, [0, 0]), hs, atol=1e-12)
+
+
+def test_bias_jacobian_form_equals_rnea(ora):
+    for i in range(4):
+        rb = arm7(i)
+        rng = np.random.default_rng(20 + i)
+        q, qd = rng.uniform(-2, 2, 7), rng.uniform(-2, 2, 7)
+        assert np.abs(ora.bias_jacobian(rb, q, qd) - ora.rnea(rb, q, qd, np.zeros(7))).max() < 1e-10
+
+
+def test_coriolis_skew_symmetry(ora):
+    """qd^T (Mdot - 2 C) qd = 0 with C qd = h(q, qd) - g(q)."""
+    rb = arm7(5)
+    rng = np.random.default_rng(3)
+    q, qd = rng.uniform(-2, 2, 7), rng.uniform(-2, 2, 7)
+    eps = 1e-6
+    Mdot = (ora.mass_jacobian_sum(rb, q + eps * qd) - ora.mass_jacobian_sum(rb, q - eps * qd)) / (2 * eps)
+    Cqd = ora.bias_jacobian(rb, q, qd) - ora.bias_jacobian(rb, q, np.zeros(7))
+    assert abs(qd @ Mdot @ qd - 2 * qd @ Cqd) < 1e-6 * (1 + abs(qd @ Mdot @ qd))
+
+
+# ---------------------------------------------------------------------------
+# forward dynamics
+# ---------------------------------------------------------------------------
+def test_aba_rnea_round_trip(ora):
+    for i in range(5):
+        rb = arm7(i)
+        rng = np.random.default_rng(30 + i)
+        q, qd, qdd = rng.uniform(-2, 2, 7), rng.uniform(-2, 2, 7), rng.uniform(-5, 5, 7)
+        f = rng.normal(size=6) * 5
+        tau = ora.rnea(rb, q, qd, qdd, f)
+        assert np.abs(ora.aba(rb, q, qd, tau, f) - qdd).max() < 1e-10
+        assert np.abs(ora.forward_dynamics(rb, q, qd, tau, f) - qdd).max() < 1e-10
+        # external wrench enters as J^T F (Sec. III-A)
+        J = ora.ee_jacobian(rb, q)
+        assert np.abs(ora.rnea(rb, q, qd, qdd) - tau - J.T @ f).max() < 1e-10
+
+
+def test_pendulum_semi_implicit_recurrence(ora):
+    """The plant's integrator is Eq. (7) as written: qd first, then q with
+    the new qd; matched to a hand-written recurrence on the closed form."""
+    rb = pendulum()
+    m, com, arm, g, Izz = 1.7, (0.31, 0.05, 0.02), 0.05, 9.81, 0.04
+    Mc = Izz + m * (com[0] ** 2 + com[1] ** 2) + arm
+    cost = inputs.position_cost(1, 1)
+    th, thd, tau, h = 0.3, -0.2, 0.8, 1e-3
+    q, qd = [th], [thd]
+    for _ in range(50):
+        q, qd = ora.plant_step(rb, cost, q, qd, [tau], h, 1)
+        acc = (tau - m * g * (com[0] * math.cos(th) - com[1] * math.sin(th))) / Mc
+        thd = thd + acc * h
+        th = th + thd * h
+    assert q[0] == pytest.approx(th, abs=1e-13)
+    assert qd[0] == pytest.approx(thd, abs=1e-13)
+
+
+def _energy_run(ora, rb, steps, h, semi_implicit):
+    q = np.array([0.3, -0.5, 0.8, 0.2, -0.4, 0.6, 0.1])[: rb["n"]]
+    qd = np.zeros(rb["n"])
+    e0 = ora.energy(rb, q, qd)
+    errs = []
+    for s in range(steps):
+        a = ora.forward_dynamics(rb, q, qd, np.zeros(rb["n"]))
+        if semi_implicit:
+            qd = qd + a * h
+            q = q + qd * h
+        else:
+            q, qd = q + qd * h, qd + a * h
+        if s % 50 == 0:
+            errs.append(ora.energy(rb, q, qd) - e0)
+    return np.array(errs)
+
+
+def test_energy_drift_bounded_semi_implicit(ora):
+    rb = planar2()
+    kin_scale = 9.81 * (2.0 + 1.3) * 0.6  # potential swing of the arm [J]
+    err = _energy_run(ora, rb, 10000, 1e-3, True)
+    assert np.abs(err).max() < 1e-2 * kin_scale
+    half = len(err) // 2
+    assert np.abs(err[half:]).max() < 2.0 * np.abs(err[:half]).max() + 1e-3 * kin_scale
+    # the discriminating power: explicit Euler drifts off on the same run
+    err_explicit = _energy_run(ora, rb, 10000, 1e-3, False)
+    assert np.abs(err_explicit).max() > 5 * np.abs(err).max()
+
+
+def test_plant_holds_rest_under_gravity_compensation(ora):
+    rb = arm7(1)
+    q0 = np.array([0.2, -0.3, 0.4, -0.5, 0.6, -0.2, 0.1])
+    g = ora.bias_jacobian(rb, q0, np.zeros(7))
+    cost = inputs.position_cost(1, 1)
+    q, qd = q0.copy(), np.zeros(7)
+    for _ in range(20):
+        q, qd = ora.plant_step(rb, cost, q, qd, g, 0.01, 10)
+    assert np.abs(q - q0).max() < 1e-12 and np.abs(qd).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# task space: log map, force estimate, wall
+# ---------------------------------------------------------------------------
+def test_so3_log_against_scipy(ora):
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        r = Rotation.random(random_state=rng)
+        rho = ora.so3_log(r.as_matrix())
+        assert np.allclose(rho, r.as_rotvec(), atol=1e-10)
+    for ang in [1e-9, 1e-5, 0.3, math.pi - 1e-4, math.pi - 1e-9, math.pi]:
+        axis = np.array([0.3, -0.5, 0.8]); axis /= np.linalg.norm(axis)
+        rho = ora.so3_log(Rotation.from_rotvec(ang * axis).as_matrix())
+        assert rho @ rho == pytest.approx(ang * ang, rel=1e-6, abs=1e-20)
+        if ang < 3.0:
+            assert np.allclose(rho, ang * axis, rtol=1e-6, atol=1e-15)
+    assert np.allclose(ora.so3_log(np.eye(3)), 0)
+
+
+def test_quat_to_R(ora):
+    rng = np.random.default_rng(8)
+    for _ in range(10):
+        r = Rotation.random(random_state=rng)
+        x, y, z, w = r.as_quat()
+        assert np.allclose(ora.quat_to_R([2 * w, 2 * x, 2 * y, 2 * z]), r.as_matrix(), atol=1e-14)
+
+
+def test_force_estimate_recovers_wrench_and_ignores_null_space(ora):
+    rb = arm7(2)
+    rng = np.random.default_rng(5)
+    q = rng.uniform(-1, 1, 7)
+    J = ora.ee_jacobian(rb, q)
+    F = rng.normal(size=6) * 10
+    assert np.allclose(ora.force_estimate(rb, q, J.T @ F), F, atol=1e-9)
+    M = ora.mass_jacobian_sum(rb, q)
+    Minv = np.linalg.inv(M)
+    Jbar = Minv @ J.T @ np.linalg.inv(J @ Minv @ J.T)
+    tau0 = rng.normal(size=7) * 5
+    tau_null = (np.eye(7) - J.T @ Jbar.T) @ tau0
+    assert np.abs(ora.force_estimate(rb, q, tau_null)).max() < 1e-9
+    assert np.abs(ora.force_estimate(rb, q, tau0) - Jbar.T @ tau0).max() < 1e-9
+
+
+def test_force_cost_reading(ora):
+    """tau_F = v - g(q): with v = g(q) + J^T F the force term sees F."""
+    case = inputs.load()["wall_k4096"][0]
+    rb, cost, tg = case["robot"], dict(case["cost"]), case["target"]
+    q = np.array(case["q0"])
+    J = ora.ee_jacobian(rb, q)
+    g = ora.bias_jacobian(rb, q, np.zeros(7))
+    F = np.array([3.0, -2.0, 5.0, 0.1, 0.2, -0.3])
+    _, parts = ora.running_cost(rb, cost, tg, q, np.zeros(7), g + J.T @ F)
+    Wf, Wr, Fd = np.array(cost["W_force"]), np.array(cost["W_reg"]), np.array(tg["F_des"])
+    assert parts["force"] == pytest.approx(np.sum(Wf * (Fd - F) ** 2 + Wr * F ** 2), rel=1e-9)
+    cost["force_mode"] = 1  # literal reading tau_F = v
+    _, parts1 = ora.running_cost(rb, cost, tg, q, np.zeros(7), J.T @ F)
+    assert parts1["force"] == pytest.approx(parts["force"], rel=1e-9)
+
+
+def test_wall_force(ora):
+    cost = inputs.wall_cost(1, 1, [0.0, -1.0, 0.0], 1, 0.2)
+    # outside the wall (n.p > d0 means no penetration): no force
+    assert np.allclose(ora.wall_force(cost, [0, -0.3, 0.5], [0, 0, 0]), 0)
+    # static penetration: p_y = 0.25 gives n.p = -0.25, delta = 0.45, F = k delta n
+    F = ora.wall_force(cost, [0, 0.25, 0.5], [0, 0, 0])
+    assert np.allclose(F, [0, -2000 * 0.45, 0])
+    # moving into the wall adds damping: delta = 0.01, d(delta)/dt = 0.5
+    assert np.allclose(ora.wall_force(cost, [0, -0.19, 0.5], [0, 0.5, 0]), [0, -(20 + 10), 0])
+    # pulling out faster than the spring pushes: clamped at zero, never pulls
+    assert np.allclose(ora.wall_force(cost, [0, -0.19, 0.5], [0, -10.0, 0]), 0)
+
+
+def test_joint_and_torque_penalties(ora):
+    rb = arm7(0)
+    cost = inputs.position_cost(1, 1)
+    cost["W_pos"] = [0.0] * 3
+    cost["w_qd"] = 3.0
+    tg = {"p_des": [0, 0, 0]}
+    q = np.array([2.9, -3.0, 0, 0, 0, 0, 0.5])
+    qd = np.array([0, 2.7, 0, 0, 0, 0, -3.0])
+    v = np.array([90.0, 0, 0, 0, -13.0, 0, 0])
+    _, parts = ora.running_cost(rb, cost, tg, q, qd, v)
+    assert parts["joint"] == pytest.approx(1e4 * (0.1 ** 2 + 0.2 ** 2) + 3.0 * (0.2 ** 2 + 0.5 ** 2))
+    assert parts["torque"] == pytest.approx(10.0 * (3.0 ** 2 + 1.0 ** 2))
+    assert parts["pos"] == 0 and parts["ori"] == 0 and parts["force"] == 0
+
+
+# ---------------------------------------------------------------------------
+# rollout and Eq. (4)
+# ---------------------------------------------------------------------------
+def test_rollout_pendulum_hand_recurrence(ora):
+    """Cost of one rollout = sum of the running cost at the pre-step states
+    plus the terminal cost, with Eq. (7) as the recurrence (no noise)."""
+    rb = pendulum()
+    m, com, arm, g, Izz = 1.7, (0.31, 0.05, 0.02), 0.05, 9.81, 0.04
+    Mc = Izz + m * (com[0] ** 2 + com[1] ** 2) + arm
+    T, dt = 12, 0.01
+    cost = inputs.position_cost(1, T, dt)
+    cost.update({"sigma": [0.0] * 7, "w_q": 0.0, "w_tau": 0.0, "w_terminal": 2.5,
+                 "W_pos": [1.0, 3.0, 7.0]})
+    tg = {"p_des": [0.1, 0.05, -0.2]}
+    U = np.linspace(-1.0, 2.0, T).reshape(T, 1)
+    S, noise = ora.rollout(rb, cost, tg, [0.4], [0.3], U, 7, 0, 0)
+    assert np.all(noise == 0)
+
+    def pos_cost(th):
+        # EE at (0.5, 0, 0) in the link frame; link frame = Rx(90) Rz(th)
+        p = np.array([0.5 * math.cos(th), 0.0, 0.5 * math.sin(th)])
+        e = np.array(tg["p_des"]) - p
+        return float(np.sum(np.array([1.0, 3.0, 7.0]) * e * e))
+
+    th, thd, ref = 0.4, 0.3, 0.0
+    for t in range(T):
+        ref += pos_cost(th)
+        acc = (U[t, 0] - m * g * (com[0] * math.cos(th) - com[1] * math.sin(th))) / Mc
+        thd += acc * dt
+        th += thd * dt
+    ref += 2.5 * pos_cost(th)
+    assert S == pytest.approx(ref, rel=1e-12)
+
+
+def test_rollout_composes_step_functions(ora, workloads):
+    case = workloads["wall_k4096"][1]
+    rb, cost, tg = case["robot"], case["cost"], case["target"]
+    U = np.array(case["U_nom"])
+    k = 17
+    S, noise = ora.rollout(rb, cost, tg, case["q0"], case["qd0"], U, case["seed"], 5, k)
+    q, qd = np.array(case["q0"]), np.array(case["qd0"])
+    ref = 0.0
+    for t in range(cost["T"]):
+        dtau = np.array(cost["sigma"]) * ora.normals(case["seed"], 5, k, t)[:7]
+        assert np.allclose(noise[t], dtau, rtol=0, atol=0)
+        v = U[t] + dtau
+        ref += ora.running_cost(rb, cost, tg, q, qd, v)[0]
+        J = ora.ee_jacobian(rb, q)
+        _, _, pe, _ = ora.fk(rb, q)
+        f = np.concatenate([ora.wall_force(cost, pe, J[:3] @ qd), np.zeros(3)])
+        qdd = ora.aba(rb, q, qd, v, f)  # independent route to qdd
+        qd = qd + qdd * cost["dt"]
+        q = q + qd * cost["dt"]
+    ref += ora.terminal_cost(rb, cost, tg, q, qd)
+    assert S == pytest.approx(ref, rel=1e-10)
+
+
+def test_single_sample_returns_its_own_noise(ora, workloads):
+    case = workloads["single_k256"][0]
+    cost = dict(case["cost"], K=1)
+    st, U_new, S, noise = ora.update(case["robot"], cost, case["target"], case["q0"],
+                                     case["qd0"], case["U_nom"], case["seed"], 0)
+    assert st == 0
+    assert np.array_equal(U_new, np.array(case["U_nom"]) + noise[0])
+
+
+def _synthetic(K=64, T=5, n=7, seed=0):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(10, 20, K), rng.normal(size=(K, T, n)), rng.normal(size=(T, n))
+
+
+def test_weights_lambda_limits(ora):
+    S, E, U = _synthetic()
+    st, Un, w = ora.weights_update(S, E, U, 1e-12)
+    assert st == 0
+    assert np.allclose(Un, U + E[np.argmin(S)], atol=1e-14)
+    st, Un, _ = ora.weights_update(S, E, U, 1e12)
+    assert np.allclose(Un, U + E.mean(axis=0), atol=1e-9)
+    # ties at the minimum are averaged as lambda -> 0
+    S2 = S.copy()
+    a, b = 3, 40
+    S2[a] = S2[b] = S.min() - 1.0
+    _, Un, _ = ora.weights_update(S2, E, U, 1e-12)
+    assert np.allclose(Un, U + 0.5 * (E[a] + E[b]), atol=1e-14)
+
+
+def test_weights_invariances(ora):
+    S, E, U = _synthetic(seed=1)
+    lam = 0.7
+    _, U0, w0 = ora.weights_update(S, E, U, lam)
+    _, U1, _ = ora.weights_update(S + 1234.5, E, U, lam)  # shift (Sec. II)
+    assert np.allclose(U0, U1, atol=1e-12)
+    perm = np.random.default_rng(2).permutation(S.size)
+    _, U2, _ = ora.weights_update(S[perm], E[perm], U, lam)
+    assert np.allclose(U0, U2, atol=1e-12)
+    _, U3, _ = ora.weights_update(3.0 * S, E, U, 3.0 * lam)
+    assert np.allclose(U0, U3, atol=1e-12)
+    eta = w0.sum()
+    assert 1.0 <= eta <= S.size and w0.max() == 1.0
+    # the update is the weighted mean of the noise (Eq. 4b)
+    assert np.allclose(U0, U + np.tensordot(w0, E, axes=1) / eta, atol=1e-12)
+
+
+def test_weights_non_finite(ora):
+    S, E, U = _synthetic(seed=3)
+    S[5] = np.nan
+    S[9] = np.inf
+    st, Un, w = ora.weights_update(S, E, U, 1.0)
+    assert st == 0 and w[5] == 0 and w[9] == 0 and np.isfinite(Un).all()
+    st, Un, w = ora.weights_update(np.full(S.size, np.nan), E, U, 1.0)
+    assert st == 2 and np.array_equal(Un, U)
+
+
+def test_update_is_deterministic_and_thread_independent(ora, workloads):
+    case = workloads["single_k256"][2]
+    args = (case["robot"], case["cost"], case["target"], case["q0"], case["qd0"],
+            case["U_nom"], case["seed"], 3)
+    _, Ua, Sa, _ = ora.update(*args, nthreads=1)
+    _, Ub, Sb, _ = ora.update(*args, nthreads=4)
+    assert np.array_equal(Ua, Ub) and np.array_equal(Sa, Sb)
+
+
+def test_orientation_cost_frame(ora):
+    """C_ori uses rho = log(R_des^T R_ee) with a diagonal weight (Eq. 11)."""
+    rb = arm7(4)
+    q = np.random.default_rng(9).uniform(-1, 1, 7)
+    _, _, pe, Re = ora.fk(rb, q)
+    Rd = Rotation.from_rotvec([0.3, -0.2, 0.5])
+    x, y, z, w = Rd.as_quat()
+    cost = inputs.position_cost(1, 1)
+    cost.update({"W_pos": [0.0] * 3, "W_ori": [1.0, 4.0, 9.0], "w_q": 0.0, "w_tau": 0.0})
+    _, parts = ora.running_cost(rb, cost, {"p_des": pe, "quat_des": [w, x, y, z]}, q,
+                                np.zeros(7), np.zeros(7))
+    rho = Rotation.from_matrix(Rd.as_matrix().T @ Re).as_rotvec()
+    assert parts["ori"] == pytest.approx(float(np.sum(np.array([1.0, 4.0, 9.0]) * rho ** 2)), rel=1e-10)
+    assert parts["pos"] == pytest.approx(0.0, abs=1e-25)
