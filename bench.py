@@ -1,0 +1,168 @@
+"""Benchmark: MPPI update rate and ABA rollout steps/s on one MI355X.
+
+A step is one MPPI update of the contact workload (K=4096 samples, T=18
+steps, dt=0.01 s, 7-DoF arm, FP32 rollouts): the rollout kernel (Philox
+noise, articulated-body dynamics, force estimate, cost, Euler) then the
+weighting kernel (minimum shift, exponentiated weights, weighted noise sum,
+shifted warm start), with every input resident in HBM.  Consecutive steps
+chain the warm start (U_nominal <- shifted U_new) and advance the Philox
+tick; the measured state is the one reached after the warm-up ticks of a
+closed loop with the on-device plant.
+
+Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MPPI update rate (Hz) + ABA rollout steps/s, K=4096 T=18 7-DoF, FP32"
+# Floating-point operations of one sample-step and of the per-sample
+# terminal cost in the rollout kernel's own formulation, counted by running
+# its per-sample code with an op-counting scalar (tests/opcount.cpp; add,
+# mul, div, sqrt = 1 flop each, a fused multiply-add = 2).  Contact workload
+# (force estimate, wall, orientation cost on).
+FLOPS_PER_SAMPLE_STEP = 9427
+FLOPS_PER_SAMPLE_TERMINAL = 822
+FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (AMD published)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=300)
+    p.add_argument("--warmup", type=int, default=30)
+    p.add_argument("--workload", default="wall_k4096")
+    p.add_argument("--case", type=int, default=0)
+    p.add_argument("--cpu-seconds", type=float, default=12.0,
+                   help="budget of the oracle CPU-baseline sample")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    return p.parse_args()
+
+
+def cpu_baseline(case, budget_s):
+    """The FP64 CPU oracle, as it stands, on the host cores: full updates of
+    the same workload (same K, T, seeds) until the time budget is used."""
+    from oracle import oracle as ora
+    ora.build()
+    n, t0 = 0, time.perf_counter()
+    while True:
+        ora.update(case["robot"], case["cost"], case["target"], case["q0"], case["qd0"],
+                   case["U_nom"], case["seed"], n, want_noise=False)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 1000:
+            break
+    K, T = case["cost"]["K"], case["cost"]["T"]
+    return {"value": n / el, "unit": "Hz", "cores": ora.max_threads(), "kind": "oracle",
+            "sample": "%d full oracle updates (K=%d, T=%d, FP64, OpenMP over samples) in %.1f s; "
+                      "%.3g sample-steps/s" % (n, K, T, el, n * K * T / el),
+            "cpu": platform.processor() or platform.machine()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2609_02020_amd import binding as B
+    from paper_2609_02020_amd import inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    case = inputs.load()[args.workload][args.case]
+    K, T, dt = case["cost"]["K"], case["cost"]["T"], case["cost"]["dt"]
+    solver = B.Solver(case["robot"], case["cost"], B.FP32)
+    dev = torch.device("cuda:0")
+    f64 = dict(dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    q = torch.tensor(case["q0"], **f64)
+    qd = torch.tensor(case["qd0"], **f64)
+    Ua = torch.tensor(case["U_nom"], **f64)
+    Ub = torch.empty_like(Ua)
+    U_new = torch.empty_like(Ua)
+    io = {"q": q, "qd": qd, "target": torch.tensor(B.target_vector(case["target"]), **f64),
+          "U_nominal": Ua, "U_new": U_new, "U_shift": Ub,
+          "costs": torch.empty(K, dtype=torch.float32, device=dev),
+          "noise": torch.empty(T * 7 * K, dtype=torch.float32, device=dev),
+          "status": torch.zeros(1, dtype=torch.int32, device=dev),
+          "seed": case["seed"], "tick": 0}
+
+    def update(tick, ev=None):
+        io["tick"] = tick
+        if ev is not None:
+            ev[0].record(stream)
+        solver.rollout_async(io, stream)
+        if ev is not None:
+            ev[1].record(stream)
+        solver.weights_async(io, stream)
+        # warm start: the shifted sequence becomes the next nominal
+        io["U_nominal"], io["U_shift"] = io["U_shift"], io["U_nominal"]
+
+    # warm-up: closed loop with the plant (ZOH of u*_0 over dt, 1 ms substeps)
+    for w in range(args.warmup):
+        update(w)
+        solver.plant_step_async(q, qd, U_new[0], dt, max(1, int(round(dt / 1e-3))), stream)
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        update(args.warmup + s, evs[s])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    roll_ms = np.array([a.elapsed_time(b) for a, b in evs])
+    status = int(io["status"].cpu()[0])
+    assert status == B.OK, status
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    rate = args.steps / elapsed
+    roll_s = float(np.mean(roll_ms)) * 1e-3
+    flops = FLOPS_PER_SAMPLE_STEP * K * T + FLOPS_PER_SAMPLE_TERMINAL * K
+    achieved = flops / roll_s / 1e12
+
+    # host-API rate (PCIe round trip: host state in, U_new and costs out)
+    Uh = np.asarray(case["U_nom"], dtype=np.float64)
+    qh, qdh = q.cpu().numpy(), qd.cpu().numpy()
+    for i in range(10):
+        solver.update(qh, qdh, case["target"], Uh, case["seed"], 10**6 + i)
+    n_host, th = 100, time.perf_counter()
+    for i in range(n_host):
+        st, Uh2, _ = solver.update(qh, qdh, case["target"], Uh, case["seed"], 2 * 10**6 + i)
+    host_rate = n_host / (time.perf_counter() - th)
+
+    out = {
+        "metric": METRIC, "value": rate, "unit": "Hz", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "%s[%d]: 7-DoF seeded arm, planar wall contact + force cost, "
+                               "K=%d, T=%d, dt=%g s" % (args.workload, args.case, K, T, dt),
+                   "K": K, "T": T, "dt": dt, "dof": 7, "precision": "fp32 rollouts"},
+        "rollout_steps_per_s": K * T / roll_s,
+        "rollout_kernel_ms": float(np.mean(roll_ms)),
+        "host_api_update_hz": host_rate,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "rollout_kernel<float, force>",
+                     "flops_per_launch": flops},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+    solver.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

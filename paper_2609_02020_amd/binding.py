@@ -1,0 +1,263 @@
+"""Thin Python binding of libmppi.so (the C ABI declared in include/mppi.h).
+
+Argument marshalling only: every step of the update runs in the library's
+HIP kernels.  PyTorch is used for device memory and streams (tensors are
+passed by ``data_ptr()``).  If the compiled library is missing the import
+of a solver fails with an error; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmppi.so")
+NJ = 7
+
+OK, EINVAL, ENONFINITE, ENOMEM, EDEVICE, ENOTSUP = range(6)
+FP32, FP64 = 0, 1
+EXT_NONE, EXT_CONST, EXT_WALL = 0, 1, 2
+
+
+class MppiError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__("%s failed: %s (status %d)" % (what, strerror(status), status))
+        self.status = status
+
+
+class LinkParams(C.Structure):
+    _fields_ = [("R_parent", C.c_double * 9), ("r_parent", C.c_double * 3),
+                ("mass", C.c_double), ("com", C.c_double * 3),
+                ("inertia_com", C.c_double * 6), ("armature", C.c_double),
+                ("q_min", C.c_double), ("q_max", C.c_double),
+                ("qd_max", C.c_double), ("tau_max", C.c_double)]
+
+
+class RobotParams(C.Structure):
+    _fields_ = [("n_joints", C.c_int), ("link", LinkParams * NJ),
+                ("R_ee", C.c_double * 9), ("r_ee", C.c_double * 3),
+                ("gravity", C.c_double * 3)]
+
+
+class CostParams(C.Structure):
+    _fields_ = [("K", C.c_int), ("T", C.c_int), ("dt", C.c_double),
+                ("lam", C.c_double), ("sigma", C.c_double * NJ),
+                ("W_pos", C.c_double * 3), ("W_ori", C.c_double * 3),
+                ("W_force", C.c_double * 6), ("W_reg", C.c_double * 6),
+                ("w_q", C.c_double), ("w_qd", C.c_double), ("w_tau", C.c_double),
+                ("w_post", C.c_double), ("q_rest", C.c_double * NJ),
+                ("w_terminal", C.c_double), ("force_mode", C.c_int),
+                ("ext_mode", C.c_int), ("F_ext", C.c_double * 6),
+                ("wall_n", C.c_double * 3), ("wall_d0", C.c_double),
+                ("wall_k", C.c_double), ("wall_c", C.c_double),
+                ("precision", C.c_int), ("lambda_fp64_threshold", C.c_double)]
+
+
+class Target(C.Structure):
+    _fields_ = [("p_des", C.c_double * 3), ("quat_des", C.c_double * 4),
+                ("F_des", C.c_double * 6)]
+
+
+class DeviceIO(C.Structure):
+    _fields_ = [("q", C.c_void_p), ("qd", C.c_void_p), ("target", C.c_void_p),
+                ("U_nominal", C.c_void_p), ("U_new", C.c_void_p), ("U_shift", C.c_void_p),
+                ("costs", C.c_void_p), ("noise", C.c_void_p), ("status", C.c_void_p),
+                ("seed", C.c_uint64), ("tick", C.c_uint64)]
+
+
+def _fill(arr, values):
+    vals = np.asarray(values, dtype=np.float64).ravel()
+    if vals.size != len(arr):
+        raise ValueError("expected %d values, got %d" % (len(arr), vals.size))
+    for i, v in enumerate(vals):
+        arr[i] = float(v)
+
+
+def robot_params(robot: dict) -> RobotParams:
+    rp = RobotParams()
+    rp.n_joints = int(robot["n"])
+    if rp.n_joints != NJ or len(robot["links"]) != NJ:
+        raise ValueError("the kernels are built for %d joints" % NJ)
+    for i, L in enumerate(robot["links"]):
+        d = rp.link[i]
+        _fill(d.R_parent, L["R_parent"])
+        _fill(d.r_parent, L["r_parent"])
+        d.mass = float(L["mass"])
+        _fill(d.com, L["com"])
+        _fill(d.inertia_com, L["inertia"])
+        d.armature = float(L["armature"])
+        d.q_min, d.q_max = float(L["q_min"]), float(L["q_max"])
+        d.qd_max, d.tau_max = float(L["qd_max"]), float(L["tau_max"])
+    _fill(rp.R_ee, robot["R_ee"])
+    _fill(rp.r_ee, robot["r_ee"])
+    _fill(rp.gravity, robot.get("gravity", [0.0, 0.0, -9.81]))
+    return rp
+
+
+def cost_params(cost: dict, precision: int = FP32, lambda_fp64_threshold: float = 0.05) -> CostParams:
+    cp = CostParams()
+    cp.K, cp.T = int(cost["K"]), int(cost["T"])
+    cp.dt, cp.lam = float(cost["dt"]), float(cost["lambda"])
+    _fill(cp.sigma, cost["sigma"])
+    for key in ("W_pos", "W_ori", "W_force", "W_reg", "q_rest", "F_ext", "wall_n"):
+        _fill(getattr(cp, key), cost.get(key, [0.0] * len(getattr(cp, key))))
+    for key in ("w_q", "w_qd", "w_tau", "w_post", "wall_d0", "wall_k", "wall_c"):
+        setattr(cp, key, float(cost.get(key, 0.0)))
+    cp.w_terminal = float(cost.get("w_terminal", 1.0))
+    cp.force_mode = int(cost.get("force_mode", 0))
+    cp.ext_mode = int(cost.get("ext_mode", EXT_NONE))
+    cp.precision = int(precision)
+    cp.lambda_fp64_threshold = float(lambda_fp64_threshold)
+    return cp
+
+
+def target_params(target: dict) -> Target:
+    t = Target()
+    _fill(t.p_des, target["p_des"])
+    _fill(t.quat_des, target.get("quat_des", [1.0, 0.0, 0.0, 0.0]))
+    _fill(t.F_des, target.get("F_des", [0.0] * 6))
+    return t
+
+
+def target_vector(target: dict) -> np.ndarray:
+    """The 13-double device layout: p_des[3], quat_des[4], F_des[6]."""
+    return np.concatenate([np.asarray(target["p_des"], float),
+                           np.asarray(target.get("quat_des", [1.0, 0.0, 0.0, 0.0]), float),
+                           np.asarray(target.get("F_des", [0.0] * 6), float)])
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        # torch ships its own HIP runtime with the same soname; loading it
+        # first makes libmppi.so bind to that one instance, so device
+        # pointers and streams from torch are valid in the library.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmppi.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        P, vp = C.POINTER, C.c_void_p
+        L.mppi_create.argtypes = [P(RobotParams), P(CostParams), P(vp)]
+        L.mppi_destroy.argtypes = [vp]
+        L.mppi_set_cost.argtypes = [vp, P(CostParams)]
+        L.mppi_update.argtypes = [vp, P(C.c_double), P(C.c_double), P(Target), P(C.c_double),
+                                  C.c_uint64, C.c_uint64, P(C.c_double), P(C.c_double)]
+        L.mppi_update_async.argtypes = [vp, P(DeviceIO), vp]
+        L.mppi_rollout_async.argtypes = [vp, P(DeviceIO), vp]
+        L.mppi_weights_async.argtypes = [vp, P(DeviceIO), vp]
+        L.mppi_plant_step_async.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int, vp]
+        L.mppi_strerror.argtypes = [C.c_int]
+        L.mppi_strerror.restype = C.c_char_p
+        L.mppi_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    try:
+        return lib().mppi_strerror(int(status)).decode()
+    except ImportError:
+        return "status %d" % status
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+class Solver:
+    """One MPPI problem: mppi_create / mppi_update / mppi_destroy."""
+
+    def __init__(self, robot: dict, cost: dict, precision: int = FP32,
+                 lambda_fp64_threshold: float = 0.05):
+        self._lib = lib()
+        self.K, self.T = int(cost["K"]), int(cost["T"])
+        self.precision = precision
+        self._h = C.c_void_p()
+        self._rp = robot_params(robot)
+        self._cp = cost_params(cost, precision, lambda_fp64_threshold)
+        st = self._lib.mppi_create(C.byref(self._rp), C.byref(self._cp), C.byref(self._h))
+        if st:
+            raise MppiError(st, "mppi_create")
+
+    def close(self):
+        if self._h:
+            self._lib.mppi_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_cost(self, cost: dict, lambda_fp64_threshold: float = 0.05):
+        self._cp = cost_params(cost, self.precision, lambda_fp64_threshold)
+        st = self._lib.mppi_set_cost(self._h, C.byref(self._cp))
+        if st:
+            raise MppiError(st, "mppi_set_cost")
+
+    def update(self, q, qd, target: dict, U_nominal, seed: int, tick: int, want_costs=True):
+        """Host-memory update.  Returns (status, U_new [T,7], costs [K] or None)."""
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        qd = np.ascontiguousarray(qd, dtype=np.float64)
+        U = np.ascontiguousarray(U_nominal, dtype=np.float64).reshape(self.T, NJ)
+        out = np.empty((self.T, NJ))
+        costs = np.empty(self.K) if want_costs else None
+        tg = target_params(target)
+        st = self._lib.mppi_update(self._h, _dp(q), _dp(qd), C.byref(tg), _dp(U),
+                                   C.c_uint64(seed), C.c_uint64(tick), _dp(out),
+                                   _dp(costs) if costs is not None else None)
+        if st not in (OK, ENONFINITE):
+            raise MppiError(st, "mppi_update")
+        return st, out, costs
+
+    def _io(self, io: dict) -> DeviceIO:
+        d = DeviceIO()
+        for key in ("q", "qd", "target", "U_nominal", "U_new", "U_shift", "costs", "noise", "status"):
+            setattr(d, key, _ptr(io.get(key)))
+        d.seed = int(io.get("seed", 0))
+        d.tick = int(io.get("tick", 0))
+        return d
+
+    def update_async(self, io: dict, stream=None):
+        """Device update; io holds torch CUDA tensors (see mppi_device_io)."""
+        d = self._io(io)
+        st = self._lib.mppi_update_async(self._h, C.byref(d), _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_update_async")
+
+    def rollout_async(self, io: dict, stream=None):
+        d = self._io(io)
+        st = self._lib.mppi_rollout_async(self._h, C.byref(d), _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_rollout_async")
+
+    def weights_async(self, io: dict, stream=None):
+        d = self._io(io)
+        st = self._lib.mppi_weights_async(self._h, C.byref(d), _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_weights_async")
+
+    def plant_step_async(self, q, qd, u, dt: float, substeps: int, stream=None):
+        st = self._lib.mppi_plant_step_async(self._h, _ptr(q), _ptr(qd), _ptr(u), float(dt),
+                                             int(substeps), _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_plant_step_async")

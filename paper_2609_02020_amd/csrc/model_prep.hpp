@@ -1,0 +1,62 @@
+// model_prep.hpp -- converts the C-ABI robot/cost structs into the layout the
+// rollout kernels read (ModelM / CostM).  The parallel-axis shift of the link
+// inertia to the link-frame origin (I_o = I_c + m (|c|^2 1 - c c^T)) runs
+// on the device in the model-preparation kernel; the cost conversion is a
+// plain field copy with a cast.
+#pragma once
+
+#include "dyn.hpp"
+#include "mppi.h"
+
+namespace mppi {
+
+template <typename R> MPPI_HD void prep_link(const mppi_link_params& P, LinkM<R>& L)
+{
+    for (int a = 0; a < 9; ++a) L.Rp[a] = R(P.R_parent[a]);
+    for (int a = 0; a < 3; ++a) L.rp[a] = R(P.r_parent[a]);
+    const double m = P.mass;
+    const double c0 = P.com[0], c1 = P.com[1], c2 = P.com[2];
+    const double cc = c0 * c0 + c1 * c1 + c2 * c2;
+    L.Io[0] = R(P.inertia_com[0] + m * (cc - c0 * c0));
+    L.Io[1] = R(P.inertia_com[1] + m * (cc - c1 * c1));
+    L.Io[2] = R(P.inertia_com[2] + m * (cc - c2 * c2));
+    L.Io[3] = R(P.inertia_com[3] - m * c0 * c1);
+    L.Io[4] = R(P.inertia_com[4] - m * c0 * c2);
+    L.Io[5] = R(P.inertia_com[5] - m * c1 * c2);
+    L.mc[0] = R(m * c0); L.mc[1] = R(m * c1); L.mc[2] = R(m * c2);
+    L.m = R(m);
+    L.arm = R(P.armature);
+    L.qmin = R(P.q_min); L.qmax = R(P.q_max); L.qdmax = R(P.qd_max); L.taumax = R(P.tau_max);
+}
+
+template <typename R> MPPI_HD void prep_model(const mppi_robot_params& P, ModelM<R>& M)
+{
+    for (int i = 0; i < NJ; ++i) prep_link(P.link[i], M.L[i]);
+    for (int a = 0; a < 9; ++a) M.Ree[a] = R(P.R_ee[a]);
+    for (int a = 0; a < 3; ++a) { M.ree[a] = R(P.r_ee[a]); M.g[a] = R(P.gravity[a]); }
+}
+
+template <typename R> inline void prep_cost(const mppi_cost_params& P, CostM<R>& C)
+{
+    C.dt = R(P.dt);
+    int ori = 0, force = 0;
+    for (int j = 0; j < NJ; ++j) { C.sigma[j] = R(P.sigma[j]); C.q_rest[j] = R(P.q_rest[j]); }
+    for (int a = 0; a < 3; ++a) {
+        C.W_pos[a] = R(P.W_pos[a]); C.W_ori[a] = R(P.W_ori[a]);
+        C.wall_n[a] = R(P.wall_n[a]);
+        ori |= P.W_ori[a] != 0.0;
+    }
+    for (int a = 0; a < 6; ++a) {
+        C.W_force[a] = R(P.W_force[a]); C.W_reg[a] = R(P.W_reg[a]); C.F_ext[a] = R(P.F_ext[a]);
+        force |= (P.W_force[a] != 0.0) | (P.W_reg[a] != 0.0);
+    }
+    C.w_q = R(P.w_q); C.w_qd = R(P.w_qd); C.w_tau = R(P.w_tau); C.w_post = R(P.w_post);
+    C.w_T = R(P.w_terminal);
+    C.wall_d0 = R(P.wall_d0); C.wall_k = R(P.wall_k); C.wall_c = R(P.wall_c);
+    C.ext_mode = P.ext_mode;
+    C.force_mode = P.force_mode;
+    C.has_ori = ori;
+    C.has_force = force;
+}
+
+}  // namespace mppi

@@ -1,0 +1,55 @@
+// rollout.hpp -- one MPPI sample rolled out over the horizon (Sec. II Eq. 3
+// with the dynamics of Sec. III-A and the cost of Sec. III-B):
+//   for t = 0 .. T-1:
+//     du_t = sigma * z(seed, tick, k, t)            (Eq. 2, Philox + Box-Muller)
+//     v_t  = u_t + du_t
+//     S   += l(x_t, v_t)                            (Eqs. 9-14, pre-step state)
+//     qdd  = M^-1 (v_t + tau_ext - h)               (Eq. 6, articulated-body)
+//     qd  += qdd dt ; q += qd dt                    (Eq. 7 as written)
+//   S += phi(x_T) = w_T (C_pos + C_ori + C_joint)(x_T)
+// The cost is accumulated in the rollout precision R.
+#pragma once
+
+#include "dyn.hpp"
+
+namespace mppi {
+
+template <typename R> MPPI_HD bool finite_(R x) { return x - x == R(0); }
+
+template <typename R, bool FORCE, typename UT>
+MPPI_HD R rollout_sample(const ModelM<R>& M, const CostM<R>& C, const TargetM<R>& tg,
+                         const R* q0, const R* qd0, const R* tau_ext_c, const UT* U_nom, int T,
+                         uint64_t seed, uint32_t tick, uint32_t k, R* noise_out, size_t noise_stride)
+{
+    R q[NJ], qd[NJ], S = R(0);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) { q[j] = q0[j]; qd[j] = qd0[j]; }
+    const int ext = C.ext_mode == EXTW_WALL ? EXTW_WALL : EXTW_NONE;
+    for (int t = 0; t < T; ++t) {
+        R z[8], v[NJ], tau[NJ];
+        normals8<R>(seed, tick, k, (uint32_t)t, z);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            R du = C.sigma[j] * z[j];
+            if (noise_out) noise_out[(size_t)(t * NJ + j) * noise_stride] = du;
+            v[j] = R(U_nom[t * NJ + j]) + du;
+            tau[j] = v[j] + tau_ext_c[j];
+        }
+        StepOut<R> o;
+        dyn_step<R, FORCE>(M, C, ext, q, qd, tau, v, o);
+        R l = motion_cost(M, C, tg, o.pee, o.Rn) + joint_cost(M, C, q, qd) + torque_cost(M, C, v);
+        if (FORCE) l += force_cost(C, tg, o.F);
+        S += l;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            qd[j] += o.qdd[j] * C.dt;
+            q[j] += qd[j] * C.dt;
+        }
+    }
+    R pee[3], Rn[9];
+    fk_ee(M, q, pee, Rn, (R*)nullptr, (R*)nullptr);
+    S += C.w_T * (motion_cost(M, C, tg, pee, Rn) + joint_cost(M, C, q, qd));
+    return S;
+}
+
+}  // namespace mppi

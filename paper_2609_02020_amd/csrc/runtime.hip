@@ -1,0 +1,371 @@
+// runtime.hip -- the C ABI of libmppi.so (include/mppi.h): handle
+// lifecycle, argument validation, device buffers and launch sequencing.
+// All arithmetic of the method runs in the kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "launch.hpp"
+#include "model_prep.hpp"
+#include "mppi.h"
+
+using namespace mppi;
+
+struct mppi_solver {
+    mppi_robot_params robot;
+    mppi_cost_params cost;
+    int device = 0;
+    mppi_robot_params* d_raw = nullptr;
+    ModelM<float>* d_mf = nullptr;
+    ModelM<double>* d_md = nullptr;
+    CostM<float>* d_cf = nullptr;
+    CostM<double>* d_cd = nullptr;
+    void* d_noise = nullptr;     // R [T][7][K]
+    void* d_costs = nullptr;     // R [K]
+    int* d_status = nullptr;
+    double* d_io = nullptr;      // q 7 | qd 7 | target 13 | U_nom T*7 | U_new T*7
+    double* h_io = nullptr;      // pinned mirror of d_io
+    void* h_costs = nullptr;     // pinned R [K]
+    int* h_status = nullptr;     // pinned
+    hipStream_t stream = nullptr;
+};
+
+namespace {
+
+constexpr int kIoQ = 0, kIoQd = 7, kIoTarget = 14, kIoU = 27;
+
+size_t rsize(const mppi_cost_params& c) { return c.precision == MPPI_FP64 ? sizeof(double) : sizeof(float); }
+
+bool finite_all(const double* p, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// Sylvester's criterion on a symmetric 3x3 given as xx yy zz xy xz yz.
+bool sym3_pd(double xx, double yy, double zz, double xy, double xz, double yz, double tol)
+{
+    double m1 = xx, m2 = xx * yy - xy * xy;
+    double m3 = xx * (yy * zz - yz * yz) - xy * (xy * zz - yz * xz) + xz * (xy * yz - yy * xz);
+    return m1 > tol && m2 > tol * tol && m3 > tol * tol * tol;
+}
+
+bool sym3_psd(double xx, double yy, double zz, double xy, double xz, double yz, double tol)
+{
+    // all principal minors >= -tol
+    if (xx < -tol || yy < -tol || zz < -tol) return false;
+    if (xx * yy - xy * xy < -tol || xx * zz - xz * xz < -tol || yy * zz - yz * yz < -tol) return false;
+    double d = xx * (yy * zz - yz * yz) - xy * (xy * zz - yz * xz) + xz * (xy * yz - yy * xz);
+    return d >= -tol;
+}
+
+int validate_robot(const mppi_robot_params* r)
+{
+    if (!r || r->n_joints != MPPI_NJ) return MPPI_EINVAL;
+    for (int i = 0; i < MPPI_NJ; ++i) {
+        const mppi_link_params& L = r->link[i];
+        if (!finite_all(L.R_parent, 9) || !finite_all(L.r_parent, 3) || !finite_all(L.com, 3) ||
+            !finite_all(L.inertia_com, 6))
+            return MPPI_EINVAL;
+        double s[6] = {L.mass, L.armature, L.q_min, L.q_max, L.qd_max, L.tau_max};
+        if (!finite_all(s, 6) || !(L.mass > 0) || L.armature < 0 || !(L.q_min < L.q_max) ||
+            !(L.qd_max > 0) || !(L.tau_max > 0))
+            return MPPI_EINVAL;
+        const double* I = L.inertia_com;
+        if (!sym3_pd(I[0], I[1], I[2], I[3], I[4], I[5], 0.0)) return MPPI_EINVAL;
+        // triangle inequality <=> tr(I)/2 * 1 - I is positive semidefinite
+        double h = 0.5 * (I[0] + I[1] + I[2]);
+        double tol = 1e-12 * (1.0 + h);
+        if (!sym3_psd(h - I[0], h - I[1], h - I[2], -I[3], -I[4], -I[5], tol)) return MPPI_EINVAL;
+        // R_parent must be a rotation
+        const double* R = L.R_parent;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double d = R[a * 3] * R[b * 3] + R[a * 3 + 1] * R[b * 3 + 1] + R[a * 3 + 2] * R[b * 3 + 2];
+                if (std::fabs(d - (a == b ? 1.0 : 0.0)) > 1e-9) return MPPI_EINVAL;
+            }
+    }
+    if (!finite_all(r->R_ee, 9) || !finite_all(r->r_ee, 3) || !finite_all(r->gravity, 3)) return MPPI_EINVAL;
+    return MPPI_OK;
+}
+
+int validate_cost(const mppi_cost_params* c)
+{
+    if (!c) return MPPI_EINVAL;
+    if (c->K < 1 || c->K > (1 << 20) || c->T < 1 || c->T > kMaxT) return MPPI_EINVAL;
+    if (!(c->dt > 0) || !std::isfinite(c->dt) || !(c->lambda > 0) || !std::isfinite(c->lambda)) return MPPI_EINVAL;
+    for (int j = 0; j < MPPI_NJ; ++j)
+        if (!(c->sigma[j] >= 0) || !std::isfinite(c->sigma[j])) return MPPI_EINVAL;
+    const double* groups[] = {c->W_pos, c->W_ori, c->W_force, c->W_reg, c->q_rest, c->F_ext, c->wall_n};
+    const int sizes[] = {3, 3, 6, 6, MPPI_NJ, 6, 3};
+    for (int g = 0; g < 7; ++g)
+        if (!finite_all(groups[g], sizes[g])) return MPPI_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (c->W_pos[a] < 0 || c->W_ori[a] < 0) return MPPI_EINVAL;
+    for (int a = 0; a < 6; ++a)
+        if (c->W_force[a] < 0 || c->W_reg[a] < 0) return MPPI_EINVAL;
+    double s[] = {c->w_q, c->w_qd, c->w_tau, c->w_post, c->w_terminal, c->wall_d0, c->wall_k, c->wall_c,
+                  c->lambda_fp64_threshold};
+    if (!finite_all(s, 9)) return MPPI_EINVAL;
+    if (c->w_q < 0 || c->w_qd < 0 || c->w_tau < 0 || c->w_post < 0 || c->w_terminal < 0) return MPPI_EINVAL;
+    if (c->force_mode != 0 && c->force_mode != 1) return MPPI_EINVAL;
+    if (c->ext_mode < MPPI_EXT_NONE || c->ext_mode > MPPI_EXT_WALL) return MPPI_EINVAL;
+    if (c->precision != MPPI_FP32 && c->precision != MPPI_FP64) return MPPI_EINVAL;
+    if (c->ext_mode == MPPI_EXT_WALL) {
+        double n = std::sqrt(c->wall_n[0] * c->wall_n[0] + c->wall_n[1] * c->wall_n[1] + c->wall_n[2] * c->wall_n[2]);
+        if (std::fabs(n - 1.0) > 1e-6 || c->wall_k < 0 || c->wall_c < 0) return MPPI_EINVAL;
+    }
+    return MPPI_OK;
+}
+
+bool has_force(const mppi_cost_params& c)
+{
+    for (int a = 0; a < 6; ++a)
+        if (c.W_force[a] != 0.0 || c.W_reg[a] != 0.0) return true;
+    return false;
+}
+
+int upload_cost(mppi_solver* h)
+{
+    CostM<float> cf;
+    CostM<double> cd;
+    prep_cost(h->cost, cf);
+    prep_cost(h->cost, cd);
+    if (hipMemcpy(h->d_cf, &cf, sizeof cf, hipMemcpyHostToDevice) != hipSuccess) return MPPI_EDEVICE;
+    if (hipMemcpy(h->d_cd, &cd, sizeof cd, hipMemcpyHostToDevice) != hipSuccess) return MPPI_EDEVICE;
+    return MPPI_OK;
+}
+
+void release(mppi_solver* h)
+{
+    if (!h) return;
+    (void)hipFree(h->d_raw);
+    (void)hipFree(h->d_mf);
+    (void)hipFree(h->d_md);
+    (void)hipFree(h->d_cf);
+    (void)hipFree(h->d_cd);
+    (void)hipFree(h->d_noise);
+    (void)hipFree(h->d_costs);
+    (void)hipFree(h->d_status);
+    (void)hipFree(h->d_io);
+    (void)hipHostFree(h->h_io);
+    (void)hipHostFree(h->h_costs);
+    (void)hipHostFree(h->h_status);
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+int rollout_enqueue(mppi_solver* h, const mppi_device_io* io, hipStream_t s, void* noise, void* costs)
+{
+    RolloutArgs a;
+    const bool fp64 = h->cost.precision == MPPI_FP64;
+    a.model = fp64 ? (const void*)h->d_md : (const void*)h->d_mf;
+    a.cost = fp64 ? (const void*)h->d_cd : (const void*)h->d_cf;
+    a.q0 = io->q;
+    a.qd0 = io->qd;
+    a.target = io->target;
+    a.U_nom = io->U_nominal;
+    a.seed = io->seed;
+    a.tick = io->tick;
+    a.K = h->cost.K;
+    a.T = h->cost.T;
+    a.noise = noise;
+    a.costs = costs;
+    return launch_rollout(h->cost.precision, has_force(h->cost), a, s) == hipSuccess ? MPPI_OK : MPPI_EDEVICE;
+}
+
+int weights_enqueue(mppi_solver* h, const mppi_device_io* io, hipStream_t s, const void* noise,
+                    const void* costs)
+{
+    WeightsArgs w;
+    w.costs = costs;
+    w.noise = noise;
+    w.U_nom = io->U_nominal;
+    w.U_new = io->U_new;
+    w.U_shift = io->U_shift;
+    w.status = io->status;
+    w.K = h->cost.K;
+    w.T = h->cost.T;
+    w.lambda = h->cost.lambda;
+    const bool acc64 = h->cost.lambda < h->cost.lambda_fp64_threshold;
+    return launch_weights(h->cost.precision, acc64, w, s) == hipSuccess ? MPPI_OK : MPPI_EDEVICE;
+}
+
+int check_io(const mppi_solver* h, const mppi_device_io* io, bool need_out)
+{
+    if (!h || !io || !io->q || !io->qd || !io->target || !io->U_nominal) return MPPI_EINVAL;
+    if (need_out && !io->U_new) return MPPI_EINVAL;
+    return MPPI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mppi_create(const mppi_robot_params* robot, const mppi_cost_params* cost, mppi_handle_t* out)
+{
+    if (!out) return MPPI_EINVAL;
+    *out = nullptr;
+    int st = validate_robot(robot);
+    if (st) return st;
+    st = validate_cost(cost);
+    if (st) return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MPPI_EDEVICE;
+    mppi_solver* h = new (std::nothrow) mppi_solver;
+    if (!h) return MPPI_ENOMEM;
+    h->robot = *robot;
+    h->cost = *cost;
+    if (hipGetDevice(&h->device) != hipSuccess) { release(h); return MPPI_EDEVICE; }
+    const size_t K = cost->K, T = cost->T, rs = rsize(*cost);
+    const size_t io_n = kIoU + 2 * T * MPPI_NJ;
+    bool ok = hipMalloc(&h->d_raw, sizeof(mppi_robot_params)) == hipSuccess &&
+              hipMalloc(&h->d_mf, sizeof(ModelM<float>)) == hipSuccess &&
+              hipMalloc(&h->d_md, sizeof(ModelM<double>)) == hipSuccess &&
+              hipMalloc(&h->d_cf, sizeof(CostM<float>)) == hipSuccess &&
+              hipMalloc(&h->d_cd, sizeof(CostM<double>)) == hipSuccess &&
+              hipMalloc(&h->d_noise, K * T * MPPI_NJ * rs) == hipSuccess &&
+              hipMalloc(&h->d_costs, K * rs) == hipSuccess &&
+              hipMalloc(&h->d_status, sizeof(int)) == hipSuccess &&
+              hipMalloc(&h->d_io, io_n * sizeof(double)) == hipSuccess &&
+              hipHostMalloc(&h->h_io, io_n * sizeof(double), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&h->h_costs, K * rs, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&h->h_status, sizeof(int), hipHostMallocDefault) == hipSuccess;
+    if (!ok) { release(h); return MPPI_ENOMEM; }
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) { release(h); return MPPI_EDEVICE; }
+    if (hipMemcpy(h->d_raw, robot, sizeof *robot, hipMemcpyHostToDevice) != hipSuccess ||
+        launch_prep_model(h->d_raw, h->d_mf, h->d_md, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess || upload_cost(h) != MPPI_OK) {
+        release(h);
+        return MPPI_EDEVICE;
+    }
+    *out = h;
+    return MPPI_OK;
+}
+
+int mppi_destroy(mppi_handle_t h)
+{
+    if (h) {
+        if (h->stream) (void)hipStreamSynchronize(h->stream);
+        release(h);
+    }
+    return MPPI_OK;
+}
+
+int mppi_set_cost(mppi_handle_t h, const mppi_cost_params* cost)
+{
+    if (!h) return MPPI_EINVAL;
+    int st = validate_cost(cost);
+    if (st) return st;
+    if (cost->K != h->cost.K || cost->T != h->cost.T || cost->precision != h->cost.precision) return MPPI_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess) return MPPI_EDEVICE;
+    h->cost = *cost;
+    return upload_cost(h);
+}
+
+int mppi_rollout_async(mppi_handle_t h, const mppi_device_io* io, void* stream)
+{
+    int st = check_io(h, io, false);
+    if (st) return st;
+    return rollout_enqueue(h, io, (hipStream_t)stream, io->noise ? io->noise : h->d_noise,
+                           io->costs ? io->costs : h->d_costs);
+}
+
+int mppi_weights_async(mppi_handle_t h, const mppi_device_io* io, void* stream)
+{
+    int st = check_io(h, io, true);
+    if (st) return st;
+    return weights_enqueue(h, io, (hipStream_t)stream, io->noise ? io->noise : h->d_noise,
+                           io->costs ? io->costs : h->d_costs);
+}
+
+int mppi_update_async(mppi_handle_t h, const mppi_device_io* io, void* stream)
+{
+    int st = check_io(h, io, true);
+    if (st) return st;
+    void* noise = io->noise ? io->noise : h->d_noise;
+    void* costs = io->costs ? io->costs : h->d_costs;
+    st = rollout_enqueue(h, io, (hipStream_t)stream, noise, costs);
+    if (st) return st;
+    return weights_enqueue(h, io, (hipStream_t)stream, noise, costs);
+}
+
+int mppi_update(mppi_handle_t h, const double* q, const double* qd, const mppi_target* target,
+                const double* U_nominal, uint64_t seed, uint64_t tick, double* U_new, double* costs)
+{
+    if (!h || !q || !qd || !target || !U_nominal || !U_new) return MPPI_EINVAL;
+    const int T = h->cost.T, K = h->cost.K;
+    if (!finite_all(q, 7) || !finite_all(qd, 7) || !finite_all(target->p_des, 3) ||
+        !finite_all(target->quat_des, 4) || !finite_all(target->F_des, 6) || !finite_all(U_nominal, T * 7))
+        return MPPI_EINVAL;
+    const double qn = target->quat_des[0] * target->quat_des[0] + target->quat_des[1] * target->quat_des[1] +
+                      target->quat_des[2] * target->quat_des[2] + target->quat_des[3] * target->quat_des[3];
+    if (!(qn > 0)) return MPPI_EINVAL;
+    double* hio = h->h_io;
+    std::memcpy(hio + kIoQ, q, 7 * sizeof(double));
+    std::memcpy(hio + kIoQd, qd, 7 * sizeof(double));
+    std::memcpy(hio + kIoTarget, target->p_des, 3 * sizeof(double));
+    std::memcpy(hio + kIoTarget + 3, target->quat_des, 4 * sizeof(double));
+    std::memcpy(hio + kIoTarget + 7, target->F_des, 6 * sizeof(double));
+    std::memcpy(hio + kIoU, U_nominal, (size_t)T * 7 * sizeof(double));
+    const size_t in_n = kIoU + (size_t)T * 7;
+    hipStream_t s = h->stream;
+    if (hipMemcpyAsync(h->d_io, hio, in_n * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+        return MPPI_EDEVICE;
+    mppi_device_io io;
+    std::memset(&io, 0, sizeof io);
+    io.q = h->d_io + kIoQ;
+    io.qd = h->d_io + kIoQd;
+    io.target = h->d_io + kIoTarget;
+    io.U_nominal = h->d_io + kIoU;
+    io.U_new = h->d_io + in_n;
+    io.status = h->d_status;
+    io.seed = seed;
+    io.tick = tick;
+    int st = rollout_enqueue(h, &io, s, h->d_noise, h->d_costs);
+    if (!st) st = weights_enqueue(h, &io, s, h->d_noise, h->d_costs);
+    if (st) return st;
+    if (hipMemcpyAsync(hio + in_n, h->d_io + in_n, (size_t)T * 7 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(h->h_status, h->d_status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return MPPI_EDEVICE;
+    if (costs && hipMemcpyAsync(h->h_costs, h->d_costs, (size_t)K * rsize(h->cost), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return MPPI_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return MPPI_EDEVICE;
+    std::memcpy(U_new, hio + in_n, (size_t)T * 7 * sizeof(double));
+    if (costs) {
+        if (h->cost.precision == MPPI_FP64) std::memcpy(costs, h->h_costs, (size_t)K * sizeof(double));
+        else
+            for (int k = 0; k < K; ++k) costs[k] = (double)((const float*)h->h_costs)[k];
+    }
+    return *h->h_status;
+}
+
+int mppi_plant_step_async(mppi_handle_t h, double* q, double* qd, const double* u, double dt, int substeps,
+                          void* stream)
+{
+    if (!h || !q || !qd || !u || !(dt > 0) || substeps < 1) return MPPI_EINVAL;
+    return launch_plant(h->d_md, h->d_cd, q, qd, u, dt, substeps, (hipStream_t)stream) == hipSuccess
+               ? MPPI_OK
+               : MPPI_EDEVICE;
+}
+
+const char* mppi_strerror(int status)
+{
+    switch (status) {
+    case MPPI_OK: return "ok";
+    case MPPI_EINVAL: return "invalid argument";
+    case MPPI_ENONFINITE: return "all sample costs non-finite";
+    case MPPI_ENOMEM: return "out of memory";
+    case MPPI_EDEVICE: return "device error";
+    case MPPI_ENOTSUP: return "not supported";
+    default: return "unknown status";
+    }
+}
+
+const char* mppi_version(void) { return "mppi-gfx950 0.1"; }
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// Host-only build of the rollout kernels' per-sample math (dyn.hpp,
+// rollout.hpp, model_prep.hpp), for CPU unit tests against the oracle and
+// for counting the algorithmic floating-point work of one sample-step.
+// Never loaded by the product library.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "mppi.h"
+#include "model_prep.hpp"
+#include "rollout.hpp"
+
+using namespace mppi;
+
+template <typename R>
+static void step_t(const mppi_robot_params* rp, const mppi_cost_params* cp, int force, int ext,
+                   const double* q, const double* qd, const double* tau, const double* v,
+                   double* qdd, double* pee, double* Rn, double* F)
+{
+    ModelM<R> M;
+    CostM<R> C;
+    prep_model(*rp, M);
+    prep_cost(*cp, C);
+    R qq[NJ], qqd[NJ], tt[NJ], vv[NJ];
+    for (int j = 0; j < NJ; ++j) { qq[j] = R(q[j]); qqd[j] = R(qd[j]); tt[j] = R(tau[j]); vv[j] = R(v[j]); }
+    StepOut<R> o;
+    if (force) dyn_step<R, true>(M, C, ext, qq, qqd, tt, vv, o);
+    else dyn_step<R, false>(M, C, ext, qq, qqd, tt, vv, o);
+    for (int j = 0; j < NJ; ++j) qdd[j] = double(o.qdd[j]);
+    for (int a = 0; a < 3; ++a) pee[a] = double(o.pee[a]);
+    for (int a = 0; a < 9; ++a) Rn[a] = double(o.Rn[a]);
+    if (force) for (int a = 0; a < 6; ++a) F[a] = double(o.F[a]);
+}
+
+extern "C" void hc_step(const mppi_robot_params* rp, const mppi_cost_params* cp, int prec, int force,
+                        int ext, const double* q, const double* qd, const double* tau,
+                        const double* v, double* qdd, double* pee, double* Rn, double* F)
+{
+    if (prec == MPPI_FP64) step_t<double>(rp, cp, force, ext, q, qd, tau, v, qdd, pee, Rn, F);
+    else step_t<float>(rp, cp, force, ext, q, qd, tau, v, qdd, pee, Rn, F);
+}
+
+template <typename R>
+static double rollout_t(const mppi_robot_params* rp, const mppi_cost_params* cp, const double* target,
+                        const double* q0, const double* qd0, const double* U, uint64_t seed,
+                        uint64_t tick, uint32_t k, double* noise)
+{
+    ModelM<R> M;
+    CostM<R> C;
+    TargetM<R> tg;
+    prep_model(*rp, M);
+    prep_cost(*cp, C);
+    make_target(target, tg);
+    R q[NJ], qd[NJ], te[NJ] = {};
+    for (int j = 0; j < NJ; ++j) { q[j] = R(q0[j]); qd[j] = R(qd0[j]); }
+    if (C.ext_mode == EXTW_CONST) const_ext_torque(M, C, q, te);
+    R nz[256 * NJ];
+    R S = C.has_force
+              ? rollout_sample<R, true>(M, C, tg, q, qd, te, U, cp->T, seed, (uint32_t)tick, k, nz, 1)
+              : rollout_sample<R, false>(M, C, tg, q, qd, te, U, cp->T, seed, (uint32_t)tick, k, nz, 1);
+    for (int i = 0; i < cp->T * NJ; ++i) noise[i] = double(nz[i]);
+    return double(S);
+}
+
+extern "C" double hc_rollout(const mppi_robot_params* rp, const mppi_cost_params* cp, int prec,
+                             const double* target, const double* q0, const double* qd0,
+                             const double* U, uint64_t seed, uint64_t tick, uint32_t k,
+                             double* noise)
+{
+    if (prec == MPPI_FP64) return rollout_t<double>(rp, cp, target, q0, qd0, U, seed, tick, k, noise);
+    return rollout_t<float>(rp, cp, target, q0, qd0, U, seed, tick, k, noise);
+}
+
+extern "C" void hc_normals(int prec, uint64_t seed, uint64_t tick, uint32_t k, uint32_t t, double* z)
+{
+    if (prec == MPPI_FP64) {
+        double zz[8];
+        normals8<double>(seed, (uint32_t)tick, k, t, zz);
+        for (int i = 0; i < 8; ++i) z[i] = zz[i];
+    } else {
+        float zz[8];
+        normals8<float>(seed, (uint32_t)tick, k, t, zz);
+        for (int i = 0; i < 8; ++i) z[i] = zz[i];
+    }
+}

@@ -1,0 +1,123 @@
+"""CPU check of the rollout kernels' per-sample math against the oracle.
+
+tests/hostcheck.cpp compiles the kernels' header-only math (dyn.hpp,
+rollout.hpp, model_prep.hpp) for the host with g++; these tests compare it,
+in FP64 and FP32, with the oracle on the same seeded inputs.  This catches
+algebra mistakes on the CPU before any GPU run; the GPU parity tests are in
+test_gpu_parity.py.
+"""
+import ctypes as C
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2609_02020_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def hc(tmp_path_factory):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    so = str(tmp_path_factory.mktemp("hc") / "libhostcheck.so")
+    subprocess.run(["g++", "-std=c++17", "-O2", "-fPIC", "-shared",
+                    "-I", os.path.join(ROOT, "include"),
+                    "-I", os.path.join(ROOT, "paper_2609_02020_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "hostcheck.cpp"), "-o", so], check=True)
+    L = C.CDLL(so)
+    D = C.POINTER(C.c_double)
+    L.hc_step.argtypes = [C.POINTER(B.RobotParams), C.POINTER(B.CostParams), C.c_int, C.c_int,
+                          C.c_int, D, D, D, D, D, D, D, D]
+    L.hc_rollout.argtypes = [C.POINTER(B.RobotParams), C.POINTER(B.CostParams), C.c_int, D, D, D,
+                             D, C.c_uint64, C.c_uint64, C.c_uint32, D]
+    L.hc_rollout.restype = C.c_double
+    L.hc_normals.argtypes = [C.c_int, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, D]
+    return L
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(C.POINTER(C.c_double))
+
+
+def step(hc, case, prec, force, ext, q, qd, tau, v):
+    rp = B.robot_params(case["robot"])
+    cp = B.cost_params(case["cost"], prec)
+    qdd, pee, Rn, F = np.zeros(7), np.zeros(3), np.zeros(9), np.zeros(6)
+    args = [np.ascontiguousarray(x, dtype=np.float64) for x in (q, qd, tau, v)]
+    hc.hc_step(C.byref(rp), C.byref(cp), prec, force, ext, *[_d(a) for a in args],
+               qdd.ctypes.data_as(C.POINTER(C.c_double)), pee.ctypes.data_as(C.POINTER(C.c_double)),
+               Rn.ctypes.data_as(C.POINTER(C.c_double)), F.ctypes.data_as(C.POINTER(C.c_double)))
+    return qdd, pee, Rn.reshape(3, 3), F
+
+
+@pytest.mark.parametrize("prec,tol", [(B.FP64, 1e-10), (B.FP32, 2e-4)])
+def test_aba_step_matches_oracle(hc, ora, workloads, prec, tol):
+    rng = np.random.default_rng(11)
+    for case in workloads["single_k256"][:6]:
+        q = rng.uniform(-2, 2, 7)
+        qd = rng.uniform(-2, 2, 7)
+        tau = rng.uniform(-20, 20, 7)
+        qdd, pee, Rn, _ = step(hc, case, prec, 0, 0, q, qd, tau, tau)
+        ref = ora.aba(case["robot"], q, qd, tau)
+        scale = np.abs(ref).max() + 1.0
+        assert np.abs(qdd - ref).max() < tol * scale
+        _, _, pe_ref, _ = ora.fk(case["robot"], q)
+        R_ref, _, _, _ = ora.fk(case["robot"], q)
+        assert np.abs(pee - pe_ref).max() < tol
+        assert np.abs(Rn - R_ref[-1]).max() < tol
+
+
+@pytest.mark.parametrize("prec,tol", [(B.FP64, 1e-9), (B.FP32, 5e-4)])
+def test_wall_step_and_force_estimate_match_oracle(hc, ora, workloads, prec, tol):
+    rng = np.random.default_rng(12)
+    for case in workloads["wall_k4096"][:5]:
+        rb, cost = case["robot"], case["cost"]
+        q = np.array(case["q0"]) + rng.uniform(-0.3, 0.3, 7)
+        qd = rng.uniform(-1, 1, 7)
+        v = rng.uniform(-10, 10, 7)
+        # push the EE into the wall so the contact force is active
+        _, _, pe, _ = ora.fk(rb, q)
+        cost = dict(cost, wall_d0=float(np.dot(cost["wall_n"], pe)) + 0.01)
+        case2 = dict(case, cost=cost)
+        qdd, _, _, F = step(hc, case2, prec, 1, 2, q, qd, v, v)
+        J = ora.ee_jacobian(rb, q)
+        fw = np.concatenate([ora.wall_force(cost, pe, J[:3] @ qd), np.zeros(3)])
+        assert np.linalg.norm(fw) > 1.0
+        ref = ora.aba(rb, q, qd, v, fw)
+        assert np.abs(qdd - ref).max() < tol * (np.abs(ref).max() + 1)
+        g = ora.bias_jacobian(rb, q, np.zeros(7))
+        Fref = ora.force_estimate(rb, q, v - g)
+        assert np.abs(F - Fref).max() < tol * (np.abs(Fref).max() + 1) * 10
+
+
+@pytest.mark.parametrize("prec", [B.FP64, B.FP32])
+def test_normals_match_oracle(hc, ora, prec):
+    for (seed, tick, k, t) in [(3000, 0, 0, 0), (2**40 + 17, 123456789, 4095, 17), (7, 5, 77, 3)]:
+        z = np.zeros(8)
+        hc.hc_normals(prec, seed, tick, k, t, z.ctypes.data_as(C.POINTER(C.c_double)))
+        ref = ora.normals(seed, tick, k, t)
+        tol = 1e-13 if prec == B.FP64 else 2e-5
+        assert np.abs(z - ref).max() < tol * (1 + np.abs(ref).max())
+
+
+@pytest.mark.parametrize("which", ["single_k256", "wall_k4096"])
+@pytest.mark.parametrize("prec,tol", [(B.FP64, 1e-9), (B.FP32, 1e-4)])
+def test_rollout_cost_matches_oracle(hc, ora, workloads, which, prec, tol):
+    for case in workloads[which][:3]:
+        rp = B.robot_params(case["robot"])
+        cp = B.cost_params(case["cost"], prec)
+        tgt = B.target_vector(case["target"])
+        U = np.ascontiguousarray(case["U_nom"], dtype=np.float64)
+        for k in (0, 5, 1234):
+            noise = np.zeros((case["cost"]["T"], 7))
+            S = hc.hc_rollout(C.byref(rp), C.byref(cp), prec, _d(tgt), _d(case["q0"]),
+                              _d(case["qd0"]), _d(U), case["seed"], 3, k,
+                              noise.ctypes.data_as(C.POINTER(C.c_double)))
+            S_ref, n_ref = ora.rollout(case["robot"], case["cost"], case["target"], case["q0"],
+                                       case["qd0"], U, case["seed"], 3, k)
+            assert abs(S - S_ref) <= tol * abs(S_ref), (S, S_ref)
+            assert np.abs(noise - n_ref).max() < (1e-12 if prec == B.FP64 else 1e-4)

@@ -1,0 +1,90 @@
+"""The C ABI library: loads, exports every declared entry point, and
+rejects invalid arguments on the host before touching the GPU.  CPU only."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2609_02020_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "mppi.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mppi_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("libmppi.so not built")
+    return B.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "mppi_create" in names and "mppi_update" in names and "mppi_update_async" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_strerror_and_version(lib):
+    assert B.strerror(B.OK) == "ok"
+    assert "non-finite" in B.strerror(B.ENONFINITE)
+    assert lib.mppi_version().decode().startswith("mppi")
+
+
+def _create(lib, robot, cost):
+    rp, cp, h = B.robot_params(robot), B.cost_params(cost), C.c_void_p()
+    return lib.mppi_create(C.byref(rp), C.byref(cp), C.byref(h)), h
+
+
+def test_invalid_arguments_rejected_before_device(lib, workloads):
+    case = workloads["single_k256"][0]
+    robot, cost = case["robot"], case["cost"]
+    bad = []
+    r = {**robot, "links": [dict(L) for L in robot["links"]]}
+    r["links"][2]["mass"] = -1.0
+    bad.append((r, cost))
+    r = {**robot, "links": [dict(L) for L in robot["links"]]}
+    r["links"][3]["inertia"] = [1.0, 0.1, 0.1, 0.0, 0.0, 0.0]   # violates the triangle inequality
+    bad.append((r, cost))
+    r = {**robot, "links": [dict(L) for L in robot["links"]]}
+    r["links"][1]["inertia"] = [0.1, 0.1, 0.1, 0.2, 0.0, 0.0]   # not positive definite
+    bad.append((r, cost))
+    r = {**robot, "links": [dict(L) for L in robot["links"]]}
+    r["links"][0]["R_parent"] = [[1, 0, 0], [0, 2, 0], [0, 0, 1]]  # not a rotation
+    bad.append((r, cost))
+    bad.append((robot, dict(cost, K=0)))
+    bad.append((robot, dict(cost, T=0)))
+    bad.append((robot, dict(cost, T=1000)))
+    bad.append((robot, dict(cost, dt=0.0)))
+    bad.append((robot, dict(cost, **{"lambda": 0.0})))
+    bad.append((robot, dict(cost, sigma=[2.0] * 6 + [-1.0])))
+    bad.append((robot, dict(cost, w_q=float("nan"))))
+    bad.append((robot, dict(cost, ext_mode=2, wall_n=[0.0, 0.0, 2.0])))
+    for rb, cs in bad:
+        st, h = _create(lib, rb, cs)
+        assert st == B.EINVAL
+        assert not h.value
+    rp = B.robot_params(robot)
+    rp.n_joints = 6
+    cp, h = B.cost_params(cost), C.c_void_p()
+    assert lib.mppi_create(C.byref(rp), C.byref(cp), C.byref(h)) == B.EINVAL
+    assert lib.mppi_create(None, C.byref(cp), C.byref(h)) == B.EINVAL
+    assert lib.mppi_destroy(None) == B.OK
+
+
+def test_null_handle_calls_fail_cleanly(lib):
+    io = B.DeviceIO()
+    assert lib.mppi_update_async(None, C.byref(io), None) == B.EINVAL
+    assert lib.mppi_rollout_async(None, C.byref(io), None) == B.EINVAL
+    assert lib.mppi_weights_async(None, C.byref(io), None) == B.EINVAL
+    D = C.POINTER(C.c_double)
+    z = np.zeros(7)
+    assert lib.mppi_update(None, z.ctypes.data_as(D), z.ctypes.data_as(D), None, None, 0, 0, None,
+                           None) == B.EINVAL

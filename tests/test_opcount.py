@@ -1,0 +1,54 @@
+"""The algorithmic flop count the benchmark divides by: the rollout kernel's
+per-sample code run on the host with an op-counting scalar."""
+import ctypes as C
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import bench
+from paper_2609_02020_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def oc(tmp_path_factory):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    so = str(tmp_path_factory.mktemp("oc") / "libopcount.so")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-fPIC", "-shared", "-I", os.path.join(ROOT, "include"),
+                    "-I", os.path.join(ROOT, "paper_2609_02020_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "opcount.cpp"), "-o", so], check=True)
+    return C.CDLL(so)
+
+
+def counts(oc, case, T):
+    D = C.POINTER(C.c_double)
+    rp = B.robot_params(case["robot"])
+    cp = B.cost_params(dict(case["cost"], T=T))
+    tgt = B.target_vector(case["target"])
+    U = np.ascontiguousarray(np.tile(np.array(case["U_nom"])[0], (T, 1)))
+    out = (C.c_longlong * 6)()
+    q0 = np.ascontiguousarray(case["q0"], dtype=float)
+    qd0 = np.ascontiguousarray(case["qd0"], dtype=float)
+    oc.oc_rollout(C.byref(rp), C.byref(cp), tgt.ctypes.data_as(D), q0.ctypes.data_as(D),
+                  qd0.ctypes.data_as(D), U.ctypes.data_as(D), T, out)
+    return np.array(list(out))
+
+
+def per_step(oc, case):
+    a, b = counts(oc, case, 1), counts(oc, case, 2)
+    step = b - a
+    return int(step[:4].sum()), int((a - step)[:4].sum())
+
+
+def test_bench_flop_constants_match_count(oc, workloads):
+    step, term = per_step(oc, workloads["wall_k4096"][0])
+    assert step == bench.FLOPS_PER_SAMPLE_STEP
+    assert term == bench.FLOPS_PER_SAMPLE_TERMINAL
+    # the count is a property of the code path, not of the inputs
+    for case in workloads["wall_k4096"][1:4]:
+        assert per_step(oc, case) == (step, term)
