@@ -44,6 +44,9 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the oracle CPU-baseline sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                   help="after the timed region, copy a MIB-sized buffer 5 times (a plain copy "
+                        "kernel of known size, to calibrate HBM byte counters)")
     return p.parse_args()
 
 
@@ -158,6 +161,13 @@ def main():
                      "kernel": "rollout_kernel<float, force>",
                      "flops_per_launch": flops},
     }
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * src.numel() * 4
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     solver.close()
