@@ -1,10 +1,12 @@
 // kernels.hip -- the MPPI hot path on gfx950.
 //
-//   rollout_kernel  (a1-a9): one sample per lane.  Noise from in-register
+//   update_kernel   (a1-a12): one sample per lane.  Noise from in-register
 //                   Philox, the per-step dynamics/cost of dyn.hpp, FP32 (or
 //                   FP64) cost accumulation; writes S_k and du[t][j][k]
-//                   (k fastest, so a wave's stores are coalesced).
-//   weights_kernel  (a10-a12): Eq. 4 with the minimum-cost shift.  Every
+//                   (k fastest, so a wave's stores are coalesced); then the
+//                   Eq. 4 weighting as per-wave partials merged by the last
+//                   block (one launch per update).
+//   weights_kernel  (a10-a12 alone, on given costs and noise).  Every
 //                   block recomputes S_min and eta = sum_k omega_k over the
 //                   K costs (L2-resident) and reduces omega_k du[row][k] for
 //                   its rows with wave shuffles; writes U_new and the shifted
@@ -31,29 +33,174 @@ __global__ void prep_model_kernel(const mppi_robot_params* __restrict__ P, Model
     }
 }
 
-template <typename R, bool FORCE>
-__global__ __launch_bounds__(kRolloutBlock) void rollout_kernel(
+template <typename A> __device__ __forceinline__ A wave_min(A v);
+template <typename A> __device__ __forceinline__ A wave_sum(A v);
+
+// One MPPI update in one launch (a1-a12).  Each block is one wave of 64
+// samples (one per lane).  Every lane rolls out its sample, writes S_k and
+// keeps du[t][j] in a padded LDS tile (rows x 65) when it fits, else in the
+// global noise buffer (also written when the caller asks for the noise).
+// The wave then reduces its samples to a partial of Eq. 4 with its own
+// shift m_w = min S_k:
+//   s_w = sum_k exp((m_w - S_k)/lambda),  V_w[r] = sum_k exp(...) du_k[r].
+// The last block to finish (device-scope counter) merges the partials with
+// the log-sum-exp rule m = min m_w, f_w = exp((m - m_w)/lambda),
+// U_new[r] = U_nom[r] + sum_w f_w V_w[r] / sum_w f_w s_w, which equals
+// Eq. 4b with S_min = m exactly in real arithmetic.  With merge == 0 the
+// kernel stops after the rollouts (costs and global noise only).
+constexpr int kLdsRowPad = 65;
+constexpr int kMaxDynLds = 48 * 1024;
+
+template <typename R, typename A, bool FORCE>
+__global__ __launch_bounds__(kRolloutBlock) void update_kernel(
     const ModelM<R>* __restrict__ Mp, const CostM<R>* __restrict__ Cp, const double* __restrict__ q0,
-    const double* __restrict__ qd0, const double* __restrict__ target, const double* __restrict__ U_nom,
-    uint64_t seed, uint32_t tick, int K, int T, R* __restrict__ noise, R* __restrict__ S)
+    const double* __restrict__ qd0, const double* __restrict__ target, const double* U_nom,
+    uint64_t seed, uint32_t tick, int K, int T, double lambda, R* __restrict__ noise,
+    R* __restrict__ S, int merge, int lds_noise, A* __restrict__ parts, unsigned int* __restrict__ counter,
+    double* U_new, double* __restrict__ U_shift, int* __restrict__ status)
 {
+    extern __shared__ char dyn_lds[];
     __shared__ R Us[kMaxT * NJ];
+    __shared__ A wl[64];
+    __shared__ int last;
     for (int i = threadIdx.x; i < T * NJ; i += blockDim.x) Us[i] = R(U_nom[i]);
     __syncthreads();
     const ModelM<R>& M = *Mp;
     const CostM<R>& C = *Cp;
-    TargetM<R> tg;
-    make_target(target, tg);
-    R q[NJ], qd[NJ], te[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) { q[j] = R(q0[j]); qd[j] = R(qd0[j]); te[j] = R(0); }
-    if (C.ext_mode == EXTW_CONST) const_ext_torque(M, C, q, te);
+    const int lane = threadIdx.x & 63;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < K) {
-        R s = rollout_sample<R, FORCE>(M, C, tg, q, qd, te, Us, T, seed, tick, (uint32_t)k,
-                                       noise + k, (size_t)K);
-        S[k] = finite_(s) ? s : R(INFINITY);
+    R* tile = reinterpret_cast<R*>(dyn_lds);   // [rows][65] when lds_noise
+    R s = R(INFINITY);
+    {
+        TargetM<R> tg;
+        make_target(target, tg);
+        R q[NJ], qd[NJ], te[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) { q[j] = R(q0[j]); qd[j] = R(qd0[j]); te[j] = R(0); }
+        if (C.ext_mode == EXTW_CONST) const_ext_torque(M, C, q, te);
+        if (k < K) {
+            R v = rollout_sample<R, FORCE>(M, C, tg, q, qd, te, Us, T, seed, tick, (uint32_t)k,
+                                           noise ? noise + k : nullptr, (size_t)K,
+                                           lds_noise ? tile + lane : nullptr, kLdsRowPad);
+            s = finite_(v) ? v : R(INFINITY);
+            S[k] = s;
+        } else if (lds_noise) {
+            for (int r = 0; r < T * NJ; ++r) tile[r * kLdsRowPad + lane] = R(0);
+        }
     }
+    if (!merge) return;
+
+    // ---- wave partial
+    const int rows = T * NJ;
+    const int P = 2 + rows;
+    const int kbase = blockIdx.x * blockDim.x;
+    const int nk = min(64, K - kbase);
+    const A inf = A(INFINITY), il = A(1) / A(lambda);
+    A m = wave_min(s < R(INFINITY) ? A(s) : inf);
+    A w = (s < R(INFINITY)) ? exp((m - A(s)) * il) : A(0);
+    A sw = wave_sum(w);
+    wl[lane] = w;
+    __syncthreads();
+    A* part = parts + (size_t)blockIdx.x * P;
+    if (lds_noise) {
+        // lane r sums row r of the tile (row stride 65: conflict-free)
+        for (int r = lane; r < rows; r += 64) {
+            const R* row = tile + r * kLdsRowPad;
+            A acc = A(0);
+#pragma unroll 16
+            for (int i = 0; i < 64; ++i) acc += wl[i] * A(row[i]);
+            part[2 + r] = acc;
+        }
+    } else {
+        // global noise: stage 64 rows at a time with coalesced loads along k
+        A* trt = reinterpret_cast<A*>(dyn_lds);   // [64][65]
+        for (int c0 = 0; c0 < rows; c0 += 64) {
+            const int nr = min(64, rows - c0);
+#pragma unroll 8
+            for (int rr = 0; rr < nr; ++rr)
+                trt[rr * kLdsRowPad + lane] = lane < nk ? A(noise[(size_t)(c0 + rr) * K + kbase + lane]) : A(0);
+            __syncthreads();
+            if (lane < nr) {
+                A acc = A(0);
+#pragma unroll 16
+                for (int i = 0; i < 64; ++i) acc += wl[i] * trt[lane * kLdsRowPad + i];
+                part[2 + c0 + lane] = acc;
+            }
+            __syncthreads();
+        }
+    }
+    if (lane == 0) { part[0] = m; part[1] = sw; }
+
+    // ---- the last block merges all partials
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const int np = gridDim.x;
+    A mg = inf;
+    for (int p = lane; p < np; p += 64) mg = fmin(mg, parts[(size_t)p * P]);
+    mg = wave_min(mg);
+    if (!(mg < inf)) {  // no finite cost: keep the nominal sequence
+        for (int r = lane; r < rows; r += 64) {
+            const int t = r / NJ, j = r % NJ;
+            const double un = U_nom[r];
+            U_new[r] = un;
+            if (U_shift) {
+                if (t >= 1) U_shift[(t - 1) * NJ + j] = un;
+                if (t == T - 1) U_shift[t * NJ + j] = un;
+            }
+        }
+        if (status && lane == 0) *status = MPPI_ENONFINITE;
+        if (lane == 0) *counter = 0u;
+        return;
+    }
+    A eta = A(0);
+    for (int p = lane; p < np; p += 64) {
+        A mp = parts[(size_t)p * P];
+        if (mp < inf) eta += exp((mg - mp) * il) * parts[(size_t)p * P + 1];
+    }
+    eta = wave_sum(eta);
+    // rows r0 + lane: V[r] = sum_p f_p V_p[r], f_p = exp((m - m_p)/lambda),
+    // 64 partials at a time (factors staged in LDS, loads coalesced along r)
+    for (int r0 = 0; r0 < rows; r0 += 64) {
+        const int r = r0 + lane;
+        A acc = A(0);
+        for (int p0 = 0; p0 < np; p0 += 64) {
+            const int p = p0 + lane;
+            A f = A(0);
+            if (p < np) {
+                A mp = parts[(size_t)p * P];
+                f = (mp < inf) ? exp((mg - mp) * il) : A(0);
+            }
+            __syncthreads();
+            wl[lane] = f;
+            __syncthreads();
+            if (r < rows) {
+                if (np - p0 >= 64) {
+                    A v[64];
+#pragma unroll
+                    for (int i = 0; i < 64; ++i) v[i] = parts[(size_t)(p0 + i) * P + 2 + r];
+#pragma unroll
+                    for (int i = 0; i < 64; ++i) acc += wl[i] * v[i];
+                } else {
+                    for (int i = 0; i < np - p0; ++i) acc += wl[i] * parts[(size_t)(p0 + i) * P + 2 + r];
+                }
+            }
+        }
+        if (r < rows) {
+            const int t = r / NJ, j = r % NJ;
+            const double un = U_nom[r] + double(acc / eta);
+            U_new[r] = un;
+            if (U_shift) {
+                if (t >= 1) U_shift[(t - 1) * NJ + j] = un;
+                if (t == T - 1) U_shift[t * NJ + j] = un;
+            }
+        }
+    }
+    if (status && lane == 0) *status = MPPI_OK;
+    if (lane == 0) *counter = 0u;
 }
 
 template <typename A> __device__ __forceinline__ A wave_min(A v)
@@ -181,20 +328,36 @@ hipError_t launch_prep_model(const mppi_robot_params* d_raw, ModelM<float>* d_mf
     return hipGetLastError();
 }
 
-template <typename R, bool FORCE> static hipError_t rollout_t(const RolloutArgs& a, hipStream_t s)
+template <typename R, typename A, bool FORCE> static hipError_t update_t(const UpdateArgs& a, hipStream_t s)
 {
     dim3 grid((a.K + kRolloutBlock - 1) / kRolloutBlock);
-    hipLaunchKernelGGL((rollout_kernel<R, FORCE>), grid, dim3(kRolloutBlock), 0, s,
-                       (const ModelM<R>*)a.model, (const CostM<R>*)a.cost, a.q0, a.qd0, a.target,
-                       a.U_nom, a.seed, (uint32_t)a.tick, a.K, a.T, (R*)a.noise, (R*)a.costs);
+    const size_t rows = (size_t)a.T * NJ;
+    const size_t tile = rows * kLdsRowPad * sizeof(R);
+    const int lds_noise = a.merge && tile <= (size_t)kMaxDynLds;
+    const size_t dyn = lds_noise ? tile : (a.merge ? 64 * kLdsRowPad * sizeof(A) : 0);
+    // global noise: always for rollouts-only launches and the global-tile
+    // path; otherwise only when the caller asked for it
+    R* noise = (R*)a.noise;
+    if (a.merge && lds_noise && !a.want_noise) noise = nullptr;
+    hipLaunchKernelGGL((update_kernel<R, A, FORCE>), grid, dim3(kRolloutBlock), dyn, s,
+                       (const ModelM<R>*)a.model, (const CostM<R>*)a.cost, a.q0, a.qd0, a.target, a.U_nom,
+                       a.seed, (uint32_t)a.tick, a.K, a.T, a.lambda, noise, (R*)a.costs, a.merge, lds_noise,
+                       (A*)a.parts, a.counter, a.U_new, a.U_shift, a.status);
     return hipGetLastError();
 }
 
-hipError_t launch_rollout(int precision, bool force, const RolloutArgs& a, hipStream_t s)
+hipError_t launch_update(int precision, bool acc64, bool force, const UpdateArgs& a, hipStream_t s)
 {
     if (a.T < 1 || a.T > kMaxT || a.K < 1) return hipErrorInvalidValue;
-    if (precision == MPPI_FP64) return force ? rollout_t<double, true>(a, s) : rollout_t<double, false>(a, s);
-    return force ? rollout_t<float, true>(a, s) : rollout_t<float, false>(a, s);
+    if (precision == MPPI_FP64)
+        return force ? update_t<double, double, true>(a, s) : update_t<double, double, false>(a, s);
+    if (acc64) return force ? update_t<float, double, true>(a, s) : update_t<float, double, false>(a, s);
+    return force ? update_t<float, float, true>(a, s) : update_t<float, float, false>(a, s);
+}
+
+size_t update_parts_bytes(int K, int T)
+{
+    return (size_t)((K + kRolloutBlock - 1) / kRolloutBlock) * (2 + (size_t)T * NJ) * sizeof(double);
 }
 
 template <typename R, typename A> static hipError_t weights_t(const WeightsArgs& a, hipStream_t s)

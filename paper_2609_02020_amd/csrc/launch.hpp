@@ -8,20 +8,6 @@
 
 namespace mppi {
 
-struct RolloutArgs {
-    const void* model;      // ModelM<R>* (device)
-    const void* cost;       // CostM<R>* (device)
-    const double* q0;
-    const double* qd0;
-    const double* target;   // 13 doubles
-    const double* U_nom;    // [T][7]
-    uint64_t seed;
-    uint64_t tick;
-    int K, T;
-    void* noise;            // R [T][7][K]
-    void* costs;            // R [K]
-};
-
 struct WeightsArgs {
     const void* costs;      // R [K]
     const void* noise;      // R [T][7][K]
@@ -33,10 +19,34 @@ struct WeightsArgs {
     double lambda;
 };
 
+struct UpdateArgs {
+    const void* model;
+    const void* cost;
+    const double* q0;
+    const double* qd0;
+    const double* target;
+    const double* U_nom;
+    uint64_t seed;
+    uint64_t tick;
+    int K, T;
+    double lambda;
+    void* noise;            // R [T][7][K]
+    void* costs;            // R [K]
+    int merge;              // 0: rollouts only
+    int want_noise;         // the caller asked for the noise (global copy)
+    void* parts;            // A [ceil(K/64)][2 + 7T]
+    unsigned int* counter;  // zero before the launch; the kernel leaves it zero
+    double* U_new;
+    double* U_shift;
+    int* status;
+};
+
+// One fused launch: rollouts, per-wave Eq. 4 partials, last-block merge.
+hipError_t launch_update(int precision, bool acc64, bool force, const UpdateArgs& a, hipStream_t s);
+size_t update_parts_bytes(int K, int T);
+
 hipError_t launch_prep_model(const mppi_robot_params* d_raw, ModelM<float>* d_mf, ModelM<double>* d_md,
                              hipStream_t s);
-// precision: MPPI_FP32 / MPPI_FP64; force: the force-cost instantiation
-hipError_t launch_rollout(int precision, bool force, const RolloutArgs& a, hipStream_t s);
 // acc64: accumulate the weights and sums in FP64
 hipError_t launch_weights(int precision, bool acc64, const WeightsArgs& a, hipStream_t s);
 hipError_t launch_plant(const ModelM<double>* M, const CostM<double>* C, double* q, double* qd,

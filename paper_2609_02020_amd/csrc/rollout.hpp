@@ -16,10 +16,13 @@ namespace mppi {
 
 template <typename R> MPPI_HD bool finite_(R x) { return x - x == R(0); }
 
+// noise_out / noise_lds (either may be null) receive du[t][j] at
+// (t*7 + j) * stride.
 template <typename R, bool FORCE, typename UT>
 MPPI_HD R rollout_sample(const ModelM<R>& M, const CostM<R>& C, const TargetM<R>& tg,
                          const R* q0, const R* qd0, const R* tau_ext_c, const UT* U_nom, int T,
-                         uint64_t seed, uint32_t tick, uint32_t k, R* noise_out, size_t noise_stride)
+                         uint64_t seed, uint32_t tick, uint32_t k, R* noise_out, size_t noise_stride,
+                         R* noise_lds = nullptr, int lds_stride = 0)
 {
     R q[NJ], qd[NJ], S = R(0);
 #pragma unroll
@@ -32,6 +35,7 @@ MPPI_HD R rollout_sample(const ModelM<R>& M, const CostM<R>& C, const TargetM<R>
         for (int j = 0; j < NJ; ++j) {
             R du = C.sigma[j] * z[j];
             if (noise_out) noise_out[(size_t)(t * NJ + j) * noise_stride] = du;
+            if (noise_lds) noise_lds[(t * NJ + j) * lds_stride] = du;
             v[j] = R(U_nom[t * NJ + j]) + du;
             tau[j] = v[j] + tau_ext_c[j];
         }

@@ -25,6 +25,8 @@ struct mppi_solver {
     CostM<double>* d_cd = nullptr;
     void* d_noise = nullptr;     // R [T][7][K]
     void* d_costs = nullptr;     // R [K]
+    void* d_parts = nullptr;     // per-wave Eq. 4 partials (FP64-sized)
+    unsigned int* d_counter = nullptr;  // last-block counter of the fused update
     int* d_status = nullptr;
     double* d_io = nullptr;      // q 7 | qd 7 | target 13 | U_nom T*7 | U_new T*7
     double* h_io = nullptr;      // pinned mirror of d_io
@@ -150,6 +152,8 @@ void release(mppi_solver* h)
     (void)hipFree(h->d_cd);
     (void)hipFree(h->d_noise);
     (void)hipFree(h->d_costs);
+    (void)hipFree(h->d_parts);
+    (void)hipFree(h->d_counter);
     (void)hipFree(h->d_status);
     (void)hipFree(h->d_io);
     (void)hipHostFree(h->h_io);
@@ -159,9 +163,14 @@ void release(mppi_solver* h)
     delete h;
 }
 
-int rollout_enqueue(mppi_solver* h, const mppi_device_io* io, hipStream_t s, void* noise, void* costs)
+bool acc64_of(const mppi_cost_params& c) { return c.precision == MPPI_FP64 || c.lambda < c.lambda_fp64_threshold; }
+
+// merge = false: rollouts only (costs, noise); merge = true: the full update.
+int update_enqueue(mppi_solver* h, const mppi_device_io* io, hipStream_t s, void* noise, void* costs, bool merge,
+                   bool want_noise)
 {
-    RolloutArgs a;
+    UpdateArgs a;
+    a.want_noise = want_noise ? 1 : 0;
     const bool fp64 = h->cost.precision == MPPI_FP64;
     a.model = fp64 ? (const void*)h->d_md : (const void*)h->d_mf;
     a.cost = fp64 ? (const void*)h->d_cd : (const void*)h->d_cf;
@@ -173,9 +182,18 @@ int rollout_enqueue(mppi_solver* h, const mppi_device_io* io, hipStream_t s, voi
     a.tick = io->tick;
     a.K = h->cost.K;
     a.T = h->cost.T;
+    a.lambda = h->cost.lambda;
     a.noise = noise;
     a.costs = costs;
-    return launch_rollout(h->cost.precision, has_force(h->cost), a, s) == hipSuccess ? MPPI_OK : MPPI_EDEVICE;
+    a.merge = merge ? 1 : 0;
+    a.parts = h->d_parts;
+    a.counter = h->d_counter;
+    a.U_new = io->U_new;
+    a.U_shift = io->U_shift;
+    a.status = io->status;
+    return launch_update(h->cost.precision, acc64_of(h->cost), has_force(h->cost), a, s) == hipSuccess
+               ? MPPI_OK
+               : MPPI_EDEVICE;
 }
 
 int weights_enqueue(mppi_solver* h, const mppi_device_io* io, hipStream_t s, const void* noise,
@@ -191,8 +209,7 @@ int weights_enqueue(mppi_solver* h, const mppi_device_io* io, hipStream_t s, con
     w.K = h->cost.K;
     w.T = h->cost.T;
     w.lambda = h->cost.lambda;
-    const bool acc64 = h->cost.lambda < h->cost.lambda_fp64_threshold;
-    return launch_weights(h->cost.precision, acc64, w, s) == hipSuccess ? MPPI_OK : MPPI_EDEVICE;
+    return launch_weights(h->cost.precision, acc64_of(h->cost), w, s) == hipSuccess ? MPPI_OK : MPPI_EDEVICE;
 }
 
 int check_io(const mppi_solver* h, const mppi_device_io* io, bool need_out)
@@ -230,6 +247,8 @@ int mppi_create(const mppi_robot_params* robot, const mppi_cost_params* cost, mp
               hipMalloc(&h->d_cd, sizeof(CostM<double>)) == hipSuccess &&
               hipMalloc(&h->d_noise, K * T * MPPI_NJ * rs) == hipSuccess &&
               hipMalloc(&h->d_costs, K * rs) == hipSuccess &&
+              hipMalloc(&h->d_parts, update_parts_bytes((int)K, (int)T)) == hipSuccess &&
+              hipMalloc(&h->d_counter, sizeof(unsigned int)) == hipSuccess &&
               hipMalloc(&h->d_status, sizeof(int)) == hipSuccess &&
               hipMalloc(&h->d_io, io_n * sizeof(double)) == hipSuccess &&
               hipHostMalloc(&h->h_io, io_n * sizeof(double), hipHostMallocDefault) == hipSuccess &&
@@ -237,7 +256,8 @@ int mppi_create(const mppi_robot_params* robot, const mppi_cost_params* cost, mp
               hipHostMalloc(&h->h_status, sizeof(int), hipHostMallocDefault) == hipSuccess;
     if (!ok) { release(h); return MPPI_ENOMEM; }
     if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) { release(h); return MPPI_EDEVICE; }
-    if (hipMemcpy(h->d_raw, robot, sizeof *robot, hipMemcpyHostToDevice) != hipSuccess ||
+    if (hipMemset(h->d_counter, 0, sizeof(unsigned int)) != hipSuccess ||
+        hipMemcpy(h->d_raw, robot, sizeof *robot, hipMemcpyHostToDevice) != hipSuccess ||
         launch_prep_model(h->d_raw, h->d_mf, h->d_md, h->stream) != hipSuccess ||
         hipStreamSynchronize(h->stream) != hipSuccess || upload_cost(h) != MPPI_OK) {
         release(h);
@@ -271,8 +291,8 @@ int mppi_rollout_async(mppi_handle_t h, const mppi_device_io* io, void* stream)
 {
     int st = check_io(h, io, false);
     if (st) return st;
-    return rollout_enqueue(h, io, (hipStream_t)stream, io->noise ? io->noise : h->d_noise,
-                           io->costs ? io->costs : h->d_costs);
+    return update_enqueue(h, io, (hipStream_t)stream, io->noise ? io->noise : h->d_noise,
+                          io->costs ? io->costs : h->d_costs, false, true);
 }
 
 int mppi_weights_async(mppi_handle_t h, const mppi_device_io* io, void* stream)
@@ -287,11 +307,8 @@ int mppi_update_async(mppi_handle_t h, const mppi_device_io* io, void* stream)
 {
     int st = check_io(h, io, true);
     if (st) return st;
-    void* noise = io->noise ? io->noise : h->d_noise;
-    void* costs = io->costs ? io->costs : h->d_costs;
-    st = rollout_enqueue(h, io, (hipStream_t)stream, noise, costs);
-    if (st) return st;
-    return weights_enqueue(h, io, (hipStream_t)stream, noise, costs);
+    return update_enqueue(h, io, (hipStream_t)stream, io->noise ? io->noise : h->d_noise,
+                          io->costs ? io->costs : h->d_costs, true, io->noise != nullptr);
 }
 
 int mppi_update(mppi_handle_t h, const double* q, const double* qd, const mppi_target* target,
@@ -326,8 +343,7 @@ int mppi_update(mppi_handle_t h, const double* q, const double* qd, const mppi_t
     io.status = h->d_status;
     io.seed = seed;
     io.tick = tick;
-    int st = rollout_enqueue(h, &io, s, h->d_noise, h->d_costs);
-    if (!st) st = weights_enqueue(h, &io, s, h->d_noise, h->d_costs);
+    int st = update_enqueue(h, &io, s, h->d_noise, h->d_costs, true, false);
     if (st) return st;
     if (hipMemcpyAsync(hio + in_n, h->d_io + in_n, (size_t)T * 7 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(h->h_status, h->d_status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)

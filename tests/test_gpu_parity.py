@@ -67,11 +67,12 @@ def test_wall_k4096_full_size_parity(ora, workloads):
         solver.close()
 
 
-@pytest.mark.parametrize("K,T", [(1, 18), (63, 7), (65, 1), (1000, 5), (4097, 3)])
+@pytest.mark.parametrize("K,T", [(1, 18), (63, 7), (65, 1), (1000, 5), (4097, 3), (300, 40)])
 def test_ragged_sizes(ora, workloads, K, T):
     case = workloads["wall_k4096"][3]
     cost = dict(case["cost"], K=K, T=T)
-    case = dict(case, cost=cost, U_nom=np.array(case["U_nom"])[:T])
+    U = np.array(case["U_nom"])
+    case = dict(case, cost=cost, U_nom=np.concatenate([U, np.repeat(U[-1:], max(0, T - len(U)), 0)])[:T])
     print("ragged K=%d T=%d" % (K, T), flush=True)
     solver = B.Solver(case["robot"], cost, B.FP32)
     out = device_update(solver, case, 99, 3, B.FP32)
@@ -148,3 +149,37 @@ def test_plant_step_matches_oracle(ora, workloads):
         assert np.abs(q.cpu().numpy() - qr).max() < 1e-9
         assert np.abs(qd.cpu().numpy() - qdr).max() < 1e-8
         solver.close()
+
+
+def test_stage_entry_points_compose_to_the_fused_update(ora, workloads):
+    """rollout_async (costs, noise) followed by weights_async gives the fused
+    update's U_new; the fused kernel's merged per-wave partials equal the
+    one-pass weighting up to rounding."""
+    torch, dev = torch_dev()
+    case = workloads["wall_k4096"][4]
+    solver = B.Solver(case["robot"], case["cost"], B.FP32)
+    fused = device_update(solver, case, 55, 2, B.FP32)
+    io = fused["io"]
+    U_fused = io["U_new"].clone()
+    io["U_new"].fill_(float("nan"))
+    solver.rollout_async(io)
+    solver.weights_async(io)
+    torch.cuda.synchronize()
+    assert np.abs(io["U_new"].cpu().numpy() - U_fused.cpu().numpy()).max() < 1e-5
+    solver.close()
+
+
+@pytest.mark.parametrize("K", [16384, 20000])
+def test_many_block_merge(ora, workloads, K):
+    """Hundreds of partials merged by the last block (K/64 waves)."""
+    case = workloads["wall_k4096"][5]
+    cost = dict(case["cost"], K=K, T=6)
+    case = dict(case, cost=cost, U_nom=np.array(case["U_nom"])[:6])
+    solver = B.Solver(case["robot"], cost, B.FP32)
+    out = device_update(solver, case, 7, 1, B.FP32)
+    U_ref, S_ref, _ = oracle_update(ora, case, cost, 7, 1)
+    check_costs_fp32(ora, case, out["costs"], S_ref, 7, 1, "K=%d" % K)
+    note = check_update(ora, case, out, 1.0, S_ref, U_ref, "K=%d" % K)
+    if note:
+        print(note)
+    solver.close()
