@@ -95,8 +95,8 @@ template <typename R> MPPI_HD R sq(R x) { return x * x; }
 template <typename R> struct LinkM {
     R Rp[9];      // R_parent, row-major
     R rp[3];      // r_parent
-    R Io[6];      // rotational inertia about the link-frame origin (xx yy zz xy xz yz)
-    R mc[3];      // mass * CoM
+    R Ic[6];      // inertia about the CoM, link-frame axes (xx yy zz xy xz yz)
+    R com[3];     // CoM in the link frame
     R m;          // mass
     R arm;        // armature
     R qmin, qmax, qdmax, taumax;
@@ -199,114 +199,11 @@ template <bool TRANS, typename R> MPPI_HD void congr_sym3(const R* Q, const R* M
         for (int j = i; j < 3; ++j)
             out[si(i, j)] = T[i * 3] * q(j, 0) + T[i * 3 + 1] * q(j, 1) + T[i * 3 + 2] * q(j, 2);
 }
-// out = Q B Q^T (TRANS = false) or Q^T B Q (TRANS = true), B general
-template <bool TRANS, typename R> MPPI_HD void congr_gen3(const R* Q, const R* B, R* out)
-{
-    auto q = [&](int i, int j) -> R { return TRANS ? Q[j * 3 + i] : Q[i * 3 + j]; };
-    R T[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            T[i * 3 + j] = q(i, 0) * B[j] + q(i, 1) * B[3 + j] + q(i, 2) * B[6 + j];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            out[i * 3 + j] = T[i * 3] * q(j, 0) + T[i * 3 + 1] * q(j, 1) + T[i * 3 + 2] * q(j, 2);
-}
-
-// (r x) M for general M, returned row-major: row i = r x (column) ...
-// P_ij = sum_k rx_ik M_kj with rx = [[0,-r2,r1],[r2,0,-r0],[-r1,r0,0]]
-template <typename R> MPPI_HD void rx_mul(const R* r, const R* M, R* P)
-{
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        R m0 = M[j], m1 = M[3 + j], m2 = M[6 + j];
-        P[j] = r[1] * m2 - r[2] * m1;
-        P[3 + j] = r[2] * m0 - r[0] * m2;
-        P[6 + j] = r[0] * m1 - r[1] * m0;
-    }
-}
-// symmetric M (sym3 storage) -> full
-template <typename R> MPPI_HD void sym_full(const R* S, R* F)
-{
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) F[i * 3 + j] = S[si(i, j)];
-}
-
 template <typename R> struct Sym6 {
     R A[6];
     R B[9];
     R C[6];
 };
-
-// Force-side congruence child -> parent: out = X^T Ia X (Ia in child
-// coordinates) for X = [E 0; -E rx E], E = Q^T.
-// Rotate to parent axes: A1 = Q A Q^T, B1 = Q B Q^T, C1 = Q C Q^T; shift
-// the reference point by r: C' = C1, B' = B1 + rx C1,
-// A' = A1 + rx B1^T + (rx B1^T)^T - rx C1 rx.
-template <typename R> MPPI_HD void congr_force(const R* Q, const R* r, const Sym6<R>& Ia, Sym6<R>& out)
-{
-    R A1[6], B1[9], C1[6], C1f[9], P[9], G[9], B1t[9];
-    congr_sym3<false>(Q, Ia.A, A1);
-    congr_gen3<false>(Q, Ia.B, B1);
-    congr_sym3<false>(Q, Ia.C, C1);
-    sym_full(C1, C1f);
-    rx_mul(r, C1f, P);                       // P = rx C1
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) B1t[i * 3 + j] = B1[j * 3 + i];
-    rx_mul(r, B1t, G);                       // G = rx B1^T
-#pragma unroll
-    for (int i = 0; i < 6; ++i) out.C[i] = C1[i];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) out.B[i] = B1[i] + P[i];
-    // (rx C1 rx)_ij = (P rx)_ij = P_i0 rx_0j + P_i1 rx_1j + P_i2 rx_2j with
-    // rx = [[0, -r2, r1], [r2, 0, -r0], [-r1, r0, 0]]
-    const R rx[9] = {R(0), -r[2], r[1], r[2], R(0), -r[0], -r[1], r[0], R(0)};
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j) {
-            R prx = P[i * 3] * rx[j] + P[i * 3 + 1] * rx[3 + j] + P[i * 3 + 2] * rx[6 + j];
-            out.A[si(i, j)] = A1[si(i, j)] + G[i * 3 + j] + G[j * 3 + i] - prx;
-        }
-}
-
-// Motion-side congruence parent -> child: out = X Om X^T (Om in parent
-// coordinates).  Shift: A' = A, B' = A rx + B,
-// C' = C - rx B - (rx B)^T - rx A rx; then rotate by E = Q^T.
-template <typename R> MPPI_HD void congr_motion(const R* Q, const R* r, const Sym6<R>& Om, Sym6<R>& out)
-{
-    R Af[9], W[9], Bs[9], G[9], C2[6];
-    sym_full(Om.A, Af);
-    // W = A rx : W_ij = sum_k A_ik rx_kj  -> equals -(rx A)^T ... compute directly
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        R a0 = Af[i * 3], a1 = Af[i * 3 + 1], a2 = Af[i * 3 + 2];
-        W[i * 3 + 0] = a1 * r[2] - a2 * r[1];
-        W[i * 3 + 1] = a2 * r[0] - a0 * r[2];
-        W[i * 3 + 2] = a0 * r[1] - a1 * r[0];
-    }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) Bs[i] = W[i] + Om.B[i];
-    rx_mul(r, Om.B, G);                      // G = rx B
-    // rx A rx = rx W
-    R H[9];
-    rx_mul(r, W, H);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j)
-            C2[si(i, j)] = Om.C[si(i, j)] - G[i * 3 + j] - G[j * 3 + i] - H[i * 3 + j];
-    congr_sym3<true>(Q, Om.A, out.A);
-    congr_gen3<true>(Q, Bs, out.B);
-    congr_sym3<true>(Q, C2, out.C);
-}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller
@@ -425,14 +322,131 @@ template <typename R> MPPI_HD void chol6_solve(const Sym6<R>& S, R* b)
 }
 
 // ---------------------------------------------------------------------------
-// one dynamics step
+// one dynamics step: articulated-body algorithm in world-aligned frames
+// centred on the joints
 // ---------------------------------------------------------------------------
+// Frame i has world axes and its origin at joint i's origin p_i; spatial
+// vectors are [angular; linear] about p_i.  Joint i then has the motion
+// subspace S_i = (z_i, 0), and moving between links is a pure translation
+// by r_i = p_i - p_{i-1} (no rotation):
+//   motion  (w, v) at p_{i-1} -> (w, v + w x r_i) at p_i
+//   force   (n, f) at p_{i+1} -> (n + r_{i+1} x f, f) at p_i
+// The spatial inertia of link i about p_i is
+//   I_i = [Ibar_c + m (|c|^2 1 - c c^T),  m c x;  (m c x)^T,  m 1],
+// Ibar_c = R_i I_c R_i^T, c = R_i com (CoM relative to p_i).  Moment arms
+// stay at link length, which keeps FP32 rounding at the level of a
+// link-local formulation while avoiding its per-link rotations.
+//   pass 1 (root->tip): v_i = X_i v_{i-1} + S_i qd_i, c_i = v_i x S_i qd_i,
+//                       p_i = v_i x* I_i v_i - f_ext,i
+//   pass 2 (tip->root): IA_i = I_i + X_{i+1}^T Ia_{i+1} X_{i+1},
+//                       pA_i = p_i + X_{i+1}^T pa_{i+1},
+//                       U_i = IA_i S_i, D_i = S_i.U_i + a_i, u_i = tau_i - S_i.pA_i,
+//                       Ia_i = IA_i - U_i U_i^T / D_i, pa_i = pA_i + Ia_i c_i + U_i u_i / D_i
+//   pass 3 (root->tip): a'_i = X_i a_{i-1} + c_i, qdd_i = (u_i - U_i.a'_i) / D_i,
+//                       a_i = a'_i + S_i qdd_i, a_{-1} = (0, -g)
+// Force path (Eq. 13): Omega_i = P_i X_i Omega_{i-1} X_i^T P_i^T + S_i S_i^T / D_i,
+// P_i = 1 - S_i U_i^T / D_i, Omega_{-1} = 0, gives Omega_n = J_n M^-1 J_n^T
+// about p_n; a zero-velocity solve with torques tau_F gives b = J_n M^-1 tau_F
+// (the uniform gravity pseudo-acceleration removed); x = Omega_n^-1 b is the
+// spatial force about p_n and the EE wrench is F = x_f,
+// N = x_n - (p_ee - p_n) x x_f.
 template <typename R> struct StepOut {
     R qdd[NJ];
     R pee[3];      // EE point, world
     R Rn[9];       // last link orientation, world
     R F[6];        // EE wrench estimate [force; moment] (FORCE only)
 };
+
+template <typename R> MPPI_HD void sym6_mv(const Sym6<R>& M, const R* x, R* y)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        y[a] = M.A[si(a, 0)] * x[0] + M.A[si(a, 1)] * x[1] + M.A[si(a, 2)] * x[2] +
+               M.B[a * 3] * x[3] + M.B[a * 3 + 1] * x[4] + M.B[a * 3 + 2] * x[5];
+        y[3 + a] = M.B[a] * x[0] + M.B[3 + a] * x[1] + M.B[6 + a] * x[2] +
+                   M.C[si(a, 0)] * x[3] + M.C[si(a, 1)] * x[4] + M.C[si(a, 2)] * x[5];
+    }
+}
+template <typename R> MPPI_HD R dot6(const R* a, const R* b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3] + a[4] * b[4] + a[5] * b[5];
+}
+// M += x y^T + y x^T (symmetric storage)
+template <typename R> MPPI_HD void sym6_rank2(Sym6<R>& M, const R* x, const R* y)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b) {
+            M.A[si(a, b)] += x[a] * y[b] + y[a] * x[b];
+            M.C[si(a, b)] += x[3 + a] * y[3 + b] + y[3 + a] * x[3 + b];
+        }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) M.B[a * 3 + b] += x[a] * y[3 + b] + y[a] * x[3 + b];
+}
+// rx M for a general 3x3 M (row-major): P_ij = sum_k rx_ik M_kj
+template <typename R> MPPI_HD void rx_mul(const R* r, const R* M, R* P)
+{
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        R m0 = M[j], m1 = M[3 + j], m2 = M[6 + j];
+        P[j] = r[1] * m2 - r[2] * m1;
+        P[3 + j] = r[2] * m0 - r[0] * m2;
+        P[6 + j] = r[0] * m1 - r[1] * m0;
+    }
+}
+// Force-side shift of a symmetric spatial matrix from a reference point p'
+// to p = p' - r (r = p' - p): out = X^T M X with X = [1 0; -rx 1]:
+//   C' = C, B' = B + rx C, A' = A + rx B^T + (rx B^T)^T - rx C rx.
+template <typename R> MPPI_HD void shift_force(const R* r, Sym6<R>& M)
+{
+    R Cf[9], P[9], Bt[9], G[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) { Cf[i * 3 + j] = M.C[si(i, j)]; Bt[i * 3 + j] = M.B[j * 3 + i]; }
+    rx_mul(r, Cf, P);   // rx C
+    rx_mul(r, Bt, G);   // rx B^T
+    const R rx[9] = {R(0), -r[2], r[1], r[2], R(0), -r[0], -r[1], r[0], R(0)};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) {
+            R prx = P[i * 3] * rx[j] + P[i * 3 + 1] * rx[3 + j] + P[i * 3 + 2] * rx[6 + j];
+            M.A[si(i, j)] += G[i * 3 + j] + G[j * 3 + i] - prx;
+        }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) M.B[i] += P[i];
+}
+// Motion-side shift from p' to p = p' + r: out = X M X^T, X = [1 0; -rx 1]:
+//   A' = A, B' = B + A rx, C' = C - rx B - (rx B)^T - rx A rx.
+template <typename R> MPPI_HD void shift_motion(const R* r, Sym6<R>& M)
+{
+    R Af[9], W[9], G[9], H[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Af[i * 3 + j] = M.A[si(i, j)];
+    // W = A rx: W_ij = sum_k A_ik rx_kj
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        R a0 = Af[i * 3], a1 = Af[i * 3 + 1], a2 = Af[i * 3 + 2];
+        W[i * 3 + 0] = a1 * r[2] - a2 * r[1];
+        W[i * 3 + 1] = a2 * r[0] - a0 * r[2];
+        W[i * 3 + 2] = a0 * r[1] - a1 * r[0];
+    }
+    rx_mul(r, M.B, G);  // rx B
+    rx_mul(r, W, H);    // rx A rx
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j)
+            M.C[si(i, j)] += -G[i * 3 + j] - G[j * 3 + i] - H[i * 3 + j];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) M.B[i] += W[i];
+}
 
 // ext: EXTW_NONE, EXTW_CONST (world wrench F_ext at the EE point, current
 // configuration) or EXTW_WALL (the cost's wall model).  tau: joint torques
@@ -442,68 +456,79 @@ template <typename R, bool FORCE>
 MPPI_HD void dyn_step(const ModelM<R>& M, const CostM<R>& Cst, int ext, const R* q, const R* qd,
                       const R* tau, const R* v, StepOut<R>& out)
 {
-    R cq[NJ], sq_[NJ];
-#pragma unroll
-    for (int i = 0; i < NJ; ++i) sincos_(q[i], &sq_[i], &cq[i]);
+    R z[NJ][3];      // joint axes (world)
+    R rr[NJ][3];     // p_i - p_{i-1} (r_0 = p_0)
+    R cc[NJ][6];     // velocity-product accelerations, about p_i
+    R pA[NJ][6];     // bias forces, about p_i
+    R Iw[NJ][6];     // rotational inertia about p_i, world axes (sym storage)
+    R mc[NJ][3];     // m c, c = CoM - p_i
 
-    // ---- pass 1 (root -> tip): world FK, link velocities, bias forces
+    // ---- pass 1 (root -> tip)
     R Rw[9] = {R(1), R(0), R(0), R(0), R(1), R(0), R(0), R(0), R(1)};
     R pw[3] = {R(0), R(0), R(0)};
-    R w[3] = {R(0), R(0), R(0)}, vl[3] = {R(0), R(0), R(0)};
-    R cc[NJ][4];     // nonzero entries of c_i = v_i x S qd_i: (0,1,3,4)
-    R pA[NJ][6];
+    R vw[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
         const LinkM<R>& L = M.L[i];
-        R Q[9];
-        joint_rot(L.Rp, cq[i], sq_[i], Q);
-        R d[3];
-        mv3(Rw, L.rp, d);
-        pw[0] += d[0]; pw[1] += d[1]; pw[2] += d[2];
+        R c, s, Q[9];
+        sincos_(q[i], &s, &c);
+        joint_rot(L.Rp, c, s, Q);
+        mv3(Rw, L.rp, rr[i]);
+        pw[0] += rr[i][0]; pw[1] += rr[i][1]; pw[2] += rr[i][2];
         mm3(Rw, Q, Rw);
-        // v_i = X_i v_{i-1} + S qd_i
-        R rxw[3], t[3];
-        cross3(L.rp, w, rxw);
-        t[0] = vl[0] - rxw[0]; t[1] = vl[1] - rxw[1]; t[2] = vl[2] - rxw[2];
-        mtv3(Q, w, w);
-        w[2] += qd[i];
-        mtv3(Q, t, vl);
-        cc[i][0] = qd[i] * w[1];
-        cc[i][1] = -qd[i] * w[0];
-        cc[i][2] = qd[i] * vl[1];
-        cc[i][3] = -qd[i] * vl[0];
-        // h = I v ; pA = v x* h
-        R hn[3], hf[3], t1[3], t2[3];
-        hn[0] = L.Io[0] * w[0] + L.Io[3] * w[1] + L.Io[4] * w[2];
-        hn[1] = L.Io[3] * w[0] + L.Io[1] * w[1] + L.Io[5] * w[2];
-        hn[2] = L.Io[4] * w[0] + L.Io[5] * w[1] + L.Io[2] * w[2];
-        cross3(L.mc, vl, t1);
-        hn[0] += t1[0]; hn[1] += t1[1]; hn[2] += t1[2];
-        cross3(L.mc, w, t2);
-        hf[0] = L.m * vl[0] - t2[0]; hf[1] = L.m * vl[1] - t2[1]; hf[2] = L.m * vl[2] - t2[2];
-        R a[3], b[3], c3[3];
-        cross3(w, hn, a);
-        cross3(vl, hf, b);
-        cross3(w, hf, c3);
-        pA[i][0] = a[0] + b[0]; pA[i][1] = a[1] + b[1]; pA[i][2] = a[2] + b[2];
-        pA[i][3] = c3[0]; pA[i][4] = c3[1]; pA[i][5] = c3[2];
+        z[i][0] = Rw[2]; z[i][1] = Rw[5]; z[i][2] = Rw[8];
+        // link inertia about p_i in world axes
+        R cw[3], Ic[6];
+        mv3(Rw, L.com, cw);
+        congr_sym3<false>(Rw, L.Ic, Ic);
+        const R c2 = dot3(cw, cw);
+        Iw[i][0] = Ic[0] + L.m * (c2 - cw[0] * cw[0]);
+        Iw[i][1] = Ic[1] + L.m * (c2 - cw[1] * cw[1]);
+        Iw[i][2] = Ic[2] + L.m * (c2 - cw[2] * cw[2]);
+        Iw[i][3] = Ic[3] - L.m * cw[0] * cw[1];
+        Iw[i][4] = Ic[4] - L.m * cw[0] * cw[2];
+        Iw[i][5] = Ic[5] - L.m * cw[1] * cw[2];
+        mc[i][0] = L.m * cw[0]; mc[i][1] = L.m * cw[1]; mc[i][2] = L.m * cw[2];
+        // v_i = X_i v_{i-1} + S_i qd_i  (shift by r_i, then the joint rate)
+        R wxr[3];
+        cross3(vw, rr[i], wxr);
+        vw[3] += wxr[0]; vw[4] += wxr[1]; vw[5] += wxr[2];
+        const R sw[3] = {z[i][0] * qd[i], z[i][1] * qd[i], z[i][2] * qd[i]};
+        vw[0] += sw[0]; vw[1] += sw[1]; vw[2] += sw[2];
+        // c_i = v_i x (S_i qd_i) = (w x sw, v x sw)
+        R t1[3], t2[3], t3[3];
+        cross3(vw, sw, t1);
+        cross3(vw + 3, sw, t2);
+        cc[i][0] = t1[0]; cc[i][1] = t1[1]; cc[i][2] = t1[2];
+        cc[i][3] = t2[0]; cc[i][4] = t2[1]; cc[i][5] = t2[2];
+        // h = I v ; p = v x* h = (w x hn + v x hf, w x hf)
+        R hn[3], hf[3], u1[3], u2[3];
+        hn[0] = Iw[i][0] * vw[0] + Iw[i][3] * vw[1] + Iw[i][4] * vw[2];
+        hn[1] = Iw[i][3] * vw[0] + Iw[i][1] * vw[1] + Iw[i][5] * vw[2];
+        hn[2] = Iw[i][4] * vw[0] + Iw[i][5] * vw[1] + Iw[i][2] * vw[2];
+        cross3(mc[i], vw + 3, u1);
+        hn[0] += u1[0]; hn[1] += u1[1]; hn[2] += u1[2];
+        cross3(mc[i], vw, u2);
+        hf[0] = L.m * vw[3] - u2[0]; hf[1] = L.m * vw[4] - u2[1]; hf[2] = L.m * vw[5] - u2[2];
+        cross3(vw, hn, t1);
+        cross3(vw + 3, hf, t2);
+        cross3(vw, hf, t3);
+        pA[i][0] = t1[0] + t2[0]; pA[i][1] = t1[1] + t2[1]; pA[i][2] = t1[2] + t2[2];
+        pA[i][3] = t3[0]; pA[i][4] = t3[1]; pA[i][5] = t3[2];
     }
-    {
-        R d[3];
-        mv3(Rw, M.ree, d);
-        out.pee[0] = pw[0] + d[0]; out.pee[1] = pw[1] + d[1]; out.pee[2] = pw[2] + d[2];
+    R ree_w[3];   // EE point relative to p_n
+    mv3(Rw, M.ree, ree_w);
+    out.pee[0] = pw[0] + ree_w[0]; out.pee[1] = pw[1] + ree_w[1]; out.pee[2] = pw[2] + ree_w[2];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) out.Rn[i] = Rw[i];
-    }
-    // external wrench on the last link (world force F at the EE point,
-    // world moment N): local force f = Rw^T F, moment n = Rw^T N + ree x f
+    for (int i = 0; i < 9; ++i) out.Rn[i] = Rw[i];
+    // external wrench on the last link: world force F at the EE point and
+    // world moment N, about p_n: (N + ree_w x F, F)
     if (ext != EXTW_NONE) {
         R Fw[3] = {R(0), R(0), R(0)}, Nw[3] = {R(0), R(0), R(0)};
         if (ext == EXTW_WALL) {
-            R wxr[3], vel[3], vee[3];
-            cross3(w, M.ree, wxr);
-            vel[0] = vl[0] + wxr[0]; vel[1] = vl[1] + wxr[1]; vel[2] = vl[2] + wxr[2];
-            mv3(Rw, vel, vee);
+            R wxr[3];
+            cross3(vw, ree_w, wxr);
+            const R vee[3] = {vw[3] + wxr[0], vw[4] + wxr[1], vw[5] + wxr[2]};
             R delta = Cst.wall_d0 - dot3(Cst.wall_n, out.pee);
             R ddelta = -dot3(Cst.wall_n, vee);
             R mag = hinge(Cst.wall_k * delta + Cst.wall_c * ddelta);
@@ -512,177 +537,121 @@ MPPI_HD void dyn_step(const ModelM<R>& M, const CostM<R>& Cst, int ext, const R*
             Fw[0] = Cst.F_ext[0]; Fw[1] = Cst.F_ext[1]; Fw[2] = Cst.F_ext[2];
             Nw[0] = Cst.F_ext[3]; Nw[1] = Cst.F_ext[4]; Nw[2] = Cst.F_ext[5];
         }
-        R fl[3], nl[3], rf[3];
-        mtv3(Rw, Fw, fl);
-        mtv3(Rw, Nw, nl);
-        cross3(M.ree, fl, rf);
-        pA[NJ - 1][0] -= nl[0] + rf[0]; pA[NJ - 1][1] -= nl[1] + rf[1]; pA[NJ - 1][2] -= nl[2] + rf[2];
-        pA[NJ - 1][3] -= fl[0]; pA[NJ - 1][4] -= fl[1]; pA[NJ - 1][5] -= fl[2];
+        R rf[3];
+        cross3(ree_w, Fw, rf);
+        pA[NJ - 1][0] -= Nw[0] + rf[0]; pA[NJ - 1][1] -= Nw[1] + rf[1]; pA[NJ - 1][2] -= Nw[2] + rf[2];
+        pA[NJ - 1][3] -= Fw[0]; pA[NJ - 1][4] -= Fw[1]; pA[NJ - 1][5] -= Fw[2];
     }
 
-    // ---- pass 2 (tip -> root): articulated inertias and bias forces
+    // ---- pass 2 (tip -> root)
     R U[NJ][6], iD[NJ], u[NJ], uF[NJ];
-    Sym6<R> acc;
+    Sym6<R> IA;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) { acc.A[i] = R(0); acc.C[i] = R(0); }
+    for (int a = 0; a < 6; ++a) { IA.A[a] = R(0); IA.C[a] = R(0); }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) acc.B[i] = R(0);
+    for (int a = 0; a < 9; ++a) IA.B[a] = R(0);
     R pacc[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     R pF[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
     for (int i = NJ - 1; i >= 0; --i) {
         const LinkM<R>& L = M.L[i];
-        Sym6<R> IA;
+        // IA_i = I_i + (child contribution, already about p_i)
 #pragma unroll
-        for (int a = 0; a < 6; ++a) IA.A[a] = L.Io[a] + acc.A[a];
-        // B = m (c x)
-        IA.B[0] = acc.B[0];            IA.B[1] = acc.B[1] - L.mc[2];  IA.B[2] = acc.B[2] + L.mc[1];
-        IA.B[3] = acc.B[3] + L.mc[2];  IA.B[4] = acc.B[4];            IA.B[5] = acc.B[5] - L.mc[0];
-        IA.B[6] = acc.B[6] - L.mc[1];  IA.B[7] = acc.B[7] + L.mc[0];  IA.B[8] = acc.B[8];
-        IA.C[0] = acc.C[0] + L.m; IA.C[1] = acc.C[1] + L.m; IA.C[2] = acc.C[2] + L.m;
-        IA.C[3] = acc.C[3];       IA.C[4] = acc.C[4];       IA.C[5] = acc.C[5];
+        for (int a = 0; a < 6; ++a) IA.A[a] += Iw[i][a];
+        IA.B[1] -= mc[i][2]; IA.B[2] += mc[i][1];
+        IA.B[3] += mc[i][2]; IA.B[5] -= mc[i][0];
+        IA.B[6] -= mc[i][1]; IA.B[7] += mc[i][0];
+        IA.C[0] += L.m; IA.C[1] += L.m; IA.C[2] += L.m;
         R p[6];
 #pragma unroll
         for (int a = 0; a < 6; ++a) p[a] = pA[i][a] + pacc[a];
-        // U = IA S (column 2)
-        U[i][0] = IA.A[si(0, 2)]; U[i][1] = IA.A[si(1, 2)]; U[i][2] = IA.A[2];
-        U[i][3] = IA.B[6];        U[i][4] = IA.B[7];        U[i][5] = IA.B[8];
-        R D = U[i][2] + L.arm;
-        iD[i] = R(1) / D;
-        u[i] = tau[i] - p[2];
-        if (FORCE) uF[i] = v[i] - pF[2];
+        // U = IA S = (A z, B^T z), D = z.(A z) + a
+        const R* zi = z[i];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            U[i][a] = IA.A[si(a, 0)] * zi[0] + IA.A[si(a, 1)] * zi[1] + IA.A[si(a, 2)] * zi[2];
+            U[i][3 + a] = IA.B[a] * zi[0] + IA.B[3 + a] * zi[1] + IA.B[6 + a] * zi[2];
+        }
+        iD[i] = R(1) / (dot3(zi, U[i]) + L.arm);
+        u[i] = tau[i] - dot3(zi, p);
+        if (FORCE) uF[i] = v[i] - dot3(zi, pF);
         if (i > 0) {
-            const R* Ui = U[i];
-            Sym6<R> Ia;
+            R nU[6];
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
+            for (int a = 0; a < 6; ++a) nU[a] = R(-0.5) * U[i][a] * iD[i];
+            sym6_rank2(IA, U[i], nU);            // Ia = IA - U U^T / D
+            R Iac[6];
+            sym6_mv(IA, cc[i], Iac);
+            const R uD = u[i] * iD[i];
 #pragma unroll
-                for (int b = a; b < 3; ++b) {
-                    Ia.A[si(a, b)] = IA.A[si(a, b)] - Ui[a] * Ui[b] * iD[i];
-                    Ia.C[si(a, b)] = IA.C[si(a, b)] - Ui[3 + a] * Ui[3 + b] * iD[i];
-                }
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) Ia.B[a * 3 + b] = IA.B[a * 3 + b] - Ui[a] * Ui[3 + b] * iD[i];
-            // pa = p + Ia c + U u / D   (c = (c0, c1, 0, c3, c4, 0))
-            R c0 = cc[i][0], c1 = cc[i][1], c3 = cc[i][2], c4 = cc[i][3];
-            R uD = u[i] * iD[i];
-            R pa[6];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                pa[a] = p[a] + Ia.A[si(a, 0)] * c0 + Ia.A[si(a, 1)] * c1 + Ia.B[a * 3] * c3 +
-                        Ia.B[a * 3 + 1] * c4 + Ui[a] * uD;
-                pa[3 + a] = p[3 + a] + Ia.B[a] * c0 + Ia.B[3 + a] * c1 + Ia.C[si(a, 0)] * c3 +
-                            Ia.C[si(a, 1)] * c4 + Ui[3 + a] * uD;
-            }
-            R Q[9];
-            joint_rot(L.Rp, cq[i], sq_[i], Q);
-            congr_force(Q, L.rp, Ia, acc);
-            // pacc = X^T pa : f_p = Q f, n_p = Q n + r x f_p
-            R fp[3], np_[3], rf[3];
-            mv3(Q, pa + 3, fp);
-            mv3(Q, pa, np_);
-            cross3(L.rp, fp, rf);
-            pacc[0] = np_[0] + rf[0]; pacc[1] = np_[1] + rf[1]; pacc[2] = np_[2] + rf[2];
-            pacc[3] = fp[0]; pacc[4] = fp[1]; pacc[5] = fp[2];
+            for (int a = 0; a < 6; ++a) pacc[a] = p[a] + Iac[a] + U[i][a] * uD;
+            // move Ia and pa to p_{i-1}: force shift by r_i
+            shift_force(rr[i], IA);
+            R rf[3];
+            cross3(rr[i], pacc + 3, rf);
+            pacc[0] += rf[0]; pacc[1] += rf[1]; pacc[2] += rf[2];
             if (FORCE) {
-                R uFD = uF[i] * iD[i], pf[6];
+                const R uFD = uF[i] * iD[i];
 #pragma unroll
-                for (int a = 0; a < 6; ++a) pf[a] = pF[a] + Ui[a] * uFD;
-                mv3(Q, pf + 3, fp);
-                mv3(Q, pf, np_);
-                cross3(L.rp, fp, rf);
-                pF[0] = np_[0] + rf[0]; pF[1] = np_[1] + rf[1]; pF[2] = np_[2] + rf[2];
-                pF[3] = fp[0]; pF[4] = fp[1]; pF[5] = fp[2];
+                for (int a = 0; a < 6; ++a) pF[a] += U[i][a] * uFD;
+                cross3(rr[i], pF + 3, rf);
+                pF[0] += rf[0]; pF[1] += rf[1]; pF[2] += rf[2];
             }
         }
     }
 
-    // ---- pass 3 (root -> tip): accelerations; force path
+    // ---- pass 3 (root -> tip)
     R a[6] = {R(0), R(0), R(0), -M.g[0], -M.g[1], -M.g[2]};
     R aF[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     if (FORCE && Cst.force_mode == 0) { aF[3] = -M.g[0]; aF[4] = -M.g[1]; aF[5] = -M.g[2]; }
     Sym6<R> Om;
+    if (FORCE) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) { Om.A[k] = R(0); Om.C[k] = R(0); }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Om.B[k] = R(0);
+    }
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
-        const LinkM<R>& L = M.L[i];
-        R Q[9];
-        joint_rot(L.Rp, cq[i], sq_[i], Q);
         // a' = X a + c
-        R rxw[3], t[3], an[6];
-        cross3(L.rp, a, rxw);
-        t[0] = a[3] - rxw[0]; t[1] = a[4] - rxw[1]; t[2] = a[5] - rxw[2];
-        mtv3(Q, a, an);
-        mtv3(Q, t, an + 3);
-        an[0] += cc[i][0]; an[1] += cc[i][1]; an[3] += cc[i][2]; an[4] += cc[i][3];
-        R Ua = U[i][0] * an[0] + U[i][1] * an[1] + U[i][2] * an[2] + U[i][3] * an[3] +
-               U[i][4] * an[4] + U[i][5] * an[5];
-        R qddi = (u[i] - Ua) * iD[i];
+        R wxr[3];
+        cross3(a, rr[i], wxr);
+        R an[6] = {a[0] + cc[i][0], a[1] + cc[i][1], a[2] + cc[i][2],
+                   a[3] + wxr[0] + cc[i][3], a[4] + wxr[1] + cc[i][4], a[5] + wxr[2] + cc[i][5]};
+        const R qddi = (u[i] - dot6(U[i], an)) * iD[i];
         out.qdd[i] = qddi;
-        an[2] += qddi;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) a[k] = an[k];
+        a[0] = an[0] + z[i][0] * qddi; a[1] = an[1] + z[i][1] * qddi; a[2] = an[2] + z[i][2] * qddi;
+        a[3] = an[3]; a[4] = an[4]; a[5] = an[5];
         if (FORCE) {
-            cross3(L.rp, aF, rxw);
-            t[0] = aF[3] - rxw[0]; t[1] = aF[4] - rxw[1]; t[2] = aF[5] - rxw[2];
-            mtv3(Q, aF, an);
-            mtv3(Q, t, an + 3);
-            R UaF = U[i][0] * an[0] + U[i][1] * an[1] + U[i][2] * an[2] + U[i][3] * an[3] +
-                    U[i][4] * an[4] + U[i][5] * an[5];
-            an[2] += (uF[i] - UaF) * iD[i];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) aF[k] = an[k];
-            if (i == 0) {
-#pragma unroll
-                for (int k = 0; k < 6; ++k) { Om.A[k] = R(0); Om.C[k] = R(0); }
-#pragma unroll
-                for (int k = 0; k < 9; ++k) Om.B[k] = R(0);
-                Om.A[2] = iD[0];
-            } else {
-                Sym6<R> Y;
-                congr_motion(Q, L.rp, Om, Y);
-                // w = Y U ; beta = U . w
-                const R* Ui = U[i];
-                R wv[6];
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    wv[r] = Y.A[si(r, 0)] * Ui[0] + Y.A[si(r, 1)] * Ui[1] + Y.A[si(r, 2)] * Ui[2] +
-                            Y.B[r * 3] * Ui[3] + Y.B[r * 3 + 1] * Ui[4] + Y.B[r * 3 + 2] * Ui[5];
-                    wv[3 + r] = Y.B[r] * Ui[0] + Y.B[3 + r] * Ui[1] + Y.B[6 + r] * Ui[2] +
-                                Y.C[si(r, 0)] * Ui[3] + Y.C[si(r, 1)] * Ui[4] + Y.C[si(r, 2)] * Ui[5];
-                }
-                R beta = Ui[0] * wv[0] + Ui[1] * wv[1] + Ui[2] * wv[2] + Ui[3] * wv[3] +
-                         Ui[4] * wv[4] + Ui[5] * wv[5];
-                R dI = iD[i];
-                // Om = Y - (e2 w^T + w e2^T)/D + e2 e2^T (beta/D^2 + 1/D)
-                Om = Y;
-                Om.A[si(0, 2)] -= wv[0] * dI;
-                Om.A[si(1, 2)] -= wv[1] * dI;
-                Om.A[2] += (beta * dI - R(2) * wv[2]) * dI + dI;
-                Om.B[6] -= wv[3] * dI;
-                Om.B[7] -= wv[4] * dI;
-                Om.B[8] -= wv[5] * dI;
-            }
+            cross3(aF, rr[i], wxr);
+            aF[3] += wxr[0]; aF[4] += wxr[1]; aF[5] += wxr[2];
+            const R qF = (uF[i] - dot6(U[i], aF)) * iD[i];
+            aF[0] += z[i][0] * qF; aF[1] += z[i][1] * qF; aF[2] += z[i][2] * qF;
+            // Omega <- P (X Omega X^T) P^T + S S^T / D
+            //   = Y + S y^T + y S^T with Y = X Omega X^T, w = Y U,
+            //     y = (beta/D^2 + 1/D)/2 S - w/D, beta = U.w
+            if (i > 0) shift_motion(rr[i], Om);
+            R wv[6];
+            sym6_mv(Om, U[i], wv);
+            const R dI = iD[i];
+            const R g2 = R(0.5) * (dot6(U[i], wv) * dI + R(1)) * dI;
+            R y[6];
+            y[0] = g2 * z[i][0] - wv[0] * dI; y[1] = g2 * z[i][1] - wv[1] * dI; y[2] = g2 * z[i][2] - wv[2] * dI;
+            y[3] = -wv[3] * dI; y[4] = -wv[4] * dI; y[5] = -wv[5] * dI;
+            const R S6[6] = {z[i][0], z[i][1], z[i][2], R(0), R(0), R(0)};
+            sym6_rank2(Om, S6, y);
         }
     }
 
     if (FORCE) {
-        // b = J_n M^-1 tau_F at the last-link origin: remove the propagated
-        // base acceleration (pure linear, -R^T g) when gravity was included
+        // b = J_n M^-1 tau_F about p_n (remove the uniform gravity term)
         R b[6] = {aF[0], aF[1], aF[2], aF[3], aF[4], aF[5]};
-        if (Cst.force_mode == 0) {
-            R gl[3];
-            mtv3(out.Rn, M.g, gl);
-            b[3] += gl[0]; b[4] += gl[1]; b[5] += gl[2];
-        }
-        chol6_solve(Om, b);   // x = Omega^-1 b  (a spatial force at the link origin)
-        // F_ee = T^-T x : F = R f, N = R (n - ree x f)
-        R rf[3], nn[3];
-        cross3(M.ree, b + 3, rf);
-        nn[0] = b[0] - rf[0]; nn[1] = b[1] - rf[1]; nn[2] = b[2] - rf[2];
-        mv3(out.Rn, b + 3, out.F);
-        mv3(out.Rn, nn, out.F + 3);
+        if (Cst.force_mode == 0) { b[3] += M.g[0]; b[4] += M.g[1]; b[5] += M.g[2]; }
+        chol6_solve(Om, b);   // x = Omega^-1 b: spatial force about p_n
+        R rf[3];
+        cross3(ree_w, b + 3, rf);
+        out.F[0] = b[3]; out.F[1] = b[4]; out.F[2] = b[5];
+        out.F[3] = b[0] - rf[0]; out.F[4] = b[1] - rf[1]; out.F[5] = b[2] - rf[2];
     }
 }
 

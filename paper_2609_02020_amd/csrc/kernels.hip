@@ -63,10 +63,22 @@ __global__ __launch_bounds__(kRolloutBlock) void update_kernel(
     __shared__ R Us[kMaxT * NJ];
     __shared__ A wl[64];
     __shared__ int last;
+    // the model and cost constants are read from LDS (uniform addresses):
+    // ~250 values are more than the scalar registers hold across a step
+    __shared__ ModelM<R> Msh;
+    __shared__ CostM<R> Csh;
+    {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(Mp);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&Msh);
+        for (int i = threadIdx.x; i < (int)(sizeof(ModelM<R>) / 4); i += blockDim.x) dst[i] = src[i];
+        src = reinterpret_cast<const uint32_t*>(Cp);
+        dst = reinterpret_cast<uint32_t*>(&Csh);
+        for (int i = threadIdx.x; i < (int)(sizeof(CostM<R>) / 4); i += blockDim.x) dst[i] = src[i];
+    }
     for (int i = threadIdx.x; i < T * NJ; i += blockDim.x) Us[i] = R(U_nom[i]);
     __syncthreads();
-    const ModelM<R>& M = *Mp;
-    const CostM<R>& C = *Cp;
+    const ModelM<R>& M = Msh;
+    const CostM<R>& C = Csh;
     const int lane = threadIdx.x & 63;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     R* tile = reinterpret_cast<R*>(dyn_lds);   // [rows][65] when lds_noise

@@ -1,8 +1,7 @@
 // model_prep.hpp -- converts the C-ABI robot/cost structs into the layout the
-// rollout kernels read (ModelM / CostM).  The parallel-axis shift of the link
-// inertia to the link-frame origin (I_o = I_c + m (|c|^2 1 - c c^T)) runs
-// on the device in the model-preparation kernel; the cost conversion is a
-// plain field copy with a cast.
+// rollout kernels read (ModelM / CostM): a field copy with a cast to the
+// rollout precision (run on the device for the model, on the host for the
+// cost).
 #pragma once
 
 #include "dyn.hpp"
@@ -15,15 +14,8 @@ template <typename R> MPPI_HD void prep_link(const mppi_link_params& P, LinkM<R>
     for (int a = 0; a < 9; ++a) L.Rp[a] = R(P.R_parent[a]);
     for (int a = 0; a < 3; ++a) L.rp[a] = R(P.r_parent[a]);
     const double m = P.mass;
-    const double c0 = P.com[0], c1 = P.com[1], c2 = P.com[2];
-    const double cc = c0 * c0 + c1 * c1 + c2 * c2;
-    L.Io[0] = R(P.inertia_com[0] + m * (cc - c0 * c0));
-    L.Io[1] = R(P.inertia_com[1] + m * (cc - c1 * c1));
-    L.Io[2] = R(P.inertia_com[2] + m * (cc - c2 * c2));
-    L.Io[3] = R(P.inertia_com[3] - m * c0 * c1);
-    L.Io[4] = R(P.inertia_com[4] - m * c0 * c2);
-    L.Io[5] = R(P.inertia_com[5] - m * c1 * c2);
-    L.mc[0] = R(m * c0); L.mc[1] = R(m * c1); L.mc[2] = R(m * c2);
+    for (int a = 0; a < 6; ++a) L.Ic[a] = R(P.inertia_com[a]);
+    for (int a = 0; a < 3; ++a) L.com[a] = R(P.com[a]);
     L.m = R(m);
     L.arm = R(P.armature);
     L.qmin = R(P.q_min); L.qmax = R(P.q_max); L.qdmax = R(P.qd_max); L.taumax = R(P.tau_max);

@@ -16,10 +16,25 @@ namespace mppi {
 
 template <typename R> MPPI_HD bool finite_(R x) { return x - x == R(0); }
 
+// The same object behind an address the compiler cannot prove loop-invariant,
+// so that reads of model constants stay inside the step loop (re-read from
+// LDS each step) instead of being hoisted and held in registers for the
+// whole rollout.
+template <typename T> MPPI_HD const T* per_step(const T* p)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    int off = 0;
+    asm volatile("" : "+s"(off));
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + off);
+#else
+    return p;
+#endif
+}
+
 // noise_out / noise_lds (either may be null) receive du[t][j] at
 // (t*7 + j) * stride.
 template <typename R, bool FORCE, typename UT>
-MPPI_HD R rollout_sample(const ModelM<R>& M, const CostM<R>& C, const TargetM<R>& tg,
+MPPI_HD R rollout_sample(const ModelM<R>& Mc, const CostM<R>& Cc, const TargetM<R>& tg,
                          const R* q0, const R* qd0, const R* tau_ext_c, const UT* U_nom, int T,
                          uint64_t seed, uint32_t tick, uint32_t k, R* noise_out, size_t noise_stride,
                          R* noise_lds = nullptr, int lds_stride = 0)
@@ -27,8 +42,10 @@ MPPI_HD R rollout_sample(const ModelM<R>& M, const CostM<R>& C, const TargetM<R>
     R q[NJ], qd[NJ], S = R(0);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) { q[j] = q0[j]; qd[j] = qd0[j]; }
-    const int ext = C.ext_mode == EXTW_WALL ? EXTW_WALL : EXTW_NONE;
+    const int ext = Cc.ext_mode == EXTW_WALL ? EXTW_WALL : EXTW_NONE;
     for (int t = 0; t < T; ++t) {
+        const ModelM<R>& M = *per_step(&Mc);
+        const CostM<R>& C = *per_step(&Cc);
         R z[8], v[NJ], tau[NJ];
         normals8<R>(seed, tick, k, (uint32_t)t, z);
 #pragma unroll
@@ -51,8 +68,8 @@ MPPI_HD R rollout_sample(const ModelM<R>& M, const CostM<R>& C, const TargetM<R>
         }
     }
     R pee[3], Rn[9];
-    fk_ee(M, q, pee, Rn, (R*)nullptr, (R*)nullptr);
-    S += C.w_T * (motion_cost(M, C, tg, pee, Rn) + joint_cost(M, C, q, qd));
+    fk_ee(Mc, q, pee, Rn, (R*)nullptr, (R*)nullptr);
+    S += Cc.w_T * (motion_cost(Mc, Cc, tg, pee, Rn) + joint_cost(Mc, Cc, q, qd));
     return S;
 }
 
