@@ -29,7 +29,7 @@ METRIC = "MPPI update rate (Hz) + ABA rollout steps/s, K=4096 T=18 7-DoF, FP32"
 # its per-sample code with an op-counting scalar (tests/opcount.cpp; add,
 # mul, div, sqrt = 1 flop each, a fused multiply-add = 2).  Contact workload
 # (force estimate, wall, orientation cost on).
-FLOPS_PER_SAMPLE_STEP = 7621
+FLOPS_PER_SAMPLE_STEP = 6967
 FLOPS_PER_SAMPLE_TERMINAL = 822
 # Eq. 4b: one multiply-add per sample and output row (weighted noise sum).
 FLOPS_PER_SAMPLE_ROW_WEIGHT = 2

@@ -86,7 +86,32 @@ MPPI_HD double atan2_(double y, double x) { return std::atan2(y, x); }
 MPPI_HD float abs_(float x) { return std::fabs(x); }
 MPPI_HD double abs_(double x) { return std::fabs(x); }
 
-template <typename R> MPPI_HD R hinge(R x) { return x > R(0) ? x : R(0); }
+MPPI_HD float fma_(float a, float b, float c) { return std::fma(a, b, c); }
+MPPI_HD double fma_(double a, double b, double c) { return std::fma(a, b, c); }
+// reciprocal / square root: the single-rounding hardware instructions in
+// FP32 (1 ulp), exact IEEE operations in FP64
+MPPI_HD float rcp_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+MPPI_HD double rcp_(double x) { return 1.0 / x; }
+MPPI_HD float rsqrt_sqrt_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return std::sqrt(x);
+#endif
+}
+MPPI_HD double rsqrt_sqrt_(double x) { return std::sqrt(x); }
+MPPI_HD float max0_(float x) { return std::fmax(x, 0.0f); }
+MPPI_HD double max0_(double x) { return std::fmax(x, 0.0); }
+
+template <typename R> MPPI_HD R hinge(R x) { return max0_(x); }
 template <typename R> MPPI_HD R sq(R x) { return x * x; }
 
 // ---------------------------------------------------------------------------
@@ -298,9 +323,9 @@ template <typename R> MPPI_HD void chol6_solve(const Sym6<R>& S, R* b)
 #pragma unroll
             for (int k = 0; k < j; ++k) s -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
             if (i == j) {
-                R d = sqrt_(s);
+                R d = rsqrt_sqrt_(s);
                 L[i * (i + 1) / 2 + i] = d;
-                inv[i] = R(1) / d;
+                inv[i] = rcp_(d);
             } else {
                 L[i * (i + 1) / 2 + j] = s * inv[j];
             }
@@ -372,19 +397,33 @@ template <typename R> MPPI_HD R dot6(const R* a, const R* b)
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3] + a[4] * b[4] + a[5] * b[5];
 }
 // M += x y^T + y x^T (symmetric storage)
-template <typename R> MPPI_HD void sym6_rank2(Sym6<R>& M, const R* x, const R* y)
+// M -= U W^T for W = U / D (symmetric result): one fma per stored entry
+template <typename R> MPPI_HD void sym6_sub_outer(Sym6<R>& M, const R* U, const R* W)
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = a; b < 3; ++b) {
-            M.A[si(a, b)] += x[a] * y[b] + y[a] * x[b];
-            M.C[si(a, b)] += x[3 + a] * y[3 + b] + y[3 + a] * x[3 + b];
+            M.A[si(a, b)] = fma_(-U[a], W[b], M.A[si(a, b)]);
+            M.C[si(a, b)] = fma_(-U[3 + a], W[3 + b], M.C[si(a, b)]);
         }
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) M.B[a * 3 + b] += x[a] * y[3 + b] + y[a] * x[3 + b];
+        for (int b = 0; b < 3; ++b) M.B[a * 3 + b] = fma_(-U[a], W[3 + b], M.B[a * 3 + b]);
+}
+// M += S y^T + y S^T for a revolute joint, S = (z, 0): the C block is
+// unchanged and B gets z_a y_lin,b only
+template <typename R> MPPI_HD void sym6_add_joint_rank2(Sym6<R>& M, const R* z, const R* y)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b) M.A[si(a, b)] = fma_(z[a], y[b], fma_(y[a], z[b], M.A[si(a, b)]));
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) M.B[a * 3 + b] = fma_(z[a], y[3 + b], M.B[a * 3 + b]);
 }
 // rx M for a general 3x3 M (row-major): P_ij = sum_k rx_ik M_kj
 template <typename R> MPPI_HD void rx_mul(const R* r, const R* M, R* P)
@@ -400,22 +439,32 @@ template <typename R> MPPI_HD void rx_mul(const R* r, const R* M, R* P)
 // Force-side shift of a symmetric spatial matrix from a reference point p'
 // to p = p' - r (r = p' - p): out = X^T M X with X = [1 0; -rx 1]:
 //   C' = C, B' = B + rx C, A' = A + rx B^T + (rx B^T)^T - rx C rx.
+// (rx M)_ij = r_{i+1} M_{i+2,j} - r_{i+2} M_{i+1,j} (indices mod 3).
 template <typename R> MPPI_HD void shift_force(const R* r, Sym6<R>& M)
 {
-    R Cf[9], P[9], Bt[9], G[9];
+    R Cf[9], P[9], G[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) { Cf[i * 3 + j] = M.C[si(i, j)]; Bt[i * 3 + j] = M.B[j * 3 + i]; }
-    rx_mul(r, Cf, P);   // rx C
-    rx_mul(r, Bt, G);   // rx B^T
-    const R rx[9] = {R(0), -r[2], r[1], r[2], R(0), -r[0], -r[1], r[0], R(0)};
+        for (int j = 0; j < 3; ++j) Cf[i * 3 + j] = M.C[si(i, j)];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            P[i * 3 + j] = fma_(r[i1], Cf[i2 * 3 + j], -r[i2] * Cf[i1 * 3 + j]);          // rx C
+            G[i * 3 + j] = fma_(r[i1], M.B[j * 3 + i2], -r[i2] * M.B[j * 3 + i1]);      // rx B^T
+        }
+    }
+    // A'_ij = A_ij + G_ij + G_ji - (P rx)_ij, (P rx)_ij = P_{i,j+1} r_{j+2} - P_{i,j+2} r_{j+1}
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = i; j < 3; ++j) {
-            R prx = P[i * 3] * rx[j] + P[i * 3 + 1] * rx[3 + j] + P[i * 3 + 2] * rx[6 + j];
-            M.A[si(i, j)] += G[i * 3 + j] + G[j * 3 + i] - prx;
+            const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            R acc = M.A[si(i, j)] + G[i * 3 + j] + G[j * 3 + i];
+            acc = fma_(P[i * 3 + j2], r[j1], acc);
+            M.A[si(i, j)] = fma_(-P[i * 3 + j1], r[j2], acc);
         }
 #pragma unroll
     for (int i = 0; i < 9; ++i) M.B[i] += P[i];
@@ -572,14 +621,14 @@ MPPI_HD void dyn_step(const ModelM<R>& M, const CostM<R>& Cst, int ext, const R*
             U[i][a] = IA.A[si(a, 0)] * zi[0] + IA.A[si(a, 1)] * zi[1] + IA.A[si(a, 2)] * zi[2];
             U[i][3 + a] = IA.B[a] * zi[0] + IA.B[3 + a] * zi[1] + IA.B[6 + a] * zi[2];
         }
-        iD[i] = R(1) / (dot3(zi, U[i]) + L.arm);
+        iD[i] = rcp_(dot3(zi, U[i]) + L.arm);
         u[i] = tau[i] - dot3(zi, p);
         if (FORCE) uF[i] = v[i] - dot3(zi, pF);
         if (i > 0) {
-            R nU[6];
+            R UD[6];
 #pragma unroll
-            for (int a = 0; a < 6; ++a) nU[a] = R(-0.5) * U[i][a] * iD[i];
-            sym6_rank2(IA, U[i], nU);            // Ia = IA - U U^T / D
+            for (int a = 0; a < 6; ++a) UD[a] = U[i][a] * iD[i];
+            sym6_sub_outer(IA, U[i], UD);        // Ia = IA - U U^T / D
             R Iac[6];
             sym6_mv(IA, cc[i], Iac);
             const R uD = u[i] * iD[i];
@@ -636,10 +685,10 @@ MPPI_HD void dyn_step(const ModelM<R>& M, const CostM<R>& Cst, int ext, const R*
             const R dI = iD[i];
             const R g2 = R(0.5) * (dot6(U[i], wv) * dI + R(1)) * dI;
             R y[6];
-            y[0] = g2 * z[i][0] - wv[0] * dI; y[1] = g2 * z[i][1] - wv[1] * dI; y[2] = g2 * z[i][2] - wv[2] * dI;
+            y[0] = fma_(g2, z[i][0], -wv[0] * dI); y[1] = fma_(g2, z[i][1], -wv[1] * dI);
+            y[2] = fma_(g2, z[i][2], -wv[2] * dI);
             y[3] = -wv[3] * dI; y[4] = -wv[4] * dI; y[5] = -wv[5] * dI;
-            const R S6[6] = {z[i][0], z[i][1], z[i][2], R(0), R(0), R(0)};
-            sym6_rank2(Om, S6, y);
+            sym6_add_joint_rank2(Om, z[i], y);
         }
     }
 

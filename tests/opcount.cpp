@@ -52,6 +52,10 @@ inline Flop sqrt_(Flop x) { g_counts.sqrt++; return Flop(std::sqrt(x.v)); }
 inline Flop log_(Flop x) { g_counts.trans++; return Flop(std::log(x.v)); }
 inline Flop atan2_(Flop y, Flop x) { g_counts.trans++; return Flop(std::atan2(y.v, x.v)); }
 inline Flop abs_(Flop x) { return Flop(std::fabs(x.v)); }
+inline Flop fma_(Flop a, Flop b, Flop c) { g_counts.mul++; g_counts.add++; return Flop(a.v * b.v + c.v); }
+inline Flop rcp_(Flop x) { g_counts.div++; return Flop(1.0 / x.v); }
+inline Flop rsqrt_sqrt_(Flop x) { g_counts.sqrt++; return Flop(std::sqrt(x.v)); }
+inline Flop max0_(Flop x) { g_counts.cmp++; return Flop(x.v > 0 ? x.v : 0.0); }
 }  // namespace mppi
 
 #include "model_prep.hpp"
