@@ -45,10 +45,14 @@ constexpr int NJ = 7;
 // ---------------------------------------------------------------------------
 // scalar math: device builtins on the GPU, libm on the host
 // ---------------------------------------------------------------------------
+// FP32 on the device: the hardware sine/cosine, whose input is in
+// revolutions (argument / 2 pi); joint angles stay far inside its range.
 MPPI_HD void sincos_(float x, float* s, float* c)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    sincosf(x, s, c);
+    const float rev = x * 0.15915494309189535f;
+    *s = __builtin_amdgcn_sinf(rev);
+    *c = __builtin_amdgcn_cosf(rev);
 #else
     *s = std::sin(x); *c = std::cos(x);
 #endif
@@ -64,7 +68,9 @@ MPPI_HD void sincos_(double x, double* s, double* c)
 MPPI_HD void sincospi_(float x, float* s, float* c)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    sincospif(x, s, c);
+    const float rev = 0.5f * x;
+    *s = __builtin_amdgcn_sinf(rev);
+    *c = __builtin_amdgcn_cosf(rev);
 #else
     *s = std::sin(3.14159265358979323846 * x); *c = std::cos(3.14159265358979323846 * x);
 #endif
@@ -79,7 +85,14 @@ MPPI_HD void sincospi_(double x, double* s, double* c)
 }
 MPPI_HD float sqrt_(float x) { return std::sqrt(x); }
 MPPI_HD double sqrt_(double x) { return std::sqrt(x); }
-MPPI_HD float log_(float x) { return std::log(x); }
+MPPI_HD float log_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_logf(x) * 0.69314718055994531f;   // hardware log2
+#else
+    return std::log(x);
+#endif
+}
 MPPI_HD double log_(double x) { return std::log(x); }
 MPPI_HD float atan2_(float y, float x) { return std::atan2(y, x); }
 MPPI_HD double atan2_(double y, double x) { return std::atan2(y, x); }
@@ -256,7 +269,7 @@ template <typename R> MPPI_HD void box_muller_pair(uint32_t xa, uint32_t xb, R& 
     const R two_m32 = R(2.3283064365386962890625e-10);   // 2^-32
     R ua = (R(xa) + R(1)) * two_m32;                     // (0, 1]
     R ub = R(xb) * two_m32;                              // [0, 1)
-    R rad = sqrt_(R(-2) * log_(ua));
+    R rad = rsqrt_sqrt_(R(-2) * log_(ua));
     R s, c;
     sincospi_(R(2) * ub, &s, &c);
     z0 = rad * c;
