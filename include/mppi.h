@@ -175,6 +175,69 @@ int mppi_plant_step_async(mppi_handle_t h, double* q, double* qd,
                           const double* u, double dt, int substeps,
                           void* stream);
 
+/* ---- batched problems (one persistent launch per control tick) ---- */
+
+typedef struct mppi_batch* mppi_batch_t;
+
+/* One problem of a batch: its own arm and cost (K, T, weights, lambda).
+ * Rollouts run in FP32 (cost->precision must be MPPI_FP32) and T must be
+ * at most 64. */
+typedef struct {
+    const mppi_robot_params* robot;
+    const mppi_cost_params* cost;
+} mppi_problem_desc;
+
+/* Creates a batch of n >= 1 problems.  Copies every struct; validates each
+ * problem as mppi_create does; builds the work list (64-sample tiles,
+ * longest horizon first) and the device tables.  Errors: MPPI_EINVAL,
+ * MPPI_ENOTSUP (FP64 or T > 64), MPPI_ENOMEM, MPPI_EDEVICE. */
+int mppi_batch_create(const mppi_problem_desc* descs, int n, mppi_batch_t* out);
+int mppi_batch_destroy(mppi_batch_t b);
+
+/* Layout of the packed arrays: problem p's U rows start at u_off[p]
+ * (in doubles, [T_p][7]) and its costs at k_off[p] (in floats).  Either
+ * output array may be NULL; totals are written when the pointers are
+ * non-NULL. */
+int mppi_batch_layout(mppi_batch_t b, size_t* u_off, size_t* k_off, size_t* u_total, size_t* k_total);
+
+/* Device I/O of a batched update.  All pointers are device memory. */
+typedef struct {
+    const double* q;          /* [n][7] */
+    const double* qd;         /* [n][7] */
+    const double* target;     /* [n][13]: p_des, quat_des, F_des */
+    const double* U_nominal;  /* packed [sum T][7] */
+    double* U_new;            /* packed [sum T][7] out (may alias U_nominal) */
+    double* U_shift;          /* packed [sum T][7] out or NULL (must not alias the others) */
+    float* costs;             /* packed [sum K] out or NULL */
+    int* status;              /* [n] out or NULL */
+    const uint64_t* seed;     /* [n] Philox keys */
+} mppi_batch_io;
+
+/* Enqueues one batched update with Philox tick `tick` on `stream`. */
+int mppi_batch_update_async(mppi_batch_t b, const mppi_batch_io* io, uint64_t tick, void* stream);
+
+/* Launch shape: waves per workgroup (1, 2 or 4) and workgroup count. */
+int mppi_batch_set_launch(mppi_batch_t b, int waves_per_group, int groups);
+
+/* Times every launch shape of the built-in search space (waves per
+ * workgroup {1, 2, 4} x resident waves {256, 512, 1024, 2048}) with `reps`
+ * updates each on `stream`, keeps the fastest and returns it.  times_ms
+ * (may be NULL) receives the 12 mean times in search order.  The io buffers
+ * are written by the timing runs. */
+int mppi_batch_autotune(mppi_batch_t b, const mppi_batch_io* io, int reps, void* stream,
+                        int* best_waves_per_group, int* best_groups, float* times_ms);
+
+/* Captures one batched update with these io pointers (which must stay
+ * valid) into a HIP graph: the update reads the Philox tick from a device
+ * slot of the graph and then advances it by one.  mppi_batch_set_tick sets
+ * that slot (synchronous; eager mppi_batch_update_async calls use a slot of
+ * their own and never move it); mppi_batch_graph_launch replays the graph
+ * on `stream`.  Replays and eager calls share the batch's work queue, so
+ * they must not overlap in time. */
+int mppi_batch_graph_capture(mppi_batch_t b, const mppi_batch_io* io);
+int mppi_batch_set_tick(mppi_batch_t b, uint64_t tick);
+int mppi_batch_graph_launch(mppi_batch_t b, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* mppi_strerror(int status);
 

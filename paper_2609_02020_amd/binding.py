@@ -261,3 +261,113 @@ class Solver:
                                              int(substeps), _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_plant_step_async")
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("robot", C.POINTER(RobotParams)), ("cost", C.POINTER(CostParams))]
+
+
+class BatchIO(C.Structure):
+    _fields_ = [("q", C.c_void_p), ("qd", C.c_void_p), ("target", C.c_void_p),
+                ("U_nominal", C.c_void_p), ("U_new", C.c_void_p), ("U_shift", C.c_void_p),
+                ("costs", C.c_void_p), ("status", C.c_void_p), ("seed", C.c_void_p)]
+
+
+def _batch_lib():
+    L = lib()
+    if not hasattr(L, "_batch_ready"):
+        P, vp = C.POINTER, C.c_void_p
+        L.mppi_batch_create.argtypes = [P(ProblemDesc), C.c_int, P(vp)]
+        L.mppi_batch_destroy.argtypes = [vp]
+        L.mppi_batch_layout.argtypes = [vp, P(C.c_size_t), P(C.c_size_t), P(C.c_size_t), P(C.c_size_t)]
+        L.mppi_batch_update_async.argtypes = [vp, P(BatchIO), C.c_uint64, vp]
+        L.mppi_batch_set_launch.argtypes = [vp, C.c_int, C.c_int]
+        L.mppi_batch_autotune.argtypes = [vp, P(BatchIO), C.c_int, vp, P(C.c_int), P(C.c_int),
+                                          P(C.c_float)]
+        L.mppi_batch_graph_capture.argtypes = [vp, P(BatchIO)]
+        L.mppi_batch_set_tick.argtypes = [vp, C.c_uint64]
+        L.mppi_batch_graph_launch.argtypes = [vp, vp]
+        L._batch_ready = True
+    return L
+
+
+class Batch:
+    """Many independent MPPI problems in one persistent launch
+    (mppi_batch_*).  Problems are (robot dict, cost dict) pairs; rollouts
+    run in FP32."""
+
+    def __init__(self, problems, lambda_fp64_threshold: float = 0.05):
+        self._lib = _batch_lib()
+        self.n = len(problems)
+        self._rps = [robot_params(r) for r, _ in problems]
+        self._cps = [cost_params(c, FP32, lambda_fp64_threshold) for _, c in problems]
+        self.K = [int(c["K"]) for _, c in problems]
+        self.T = [int(c["T"]) for _, c in problems]
+        descs = (ProblemDesc * self.n)()
+        for i in range(self.n):
+            descs[i].robot = C.pointer(self._rps[i])
+            descs[i].cost = C.pointer(self._cps[i])
+        self._h = C.c_void_p()
+        st = self._lib.mppi_batch_create(descs, self.n, C.byref(self._h))
+        if st:
+            raise MppiError(st, "mppi_batch_create")
+        u_off = (C.c_size_t * self.n)()
+        k_off = (C.c_size_t * self.n)()
+        ut, kt = C.c_size_t(), C.c_size_t()
+        self._lib.mppi_batch_layout(self._h, u_off, k_off, C.byref(ut), C.byref(kt))
+        self.u_off, self.k_off = list(u_off), list(k_off)
+        self.u_total, self.k_total = ut.value, kt.value
+
+    def close(self):
+        if self._h:
+            self._lib.mppi_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _io(self, io: dict) -> BatchIO:
+        d = BatchIO()
+        for key in ("q", "qd", "target", "U_nominal", "U_new", "U_shift", "costs", "status", "seed"):
+            setattr(d, key, _ptr(io.get(key)))
+        return d
+
+    def update_async(self, io: dict, tick: int, stream=None):
+        d = self._io(io)
+        st = self._lib.mppi_batch_update_async(self._h, C.byref(d), C.c_uint64(tick), _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_batch_update_async")
+
+    def set_launch(self, waves_per_group: int, groups: int):
+        st = self._lib.mppi_batch_set_launch(self._h, int(waves_per_group), int(groups))
+        if st:
+            raise MppiError(st, "mppi_batch_set_launch")
+
+    def autotune(self, io: dict, reps: int = 3, stream=None):
+        d = self._io(io)
+        w, g = C.c_int(), C.c_int()
+        times = (C.c_float * 12)()
+        st = self._lib.mppi_batch_autotune(self._h, C.byref(d), int(reps), _stream_ptr(stream),
+                                           C.byref(w), C.byref(g), times)
+        if st:
+            raise MppiError(st, "mppi_batch_autotune")
+        return w.value, g.value, list(times)
+
+    def graph_capture(self, io: dict):
+        self._graph_io = self._io(io)
+        st = self._lib.mppi_batch_graph_capture(self._h, C.byref(self._graph_io))
+        if st:
+            raise MppiError(st, "mppi_batch_graph_capture")
+
+    def set_tick(self, tick: int):
+        st = self._lib.mppi_batch_set_tick(self._h, C.c_uint64(tick))
+        if st:
+            raise MppiError(st, "mppi_batch_set_tick")
+
+    def graph_launch(self, stream=None):
+        st = self._lib.mppi_batch_graph_launch(self._h, _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_batch_graph_launch")

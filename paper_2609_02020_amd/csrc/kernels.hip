@@ -17,10 +17,12 @@
 
 #include <cfloat>
 #include <cmath>
+#include <cstring>
 
 #include "launch.hpp"
 #include "model_prep.hpp"
 #include "rollout.hpp"
+#include "wave.hpp"
 
 namespace mppi {
 
@@ -33,22 +35,14 @@ __global__ void prep_model_kernel(const mppi_robot_params* __restrict__ P, Model
     }
 }
 
-template <typename A> __device__ __forceinline__ A wave_min(A v);
-template <typename A> __device__ __forceinline__ A wave_sum(A v);
-
-// One MPPI update in one launch (a1-a12).  Each block is one wave of 64
-// samples (one per lane).  Every lane rolls out its sample, writes S_k and
-// keeps du[t][j] in a padded LDS tile (rows x 65) when it fits, else in the
-// global noise buffer (also written when the caller asks for the noise).
-// The wave then reduces its samples to a partial of Eq. 4 with its own
-// shift m_w = min S_k:
-//   s_w = sum_k exp((m_w - S_k)/lambda),  V_w[r] = sum_k exp(...) du_k[r].
-// The last block to finish (device-scope counter) merges the partials with
-// the log-sum-exp rule m = min m_w, f_w = exp((m - m_w)/lambda),
-// U_new[r] = U_nom[r] + sum_w f_w V_w[r] / sum_w f_w s_w, which equals
-// Eq. 4b with S_min = m exactly in real arithmetic.  With merge == 0 the
-// kernel stops after the rollouts (costs and global noise only).
-constexpr int kLdsRowPad = 65;
+// One MPPI update in one launch (a1-a12).  Each workgroup is one wave of
+// 64 samples (one per lane).  Every lane rolls out its sample and writes
+// S_k; the noise goes to a padded LDS tile when it fits (else it is
+// regenerated from the Philox counters for the weighting) and to the
+// global noise buffer only when the caller asks for it.  The wave reduces
+// its samples to a partial of Eq. 4 (wave.hpp) and the last workgroup to
+// finish merges the partials.  With merge == 0 the kernel stops after the
+// rollouts (costs and global noise only).
 constexpr int kMaxDynLds = 48 * 1024;
 
 template <typename R, typename A, bool FORCE>
@@ -67,21 +61,15 @@ __global__ __launch_bounds__(kRolloutBlock) void update_kernel(
     // ~250 values are more than the scalar registers hold across a step
     __shared__ ModelM<R> Msh;
     __shared__ CostM<R> Csh;
-    {
-        const uint32_t* src = reinterpret_cast<const uint32_t*>(Mp);
-        uint32_t* dst = reinterpret_cast<uint32_t*>(&Msh);
-        for (int i = threadIdx.x; i < (int)(sizeof(ModelM<R>) / 4); i += blockDim.x) dst[i] = src[i];
-        src = reinterpret_cast<const uint32_t*>(Cp);
-        dst = reinterpret_cast<uint32_t*>(&Csh);
-        for (int i = threadIdx.x; i < (int)(sizeof(CostM<R>) / 4); i += blockDim.x) dst[i] = src[i];
-    }
+    const int lane = threadIdx.x & 63;
+    wave_copy(&Msh, Mp, sizeof(ModelM<R>), lane);
+    wave_copy(&Csh, Cp, sizeof(CostM<R>), lane);
     for (int i = threadIdx.x; i < T * NJ; i += blockDim.x) Us[i] = R(U_nom[i]);
     __syncthreads();
     const ModelM<R>& M = Msh;
     const CostM<R>& C = Csh;
-    const int lane = threadIdx.x & 63;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    R* tile = reinterpret_cast<R*>(dyn_lds);   // [rows][65] when lds_noise
+    R* tile = reinterpret_cast<R*>(dyn_lds);   // [rows][65] (noise) or [64][65] (regeneration)
     R s = R(INFINITY);
     {
         TargetM<R> tg;
@@ -102,130 +90,143 @@ __global__ __launch_bounds__(kRolloutBlock) void update_kernel(
     }
     if (!merge) return;
 
-    // ---- wave partial
-    const int rows = T * NJ;
-    const int P = 2 + rows;
-    const int kbase = blockIdx.x * blockDim.x;
-    const int nk = min(64, K - kbase);
-    const A inf = A(INFINITY), il = A(1) / A(lambda);
-    A m = wave_min(s < R(INFINITY) ? A(s) : inf);
-    A w = (s < R(INFINITY)) ? exp((m - A(s)) * il) : A(0);
-    A sw = wave_sum(w);
-    wl[lane] = w;
-    __syncthreads();
-    A* part = parts + (size_t)blockIdx.x * P;
-    if (lds_noise) {
-        // lane r sums row r of the tile (row stride 65: conflict-free)
-        for (int r = lane; r < rows; r += 64) {
-            const R* row = tile + r * kLdsRowPad;
-            A acc = A(0);
-#pragma unroll 16
-            for (int i = 0; i < 64; ++i) acc += wl[i] * A(row[i]);
-            part[2 + r] = acc;
-        }
-    } else {
-        // global noise: stage 64 rows at a time with coalesced loads along k
-        A* trt = reinterpret_cast<A*>(dyn_lds);   // [64][65]
-        for (int c0 = 0; c0 < rows; c0 += 64) {
-            const int nr = min(64, rows - c0);
-#pragma unroll 8
-            for (int rr = 0; rr < nr; ++rr)
-                trt[rr * kLdsRowPad + lane] = lane < nk ? A(noise[(size_t)(c0 + rr) * K + kbase + lane]) : A(0);
-            __syncthreads();
-            if (lane < nr) {
-                A acc = A(0);
-#pragma unroll 16
-                for (int i = 0; i < 64; ++i) acc += wl[i] * trt[lane * kLdsRowPad + i];
-                part[2 + c0 + lane] = acc;
-            }
-            __syncthreads();
-        }
-    }
-    if (lane == 0) { part[0] = m; part[1] = sw; }
+    const int P = 2 + T * NJ;
+    wave_sync();
+    wave_partial<R, A>(s, lane, T, lambda, lds_noise ? tile : nullptr, C, seed, tick, (uint32_t)k, tile, wl,
+                       parts + (size_t)blockIdx.x * P);
 
-    // ---- the last block merges all partials
+    // the last workgroup merges all partials
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
     __syncthreads();
     if (!last) return;
     __threadfence();
-    const int np = gridDim.x;
-    A mg = inf;
-    for (int p = lane; p < np; p += 64) mg = fmin(mg, parts[(size_t)p * P]);
-    mg = wave_min(mg);
-    if (!(mg < inf)) {  // no finite cost: keep the nominal sequence
-        for (int r = lane; r < rows; r += 64) {
-            const int t = r / NJ, j = r % NJ;
-            const double un = U_nom[r];
-            U_new[r] = un;
-            if (U_shift) {
-                if (t >= 1) U_shift[(t - 1) * NJ + j] = un;
-                if (t == T - 1) U_shift[t * NJ + j] = un;
-            }
-        }
-        if (status && lane == 0) *status = MPPI_ENONFINITE;
-        if (lane == 0) *counter = 0u;
-        return;
-    }
-    A eta = A(0);
-    for (int p = lane; p < np; p += 64) {
-        A mp = parts[(size_t)p * P];
-        if (mp < inf) eta += exp((mg - mp) * il) * parts[(size_t)p * P + 1];
-    }
-    eta = wave_sum(eta);
-    // rows r0 + lane: V[r] = sum_p f_p V_p[r], f_p = exp((m - m_p)/lambda),
-    // 64 partials at a time (factors staged in LDS, loads coalesced along r)
-    for (int r0 = 0; r0 < rows; r0 += 64) {
-        const int r = r0 + lane;
-        A acc = A(0);
-        for (int p0 = 0; p0 < np; p0 += 64) {
-            const int p = p0 + lane;
-            A f = A(0);
-            if (p < np) {
-                A mp = parts[(size_t)p * P];
-                f = (mp < inf) ? exp((mg - mp) * il) : A(0);
-            }
-            __syncthreads();
-            wl[lane] = f;
-            __syncthreads();
-            if (r < rows) {
-                if (np - p0 >= 64) {
-                    A v[64];
-#pragma unroll
-                    for (int i = 0; i < 64; ++i) v[i] = parts[(size_t)(p0 + i) * P + 2 + r];
-#pragma unroll
-                    for (int i = 0; i < 64; ++i) acc += wl[i] * v[i];
-                } else {
-                    for (int i = 0; i < np - p0; ++i) acc += wl[i] * parts[(size_t)(p0 + i) * P + 2 + r];
-                }
-            }
-        }
-        if (r < rows) {
-            const int t = r / NJ, j = r % NJ;
-            const double un = U_nom[r] + double(acc / eta);
-            U_new[r] = un;
-            if (U_shift) {
-                if (t >= 1) U_shift[(t - 1) * NJ + j] = un;
-                if (t == T - 1) U_shift[t * NJ + j] = un;
-            }
-        }
-    }
-    if (status && lane == 0) *status = MPPI_OK;
+    wave_merge<A>(parts, gridDim.x, T, lambda, U_nom, U_new, U_shift, status, lane, wl);
     if (lane == 0) *counter = 0u;
 }
 
-template <typename A> __device__ __forceinline__ A wave_min(A v)
+// Batched update (a13): many independent problems (own arm, cost, K, T,
+// seed) in one persistent launch.  Work items are 64-sample tiles, ordered
+// longest horizon first on the host; every wave pops items from a
+// device-scope queue, rolls out its tile, writes the tile's Eq. 4 partial
+// (noise regenerated from the Philox counters) and bumps its problem's
+// counter; the wave that completes a problem merges that problem's
+// partials.  The last wave to leave resets the queue, and every problem
+// counter is reset by its merging wave, so the launch can be replayed (a
+// captured graph) without clearing memory in between.
+struct BatchProblem {
+    const ModelM<float>* model;
+    const CostM<float>* cost;
+    int K, T, force, acc64;
+    double lambda;
+    int ntiles;
+    int pad;
+    long long u_off;      // into the packed [sum T][7] arrays
+    long long k_off;      // into the packed costs
+    long long part_off;   // into the partials buffer, in doubles
+};
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void batch_kernel(
+    const BatchProblem* __restrict__ probs, const int2* __restrict__ items, int nitems,
+    unsigned int* queue, unsigned int* done, unsigned int* counters, const double* __restrict__ q,
+    const double* __restrict__ qd, const double* __restrict__ target, const double* U_nom, double* U_new,
+    double* U_shift, float* __restrict__ costs, int* __restrict__ status, const uint64_t* __restrict__ seeds,
+    const uint64_t* __restrict__ tickp, double* __restrict__ parts)
 {
+    __shared__ ModelM<float> Msh[W];
+    __shared__ CostM<float> Csh[W];
+    __shared__ float Us[W][kMaxTBatch * NJ];
+    __shared__ float tr[W][64 * kLdsRowPad];
+    __shared__ double wl[W][64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint32_t tick = (uint32_t)*tickp;
+    // Queue pops, completion counts and the exit count are atomics that every
+    // lane executes (adding 1 on lane 0 and 0 elsewhere) with the result
+    // taken from lane 0, so the control flow around them stays uniform: a
+    // lane-0-only atomic inside this loop let the compiler split the loop
+    // so that lanes 1..63 re-ran a tile with a stale item.
+    for (;;) {
+        const int item = __builtin_amdgcn_readfirstlane((int)atomicAdd(queue, lane == 0 ? 1u : 0u));
+        if (item >= nitems) break;
+        const int2 it = items[item];
+        const BatchProblem& Pb = probs[it.x];
+        const int T = Pb.T, K = Pb.K;
+        wave_sync();
+        wave_copy(&Msh[wid], Pb.model, sizeof(ModelM<float>), lane);
+        wave_copy(&Csh[wid], Pb.cost, sizeof(CostM<float>), lane);
+        for (int i = lane; i < T * NJ; i += 64) Us[wid][i] = float(U_nom[Pb.u_off + i]);
+        wave_sync();
+        const ModelM<float>& M = Msh[wid];
+        const CostM<float>& C = Csh[wid];
+        const int k = it.y * 64 + lane;
+        const uint64_t seed = seeds[it.x];
+        float s = INFINITY;
+        {
+            TargetM<float> tg;
+            make_target(target + (size_t)it.x * 13, tg);
+            float q0[NJ], qd0[NJ], te[NJ];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    return v;
+            for (int j = 0; j < NJ; ++j) {
+                q0[j] = float(q[it.x * NJ + j]);
+                qd0[j] = float(qd[it.x * NJ + j]);
+                te[j] = 0.0f;
+            }
+            if (C.ext_mode == EXTW_CONST) const_ext_torque(M, C, q0, te);
+            if (k < K) {
+                float v = Pb.force ? rollout_sample<float, true>(M, C, tg, q0, qd0, te, Us[wid], T, seed, tick,
+                                                                 (uint32_t)k, (float*)nullptr, 0)
+                                   : rollout_sample<float, false>(M, C, tg, q0, qd0, te, Us[wid], T, seed, tick,
+                                                                  (uint32_t)k, (float*)nullptr, 0);
+                s = finite_(v) ? v : INFINITY;
+                if (costs) costs[Pb.k_off + k] = s;
+            }
+        }
+        const int P = 2 + T * NJ;
+        double* pbase = parts + Pb.part_off;
+        wave_sync();
+        if (Pb.acc64)
+            wave_partial<float, double>(s, lane, T, Pb.lambda, nullptr, C, seed, tick, (uint32_t)k, tr[wid],
+                                        wl[wid], pbase + (size_t)it.y * P);
+        else
+            wave_partial<float, float>(s, lane, T, Pb.lambda, nullptr, C, seed, tick, (uint32_t)k, tr[wid],
+                                       reinterpret_cast<float*>(wl[wid]),
+                                       reinterpret_cast<float*>(pbase) + (size_t)it.y * P);
+        __threadfence();
+        const unsigned done_tiles =
+            (unsigned)__builtin_amdgcn_readfirstlane((int)atomicAdd(&counters[it.x], lane == 0 ? 1u : 0u));
+        if (done_tiles == (unsigned)(Pb.ntiles - 1)) {
+            __threadfence();
+            const double* un = U_nom + Pb.u_off;
+            double* uw = U_new + Pb.u_off;
+            double* us = U_shift ? U_shift + Pb.u_off : nullptr;
+            int* st = status ? status + it.x : nullptr;
+            if (Pb.acc64) wave_merge<double>(pbase, Pb.ntiles, T, Pb.lambda, un, uw, us, st, lane, wl[wid]);
+            else
+                wave_merge<float>(reinterpret_cast<const float*>(pbase), Pb.ntiles, T, Pb.lambda, un, uw, us, st,
+                                  lane, reinterpret_cast<float*>(wl[wid]));
+            if (lane == 0) counters[it.x] = 0u;
+        }
+    }
+    // the last wave out resets the queue for the next launch
+    __threadfence();
+    const unsigned out = (unsigned)__builtin_amdgcn_readfirstlane((int)atomicAdd(done, lane == 0 ? 1u : 0u));
+    if (out == gridDim.x * W - 1 && lane == 0) {
+        *queue = 0u;
+        *done = 0u;
+        __threadfence();
+    }
 }
-template <typename A> __device__ __forceinline__ A wave_sum(A v)
+
+__global__ void advance_tick_kernel(uint64_t* tick)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *tick += 1;
+}
+
+__global__ void set_tick_kernel(uint64_t* tick, uint64_t v)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *tick = v;
 }
 
 template <typename R, typename A, int ROWS>
@@ -346,11 +347,11 @@ template <typename R, typename A, bool FORCE> static hipError_t update_t(const U
     const size_t rows = (size_t)a.T * NJ;
     const size_t tile = rows * kLdsRowPad * sizeof(R);
     const int lds_noise = a.merge && tile <= (size_t)kMaxDynLds;
-    const size_t dyn = lds_noise ? tile : (a.merge ? 64 * kLdsRowPad * sizeof(A) : 0);
-    // global noise: always for rollouts-only launches and the global-tile
-    // path; otherwise only when the caller asked for it
+    const size_t dyn = lds_noise ? tile : (a.merge ? 64 * kLdsRowPad * sizeof(R) : 0);
+    // global noise: always for rollouts-only launches, otherwise only when
+    // the caller asked for it
     R* noise = (R*)a.noise;
-    if (a.merge && lds_noise && !a.want_noise) noise = nullptr;
+    if (a.merge && !a.want_noise) noise = nullptr;
     hipLaunchKernelGGL((update_kernel<R, A, FORCE>), grid, dim3(kRolloutBlock), dyn, s,
                        (const ModelM<R>*)a.model, (const CostM<R>*)a.cost, a.q0, a.qd0, a.target, a.U_nom,
                        a.seed, (uint32_t)a.tick, a.K, a.T, a.lambda, noise, (R*)a.costs, a.merge, lds_noise,
@@ -385,6 +386,51 @@ hipError_t launch_weights(int precision, bool acc64, const WeightsArgs& a, hipSt
 {
     if (precision == MPPI_FP64) return weights_t<double, double>(a, s);
     return acc64 ? weights_t<float, double>(a, s) : weights_t<float, float>(a, s);
+}
+
+template <int W> static hipError_t batch_t(const BatchArgs& a, int groups, hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_kernel<W>), dim3(groups), dim3(64 * W), 0, s, (const BatchProblem*)a.probs,
+                       (const int2*)a.items, a.nitems, a.queue, a.done, a.counters, a.q, a.qd, a.target, a.U_nom,
+                       a.U_new, a.U_shift, a.costs, a.status, a.seeds, a.tick, a.parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs& a, int waves_per_group, int groups, hipStream_t s)
+{
+    if (groups < 1 || a.nitems < 1) return hipErrorInvalidValue;
+    switch (waves_per_group) {
+    case 1: return batch_t<1>(a, groups, s);
+    case 2: return batch_t<2>(a, groups, s);
+    case 4: return batch_t<4>(a, groups, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_advance_tick(uint64_t* tick, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_tick_kernel, dim3(1), dim3(64), 0, s, tick);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_tick(uint64_t* tick, uint64_t v, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_tick_kernel, dim3(1), dim3(64), 0, s, tick, v);
+    return hipGetLastError();
+}
+
+size_t batch_problem_bytes() { return sizeof(BatchProblem); }
+
+void fill_batch_problem(void* dst, const void* model, const void* cost, int K, int T, int force, int acc64,
+                        double lambda, int ntiles, long long u_off, long long k_off, long long part_off)
+{
+    BatchProblem p;
+    p.model = (const ModelM<float>*)model;
+    p.cost = (const CostM<float>*)cost;
+    p.K = K; p.T = T; p.force = force; p.acc64 = acc64;
+    p.lambda = lambda; p.ntiles = ntiles; p.pad = 0;
+    p.u_off = u_off; p.k_off = k_off; p.part_off = part_off;
+    memcpy(dst, &p, sizeof p);
 }
 
 hipError_t launch_plant(const ModelM<double>* M, const CostM<double>* C, double* q, double* qd,

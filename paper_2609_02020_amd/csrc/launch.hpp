@@ -45,6 +45,34 @@ struct UpdateArgs {
 hipError_t launch_update(int precision, bool acc64, bool force, const UpdateArgs& a, hipStream_t s);
 size_t update_parts_bytes(int K, int T);
 
+struct BatchArgs {
+    const void* probs;      // BatchProblem [n] (device)
+    const void* items;      // int2 [nitems]: (problem, tile), in schedule order
+    int nitems;
+    unsigned int* queue;    // zero before the first launch; the kernel leaves it zero
+    unsigned int* done;
+    unsigned int* counters; // [n], zero; each reset by the problem's merging wave
+    const double* q;        // [n][7]
+    const double* qd;       // [n][7]
+    const double* target;   // [n][13]
+    const double* U_nom;    // packed [sum T][7]
+    double* U_new;
+    double* U_shift;        // may be null
+    float* costs;           // packed [sum K], may be null
+    int* status;            // [n], may be null
+    const uint64_t* seeds;  // [n]
+    const uint64_t* tick;   // [1] (device)
+    double* parts;          // partials, sized by the host
+};
+
+// Persistent batched update: `groups` workgroups of `waves_per_group` waves.
+hipError_t launch_batch(const BatchArgs& a, int waves_per_group, int groups, hipStream_t s);
+hipError_t launch_advance_tick(uint64_t* tick, hipStream_t s);
+hipError_t launch_set_tick(uint64_t* tick, uint64_t v, hipStream_t s);
+size_t batch_problem_bytes();
+void fill_batch_problem(void* dst, const void* model, const void* cost, int K, int T, int force, int acc64,
+                        double lambda, int ntiles, long long u_off, long long k_off, long long part_off);
+
 hipError_t launch_prep_model(const mppi_robot_params* d_raw, ModelM<float>* d_mf, ModelM<double>* d_md,
                              hipStream_t s);
 // acc64: accumulate the weights and sums in FP64
@@ -56,5 +84,6 @@ constexpr int kRolloutBlock = 64;
 constexpr int kWeightsBlock = 256;
 constexpr int kWeightsRows = 2;
 constexpr int kMaxT = 256;
+constexpr int kMaxTBatch = 64;   // horizon limit of the batched kernel
 
 }  // namespace mppi

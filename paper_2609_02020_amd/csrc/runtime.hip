@@ -385,3 +385,284 @@ const char* mppi_strerror(int status)
 const char* mppi_version(void) { return "mppi-gfx950 0.1"; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched problems
+// ---------------------------------------------------------------------------
+#include <algorithm>
+#include <vector>
+
+struct mppi_batch {
+    int n = 0;
+    std::vector<mppi_robot_params> robot;
+    std::vector<mppi_cost_params> cost;
+    std::vector<size_t> u_off, k_off;
+    size_t u_total = 0, k_total = 0;
+    mppi_robot_params* d_raw = nullptr;
+    ModelM<float>* d_mf = nullptr;
+    ModelM<double>* d_md = nullptr;
+    CostM<float>* d_cf = nullptr;
+    void* d_probs = nullptr;
+    int2* d_items = nullptr;
+    int nitems = 0;
+    unsigned int* d_sync = nullptr;   // queue, done, counters[n]
+    double* d_parts = nullptr;
+    uint64_t* d_tick = nullptr;   // [0]: graph replays (advanced by the graph), [1]: eager launches
+    int wpg = 1, groups = 1024;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+void batch_release(mppi_batch* b)
+{
+    if (!b) return;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    (void)hipFree(b->d_raw);
+    (void)hipFree(b->d_mf);
+    (void)hipFree(b->d_md);
+    (void)hipFree(b->d_cf);
+    (void)hipFree(b->d_probs);
+    (void)hipFree(b->d_items);
+    (void)hipFree(b->d_sync);
+    (void)hipFree(b->d_parts);
+    (void)hipFree(b->d_tick);
+    delete b;
+}
+
+BatchArgs batch_args(mppi_batch* b, const mppi_batch_io* io, const uint64_t* tick_slot)
+{
+    BatchArgs a;
+    a.probs = b->d_probs;
+    a.items = b->d_items;
+    a.nitems = b->nitems;
+    a.queue = b->d_sync;
+    a.done = b->d_sync + 1;
+    a.counters = b->d_sync + 2;
+    a.q = io->q;
+    a.qd = io->qd;
+    a.target = io->target;
+    a.U_nom = io->U_nominal;
+    a.U_new = io->U_new;
+    a.U_shift = io->U_shift;
+    a.costs = io->costs;
+    a.status = io->status;
+    a.seeds = io->seed;
+    a.tick = tick_slot;
+    a.parts = b->d_parts;
+    return a;
+}
+
+int check_batch_io(const mppi_batch* b, const mppi_batch_io* io)
+{
+    if (!b || !io || !io->q || !io->qd || !io->target || !io->U_nominal || !io->U_new || !io->seed)
+        return MPPI_EINVAL;
+    return MPPI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mppi_batch_create(const mppi_problem_desc* descs, int n, mppi_batch_t* out)
+{
+    if (!out) return MPPI_EINVAL;
+    *out = nullptr;
+    if (!descs || n < 1 || n > (1 << 16)) return MPPI_EINVAL;
+    for (int p = 0; p < n; ++p) {
+        int st = validate_robot(descs[p].robot);
+        if (!st) st = validate_cost(descs[p].cost);
+        if (st) return st;
+        if (descs[p].cost->precision != MPPI_FP32 || descs[p].cost->T > kMaxTBatch) return MPPI_ENOTSUP;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MPPI_EDEVICE;
+    mppi_batch* b = new (std::nothrow) mppi_batch;
+    if (!b) return MPPI_ENOMEM;
+    b->n = n;
+    b->robot.resize(n);
+    b->cost.resize(n);
+    b->u_off.resize(n);
+    b->k_off.resize(n);
+    std::vector<long long> part_off(n);
+    std::vector<int> ntiles(n);
+    long long parts_total = 0;
+    for (int p = 0; p < n; ++p) {
+        b->robot[p] = *descs[p].robot;
+        b->cost[p] = *descs[p].cost;
+        const int K = b->cost[p].K, T = b->cost[p].T;
+        b->u_off[p] = b->u_total;
+        b->k_off[p] = b->k_total;
+        b->u_total += (size_t)T * MPPI_NJ;
+        b->k_total += (size_t)K;
+        ntiles[p] = (K + 63) / 64;
+        part_off[p] = parts_total;
+        parts_total += (long long)ntiles[p] * (2 + T * MPPI_NJ);
+    }
+    // work list: 64-sample tiles, heaviest per-tile work (horizon, force
+    // cost) first, so the long rollouts start early (longest-processing-time
+    // order)
+    std::vector<int> order(n);
+    for (int p = 0; p < n; ++p) order[p] = p;
+    auto work = [&](int p) { return (double)b->cost[p].T * (has_force(b->cost[p]) ? 1.25 : 1.0); };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+    std::vector<int2> items;
+    for (int p : order)
+        for (int t = 0; t < ntiles[p]; ++t) items.push_back(make_int2(p, t));
+    b->nitems = (int)items.size();
+    bool ok = hipMalloc(&b->d_raw, sizeof(mppi_robot_params) * n) == hipSuccess &&
+              hipMalloc(&b->d_mf, sizeof(ModelM<float>) * n) == hipSuccess &&
+              hipMalloc(&b->d_md, sizeof(ModelM<double>) * n) == hipSuccess &&
+              hipMalloc(&b->d_cf, sizeof(CostM<float>) * n) == hipSuccess &&
+              hipMalloc(&b->d_probs, batch_problem_bytes() * n) == hipSuccess &&
+              hipMalloc(&b->d_items, sizeof(int2) * items.size()) == hipSuccess &&
+              hipMalloc(&b->d_sync, sizeof(unsigned int) * (2 + n)) == hipSuccess &&
+              hipMalloc(&b->d_parts, sizeof(double) * parts_total) == hipSuccess &&
+              hipMalloc(&b->d_tick, 2 * sizeof(uint64_t)) == hipSuccess;
+    if (!ok) { batch_release(b); return MPPI_ENOMEM; }
+    std::vector<CostM<float>> cf(n);
+    std::vector<char> probs(batch_problem_bytes() * n);
+    for (int p = 0; p < n; ++p) {
+        prep_cost(b->cost[p], cf[p]);
+        const mppi_cost_params& c = b->cost[p];
+        fill_batch_problem(probs.data() + batch_problem_bytes() * p, b->d_mf + p, b->d_cf + p, c.K, c.T,
+                           has_force(c) ? 1 : 0, acc64_of(c) ? 1 : 0, c.lambda, ntiles[p],
+                           (long long)b->u_off[p], (long long)b->k_off[p], part_off[p]);
+    }
+    ok = hipMemcpy(b->d_raw, b->robot.data(), sizeof(mppi_robot_params) * n, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->d_cf, cf.data(), sizeof(CostM<float>) * n, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->d_probs, probs.data(), probs.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemset(b->d_sync, 0, sizeof(unsigned int) * (2 + n)) == hipSuccess &&
+         hipMemset(b->d_tick, 0, 2 * sizeof(uint64_t)) == hipSuccess;
+    for (int p = 0; ok && p < n; ++p)
+        ok = launch_prep_model(b->d_raw + p, b->d_mf + p, b->d_md + p, nullptr) == hipSuccess;
+    if (!ok || hipDeviceSynchronize() != hipSuccess) { batch_release(b); return MPPI_EDEVICE; }
+    *out = b;
+    return MPPI_OK;
+}
+
+int mppi_batch_destroy(mppi_batch_t b)
+{
+    if (b) {
+        (void)hipDeviceSynchronize();
+        batch_release(b);
+    }
+    return MPPI_OK;
+}
+
+int mppi_batch_layout(mppi_batch_t b, size_t* u_off, size_t* k_off, size_t* u_total, size_t* k_total)
+{
+    if (!b) return MPPI_EINVAL;
+    for (int p = 0; p < b->n; ++p) {
+        if (u_off) u_off[p] = b->u_off[p];
+        if (k_off) k_off[p] = b->k_off[p];
+    }
+    if (u_total) *u_total = b->u_total;
+    if (k_total) *k_total = b->k_total;
+    return MPPI_OK;
+}
+
+int mppi_batch_set_launch(mppi_batch_t b, int waves_per_group, int groups)
+{
+    if (!b || (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4) || groups < 1 ||
+        groups > (1 << 16))
+        return MPPI_EINVAL;
+    b->wpg = waves_per_group;
+    b->groups = groups;
+    return MPPI_OK;
+}
+
+int mppi_batch_set_tick(mppi_batch_t b, uint64_t tick)
+{
+    if (!b) return MPPI_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess) return MPPI_EDEVICE;
+    return hipMemcpy(b->d_tick, &tick, sizeof tick, hipMemcpyHostToDevice) == hipSuccess ? MPPI_OK : MPPI_EDEVICE;
+}
+
+int mppi_batch_update_async(mppi_batch_t b, const mppi_batch_io* io, uint64_t tick, void* stream)
+{
+    int st = check_batch_io(b, io);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (launch_set_tick(b->d_tick + 1, tick, s) != hipSuccess) return MPPI_EDEVICE;
+    BatchArgs a = batch_args(b, io, b->d_tick + 1);
+    return launch_batch(a, b->wpg, b->groups, s) == hipSuccess ? MPPI_OK : MPPI_EDEVICE;
+}
+
+int mppi_batch_autotune(mppi_batch_t b, const mppi_batch_io* io, int reps, void* stream, int* best_wpg,
+                        int* best_groups, float* times_ms)
+{
+    int st = check_batch_io(b, io);
+    if (st) return st;
+    if (reps < 1) return MPPI_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int wpgs[3] = {1, 2, 4};
+    const int waves[4] = {256, 512, 1024, 2048};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MPPI_EDEVICE;
+    BatchArgs a = batch_args(b, io, b->d_tick + 1);
+    float best = 1e30f;
+    int bw = b->wpg, bg = b->groups, idx = 0;
+    st = MPPI_OK;
+    for (int wi = 0; wi < 3 && !st; ++wi)
+        for (int vi = 0; vi < 4 && !st; ++vi, ++idx) {
+            const int w = wpgs[wi], g = waves[vi] / w;
+            // one untimed launch, then `reps` timed ones
+            if (launch_set_tick(b->d_tick + 1, 0, s) != hipSuccess || launch_batch(a, w, g, s) != hipSuccess ||
+                hipEventRecord(e0, s) != hipSuccess) { st = MPPI_EDEVICE; break; }
+            for (int r = 0; r < reps; ++r)
+                if (launch_set_tick(b->d_tick + 1, (uint64_t)r + 1, s) != hipSuccess ||
+                    launch_batch(a, w, g, s) != hipSuccess) { st = MPPI_EDEVICE; break; }
+            float ms = 0;
+            if (st || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = MPPI_EDEVICE; break; }
+            ms /= reps;
+            if (times_ms) times_ms[idx] = ms;
+            if (ms < best) { best = ms; bw = w; bg = g; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    b->wpg = bw;
+    b->groups = bg;
+    if (best_wpg) *best_wpg = bw;
+    if (best_groups) *best_groups = bg;
+    return MPPI_OK;
+}
+
+int mppi_batch_graph_capture(mppi_batch_t b, const mppi_batch_io* io)
+{
+    int st = check_batch_io(b, io);
+    if (st) return st;
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return MPPI_EDEVICE;
+    BatchArgs a = batch_args(b, io, b->d_tick);
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    ok = ok && launch_batch(a, b->wpg, b->groups, cs) == hipSuccess;
+    ok = ok && launch_advance_tick(b->d_tick, cs) == hipSuccess;
+    hipGraph_t g = nullptr;
+    ok = (hipStreamEndCapture(cs, &g) == hipSuccess) && ok && g;
+    (void)hipStreamDestroy(cs);
+    if (!ok) { if (g) (void)hipGraphDestroy(g); return MPPI_EDEVICE; }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        b->graph = nullptr;
+        b->gexec = nullptr;
+        return MPPI_EDEVICE;
+    }
+    return MPPI_OK;
+}
+
+int mppi_batch_graph_launch(mppi_batch_t b, void* stream)
+{
+    if (!b || !b->gexec) return MPPI_EINVAL;
+    return hipGraphLaunch(b->gexec, (hipStream_t)stream) == hipSuccess ? MPPI_OK : MPPI_EDEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+"""GPU tests of the batched persistent launch (mppi_batch_*).
+
+Each problem of a batch must give the single-problem update's result for
+the same seed and tick (same noise and per-wave partials; the two kernels
+may fuse multiply-adds differently, so agreement is to FP32 rounding, not
+bitwise), and match the oracle on sampled problems; graph replays must be
+bitwise equal to eager launches of the same kernel; the autotuner must
+return a shape from its search space.
+"""
+import numpy as np
+import pytest
+
+from paper_2609_02020_amd import binding as B
+from gpu_util import check_costs_fp32, check_update, device_update, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def batch_io(batch, cases, torch, dev):
+    f64 = dict(dtype=torch.float64, device=dev)
+    U = np.zeros((batch.u_total // 7, 7))
+    for p, c in enumerate(cases):
+        U[batch.u_off[p] // 7: batch.u_off[p] // 7 + batch.T[p]] = np.asarray(c["U_nom"])[:batch.T[p]]
+    return {
+        "q": torch.tensor(np.array([c["q0"] for c in cases]), **f64),
+        "qd": torch.tensor(np.array([c["qd0"] for c in cases]), **f64),
+        "target": torch.tensor(np.array([B.target_vector(c["target"]) for c in cases]), **f64),
+        "U_nominal": torch.tensor(U, **f64),
+        "U_new": torch.full(U.shape, float("nan"), **f64),
+        "U_shift": torch.full(U.shape, float("nan"), **f64),
+        "costs": torch.full((batch.k_total,), float("nan"), dtype=torch.float32, device=dev),
+        "status": torch.full((len(cases),), -1, dtype=torch.int32, device=dev),
+        "seed": torch.tensor([c["seed"] for c in cases], dtype=torch.int64, device=dev),
+    }
+
+
+def same_result(S_b, U_b, out, label):
+    bad = ~(np.isfinite(S_b) & np.isfinite(out["costs"]))
+    if bad.any():
+        print(label, "non-finite samples:", np.nonzero(bad)[0][:10], S_b[bad][:10], out["costs"][bad][:10])
+    rel = np.abs(S_b - out["costs"]) / np.abs(out["costs"])
+    assert rel.max() <= 1e-4, (label, rel.max())
+    assert np.abs(U_b - out["U_new"]).max() <= 1e-4, (label, np.abs(U_b - out["U_new"]).max())
+
+
+def pick(io, batch, p):
+    u0, k0, T, K = batch.u_off[p] // 7, batch.k_off[p], batch.T[p], batch.K[p]
+    return (io["U_new"][u0:u0 + T].cpu().numpy(), io["U_shift"][u0:u0 + T].cpu().numpy(),
+            io["costs"][k0:k0 + K].double().cpu().numpy(), int(io["status"][p].cpu()))
+
+
+def small_cases(workloads, n=12, tmax=None):
+    cases = []
+    for i, c in enumerate(workloads["batch64"][:n]):
+        K = min(c["cost"]["K"], 1500 + 37 * i)
+        cost = dict(c["cost"], K=K)
+        if tmax:
+            cost["T"] = min(cost["T"], tmax)
+        cases.append(dict(c, cost=cost, U_nom=np.asarray(c["U_nom"])[:cost["T"]]))
+    return cases
+
+
+def test_batch_equals_single_problem_updates(workloads):
+    torch, dev = torch_dev()
+    cases = small_cases(workloads, 12)
+    batch = B.Batch([(c["robot"], c["cost"]) for c in cases])
+    io = batch_io(batch, cases, torch, dev)
+    batch.update_async(io, tick=5)
+    torch.cuda.synchronize()
+    for p, c in enumerate(cases):
+        print("problem %d K=%d T=%d kind=%s" % (p, batch.K[p], batch.T[p], c["kind"]), flush=True)
+        U_b, Us_b, S_b, st = pick(io, batch, p)
+        solver = B.Solver(c["robot"], c["cost"], B.FP32)
+        out = device_update(solver, c, c["seed"], 5, B.FP32)
+        solver.close()
+        assert st == B.OK
+        same_result(S_b, U_b, out, "problem %d" % p)
+        assert np.array_equal(Us_b[:-1], U_b[1:]) and np.array_equal(Us_b[-1], U_b[-1])
+    batch.close()
+
+
+def test_batch_matches_oracle(ora, workloads):
+    torch, dev = torch_dev()
+    cases = small_cases(workloads, 6)
+    batch = B.Batch([(c["robot"], c["cost"]) for c in cases])
+    io = batch_io(batch, cases, torch, dev)
+    batch.update_async(io, tick=11)
+    torch.cuda.synchronize()
+    for p, c in enumerate(cases):
+        U_b, _, S_b, st = pick(io, batch, p)
+        stt, U_ref, S_ref, E_ref = ora.update(c["robot"], c["cost"], c["target"], c["q0"], c["qd0"],
+                                              c["U_nom"], c["seed"], 11)
+        check_costs_fp32(ora, c, S_b, S_ref, c["seed"], 11, "batch %d" % p)
+        out = {"U_new": U_b, "costs": S_b, "noise": E_ref}
+        note = check_update(ora, c, out, c["cost"]["lambda"], S_ref, U_ref, "batch %d" % p)
+        if note:
+            print(note)
+    batch.close()
+
+
+def test_batch_ragged_and_extreme_sizes(ora, workloads):
+    torch, dev = torch_dev()
+    base = workloads["batch64"]
+    specs = [(1, 1), (63, 64), (65, 2), (130, 17), (4097, 10)]
+    cases = []
+    for i, (K, T) in enumerate(specs):
+        c = base[i]
+        U = np.asarray(c["U_nom"])
+        U = np.concatenate([U, np.repeat(U[-1:], max(0, T - len(U)), 0)])[:T]
+        cases.append(dict(c, cost=dict(c["cost"], K=K, T=T), U_nom=U))
+    batch = B.Batch([(c["robot"], c["cost"]) for c in cases])
+    io = batch_io(batch, cases, torch, dev)
+    batch.update_async(io, tick=2)
+    torch.cuda.synchronize()
+    for p, c in enumerate(cases):
+        U_b, _, S_b, st = pick(io, batch, p)
+        solver = B.Solver(c["robot"], c["cost"], B.FP32)
+        out = device_update(solver, c, c["seed"], 2, B.FP32)
+        solver.close()
+        assert st == B.OK
+        same_result(S_b, U_b, out, "ragged %d" % p)
+    batch.close()
+
+
+def test_graph_replays_match_eager_launches(workloads):
+    torch, dev = torch_dev()
+    cases = small_cases(workloads, 8, tmax=20)
+    batch = B.Batch([(c["robot"], c["cost"]) for c in cases])
+    io_g = batch_io(batch, cases, torch, dev)
+    io_e = batch_io(batch, cases, torch, dev)
+    batch.graph_capture(io_g)
+    batch.set_tick(100)
+    stream = torch.cuda.current_stream()
+    for r in range(4):
+        batch.graph_launch(stream)
+        torch.cuda.synchronize()
+        _ = (io_e["U_nominal"] * 2.0).sum().item()   # eager work between replays
+        batch.update_async(io_e, tick=100 + r, stream=stream)
+        torch.cuda.synchronize()
+        assert torch.equal(io_g["U_new"], io_e["U_new"]), r
+        assert torch.equal(io_g["costs"], io_e["costs"]), r
+    batch.close()
+
+
+def test_autotune_picks_a_shape(workloads):
+    torch, dev = torch_dev()
+    cases = small_cases(workloads, 8, tmax=16)
+    batch = B.Batch([(c["robot"], c["cost"]) for c in cases])
+    io = batch_io(batch, cases, torch, dev)
+    w, g, times = batch.autotune(io, reps=2)
+    print("autotune: waves/group %d, groups %d, times %s" % (w, g, np.round(times, 3)))
+    assert w in (1, 2, 4) and g * w in (256, 512, 1024, 2048)
+    assert all(t > 0 for t in times) and min(times) == pytest.approx(times[[1, 2, 4].index(w) * 4 + [256, 512, 1024, 2048].index(g * w)])
+    # still correct after the timing runs, with the chosen shape
+    batch.update_async(io, tick=3)
+    torch.cuda.synchronize()
+    c = cases[0]
+    U_b, _, S_b, _ = pick(io, batch, 0)
+    solver = B.Solver(c["robot"], c["cost"], B.FP32)
+    out = device_update(solver, c, c["seed"], 3, B.FP32)
+    same_result(S_b, U_b, out, "after autotune")
+    batch.close()
