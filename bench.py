@@ -31,9 +31,38 @@ METRIC = "MPPI update rate (Hz) + ABA rollout steps/s, K=4096 T=18 7-DoF, FP32"
 # (force estimate, wall, orientation cost on).
 FLOPS_PER_SAMPLE_STEP = 6967
 FLOPS_PER_SAMPLE_TERMINAL = 822
+# Free-space problems (no wall, no force term, no orientation cost).
+FLOPS_PER_SAMPLE_STEP_FREE = 4573
+FLOPS_PER_SAMPLE_TERMINAL_FREE = 704
 # Eq. 4b: one multiply-add per sample and output row (weighted noise sum).
 FLOPS_PER_SAMPLE_ROW_WEIGHT = 2
 FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (AMD published)
+
+# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs of this
+# script, each scaled by what the counter reads for a plain device copy of
+# known size (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 on gfx950), taken on the
+# kernel sources whose digest is recorded here; reported as null once the
+# sources differ.
+PROFILED_DIGEST = "fed12822bb0ccc48"
+PROFILED_TRAFFIC = {"update_kernel": 679_635 + 53_433,       # K=4096, T=18 contact workload
+                    "batch_kernel": 6_427_446 + 6_094_107}   # 64-problem batch, 2048 groups
+
+
+def kernel_source_digest():
+    """SHA-256 (16 hex digits) over the HIP sources and the C-ABI header."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2609_02020_amd", "csrc")
+    files = [os.path.join(d, n) for n in sorted(os.listdir(d)) if n.endswith((".hip", ".hpp", ".h"))]
+    for f in files + [os.path.join(ROOT, "include", "mppi.h")]:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel):
+    return PROFILED_TRAFFIC[kernel] if kernel_source_digest() == PROFILED_DIGEST else None
 
 
 def parse():
@@ -46,6 +75,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the oracle CPU-baseline sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--batch-ticks", type=int, default=30,
+                   help="graph replays of the 64-problem batched tick (0: skip)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="after the timed region, copy a MIB-sized buffer 5 times (a plain copy "
                         "kernel of known size, to calibrate HBM byte counters)")
@@ -70,6 +101,75 @@ def cpu_baseline(case, budget_s):
             "sample": "%d full oracle updates (K=%d, T=%d, FP64, OpenMP over samples) in %.1f s; "
                       "%.3g sample-steps/s" % (n, K, T, el, n * K * T / el),
             "cpu": platform.processor() or platform.machine()}
+
+
+def has_force(cost):
+    return any(w != 0 for w in cost["W_force"]) or any(w != 0 for w in cost["W_reg"])
+
+
+def problem_flops(cost):
+    K, T = cost["K"], cost["T"]
+    step, term = ((FLOPS_PER_SAMPLE_STEP, FLOPS_PER_SAMPLE_TERMINAL) if has_force(cost) else
+                  (FLOPS_PER_SAMPLE_STEP_FREE, FLOPS_PER_SAMPLE_TERMINAL_FREE))
+    return step * K * T + term * K + FLOPS_PER_SAMPLE_ROW_WEIGHT * K * T * 7
+
+
+def batch_bench(B, cases, torch, dev, ticks):
+    """64 independent problems (K in [512, 8192], T in [10, 50], half with
+    the wall and force cost) per tick: one persistent launch, autotuned
+    launch shape, replayed from a captured HIP graph.  The graph reads and
+    advances its Philox tick on the device; the nominal sequences stay fixed
+    across replays (each replay is a full update of all 64 problems)."""
+    import numpy as np
+    batch = B.Batch([(c["robot"], c["cost"]) for c in cases])
+    f64 = dict(dtype=torch.float64, device=dev)
+    U = np.zeros((batch.u_total // 7, 7))
+    for p, c in enumerate(cases):
+        U[batch.u_off[p] // 7: batch.u_off[p] // 7 + batch.T[p]] = np.asarray(c["U_nom"])[:batch.T[p]]
+    io = {"q": torch.tensor(np.array([c["q0"] for c in cases]), **f64),
+          "qd": torch.tensor(np.array([c["qd0"] for c in cases]), **f64),
+          "target": torch.tensor(np.array([B.target_vector(c["target"]) for c in cases]), **f64),
+          "U_nominal": torch.tensor(U, **f64), "U_new": torch.empty(U.shape, **f64),
+          "U_shift": torch.empty(U.shape, **f64),
+          "costs": torch.empty(batch.k_total, dtype=torch.float32, device=dev),
+          "status": torch.zeros(len(cases), dtype=torch.int32, device=dev),
+          "seed": torch.tensor([c["seed"] for c in cases], dtype=torch.int64, device=dev)}
+    stream = torch.cuda.current_stream()
+    wpg, groups, _ = batch.autotune(io, reps=3, stream=stream)
+    batch.graph_capture(io)
+    batch.set_tick(0)
+    for _ in range(3):
+        batch.graph_launch(stream)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(ticks)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        batch.graph_launch(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = io["status"].cpu().numpy()
+    assert (st == B.OK).all(), st
+    tick_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    sample_steps = sum(c["cost"]["K"] * c["cost"]["T"] for c in cases)
+    flops = sum(problem_flops(c["cost"]) for c in cases)
+    batch.close()
+    return {"workload": "batch64: 64 problems, K in [%d, %d], T in [%d, %d], %d with the wall + force "
+                        "cost, %d sample-steps per tick" % (
+                            min(c["cost"]["K"] for c in cases), max(c["cost"]["K"] for c in cases),
+                            min(c["cost"]["T"] for c in cases), max(c["cost"]["T"] for c in cases),
+                            sum(has_force(c["cost"]) for c in cases), sample_steps),
+            "ticks_per_s": ticks / elapsed, "tick_ms": tick_ms, "ticks": ticks,
+            "problem_updates_per_s": len(cases) * ticks / elapsed,
+            "rollout_steps_per_s": sample_steps / (tick_ms * 1e-3),
+            "launch": {"waves_per_group": wpg, "groups": groups, "graph": True},
+            "roofline": {"bound": "alu", "achieved": flops / (tick_ms * 1e-3) / 1e12,
+                         "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": flops / (tick_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+                         "traffic": profiled_traffic("batch_kernel"),
+                         "kernel": "batch_kernel", "flops_per_launch": flops}}
 
 
 def main():
@@ -158,10 +258,13 @@ def main():
         "update_kernel_ms": float(np.mean(roll_ms)),
         "host_api_update_hz": host_rate,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": profiled_traffic("update_kernel"),
                      "kernel": "update_kernel<float, float, force>",
                      "flops_per_launch": flops},
     }
+    if args.batch_ticks > 0:
+        out["batch"] = batch_bench(B, inputs.load()["batch64"], torch, dev, args.batch_ticks)
     if args.copy_probe > 0:
         src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -52,3 +52,12 @@ def test_bench_flop_constants_match_count(oc, workloads):
     # the count is a property of the code path, not of the inputs
     for case in workloads["wall_k4096"][1:4]:
         assert per_step(oc, case) == (step, term)
+
+
+def test_bench_flop_constants_free_space(oc, workloads):
+    """The free-space problems of the batched workload (no wall, no force or
+    orientation cost) take the shorter path."""
+    free = [c for c in workloads["batch64"] if not bench.has_force(c["cost"])]
+    assert free
+    for case in free[:4]:
+        assert per_step(oc, case) == (bench.FLOPS_PER_SAMPLE_STEP_FREE, bench.FLOPS_PER_SAMPLE_TERMINAL_FREE)
