@@ -133,3 +133,27 @@ def load(path: str = WORKLOADS_JSON) -> dict:
     """Stored workloads (written by tests/golden/make_workloads.py)."""
     with open(path) as f:
         return json.load(f)
+
+
+MLP_DIMS = (21, 256, 256, 256, 126)
+
+
+def draw_mlp_params(seed: int) -> np.ndarray:
+    """Initial parameters of the proposal network, flat FP64 in the layout
+    W_1, b_1, ..., W_4, b_4 (W_l row-major [out][in]): every entry of layer l
+    uniform in +-1/sqrt(fan_in)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for n_in, n_out in zip(MLP_DIMS[:-1], MLP_DIMS[1:]):
+        s = 1.0 / np.sqrt(n_in)
+        parts.append(rng.uniform(-s, s, size=n_out * n_in))
+        parts.append(rng.uniform(-s, s, size=n_out))
+    return np.concatenate(parts)
+
+
+def draw_mlp_batch(seed: int, rows: int, scale: float = 1.0):
+    """A synthetic regression batch for the network kernels: inputs
+    X [rows][21] uniform in +-scale, targets Y [rows][126] uniform in +-0.5."""
+    rng = np.random.default_rng(seed)
+    return (rng.uniform(-scale, scale, size=(rows, MLP_DIMS[0])),
+            rng.uniform(-0.5, 0.5, size=(rows, MLP_DIMS[-1])))
