@@ -238,6 +238,87 @@ int mppi_batch_graph_capture(mppi_batch_t b, const mppi_batch_io* io);
 int mppi_batch_set_tick(mppi_batch_t b, uint64_t tick);
 int mppi_batch_graph_launch(mppi_batch_t b, void* stream);
 
+/* Advances every problem's measured state (io->q, io->qd, written in place;
+ * the io struct's const is cast away for these two) by dt seconds of the
+ * FP64 zero-order-hold plant of mppi_plant_step_async, holding the first
+ * row of the problem's io->U_new (clamped to the torque limits).  One
+ * workgroup per problem. */
+int mppi_batch_plant_step_async(mppi_batch_t b, const mppi_batch_io* io, double dt, int substeps, void* stream);
+
+/* ---- nominal-sequence selection (plain MPPI as the fallback) ---- */
+
+/* Rolls out two sequences from the state of `io` without noise (the same
+ * dynamics and cost as an update, sigma taken as 0): io->U_nominal (the
+ * plain warm start, candidate 0) and U_candidate ([T][7], device,
+ * candidate 1), and replaces the content of io->U_nominal (written through
+ * the pointer: it must be writable device memory) with U_candidate only
+ * when its cost is lower (a tie keeps the warm start).  costs (device
+ * double [2] or NULL) receives both costs.  Errors: MPPI_EINVAL. */
+int mppi_select_nominal_async(mppi_handle_t h, const mppi_device_io* io, const double* U_candidate, double* costs,
+                              void* stream);
+/* The same for every problem of a batch, one workgroup each; U_candidates
+ * in the packed layout of U_nominal, costs (device double [n][2] or NULL). */
+int mppi_batch_select_nominal_async(mppi_batch_t b, const mppi_batch_io* io, const double* U_candidates,
+                                    double* costs, void* stream);
+
+/* ---- learned proposal network ----
+ *
+ * An addition to the method, whose sampling of Eq. 2 centres on the shifted
+ * warm start: a multilayer perceptron maps the measured state and the pose
+ * target to a mean torque sequence over an 18-step horizon, which the
+ * selection above offers to plain MPPI as an alternative nominal sequence.
+ *
+ *   x = (q / q_max, qd / qd_max, p_des, quat_des) in R^21 (quaternion
+ *       normalised, sign chosen so that w >= 0; limits from the robot)
+ *   z_l = W_l a_{l-1} + b_l, a_l = gelu(z_l) for l = 1, 2, 3 (tanh form of
+ *       GELU), widths 21-256-256-256-126; y = W_4 a_3 + b_4
+ *   U[t][j] = tau_max_j y[7 t + j]
+ *   training loss L = sum (y - y*)^2 / (B 126), y* = U* / tau_max
+ *
+ * BF16 weights, input features, hidden activations and backward signals
+ * (round to nearest even) with FP32 accumulation on the matrix cores; FP32
+ * biases; FP32 master weights and moments for Adam.  Parameters are passed
+ * flat in the order W_1 [256][21], b_1, W_2 [256][256], b_2, W_3, b_3,
+ * W_4 [126][256], b_4 (row-major [out][in]); MPPI_MLP_PARAMS values. */
+#define MPPI_MLP_INPUTS 21
+#define MPPI_MLP_OUTPUTS 126
+#define MPPI_MLP_PARAMS 169598
+
+typedef struct mppi_mlp* mppi_mlp_t;
+
+typedef struct {
+    double lr, beta1, beta2, eps;   /* Adam (Kingma and Ba), bias-corrected */
+} mppi_adam_params;
+
+/* Creates a network for `robot` (feature and torque scales) with room for
+ * batches of up to max_batch rows (1 .. 65536).  Parameters start at zero;
+ * set them before use.  Errors: MPPI_EINVAL, MPPI_ENOMEM, MPPI_EDEVICE. */
+int mppi_mlp_create(const mppi_robot_params* robot, int max_batch, mppi_mlp_t* out);
+int mppi_mlp_destroy(mppi_mlp_t m);
+/* Host FP32 parameters in and out (n must be MPPI_MLP_PARAMS; synchronous).
+ * Setting them also clears the Adam moments and step count. */
+int mppi_mlp_set_params(mppi_mlp_t m, const float* params, size_t n);
+int mppi_mlp_get_params(mppi_mlp_t m, float* params, size_t n);
+/* y [B][126] = network(x [B][21]) (device FP32, 1 <= B <= max_batch). */
+int mppi_mlp_forward_async(mppi_mlp_t m, const float* x, int B, float* y, void* stream);
+/* Loss and gradient of one batch (x [B][21], y_target [B][126]): the
+ * gradient stays in the network for mppi_mlp_adam_async and is copied to
+ * grad (device FP32 [MPPI_MLP_PARAMS] in the flat order) when non-NULL;
+ * loss (device FP32 [1]) may be NULL. */
+int mppi_mlp_grad_async(mppi_mlp_t m, const float* x, const float* y_target, int B, float* grad, float* loss,
+                        void* stream);
+/* One Adam step with the last gradient (the step count t advances on the
+ * host with every call). */
+int mppi_mlp_adam_async(mppi_mlp_t m, const mppi_adam_params* p, void* stream);
+/* mppi_mlp_grad_async (no gradient copy) followed by mppi_mlp_adam_async. */
+int mppi_mlp_train_step_async(mppi_mlp_t m, const float* x, const float* y_target, int B,
+                              const mppi_adam_params* p, float* loss, void* stream);
+/* Mean torque sequences of n states (1 <= n <= max_batch): q, qd [n][7],
+ * target [n][13] (the update's layout; F_des unused) in, U [n][u_stride]
+ * doubles out (the first 126 of each row: [18][7]); all device memory. */
+int mppi_mlp_propose_async(mppi_mlp_t m, int n, const double* q, const double* qd, const double* target,
+                           double* U, int u_stride, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* mppi_strerror(int status);
 

@@ -154,6 +154,7 @@ def lib():
         L.mppi_rollout_async.argtypes = [vp, P(DeviceIO), vp]
         L.mppi_weights_async.argtypes = [vp, P(DeviceIO), vp]
         L.mppi_plant_step_async.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int, vp]
+        L.mppi_select_nominal_async.argtypes = [vp, P(DeviceIO), vp, vp, vp]
         L.mppi_strerror.argtypes = [C.c_int]
         L.mppi_strerror.restype = C.c_char_p
         L.mppi_version.restype = C.c_char_p
@@ -262,6 +263,15 @@ class Solver:
         if st:
             raise MppiError(st, "mppi_plant_step_async")
 
+    def select_nominal_async(self, io: dict, U_candidate, costs=None, stream=None):
+        """Keeps io["U_nominal"] or replaces it with U_candidate, whichever
+        has the lower noise-free rollout cost (mppi_select_nominal_async)."""
+        d = self._io(io)
+        st = self._lib.mppi_select_nominal_async(self._h, C.byref(d), _ptr(U_candidate), _ptr(costs),
+                                                 _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_select_nominal_async")
+
 
 class ProblemDesc(C.Structure):
     _fields_ = [("robot", C.POINTER(RobotParams)), ("cost", C.POINTER(CostParams))]
@@ -287,6 +297,8 @@ def _batch_lib():
         L.mppi_batch_graph_capture.argtypes = [vp, P(BatchIO)]
         L.mppi_batch_set_tick.argtypes = [vp, C.c_uint64]
         L.mppi_batch_graph_launch.argtypes = [vp, vp]
+        L.mppi_batch_plant_step_async.argtypes = [vp, P(BatchIO), C.c_double, C.c_int, vp]
+        L.mppi_batch_select_nominal_async.argtypes = [vp, P(BatchIO), vp, vp, vp]
         L._batch_ready = True
     return L
 
@@ -371,3 +383,115 @@ class Batch:
         st = self._lib.mppi_batch_graph_launch(self._h, _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_batch_graph_launch")
+
+    def plant_step_async(self, io: dict, dt: float, substeps: int, stream=None):
+        """Advances io["q"], io["qd"] of every problem by the FP64 plant,
+        holding the first row of its U_new."""
+        d = self._io(io)
+        st = self._lib.mppi_batch_plant_step_async(self._h, C.byref(d), float(dt), int(substeps),
+                                                   _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_batch_plant_step_async")
+
+    def select_nominal_async(self, io: dict, U_candidates, costs=None, stream=None):
+        d = self._io(io)
+        st = self._lib.mppi_batch_select_nominal_async(self._h, C.byref(d), _ptr(U_candidates), _ptr(costs),
+                                                       _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_batch_select_nominal_async")
+
+
+MLP_INPUTS, MLP_OUTPUTS, MLP_PARAMS = 21, 126, 169598
+
+
+class AdamParams(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
+
+
+def _mlp_lib():
+    L = lib()
+    if not hasattr(L, "_mlp_ready"):
+        P, vp = C.POINTER, C.c_void_p
+        L.mppi_mlp_create.argtypes = [P(RobotParams), C.c_int, P(vp)]
+        L.mppi_mlp_destroy.argtypes = [vp]
+        L.mppi_mlp_set_params.argtypes = [vp, P(C.c_float), C.c_size_t]
+        L.mppi_mlp_get_params.argtypes = [vp, P(C.c_float), C.c_size_t]
+        L.mppi_mlp_forward_async.argtypes = [vp, vp, C.c_int, vp, vp]
+        L.mppi_mlp_grad_async.argtypes = [vp, vp, vp, C.c_int, vp, vp, vp]
+        L.mppi_mlp_adam_async.argtypes = [vp, P(AdamParams), vp]
+        L.mppi_mlp_train_step_async.argtypes = [vp, vp, vp, C.c_int, P(AdamParams), vp, vp]
+        L.mppi_mlp_propose_async.argtypes = [vp, C.c_int, vp, vp, vp, vp, C.c_int, vp]
+        L._mlp_ready = True
+    return L
+
+
+class Mlp:
+    """The learned proposal network (mppi_mlp_*).  Device arrays are torch
+    CUDA tensors (float32 rows of 21 inputs / 126 outputs; float64 states)."""
+
+    def __init__(self, robot: dict, max_batch: int):
+        self._lib = _mlp_lib()
+        self._rp = robot_params(robot)
+        self.max_batch = int(max_batch)
+        self._h = C.c_void_p()
+        st = self._lib.mppi_mlp_create(C.byref(self._rp), self.max_batch, C.byref(self._h))
+        if st:
+            raise MppiError(st, "mppi_mlp_create")
+
+    def close(self):
+        if self._h:
+            self._lib.mppi_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        st = self._lib.mppi_mlp_set_params(self._h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size)
+        if st:
+            raise MppiError(st, "mppi_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(MLP_PARAMS, dtype=np.float32)
+        st = self._lib.mppi_mlp_get_params(self._h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size)
+        if st:
+            raise MppiError(st, "mppi_mlp_get_params")
+        return a
+
+    def forward_async(self, x, y, stream=None):
+        st = self._lib.mppi_mlp_forward_async(self._h, _ptr(x), int(x.shape[0]), _ptr(y), _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_mlp_forward_async")
+
+    def grad_async(self, x, y_target, grad=None, loss=None, stream=None):
+        st = self._lib.mppi_mlp_grad_async(self._h, _ptr(x), _ptr(y_target), int(x.shape[0]), _ptr(grad),
+                                           _ptr(loss), _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_mlp_grad_async")
+
+    @staticmethod
+    def _adam(lr, beta1, beta2, eps):
+        return AdamParams(float(lr), float(beta1), float(beta2), float(eps))
+
+    def adam_async(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        p = self._adam(lr, beta1, beta2, eps)
+        st = self._lib.mppi_mlp_adam_async(self._h, C.byref(p), _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_mlp_adam_async")
+
+    def train_step_async(self, x, y_target, loss=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        p = self._adam(lr, beta1, beta2, eps)
+        st = self._lib.mppi_mlp_train_step_async(self._h, _ptr(x), _ptr(y_target), int(x.shape[0]), C.byref(p),
+                                                 _ptr(loss), _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_mlp_train_step_async")
+
+    def propose_async(self, q, qd, target, U, u_stride=MLP_OUTPUTS, stream=None):
+        st = self._lib.mppi_mlp_propose_async(self._h, int(q.shape[0]), _ptr(q), _ptr(qd), _ptr(target), _ptr(U),
+                                              int(u_stride), _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_mlp_propose_async")

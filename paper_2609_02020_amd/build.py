@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmppi.so")
-SOURCES = ["kernels.hip", "runtime.hip"]
+SOURCES = ["kernels.hip", "runtime.hip", "mlp.hip", "proposal.hip"]
 ARCH = os.environ.get("MPPI_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

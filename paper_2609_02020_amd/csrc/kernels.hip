@@ -12,7 +12,10 @@
 //                   its rows with wave shuffles; writes U_new and the shifted
 //                   warm start.
 //   prep_model_kernel: parallel-axis shift of the link inertias (create).
-//   plant_kernel:   FP64 zero-order-hold plant for the closed loop.
+//   plant_kernel, batch_plant_kernel: FP64 zero-order-hold plant for the
+//                   closed loop (one problem, or one workgroup per problem).
+//   select_kernel, batch_select_kernel: noise-free costs of the warm start
+//                   and a proposed nominal sequence; keeps the cheaper.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -118,6 +121,8 @@ __global__ __launch_bounds__(kRolloutBlock) void update_kernel(
 struct BatchProblem {
     const ModelM<float>* model;
     const CostM<float>* cost;
+    const ModelM<double>* model64;   // the FP64 plant
+    const CostM<double>* cost64;
     int K, T, force, acc64;
     double lambda;
     int ntiles;
@@ -305,12 +310,11 @@ __global__ __launch_bounds__(kWeightsBlock) void weights_kernel(
     if (status && blockIdx.x == 0 && tid == 0) *status = MPPI_OK;
 }
 
-__global__ void plant_kernel(const ModelM<double>* __restrict__ Mp, const CostM<double>* __restrict__ Cp,
-                             double* q, double* qd, const double* __restrict__ u, double dt, int substeps)
+// zero-order hold of u (clamped to the torque limits) over dt in
+// `substeps` semi-implicit Euler steps of the FP64 dynamics
+__device__ void plant_advance(const ModelM<double>& M, const CostM<double>& C, double* q, double* qd,
+                              const double* u, double dt, int substeps)
 {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    const ModelM<double>& M = *Mp;
-    const CostM<double>& C = *Cp;
     double tau[NJ], qq[NJ], qv[NJ];
     for (int j = 0; j < NJ; ++j) {
         double lim = M.L[j].taumax;
@@ -329,6 +333,92 @@ __global__ void plant_kernel(const ModelM<double>* __restrict__ Mp, const CostM<
         }
     }
     for (int j = 0; j < NJ; ++j) { q[j] = qq[j]; qd[j] = qv[j]; }
+}
+
+__global__ void plant_kernel(const ModelM<double>* __restrict__ Mp, const CostM<double>* __restrict__ Cp,
+                             double* q, double* qd, const double* __restrict__ u, double dt, int substeps)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    plant_advance(*Mp, *Cp, q, qd, u, dt, substeps);
+}
+
+// one workgroup per problem of a batch: the first row of its U_new
+__global__ void batch_plant_kernel(const BatchProblem* __restrict__ probs, int n, double* q, double* qd,
+                                   const double* __restrict__ U_new, double dt, int substeps)
+{
+    const int p = blockIdx.x;
+    if (p >= n || threadIdx.x != 0) return;
+    const BatchProblem& Pb = probs[p];
+    plant_advance(*Pb.model64, *Pb.cost64, q + p * NJ, qd + p * NJ, U_new + Pb.u_off, dt, substeps);
+}
+
+// Noise-free costs of two sequences from one state (lane 0: the current
+// nominal, lane 1: the candidate; the sampling scale is zeroed in the LDS
+// copy of the cost, so v_t = u_t exactly); the candidate replaces the
+// nominal only when it costs less.
+template <typename R, bool FORCE>
+__device__ void select_two(const ModelM<R>& Mg, const CostM<R>& Cg, const double* q0, const double* qd0,
+                           const double* target, double* U_nom, const double* U_cand, int T, double* costs,
+                           ModelM<R>& Msh, CostM<R>& Csh, R* Us, R* sc)
+{
+    const int lane = threadIdx.x & 63;
+    wave_copy(&Msh, &Mg, sizeof(ModelM<R>), lane);
+    wave_copy(&Csh, &Cg, sizeof(CostM<R>), lane);
+    for (int i = lane; i < T * NJ; i += 64) {
+        Us[i] = R(U_nom[i]);
+        Us[kMaxT * NJ + i] = R(U_cand[i]);
+    }
+    wave_sync();
+    if (lane < NJ) Csh.sigma[lane] = R(0);
+    wave_sync();
+    if (lane < 2) {
+        TargetM<R> tg;
+        make_target(target, tg);
+        R q[NJ], qd[NJ], te[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) { q[j] = R(q0[j]); qd[j] = R(qd0[j]); te[j] = R(0); }
+        if (Csh.ext_mode == EXTW_CONST) const_ext_torque(Msh, Csh, q, te);
+        const R v = rollout_sample<R, FORCE>(Msh, Csh, tg, q, qd, te, Us + lane * kMaxT * NJ, T, 0ull, 0u, 0u,
+                                             (R*)nullptr, 0);
+        sc[lane] = finite_(v) ? v : R(INFINITY);
+    }
+    wave_sync();
+    const bool take = sc[1] < sc[0];
+    if (take)
+        for (int i = lane; i < T * NJ; i += 64) U_nom[i] = U_cand[i];
+    if (costs && lane < 2) costs[lane] = double(sc[lane]);
+}
+
+template <typename R, bool FORCE>
+__global__ __launch_bounds__(64) void select_kernel(const ModelM<R>* __restrict__ Mp, const CostM<R>* __restrict__ Cp,
+                                                    const double* q0, const double* qd0, const double* target,
+                                                    double* U_nom, const double* U_cand, int T, double* costs)
+{
+    __shared__ ModelM<R> Msh;
+    __shared__ CostM<R> Csh;
+    __shared__ R Us[2 * kMaxT * NJ];
+    __shared__ R sc[2];
+    select_two<R, FORCE>(*Mp, *Cp, q0, qd0, target, U_nom, U_cand, T, costs, Msh, Csh, Us, sc);
+}
+
+__global__ __launch_bounds__(64) void batch_select_kernel(const BatchProblem* __restrict__ probs, int n,
+                                                          const double* q, const double* qd, const double* target,
+                                                          double* U_nom, const double* U_cand, double* costs)
+{
+    __shared__ ModelM<float> Msh;
+    __shared__ CostM<float> Csh;
+    __shared__ float Us[2 * kMaxT * NJ];
+    __shared__ float sc[2];
+    const int p = blockIdx.x;
+    if (p >= n) return;
+    const BatchProblem& Pb = probs[p];
+    double* c = costs ? costs + 2 * p : nullptr;
+    if (Pb.force)
+        select_two<float, true>(*Pb.model, *Pb.cost, q + p * NJ, qd + p * NJ, target + (size_t)p * 13,
+                                U_nom + Pb.u_off, U_cand + Pb.u_off, Pb.T, c, Msh, Csh, Us, sc);
+    else
+        select_two<float, false>(*Pb.model, *Pb.cost, q + p * NJ, qd + p * NJ, target + (size_t)p * 13,
+                                 U_nom + Pb.u_off, U_cand + Pb.u_off, Pb.T, c, Msh, Csh, Us, sc);
 }
 
 // ---------------------------------------------------------------------------
@@ -421,12 +511,15 @@ hipError_t launch_set_tick(uint64_t* tick, uint64_t v, hipStream_t s)
 
 size_t batch_problem_bytes() { return sizeof(BatchProblem); }
 
-void fill_batch_problem(void* dst, const void* model, const void* cost, int K, int T, int force, int acc64,
-                        double lambda, int ntiles, long long u_off, long long k_off, long long part_off)
+void fill_batch_problem(void* dst, const void* model, const void* cost, const void* model64, const void* cost64,
+                        int K, int T, int force, int acc64, double lambda, int ntiles, long long u_off,
+                        long long k_off, long long part_off)
 {
     BatchProblem p;
     p.model = (const ModelM<float>*)model;
     p.cost = (const CostM<float>*)cost;
+    p.model64 = (const ModelM<double>*)model64;
+    p.cost64 = (const CostM<double>*)cost64;
     p.K = K; p.T = T; p.force = force; p.acc64 = acc64;
     p.lambda = lambda; p.ntiles = ntiles; p.pad = 0;
     p.u_off = u_off; p.k_off = k_off; p.part_off = part_off;
@@ -437,6 +530,39 @@ hipError_t launch_plant(const ModelM<double>* M, const CostM<double>* C, double*
                         const double* u, double dt, int substeps, hipStream_t s)
 {
     hipLaunchKernelGGL(plant_kernel, dim3(1), dim3(64), 0, s, M, C, q, qd, u, dt, substeps);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_plant(const void* probs, int n, double* q, double* qd, const double* U_new, double dt,
+                              int substeps, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_plant_kernel, dim3(n), dim3(64), 0, s, (const BatchProblem*)probs, n, q, qd, U_new,
+                       dt, substeps);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(int precision, bool force, const void* model, const void* cost, const double* q0,
+                         const double* qd0, const double* target, double* U_nom, const double* U_cand, int T,
+                         double* costs, hipStream_t s)
+{
+    if (T < 1 || T > kMaxT) return hipErrorInvalidValue;
+    if (precision == MPPI_FP64) {
+        auto k = force ? select_kernel<double, true> : select_kernel<double, false>;
+        hipLaunchKernelGGL(k, dim3(1), dim3(64), 0, s, (const ModelM<double>*)model, (const CostM<double>*)cost, q0,
+                           qd0, target, U_nom, U_cand, T, costs);
+    } else {
+        auto k = force ? select_kernel<float, true> : select_kernel<float, false>;
+        hipLaunchKernelGGL(k, dim3(1), dim3(64), 0, s, (const ModelM<float>*)model, (const CostM<float>*)cost, q0,
+                           qd0, target, U_nom, U_cand, T, costs);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_select(const void* probs, int n, const double* q, const double* qd, const double* target,
+                               double* U_nom, const double* U_cand, double* costs, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_select_kernel, dim3(n), dim3(64), 0, s, (const BatchProblem*)probs, n, q, qd, target,
+                       U_nom, U_cand, costs);
     return hipGetLastError();
 }
 

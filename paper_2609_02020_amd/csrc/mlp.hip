@@ -1,0 +1,423 @@
+// mlp.hip -- the proposal network on gfx950: BF16 matrix-core products
+// (v_mfma_f32_16x16x16_bf16) with FP32 accumulation.
+//
+//   mlp_forward_kernel<TRAIN>  one workgroup (4 waves) per 64 states; the
+//                   layers run back to back with the activation tile in
+//                   LDS.  Training adds the MSE signal and the backward
+//                   products e_{l-1} = (e_l W_l) * gelu'(z_{l-1}) in the same
+//                   workgroup (the rows are independent), storing every
+//                   activation and signal transposed for the weight gradients.
+//   mlp_wgrad_kernel   dW_l = e_l^T a_{l-1} (a contraction over the batch),
+//                   one wave per 32 x 32 tile of one layer; db_l = sum of e_l.
+//   mlp_adam_kernel    Adam on the FP32 master weights, then the BF16 copies
+//                   (row-major and transposed).
+//   mlp_features_kernel  (q/q_max, qd/qd_max, p_des, quat_des with w >= 0).
+//
+// Matrix-core fragments (16 x 16 x 16): lane l holds row (l mod 16) of A and
+// column (l mod 16) of B, each with the four k values 4 (l div 16) + 0..3;
+// the FP32 result holds column (l mod 16), rows 4 (l div 16) + 0..3.
+// Every operand is read with k contiguous: A from the LDS tile [row][k]
+// (row stride 264 BF16, so the 64 lanes of a fragment read hit distinct
+// banks), B^T from the row-major weights [n][k] (forward) or from their
+// stored transposes (backward), and both operands of the weight gradient
+// from the transposed [feature][batch] buffers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "mlp.hpp"
+
+namespace mppi {
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kLda = 264;
+
+// FP32 -> BF16, round to nearest, ties to even (NaN stays NaN)
+__device__ __forceinline__ uint16_t to_bf16(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// tanh form of GELU and its derivative
+__device__ __forceinline__ float gelu_f(float z)
+{
+    const float c = 0.7978845608028654f, a = 0.044715f;
+    return 0.5f * z * (1.0f + tanhf(c * (z + a * z * z * z)));
+}
+__device__ __forceinline__ float gelu_d(float z)
+{
+    const float c = 0.7978845608028654f, a = 0.044715f;
+    const float t = tanhf(c * (z + a * z * z * z));
+    return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * c * (1.0f + 3.0f * a * z * z);
+}
+
+__device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// acc[i][j] = sum_k A[16 i + r][k] Bt[nb + 16 j + c][k] over the 64 rows of
+// the LDS tile A and CT column tiles of the global k-contiguous Bt [N][K].
+template <int CT>
+__device__ __forceinline__ void tile_mm(const uint16_t* A, const uint16_t* __restrict__ Bt, int K, int nb,
+                                        v4f (&acc)[4][CT], int lane)
+{
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < CT; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 2
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        v4s a[4], b[CT];
+#pragma unroll
+        for (int j = 0; j < CT; ++j) b[j] = *reinterpret_cast<const v4s*>(Bt + (size_t)(nb + 16 * j + r) * K + k0 + kq);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const v4s*>(A + (16 * i + r) * kLda + k0 + kq);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < CT; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+    }
+}
+
+// LDS tile columns [0, ncols) -> global [c][Bp] at rows b0..b0+63
+__device__ __forceinline__ void store_transposed(const uint16_t* tile, int ncols, uint16_t* dst, int Bp, int b0,
+                                                 int tid)
+{
+    for (int i = tid; i < ncols * kMlpRows; i += kThreads) {
+        const int c = i / kMlpRows, r = i % kMlpRows;
+        dst[(size_t)c * Bp + b0 + r] = tile[r * kLda + c];
+    }
+}
+
+// hidden layer forward: out = bf16(gelu(A W^T + b)); z stored when given
+__device__ __forceinline__ void hidden_forward(const uint16_t* A, int K, const uint16_t* __restrict__ W,
+                                               const float* __restrict__ bias, float* z, uint16_t* out, int b0,
+                                               int w, int lane)
+{
+    v4f acc[4][4];
+    tile_mm<4>(A, W, K, w * 64, acc, lane);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = 16 * i + 4 * (lane >> 4) + e, col = w * 64 + 16 * j + (lane & 15);
+                const float zz = acc[i][j][e] + bias[col];
+                if (z) z[(size_t)(b0 + row) * kMlpHid + col] = zz;
+                out[row * kLda + col] = to_bf16(gelu_f(zz));
+            }
+}
+
+// hidden layer backward: out = bf16((E Wt^T) * gelu'(z)); each thread reads
+// back only the z values it stored in the forward pass (same fragment map)
+__device__ __forceinline__ void hidden_backward(const uint16_t* E, int K, const uint16_t* __restrict__ Wt,
+                                                const float* z, uint16_t* out, int b0, int w, int lane)
+{
+    v4f acc[4][4];
+    tile_mm<4>(E, Wt, K, w * 64, acc, lane);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = 16 * i + 4 * (lane >> 4) + e, col = w * 64 + 16 * j + (lane & 15);
+                out[row * kLda + col] = to_bf16(acc[i][j][e] * gelu_d(z[(size_t)(b0 + row) * kMlpHid + col]));
+            }
+}
+
+template <bool TRAIN>
+__global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const float* __restrict__ X, int B,
+                                                               const float* __restrict__ Ytgt, float* __restrict__ Y,
+                                                               double* __restrict__ U, int u_stride, float gscale)
+{
+    __shared__ __align__(16) uint16_t buf[2][kMlpRows * kLda];
+    __shared__ float red[kThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int b0 = blockIdx.x * kMlpRows;
+    const float* th = d.theta;
+
+    // a_0 = bf16(x); feature columns 21..31 and rows past B are zero
+    for (int i = tid; i < kMlpRows * kMlpInPad; i += kThreads) {
+        const int r = i / kMlpInPad, c = i % kMlpInPad;
+        const float x = (c < kMlpIn && b0 + r < B) ? X[(size_t)(b0 + r) * kMlpIn + c] : 0.0f;
+        buf[0][r * kLda + c] = to_bf16(x);
+    }
+    __syncthreads();
+    if (TRAIN) store_transposed(buf[0], kMlpInPad, d.aT0, d.Bp, b0, tid);
+
+    hidden_forward(buf[0], kMlpInPad, d.W1, th + kOffB1, TRAIN ? d.z1 : nullptr, buf[1], b0, w, lane);
+    __syncthreads();
+    if (TRAIN) store_transposed(buf[1], kMlpHid, d.aT1, d.Bp, b0, tid);
+    hidden_forward(buf[1], kMlpHid, d.W2, th + kOffB2, TRAIN ? d.z2 : nullptr, buf[0], b0, w, lane);
+    __syncthreads();
+    if (TRAIN) store_transposed(buf[0], kMlpHid, d.aT2, d.Bp, b0, tid);
+    hidden_forward(buf[0], kMlpHid, d.W3, th + kOffB3, TRAIN ? d.z3 : nullptr, buf[1], b0, w, lane);
+    __syncthreads();
+    if (TRAIN) store_transposed(buf[1], kMlpHid, d.aT3, d.Bp, b0, tid);
+
+    // output layer; training: e_4 = bf16(2 (y - y*) / (B 126)) into buf[0]
+    {
+        v4f acc[4][2];
+        tile_mm<2>(buf[1], d.W4, kMlpHid, w * 32, acc, lane);
+        float sq = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = 16 * i + 4 * (lane >> 4) + e, col = w * 32 + 16 * j + (lane & 15);
+                    const bool valid = col < kMlpOut && b0 + row < B;
+                    const float y = acc[i][j][e] + (col < kMlpOut ? th[kOffB4 + col] : 0.0f);
+                    if (valid) {
+                        if (Y) Y[(size_t)(b0 + row) * kMlpOut + col] = y;
+                        if (U) U[(size_t)(b0 + row) * u_stride + col] = d.scale[14 + col % 7] * (double)y;
+                    }
+                    if (TRAIN) {
+                        const float res = valid ? y - Ytgt[(size_t)(b0 + row) * kMlpOut + col] : 0.0f;
+                        sq += res * res;
+                        buf[0][row * kLda + col] = to_bf16(res * gscale);
+                    }
+                }
+        if (!TRAIN) return;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+        if (lane == 0) red[w] = sq;
+    }
+    __syncthreads();
+    if (tid == 0) d.lossp[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    store_transposed(buf[0], kMlpOutPad, d.eT4, d.Bp, b0, tid);
+
+    hidden_backward(buf[0], kMlpOutPad, d.W4t, d.z3, buf[1], b0, w, lane);
+    __syncthreads();
+    store_transposed(buf[1], kMlpHid, d.eT3, d.Bp, b0, tid);
+    hidden_backward(buf[1], kMlpHid, d.W3t, d.z2, buf[0], b0, w, lane);
+    __syncthreads();
+    store_transposed(buf[0], kMlpHid, d.eT2, d.Bp, b0, tid);
+    hidden_backward(buf[0], kMlpHid, d.W2t, d.z1, buf[1], b0, w, lane);
+    __syncthreads();
+    store_transposed(buf[1], kMlpHid, d.eT1, d.Bp, b0, tid);
+}
+
+// Tiles of 32 x 32: layer 1 8 (256 x 32 padded), layers 2, 3 64 each,
+// layer 4 32 (128 padded x 256).
+constexpr int kWgradTiles = 8 + 64 + 64 + 32;
+
+__global__ __launch_bounds__(64) void mlp_wgrad_kernel(MlpDev d, int B, float* loss)
+{
+    const int lane = threadIdx.x;
+    int t = blockIdx.x;
+    const uint16_t *E, *Act;
+    int nreal, kreal, woff, boff, tm, tn;
+    if (t < 8) {
+        E = d.eT1; Act = d.aT0; nreal = kMlpHid; kreal = kMlpIn; woff = kOffW1; boff = kOffB1; tm = t; tn = 0;
+    } else if (t < 72) {
+        t -= 8;
+        E = d.eT2; Act = d.aT1; nreal = kMlpHid; kreal = kMlpHid; woff = kOffW2; boff = kOffB2; tm = t / 8; tn = t % 8;
+    } else if (t < 136) {
+        t -= 72;
+        E = d.eT3; Act = d.aT2; nreal = kMlpHid; kreal = kMlpHid; woff = kOffW3; boff = kOffB3; tm = t / 8; tn = t % 8;
+    } else {
+        t -= 136;
+        E = d.eT4; Act = d.aT3; nreal = kMlpOut; kreal = kMlpHid; woff = kOffW4; boff = kOffB4; tm = t / 8; tn = t % 8;
+    }
+    // rows of this batch: the forward workgroups covered ceil(B / 64) * 64
+    // (rows past B carry e = 0); later rows of the buffers are stale
+    const int m0 = tm * 32, n0 = tn * 32, Bp = d.Bp;
+    const int nb = (B + kMlpRows - 1) / kMlpRows, Bb = nb * kMlpRows;
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+    v4f acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+    for (int k0 = 0; k0 < Bb; k0 += 16) {
+        v4s a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const v4s*>(E + (size_t)(m0 + 16 * i + r) * Bp + k0 + kq);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const v4s*>(Act + (size_t)(n0 + 16 * j + r) * Bp + k0 + kq);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = m0 + 16 * i + 4 * (lane >> 4) + e, col = n0 + 16 * j + r;
+                if (row < nreal && col < kreal) d.grad[woff + row * kreal + col] = acc[i][j][e];
+            }
+    if (tn == 0 && lane < 32 && m0 + lane < nreal) {
+        const uint16_t* er = E + (size_t)(m0 + lane) * Bp;
+        float s = 0.0f;
+        for (int b = 0; b < Bb; ++b) s += from_bf16(er[b]);
+        d.grad[boff + m0 + lane] = s;
+    }
+    if (blockIdx.x == 0 && lane == 0 && loss) {
+        float s = 0.0f;
+        for (int i = 0; i < nb; ++i) s += d.lossp[i];
+        *loss = s / ((float)B * (float)kMlpOut);
+    }
+}
+
+__global__ void mlp_adam_kernel(MlpDev d, int update, float lr, float beta1, float beta2, float eps, float c1,
+                                float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kMlpParams) return;
+    float th = d.theta[i];
+    if (update) {
+        const float g = d.grad[i];
+        const float m = beta1 * d.m[i] + (1.0f - beta1) * g;
+        const float v = beta2 * d.v[i] + (1.0f - beta2) * g * g;
+        th -= lr * (m * c1) / (sqrtf(v * c2) + eps);
+        d.m[i] = m;
+        d.v[i] = v;
+        d.theta[i] = th;
+    }
+    const uint16_t h = to_bf16(th);
+    if (i < kOffB1) {
+        const int n = i / kMlpIn, k = i % kMlpIn;
+        d.W1[n * kMlpInPad + k] = h;
+    } else if (i >= kOffW2 && i < kOffB2) {
+        const int j = i - kOffW2, n = j / kMlpHid, k = j % kMlpHid;
+        d.W2[n * kMlpHid + k] = h;
+        d.W2t[k * kMlpHid + n] = h;
+    } else if (i >= kOffW3 && i < kOffB3) {
+        const int j = i - kOffW3, n = j / kMlpHid, k = j % kMlpHid;
+        d.W3[n * kMlpHid + k] = h;
+        d.W3t[k * kMlpHid + n] = h;
+    } else if (i >= kOffW4 && i < kOffB4) {
+        const int j = i - kOffW4, n = j / kMlpHid, k = j % kMlpHid;
+        d.W4[n * kMlpHid + k] = h;
+        d.W4t[k * kMlpOutPad + n] = h;
+    }
+}
+
+__global__ void mlp_features_kernel(MlpDev d, int n, const double* __restrict__ q, const double* __restrict__ qd,
+                                    const double* __restrict__ target)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    float* x = d.X + (size_t)p * kMlpIn;
+    for (int j = 0; j < 7; ++j) {
+        x[j] = (float)(q[p * 7 + j] / d.scale[j]);
+        x[7 + j] = (float)(qd[p * 7 + j] / d.scale[7 + j]);
+    }
+    const double* tg = target + (size_t)p * 13;
+    for (int c = 0; c < 3; ++c) x[14 + c] = (float)tg[c];
+    const double nrm = sqrt(tg[3] * tg[3] + tg[4] * tg[4] + tg[5] * tg[5] + tg[6] * tg[6]);
+    const double sg = (tg[3] < 0.0 ? -1.0 : 1.0) / nrm;
+    for (int c = 0; c < 4; ++c) x[17 + c] = (float)(tg[3 + c] * sg);
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+size_t mlp_scratch_bytes(int Bp)
+{
+    const size_t P = kMlpParams;
+    size_t b = 0;
+    b += 4 * align256(P * sizeof(float));                                      // theta, m, v, grad
+    b += align256((size_t)kMlpHid * kMlpInPad * 2) + 2 * align256((size_t)kMlpHid * kMlpHid * 2) +
+         align256((size_t)kMlpOutPad * kMlpHid * 2);                           // W1..W4
+    b += 2 * align256((size_t)kMlpHid * kMlpHid * 2) + align256((size_t)kMlpHid * kMlpOutPad * 2);   // W2t..W4t
+    b += align256((size_t)kMlpInPad * Bp * 2) + 3 * align256((size_t)kMlpHid * Bp * 2);   // aT0..aT3
+    b += 3 * align256((size_t)kMlpHid * Bp * 2) + align256((size_t)kMlpOutPad * Bp * 2);  // eT1..eT4
+    b += 3 * align256((size_t)Bp * kMlpHid * sizeof(float));                   // z1..z3
+    b += align256((size_t)(Bp / kMlpRows) * sizeof(float));                    // lossp
+    b += align256((size_t)Bp * kMlpIn * sizeof(float));                        // X
+    b += align256(21 * sizeof(double));                                        // scale
+    return b;
+}
+
+void mlp_carve(MlpDev& d, void* base, int Bp)
+{
+    char* p = static_cast<char*>(base);
+    auto take = [&](size_t bytes) { char* q = p; p += align256(bytes); return q; };
+    const size_t P = kMlpParams;
+    d.theta = (float*)take(P * 4);
+    d.m = (float*)take(P * 4);
+    d.v = (float*)take(P * 4);
+    d.grad = (float*)take(P * 4);
+    d.W1 = (uint16_t*)take((size_t)kMlpHid * kMlpInPad * 2);
+    d.W2 = (uint16_t*)take((size_t)kMlpHid * kMlpHid * 2);
+    d.W3 = (uint16_t*)take((size_t)kMlpHid * kMlpHid * 2);
+    d.W4 = (uint16_t*)take((size_t)kMlpOutPad * kMlpHid * 2);
+    d.W2t = (uint16_t*)take((size_t)kMlpHid * kMlpHid * 2);
+    d.W3t = (uint16_t*)take((size_t)kMlpHid * kMlpHid * 2);
+    d.W4t = (uint16_t*)take((size_t)kMlpHid * kMlpOutPad * 2);
+    d.aT0 = (uint16_t*)take((size_t)kMlpInPad * Bp * 2);
+    d.aT1 = (uint16_t*)take((size_t)kMlpHid * Bp * 2);
+    d.aT2 = (uint16_t*)take((size_t)kMlpHid * Bp * 2);
+    d.aT3 = (uint16_t*)take((size_t)kMlpHid * Bp * 2);
+    d.eT1 = (uint16_t*)take((size_t)kMlpHid * Bp * 2);
+    d.eT2 = (uint16_t*)take((size_t)kMlpHid * Bp * 2);
+    d.eT3 = (uint16_t*)take((size_t)kMlpHid * Bp * 2);
+    d.eT4 = (uint16_t*)take((size_t)kMlpOutPad * Bp * 2);
+    d.z1 = (float*)take((size_t)Bp * kMlpHid * 4);
+    d.z2 = (float*)take((size_t)Bp * kMlpHid * 4);
+    d.z3 = (float*)take((size_t)Bp * kMlpHid * 4);
+    d.lossp = (float*)take((size_t)(Bp / kMlpRows) * 4);
+    d.X = (float*)take((size_t)Bp * kMlpIn * 4);
+    d.scale = (const double*)take(21 * sizeof(double));
+    d.Bp = Bp;
+}
+
+hipError_t launch_mlp_forward(const MlpDev& d, const float* X, int B, const float* Ytgt, float* Y, double* U,
+                              int u_stride, hipStream_t s)
+{
+    if (B < 1 || B > d.Bp) return hipErrorInvalidValue;
+    const dim3 grid((B + kMlpRows - 1) / kMlpRows);
+    const float gscale = 2.0f / ((float)B * (float)kMlpOut);
+    if (Ytgt)
+        hipLaunchKernelGGL(mlp_forward_kernel<true>, grid, dim3(kThreads), 0, s, d, X, B, Ytgt, Y, U, u_stride, gscale);
+    else
+        hipLaunchKernelGGL(mlp_forward_kernel<false>, grid, dim3(kThreads), 0, s, d, X, B, Ytgt, Y, U, u_stride,
+                           gscale);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_wgrad(const MlpDev& d, int B, float* loss, hipStream_t s)
+{
+    if (B < 1 || B > d.Bp) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mlp_wgrad_kernel, dim3(kWgradTiles), dim3(64), 0, s, d, B, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(const MlpDev& d, int update, float lr, float beta1, float beta2, float eps, float c1,
+                           float c2, hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, d, update, lr, beta1,
+                       beta2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_features(const MlpDev& d, int n, const double* q, const double* qd, const double* target,
+                               hipStream_t s)
+{
+    if (n < 1 || n > d.Bp) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mlp_features_kernel, dim3((n + 63) / 64), dim3(64), 0, s, d, n, q, qd, target);
+    return hipGetLastError();
+}
+
+}  // namespace mppi

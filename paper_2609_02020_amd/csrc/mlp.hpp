@@ -1,0 +1,89 @@
+// mlp.hpp -- the proposal network's device layout and launchers (internal).
+//
+// Network: 21 -> 256 -> 256 -> 256 -> 126, tanh-GELU on the hidden layers,
+// BF16 weights and activations, FP32 accumulation (MFMA), FP32 biases, FP32
+// master weights for Adam.  Flat parameter order (the C ABI's): W_1 [256][21],
+// b_1, W_2 [256][256], b_2, W_3 [256][256], b_3, W_4 [126][256], b_4.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mppi {
+
+constexpr int kMlpIn = 21, kMlpInPad = 32, kMlpHid = 256, kMlpOut = 126, kMlpOutPad = 128;
+constexpr int kMlpRows = 64;      // states per workgroup
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kMlpHid * kMlpIn;
+constexpr int kOffW2 = kOffB1 + kMlpHid;
+constexpr int kOffB2 = kOffW2 + kMlpHid * kMlpHid;
+constexpr int kOffW3 = kOffB2 + kMlpHid;
+constexpr int kOffB3 = kOffW3 + kMlpHid * kMlpHid;
+constexpr int kOffW4 = kOffB3 + kMlpHid;
+constexpr int kOffB4 = kOffW4 + kMlpOut * kMlpHid;
+constexpr int kMlpParams = kOffB4 + kMlpOut;
+static_assert(kMlpParams == 169598, "parameter count");
+
+// Device buffers of one network.  Weight copies are BF16 bit patterns:
+// W1 [256][32] (columns 21..31 zero), W2, W3 [256][256], W4 [128][256]
+// (rows 126, 127 zero); the transposes W2t, W3t [256][256] and W4t
+// [256][128] (columns 126, 127 zero) feed the backward products.
+// Training scratch holds one batch of up to Bp rows (a multiple of 64):
+// activations a_l and backward signals e_l stored transposed ([features][Bp],
+// BF16) for the weight-gradient contraction over the batch, and the FP32
+// pre-activations z_l [Bp][256] for GELU'.
+struct MlpDev {
+    float* theta;     // [P] FP32 master parameters
+    float* m;         // [P] Adam first moment
+    float* v;         // [P] Adam second moment
+    float* grad;      // [P] last gradient
+    uint16_t* W1;
+    uint16_t* W2;
+    uint16_t* W3;
+    uint16_t* W4;
+    uint16_t* W2t;
+    uint16_t* W3t;
+    uint16_t* W4t;
+    uint16_t* aT0;    // [32][Bp]
+    uint16_t* aT1;    // [256][Bp]
+    uint16_t* aT2;
+    uint16_t* aT3;
+    uint16_t* eT1;    // [256][Bp]
+    uint16_t* eT2;
+    uint16_t* eT3;
+    uint16_t* eT4;    // [128][Bp]
+    float* z1;        // [Bp][256]
+    float* z2;
+    float* z3;
+    float* lossp;     // [Bp / 64] per-workgroup sums of squared residuals
+    float* X;         // [Bp][21] feature scratch of the proposal path
+    const double* scale;   // [21]: q_max[7], qd_max[7], then 7 torque limits
+    int Bp;
+};
+
+// Bytes of each buffer for a batch capacity Bp (host helper).
+size_t mlp_scratch_bytes(int Bp);
+// Lays the buffers out in one allocation of mlp_scratch_bytes(Bp) bytes.
+void mlp_carve(MlpDev& d, void* base, int Bp);
+
+// Forward for B rows (B <= d.Bp).  Inference: Ytgt == nullptr; writes Y
+// [B][126] and/or U [B][u_stride] = tau_max * y (either may be null).
+// Training: Ytgt [B][126] given; also stores the activations, the
+// pre-activations and the backward signals of the MSE loss, and the
+// per-workgroup loss sums.
+hipError_t launch_mlp_forward(const MlpDev& d, const float* X, int B, const float* Ytgt, float* Y, double* U,
+                              int u_stride, hipStream_t s);
+// Weight and bias gradients from the stored signals (after a training
+// forward of the same B), and the loss into *loss (may be null).
+hipError_t launch_mlp_wgrad(const MlpDev& d, int B, float* loss, hipStream_t s);
+// One Adam step on d.grad (update != 0), then the BF16 weight copies.
+// c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t).
+hipError_t launch_mlp_adam(const MlpDev& d, int update, float lr, float beta1, float beta2, float eps, float c1,
+                           float c2, hipStream_t s);
+// Features of n states: X [n][21] into d.X.
+hipError_t launch_mlp_features(const MlpDev& d, int n, const double* q, const double* qd, const double* target,
+                               hipStream_t s);
+
+}  // namespace mppi

@@ -369,6 +369,19 @@ int mppi_plant_step_async(mppi_handle_t h, double* q, double* qd, const double* 
                : MPPI_EDEVICE;
 }
 
+int mppi_select_nominal_async(mppi_handle_t h, const mppi_device_io* io, const double* U_candidate, double* costs,
+                              void* stream)
+{
+    if (check_io(h, io, false) || !U_candidate) return MPPI_EINVAL;
+    const bool fp64 = h->cost.precision == MPPI_FP64;
+    return launch_select(h->cost.precision, has_force(h->cost), fp64 ? (const void*)h->d_md : (const void*)h->d_mf,
+                         fp64 ? (const void*)h->d_cd : (const void*)h->d_cf, io->q, io->qd, io->target,
+                         const_cast<double*>(io->U_nominal), U_candidate, h->cost.T, costs,
+                         (hipStream_t)stream) == hipSuccess
+               ? MPPI_OK
+               : MPPI_EDEVICE;
+}
+
 const char* mppi_strerror(int status)
 {
     switch (status) {
@@ -402,6 +415,7 @@ struct mppi_batch {
     ModelM<float>* d_mf = nullptr;
     ModelM<double>* d_md = nullptr;
     CostM<float>* d_cf = nullptr;
+    CostM<double>* d_cd = nullptr;   // the FP64 plant's wall and external force
     void* d_probs = nullptr;
     int2* d_items = nullptr;
     int nitems = 0;
@@ -424,6 +438,7 @@ void batch_release(mppi_batch* b)
     (void)hipFree(b->d_mf);
     (void)hipFree(b->d_md);
     (void)hipFree(b->d_cf);
+    (void)hipFree(b->d_cd);
     (void)hipFree(b->d_probs);
     (void)hipFree(b->d_items);
     (void)hipFree(b->d_sync);
@@ -516,6 +531,7 @@ int mppi_batch_create(const mppi_problem_desc* descs, int n, mppi_batch_t* out)
               hipMalloc(&b->d_mf, sizeof(ModelM<float>) * n) == hipSuccess &&
               hipMalloc(&b->d_md, sizeof(ModelM<double>) * n) == hipSuccess &&
               hipMalloc(&b->d_cf, sizeof(CostM<float>) * n) == hipSuccess &&
+              hipMalloc(&b->d_cd, sizeof(CostM<double>) * n) == hipSuccess &&
               hipMalloc(&b->d_probs, batch_problem_bytes() * n) == hipSuccess &&
               hipMalloc(&b->d_items, sizeof(int2) * items.size()) == hipSuccess &&
               hipMalloc(&b->d_sync, sizeof(unsigned int) * (2 + n)) == hipSuccess &&
@@ -523,16 +539,19 @@ int mppi_batch_create(const mppi_problem_desc* descs, int n, mppi_batch_t* out)
               hipMalloc(&b->d_tick, 2 * sizeof(uint64_t)) == hipSuccess;
     if (!ok) { batch_release(b); return MPPI_ENOMEM; }
     std::vector<CostM<float>> cf(n);
+    std::vector<CostM<double>> cd(n);
     std::vector<char> probs(batch_problem_bytes() * n);
     for (int p = 0; p < n; ++p) {
         prep_cost(b->cost[p], cf[p]);
+        prep_cost(b->cost[p], cd[p]);
         const mppi_cost_params& c = b->cost[p];
-        fill_batch_problem(probs.data() + batch_problem_bytes() * p, b->d_mf + p, b->d_cf + p, c.K, c.T,
-                           has_force(c) ? 1 : 0, acc64_of(c) ? 1 : 0, c.lambda, ntiles[p],
+        fill_batch_problem(probs.data() + batch_problem_bytes() * p, b->d_mf + p, b->d_cf + p, b->d_md + p,
+                           b->d_cd + p, c.K, c.T, has_force(c) ? 1 : 0, acc64_of(c) ? 1 : 0, c.lambda, ntiles[p],
                            (long long)b->u_off[p], (long long)b->k_off[p], part_off[p]);
     }
     ok = hipMemcpy(b->d_raw, b->robot.data(), sizeof(mppi_robot_params) * n, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(b->d_cf, cf.data(), sizeof(CostM<float>) * n, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->d_cd, cd.data(), sizeof(CostM<double>) * n, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(b->d_probs, probs.data(), probs.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(b->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemset(b->d_sync, 0, sizeof(unsigned int) * (2 + n)) == hipSuccess &&
@@ -563,6 +582,25 @@ int mppi_batch_layout(mppi_batch_t b, size_t* u_off, size_t* k_off, size_t* u_to
     if (u_total) *u_total = b->u_total;
     if (k_total) *k_total = b->k_total;
     return MPPI_OK;
+}
+
+int mppi_batch_plant_step_async(mppi_batch_t b, const mppi_batch_io* io, double dt, int substeps, void* stream)
+{
+    if (check_batch_io(b, io) || !(dt > 0) || substeps < 1) return MPPI_EINVAL;
+    return launch_batch_plant(b->d_probs, b->n, const_cast<double*>(io->q), const_cast<double*>(io->qd), io->U_new,
+                              dt, substeps, (hipStream_t)stream) == hipSuccess
+               ? MPPI_OK
+               : MPPI_EDEVICE;
+}
+
+int mppi_batch_select_nominal_async(mppi_batch_t b, const mppi_batch_io* io, const double* U_candidates,
+                                    double* costs, void* stream)
+{
+    if (check_batch_io(b, io) || !U_candidates) return MPPI_EINVAL;
+    return launch_batch_select(b->d_probs, b->n, io->q, io->qd, io->target, const_cast<double*>(io->U_nominal),
+                               U_candidates, costs, (hipStream_t)stream) == hipSuccess
+               ? MPPI_OK
+               : MPPI_EDEVICE;
 }
 
 int mppi_batch_set_launch(mppi_batch_t b, int waves_per_group, int groups)

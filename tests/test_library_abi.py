@@ -88,3 +88,29 @@ def test_null_handle_calls_fail_cleanly(lib):
     z = np.zeros(7)
     assert lib.mppi_update(None, z.ctypes.data_as(D), z.ctypes.data_as(D), None, None, 0, 0, None,
                            None) == B.EINVAL
+
+
+def test_proposal_and_selection_entry_points_reject_bad_arguments(lib, workloads):
+    B._mlp_lib()
+    B._batch_lib()
+    rp = B.robot_params(workloads["single_k256"][0]["robot"])
+    h = C.c_void_p()
+    assert lib.mppi_mlp_create(None, 64, C.byref(h)) == B.EINVAL
+    assert lib.mppi_mlp_create(C.byref(rp), 0, C.byref(h)) == B.EINVAL
+    assert lib.mppi_mlp_create(C.byref(rp), 70000, C.byref(h)) == B.EINVAL
+    bad = B.robot_params(workloads["single_k256"][0]["robot"])
+    bad.link[3].tau_max = 0.0
+    assert lib.mppi_mlp_create(C.byref(bad), 64, C.byref(h)) == B.EINVAL
+    bad.link[3].tau_max = float("nan")
+    assert lib.mppi_mlp_create(C.byref(bad), 64, C.byref(h)) == B.EINVAL
+    f = np.zeros(B.MLP_PARAMS, dtype=np.float32)
+    assert lib.mppi_mlp_set_params(None, f.ctypes.data_as(C.POINTER(C.c_float)), f.size) == B.EINVAL
+    assert lib.mppi_mlp_forward_async(None, None, 1, None, None) == B.EINVAL
+    assert lib.mppi_mlp_grad_async(None, None, None, 1, None, None, None) == B.EINVAL
+    assert lib.mppi_mlp_train_step_async(None, None, None, 1, None, None, None) == B.EINVAL
+    assert lib.mppi_mlp_propose_async(None, 1, None, None, None, None, 126, None) == B.EINVAL
+    io = B.DeviceIO()
+    assert lib.mppi_select_nominal_async(None, C.byref(io), None, None, None) == B.EINVAL
+    bio = B.BatchIO()
+    assert lib.mppi_batch_select_nominal_async(None, C.byref(bio), None, None, None) == B.EINVAL
+    assert lib.mppi_batch_plant_step_async(None, C.byref(bio), 0.01, 10, None) == B.EINVAL
