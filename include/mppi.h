@@ -319,6 +319,13 @@ int mppi_mlp_train_step_async(mppi_mlp_t m, const float* x, const float* y_targe
 int mppi_mlp_propose_async(mppi_mlp_t m, int n, const double* q, const double* qd, const double* target,
                            double* U, int u_stride, void* stream);
 
+/* Training rows from n recorded (state, target, solution) triples: x
+ * [n][21] features (as the proposal computes them) and, when y is non-NULL,
+ * y [n][126] = U [n][u_stride] / tau_max (U [t][j] row-major in the first
+ * 126 values of each row).  Device memory; n is not bounded by max_batch. */
+int mppi_mlp_encode_async(mppi_mlp_t m, int n, const double* q, const double* qd, const double* target,
+                          const double* U, int u_stride, float* x, float* y, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* mppi_strerror(int status);
 

@@ -421,6 +421,7 @@ def _mlp_lib():
         L.mppi_mlp_adam_async.argtypes = [vp, P(AdamParams), vp]
         L.mppi_mlp_train_step_async.argtypes = [vp, vp, vp, C.c_int, P(AdamParams), vp, vp]
         L.mppi_mlp_propose_async.argtypes = [vp, C.c_int, vp, vp, vp, vp, C.c_int, vp]
+        L.mppi_mlp_encode_async.argtypes = [vp, C.c_int, vp, vp, vp, vp, C.c_int, vp, vp, vp]
         L._mlp_ready = True
     return L
 
@@ -495,3 +496,11 @@ class Mlp:
                                               int(u_stride), _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_mlp_propose_async")
+
+    def encode_async(self, q, qd, target, x, U=None, y=None, u_stride=MLP_OUTPUTS, stream=None):
+        """Training rows: features x [n][21] and, with U and y, the
+        normalised targets y [n][126] = U / tau_max."""
+        st = self._lib.mppi_mlp_encode_async(self._h, int(q.shape[0]), _ptr(q), _ptr(qd), _ptr(target), _ptr(U),
+                                             int(u_stride), _ptr(x), _ptr(y), _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_mlp_encode_async")

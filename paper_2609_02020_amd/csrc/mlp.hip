@@ -11,7 +11,8 @@
 //                   one wave per 32 x 32 tile of one layer; db_l = sum of e_l.
 //   mlp_adam_kernel    Adam on the FP32 master weights, then the BF16 copies
 //                   (row-major and transposed).
-//   mlp_features_kernel  (q/q_max, qd/qd_max, p_des, quat_des with w >= 0).
+//   mlp_features_kernel  (q/q_max, qd/qd_max, p_des, quat_des with w >= 0),
+//                   and optionally the normalised targets U* / tau_max.
 //
 // Matrix-core fragments (16 x 16 x 16): lane l holds row (l mod 16) of A and
 // column (l mod 16) of B, each with the four k values 4 (l div 16) + 0..3;
@@ -313,11 +314,14 @@ __global__ void mlp_adam_kernel(MlpDev d, int update, float lr, float beta1, flo
 }
 
 __global__ void mlp_features_kernel(MlpDev d, int n, const double* __restrict__ q, const double* __restrict__ qd,
-                                    const double* __restrict__ target)
+                                    const double* __restrict__ target, float* __restrict__ X,
+                                    const double* __restrict__ U, int u_stride, float* __restrict__ Y)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    float* x = d.X + (size_t)p * kMlpIn;
+    if (U && Y)   // normalised training targets y* = U* / tau_max
+        for (int c = 0; c < kMlpOut; ++c) Y[(size_t)p * kMlpOut + c] = (float)(U[(size_t)p * u_stride + c] / d.scale[14 + c % 7]);
+    float* x = X + (size_t)p * kMlpIn;
     for (int j = 0; j < 7; ++j) {
         x[j] = (float)(q[p * 7 + j] / d.scale[j]);
         x[7 + j] = (float)(qd[p * 7 + j] / d.scale[7 + j]);
@@ -413,10 +417,11 @@ hipError_t launch_mlp_adam(const MlpDev& d, int update, float lr, float beta1, f
 }
 
 hipError_t launch_mlp_features(const MlpDev& d, int n, const double* q, const double* qd, const double* target,
-                               hipStream_t s)
+                               float* X, const double* U, int u_stride, float* Y, hipStream_t s)
 {
-    if (n < 1 || n > d.Bp) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(mlp_features_kernel, dim3((n + 63) / 64), dim3(64), 0, s, d, n, q, qd, target);
+    if (n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mlp_features_kernel, dim3((n + 63) / 64), dim3(64), 0, s, d, n, q, qd, target, X, U,
+                       u_stride, Y);
     return hipGetLastError();
 }
 

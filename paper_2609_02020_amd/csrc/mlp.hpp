@@ -82,8 +82,9 @@ hipError_t launch_mlp_wgrad(const MlpDev& d, int B, float* loss, hipStream_t s);
 // c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t).
 hipError_t launch_mlp_adam(const MlpDev& d, int update, float lr, float beta1, float beta2, float eps, float c1,
                            float c2, hipStream_t s);
-// Features of n states: X [n][21] into d.X.
+// Features of n states into X [n][21]; with U and Y also the normalised
+// targets Y [n][126] = U [n][u_stride] / tau_max.
 hipError_t launch_mlp_features(const MlpDev& d, int n, const double* q, const double* qd, const double* target,
-                               hipStream_t s);
+                               float* X, const double* U, int u_stride, float* Y, hipStream_t s);
 
 }  // namespace mppi

@@ -161,10 +161,20 @@ int mppi_mlp_propose_async(mppi_mlp_t m, int n, const double* q, const double* q
 {
     if (!m || !q || !qd || !target || !U || n < 1 || n > m->max_batch || u_stride < kMlpOut) return MPPI_EINVAL;
     const hipStream_t s = (hipStream_t)stream;
-    if (launch_mlp_features(m->d, n, q, qd, target, s) != hipSuccess ||
+    if (launch_mlp_features(m->d, n, q, qd, target, m->d.X, nullptr, 0, nullptr, s) != hipSuccess ||
         launch_mlp_forward(m->d, m->d.X, n, nullptr, nullptr, U, u_stride, s) != hipSuccess)
         return MPPI_EDEVICE;
     return MPPI_OK;
+}
+
+int mppi_mlp_encode_async(mppi_mlp_t m, int n, const double* q, const double* qd, const double* target,
+                          const double* U, int u_stride, float* x, float* y, void* stream)
+{
+    if (!m || !q || !qd || !target || !x || n < 1 || (y && (!U || u_stride < kMlpOut))) return MPPI_EINVAL;
+    return launch_mlp_features(m->d, n, q, qd, target, x, y ? U : nullptr, u_stride, y, (hipStream_t)stream) ==
+                   hipSuccess
+               ? MPPI_OK
+               : MPPI_EDEVICE;
 }
 
 }  // extern "C"

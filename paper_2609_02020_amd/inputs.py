@@ -30,6 +30,7 @@ NJ = 7
 TAU_MAX = [87.0, 87.0, 87.0, 87.0, 12.0, 12.0, 12.0]
 WORKLOADS_JSON = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                               "tests", "golden", "workloads.json")
+LEARNED_JSON = os.path.join(os.path.dirname(WORKLOADS_JSON), "learned_wall.json")
 
 _RX_PLUS = [[1.0, 0.0, 0.0], [0.0, 0.0, -1.0], [0.0, 1.0, 0.0]]
 _RX_MINUS = [[1.0, 0.0, 0.0], [0.0, 0.0, 1.0], [0.0, -1.0, 0.0]]
@@ -129,6 +130,20 @@ def wall_cost(K: int, T: int, normal, axis: int, d0: float, dt: float = 0.01,
     return c
 
 
+def draw_perturbation(seed: int, n: int = NJ, start_width: float = 0.2, goal_width: float = 0.3):
+    """Offsets of a start and a goal configuration, uniform in +-start_width
+    and +-goal_width rad per joint."""
+    rng = np.random.default_rng(seed)
+    return (rng.uniform(-start_width, start_width, size=n).tolist(),
+            rng.uniform(-goal_width, goal_width, size=n).tolist())
+
+
+def draw_postures(seed: int, count: int, n: int = NJ, half_width: float = 2.5) -> np.ndarray:
+    """count candidate configurations, uniform in +-half_width rad per joint."""
+    rng = np.random.default_rng(seed)
+    return np.array([rng.uniform(-half_width, half_width, size=n) for _ in range(count)])
+
+
 def load(path: str = WORKLOADS_JSON) -> dict:
     """Stored workloads (written by tests/golden/make_workloads.py)."""
     with open(path) as f:
@@ -157,3 +172,16 @@ def draw_mlp_batch(seed: int, rows: int, scale: float = 1.0):
     rng = np.random.default_rng(seed)
     return (rng.uniform(-scale, scale, size=(rows, MLP_DIMS[0])),
             rng.uniform(-0.5, 0.5, size=(rows, MLP_DIMS[-1])))
+
+
+def load_learned(path: str = LEARNED_JSON) -> dict:
+    """Episodes of the learned-proposal task (one arm, one wall, written by
+    tests/golden/make_workloads.py): {"robot", "cost", "train": [...],
+    "eval": [...]}, each episode {"q0", "qd0", "target", "U_nom", "seed"}."""
+    with open(path) as f:
+        d = json.load(f)
+    T = d["cost"]["T"]
+    for part in ("train", "eval"):
+        for e in d[part]:
+            e["U_nom"] = [list(e["g0"])] * T
+    return d

@@ -15,6 +15,7 @@ Recipe (all seeds fixed):
     10 N into the wall (F_des = -10 n).
   * initial nominal U_nom[t] = g(q0) for every step (gravity compensation).
   * Philox key = 3000 + case index (single updates) / episode.
+  * learned_wall.json: the learned-proposal task (see learned_wall()).
 """
 from __future__ import annotations
 
@@ -73,6 +74,63 @@ def make_case(index, kind, K, T, dt, lam, seed, arm_base=1000, state_base=2000,
             "seed": int(seed), "tick": 0}
 
 
+def gravity_stable(arm, q, tol=0.5):
+    """The arm hangs at q: every eigenvalue of M^-1 dg/dq (g the gravity
+    torque, central differences) is >= -tol, so no configuration mode is
+    pushed away from q by gravity."""
+    M = ora.crba(arm, q)
+    h = 1e-6
+    G = np.array([(ora.bias_jacobian(arm, q + e, np.zeros(7)) - ora.bias_jacobian(arm, q - e, np.zeros(7))) / (2 * h)
+                  for e in np.eye(7) * h]).T
+    return np.linalg.eigvals(np.linalg.solve(M, G)).real.min() >= -tol
+
+
+def learned_wall(n_train=1000, n_eval=50):
+    """The learned-proposal task: the arm and wall normal of wall_k4096[0];
+    the base posture is the first of draw_postures(1, 20000) that passes the
+    gravity and Jacobian acceptance tests and is gravity-stable (the arm
+    hangs); the wall plane lies 0.03 m beyond the base EE point along -n.
+    Every episode starts at base + draw_perturbation (+-0.2 rad start,
+    +-0.3 rad goal) with qd0 = 0, U_nom = g(q0), the target pose FK(goal)
+    and 10 N into the wall, accepted when the gravity torques at start and
+    goal are within 0.6 tau_max, sigma_min(J(q0)) >= 0.05 and the start EE
+    point lies 0-0.08 m in front of the wall.  Cost: the wall cost of the
+    contact workload with the velocity-limit penalty on (w_qd = 1e4) and
+    lambda = 10."""
+    base = make_case(100, "wall", 4096, 18, 0.01, 1.0, 3000)
+    arm = base["robot"]
+    n = np.array(base["cost"]["wall_n"])
+    lim = np.array([L["tau_max"] for L in arm["links"]])
+
+    def gravity_ok(q):
+        return (np.abs(ora.bias_jacobian(arm, q, np.zeros(7))) <= 0.6 * lim).all()
+
+    def smin(q):
+        return np.linalg.svd(ora.ee_jacobian(arm, q), compute_uv=False).min()
+
+    qb = next(q for q in inputs.draw_postures(1, 20000)
+              if gravity_ok(q) and gravity_stable(arm, q) and smin(q) >= 0.05)
+    _, _, peb, _ = ora.fk(arm, qb)
+    d0 = float(n @ peb - 0.03)
+    axis = int(np.argmax(np.abs(n)))
+    cost = inputs.wall_cost(4096, 18, n.tolist(), axis, d0, 0.01, 10.0)
+    cost["w_qd"] = 1e4
+    F_des = [-10.0 * v for v in n] + [0.0, 0.0, 0.0]
+    eps = []
+    for e in range(n_train + n_eval):
+        for attempt in range(200):
+            dq0, dqg = inputs.draw_perturbation(6000 + e + 100000 * attempt)
+            q0, qg = qb + dq0, qb + dqg
+            _, _, pe, _ = ora.fk(arm, q0)
+            if gravity_ok(q0) and gravity_ok(qg) and smin(q0) >= 0.05 and 0.0 <= n @ pe - d0 <= 0.08:
+                break
+        else:
+            raise RuntimeError("no acceptable episode %d" % e)
+        eps.append({"q0": q0.tolist(), "qd0": [0.0] * 7, "target": target_of(arm, qg, F_des),
+                    "g0": ora.bias_jacobian(arm, q0, np.zeros(7)).tolist(), "seed": 5000 + e})
+    return {"robot": arm, "cost": cost, "q_base": qb.tolist(), "train": eps[:n_train], "eval": eps[n_train:]}
+
+
 def main():
     out = {"recipe": __doc__.strip().splitlines()[0]}
     # single update, position cost, K=256, T=18, dt=0.01, lambda=1 (FP64 case)
@@ -89,6 +147,10 @@ def main():
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "workloads.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=None, separators=(",", ":"))
+    print("wrote", path, os.path.getsize(path), "bytes")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "learned_wall.json")
+    with open(path, "w") as f:
+        json.dump(learned_wall(), f, indent=None, separators=(",", ":"))
     print("wrote", path, os.path.getsize(path), "bytes")
 
 

@@ -1,0 +1,78 @@
+"""The learned proposal end to end on the GPU: closed-loop plain MPPI at
+K=4096 generates the (state, target) -> U* pairs (1000 episodes x 200
+ticks of the one-arm wall task), the project's kernels train the network,
+and 50 held-out episodes are run at K in {256, 1024} with the proposal
+against plain MPPI at the same K and at K=4096, with the same arm, wall,
+seeds and Philox ticks.
+
+Score: the realised closed-loop cost, the running cost of Eqs. 9-14 of the
+commanded torque at every tick's measured state (FP64 oracle), summed over
+the 200 ticks, per episode; mean and median over the episodes.  The test
+requires the proposal to lower the median at K=256 (the gain over the
+method without it) and reports every ratio, including learned@K /
+plain@4096.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2609_02020_amd import binding as B
+from paper_2609_02020_amd import inputs, learned
+from gpu_util import torch_dev
+
+pytestmark = pytest.mark.gpu
+TICKS = 200
+
+
+def realised_cost(ora, robot, cost, run, episodes):
+    q, qd, u = (run[k].cpu().numpy() for k in ("q", "qd", "u"))
+    tot = np.zeros(len(episodes))
+    for p, e in enumerate(episodes):
+        for t in range(q.shape[0]):
+            tot[p] += ora.running_cost(robot, cost, e["target"], q[t, p], qd[t, p], u[t, p])[0]
+    return tot
+
+
+def test_learned_proposal_gain(ora):
+    torch, dev = torch_dev()
+    d = inputs.load_learned()
+    robot, cost = d["robot"], d["cost"]
+    t0 = time.time()
+
+    def log(msg):
+        print("[%6.1f s] %s" % (time.time() - t0, msg), flush=True)
+
+    data = learned.make_dataset(robot, cost, d["train"], K=4096, ticks=TICKS, log=log)
+    log("dataset: %d rows" % data["q"].shape[0])
+    net = B.Mlp(robot, 512)
+    net.set_params(inputs.draw_mlp_params(11).astype(np.float32))
+    hist = learned.train(net, data, epochs=30, batch=512, lr=1e-3, log=log)
+    assert hist[-1] < 0.5 * hist[0]   # initial parameters vs last epoch
+
+    ev = d["eval"]
+    scores, picked = {}, {}
+    for name, K, prop in (("plain4096", 4096, None), ("plain1024", 1024, None), ("plain256", 256, None),
+                          ("learned1024", 1024, net), ("learned256", 256, net)):
+        run = learned.closed_loop(robot, cost, ev, K, TICKS, proposal=prop)
+        assert (run["status"] == B.OK).all()
+        scores[name] = realised_cost(ora, robot, cost, run, ev)
+        picked[name] = float(run["picked"].float().mean().item())
+        log("%s: mean realised cost %.4g (proposal taken on %.1f%% of ticks)"
+            % (name, scores[name].mean(), 100 * picked[name]))
+    ref, ref_med = scores["plain4096"].mean(), np.median(scores["plain4096"])
+    print("\n| variant | mean realised cost | median | mean / plain K=4096 | median / plain K=4096 | "
+          "median / plain at same K | proposal taken |")
+    print("|---|---|---|---|---|---|---|")
+    for name in scores:
+        same = "plain" + name.replace("learned", "") if name.startswith("learned") else name
+        print("| %s | %.5g | %.5g | %.4f | %.4f | %.4f | %.1f%% |" % (
+            name, scores[name].mean(), np.median(scores[name]), scores[name].mean() / ref,
+            np.median(scores[name]) / ref_med, np.median(scores[name]) / np.median(scores[same]),
+            100 * picked[name]))
+    assert picked["learned256"] > 0
+    # the gain: the proposal lowers the realised cost of MPPI at K=256
+    # (median over the held-out episodes: a few diverging episodes dominate
+    # the mean of every variant)
+    assert np.median(scores["learned256"]) < np.median(scores["plain256"])
+    net.close()

@@ -253,3 +253,27 @@ def test_batch_plant_and_select_match_single_problem(workloads):
         assert np.abs(io["qd"][p].cpu().numpy() - qd1.cpu().numpy()).max() <= 1e-10, p
         solver.close()
     batch.close()
+
+
+def test_encode_rows_match_oracle(workloads):
+    """Training rows: features and torque-limit-normalised targets."""
+    torch, dev = torch_dev()
+    cases = workloads["wall_k4096"][:4]
+    rb = cases[0]["robot"]
+    net = B.Mlp(rb, 64)
+    rng = np.random.default_rng(12)
+    n = 300   # more rows than the network's batch capacity
+    q = rng.uniform(-2, 2, (n, 7))
+    qd = rng.uniform(-2, 2, (n, 7))
+    tg = np.array([B.target_vector(cases[i % 4]["target"]) for i in range(n)])
+    U = rng.uniform(-80, 80, (n, 126))
+    x = torch.zeros((n, 21), device=dev)
+    y = torch.zeros((n, 126), device=dev)
+    net.encode_async(to_dev(torch, dev, q, torch.float64), to_dev(torch, dev, qd, torch.float64),
+                     to_dev(torch, dev, tg, torch.float64), x, U=to_dev(torch, dev, U, torch.float64), y=y)
+    torch.cuda.synchronize()
+    for p in range(n):
+        t = {"p_des": tg[p, :3], "quat_des": tg[p, 3:7]}
+        assert np.abs(x[p].cpu().numpy() - om.features(rb, q[p], qd[p], t)).max() <= 1e-6
+        assert np.abs(y[p].cpu().numpy() - om.normalised_targets(rb, U[p].reshape(18, 7))).max() <= 1e-6
+    net.close()
