@@ -77,6 +77,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--batch-ticks", type=int, default=30,
                    help="graph replays of the 64-problem batched tick (0: skip)")
+    p.add_argument("--no-mlp", action="store_true", help="skip the proposal-network timings")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="after the timed region, copy a MIB-sized buffer 5 times (a plain copy "
                         "kernel of known size, to calibrate HBM byte counters)")
@@ -101,6 +102,60 @@ def cpu_baseline(case, budget_s):
             "sample": "%d full oracle updates (K=%d, T=%d, FP64, OpenMP over samples) in %.1f s; "
                       "%.3g sample-steps/s" % (n, K, T, el, n * K * T / el),
             "cpu": platform.processor() or platform.machine()}
+
+
+# Proposal network 21-256-256-256-126 (unpadded dimensions): a forward
+# pass is 2 * 168,704 flops per row; training adds the backward products of
+# layers 4..2 (2 * 163,328) and the weight gradients (2 * 168,704).
+MLP_FWD_FLOPS_PER_ROW = 2 * (21 * 256 + 256 * 256 + 256 * 256 + 256 * 126)
+MLP_TRAIN_FLOPS_PER_ROW = MLP_FWD_FLOPS_PER_ROW + 2 * (126 * 256 + 256 * 256 + 256 * 256) + MLP_FWD_FLOPS_PER_ROW
+BF16_MFMA_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix cores (AMD published)
+
+
+def mlp_bench(B, inputs, robot, torch, dev, reps=50, rows=512):
+    """The proposal network's kernels: one training step (forward, MSE,
+    backward, weight gradients, Adam) on a batch of `rows` synthetic rows,
+    and the proposal (features, forward, torque scaling) for 1 and 64
+    states, each timed with HIP events over `reps` launches."""
+    import numpy as np
+    net = B.Mlp(robot, max(rows, 64))
+    net.set_params(inputs.draw_mlp_params(1).astype(np.float32))
+    X, Y = inputs.draw_mlp_batch(2, rows)
+    Xd = torch.tensor(X, dtype=torch.float32, device=dev)
+    Yd = torch.tensor(Y, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    loss = torch.zeros(1, device=dev)
+    grad_ms = timed(lambda: net.grad_async(Xd, Yd, loss=loss, stream=stream))
+    train_ms = timed(lambda: net.train_step_async(Xd, Yd, loss, lr=1e-4, stream=stream))
+    fwd_ms = timed(lambda: net.forward_async(Xd, torch.empty((rows, 126), device=dev), stream=stream))
+    prop = {}
+    for n in (1, 64):
+        q = torch.zeros((n, 7), dtype=torch.float64, device=dev)
+        tg = torch.zeros((n, 13), dtype=torch.float64, device=dev)
+        tg[:, 3] = 1.0
+        U = torch.empty((n, 126), dtype=torch.float64, device=dev)
+        prop[n] = timed(lambda: net.propose_async(q, q, tg, U, stream=stream))
+    net.close()
+    tf = MLP_TRAIN_FLOPS_PER_ROW * rows / (grad_ms * 1e-3) / 1e12
+    return {"rows": rows, "train_step_ms": train_ms, "train_rows_per_s": rows / (train_ms * 1e-3),
+            "grad_ms": grad_ms, "forward_ms": fwd_ms, "propose_us": {"1": 1e3 * prop[1], "64": 1e3 * prop[64]},
+            "flops_per_row": {"forward": MLP_FWD_FLOPS_PER_ROW, "train": MLP_TRAIN_FLOPS_PER_ROW},
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
+                         "kernel": "mlp_forward_kernel<true> + mlp_wgrad_kernel (forward, backward, gradients)",
+                         "flops_per_launch": MLP_TRAIN_FLOPS_PER_ROW * rows}}
 
 
 def has_force(cost):
@@ -265,6 +320,8 @@ def main():
     }
     if args.batch_ticks > 0:
         out["batch"] = batch_bench(B, inputs.load()["batch64"], torch, dev, args.batch_ticks)
+    if not args.no_mlp:
+        out["mlp"] = mlp_bench(B, inputs, case["robot"], torch, dev)
     if args.copy_probe > 0:
         src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -8,7 +8,8 @@
 //                   workgroup (the rows are independent), storing every
 //                   activation and signal transposed for the weight gradients.
 //   mlp_wgrad_kernel   dW_l = e_l^T a_{l-1} (a contraction over the batch),
-//                   one wave per 32 x 32 tile of one layer; db_l = sum of e_l.
+//                   one workgroup per 32 x 32 tile of one layer, its 4 waves
+//                   splitting the batch; db_l = sum of e_l.
 //   mlp_adam_kernel    Adam on the FP32 master weights, then the BF16 copies
 //                   (row-major and transposed).
 //   mlp_features_kernel  (q/q_max, qd/qd_max, p_des, quat_des with w >= 0),
@@ -48,16 +49,24 @@ __device__ __forceinline__ uint16_t to_bf16(float x)
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// tanh(u) = 1 - 2 / (exp(2u) + 1) with the hardware exponential and
+// reciprocal (absolute error ~1e-7, far below the BF16 rounding that
+// follows; exp overflow gives the limits +-1 exactly)
+__device__ __forceinline__ float tanh_fast(float u)
+{
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * u) + 1.0f);
+}
+
 // tanh form of GELU and its derivative
 __device__ __forceinline__ float gelu_f(float z)
 {
     const float c = 0.7978845608028654f, a = 0.044715f;
-    return 0.5f * z * (1.0f + tanhf(c * (z + a * z * z * z)));
+    return 0.5f * z * (1.0f + tanh_fast(c * (z + a * z * z * z)));
 }
 __device__ __forceinline__ float gelu_d(float z)
 {
     const float c = 0.7978845608028654f, a = 0.044715f;
-    const float t = tanhf(c * (z + a * z * z * z));
+    const float t = tanh_fast(c * (z + a * z * z * z));
     return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * c * (1.0f + 3.0f * a * z * z);
 }
 
@@ -68,26 +77,35 @@ __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
 
 // acc[i][j] = sum_k A[16 i + r][k] Bt[nb + 16 j + c][k] over the 64 rows of
 // the LDS tile A and CT column tiles of the global k-contiguous Bt [N][K].
-template <int CT>
-__device__ __forceinline__ void tile_mm(const uint16_t* A, const uint16_t* __restrict__ Bt, int K, int nb,
+// Every B fragment of the layer is requested before the first product, so
+// the wave waits for one memory latency per layer instead of one per k-step.
+template <int K, int CT>
+__device__ __forceinline__ void tile_mm(const uint16_t* A, const uint16_t* __restrict__ Bt, int nb,
                                         v4f (&acc)[4][CT], int lane)
 {
+    constexpr int KS = K / 16;
     const int r = lane & 15, kq = (lane >> 4) * 4;
+    v4s b[KS][CT];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int j = 0; j < CT; ++j)
+            b[s][j] = *reinterpret_cast<const v4s*>(Bt + (size_t)(nb + 16 * j + r) * K + 16 * s + kq);
+    // keep the scheduler from sinking the loads next to their products
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < CT; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 2
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        v4s a[4], b[CT];
 #pragma unroll
-        for (int j = 0; j < CT; ++j) b[j] = *reinterpret_cast<const v4s*>(Bt + (size_t)(nb + 16 * j + r) * K + k0 + kq);
+    for (int s = 0; s < KS; ++s) {
+        v4s a[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const v4s*>(A + (16 * i + r) * kLda + k0 + kq);
+        for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const v4s*>(A + (16 * i + r) * kLda + 16 * s + kq);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < CT; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+            for (int j = 0; j < CT; ++j) acc[i][j] = mfma(a[i], b[s][j], acc[i][j]);
     }
 }
 
@@ -101,13 +119,16 @@ __device__ __forceinline__ void store_transposed(const uint16_t* tile, int ncols
     }
 }
 
-// hidden layer forward: out = bf16(gelu(A W^T + b)); z stored when given
-__device__ __forceinline__ void hidden_forward(const uint16_t* A, int K, const uint16_t* __restrict__ W,
+// hidden layer forward: out = bf16(gelu(A W^T + b)); z stored when given.
+// Rows past `rows` (padding of the last workgroup) are set to zero without
+// evaluating GELU (rows never mix, so they cannot reach a valid output).
+template <int K>
+__device__ __forceinline__ void hidden_forward(const uint16_t* A, const uint16_t* __restrict__ W,
                                                const float* __restrict__ bias, float* z, uint16_t* out, int b0,
-                                               int w, int lane)
+                                               int rows, int w, int lane)
 {
     v4f acc[4][4];
-    tile_mm<4>(A, W, K, w * 64, acc, lane);
+    tile_mm<K, 4>(A, W, w * 64, acc, lane);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -117,17 +138,18 @@ __device__ __forceinline__ void hidden_forward(const uint16_t* A, int K, const u
                 const int row = 16 * i + 4 * (lane >> 4) + e, col = w * 64 + 16 * j + (lane & 15);
                 const float zz = acc[i][j][e] + bias[col];
                 if (z) z[(size_t)(b0 + row) * kMlpHid + col] = zz;
-                out[row * kLda + col] = to_bf16(gelu_f(zz));
+                out[row * kLda + col] = row < rows ? to_bf16(gelu_f(zz)) : (uint16_t)0;
             }
 }
 
 // hidden layer backward: out = bf16((E Wt^T) * gelu'(z)); each thread reads
 // back only the z values it stored in the forward pass (same fragment map)
-__device__ __forceinline__ void hidden_backward(const uint16_t* E, int K, const uint16_t* __restrict__ Wt,
-                                                const float* z, uint16_t* out, int b0, int w, int lane)
+template <int K>
+__device__ __forceinline__ void hidden_backward(const uint16_t* E, const uint16_t* __restrict__ Wt, const float* z,
+                                                uint16_t* out, int b0, int w, int lane)
 {
     v4f acc[4][4];
-    tile_mm<4>(E, Wt, K, w * 64, acc, lane);
+    tile_mm<K, 4>(E, Wt, w * 64, acc, lane);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -159,20 +181,22 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
     __syncthreads();
     if (TRAIN) store_transposed(buf[0], kMlpInPad, d.aT0, d.Bp, b0, tid);
 
-    hidden_forward(buf[0], kMlpInPad, d.W1, th + kOffB1, TRAIN ? d.z1 : nullptr, buf[1], b0, w, lane);
+    // training keeps every row (the backward pass reads them all)
+    const int rows = TRAIN ? kMlpRows : min(kMlpRows, B - b0);
+    hidden_forward<kMlpInPad>(buf[0], d.W1, th + kOffB1, TRAIN ? d.z1 : nullptr, buf[1], b0, rows, w, lane);
     __syncthreads();
     if (TRAIN) store_transposed(buf[1], kMlpHid, d.aT1, d.Bp, b0, tid);
-    hidden_forward(buf[1], kMlpHid, d.W2, th + kOffB2, TRAIN ? d.z2 : nullptr, buf[0], b0, w, lane);
+    hidden_forward<kMlpHid>(buf[1], d.W2, th + kOffB2, TRAIN ? d.z2 : nullptr, buf[0], b0, rows, w, lane);
     __syncthreads();
     if (TRAIN) store_transposed(buf[0], kMlpHid, d.aT2, d.Bp, b0, tid);
-    hidden_forward(buf[0], kMlpHid, d.W3, th + kOffB3, TRAIN ? d.z3 : nullptr, buf[1], b0, w, lane);
+    hidden_forward<kMlpHid>(buf[0], d.W3, th + kOffB3, TRAIN ? d.z3 : nullptr, buf[1], b0, rows, w, lane);
     __syncthreads();
     if (TRAIN) store_transposed(buf[1], kMlpHid, d.aT3, d.Bp, b0, tid);
 
     // output layer; training: e_4 = bf16(2 (y - y*) / (B 126)) into buf[0]
     {
         v4f acc[4][2];
-        tile_mm<2>(buf[1], d.W4, kMlpHid, w * 32, acc, lane);
+        tile_mm<kMlpHid, 2>(buf[1], d.W4, w * 32, acc, lane);
         float sq = 0.0f;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -202,24 +226,29 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
     if (tid == 0) d.lossp[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
     store_transposed(buf[0], kMlpOutPad, d.eT4, d.Bp, b0, tid);
 
-    hidden_backward(buf[0], kMlpOutPad, d.W4t, d.z3, buf[1], b0, w, lane);
+    hidden_backward<kMlpOutPad>(buf[0], d.W4t, d.z3, buf[1], b0, w, lane);
     __syncthreads();
     store_transposed(buf[1], kMlpHid, d.eT3, d.Bp, b0, tid);
-    hidden_backward(buf[1], kMlpHid, d.W3t, d.z2, buf[0], b0, w, lane);
+    hidden_backward<kMlpHid>(buf[1], d.W3t, d.z2, buf[0], b0, w, lane);
     __syncthreads();
     store_transposed(buf[0], kMlpHid, d.eT2, d.Bp, b0, tid);
-    hidden_backward(buf[0], kMlpHid, d.W2t, d.z1, buf[1], b0, w, lane);
+    hidden_backward<kMlpHid>(buf[0], d.W2t, d.z1, buf[1], b0, w, lane);
     __syncthreads();
     store_transposed(buf[1], kMlpHid, d.eT1, d.Bp, b0, tid);
 }
 
 // Tiles of 32 x 32: layer 1 8 (256 x 32 padded), layers 2, 3 64 each,
-// layer 4 32 (128 padded x 256).
+// layer 4 32 (128 padded x 256).  Each workgroup's 4 waves split the batch
+// (the contraction index) in quarters and add their partial tiles in LDS.
 constexpr int kWgradTiles = 8 + 64 + 64 + 32;
+constexpr int kWgradWaves = 4;
+constexpr int kWgradChunk = 8;    // k-steps of 16 rows requested together
 
-__global__ __launch_bounds__(64) void mlp_wgrad_kernel(MlpDev d, int B, float* loss)
+__global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, int B, float* loss)
 {
-    const int lane = threadIdx.x;
+    __shared__ float part[kWgradWaves - 1][32 * 32];
+    __shared__ float bpart[kWgradWaves * 2][32];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     int t = blockIdx.x;
     const uint16_t *E, *Act;
     int nreal, kreal, woff, boff, tm, tn;
@@ -239,43 +268,84 @@ __global__ __launch_bounds__(64) void mlp_wgrad_kernel(MlpDev d, int B, float* l
     // (rows past B carry e = 0); later rows of the buffers are stale
     const int m0 = tm * 32, n0 = tn * 32, Bp = d.Bp;
     const int nb = (B + kMlpRows - 1) / kMlpRows, Bb = nb * kMlpRows;
+    const int quarter = Bb / kWgradWaves, kb = w * quarter;   // a multiple of 16
     const int r = lane & 15, kq = (lane >> 4) * 4;
+    const uint16_t* ea[2] = {E + (size_t)(m0 + r) * Bp + kq, E + (size_t)(m0 + 16 + r) * Bp + kq};
+    const uint16_t* ab[2] = {Act + (size_t)(n0 + r) * Bp + kq, Act + (size_t)(n0 + 16 + r) * Bp + kq};
     v4f acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 4
-    for (int k0 = 0; k0 < Bb; k0 += 16) {
-        v4s a[2], b[2];
+    for (int k0 = kb; k0 < kb + quarter; k0 += 16 * kWgradChunk) {
+        const int ns = min(kWgradChunk, (kb + quarter - k0) / 16);
+        v4s a[kWgradChunk][2], b[kWgradChunk][2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const v4s*>(E + (size_t)(m0 + 16 * i + r) * Bp + k0 + kq);
+        for (int s = 0; s < kWgradChunk; ++s)
+            if (s < ns)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const v4s*>(Act + (size_t)(n0 + 16 * j + r) * Bp + k0 + kq);
+                for (int i = 0; i < 2; ++i) {
+                    a[s][i] = *reinterpret_cast<const v4s*>(ea[i] + k0 + 16 * s);
+                    b[s][i] = *reinterpret_cast<const v4s*>(ab[i] + k0 + 16 * s);
+                }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < kWgradChunk; ++s)
+            if (s < ns)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) acc[i][j] = mfma(a[s][i], b[s][j], acc[i][j]);
+    }
+    // db: lanes 0-31 and 32-63 sum the two halves of this wave's quarter
+    const bool bias = tn == 0;
+    if (bias) {
+        const int row = m0 + (lane & 31), h = quarter / 2, k1 = kb + (lane >> 5) * h;
+        float sb = 0.0f;
+        if (row < nreal) {
+            const uint16_t* er = E + (size_t)row * Bp;
+            for (int k = k1; k < k1 + h; k += 8) {
+                const uint4 v = *reinterpret_cast<const uint4*>(er + k);
+                const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sb += __uint_as_float(u[c] << 16) + __uint_as_float(u[c] & 0xffff0000u);
+            }
+        }
+        bpart[w * 2 + (lane >> 5)][lane & 31] = sb;
+    }
+    if (w > 0) {
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    part[w - 1][(16 * i + 4 * (lane >> 4) + e) * 32 + 16 * j + r] = acc[i][j][e];
     }
+    __syncthreads();
+    if (w != 0) return;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = m0 + 16 * i + 4 * (lane >> 4) + e, col = n0 + 16 * j + r;
-                if (row < nreal && col < kreal) d.grad[woff + row * kreal + col] = acc[i][j][e];
+                const int rl = 16 * i + 4 * (lane >> 4) + e, cl = 16 * j + r;
+                float v = acc[i][j][e];
+#pragma unroll
+                for (int q = 0; q < kWgradWaves - 1; ++q) v += part[q][rl * 32 + cl];
+                if (m0 + rl < nreal && n0 + cl < kreal) d.grad[woff + (m0 + rl) * kreal + n0 + cl] = v;
             }
-    if (tn == 0 && lane < 32 && m0 + lane < nreal) {
-        const uint16_t* er = E + (size_t)(m0 + lane) * Bp;
-        float s = 0.0f;
-        for (int b = 0; b < Bb; ++b) s += from_bf16(er[b]);
-        d.grad[boff + m0 + lane] = s;
+    if (bias && lane < 32 && m0 + lane < nreal) {
+        float sb = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 2 * kWgradWaves; ++q) sb += bpart[q][lane];
+        d.grad[boff + m0 + lane] = sb;
     }
     if (blockIdx.x == 0 && lane == 0 && loss) {
-        float s = 0.0f;
-        for (int i = 0; i < nb; ++i) s += d.lossp[i];
-        *loss = s / ((float)B * (float)kMlpOut);
+        float sl = 0.0f;
+        for (int i = 0; i < nb; ++i) sl += d.lossp[i];
+        *loss = sl / ((float)B * (float)kMlpOut);
     }
 }
 
@@ -404,7 +474,7 @@ hipError_t launch_mlp_forward(const MlpDev& d, const float* X, int B, const floa
 hipError_t launch_mlp_wgrad(const MlpDev& d, int B, float* loss, hipStream_t s)
 {
     if (B < 1 || B > d.Bp) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(mlp_wgrad_kernel, dim3(kWgradTiles), dim3(64), 0, s, d, B, loss);
+    hipLaunchKernelGGL(mlp_wgrad_kernel, dim3(kWgradTiles), dim3(64 * kWgradWaves), 0, s, d, B, loss);
     return hipGetLastError();
 }
 

@@ -61,3 +61,12 @@ def test_bench_flop_constants_free_space(oc, workloads):
     assert free
     for case in free[:4]:
         assert per_step(oc, case) == (bench.FLOPS_PER_SAMPLE_STEP_FREE, bench.FLOPS_PER_SAMPLE_TERMINAL_FREE)
+
+
+def test_mlp_flop_constants():
+    """2 flops per weight per row forward; training adds the backward
+    products of layers 4..2 and the weight gradients."""
+    from oracle import mlp as om
+    weights = sum(shape[0] * shape[1] for _, shape, _ in om.layer_slices())
+    assert bench.MLP_FWD_FLOPS_PER_ROW == 2 * weights
+    assert bench.MLP_TRAIN_FLOPS_PER_ROW == 4 * weights + 2 * (weights - 21 * 256)
