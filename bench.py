@@ -43,9 +43,10 @@ FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (AMD published)
 # known size (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 on gfx950), taken on the
 # kernel sources whose digest is recorded here; reported as null once the
 # sources differ.
-PROFILED_DIGEST = "fed12822bb0ccc48"
-PROFILED_TRAFFIC = {"update_kernel": 679_635 + 53_433,       # K=4096, T=18 contact workload
-                    "batch_kernel": 6_427_446 + 6_094_107}   # 64-problem batch, 2048 groups
+PROFILED_DIGEST = "75ab6efe72199f5e"
+PROFILED_TRAFFIC = {"update_kernel": 674899 + 53614,        # K=4096, T=18 contact workload
+                    "batch_kernel": 6484235 + 6094275,      # 64-problem batch, 2048 groups
+                    "mlp_train": 15934666 + 3988256}        # forward/backward + weight gradients, 512 rows
 
 
 def kernel_source_digest():
@@ -153,7 +154,7 @@ def mlp_bench(B, inputs, robot, torch, dev, reps=50, rows=512):
             "grad_ms": grad_ms, "forward_ms": fwd_ms, "propose_us": {"1": 1e3 * prop[1], "64": 1e3 * prop[64]},
             "flops_per_row": {"forward": MLP_FWD_FLOPS_PER_ROW, "train": MLP_TRAIN_FLOPS_PER_ROW},
             "roofline": {"bound": "mfma", "achieved": tf, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": tf / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
+                         "frac": tf / BF16_MFMA_PEAK_TFLOPS, "traffic": profiled_traffic("mlp_train"),
                          "kernel": "mlp_forward_kernel<true> + mlp_wgrad_kernel (forward, backward, gradients)",
                          "flops_per_launch": MLP_TRAIN_FLOPS_PER_ROW * rows}}
 
