@@ -60,16 +60,17 @@ __global__ __launch_bounds__(kRolloutBlock) void update_kernel(
     __shared__ R Us[kMaxT * NJ];
     __shared__ A wl[64];
     __shared__ int last;
-    // the model and cost constants are read from LDS (uniform addresses):
-    // ~250 values are more than the scalar registers hold across a step
-    __shared__ ModelM<R> Msh;
+    // Model constants (~190 values) are read through the scalar cache at
+    // uniform addresses, re-issued every step (rollout.hpp per_step), so
+    // their scalar-register lifetimes stay within a step; the cost
+    // constants are read from an LDS copy, which measured faster than
+    // adding them to the scalar stream.
     __shared__ CostM<R> Csh;
     const int lane = threadIdx.x & 63;
-    wave_copy(&Msh, Mp, sizeof(ModelM<R>), lane);
     wave_copy(&Csh, Cp, sizeof(CostM<R>), lane);
     for (int i = threadIdx.x; i < T * NJ; i += blockDim.x) Us[i] = R(U_nom[i]);
     __syncthreads();
-    const ModelM<R>& M = Msh;
+    const ModelM<R>& M = *Mp;
     const CostM<R>& C = Csh;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     R* tile = reinterpret_cast<R*>(dyn_lds);   // [rows][65] (noise) or [64][65] (regeneration)
@@ -140,7 +141,6 @@ __global__ __launch_bounds__(64 * W) void batch_kernel(
     double* U_shift, float* __restrict__ costs, int* __restrict__ status, const uint64_t* __restrict__ seeds,
     const uint64_t* __restrict__ tickp, double* __restrict__ parts)
 {
-    __shared__ ModelM<float> Msh[W];
     __shared__ CostM<float> Csh[W];
     __shared__ float Us[W][kMaxTBatch * NJ];
     __shared__ float tr[W][64 * kLdsRowPad];
@@ -159,11 +159,10 @@ __global__ __launch_bounds__(64 * W) void batch_kernel(
         const BatchProblem& Pb = probs[it.x];
         const int T = Pb.T, K = Pb.K;
         wave_sync();
-        wave_copy(&Msh[wid], Pb.model, sizeof(ModelM<float>), lane);
         wave_copy(&Csh[wid], Pb.cost, sizeof(CostM<float>), lane);
         for (int i = lane; i < T * NJ; i += 64) Us[wid][i] = float(U_nom[Pb.u_off + i]);
         wave_sync();
-        const ModelM<float>& M = Msh[wid];
+        const ModelM<float>& M = *Pb.model;   // scalar cache, as in update_kernel
         const CostM<float>& C = Csh[wid];
         const int k = it.y * 64 + lane;
         const uint64_t seed = seeds[it.x];

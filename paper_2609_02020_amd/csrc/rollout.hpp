@@ -17,9 +17,9 @@ namespace mppi {
 template <typename R> MPPI_HD bool finite_(R x) { return x - x == R(0); }
 
 // The same object behind an address the compiler cannot prove loop-invariant,
-// so that reads of model constants stay inside the step loop (re-read from
-// LDS each step) instead of being hoisted and held in registers for the
-// whole rollout.
+// so that reads of model and cost constants stay inside the step loop
+// (re-read each step from the scalar cache or LDS) instead of being hoisted
+// and held in registers for the whole rollout.
 template <typename T> MPPI_HD const T* per_step(const T* p)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
