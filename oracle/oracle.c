@@ -821,12 +821,95 @@ double ora_running_cost(const ora_robot* rb, const ora_cost* cp,
     cjoint = joint_cost(rb, cp, q, qd);
     for (int j = 0; j < n; ++j)
         ctau += cp->w_tau * hinge_sq(fabs(v[j]) - rb->link[j].tau_max);
-    double total = cpos + cori + cforce + cjoint + ctau;
+    /* Eq. (14): C_constraint = C_joint + C_collision */
+    double ccoll = ora_collision_cost(rb, cp, q, NULL);
+    double total = cpos + cori + cforce + cjoint + ctau + ccoll;
     if (parts) {
         parts[0] = cpos; parts[1] = cori; parts[2] = cforce;
-        parts[3] = cjoint; parts[4] = ctau; parts[5] = total;
+        parts[3] = cjoint; parts[4] = ctau; parts[5] = ccoll; parts[6] = total;
     }
     return total;
+}
+
+/* Minimum distance between two segments (the quantity Eq. (15) thresholds;
+   the paper computes it with Lumelsky's method).  Here straight from the
+   definition: |a0 + s da - b0 - t db|^2 is a convex quadratic in (s, t), so
+   its minimum over the unit square is the interior stationary point when
+   that lies in the square, else the minimum over the four edges, each a
+   one-variable quadratic minimised by clamping its stationary point. */
+static double seg_d2(const double* a0, const double* da, const double* b0, const double* db, double s, double t)
+{
+    double d2 = 0;
+    for (int c = 0; c < 3; ++c) {
+        double e = a0[c] + s * da[c] - b0[c] - t * db[c];
+        d2 += e * e;
+    }
+    return d2;
+}
+
+static double clamp01(double x) { return x < 0 ? 0 : (x > 1 ? 1 : x); }
+
+double ora_segment_distance(const double* a0, const double* a1, const double* b0, const double* b1)
+{
+    double da[3], db[3], r[3];
+    for (int c = 0; c < 3; ++c) { da[c] = a1[c] - a0[c]; db[c] = b1[c] - b0[c]; r[c] = a0[c] - b0[c]; }
+    /* f(s,t) = |r + s da - t db|^2 = A s^2 - 2 B s t + E t^2 + 2 C s - 2 F t + |r|^2 */
+    double A = 0, B = 0, E = 0, Cc = 0, F = 0;
+    for (int c = 0; c < 3; ++c) {
+        A += da[c] * da[c]; B += da[c] * db[c]; E += db[c] * db[c];
+        Cc += da[c] * r[c]; F += db[c] * r[c];
+    }
+    double best = INFINITY;
+    double det = A * E - B * B;
+    if (det > 1e-12 * (A * E + 1e-300)) {
+        /* grad = 0:  A s - B t = -C,  -B s + E t = F */
+        double s = (-Cc * E + B * F) / det, t = (A * F - B * Cc) / det;
+        if (s >= 0 && s <= 1 && t >= 0 && t <= 1) best = seg_d2(a0, da, b0, db, s, t);
+    }
+    /* edges s = 0, 1: minimise over t; edges t = 0, 1: minimise over s */
+    for (int e = 0; e < 2; ++e) {
+        double s = e, t = E > 0 ? clamp01((F + B * s) / E) : 0;
+        double d2 = seg_d2(a0, da, b0, db, s, t);
+        if (d2 < best) best = d2;
+        t = e;
+        s = A > 0 ? clamp01((B * t - Cc) / A) : 0;
+        d2 = seg_d2(a0, da, b0, db, s, t);
+        if (d2 < best) best = d2;
+    }
+    return sqrt(best);
+}
+
+void ora_link_segments(const ora_robot* rb, const double* q, double* seg)
+{
+    int n = rb->n;
+    double R[9 * N], p[3 * N], pe[3], Re[9];
+    ora_fk(rb, q, R, p, pe, Re);
+    for (int i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) {
+            seg[i * 6 + c] = p[i * 3 + c];
+            seg[i * 6 + 3 + c] = i + 1 < n ? p[(i + 1) * 3 + c] : pe[c];
+        }
+}
+
+double ora_collision_cost(const ora_robot* rb, const ora_cost* cp, const double* q, double* margin)
+{
+    double m = INFINITY, cost = 0;
+    if (cp->n_pairs > 0) {
+        int n = rb->n;
+        double seg[6 * (N + ORA_MAXOBS)];
+        ora_link_segments(rb, q, seg);
+        for (int o = 0; o < cp->n_obstacles; ++o)
+            for (int c = 0; c < 6; ++c) seg[(n + o) * 6 + c] = cp->obstacles[o][c];
+        for (int i = 0; i < cp->n_pairs; ++i) {
+            const double* a = seg + 6 * cp->pairs[i][0];
+            const double* b = seg + 6 * cp->pairs[i][1];
+            double d = ora_segment_distance(a, a + 3, b, b + 3);
+            if (d < cp->d_th[i]) cost += cp->w_collision;   /* the indicator of Eq. (15) */
+            if (fabs(d - cp->d_th[i]) < m) m = fabs(d - cp->d_th[i]);
+        }
+    }
+    if (margin) *margin = m;
+    return cost;
 }
 
 /* phi(x_T): the paper leaves it unspecified; here w_T times the motion and
@@ -851,7 +934,16 @@ double ora_rollout(const ora_robot* rb, const ora_cost* cp,
                    const double* U_nom, uint64_t seed, uint64_t tick,
                    uint32_t k, double* noise)
 {
+    return ora_rollout_margin(rb, cp, tg, q0, qd0, U_nom, seed, tick, k, noise, NULL);
+}
+
+double ora_rollout_margin(const ora_robot* rb, const ora_cost* cp,
+                          const ora_target* tg, const double* q0, const double* qd0,
+                          const double* U_nom, uint64_t seed, uint64_t tick,
+                          uint32_t k, double* noise, double* margin)
+{
     int n = rb->n;
+    if (margin) *margin = INFINITY;
     double q[N], qd[N], S = 0.0;
     double tau_ext_const[N] = {0};
     memcpy(q, q0, sizeof(double) * n);
@@ -872,6 +964,11 @@ double ora_rollout(const ora_robot* rb, const ora_cost* cp,
             v[j] = U_nom[t * n + j] + du;
         }
         S += ora_running_cost(rb, cp, tg, q, qd, v, NULL);
+        if (margin && cp->n_pairs > 0) {
+            double m;
+            ora_collision_cost(rb, cp, q, &m);
+            if (m < *margin) *margin = m;
+        }
         for (int j = 0; j < n; ++j) rhs[j] = v[j] + tau_ext_const[j];
         if (cp->ext_mode == ORA_EXT_WALL) {
             double f[6];

@@ -28,6 +28,8 @@ extern "C" {
 #endif
 
 #define ORA_MAXJ 7
+#define ORA_MAXOBS 4
+#define ORA_MAXPAIRS 32
 
 typedef struct {
     double R_parent[9];  /* rotation of joint frame i in frame i-1 (before Rz(q_i)) */
@@ -66,6 +68,15 @@ typedef struct {
     double wall_n[3];         /* unit wall normal (points out of the wall) */
     double wall_d0;           /* wall plane: n . p = d0 */
     double wall_k, wall_c;    /* spring [N/m], damper [N s/m] */
+    /* collision term of Eqs. (14)-(15): w_collision * #{pairs with d < d_th};
+       segment ids 0..n-1 are the links (link i from the origin of joint i to
+       that of joint i+1, the last one to the EE point), n + o is obstacle o */
+    double w_collision;
+    int n_obstacles;                       /* 0..ORA_MAXOBS */
+    double obstacles[ORA_MAXOBS][6];       /* world segments: end a, end b [m] */
+    int n_pairs;                           /* 0..ORA_MAXPAIRS */
+    int pairs[ORA_MAXPAIRS][2];            /* segment ids */
+    double d_th[ORA_MAXPAIRS];             /* thresholds [m] */
 } ora_cost;
 
 typedef struct {
@@ -130,6 +141,13 @@ void ora_normals(uint64_t seed, uint64_t tick, uint32_t k, uint32_t t,
 double ora_running_cost(const ora_robot* rb, const ora_cost* c,
                         const ora_target* tg, const double* q,
                         const double* qd, const double* v, double* parts);
+/* Minimum distance between the segments [a0, a1] and [b0, b1]. */
+double ora_segment_distance(const double* a0, const double* a1, const double* b0, const double* b1);
+/* The n link segments at q: seg[i*6 .. i*6+5] = (start, end). */
+void ora_link_segments(const ora_robot* rb, const double* q, double* seg);
+/* C_collision of Eq. (15) at q; *margin (may be NULL) receives
+   min_i |d_i - d_th,i| (infinity without pairs). */
+double ora_collision_cost(const ora_robot* rb, const ora_cost* c, const double* q, double* margin);
 double ora_terminal_cost(const ora_robot* rb, const ora_cost* c,
                          const ora_target* tg, const double* q,
                          const double* qd);
@@ -140,6 +158,13 @@ double ora_rollout(const ora_robot* rb, const ora_cost* c,
                    const ora_target* tg, const double* q0, const double* qd0,
                    const double* U_nom, uint64_t seed, uint64_t tick,
                    uint32_t k, double* noise);
+/* The same rollout; also returns, in *margin, the smallest |d_i - d_th,i|
+   over every pre-step state of the horizon (the collision indicator's
+   distance to a flip). */
+double ora_rollout_margin(const ora_robot* rb, const ora_cost* c,
+                          const ora_target* tg, const double* q0, const double* qd0,
+                          const double* U_nom, uint64_t seed, uint64_t tick,
+                          uint32_t k, double* noise, double* margin);
 /* Eq. 4 weighting of given costs and noise (K x T x n) into U_new. */
 int  ora_weights_update(int K, int T, int n, double lambda, const double* S,
                         const double* noise, const double* U_nom,

@@ -21,6 +21,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 MAXJ = 7
+MAXOBS, MAXPAIRS = 4, 32
 
 OK, EINVAL, ENONFINITE, ESINGULAR = 0, 1, 2, 3
 EXT_NONE, EXT_CONST, EXT_WALL = 0, 1, 2
@@ -63,7 +64,10 @@ class Cost(C.Structure):
                 ("force_mode", C.c_int), ("ext_mode", C.c_int),
                 ("F_ext", C.c_double * 6), ("wall_n", C.c_double * 3),
                 ("wall_d0", C.c_double), ("wall_k", C.c_double),
-                ("wall_c", C.c_double)]
+                ("wall_c", C.c_double), ("w_collision", C.c_double),
+                ("n_obstacles", C.c_int), ("obstacles", (C.c_double * 6) * MAXOBS),
+                ("n_pairs", C.c_int), ("pairs", (C.c_int * 2) * MAXPAIRS),
+                ("d_th", C.c_double * MAXPAIRS)]
 
 
 class Target(C.Structure):
@@ -119,6 +123,14 @@ def lib():
             L.ora_update.restype = C.c_int
             L.ora_plant_step.argtypes = [P(Robot), P(Cost), _D, _D, _D, C.c_double, C.c_int]
             L.ora_max_threads.restype = C.c_int
+            L.ora_segment_distance.argtypes = [_D, _D, _D, _D]
+            L.ora_segment_distance.restype = C.c_double
+            L.ora_link_segments.argtypes = [P(Robot), _D, _D]
+            L.ora_collision_cost.argtypes = [P(Robot), P(Cost), _D, P(C.c_double)]
+            L.ora_collision_cost.restype = C.c_double
+            L.ora_rollout_margin.argtypes = [P(Robot), P(Cost), P(Target), _D, _D, _D,
+                                             C.c_uint64, C.c_uint64, C.c_uint32, _D, P(C.c_double)]
+            L.ora_rollout_margin.restype = C.c_double
             _lib = L
     return _lib
 
@@ -167,6 +179,17 @@ def cost_struct(cost: dict) -> Cost:
     c.w_terminal = float(cost.get("w_terminal", 1.0))
     c.force_mode = int(cost.get("force_mode", 0))
     c.ext_mode = int(cost.get("ext_mode", EXT_NONE))
+    c.w_collision = float(cost.get("w_collision", 0.0))
+    obs = cost.get("obstacles", [])
+    pairs = cost.get("pairs", [])
+    assert len(obs) <= MAXOBS and len(pairs) <= MAXPAIRS
+    c.n_obstacles = len(obs)
+    for o, seg in enumerate(obs):
+        _fill(c.obstacles[o], seg)
+    c.n_pairs = len(pairs)
+    for i, (a, b) in enumerate(pairs):
+        c.pairs[i][0], c.pairs[i][1] = int(a), int(b)
+        c.d_th[i] = float(cost["d_th"][i])
     return c
 
 
@@ -316,11 +339,41 @@ def normals(seed, tick, k, t):
 
 def running_cost(robot, cost, target, q, qd, v):
     rb, c, tg = robot_struct(robot), cost_struct(cost), target_struct(target)
-    parts = np.zeros(6)
+    parts = np.zeros(7)
     total = lib().ora_running_cost(C.byref(rb), C.byref(c), C.byref(tg),
                                    _p(_vec(q, rb.n)), _p(_vec(qd, rb.n)),
                                    _p(_vec(v, rb.n)), _p(parts))
-    return total, dict(zip(("pos", "ori", "force", "joint", "torque", "total"), parts))
+    return total, dict(zip(("pos", "ori", "force", "joint", "torque", "collision", "total"), parts))
+
+
+def segment_distance(a0, a1, b0, b1):
+    return float(lib().ora_segment_distance(*(_p(_vec(x, 3)) for x in (a0, a1, b0, b1))))
+
+
+def link_segments(robot, q):
+    rb = robot_struct(robot)
+    seg = np.zeros((rb.n, 6))
+    lib().ora_link_segments(C.byref(rb), _p(_vec(q, rb.n)), _p(seg))
+    return seg
+
+
+def collision_cost(robot, cost, q):
+    """(C_collision at q, min_i |d_i - d_th,i|)."""
+    rb, c = robot_struct(robot), cost_struct(cost)
+    m = C.c_double()
+    v = lib().ora_collision_cost(C.byref(rb), C.byref(c), _p(_vec(q, rb.n)), C.byref(m))
+    return float(v), m.value
+
+
+def rollout_margin(robot, cost, target, q0, qd0, U_nom, seed, tick, k):
+    """(S_k, smallest |d_i - d_th,i| over the horizon's pre-step states)."""
+    rb, c, tg = robot_struct(robot), cost_struct(cost), target_struct(target)
+    U = _vec(U_nom, c.T * rb.n)
+    m = C.c_double()
+    S = lib().ora_rollout_margin(C.byref(rb), C.byref(c), C.byref(tg), _p(_vec(q0, rb.n)),
+                                 _p(_vec(qd0, rb.n)), _p(U), C.c_uint64(seed), C.c_uint64(tick),
+                                 C.c_uint32(k), None, C.byref(m))
+    return S, m.value
 
 
 def terminal_cost(robot, cost, target, q, qd):
