@@ -160,6 +160,38 @@ def mlp_bench(B, inputs, robot, torch, dev, reps=50, rows=512):
                          "flops_per_launch": MLP_TRAIN_FLOPS_PER_ROW * rows}}
 
 
+def collision_bench(B, case, torch, dev, steps=100):
+    """The contact workload with the collision term of Eqs. 14-15 (two
+    obstacles, 20 pairs): device-resident updates timed with HIP events."""
+    import numpy as np
+    solver = B.Solver(case["robot"], case["cost"], B.FP32)
+    f64 = dict(dtype=torch.float64, device=dev)
+    K, T = case["cost"]["K"], case["cost"]["T"]
+    io = {"q": torch.tensor(case["q0"], **f64), "qd": torch.tensor(case["qd0"], **f64),
+          "target": torch.tensor(B.target_vector(case["target"]), **f64),
+          "U_nominal": torch.tensor(case["U_nom"], **f64), "U_new": torch.empty((T, 7), **f64),
+          "U_shift": torch.empty((T, 7), **f64), "costs": torch.empty(K, dtype=torch.float32, device=dev),
+          "status": torch.zeros(1, dtype=torch.int32, device=dev), "seed": case["seed"], "tick": 0}
+    stream = torch.cuda.current_stream()
+    for i in range(10):
+        io["tick"] = i
+        solver.update_async(io, stream)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(evs):
+        io["tick"] = 10 + i
+        a.record(stream)
+        solver.update_async(io, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    solver.close()
+    return {"workload": "collision_k4096[0]: the contact workload plus %d obstacles and %d collision pairs "
+                        "(w_collision = %g), K=%d, T=%d" % (len(case["cost"]["obstacles"]), len(case["cost"]["pairs"]),
+                                                          case["cost"]["w_collision"], K, T),
+            "update_kernel_ms": ms, "update_hz_kernel_only": 1e3 / ms, "rollout_steps_per_s": K * T / (ms * 1e-3)}
+
+
 def has_force(cost):
     return any(w != 0 for w in cost["W_force"]) or any(w != 0 for w in cost["W_reg"])
 
@@ -324,6 +356,7 @@ def main():
         out["batch"] = batch_bench(B, inputs.load()["batch64"], torch, dev, args.batch_ticks)
     if not args.no_mlp:
         out["mlp"] = mlp_bench(B, inputs, case["robot"], torch, dev)
+    out["collision"] = collision_bench(B, inputs.load()["collision_k4096"][0], torch, dev)
     if args.copy_probe > 0:
         src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

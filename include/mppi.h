@@ -37,6 +37,8 @@ extern "C" {
 #endif
 
 #define MPPI_NJ 7 /* joints supported by the kernels */
+#define MPPI_MAX_OBSTACLES 4
+#define MPPI_MAX_PAIRS 32
 
 typedef enum {
     MPPI_OK = 0,
@@ -98,6 +100,19 @@ typedef struct {
     int precision;           /* mppi_precision of the rollouts */
     double lambda_fp64_threshold; /* weights and weighted sum in FP64 when
                                      lambda < threshold (FP32 otherwise) */
+    /* Collision term of Eqs. 14-15: C_collision = w_collision times the
+     * number of pairs whose minimum segment distance d_i is below d_th[i],
+     * added to the running cost at every pre-step state (not to phi).
+     * Segment ids: 0..6 are the links (link i runs from the origin of
+     * joint i to that of joint i+1, link 6 to the EE point; cylinder radii
+     * go into the thresholds), 7 + o is obstacle o, a world segment held
+     * over the horizon (change it between updates with mppi_set_cost). */
+    double w_collision;      /* >= 0 */
+    int n_obstacles;         /* 0 .. MPPI_MAX_OBSTACLES */
+    double obstacles[MPPI_MAX_OBSTACLES][6];  /* end a [3], end b [3], world [m] */
+    int n_pairs;             /* 0 .. MPPI_MAX_PAIRS; 0 disables the term */
+    int pairs[MPPI_MAX_PAIRS][2];             /* segment ids, < 7 + n_obstacles */
+    double d_th[MPPI_MAX_PAIRS];              /* thresholds [m], >= 0 */
 } mppi_cost_params;
 
 typedef struct {

@@ -41,6 +41,9 @@ class RobotParams(C.Structure):
                 ("gravity", C.c_double * 3)]
 
 
+MAX_OBSTACLES, MAX_PAIRS = 4, 32
+
+
 class CostParams(C.Structure):
     _fields_ = [("K", C.c_int), ("T", C.c_int), ("dt", C.c_double),
                 ("lam", C.c_double), ("sigma", C.c_double * NJ),
@@ -52,7 +55,10 @@ class CostParams(C.Structure):
                 ("ext_mode", C.c_int), ("F_ext", C.c_double * 6),
                 ("wall_n", C.c_double * 3), ("wall_d0", C.c_double),
                 ("wall_k", C.c_double), ("wall_c", C.c_double),
-                ("precision", C.c_int), ("lambda_fp64_threshold", C.c_double)]
+                ("precision", C.c_int), ("lambda_fp64_threshold", C.c_double),
+                ("w_collision", C.c_double), ("n_obstacles", C.c_int),
+                ("obstacles", (C.c_double * 6) * MAX_OBSTACLES), ("n_pairs", C.c_int),
+                ("pairs", (C.c_int * 2) * MAX_PAIRS), ("d_th", C.c_double * MAX_PAIRS)]
 
 
 class Target(C.Structure):
@@ -110,6 +116,17 @@ def cost_params(cost: dict, precision: int = FP32, lambda_fp64_threshold: float 
     cp.ext_mode = int(cost.get("ext_mode", EXT_NONE))
     cp.precision = int(precision)
     cp.lambda_fp64_threshold = float(lambda_fp64_threshold)
+    cp.w_collision = float(cost.get("w_collision", 0.0))
+    obs, pairs = cost.get("obstacles", []), cost.get("pairs", [])
+    if len(obs) > MAX_OBSTACLES or len(pairs) > MAX_PAIRS:
+        raise ValueError("at most %d obstacles and %d collision pairs" % (MAX_OBSTACLES, MAX_PAIRS))
+    cp.n_obstacles = len(obs)
+    for o, seg in enumerate(obs):
+        _fill(cp.obstacles[o], seg)
+    cp.n_pairs = len(pairs)
+    for i, (a, b) in enumerate(pairs):
+        cp.pairs[i][0], cp.pairs[i][1] = int(a), int(b)
+        cp.d_th[i] = float(cost["d_th"][i])
     return cp
 
 

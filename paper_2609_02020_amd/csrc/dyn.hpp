@@ -163,6 +163,12 @@ template <typename R> struct CostM {
     int force_mode;   // 0: tau_F = v - g(q); 1: tau_F = v
     int has_ori;      // any W_ori != 0
     int has_force;    // any W_force / W_reg != 0
+    // collision term (Eqs. 14-15)
+    R w_coll;
+    R obs[4][6];      // obstacle segments, world
+    R dth2[32];       // squared thresholds
+    int n_pairs;
+    int pa[32], pb[32];   // segment ids: 0..NJ-1 links, NJ + o obstacle o
 };
 
 // ---------------------------------------------------------------------------
@@ -743,8 +749,92 @@ MPPI_HD void fk_ee(const ModelM<R>& M, const R* q, R* pee, R* Rn, R* Pj /* [NJ][
 }
 
 // ---------------------------------------------------------------------------
+// collision term (Eqs. 14-15)
+// ---------------------------------------------------------------------------
+MPPI_HD int uniform_(int x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_readfirstlane(x);   // the same in every lane
+#else
+    return x;
+#endif
+}
+template <typename R> MPPI_HD R clamp01_(R x) { return x < R(0) ? R(0) : (x > R(1) ? R(1) : x); }
+
+// Squared minimum distance between segments [a0, a1] and [b0, b1] (the
+// closest-point construction of Lumelsky's method): the line-line optimum
+// s clamped to [0, 1] (0 for parallel lines), t optimal for that s, and if
+// t leaves [0, 1] it is clamped and s re-optimised for it.
+template <typename R> MPPI_HD R seg_dist2(const R* a0, const R* a1, const R* b0, const R* b1)
+{
+    R da[3], db[3], r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { da[c] = a1[c] - a0[c]; db[c] = b1[c] - b0[c]; r[c] = a0[c] - b0[c]; }
+    const R A = dot3(da, da), B = dot3(da, db), E = dot3(db, db), Cr = dot3(da, r), F = dot3(db, r);
+    R s, t;
+    if (E <= R(0)) {            // b is a point
+        t = R(0);
+        s = A > R(0) ? clamp01_(-Cr / A) : R(0);
+    } else {
+        const R den = A * E - B * B;
+        s = den > R(0) ? clamp01_((B * F - Cr * E) / den) : R(0);
+        t = (B * s + F) / E;
+        if (t < R(0)) {
+            t = R(0);
+            s = A > R(0) ? clamp01_(-Cr / A) : R(0);
+        } else if (t > R(1)) {
+            t = R(1);
+            s = A > R(0) ? clamp01_((B - Cr) / A) : R(0);
+        }
+    }
+    R e[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) e[c] = r[c] + s * da[c] - t * db[c];
+    return dot3(e, e);
+}
+
+// ends of segment `id` (uniform): link id from joint origin P[id] to
+// P[id + 1] (P[NJ] = EE point), else obstacle id - NJ
+template <typename R>
+MPPI_HD void seg_ends(int id, const R (&P)[NJ + 1][3], const CostM<R>& C, R* e0, R* e1)
+{
+    switch (id) {
+#define MPPI_LINK_SEG(i)                                                                    \
+    case i:                                                                                 \
+        for (int c = 0; c < 3; ++c) { e0[c] = P[i][c]; e1[c] = P[i + 1][c]; }              \
+        return;
+        MPPI_LINK_SEG(0) MPPI_LINK_SEG(1) MPPI_LINK_SEG(2) MPPI_LINK_SEG(3)
+        MPPI_LINK_SEG(4) MPPI_LINK_SEG(5) MPPI_LINK_SEG(6)
+#undef MPPI_LINK_SEG
+    default:
+        for (int c = 0; c < 3; ++c) { e0[c] = C.obs[id - NJ][c]; e1[c] = C.obs[id - NJ][3 + c]; }
+    }
+}
+
+// C_collision(q) = w_collision * #{pairs i: d_i < d_th,i}, compared as
+// squared distances
+template <typename R>
+MPPI_HD R collision_cost(const ModelM<R>& M, const CostM<R>& C, const R* q);
+
+// ---------------------------------------------------------------------------
 // cost terms (Eqs. 9-14)
 // ---------------------------------------------------------------------------
+template <typename R>
+MPPI_HD R collision_cost(const ModelM<R>& M, const CostM<R>& C, const R* q)
+{
+    R P[NJ + 1][3], Rn[9];
+    fk_ee(M, q, P[NJ], Rn, &P[0][0], (R*)nullptr);
+    R hits = R(0);
+    const int np = uniform_(C.n_pairs);
+    for (int i = 0; i < np; ++i) {
+        R a0[3], a1[3], b0[3], b1[3];
+        seg_ends(uniform_(C.pa[i]), P, C, a0, a1);
+        seg_ends(uniform_(C.pb[i]), P, C, b0, b1);
+        if (seg_dist2(a0, a1, b0, b1) < C.dth2[i]) hits += R(1);
+    }
+    return C.w_coll * hits;
+}
+
 template <typename R> struct TargetM {
     R p_des[3];
     R RdT[9];     // R_des^T

@@ -28,6 +28,8 @@ template <typename R> MPPI_HD void prep_model(const mppi_robot_params& P, ModelM
     for (int a = 0; a < 3; ++a) { M.ree[a] = R(P.r_ee[a]); M.g[a] = R(P.gravity[a]); }
 }
 
+static_assert(MPPI_MAX_OBSTACLES == 4 && MPPI_MAX_PAIRS == 32, "CostM collision arrays");
+
 template <typename R> inline void prep_cost(const mppi_cost_params& P, CostM<R>& C)
 {
     C.dt = R(P.dt);
@@ -49,6 +51,16 @@ template <typename R> inline void prep_cost(const mppi_cost_params& P, CostM<R>&
     C.force_mode = P.force_mode;
     C.has_ori = ori;
     C.has_force = force;
+    C.w_coll = R(P.w_collision);
+    for (int o = 0; o < 4; ++o)
+        for (int a = 0; a < 6; ++a) C.obs[o][a] = o < P.n_obstacles ? R(P.obstacles[o][a]) : R(0);
+    C.n_pairs = P.n_pairs;
+    for (int i = 0; i < 32; ++i) {
+        const bool on = i < P.n_pairs;
+        C.pa[i] = on ? P.pairs[i][0] : 0;
+        C.pb[i] = on ? P.pairs[i][1] : 0;
+        C.dth2[i] = on ? R(P.d_th[i]) * R(P.d_th[i]) : R(0);
+    }
 }
 
 }  // namespace mppi

@@ -60,6 +60,7 @@ MPPI_HD R rollout_sample(const ModelM<R>& Mc, const CostM<R>& Cc, const TargetM<
         dyn_step<R, FORCE>(M, C, ext, q, qd, tau, v, o);
         R l = motion_cost(M, C, tg, o.pee, o.Rn) + joint_cost(M, C, q, qd) + torque_cost(M, C, v);
         if (FORCE) l += force_cost(C, tg, o.F);
+        if (C.n_pairs > 0) l += collision_cost(M, C, q);   // Eq. 14's C_collision
         S += l;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {

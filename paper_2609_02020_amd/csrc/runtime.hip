@@ -121,6 +121,18 @@ int validate_cost(const mppi_cost_params* c)
         double n = std::sqrt(c->wall_n[0] * c->wall_n[0] + c->wall_n[1] * c->wall_n[1] + c->wall_n[2] * c->wall_n[2]);
         if (std::fabs(n - 1.0) > 1e-6 || c->wall_k < 0 || c->wall_c < 0) return MPPI_EINVAL;
     }
+    // collision term
+    if (!std::isfinite(c->w_collision) || c->w_collision < 0) return MPPI_EINVAL;
+    if (c->n_obstacles < 0 || c->n_obstacles > MPPI_MAX_OBSTACLES) return MPPI_EINVAL;
+    if (c->n_pairs < 0 || c->n_pairs > MPPI_MAX_PAIRS) return MPPI_EINVAL;
+    for (int o = 0; o < c->n_obstacles; ++o)
+        if (!finite_all(c->obstacles[o], 6)) return MPPI_EINVAL;
+    for (int i = 0; i < c->n_pairs; ++i) {
+        const int nseg = MPPI_NJ + c->n_obstacles;
+        if (c->pairs[i][0] < 0 || c->pairs[i][0] >= nseg || c->pairs[i][1] < 0 || c->pairs[i][1] >= nseg)
+            return MPPI_EINVAL;
+        if (!std::isfinite(c->d_th[i]) || c->d_th[i] < 0) return MPPI_EINVAL;
+    }
     return MPPI_OK;
 }
 

@@ -15,6 +15,8 @@ Recipe (all seeds fixed):
     10 N into the wall (F_des = -10 n).
   * initial nominal U_nom[t] = g(q0) for every step (gravity compensation).
   * Philox key = 3000 + case index (single updates) / episode.
+  * collision_k4096: wall_k4096[0..3] with the collision term (see
+    with_collision()).
   * learned_wall.json: the learned-proposal task (see learned_wall()).
 """
 from __future__ import annotations
@@ -131,6 +133,22 @@ def learned_wall(n_train=1000, n_eval=50):
     return {"robot": arm, "cost": cost, "q_base": qb.tolist(), "train": eps[:n_train], "eval": eps[n_train:]}
 
 
+def with_collision(case):
+    """The contact case plus the collision term of Eqs. 14-15: two vertical
+    obstacle segments beside the target point (0.15 m along +x, 0.25 m
+    along -y), the 12 first pairs of non-adjacent links (threshold 0.08 m)
+    and links 3-6 against both obstacles (threshold 0.2 m, the paper's
+    safety distance); w_collision = 3e4 (Table I)."""
+    pe = np.asarray(case["target"]["p_des"])
+    obstacles = [[pe[0] + 0.15, pe[1], pe[2] - 0.3, pe[0] + 0.15, pe[1], pe[2] + 0.3],
+                 [pe[0], pe[1] - 0.25, 0.0, pe[0], pe[1] - 0.25, 1.0]]
+    pairs = [[i, j] for i in range(7) for j in range(i + 2, 7)][:12]
+    pairs += [[i, 7 + o] for o in range(2) for i in (3, 4, 5, 6)]
+    cost = dict(case["cost"], w_collision=3e4, obstacles=obstacles, pairs=pairs,
+                d_th=[0.08] * 12 + [0.2] * 8)
+    return dict(case, cost=cost)
+
+
 def main():
     out = {"recipe": __doc__.strip().splitlines()[0]}
     # single update, position cost, K=256, T=18, dt=0.01, lambda=1 (FP64 case)
@@ -144,6 +162,8 @@ def main():
     Ks, Ts = inputs.draw_horizon(4000, 64)
     out["batch64"] = [make_case(200 + i, "position" if i % 2 == 0 else "wall", Ks[i], Ts[i],
                                 0.01, 1.0, 3200 + i) for i in range(64)]
+    # contact task with the collision term, K=4096, T=18
+    out["collision_k4096"] = [with_collision(c) for c in out["wall_k4096"][:4]]
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "workloads.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=None, separators=(",", ":"))

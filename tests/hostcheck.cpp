@@ -83,3 +83,28 @@ extern "C" void hc_normals(int prec, uint64_t seed, uint64_t tick, uint32_t k, u
         for (int i = 0; i < 8; ++i) z[i] = zz[i];
     }
 }
+
+extern "C" double hc_seg_dist2(int prec, const double* a0, const double* a1, const double* b0, const double* b1)
+{
+    if (prec == MPPI_FP64) return seg_dist2<double>(a0, a1, b0, b1);
+    float f[4][3];
+    for (int c = 0; c < 3; ++c) { f[0][c] = float(a0[c]); f[1][c] = float(a1[c]); f[2][c] = float(b0[c]); f[3][c] = float(b1[c]); }
+    return double(seg_dist2<float>(f[0], f[1], f[2], f[3]));
+}
+
+template <typename R>
+static double collision_t(const mppi_robot_params* rp, const mppi_cost_params* cp, const double* q)
+{
+    ModelM<R> M;
+    CostM<R> C;
+    prep_model(*rp, M);
+    prep_cost(*cp, C);
+    R qq[NJ];
+    for (int j = 0; j < NJ; ++j) qq[j] = R(q[j]);
+    return double(collision_cost(M, C, qq));
+}
+
+extern "C" double hc_collision(const mppi_robot_params* rp, const mppi_cost_params* cp, int prec, const double* q)
+{
+    return prec == MPPI_FP64 ? collision_t<double>(rp, cp, q) : collision_t<float>(rp, cp, q);
+}

@@ -36,6 +36,10 @@ def hc(tmp_path_factory):
                              D, C.c_uint64, C.c_uint64, C.c_uint32, D]
     L.hc_rollout.restype = C.c_double
     L.hc_normals.argtypes = [C.c_int, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, D]
+    L.hc_seg_dist2.argtypes = [C.c_int, D, D, D, D]
+    L.hc_seg_dist2.restype = C.c_double
+    L.hc_collision.argtypes = [C.POINTER(B.RobotParams), C.POINTER(B.CostParams), C.c_int, D]
+    L.hc_collision.restype = C.c_double
     return L
 
 
@@ -121,3 +125,57 @@ def test_rollout_cost_matches_oracle(hc, ora, workloads, which, prec, tol):
                                        case["qd0"], U, case["seed"], 3, k)
             assert abs(S - S_ref) <= tol * abs(S_ref), (S, S_ref)
             assert np.abs(noise - n_ref).max() < (1e-12 if prec == B.FP64 else 1e-4)
+
+
+def _dp(a):
+    return np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(C.POINTER(C.c_double))
+
+
+@pytest.mark.parametrize("prec,tol", [(B.FP64, 1e-12), (B.FP32, 2e-5)])
+def test_segment_distance_matches_oracle(hc, ora, prec, tol):
+    """The kernels' clamped closest-point construction against the oracle's
+    minimisation over the unit square, including parallel, crossing and
+    point-like segments."""
+    rng = np.random.default_rng(2)
+    cases = [rng.normal(size=(4, 3)) for _ in range(400)]
+    a = np.array([0.0, 0, 0])
+    cases += [np.array([a, [1, 0, 0], [0.5, 0.3, 0], [2, 0.3, 0]]),      # parallel overlap
+              np.array([a, [1, 0, 0], [2, 0.3, 0], [3, 0.3, 0]]),        # parallel apart
+              np.array([[-1, 0, 0], [1, 0, 0], [0, -1, 0], [0, 1, 0]]),   # crossing
+              np.array([[0.5, 2, 0], [0.5, 2, 0], a, [1, 0, 0]]),        # a is a point
+              np.array([a, [1, 0, 0], [3, 1, 0], [3, 1, 0]]),            # b is a point
+              np.array([[1, 1, 1]] * 4)]                                   # both points, same
+    for s in cases:
+        ref = ora.segment_distance(*s)
+        got = np.sqrt(hc.hc_seg_dist2(prec, *(_dp(x) for x in s)))
+        assert abs(got - ref) <= tol * max(1.0, ref), (s, got, ref)
+
+
+def collision_cost_dict(case, rng):
+    """Self pairs of non-adjacent links and link-obstacle pairs against two
+    vertical obstacles near the start configuration."""
+    pe = np.asarray(case["target"]["p_des"])
+    obstacles = [[pe[0] + 0.15, pe[1], pe[2] - 0.3, pe[0] + 0.15, pe[1], pe[2] + 0.3],
+                 [pe[0], pe[1] - 0.25, 0.0, pe[0], pe[1] - 0.25, 1.0]]
+    pairs = [[i, j] for i in range(7) for j in range(i + 2, 7)][:12]
+    pairs += [[i, 7 + o] for o in range(2) for i in (3, 4, 5, 6)]
+    d_th = [0.08] * 12 + [0.2] * 8
+    return dict(case["cost"], w_collision=3e4, obstacles=obstacles, pairs=pairs, d_th=d_th)
+
+
+@pytest.mark.parametrize("prec", [B.FP64, B.FP32])
+def test_collision_cost_matches_oracle(hc, ora, workloads, prec):
+    rng = np.random.default_rng(3)
+    compared = 0
+    for case in workloads["wall_k4096"][:5]:
+        cost = collision_cost_dict(case, rng)
+        rp = B.robot_params(case["robot"])
+        cp = B.cost_params(cost, prec)
+        for _ in range(40):
+            q = np.asarray(case["q0"]) + rng.uniform(-0.8, 0.8, 7)
+            ref, margin = ora.collision_cost(case["robot"], cost, q)
+            if margin < (1e-9 if prec == B.FP64 else 1e-4):
+                continue   # an indicator that rounding may flip
+            assert hc.hc_collision(C.byref(rp), C.byref(cp), prec, _dp(q)) == ref
+            compared += 1
+    assert compared > 150
