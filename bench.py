@@ -34,6 +34,8 @@ FLOPS_PER_SAMPLE_TERMINAL = 822
 # Free-space problems (no wall, no force term, no orientation cost).
 FLOPS_PER_SAMPLE_STEP_FREE = 4573
 FLOPS_PER_SAMPLE_TERMINAL_FREE = 704
+# The paper's own dynamics route (M by Eq. 8, Cholesky), contact workload.
+FLOPS_PER_SAMPLE_STEP_EXPLICIT = 6709
 # Eq. 4b: one multiply-add per sample and output row (weighted noise sum).
 FLOPS_PER_SAMPLE_ROW_WEIGHT = 2
 FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (AMD published)
@@ -43,11 +45,11 @@ FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (AMD published)
 # known size (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 on gfx950), taken on the
 # kernel sources whose digest is recorded here; reported as null once the
 # sources differ.
-PROFILED_DIGEST = "c1f5d4ca09295ecc"
-PROFILED_TRAFFIC = {"update_kernel": 680146 + 53782,        # K=4096, T=18 contact workload
-                    "batch_kernel": 6433376 + 6071341,      # 64-problem batch (W=2 x 1024; the
+PROFILED_DIGEST = "d3f7e19c3d74f1b6"
+PROFILED_TRAFFIC = {"update_kernel": 685620 + 54145,        # K=4096, T=18 contact workload
+                    "batch_kernel": 6592875 + 6081307,      # 64-problem batch (W=2 x 1024; the
                                                             # fastest shapes differ by < 1 %)
-                    "mlp_train": 15934703 + 3988256}        # forward/backward + weight gradients, 512 rows
+                    "mlp_train": 15934686 + 3988256}        # forward/backward + weight gradients, 512 rows
 
 
 def kernel_source_digest():
@@ -190,6 +192,39 @@ def collision_bench(B, case, torch, dev, steps=100):
                         "(w_collision = %g), K=%d, T=%d" % (len(case["cost"]["obstacles"]), len(case["cost"]["pairs"]),
                                                           case["cost"]["w_collision"], K, T),
             "update_kernel_ms": ms, "update_hz_kernel_only": 1e3 / ms, "rollout_steps_per_s": K * T / (ms * 1e-3)}
+
+
+def explicit_bench(B, case, torch, dev, steps=100):
+    """The contact workload on both dynamics routes (articulated-body vs M
+    by Eq. 8 with a Cholesky solve): update-kernel time with HIP events."""
+    import numpy as np
+    f64 = dict(dtype=torch.float64, device=dev)
+    K, T = case["cost"]["K"], case["cost"]["T"]
+    res = {}
+    for name, dyn in (("aba", B.DYN_ABA), ("explicit_m", B.DYN_EXPLICIT_M)):
+        solver = B.Solver(case["robot"], dict(case["cost"], dynamics=dyn), B.FP32)
+        io = {"q": torch.tensor(case["q0"], **f64), "qd": torch.tensor(case["qd0"], **f64),
+              "target": torch.tensor(B.target_vector(case["target"]), **f64),
+              "U_nominal": torch.tensor(case["U_nom"], **f64), "U_new": torch.empty((T, 7), **f64),
+              "U_shift": torch.empty((T, 7), **f64), "costs": torch.empty(K, dtype=torch.float32, device=dev),
+              "status": torch.zeros(1, dtype=torch.int32, device=dev), "seed": case["seed"], "tick": 0}
+        stream = torch.cuda.current_stream()
+        for i in range(10):
+            io["tick"] = i
+            solver.update_async(io, stream)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(evs):
+            io["tick"] = 10 + i
+            a.record(stream)
+            solver.update_async(io, stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        res[name + "_kernel_ms"] = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        solver.close()
+    res["flops_per_sample_step"] = {"aba": FLOPS_PER_SAMPLE_STEP, "explicit_m": FLOPS_PER_SAMPLE_STEP_EXPLICIT}
+    res["workload"] = "wall_k4096[0], K=%d, T=%d, FP32" % (K, T)
+    return res
 
 
 def has_force(cost):
@@ -357,6 +392,7 @@ def main():
     if not args.no_mlp:
         out["mlp"] = mlp_bench(B, inputs, case["robot"], torch, dev)
     out["collision"] = collision_bench(B, inputs.load()["collision_k4096"][0], torch, dev)
+    out["dynamics_routes"] = explicit_bench(B, case, torch, dev)
     if args.copy_probe > 0:
         src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

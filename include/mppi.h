@@ -50,6 +50,10 @@ typedef enum {
 } mppi_status;
 
 typedef enum { MPPI_FP32 = 0, MPPI_FP64 = 1 } mppi_precision;
+/* Forward dynamics of the rollouts: the articulated-body algorithm
+ * (default), or the paper's own route, M formed by the Jacobian sum of
+ * Eq. 8 and h from the Jacobian time derivatives, solved by Cholesky. */
+typedef enum { MPPI_DYN_ABA = 0, MPPI_DYN_EXPLICIT_M = 1 } mppi_dynamics;
 typedef enum { MPPI_EXT_NONE = 0, MPPI_EXT_CONST = 1, MPPI_EXT_WALL = 2 } mppi_ext_mode;
 
 /* One link of the serial chain (Fig. 1 caption: joint transforms and CoM
@@ -113,6 +117,8 @@ typedef struct {
     int n_pairs;             /* 0 .. MPPI_MAX_PAIRS; 0 disables the term */
     int pairs[MPPI_MAX_PAIRS][2];             /* segment ids, < 7 + n_obstacles */
     double d_th[MPPI_MAX_PAIRS];              /* thresholds [m], >= 0 */
+    int dynamics;            /* mppi_dynamics (single-problem solvers; batches
+                                and the nominal selection use MPPI_DYN_ABA) */
 } mppi_cost_params;
 
 typedef struct {

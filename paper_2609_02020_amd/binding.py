@@ -42,6 +42,7 @@ class RobotParams(C.Structure):
 
 
 MAX_OBSTACLES, MAX_PAIRS = 4, 32
+DYN_ABA, DYN_EXPLICIT_M = 0, 1
 
 
 class CostParams(C.Structure):
@@ -58,7 +59,8 @@ class CostParams(C.Structure):
                 ("precision", C.c_int), ("lambda_fp64_threshold", C.c_double),
                 ("w_collision", C.c_double), ("n_obstacles", C.c_int),
                 ("obstacles", (C.c_double * 6) * MAX_OBSTACLES), ("n_pairs", C.c_int),
-                ("pairs", (C.c_int * 2) * MAX_PAIRS), ("d_th", C.c_double * MAX_PAIRS)]
+                ("pairs", (C.c_int * 2) * MAX_PAIRS), ("d_th", C.c_double * MAX_PAIRS),
+                ("dynamics", C.c_int)]
 
 
 class Target(C.Structure):
@@ -127,6 +129,7 @@ def cost_params(cost: dict, precision: int = FP32, lambda_fp64_threshold: float 
     for i, (a, b) in enumerate(pairs):
         cp.pairs[i][0], cp.pairs[i][1] = int(a), int(b)
         cp.d_th[i] = float(cost["d_th"][i])
+    cp.dynamics = int(cost.get("dynamics", DYN_ABA))
     return cp
 
 

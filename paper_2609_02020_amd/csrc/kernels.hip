@@ -48,7 +48,7 @@ __global__ void prep_model_kernel(const mppi_robot_params* __restrict__ P, Model
 // rollouts (costs and global noise only).
 constexpr int kMaxDynLds = 48 * 1024;
 
-template <typename R, typename A, bool FORCE>
+template <typename R, typename A, bool FORCE, bool EXPLICIT, bool COLL>
 __global__ __launch_bounds__(kRolloutBlock) void update_kernel(
     const ModelM<R>* __restrict__ Mp, const CostM<R>* __restrict__ Cp, const double* __restrict__ q0,
     const double* __restrict__ qd0, const double* __restrict__ target, const double* U_nom,
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kRolloutBlock) void update_kernel(
         for (int j = 0; j < NJ; ++j) { q[j] = R(q0[j]); qd[j] = R(qd0[j]); te[j] = R(0); }
         if (C.ext_mode == EXTW_CONST) const_ext_torque(M, C, q, te);
         if (k < K) {
-            R v = rollout_sample<R, FORCE>(M, C, tg, q, qd, te, Us, T, seed, tick, (uint32_t)k,
+            R v = rollout_sample<R, FORCE, EXPLICIT, COLL>(M, C, tg, q, qd, te, Us, T, seed, tick, (uint32_t)k,
                                            noise ? noise + k : nullptr, (size_t)K,
                                            lds_noise ? tile + lane : nullptr, kLdsRowPad);
             s = finite_(v) ? v : R(INFINITY);
@@ -124,7 +124,7 @@ struct BatchProblem {
     const CostM<float>* cost;
     const ModelM<double>* model64;   // the FP64 plant
     const CostM<double>* cost64;
-    int K, T, force, acc64;
+    int K, T, force, acc64, coll;
     double lambda;
     int ntiles;
     int pad;
@@ -133,7 +133,9 @@ struct BatchProblem {
     long long part_off;   // into the partials buffer, in doubles
 };
 
-template <int W>
+// COLL: some problem of the batch has the collision term (the collision
+// rollout variants are compiled in only then)
+template <int W, bool COLL>
 __global__ __launch_bounds__(64 * W) void batch_kernel(
     const BatchProblem* __restrict__ probs, const int2* __restrict__ items, int nitems,
     unsigned int* queue, unsigned int* done, unsigned int* counters, const double* __restrict__ q,
@@ -179,10 +181,17 @@ __global__ __launch_bounds__(64 * W) void batch_kernel(
             }
             if (C.ext_mode == EXTW_CONST) const_ext_torque(M, C, q0, te);
             if (k < K) {
-                float v = Pb.force ? rollout_sample<float, true>(M, C, tg, q0, qd0, te, Us[wid], T, seed, tick,
-                                                                 (uint32_t)k, (float*)nullptr, 0)
-                                   : rollout_sample<float, false>(M, C, tg, q0, qd0, te, Us[wid], T, seed, tick,
-                                                                  (uint32_t)k, (float*)nullptr, 0);
+                float v;
+                if (COLL && Pb.coll)
+                    v = Pb.force ? rollout_sample<float, true, false, true>(M, C, tg, q0, qd0, te, Us[wid], T, seed,
+                                                                            tick, (uint32_t)k, (float*)nullptr, 0)
+                                 : rollout_sample<float, false, false, true>(M, C, tg, q0, qd0, te, Us[wid], T, seed,
+                                                                             tick, (uint32_t)k, (float*)nullptr, 0);
+                else
+                    v = Pb.force ? rollout_sample<float, true>(M, C, tg, q0, qd0, te, Us[wid], T, seed, tick,
+                                                               (uint32_t)k, (float*)nullptr, 0)
+                                 : rollout_sample<float, false>(M, C, tg, q0, qd0, te, Us[wid], T, seed, tick,
+                                                                (uint32_t)k, (float*)nullptr, 0);
                 s = finite_(v) ? v : INFINITY;
                 if (costs) costs[Pb.k_off + k] = s;
             }
@@ -355,7 +364,7 @@ __global__ void batch_plant_kernel(const BatchProblem* __restrict__ probs, int n
 // nominal, lane 1: the candidate; the sampling scale is zeroed in the LDS
 // copy of the cost, so v_t = u_t exactly); the candidate replaces the
 // nominal only when it costs less.
-template <typename R, bool FORCE>
+template <typename R, bool FORCE, bool COLL>
 __device__ void select_two(const ModelM<R>& Mg, const CostM<R>& Cg, const double* q0, const double* qd0,
                            const double* target, double* U_nom, const double* U_cand, int T, double* costs,
                            ModelM<R>& Msh, CostM<R>& Csh, R* Us, R* sc)
@@ -377,7 +386,7 @@ __device__ void select_two(const ModelM<R>& Mg, const CostM<R>& Cg, const double
 #pragma unroll
         for (int j = 0; j < NJ; ++j) { q[j] = R(q0[j]); qd[j] = R(qd0[j]); te[j] = R(0); }
         if (Csh.ext_mode == EXTW_CONST) const_ext_torque(Msh, Csh, q, te);
-        const R v = rollout_sample<R, FORCE>(Msh, Csh, tg, q, qd, te, Us + lane * kMaxT * NJ, T, 0ull, 0u, 0u,
+        const R v = rollout_sample<R, FORCE, false, COLL>(Msh, Csh, tg, q, qd, te, Us + lane * kMaxT * NJ, T, 0ull, 0u, 0u,
                                              (R*)nullptr, 0);
         sc[lane] = finite_(v) ? v : R(INFINITY);
     }
@@ -388,7 +397,7 @@ __device__ void select_two(const ModelM<R>& Mg, const CostM<R>& Cg, const double
     if (costs && lane < 2) costs[lane] = double(sc[lane]);
 }
 
-template <typename R, bool FORCE>
+template <typename R, bool FORCE, bool COLL>
 __global__ __launch_bounds__(64) void select_kernel(const ModelM<R>* __restrict__ Mp, const CostM<R>* __restrict__ Cp,
                                                     const double* q0, const double* qd0, const double* target,
                                                     double* U_nom, const double* U_cand, int T, double* costs)
@@ -397,7 +406,7 @@ __global__ __launch_bounds__(64) void select_kernel(const ModelM<R>* __restrict_
     __shared__ CostM<R> Csh;
     __shared__ R Us[2 * kMaxT * NJ];
     __shared__ R sc[2];
-    select_two<R, FORCE>(*Mp, *Cp, q0, qd0, target, U_nom, U_cand, T, costs, Msh, Csh, Us, sc);
+    select_two<R, FORCE, COLL>(*Mp, *Cp, q0, qd0, target, U_nom, U_cand, T, costs, Msh, Csh, Us, sc);
 }
 
 __global__ __launch_bounds__(64) void batch_select_kernel(const BatchProblem* __restrict__ probs, int n,
@@ -412,12 +421,18 @@ __global__ __launch_bounds__(64) void batch_select_kernel(const BatchProblem* __
     if (p >= n) return;
     const BatchProblem& Pb = probs[p];
     double* c = costs ? costs + 2 * p : nullptr;
-    if (Pb.force)
-        select_two<float, true>(*Pb.model, *Pb.cost, q + p * NJ, qd + p * NJ, target + (size_t)p * 13,
-                                U_nom + Pb.u_off, U_cand + Pb.u_off, Pb.T, c, Msh, Csh, Us, sc);
-    else
-        select_two<float, false>(*Pb.model, *Pb.cost, q + p * NJ, qd + p * NJ, target + (size_t)p * 13,
-                                 U_nom + Pb.u_off, U_cand + Pb.u_off, Pb.T, c, Msh, Csh, Us, sc);
+    const double* qp = q + p * NJ;
+    const double* qdp = qd + p * NJ;
+    const double* tp = target + (size_t)p * 13;
+    double* un = U_nom + Pb.u_off;
+    const double* uc = U_cand + Pb.u_off;
+    if (Pb.coll) {
+        if (Pb.force) select_two<float, true, true>(*Pb.model, *Pb.cost, qp, qdp, tp, un, uc, Pb.T, c, Msh, Csh, Us, sc);
+        else select_two<float, false, true>(*Pb.model, *Pb.cost, qp, qdp, tp, un, uc, Pb.T, c, Msh, Csh, Us, sc);
+    } else {
+        if (Pb.force) select_two<float, true, false>(*Pb.model, *Pb.cost, qp, qdp, tp, un, uc, Pb.T, c, Msh, Csh, Us, sc);
+        else select_two<float, false, false>(*Pb.model, *Pb.cost, qp, qdp, tp, un, uc, Pb.T, c, Msh, Csh, Us, sc);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -430,7 +445,8 @@ hipError_t launch_prep_model(const mppi_robot_params* d_raw, ModelM<float>* d_mf
     return hipGetLastError();
 }
 
-template <typename R, typename A, bool FORCE> static hipError_t update_t(const UpdateArgs& a, hipStream_t s)
+template <typename R, typename A, bool FORCE, bool EXPLICIT, bool COLL>
+static hipError_t update_t(const UpdateArgs& a, hipStream_t s)
 {
     dim3 grid((a.K + kRolloutBlock - 1) / kRolloutBlock);
     const size_t rows = (size_t)a.T * NJ;
@@ -441,20 +457,34 @@ template <typename R, typename A, bool FORCE> static hipError_t update_t(const U
     // the caller asked for it
     R* noise = (R*)a.noise;
     if (a.merge && !a.want_noise) noise = nullptr;
-    hipLaunchKernelGGL((update_kernel<R, A, FORCE>), grid, dim3(kRolloutBlock), dyn, s,
+    hipLaunchKernelGGL((update_kernel<R, A, FORCE, EXPLICIT, COLL>), grid, dim3(kRolloutBlock), dyn, s,
                        (const ModelM<R>*)a.model, (const CostM<R>*)a.cost, a.q0, a.qd0, a.target, a.U_nom,
                        a.seed, (uint32_t)a.tick, a.K, a.T, a.lambda, noise, (R*)a.costs, a.merge, lds_noise,
                        (A*)a.parts, a.counter, a.U_new, a.U_shift, a.status);
     return hipGetLastError();
 }
 
+template <bool EXPLICIT, bool COLL>
+static hipError_t update_dispatch(int precision, bool acc64, bool force, const UpdateArgs& a, hipStream_t s)
+{
+    if (precision == MPPI_FP64)
+        return force ? update_t<double, double, true, EXPLICIT, COLL>(a, s)
+                     : update_t<double, double, false, EXPLICIT, COLL>(a, s);
+    if (acc64)
+        return force ? update_t<float, double, true, EXPLICIT, COLL>(a, s)
+                     : update_t<float, double, false, EXPLICIT, COLL>(a, s);
+    return force ? update_t<float, float, true, EXPLICIT, COLL>(a, s) : update_t<float, float, false, EXPLICIT, COLL>(a, s);
+}
+
 hipError_t launch_update(int precision, bool acc64, bool force, const UpdateArgs& a, hipStream_t s)
 {
     if (a.T < 1 || a.T > kMaxT || a.K < 1) return hipErrorInvalidValue;
-    if (precision == MPPI_FP64)
-        return force ? update_t<double, double, true>(a, s) : update_t<double, double, false>(a, s);
-    if (acc64) return force ? update_t<float, double, true>(a, s) : update_t<float, double, false>(a, s);
-    return force ? update_t<float, float, true>(a, s) : update_t<float, float, false>(a, s);
+    const bool ex = a.dynamics == MPPI_DYN_EXPLICIT_M;
+    if (a.collision)
+        return ex ? update_dispatch<true, true>(precision, acc64, force, a, s)
+                  : update_dispatch<false, true>(precision, acc64, force, a, s);
+    return ex ? update_dispatch<true, false>(precision, acc64, force, a, s)
+              : update_dispatch<false, false>(precision, acc64, force, a, s);
 }
 
 size_t update_parts_bytes(int K, int T)
@@ -477,9 +507,9 @@ hipError_t launch_weights(int precision, bool acc64, const WeightsArgs& a, hipSt
     return acc64 ? weights_t<float, double>(a, s) : weights_t<float, float>(a, s);
 }
 
-template <int W> static hipError_t batch_t(const BatchArgs& a, int groups, hipStream_t s)
+template <int W, bool COLL> static hipError_t batch_t(const BatchArgs& a, int groups, hipStream_t s)
 {
-    hipLaunchKernelGGL((batch_kernel<W>), dim3(groups), dim3(64 * W), 0, s, (const BatchProblem*)a.probs,
+    hipLaunchKernelGGL((batch_kernel<W, COLL>), dim3(groups), dim3(64 * W), 0, s, (const BatchProblem*)a.probs,
                        (const int2*)a.items, a.nitems, a.queue, a.done, a.counters, a.q, a.qd, a.target, a.U_nom,
                        a.U_new, a.U_shift, a.costs, a.status, a.seeds, a.tick, a.parts);
     return hipGetLastError();
@@ -489,9 +519,9 @@ hipError_t launch_batch(const BatchArgs& a, int waves_per_group, int groups, hip
 {
     if (groups < 1 || a.nitems < 1) return hipErrorInvalidValue;
     switch (waves_per_group) {
-    case 1: return batch_t<1>(a, groups, s);
-    case 2: return batch_t<2>(a, groups, s);
-    case 4: return batch_t<4>(a, groups, s);
+    case 1: return a.collision ? batch_t<1, true>(a, groups, s) : batch_t<1, false>(a, groups, s);
+    case 2: return a.collision ? batch_t<2, true>(a, groups, s) : batch_t<2, false>(a, groups, s);
+    case 4: return a.collision ? batch_t<4, true>(a, groups, s) : batch_t<4, false>(a, groups, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -511,7 +541,7 @@ hipError_t launch_set_tick(uint64_t* tick, uint64_t v, hipStream_t s)
 size_t batch_problem_bytes() { return sizeof(BatchProblem); }
 
 void fill_batch_problem(void* dst, const void* model, const void* cost, const void* model64, const void* cost64,
-                        int K, int T, int force, int acc64, double lambda, int ntiles, long long u_off,
+                        int K, int T, int force, int acc64, int coll, double lambda, int ntiles, long long u_off,
                         long long k_off, long long part_off)
 {
     BatchProblem p;
@@ -519,7 +549,7 @@ void fill_batch_problem(void* dst, const void* model, const void* cost, const vo
     p.cost = (const CostM<float>*)cost;
     p.model64 = (const ModelM<double>*)model64;
     p.cost64 = (const CostM<double>*)cost64;
-    p.K = K; p.T = T; p.force = force; p.acc64 = acc64;
+    p.K = K; p.T = T; p.force = force; p.acc64 = acc64; p.coll = coll;
     p.lambda = lambda; p.ntiles = ntiles; p.pad = 0;
     p.u_off = u_off; p.k_off = k_off; p.part_off = part_off;
     memcpy(dst, &p, sizeof p);
@@ -540,17 +570,19 @@ hipError_t launch_batch_plant(const void* probs, int n, double* q, double* qd, c
     return hipGetLastError();
 }
 
-hipError_t launch_select(int precision, bool force, const void* model, const void* cost, const double* q0,
-                         const double* qd0, const double* target, double* U_nom, const double* U_cand, int T,
-                         double* costs, hipStream_t s)
+hipError_t launch_select(int precision, bool force, bool coll, const void* model, const void* cost,
+                         const double* q0, const double* qd0, const double* target, double* U_nom,
+                         const double* U_cand, int T, double* costs, hipStream_t s)
 {
     if (T < 1 || T > kMaxT) return hipErrorInvalidValue;
     if (precision == MPPI_FP64) {
-        auto k = force ? select_kernel<double, true> : select_kernel<double, false>;
+        auto k = coll ? (force ? select_kernel<double, true, true> : select_kernel<double, false, true>)
+                      : (force ? select_kernel<double, true, false> : select_kernel<double, false, false>);
         hipLaunchKernelGGL(k, dim3(1), dim3(64), 0, s, (const ModelM<double>*)model, (const CostM<double>*)cost, q0,
                            qd0, target, U_nom, U_cand, T, costs);
     } else {
-        auto k = force ? select_kernel<float, true> : select_kernel<float, false>;
+        auto k = coll ? (force ? select_kernel<float, true, true> : select_kernel<float, false, true>)
+                      : (force ? select_kernel<float, true, false> : select_kernel<float, false, false>);
         hipLaunchKernelGGL(k, dim3(1), dim3(64), 0, s, (const ModelM<float>*)model, (const CostM<float>*)cost, q0,
                            qd0, target, U_nom, U_cand, T, costs);
     }

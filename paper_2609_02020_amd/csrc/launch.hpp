@@ -39,6 +39,8 @@ struct UpdateArgs {
     double* U_new;
     double* U_shift;
     int* status;
+    int dynamics;           // mppi_dynamics
+    int collision;          // the collision term is on (n_pairs > 0)
 };
 
 // One fused launch: rollouts, per-wave Eq. 4 partials, last-block merge.
@@ -63,6 +65,7 @@ struct BatchArgs {
     const uint64_t* seeds;  // [n]
     const uint64_t* tick;   // [1] (device)
     double* parts;          // partials, sized by the host
+    int collision;          // some problem has the collision term
 };
 
 // Persistent batched update: `groups` workgroups of `waves_per_group` waves.
@@ -71,16 +74,16 @@ hipError_t launch_advance_tick(uint64_t* tick, hipStream_t s);
 hipError_t launch_set_tick(uint64_t* tick, uint64_t v, hipStream_t s);
 size_t batch_problem_bytes();
 void fill_batch_problem(void* dst, const void* model, const void* cost, const void* model64, const void* cost64,
-                        int K, int T, int force, int acc64, double lambda, int ntiles, long long u_off,
+                        int K, int T, int force, int acc64, int coll, double lambda, int ntiles, long long u_off,
                         long long k_off, long long part_off);
 hipError_t launch_batch_plant(const void* probs, int n, double* q, double* qd, const double* U_new, double dt,
                               int substeps, hipStream_t s);
 hipError_t launch_batch_select(const void* probs, int n, const double* q, const double* qd, const double* target,
                                double* U_nom, const double* U_cand, double* costs, hipStream_t s);
 // model/cost: ModelM<R>/CostM<R> of the rollout precision
-hipError_t launch_select(int precision, bool force, const void* model, const void* cost, const double* q0,
-                         const double* qd0, const double* target, double* U_nom, const double* U_cand, int T,
-                         double* costs, hipStream_t s);
+hipError_t launch_select(int precision, bool force, bool coll, const void* model, const void* cost,
+                         const double* q0, const double* qd0, const double* target, double* U_nom,
+                         const double* U_cand, int T, double* costs, hipStream_t s);
 
 hipError_t launch_prep_model(const mppi_robot_params* d_raw, ModelM<float>* d_mf, ModelM<double>* d_md,
                              hipStream_t s);

@@ -11,6 +11,7 @@
 #pragma once
 
 #include "dyn.hpp"
+#include "dyn_m.hpp"
 
 namespace mppi {
 
@@ -33,7 +34,11 @@ template <typename T> MPPI_HD const T* per_step(const T* p)
 
 // noise_out / noise_lds (either may be null) receive du[t][j] at
 // (t*7 + j) * stride.
-template <typename R, bool FORCE, typename UT>
+// EXPLICIT selects the paper's own dynamics route (dyn_m.hpp: M by Eq. 8,
+// Cholesky solve) instead of the articulated-body step; COLL adds the
+// collision term (a compile-time switch: its code in the step loop slows
+// the rollouts that do not use it).
+template <typename R, bool FORCE, bool EXPLICIT = false, bool COLL = false, typename UT>
 MPPI_HD R rollout_sample(const ModelM<R>& Mc, const CostM<R>& Cc, const TargetM<R>& tg,
                          const R* q0, const R* qd0, const R* tau_ext_c, const UT* U_nom, int T,
                          uint64_t seed, uint32_t tick, uint32_t k, R* noise_out, size_t noise_stride,
@@ -57,10 +62,11 @@ MPPI_HD R rollout_sample(const ModelM<R>& Mc, const CostM<R>& Cc, const TargetM<
             tau[j] = v[j] + tau_ext_c[j];
         }
         StepOut<R> o;
-        dyn_step<R, FORCE>(M, C, ext, q, qd, tau, v, o);
+        if constexpr (EXPLICIT) dyn_step_m<R, FORCE>(M, C, ext, q, qd, tau, v, o);
+        else dyn_step<R, FORCE>(M, C, ext, q, qd, tau, v, o);
         R l = motion_cost(M, C, tg, o.pee, o.Rn) + joint_cost(M, C, q, qd) + torque_cost(M, C, v);
         if (FORCE) l += force_cost(C, tg, o.F);
-        if (C.n_pairs > 0) l += collision_cost(M, C, q);   // Eq. 14's C_collision
+        if constexpr (COLL) l += collision_cost(M, C, q);   // Eq. 14's C_collision
         S += l;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {

@@ -121,6 +121,7 @@ int validate_cost(const mppi_cost_params* c)
         double n = std::sqrt(c->wall_n[0] * c->wall_n[0] + c->wall_n[1] * c->wall_n[1] + c->wall_n[2] * c->wall_n[2]);
         if (std::fabs(n - 1.0) > 1e-6 || c->wall_k < 0 || c->wall_c < 0) return MPPI_EINVAL;
     }
+    if (c->dynamics != MPPI_DYN_ABA && c->dynamics != MPPI_DYN_EXPLICIT_M) return MPPI_EINVAL;
     // collision term
     if (!std::isfinite(c->w_collision) || c->w_collision < 0) return MPPI_EINVAL;
     if (c->n_obstacles < 0 || c->n_obstacles > MPPI_MAX_OBSTACLES) return MPPI_EINVAL;
@@ -203,6 +204,8 @@ int update_enqueue(mppi_solver* h, const mppi_device_io* io, hipStream_t s, void
     a.U_new = io->U_new;
     a.U_shift = io->U_shift;
     a.status = io->status;
+    a.dynamics = h->cost.dynamics;
+    a.collision = h->cost.n_pairs > 0 ? 1 : 0;
     return launch_update(h->cost.precision, acc64_of(h->cost), has_force(h->cost), a, s) == hipSuccess
                ? MPPI_OK
                : MPPI_EDEVICE;
@@ -386,7 +389,8 @@ int mppi_select_nominal_async(mppi_handle_t h, const mppi_device_io* io, const d
 {
     if (check_io(h, io, false) || !U_candidate) return MPPI_EINVAL;
     const bool fp64 = h->cost.precision == MPPI_FP64;
-    return launch_select(h->cost.precision, has_force(h->cost), fp64 ? (const void*)h->d_md : (const void*)h->d_mf,
+    return launch_select(h->cost.precision, has_force(h->cost), h->cost.n_pairs > 0,
+                         fp64 ? (const void*)h->d_md : (const void*)h->d_mf,
                          fp64 ? (const void*)h->d_cd : (const void*)h->d_cf, io->q, io->qd, io->target,
                          const_cast<double*>(io->U_nominal), U_candidate, h->cost.T, costs,
                          (hipStream_t)stream) == hipSuccess
@@ -435,6 +439,7 @@ struct mppi_batch {
     double* d_parts = nullptr;
     uint64_t* d_tick = nullptr;   // [0]: graph replays (advanced by the graph), [1]: eager launches
     int wpg = 1, groups = 1024;
+    int collision = 0;            // some problem has the collision term
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
 };
@@ -479,6 +484,7 @@ BatchArgs batch_args(mppi_batch* b, const mppi_batch_io* io, const uint64_t* tic
     a.seeds = io->seed;
     a.tick = tick_slot;
     a.parts = b->d_parts;
+    a.collision = b->collision;
     return a;
 }
 
@@ -502,7 +508,9 @@ int mppi_batch_create(const mppi_problem_desc* descs, int n, mppi_batch_t* out)
         int st = validate_robot(descs[p].robot);
         if (!st) st = validate_cost(descs[p].cost);
         if (st) return st;
-        if (descs[p].cost->precision != MPPI_FP32 || descs[p].cost->T > kMaxTBatch) return MPPI_ENOTSUP;
+        if (descs[p].cost->precision != MPPI_FP32 || descs[p].cost->T > kMaxTBatch ||
+            descs[p].cost->dynamics != MPPI_DYN_ABA)
+            return MPPI_ENOTSUP;
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MPPI_EDEVICE;
@@ -519,6 +527,7 @@ int mppi_batch_create(const mppi_problem_desc* descs, int n, mppi_batch_t* out)
     for (int p = 0; p < n; ++p) {
         b->robot[p] = *descs[p].robot;
         b->cost[p] = *descs[p].cost;
+        if (b->cost[p].n_pairs > 0) b->collision = 1;
         const int K = b->cost[p].K, T = b->cost[p].T;
         b->u_off[p] = b->u_total;
         b->k_off[p] = b->k_total;
@@ -558,7 +567,8 @@ int mppi_batch_create(const mppi_problem_desc* descs, int n, mppi_batch_t* out)
         prep_cost(b->cost[p], cd[p]);
         const mppi_cost_params& c = b->cost[p];
         fill_batch_problem(probs.data() + batch_problem_bytes() * p, b->d_mf + p, b->d_cf + p, b->d_md + p,
-                           b->d_cd + p, c.K, c.T, has_force(c) ? 1 : 0, acc64_of(c) ? 1 : 0, c.lambda, ntiles[p],
+                           b->d_cd + p, c.K, c.T, has_force(c) ? 1 : 0, acc64_of(c) ? 1 : 0, c.n_pairs > 0 ? 1 : 0,
+                           c.lambda, ntiles[p],
                            (long long)b->u_off[p], (long long)b->k_off[p], part_off[p]);
     }
     ok = hipMemcpy(b->d_raw, b->robot.data(), sizeof(mppi_robot_params) * n, hipMemcpyHostToDevice) == hipSuccess &&

@@ -12,7 +12,7 @@
 
 using namespace mppi;
 
-template <typename R>
+template <typename R, bool EXPLICIT = false>
 static void step_t(const mppi_robot_params* rp, const mppi_cost_params* cp, int force, int ext,
                    const double* q, const double* qd, const double* tau, const double* v,
                    double* qdd, double* pee, double* Rn, double* F)
@@ -24,8 +24,13 @@ static void step_t(const mppi_robot_params* rp, const mppi_cost_params* cp, int 
     R qq[NJ], qqd[NJ], tt[NJ], vv[NJ];
     for (int j = 0; j < NJ; ++j) { qq[j] = R(q[j]); qqd[j] = R(qd[j]); tt[j] = R(tau[j]); vv[j] = R(v[j]); }
     StepOut<R> o;
-    if (force) dyn_step<R, true>(M, C, ext, qq, qqd, tt, vv, o);
-    else dyn_step<R, false>(M, C, ext, qq, qqd, tt, vv, o);
+    if (EXPLICIT) {
+        if (force) dyn_step_m<R, true>(M, C, ext, qq, qqd, tt, vv, o);
+        else dyn_step_m<R, false>(M, C, ext, qq, qqd, tt, vv, o);
+    } else {
+        if (force) dyn_step<R, true>(M, C, ext, qq, qqd, tt, vv, o);
+        else dyn_step<R, false>(M, C, ext, qq, qqd, tt, vv, o);
+    }
     for (int j = 0; j < NJ; ++j) qdd[j] = double(o.qdd[j]);
     for (int a = 0; a < 3; ++a) pee[a] = double(o.pee[a]);
     for (int a = 0; a < 9; ++a) Rn[a] = double(o.Rn[a]);
@@ -36,8 +41,14 @@ extern "C" void hc_step(const mppi_robot_params* rp, const mppi_cost_params* cp,
                         int ext, const double* q, const double* qd, const double* tau,
                         const double* v, double* qdd, double* pee, double* Rn, double* F)
 {
-    if (prec == MPPI_FP64) step_t<double>(rp, cp, force, ext, q, qd, tau, v, qdd, pee, Rn, F);
-    else step_t<float>(rp, cp, force, ext, q, qd, tau, v, qdd, pee, Rn, F);
+    const bool ex = cp->dynamics == MPPI_DYN_EXPLICIT_M;
+    if (prec == MPPI_FP64) {
+        if (ex) step_t<double, true>(rp, cp, force, ext, q, qd, tau, v, qdd, pee, Rn, F);
+        else step_t<double>(rp, cp, force, ext, q, qd, tau, v, qdd, pee, Rn, F);
+    } else {
+        if (ex) step_t<float, true>(rp, cp, force, ext, q, qd, tau, v, qdd, pee, Rn, F);
+        else step_t<float>(rp, cp, force, ext, q, qd, tau, v, qdd, pee, Rn, F);
+    }
 }
 
 template <typename R>
@@ -55,9 +66,19 @@ static double rollout_t(const mppi_robot_params* rp, const mppi_cost_params* cp,
     for (int j = 0; j < NJ; ++j) { q[j] = R(q0[j]); qd[j] = R(qd0[j]); }
     if (C.ext_mode == EXTW_CONST) const_ext_torque(M, C, q, te);
     R nz[256 * NJ];
-    R S = C.has_force
-              ? rollout_sample<R, true>(M, C, tg, q, qd, te, U, cp->T, seed, (uint32_t)tick, k, nz, 1)
-              : rollout_sample<R, false>(M, C, tg, q, qd, te, U, cp->T, seed, (uint32_t)tick, k, nz, 1);
+    const bool ex = cp->dynamics == MPPI_DYN_EXPLICIT_M, co = cp->n_pairs > 0;
+    const uint32_t tk = (uint32_t)tick;
+    R S;
+    if (co)
+        S = C.has_force ? (ex ? rollout_sample<R, true, true, true>(M, C, tg, q, qd, te, U, cp->T, seed, tk, k, nz, 1)
+                              : rollout_sample<R, true, false, true>(M, C, tg, q, qd, te, U, cp->T, seed, tk, k, nz, 1))
+                        : (ex ? rollout_sample<R, false, true, true>(M, C, tg, q, qd, te, U, cp->T, seed, tk, k, nz, 1)
+                              : rollout_sample<R, false, false, true>(M, C, tg, q, qd, te, U, cp->T, seed, tk, k, nz, 1));
+    else
+        S = C.has_force ? (ex ? rollout_sample<R, true, true>(M, C, tg, q, qd, te, U, cp->T, seed, tk, k, nz, 1)
+                              : rollout_sample<R, true>(M, C, tg, q, qd, te, U, cp->T, seed, tk, k, nz, 1))
+                        : (ex ? rollout_sample<R, false, true>(M, C, tg, q, qd, te, U, cp->T, seed, tk, k, nz, 1)
+                              : rollout_sample<R, false>(M, C, tg, q, qd, te, U, cp->T, seed, tk, k, nz, 1));
     for (int i = 0; i < cp->T * NJ; ++i) noise[i] = double(nz[i]);
     return double(S);
 }

@@ -77,8 +77,19 @@ extern "C" void oc_rollout(const mppi_robot_params* rp, const mppi_cost_params* 
     for (int j = 0; j < NJ; ++j) { q[j] = Flop(q0[j]); qd[j] = Flop(qd0[j]); te[j] = Flop(0.0); }
     Flop nz[256 * NJ];
     g_counts = Counts();
-    if (C.has_force) rollout_sample<Flop, true>(M, C, tg, q, qd, te, U, T, 1, 0, 0, nz, 1);
-    else rollout_sample<Flop, false>(M, C, tg, q, qd, te, U, T, 1, 0, 0, nz, 1);
+    const bool ex = cp->dynamics == MPPI_DYN_EXPLICIT_M;
+    // (the collision term is counted only when enabled; its per-pair work
+    // depends on the clamping branch taken)
+    if (cp->n_pairs > 0) {
+        if (C.has_force) rollout_sample<Flop, true, false, true>(M, C, tg, q, qd, te, U, T, 1, 0, 0, nz, 1);
+        else rollout_sample<Flop, false, false, true>(M, C, tg, q, qd, te, U, T, 1, 0, 0, nz, 1);
+    } else if (C.has_force) {
+        if (ex) rollout_sample<Flop, true, true>(M, C, tg, q, qd, te, U, T, 1, 0, 0, nz, 1);
+        else rollout_sample<Flop, true>(M, C, tg, q, qd, te, U, T, 1, 0, 0, nz, 1);
+    } else {
+        if (ex) rollout_sample<Flop, false, true>(M, C, tg, q, qd, te, U, T, 1, 0, 0, nz, 1);
+        else rollout_sample<Flop, false>(M, C, tg, q, qd, te, U, T, 1, 0, 0, nz, 1);
+    }
     counts[0] = g_counts.add; counts[1] = g_counts.mul; counts[2] = g_counts.div;
     counts[3] = g_counts.sqrt; counts[4] = g_counts.trans; counts[5] = g_counts.cmp;
 }

@@ -179,3 +179,52 @@ def test_collision_cost_matches_oracle(hc, ora, workloads, prec):
             assert hc.hc_collision(C.byref(rp), C.byref(cp), prec, _dp(q)) == ref
             compared += 1
     assert compared > 150
+
+
+@pytest.mark.parametrize("prec,tol", [(B.FP64, 1e-10), (B.FP32, 2e-4)])
+def test_explicit_m_step_matches_oracle(hc, ora, workloads, prec, tol):
+    """The paper's route (M by Eq. 8, Cholesky) against the oracle's forward
+    dynamics, with and without the wall, and its force estimate."""
+    rng = np.random.default_rng(21)
+    for case in workloads["wall_k4096"][:5]:
+        rb = case["robot"]
+        q = np.array(case["q0"]) + rng.uniform(-0.5, 0.5, 7)
+        qd = rng.uniform(-2, 2, 7)
+        v = rng.uniform(-15, 15, 7)
+        _, _, pe, _ = ora.fk(rb, q)
+        cost = dict(case["cost"], dynamics=B.DYN_EXPLICIT_M,
+                    wall_d0=float(np.dot(case["cost"]["wall_n"], pe)) + 0.01)
+        case2 = dict(case, cost=cost)
+        # free motion
+        qdd, pee, Rn, _ = step(hc, case2, prec, 0, 0, q, qd, v, v)
+        ref = ora.forward_dynamics(rb, q, qd, v)
+        assert np.abs(qdd - ref).max() < tol * (np.abs(ref).max() + 1)
+        assert np.abs(pee - pe).max() < tol
+        # wall contact + force estimate
+        qdd, _, _, F = step(hc, case2, prec, 1, 2, q, qd, v, v)
+        J = ora.ee_jacobian(rb, q)
+        fw = np.concatenate([ora.wall_force(cost, pe, J[:3] @ qd), np.zeros(3)])
+        assert np.linalg.norm(fw) > 1.0
+        ref = ora.forward_dynamics(rb, q, qd, v, fw)
+        assert np.abs(qdd - ref).max() < tol * (np.abs(ref).max() + 1)
+        g = ora.bias_jacobian(rb, q, np.zeros(7))
+        Fref = ora.force_estimate(rb, q, v - g)
+        assert np.abs(F - Fref).max() < tol * (np.abs(Fref).max() + 1) * 10
+
+
+def test_explicit_m_rollout_matches_oracle(hc, ora, workloads):
+    """Whole FP64 rollouts of the contact workload on the explicit route."""
+    D = C.POINTER(C.c_double)
+    for case in workloads["wall_k4096"][:3]:
+        cost = dict(case["cost"], dynamics=B.DYN_EXPLICIT_M)
+        rp, cp = B.robot_params(case["robot"]), B.cost_params(cost, B.FP64)
+        tgt = B.target_vector(case["target"])
+        U = np.ascontiguousarray(case["U_nom"], dtype=np.float64)
+        noise = np.zeros(18 * 7)
+        for k in (0, 5, 77):
+            S = hc.hc_rollout(C.byref(rp), C.byref(cp), B.FP64, tgt.ctypes.data_as(D),
+                              _dp(case["q0"]), _dp(case["qd0"]), U.ctypes.data_as(D), case["seed"], 2, k,
+                              noise.ctypes.data_as(D))
+            ref, _ = ora.rollout(case["robot"], case["cost"], case["target"], case["q0"], case["qd0"],
+                                 case["U_nom"], case["seed"], 2, k)
+            assert abs(S - ref) <= 1e-9 * abs(ref)

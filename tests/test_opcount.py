@@ -70,3 +70,11 @@ def test_mlp_flop_constants():
     weights = sum(shape[0] * shape[1] for _, shape, _ in om.layer_slices())
     assert bench.MLP_FWD_FLOPS_PER_ROW == 2 * weights
     assert bench.MLP_TRAIN_FLOPS_PER_ROW == 4 * weights + 2 * (weights - 21 * 256)
+
+
+def test_bench_flop_constant_explicit_route(oc, workloads):
+    """The paper's dynamics route (M by Eq. 8, Cholesky) on the contact
+    workload."""
+    for case in workloads["wall_k4096"][:3]:
+        c = dict(case, cost=dict(case["cost"], dynamics=B.DYN_EXPLICIT_M))
+        assert per_step(oc, c) == (bench.FLOPS_PER_SAMPLE_STEP_EXPLICIT, bench.FLOPS_PER_SAMPLE_TERMINAL)
