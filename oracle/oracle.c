@@ -955,11 +955,15 @@ double ora_rollout_margin(const ora_robot* rb, const ora_cost* cp,
         for (int j = 0; j < n; ++j)
             for (int r = 0; r < 6; ++r) tau_ext_const[j] += J[r * n + j] * cp->F_ext[r];
     }
+    double du_prev[N] = {0};
+    const double rho = cp->noise_rho, rho_c = sqrt(1.0 - cp->noise_rho * cp->noise_rho);
     for (int t = 0; t < cp->T; ++t) {
         double z[8], v[N], rhs[N], qdd[N];
         ora_normals(seed, tick, k, (uint32_t)t, z);
         for (int j = 0; j < n; ++j) {
-            double du = cp->sigma[j] * z[j];
+            /* Eq. 2's perturbation; correlated in time when rho > 0 */
+            double du = t == 0 ? cp->sigma[j] * z[j] : rho * du_prev[j] + rho_c * cp->sigma[j] * z[j];
+            du_prev[j] = du;
             if (noise) noise[t * n + j] = du;
             v[j] = U_nom[t * n + j] + du;
         }
@@ -1048,15 +1052,29 @@ int ora_update(const ora_robot* rb, const ora_cost* cp, const ora_target* tg,
         if (ownE) free(E);
         return ORA_EINVAL;
     }
+    int iters = cp->iterations > 1 ? cp->iterations : 1;
+    double* Ucur = (double*)malloc(sizeof(double) * per);
+    if (!Ucur) {
+        if (ownS) free(S);
+        if (ownE) free(E);
+        return ORA_EINVAL;
+    }
+    memcpy(Ucur, U_nom, sizeof(double) * per);
+    int st = ORA_OK;
+    for (int it = 0; it < iters; ++it) {
+        uint64_t tk = tick * (uint64_t)iters + (uint64_t)it;
 #ifdef _OPENMP
-    int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+        int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 8) num_threads(nt)
 #endif
-    for (int k = 0; k < K; ++k)
-        S[k] = ora_rollout(rb, cp, tg, q0, qd0, U_nom, seed, tick,
-                           (uint32_t)k, E + per * (size_t)k);
+        for (int k = 0; k < K; ++k)
+            S[k] = ora_rollout(rb, cp, tg, q0, qd0, Ucur, seed, tk,
+                               (uint32_t)k, E + per * (size_t)k);
+        st = ora_weights_update(K, T, n, cp->lambda, S, E, Ucur, U_new, NULL);
+        memcpy(Ucur, U_new, sizeof(double) * per);
+    }
     (void)nthreads;
-    int st = ora_weights_update(K, T, n, cp->lambda, S, E, U_nom, U_new, NULL);
+    free(Ucur);
     if (ownS) free(S);
     if (ownE) free(E);
     return st;

@@ -77,6 +77,12 @@ typedef struct {
     int n_pairs;                           /* 0..ORA_MAXPAIRS */
     int pairs[ORA_MAXPAIRS][2];            /* segment ids */
     double d_th[ORA_MAXPAIRS];             /* thresholds [m] */
+    /* sampling variants: du_t = rho du_{t-1} + sqrt(1 - rho^2) sigma z_t
+       (du_0 = sigma z_0; rho = 0 is the i.i.d. noise of Eq. 2), and
+       `iterations` MPPI updates per call, each from the previous U_new,
+       iteration i using the Philox tick iterations * tick + i */
+    double noise_rho;                      /* 0 <= rho < 1 */
+    int iterations;                        /* <= 1: one update */
 } ora_cost;
 
 typedef struct {

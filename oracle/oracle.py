@@ -67,7 +67,8 @@ class Cost(C.Structure):
                 ("wall_c", C.c_double), ("w_collision", C.c_double),
                 ("n_obstacles", C.c_int), ("obstacles", (C.c_double * 6) * MAXOBS),
                 ("n_pairs", C.c_int), ("pairs", (C.c_int * 2) * MAXPAIRS),
-                ("d_th", C.c_double * MAXPAIRS)]
+                ("d_th", C.c_double * MAXPAIRS),
+                ("noise_rho", C.c_double), ("iterations", C.c_int)]
 
 
 class Target(C.Structure):
@@ -190,6 +191,8 @@ def cost_struct(cost: dict) -> Cost:
     for i, (a, b) in enumerate(pairs):
         c.pairs[i][0], c.pairs[i][1] = int(a), int(b)
         c.d_th[i] = float(cost["d_th"][i])
+    c.noise_rho = float(cost.get("noise_rho", 0.0))
+    c.iterations = int(cost.get("iterations", 1))
     return c
 
 
