@@ -227,6 +227,39 @@ def explicit_bench(B, case, torch, dev, steps=100):
     return res
 
 
+def sampling_bench(B, case, torch, dev, steps=100):
+    """The contact workload with the sampling variants: independent draws,
+    perturbations correlated in time (rho = 0.8) and three MPPI iterations
+    per update (three fused launches): GPU time per update with HIP events."""
+    import numpy as np
+    f64 = dict(dtype=torch.float64, device=dev)
+    K, T = case["cost"]["K"], case["cost"]["T"]
+    res = {}
+    for name, kw in (("iid", {}), ("ar1_rho0.8", {"noise_rho": 0.8}), ("iterations3", {"iterations": 3})):
+        solver = B.Solver(case["robot"], dict(case["cost"], **kw), B.FP32)
+        io = {"q": torch.tensor(case["q0"], **f64), "qd": torch.tensor(case["qd0"], **f64),
+              "target": torch.tensor(B.target_vector(case["target"]), **f64),
+              "U_nominal": torch.tensor(case["U_nom"], **f64), "U_new": torch.empty((T, 7), **f64),
+              "U_shift": torch.empty((T, 7), **f64), "costs": torch.empty(K, dtype=torch.float32, device=dev),
+              "status": torch.zeros(1, dtype=torch.int32, device=dev), "seed": case["seed"], "tick": 0}
+        stream = torch.cuda.current_stream()
+        for i in range(10):
+            io["tick"] = i
+            solver.update_async(io, stream)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(evs):
+            io["tick"] = 10 + i
+            a.record(stream)
+            solver.update_async(io, stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        res[name + "_update_ms"] = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        solver.close()
+    res["workload"] = "wall_k4096[0], K=%d, T=%d, FP32" % (K, T)
+    return res
+
+
 def has_force(cost):
     return any(w != 0 for w in cost["W_force"]) or any(w != 0 for w in cost["W_reg"])
 
@@ -393,6 +426,7 @@ def main():
         out["mlp"] = mlp_bench(B, inputs, case["robot"], torch, dev)
     out["collision"] = collision_bench(B, inputs.load()["collision_k4096"][0], torch, dev)
     out["dynamics_routes"] = explicit_bench(B, case, torch, dev)
+    out["sampling_variants"] = sampling_bench(B, case, torch, dev)
     if args.copy_probe > 0:
         src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

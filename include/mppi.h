@@ -39,6 +39,7 @@ extern "C" {
 #define MPPI_NJ 7 /* joints supported by the kernels */
 #define MPPI_MAX_OBSTACLES 4
 #define MPPI_MAX_PAIRS 32
+#define MPPI_MAX_ITERATIONS 64
 
 typedef enum {
     MPPI_OK = 0,
@@ -119,6 +120,20 @@ typedef struct {
     double d_th[MPPI_MAX_PAIRS];              /* thresholds [m], >= 0 */
     int dynamics;            /* mppi_dynamics (single-problem solvers; batches
                                 and the nominal selection use MPPI_DYN_ABA) */
+    /* Sampling variants (the paper defers its sampling strategy to a cited
+     * work, end of Sec. III-B; these are two common choices).  noise_rho in [0, 1): the
+     * perturbation of Eq. 2 becomes an AR(1) process in time,
+     * du_0 = sigma z_0, du_t = rho du_{t-1} + sqrt(1 - rho^2) sigma z_t, with
+     * the marginal variance sigma^2 at every step (0: independent draws).
+     * iterations in 0 .. MPPI_MAX_ITERATIONS (0 and 1: one update): an update
+     * runs that many MPPI iterations on the same state, each from the
+     * previous one's U_new, iteration i drawing its noise with the Philox
+     * tick word iterations * tick + i; costs, noise and status are the last
+     * iteration's.  Batches and the stage-isolated calls
+     * (mppi_rollout_async, mppi_weights_async) take one iteration only
+     * (MPPI_ENOTSUP otherwise). */
+    double noise_rho;
+    int iterations;
 } mppi_cost_params;
 
 typedef struct {
@@ -211,7 +226,8 @@ typedef struct {
 /* Creates a batch of n >= 1 problems.  Copies every struct; validates each
  * problem as mppi_create does; builds the work list (64-sample tiles,
  * longest horizon first) and the device tables.  Errors: MPPI_EINVAL,
- * MPPI_ENOTSUP (FP64 or T > 64), MPPI_ENOMEM, MPPI_EDEVICE. */
+ * MPPI_ENOTSUP (FP64, T > 64, the explicit-M dynamics or more than one
+ * iteration per update), MPPI_ENOMEM, MPPI_EDEVICE. */
 int mppi_batch_create(const mppi_problem_desc* descs, int n, mppi_batch_t* out);
 int mppi_batch_destroy(mppi_batch_t b);
 

@@ -411,7 +411,8 @@ def weights_update(S, noise, U_nom, lam):
 
 def update(robot, cost, target, q0, qd0, U_nom, seed, tick, nthreads=0,
            want_noise=True):
-    """One full MPPI update.  Returns (status, U_new[T,n], costs[K], noise[K,T,n])."""
+    """One MPPI update (cost["iterations"] chained iterations, one if absent).
+    Returns (status, U_new[T,n], costs[K], noise[K,T,n]) of the last iteration."""
     rb, c, tg = robot_struct(robot), cost_struct(cost), target_struct(target)
     K, T, n = c.K, c.T, rb.n
     U = _vec(U_nom, T * n)

@@ -60,7 +60,7 @@ class CostParams(C.Structure):
                 ("w_collision", C.c_double), ("n_obstacles", C.c_int),
                 ("obstacles", (C.c_double * 6) * MAX_OBSTACLES), ("n_pairs", C.c_int),
                 ("pairs", (C.c_int * 2) * MAX_PAIRS), ("d_th", C.c_double * MAX_PAIRS),
-                ("dynamics", C.c_int)]
+                ("dynamics", C.c_int), ("noise_rho", C.c_double), ("iterations", C.c_int)]
 
 
 class Target(C.Structure):
@@ -130,6 +130,8 @@ def cost_params(cost: dict, precision: int = FP32, lambda_fp64_threshold: float 
         cp.pairs[i][0], cp.pairs[i][1] = int(a), int(b)
         cp.d_th[i] = float(cost["d_th"][i])
     cp.dynamics = int(cost.get("dynamics", DYN_ABA))
+    cp.noise_rho = float(cost.get("noise_rho", 0.0))
+    cp.iterations = int(cost.get("iterations", 1))
     return cp
 
 

@@ -152,6 +152,10 @@ enum { EXTW_NONE = 0, EXTW_CONST = 1, EXTW_WALL = 2 };
 template <typename R> struct CostM {
     R dt;
     R sigma[NJ];
+    // time correlation of the perturbation: du_t = rho du_{t-1} + sig_c z_t
+    // for t >= 1 with sig_c = sqrt(1 - rho^2) sigma (rho = 0: i.i.d.)
+    R rho;
+    R sig_c[NJ];
     R W_pos[3], W_ori[3], W_force[6], W_reg[6];
     R w_q, w_qd, w_tau, w_post;
     R q_rest[NJ];

@@ -361,7 +361,7 @@ __global__ void batch_plant_kernel(const BatchProblem* __restrict__ probs, int n
 }
 
 // Noise-free costs of two sequences from one state (lane 0: the current
-// nominal, lane 1: the candidate; the sampling scale is zeroed in the LDS
+// nominal, lane 1: the candidate; the sampling scales are zeroed in the LDS
 // copy of the cost, so v_t = u_t exactly); the candidate replaces the
 // nominal only when it costs less.
 template <typename R, bool FORCE, bool COLL>
@@ -377,7 +377,7 @@ __device__ void select_two(const ModelM<R>& Mg, const CostM<R>& Cg, const double
         Us[kMaxT * NJ + i] = R(U_cand[i]);
     }
     wave_sync();
-    if (lane < NJ) Csh.sigma[lane] = R(0);
+    if (lane < NJ) Csh.sigma[lane] = Csh.sig_c[lane] = R(0);
     wave_sync();
     if (lane < 2) {
         TargetM<R> tg;

@@ -4,6 +4,8 @@
 // cost).
 #pragma once
 
+#include <cmath>
+
 #include "dyn.hpp"
 #include "mppi.h"
 
@@ -35,6 +37,9 @@ template <typename R> inline void prep_cost(const mppi_cost_params& P, CostM<R>&
     C.dt = R(P.dt);
     int ori = 0, force = 0;
     for (int j = 0; j < NJ; ++j) { C.sigma[j] = R(P.sigma[j]); C.q_rest[j] = R(P.q_rest[j]); }
+    C.rho = R(P.noise_rho);
+    const double rc = std::sqrt(1.0 - P.noise_rho * P.noise_rho);
+    for (int j = 0; j < NJ; ++j) C.sig_c[j] = R(rc * P.sigma[j]);
     for (int a = 0; a < 3; ++a) {
         C.W_pos[a] = R(P.W_pos[a]); C.W_ori[a] = R(P.W_ori[a]);
         C.wall_n[a] = R(P.wall_n[a]);

@@ -28,6 +28,7 @@ struct mppi_solver {
     void* d_parts = nullptr;     // per-wave Eq. 4 partials (FP64-sized)
     unsigned int* d_counter = nullptr;  // last-block counter of the fused update
     int* d_status = nullptr;
+    double* d_iter = nullptr;    // [2][T][7]: U of the intermediate iterations
     double* d_io = nullptr;      // q 7 | qd 7 | target 13 | U_nom T*7 | U_new T*7
     double* h_io = nullptr;      // pinned mirror of d_io
     void* h_costs = nullptr;     // pinned R [K]
@@ -134,8 +135,12 @@ int validate_cost(const mppi_cost_params* c)
             return MPPI_EINVAL;
         if (!std::isfinite(c->d_th[i]) || c->d_th[i] < 0) return MPPI_EINVAL;
     }
+    if (!(c->noise_rho >= 0.0 && c->noise_rho < 1.0)) return MPPI_EINVAL;
+    if (c->iterations < 0 || c->iterations > MPPI_MAX_ITERATIONS) return MPPI_EINVAL;
     return MPPI_OK;
 }
+
+int iterations_of(const mppi_cost_params& c) { return c.iterations > 1 ? c.iterations : 1; }
 
 bool has_force(const mppi_cost_params& c)
 {
@@ -168,6 +173,7 @@ void release(mppi_solver* h)
     (void)hipFree(h->d_parts);
     (void)hipFree(h->d_counter);
     (void)hipFree(h->d_status);
+    (void)hipFree(h->d_iter);
     (void)hipFree(h->d_io);
     (void)hipHostFree(h->h_io);
     (void)hipHostFree(h->h_costs);
@@ -178,9 +184,8 @@ void release(mppi_solver* h)
 
 bool acc64_of(const mppi_cost_params& c) { return c.precision == MPPI_FP64 || c.lambda < c.lambda_fp64_threshold; }
 
-// merge = false: rollouts only (costs, noise); merge = true: the full update.
-int update_enqueue(mppi_solver* h, const mppi_device_io* io, hipStream_t s, void* noise, void* costs, bool merge,
-                   bool want_noise)
+int update_enqueue_one(mppi_solver* h, const mppi_device_io* io, hipStream_t s, void* noise, void* costs,
+                       bool merge, bool want_noise)
 {
     UpdateArgs a;
     a.want_noise = want_noise ? 1 : 0;
@@ -209,6 +214,33 @@ int update_enqueue(mppi_solver* h, const mppi_device_io* io, hipStream_t s, void
     return launch_update(h->cost.precision, acc64_of(h->cost), has_force(h->cost), a, s) == hipSuccess
                ? MPPI_OK
                : MPPI_EDEVICE;
+}
+
+// merge = false: rollouts only (costs, noise); merge = true: the full update,
+// one fused launch per MPPI iteration.  Iteration i of n reads the previous
+// iteration's U_new (io->U_nominal for the first), writes it to one of the
+// two intermediate buffers (io->U_new and io->U_shift for the last) and
+// draws with the Philox tick word n * tick + i; the global noise, when
+// asked for, is the last iteration's.
+int update_enqueue(mppi_solver* h, const mppi_device_io* io, hipStream_t s, void* noise, void* costs, bool merge,
+                   bool want_noise)
+{
+    const int n = iterations_of(h->cost);
+    if (n > 1 && !merge) return MPPI_ENOTSUP;
+    const size_t TJ = (size_t)h->cost.T * MPPI_NJ;
+    for (int i = 0; i < n; ++i) {
+        mppi_device_io it = *io;
+        const bool last = i == n - 1;
+        it.U_nominal = i == 0 ? io->U_nominal : h->d_iter + ((i - 1) & 1) * TJ;
+        if (!last) {
+            it.U_new = h->d_iter + (i & 1) * TJ;
+            it.U_shift = nullptr;
+        }
+        it.tick = io->tick * (uint64_t)n + (uint64_t)i;
+        const int st = update_enqueue_one(h, &it, s, noise, costs, merge, want_noise && last);
+        if (st) return st;
+    }
+    return MPPI_OK;
 }
 
 int weights_enqueue(mppi_solver* h, const mppi_device_io* io, hipStream_t s, const void* noise,
@@ -265,6 +297,7 @@ int mppi_create(const mppi_robot_params* robot, const mppi_cost_params* cost, mp
               hipMalloc(&h->d_parts, update_parts_bytes((int)K, (int)T)) == hipSuccess &&
               hipMalloc(&h->d_counter, sizeof(unsigned int)) == hipSuccess &&
               hipMalloc(&h->d_status, sizeof(int)) == hipSuccess &&
+              hipMalloc(&h->d_iter, 2 * T * MPPI_NJ * sizeof(double)) == hipSuccess &&
               hipMalloc(&h->d_io, io_n * sizeof(double)) == hipSuccess &&
               hipHostMalloc(&h->h_io, io_n * sizeof(double), hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(&h->h_costs, K * rs, hipHostMallocDefault) == hipSuccess &&
@@ -314,6 +347,7 @@ int mppi_weights_async(mppi_handle_t h, const mppi_device_io* io, void* stream)
 {
     int st = check_io(h, io, true);
     if (st) return st;
+    if (iterations_of(h->cost) > 1) return MPPI_ENOTSUP;
     return weights_enqueue(h, io, (hipStream_t)stream, io->noise ? io->noise : h->d_noise,
                            io->costs ? io->costs : h->d_costs);
 }
@@ -509,7 +543,7 @@ int mppi_batch_create(const mppi_problem_desc* descs, int n, mppi_batch_t* out)
         if (!st) st = validate_cost(descs[p].cost);
         if (st) return st;
         if (descs[p].cost->precision != MPPI_FP32 || descs[p].cost->T > kMaxTBatch ||
-            descs[p].cost->dynamics != MPPI_DYN_ABA)
+            descs[p].cost->dynamics != MPPI_DYN_ABA || iterations_of(*descs[p].cost) > 1)
             return MPPI_ENOTSUP;
     }
     int ndev = 0;

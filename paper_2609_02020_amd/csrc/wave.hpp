@@ -78,14 +78,17 @@ __device__ void wave_partial(R s_lane, int lane, int T, double lambda, const R* 
         }
     } else {
         // 9 steps (63 rows) at a time: lane stages du[t][j] in column `lane`,
-        // then lane r sums w_i du_i over row r
+        // then lane r sums w_i du_i over row r; du carries the time
+        // recursion of correlated noise across the blocks
+        R du[NJ];
         for (int t0 = 0; t0 < T; t0 += 9) {
             const int nt = min(9, T - t0);
             for (int tt = 0; tt < nt; ++tt) {
                 R z[8];
                 normals8<R>(seed, tick, k, (uint32_t)(t0 + tt), z);
+                noise_step(C, z, du, t0 + tt);
 #pragma unroll
-                for (int j = 0; j < NJ; ++j) tr[(tt * NJ + j) * kLdsRowPad + lane] = C.sigma[j] * z[j];
+                for (int j = 0; j < NJ; ++j) tr[(tt * NJ + j) * kLdsRowPad + lane] = du[j];
             }
             wave_sync();
             const int nr = nt * NJ;

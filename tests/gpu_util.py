@@ -76,10 +76,10 @@ def force_condition(ora, case, seed, tick, k):
     rb, cost = case["robot"], case["cost"]
     q, qd = np.array(case["q0"], float), np.array(case["qd0"], float)
     U = np.asarray(case["U_nom"], float)
-    sig = np.asarray(cost["sigma"], float)
+    _, E = ora.rollout(rb, cost, case["target"], case["q0"], case["qd0"], U, seed, tick, k)
     worst = 1.0
     for t in range(cost["T"]):
-        v = U[t] + sig * ora.normals(seed, tick, k, t)[:7]
+        v = U[t] + E[t]
         J = ora.ee_jacobian(rb, q)
         M = ora.mass_jacobian_sum(rb, q)
         worst = max(worst, np.linalg.cond(J @ np.linalg.solve(M, J.T)))

@@ -1,0 +1,179 @@
+"""GPU parity of the sampling variants: perturbations correlated in time
+(AR(1), noise_rho) and several MPPI iterations per update (iterations),
+against the oracle under the usual criteria (per-sample costs 1e-4
+relative in FP32, 1e-9 in FP64; U_new 1e-3 N m)."""
+import numpy as np
+import pytest
+
+from paper_2609_02020_amd import binding as B
+from gpu_util import U_ATOL, check_costs_fp32, check_update, cost_rel_err, device_update, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def with_cost(case, **kw):
+    return dict(case, cost=dict(case["cost"], **kw))
+
+
+def long_horizon(case, T):
+    U = np.asarray(case["U_nom"])
+    U = np.concatenate([U] * (T // len(U) + 1))[:T]
+    return dict(case, U_nom=U.tolist(), cost=dict(case["cost"], T=T))
+
+
+def check_costs(ora, case, out, S_ref, precision, seed, tick, label):
+    if precision == B.FP64:
+        assert cost_rel_err(out["costs"], S_ref).max() <= 1e-9, label
+    else:
+        check_costs_fp32(ora, case, out["costs"], S_ref, seed, tick, label)
+
+
+@pytest.mark.parametrize("precision", [B.FP32, B.FP64])
+@pytest.mark.parametrize("rho", [0.6, 0.95])
+def test_correlated_noise_update_parity(ora, workloads, precision, rho):
+    """Contact workload (T = 18: the weighting reads the noise from LDS in
+    FP32 and regenerates it in FP64)."""
+    for i, base in enumerate(workloads["wall_k4096"][:2]):
+        case = with_cost(base, noise_rho=rho)
+        seed, tick, label = case["seed"], 11, "wall %d rho %g prec %d" % (i, rho, precision)
+        print(label, flush=True)
+        solver = B.Solver(case["robot"], case["cost"], precision)
+        out = device_update(solver, case, seed, tick, precision)
+        solver.close()
+        st, U_ref, S_ref, E_ref = ora.update(case["robot"], case["cost"], case["target"], case["q0"], case["qd0"],
+                                             case["U_nom"], seed, tick)
+        assert st == 0 and out["status"] == B.OK
+        assert np.abs(out["noise"] - E_ref).max() <= (1e-12 if precision == B.FP64 else 1e-4) * max(case["cost"]["sigma"])
+        check_costs(ora, case, out, S_ref, precision, seed, tick, label)
+        note = check_update(ora, case, out, case["cost"]["lambda"], S_ref, U_ref, label)
+        if note:
+            print(note)
+
+
+def test_correlated_noise_regenerated_for_the_weighting(ora, workloads):
+    """FP32 at T = 36: the noise tile does not fit in LDS, so the weighting
+    regenerates the correlated noise from the Philox counters; the
+    stage-isolated criterion checks it against the noise the rollouts wrote."""
+    base = long_horizon(workloads["single_k256"][3], 36)
+    case = with_cost(base, K=2048, noise_rho=0.8)
+    seed, tick = case["seed"], 2
+    solver = B.Solver(case["robot"], case["cost"], B.FP32)
+    out = device_update(solver, case, seed, tick, B.FP32)
+    solver.close()
+    st, U_ref, S_ref, E_ref = ora.update(case["robot"], case["cost"], case["target"], case["q0"], case["qd0"],
+                                         case["U_nom"], seed, tick)
+    assert st == 0 and out["status"] == B.OK
+    assert np.abs(out["noise"] - E_ref).max() <= 1e-4 * max(case["cost"]["sigma"])
+    check_costs(ora, case, out, S_ref, B.FP32, seed, tick, "T36")
+    note = check_update(ora, case, out, case["cost"]["lambda"], S_ref, U_ref, "T36")
+    if note:
+        print(note)
+
+
+@pytest.mark.parametrize("precision", [B.FP32, B.FP64])
+@pytest.mark.parametrize("which,n,rho", [("single_k256", 3, 0.0), ("wall_k4096", 4, 0.0), ("wall_k4096", 2, 0.8)])
+def test_iterations_update_parity(ora, workloads, precision, which, n, rho):
+    """An n-iteration update equals n single updates chained on the GPU with
+    the Philox ticks n*tick + i (bitwise: the same launches); each of those
+    meets the single-update criteria against the oracle from the same input
+    sequence; and where the cost errors cannot move the weights (FP64) the
+    result matches the oracle's own n-iteration update end to end."""
+    for c, base in enumerate(workloads[which][:2]):
+        case = with_cost(base, iterations=n, noise_rho=rho)
+        one = dict(case["cost"], iterations=1)
+        seed, tick, label = case["seed"], 5, "%s %d: %d iterations, rho %g, prec %d" % (which, c, n, rho, precision)
+        print(label, flush=True)
+        solver = B.Solver(case["robot"], case["cost"], precision)
+        fused = device_update(solver, case, seed, tick, precision)
+        solver.close()
+        assert fused["status"] == B.OK
+        solver = B.Solver(case["robot"], one, precision)
+        U, e2e = np.asarray(case["U_nom"], float), True
+        for i in range(n):
+            ci = dict(case, cost=one, U_nom=U.tolist())
+            o = device_update(solver, ci, seed, n * tick + i, precision)
+            st, U_ref, S_ref, E_ref = ora.update(case["robot"], one, case["target"], case["q0"], case["qd0"], U,
+                                                 seed, n * tick + i)
+            assert st == 0 and o["status"] == B.OK
+            assert np.abs(o["noise"] - E_ref).max() <= (1e-12 if precision == B.FP64 else 1e-4) * max(one["sigma"])
+            check_costs(ora, ci, o, S_ref, precision, seed, n * tick + i, "%s, iteration %d" % (label, i))
+            note = check_update(ora, ci, o, one["lambda"], S_ref, U_ref, "%s, iteration %d" % (label, i))
+            if note:
+                print(note)
+                e2e = False
+            U = o["U_new"]
+        solver.close()
+        for key in ("U_new", "U_shift", "costs", "noise"):
+            assert np.array_equal(fused[key], o[key]), key
+        st, U_all, _, _ = ora.update(case["robot"], case["cost"], case["target"], case["q0"], case["qd0"],
+                                     case["U_nom"], seed, tick, want_noise=False)
+        if e2e:
+            assert np.abs(fused["U_new"] - U_all).max() <= U_ATOL, label
+        # the iterations move the sequence well beyond what one update does
+        _, U1, _, _ = ora.update(case["robot"], one, case["target"], case["q0"], case["qd0"], case["U_nom"], seed,
+                                 tick, want_noise=False)
+        assert np.abs(U_all - U1).max() > 10 * U_ATOL
+
+
+def test_one_iteration_is_the_plain_update(workloads):
+    torch, dev = torch_dev()
+    case = workloads["wall_k4096"][3]
+    outs = []
+    for it in (0, 1):
+        c = with_cost(case, iterations=it)
+        solver = B.Solver(c["robot"], c["cost"], B.FP32)
+        outs.append(device_update(solver, c, c["seed"], 9, B.FP32))
+        solver.close()
+    for key in ("U_new", "U_shift", "costs", "noise"):
+        assert np.array_equal(outs[0][key], outs[1][key]), key
+
+
+def test_multi_iteration_limits(workloads):
+    """Stage-isolated calls and batches take one iteration; a batch takes the
+    correlated noise."""
+    torch, dev = torch_dev()
+    case = with_cost(workloads["wall_k4096"][0], iterations=2)
+    solver = B.Solver(case["robot"], case["cost"], B.FP32)
+    with pytest.raises(B.MppiError) as e:
+        device_update(solver, case, 1, 1, B.FP32, stage=True)
+    assert e.value.status == B.ENOTSUP
+    f64 = dict(dtype=torch.float64, device=dev)
+    io = {"q": torch.tensor(case["q0"], **f64), "qd": torch.tensor(case["qd0"], **f64),
+          "target": torch.tensor(B.target_vector(case["target"]), **f64),
+          "U_nominal": torch.tensor(case["U_nom"], **f64), "seed": 1, "tick": 1}
+    with pytest.raises(B.MppiError) as e:
+        solver.rollout_async(io)
+    assert e.value.status == B.ENOTSUP
+    solver.close()
+    with pytest.raises(B.MppiError) as e:
+        B.Batch([(case["robot"], case["cost"])])
+    assert e.value.status == B.ENOTSUP
+
+
+def test_correlated_noise_in_a_batch_equals_single_problem(workloads):
+    torch, dev = torch_dev()
+    cases = [with_cost(c, K=1024 + 448 * j, noise_rho=0.3 * j)
+             for j, c in enumerate(workloads["wall_k4096"][4:7] + workloads["single_k256"][:1])]
+    batch = B.Batch([(c["robot"], c["cost"]) for c in cases])
+    f64 = dict(dtype=torch.float64, device=dev)
+    U = np.concatenate([np.asarray(c["U_nom"]) for c in cases])
+    io = {"q": torch.tensor(np.array([c["q0"] for c in cases]), **f64),
+          "qd": torch.tensor(np.array([c["qd0"] for c in cases]), **f64),
+          "target": torch.tensor(np.array([B.target_vector(c["target"]) for c in cases]), **f64),
+          "U_nominal": torch.tensor(U, **f64), "U_new": torch.zeros(U.shape, **f64),
+          "costs": torch.zeros(batch.k_total, dtype=torch.float32, device=dev),
+          "status": torch.full((len(cases),), -1, dtype=torch.int32, device=dev),
+          "seed": torch.tensor([c["seed"] for c in cases], dtype=torch.int64, device=dev)}
+    batch.update_async(io, tick=6)
+    torch.cuda.synchronize()
+    for p, c in enumerate(cases):
+        solver = B.Solver(c["robot"], c["cost"], B.FP32)
+        out = device_update(solver, c, c["seed"], 6, B.FP32)
+        solver.close()
+        k0, K = batch.k_off[p], batch.K[p]
+        S_b = io["costs"][k0:k0 + K].double().cpu().numpy()
+        assert (np.abs(S_b - out["costs"]) / np.abs(out["costs"])).max() <= 1e-4, p
+        u0 = batch.u_off[p] // 7
+        assert np.abs(io["U_new"][u0:u0 + c["cost"]["T"]].cpu().numpy() - out["U_new"]).max() <= U_ATOL
+        assert int(io["status"][p].cpu()) == B.OK
+    batch.close()

@@ -127,6 +127,31 @@ def test_rollout_cost_matches_oracle(hc, ora, workloads, which, prec, tol):
             assert np.abs(noise - n_ref).max() < (1e-12 if prec == B.FP64 else 1e-4)
 
 
+@pytest.mark.parametrize("rho", [0.5, 0.95])
+@pytest.mark.parametrize("prec,tol", [(B.FP64, 1e-9), (B.FP32, 1e-4)])
+def test_correlated_noise_rollout_matches_oracle(hc, ora, workloads, rho, prec, tol):
+    """AR(1) perturbation in time (noise_step) against the oracle's recursion."""
+    for which in ("single_k256", "wall_k4096"):
+        case = workloads[which][0]
+        cost = dict(case["cost"], noise_rho=rho)
+        rp = B.robot_params(case["robot"])
+        cp = B.cost_params(cost, prec)
+        tgt = B.target_vector(case["target"])
+        U = np.ascontiguousarray(case["U_nom"], dtype=np.float64)
+        for k in (0, 77):
+            noise = np.zeros((cost["T"], 7))
+            S = hc.hc_rollout(C.byref(rp), C.byref(cp), prec, _d(tgt), _d(case["q0"]), _d(case["qd0"]), _d(U),
+                              case["seed"], 3, k, noise.ctypes.data_as(C.POINTER(C.c_double)))
+            S_ref, n_ref = ora.rollout(case["robot"], cost, case["target"], case["q0"], case["qd0"], U,
+                                       case["seed"], 3, k)
+            assert abs(S - S_ref) <= tol * abs(S_ref), (S, S_ref)
+            assert np.abs(noise - n_ref).max() < (1e-12 if prec == B.FP64 else 1e-4)
+            # the recursion is in effect: later steps differ from the independent draws
+            _, n_iid = ora.rollout(case["robot"], case["cost"], case["target"], case["q0"], case["qd0"], U,
+                                   case["seed"], 3, k)
+            assert np.array_equal(n_ref[0], n_iid[0]) and np.abs(n_ref[1:] - n_iid[1:]).max() > 1e-3
+
+
 def _dp(a):
     return np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(C.POINTER(C.c_double))
 

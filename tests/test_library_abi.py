@@ -67,6 +67,10 @@ def test_invalid_arguments_rejected_before_device(lib, workloads):
     bad.append((robot, dict(cost, sigma=[2.0] * 6 + [-1.0])))
     bad.append((robot, dict(cost, w_q=float("nan"))))
     bad.append((robot, dict(cost, ext_mode=2, wall_n=[0.0, 0.0, 2.0])))
+    for rho in (1.0, -0.1, float("nan")):
+        bad.append((robot, dict(cost, noise_rho=rho)))
+    for it in (-1, 65):
+        bad.append((robot, dict(cost, iterations=it)))
     for rb, cs in bad:
         st, h = _create(lib, rb, cs)
         assert st == B.EINVAL

@@ -55,3 +55,17 @@ def test_iterations_chain_updates(ora, workloads):
                                 case["qd0"], U0, 4, 7)
     st0, U0b, S0, _ = ora.update(case["robot"], case["cost"], case["target"], case["q0"], case["qd0"], U0, 4, 7)
     assert np.array_equal(U1, U0b) and np.array_equal(S1, S0)
+
+
+def test_iterations_are_chained_single_updates(ora, workloads):
+    """n iterations at tick t are n single updates at the ticks n t + i, each
+    from the previous U_new (structure of the chaining, K = 256)."""
+    case = workloads["single_k256"][4]
+    n, t = 3, 4
+    st, U_n, S_n, E_n = ora.update(case["robot"], dict(case["cost"], iterations=n), case["target"], case["q0"],
+                                   case["qd0"], case["U_nom"], 2, t)
+    U = np.asarray(case["U_nom"])
+    for i in range(n):
+        st, U, S, E = ora.update(case["robot"], case["cost"], case["target"], case["q0"], case["qd0"], U, 2,
+                                 n * t + i)
+    assert np.array_equal(U, U_n) and np.array_equal(S, S_n) and np.array_equal(E, E_n)
