@@ -1083,6 +1083,23 @@ int ora_update(const ora_robot* rb, const ora_cost* cp, const ora_target* tg,
 /* Plant for the closed loop: the command is held (zero-order hold) over
    one control period, split into semi-implicit Euler substeps, with the
    torque clamped to the joint limits. */
+void ora_warm_start(int T, int n, const double* U, double s, double* out)
+{
+    for (int t = 0; t < T; ++t) {
+        const double a = t + s, b = a + 1.0;
+        for (int j = 0; j < n; ++j) out[t * n + j] = 0.0;
+        /* overlap of [a, b) with each held interval [i, i + 1) */
+        const int i0 = (int)floor(a);
+        for (int i = i0; i <= i0 + 1; ++i) {
+            const double lo = a > i ? a : (double)i;
+            const double hi = b < i + 1.0 ? b : i + 1.0;
+            if (hi <= lo) continue;
+            const int row = i < T ? i : T - 1;
+            for (int j = 0; j < n; ++j) out[t * n + j] += (hi - lo) * U[row * n + j];
+        }
+    }
+}
+
 void ora_plant_step(const ora_robot* rb, const ora_cost* cp, double* q,
                     double* qd, const double* u, double dt, int substeps)
 {

@@ -181,6 +181,12 @@ int  ora_update(const ora_robot* rb, const ora_cost* c, const ora_target* tg,
                 const double* q0, const double* qd0, const double* U_nom,
                 uint64_t seed, uint64_t tick, double* U_new, double* costs,
                 double* noise, int nthreads);
+/* Receding-horizon warm start after s >= 0 horizon steps of elapsed time
+   (Sec. II: the rest of the optimised sequence seeds the next update).  The
+   sequence U (T x n) is read as piecewise constant in time, row i held over
+   [i, i+1) in units of dt and the last row held past the horizon; row t of
+   out is its mean over [t + s, t + s + 1).  s = 1 is the one-step shift. */
+void ora_warm_start(int T, int n, const double* U, double s, double* out);
 /* Closed-loop plant: hold torque u (clamped to tau_max) for dt using
    `substeps` semi-implicit Euler substeps with the wall/constant wrench. */
 void ora_plant_step(const ora_robot* rb, const ora_cost* c, double* q,

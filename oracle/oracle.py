@@ -123,6 +123,7 @@ def lib():
                                      C.c_uint64, C.c_uint64, _D, _D, _D, C.c_int]
             L.ora_update.restype = C.c_int
             L.ora_plant_step.argtypes = [P(Robot), P(Cost), _D, _D, _D, C.c_double, C.c_int]
+            L.ora_warm_start.argtypes = [C.c_int, C.c_int, _D, C.c_double, _D]
             L.ora_max_threads.restype = C.c_int
             L.ora_segment_distance.argtypes = [_D, _D, _D, _D]
             L.ora_segment_distance.restype = C.c_double
@@ -424,6 +425,15 @@ def update(robot, cost, target, q0, qd0, U_nom, seed, tick, nthreads=0,
                           _p(U_new), _p(costs), _p(noise) if noise is not None else None,
                           int(nthreads))
     return st, U_new, costs, noise
+
+
+def warm_start(U, s):
+    """Warm start after s horizon steps (ora_warm_start)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    T, n = U.shape
+    out = np.zeros((T, n))
+    lib().ora_warm_start(int(T), int(n), _p(U.ravel()), float(s), _p(out))
+    return out
 
 
 def plant_step(robot, cost, q, qd, u, dt, substeps):
