@@ -282,6 +282,24 @@ int mppi_batch_graph_launch(mppi_batch_t b, void* stream);
  * workgroup per problem. */
 int mppi_batch_plant_step_async(mppi_batch_t b, const mppi_batch_io* io, double dt, int substeps, void* stream);
 
+/* ---- warm start for a solver period that differs from dt ---- */
+
+/* Receding horizon (Sec. II: the rest of the optimised sequence seeds the
+ * next update) after shift_steps = s horizon steps of elapsed time (the
+ * solver period over dt): U_new is read as piecewise constant in time (row
+ * t held over [t dt, (t+1) dt), the last row held past the horizon) and row
+ * t of U_out is its mean over [(t + s) dt, (t + s + 1) dt), i.e.
+ *   (1 - f) U_new[min(t + m, T-1)] + f U_new[min(t + m + 1, T-1)],
+ * m = floor(s), f = s - m.  s = 1 gives U_shift of an update bit for bit.
+ * Device [T][7] buffers that must not overlap; 0 <= s <= T.
+ * Errors: MPPI_EINVAL (null, overlap, s out of range or non-finite),
+ * MPPI_EDEVICE. */
+int mppi_warm_start_async(mppi_handle_t h, const double* U_new, double* U_out, double shift_steps, void* stream);
+/* The same for every problem of a batch, in the packed layout
+ * (0 <= s <= 64). */
+int mppi_batch_warm_start_async(mppi_batch_t b, const double* U_new, double* U_out, double shift_steps,
+                                void* stream);
+
 /* ---- nominal-sequence selection (plain MPPI as the fallback) ---- */
 
 /* Rolls out two sequences from the state of `io` without noise (the same

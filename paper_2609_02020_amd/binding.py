@@ -176,6 +176,7 @@ def lib():
         L.mppi_rollout_async.argtypes = [vp, P(DeviceIO), vp]
         L.mppi_weights_async.argtypes = [vp, P(DeviceIO), vp]
         L.mppi_plant_step_async.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int, vp]
+        L.mppi_warm_start_async.argtypes = [vp, vp, vp, C.c_double, vp]
         L.mppi_select_nominal_async.argtypes = [vp, P(DeviceIO), vp, vp, vp]
         L.mppi_strerror.argtypes = [C.c_int]
         L.mppi_strerror.restype = C.c_char_p
@@ -285,6 +286,13 @@ class Solver:
         if st:
             raise MppiError(st, "mppi_plant_step_async")
 
+    def warm_start_async(self, U_new, U_out, shift_steps: float, stream=None):
+        """U_out = U_new advanced by shift_steps horizon steps (mppi_warm_start_async)."""
+        st = self._lib.mppi_warm_start_async(self._h, _ptr(U_new), _ptr(U_out), float(shift_steps),
+                                             _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_warm_start_async")
+
     def select_nominal_async(self, io: dict, U_candidate, costs=None, stream=None):
         """Keeps io["U_nominal"] or replaces it with U_candidate, whichever
         has the lower noise-free rollout cost (mppi_select_nominal_async)."""
@@ -320,6 +328,7 @@ def _batch_lib():
         L.mppi_batch_set_tick.argtypes = [vp, C.c_uint64]
         L.mppi_batch_graph_launch.argtypes = [vp, vp]
         L.mppi_batch_plant_step_async.argtypes = [vp, P(BatchIO), C.c_double, C.c_int, vp]
+        L.mppi_batch_warm_start_async.argtypes = [vp, vp, vp, C.c_double, vp]
         L.mppi_batch_select_nominal_async.argtypes = [vp, P(BatchIO), vp, vp, vp]
         L._batch_ready = True
     return L
@@ -414,6 +423,13 @@ class Batch:
                                                    _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_batch_plant_step_async")
+
+    def warm_start_async(self, U_new, U_out, shift_steps: float, stream=None):
+        """Packed U_out = U_new advanced by shift_steps horizon steps."""
+        st = self._lib.mppi_batch_warm_start_async(self._h, _ptr(U_new), _ptr(U_out), float(shift_steps),
+                                                   _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_batch_warm_start_async")
 
     def select_nominal_async(self, io: dict, U_candidates, costs=None, stream=None):
         d = self._io(io)

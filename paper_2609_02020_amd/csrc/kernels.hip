@@ -360,6 +360,39 @@ __global__ void batch_plant_kernel(const BatchProblem* __restrict__ probs, int n
     plant_advance(*Pb.model64, *Pb.cost64, q + p * NJ, qd + p * NJ, U_new + Pb.u_off, dt, substeps);
 }
 
+// Warm start after s horizon steps of elapsed time (solver period != dt):
+// the sequence read as piecewise constant in time (row i held over
+// [i, i+1) steps, the last row held past the horizon), averaged over
+// [t + s, t + s + 1):  out[t] = (1 - f) U[min(t+m, T-1)] + f U[min(t+m+1, T-1)]
+// with m = floor(s), f = s - m (f = 0 copies the row, so s = 1 is the
+// one-step shift bit for bit).
+__device__ void warm_start_rows(const double* U, double* out, int T, double s, int tid, int nthreads)
+{
+    const double mf = floor(s), f = s - mf;
+    const int m = (int)mf;
+    for (int r = tid; r < T * NJ; r += nthreads) {
+        const int t = r / NJ, j = r - t * NJ;
+        const int i0 = min(t + m, T - 1), i1 = min(t + m + 1, T - 1);
+        const double a = U[i0 * NJ + j];
+        out[r] = f == 0.0 ? a : (1.0 - f) * a + f * U[i1 * NJ + j];
+    }
+}
+
+__global__ void warm_start_kernel(const double* __restrict__ U, double* __restrict__ out, int T, double s)
+{
+    warm_start_rows(U, out, T, s, threadIdx.x, blockDim.x);
+}
+
+// one workgroup per problem of a batch (packed layout)
+__global__ void batch_warm_start_kernel(const BatchProblem* __restrict__ probs, int n, const double* __restrict__ U,
+                                        double* __restrict__ out, double s)
+{
+    const int p = blockIdx.x;
+    if (p >= n) return;
+    const BatchProblem& Pb = probs[p];
+    warm_start_rows(U + Pb.u_off, out + Pb.u_off, Pb.T, s, threadIdx.x, blockDim.x);
+}
+
 // Noise-free costs of two sequences from one state (lane 0: the current
 // nominal, lane 1: the candidate; the sampling scales are zeroed in the LDS
 // copy of the cost, so v_t = u_t exactly); the candidate replaces the
@@ -567,6 +600,21 @@ hipError_t launch_batch_plant(const void* probs, int n, double* q, double* qd, c
 {
     hipLaunchKernelGGL(batch_plant_kernel, dim3(n), dim3(64), 0, s, (const BatchProblem*)probs, n, q, qd, U_new,
                        dt, substeps);
+    return hipGetLastError();
+}
+
+hipError_t launch_warm_start(const double* U, double* out, int T, double shift, hipStream_t s)
+{
+    if (T < 1 || T > kMaxT) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(warm_start_kernel, dim3(1), dim3(256), 0, s, U, out, T, shift);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_warm_start(const void* probs, int n, const double* U, double* out, double shift,
+                                   hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_warm_start_kernel, dim3(n), dim3(64), 0, s, (const BatchProblem*)probs, n, U, out,
+                       shift);
     return hipGetLastError();
 }
 

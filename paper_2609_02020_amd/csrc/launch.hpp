@@ -78,6 +78,10 @@ void fill_batch_problem(void* dst, const void* model, const void* cost, const vo
                         long long k_off, long long part_off);
 hipError_t launch_batch_plant(const void* probs, int n, double* q, double* qd, const double* U_new, double dt,
                               int substeps, hipStream_t s);
+// warm start after `shift` horizon steps (0 <= shift), [T][7] or packed
+hipError_t launch_warm_start(const double* U, double* out, int T, double shift, hipStream_t s);
+hipError_t launch_batch_warm_start(const void* probs, int n, const double* U, double* out, double shift,
+                                   hipStream_t s);
 hipError_t launch_batch_select(const void* probs, int n, const double* q, const double* qd, const double* target,
                                double* U_nom, const double* U_cand, double* costs, hipStream_t s);
 // model/cost: ModelM<R>/CostM<R> of the rollout precision

@@ -432,6 +432,16 @@ int mppi_select_nominal_async(mppi_handle_t h, const mppi_device_io* io, const d
                : MPPI_EDEVICE;
 }
 
+int mppi_warm_start_async(mppi_handle_t h, const double* U_new, double* U_out, double shift_steps, void* stream)
+{
+    if (!h || !U_new || !U_out || !std::isfinite(shift_steps) || shift_steps < 0 || shift_steps > h->cost.T)
+        return MPPI_EINVAL;
+    const size_t TJ = (size_t)h->cost.T * MPPI_NJ;
+    if (U_out < U_new + TJ && U_new < U_out + TJ) return MPPI_EINVAL;
+    return launch_warm_start(U_new, U_out, h->cost.T, shift_steps, (hipStream_t)stream) == hipSuccess ? MPPI_OK
+                                                                                                      : MPPI_EDEVICE;
+}
+
 const char* mppi_strerror(int status)
 {
     switch (status) {
@@ -655,6 +665,18 @@ int mppi_batch_select_nominal_async(mppi_batch_t b, const mppi_batch_io* io, con
     if (check_batch_io(b, io) || !U_candidates) return MPPI_EINVAL;
     return launch_batch_select(b->d_probs, b->n, io->q, io->qd, io->target, const_cast<double*>(io->U_nominal),
                                U_candidates, costs, (hipStream_t)stream) == hipSuccess
+               ? MPPI_OK
+               : MPPI_EDEVICE;
+}
+
+int mppi_batch_warm_start_async(mppi_batch_t b, const double* U_new, double* U_out, double shift_steps,
+                                void* stream)
+{
+    if (!b || !U_new || !U_out || !std::isfinite(shift_steps) || shift_steps < 0 || shift_steps > kMaxTBatch)
+        return MPPI_EINVAL;
+    const size_t n = b->u_total;   // doubles
+    if (U_out < U_new + n && U_new < U_out + n) return MPPI_EINVAL;
+    return launch_batch_warm_start(b->d_probs, b->n, U_new, U_out, shift_steps, (hipStream_t)stream) == hipSuccess
                ? MPPI_OK
                : MPPI_EDEVICE;
 }

@@ -1,0 +1,61 @@
+"""Solver rate versus closed-loop quality (the paper's controller runs at
+about 166 Hz behind a zero-order hold to a 1 kHz torque interface,
+Sec. IV-A).  The contact task of the learned-proposal workload (pose target
+on the wall-tangent axes, 10 N normal force into a spring-damper wall) runs
+with the plant at 1 kHz and the solver every 10, 6 or 1 ms, the command
+applied at once or one solver period late; the warm start advances by the
+elapsed time.  Quality is measured on the plant states with the oracle's
+kinematics and wall model.  Task-level behaviour, not parity."""
+import numpy as np
+import pytest
+
+from paper_2609_02020_amd import binding as B
+from paper_2609_02020_amd import inputs, rate
+
+pytestmark = pytest.mark.gpu
+
+
+def evaluate(ora, robot, cost, episodes, out, t0_ms, stride=2, plant_ms=1.0):
+    """Means over the episodes and the plant states from t0_ms on: position
+    error on the weighted axes [m], orientation error [rad], contact-force
+    error on the weighted force axes [N] (the force the EE exerts on the
+    wall against F_des) and the running cost of the applied torques."""
+    w_pos = np.asarray(cost["W_pos"]) > 0
+    w_f = np.asarray(cost["W_force"][:3]) > 0
+    steps = out["u"].shape[0]
+    acc = {"pos": [], "ori": [], "force": [], "cost": []}
+    for e, ep in enumerate(episodes):
+        tg = ep["target"]
+        Rd = ora.quat_to_R(tg["quat_des"])
+        Fd = np.asarray(tg["F_des"][:3])
+        for s in range(int(round(t0_ms / plant_ms)), steps, stride):
+            q, qd = out["q"][s, e], out["qd"][s, e]
+            _, _, pe, Re = ora.fk(robot, q)
+            acc["pos"].append(np.linalg.norm((pe - np.asarray(tg["p_des"]))[w_pos]))
+            acc["ori"].append(np.linalg.norm(ora.so3_log(Rd.T @ Re)))
+            v = ora.ee_jacobian(robot, q)[:3] @ qd
+            F = -ora.wall_force(cost, pe, v)
+            acc["force"].append(np.linalg.norm((F - Fd)[w_f]))
+            acc["cost"].append(ora.running_cost(robot, cost, tg, q, qd, out["u"][s, e])[0])
+    return {k: float(np.mean(v)) for k, v in acc.items()}
+
+
+def study(ora, K, configs, n_episodes, seconds, t0_ms):
+    d = inputs.load_learned()
+    eps = d["eval"][:n_episodes]
+    rows = {}
+    for period, delay in configs:
+        out = rate.run(d["robot"], d["cost"], eps, K, period, seconds, delay=delay)
+        assert (out["status"] == B.OK).all()
+        assert np.isfinite(out["q"]).all()
+        m = evaluate(ora, d["robot"], d["cost"], eps, out, t0_ms)
+        rows[(period, delay)] = m
+        print("K %5d  solver %4.0f Hz  delay %d: position %.4f m  orientation %.4f rad  force %.3f N  cost %.4g"
+              % (K, 1e3 / period, delay, m["pos"], m["ori"], m["force"], m["cost"]), flush=True)
+    return rows
+
+
+def test_rate_study(ora):
+    rows = study(ora, 1024, [(10.0, 0), (6.0, 1), (1.0, 0)], 8, 1.5, 500.0)
+    fast, paper = rows[(1.0, 0)], rows[(6.0, 1)]
+    assert fast["cost"] <= paper["cost"]

@@ -92,6 +92,9 @@ def test_null_handle_calls_fail_cleanly(lib):
     z = np.zeros(7)
     assert lib.mppi_update(None, z.ctypes.data_as(D), z.ctypes.data_as(D), None, None, 0, 0, None,
                            None) == B.EINVAL
+    B._batch_lib()
+    assert lib.mppi_warm_start_async(None, None, None, C.c_double(1.0), None) == B.EINVAL
+    assert lib.mppi_batch_warm_start_async(None, None, None, C.c_double(1.0), None) == B.EINVAL
 
 
 def test_proposal_and_selection_entry_points_reject_bad_arguments(lib, workloads):
