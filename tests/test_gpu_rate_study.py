@@ -23,7 +23,7 @@ def evaluate(ora, robot, cost, episodes, out, t0_ms, stride=2, plant_ms=1.0):
     w_pos = np.asarray(cost["W_pos"]) > 0
     w_f = np.asarray(cost["W_force"][:3]) > 0
     steps = out["u"].shape[0]
-    acc = {"pos": [], "ori": [], "force": [], "cost": []}
+    acc = {"pos": [], "ori": [], "force": [], "cost": [], "contact": [], "f_n": [], "gap": []}
     for e, ep in enumerate(episodes):
         tg = ep["target"]
         Rd = ora.quat_to_R(tg["quat_des"])
@@ -36,6 +36,11 @@ def evaluate(ora, robot, cost, episodes, out, t0_ms, stride=2, plant_ms=1.0):
             v = ora.ee_jacobian(robot, q)[:3] @ qd
             F = -ora.wall_force(cost, pe, v)
             acc["force"].append(np.linalg.norm((F - Fd)[w_f]))
+            # normal force on the wall and the EE's distance in front of it
+            n = np.asarray(cost["wall_n"])
+            acc["f_n"].append(float(-F @ n))
+            acc["contact"].append(float(-F @ n > 0))
+            acc["gap"].append(float(n @ pe - cost["wall_d0"]))
             acc["cost"].append(ora.running_cost(robot, cost, tg, q, qd, out["u"][s, e])[0])
     return {k: float(np.mean(v)) for k, v in acc.items()}
 
@@ -51,7 +56,9 @@ def study(ora, K, configs, n_episodes, seconds, t0_ms):
         m = evaluate(ora, d["robot"], d["cost"], eps, out, t0_ms)
         rows[(period, delay)] = m
         print("K %5d  solver %4.0f Hz  delay %d: position %.4f m  orientation %.4f rad  force %.3f N  cost %.4g"
-              % (K, 1e3 / period, delay, m["pos"], m["ori"], m["force"], m["cost"]), flush=True)
+              "  (in contact %.2f, mean normal force %.2f N, mean gap %.4f m)"
+              % (K, 1e3 / period, delay, m["pos"], m["ori"], m["force"], m["cost"], m["contact"], m["f_n"],
+                 m["gap"]), flush=True)
     return rows
 
 
