@@ -137,8 +137,8 @@ struct BatchProblem {
 // rollout variants are compiled in only then)
 template <int W, bool COLL>
 __global__ __launch_bounds__(64 * W) void batch_kernel(
-    const BatchProblem* __restrict__ probs, const int2* __restrict__ items, int nitems,
-    unsigned int* queue, unsigned int* done, unsigned int* counters, const double* __restrict__ q,
+    const BatchProblem* __restrict__ probs, const ModelM<float>* __restrict__ models,
+    const int2* __restrict__ items, int nitems, unsigned int* queue, unsigned int* done, unsigned int* counters, const double* __restrict__ q,
     const double* __restrict__ qd, const double* __restrict__ target, const double* U_nom, double* U_new,
     double* U_shift, float* __restrict__ costs, int* __restrict__ status, const uint64_t* __restrict__ seeds,
     const uint64_t* __restrict__ tickp, double* __restrict__ parts)
@@ -164,7 +164,11 @@ __global__ __launch_bounds__(64 * W) void batch_kernel(
         wave_copy(&Csh[wid], Pb.cost, sizeof(CostM<float>), lane);
         for (int i = lane; i < T * NJ; i += 64) Us[wid][i] = float(U_nom[Pb.u_off + i]);
         wave_sync();
-        const ModelM<float>& M = *Pb.model;   // scalar cache, as in update_kernel
+        // problem p's model is models[p] (== *Pb.model); read through the
+        // restrict-qualified kernel argument at a uniform index it becomes
+        // scalar loads, as in update_kernel (a pointer loaded from the
+        // problem table is read with vector loads)
+        const ModelM<float>& M = models[it.x];
         const CostM<float>& C = Csh[wid];
         const int k = it.y * 64 + lane;
         const uint64_t seed = seeds[it.x];
@@ -543,8 +547,8 @@ hipError_t launch_weights(int precision, bool acc64, const WeightsArgs& a, hipSt
 template <int W, bool COLL> static hipError_t batch_t(const BatchArgs& a, int groups, hipStream_t s)
 {
     hipLaunchKernelGGL((batch_kernel<W, COLL>), dim3(groups), dim3(64 * W), 0, s, (const BatchProblem*)a.probs,
-                       (const int2*)a.items, a.nitems, a.queue, a.done, a.counters, a.q, a.qd, a.target, a.U_nom,
-                       a.U_new, a.U_shift, a.costs, a.status, a.seeds, a.tick, a.parts);
+                       (const ModelM<float>*)a.models, (const int2*)a.items, a.nitems, a.queue, a.done, a.counters,
+                       a.q, a.qd, a.target, a.U_nom, a.U_new, a.U_shift, a.costs, a.status, a.seeds, a.tick, a.parts);
     return hipGetLastError();
 }
 

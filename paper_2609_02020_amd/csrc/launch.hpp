@@ -49,6 +49,7 @@ size_t update_parts_bytes(int K, int T);
 
 struct BatchArgs {
     const void* probs;      // BatchProblem [n] (device)
+    const void* models;     // ModelM<float> [n] (device): problem p's model
     const void* items;      // int2 [nitems]: (problem, tile), in schedule order
     int nitems;
     unsigned int* queue;    // zero before the first launch; the kernel leaves it zero

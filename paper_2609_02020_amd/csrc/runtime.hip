@@ -512,6 +512,7 @@ BatchArgs batch_args(mppi_batch* b, const mppi_batch_io* io, const uint64_t* tic
 {
     BatchArgs a;
     a.probs = b->d_probs;
+    a.models = b->d_mf;
     a.items = b->d_items;
     a.nitems = b->nitems;
     a.queue = b->d_sync;

@@ -183,3 +183,56 @@ def test_many_block_merge(ora, workloads, K):
     if note:
         print(note)
     solver.close()
+
+
+def test_maximum_sample_count(ora, workloads):
+    """K = 2^20 (the largest K a solver accepts), T = 18, contact cost, FP32:
+    200 sampled costs against the oracle's rollouts of those samples, the
+    noise of those samples, and U_new against the oracle's Eq. 4 on the
+    GPU's own K costs and noise (stage-isolated criterion)."""
+    case = workloads["wall_k4096"][6]
+    K = 1 << 20
+    cost = dict(case["cost"], K=K)
+    solver = B.Solver(case["robot"], cost, B.FP32)
+    out = device_update(solver, dict(case, cost=cost), case["seed"], 2, B.FP32)
+    solver.close()
+    assert out["status"] == B.OK
+    ks = np.random.default_rng(11).choice(K, 200, replace=False)
+    ks[:2] = [0, K - 1]
+    S_ref = np.zeros(len(ks))
+    for i, k in enumerate(ks):
+        S_ref[i], E_k = ora.rollout(case["robot"], cost, case["target"], case["q0"], case["qd0"], case["U_nom"],
+                                    case["seed"], 2, int(k))
+        assert np.abs(out["noise"][k] - E_k).max() <= 5e-5
+    sub = dict(case, cost=cost)
+    flagged = check_costs_fp32(ora, sub, out["costs"][ks], S_ref, case["seed"], 2, "K=2^20")
+    assert len(flagged) <= 2
+    st, U_stage, _ = ora.weights_update(out["costs"], out["noise"], case["U_nom"], cost["lambda"])
+    assert st == 0 and np.abs(out["U_new"] - U_stage).max() <= U_ATOL
+
+
+@pytest.mark.parametrize("precision", [B.FP32, B.FP64])
+def test_maximum_horizon(ora, workloads, precision):
+    """T = 256 (the largest horizon) at K = 320 (five waves), position task,
+    dt = 2 ms (a 0.512 s horizon: at 10 ms random torques drive most
+    trajectories past FP32 range): every sample against the oracle; the
+    weighting regenerates the noise (the tile does not fit in LDS)."""
+    base = workloads["single_k256"][7]
+    U = np.asarray(base["U_nom"])
+    U = np.concatenate([U] * 15)[:256]
+    cost = dict(base["cost"], K=320, T=256, dt=0.002)
+    case = dict(base, cost=cost, U_nom=U.tolist())
+    solver = B.Solver(case["robot"], cost, precision)
+    out = device_update(solver, case, case["seed"], 3, precision)
+    solver.close()
+    U_ref, S_ref, E_ref = oracle_update(ora, case, cost, case["seed"], 3)
+    assert out["status"] == B.OK
+    if precision == B.FP64:
+        assert cost_rel_err(out["costs"], S_ref).max() <= 1e-9
+        assert np.abs(out["noise"] - E_ref).max() <= 1e-12
+    else:
+        check_costs_fp32(ora, case, out["costs"], S_ref, case["seed"], 3, "T=256")
+        assert np.abs(out["noise"] - E_ref).max() <= 5e-5
+    note = check_update(ora, case, out, cost["lambda"], S_ref, U_ref, "T=256")
+    if note:
+        print(note)
