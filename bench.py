@@ -66,7 +66,7 @@ def kernel_source_digest():
 
 
 def profiled_traffic(kernel):
-    return PROFILED_TRAFFIC[kernel] if kernel_source_digest() == PROFILED_DIGEST else None
+    return PROFILED_TRAFFIC.get(kernel) if kernel_source_digest() == PROFILED_DIGEST else None
 
 
 def parse():
@@ -416,10 +416,21 @@ def main():
         "host_api_update_hz": host_rate,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-                     "traffic": profiled_traffic("update_kernel"),
-                     "kernel": "update_kernel<float, float, force>",
+                     "traffic": profiled_traffic("update_split_kernel"),
+                     "kernel": "update_split_kernel<float, force> (two waves per 64 samples)",
                      "flops_per_launch": flops},
     }
+    # the same update on one wave per 64 samples, for comparison
+    solver.set_launch(1)
+    ev1 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
+    for s in range(10):
+        update(10**7 + s)
+    for s in range(100):
+        update(10**7 + 10 + s, ev1[s])
+    torch.cuda.synchronize()
+    solver.set_launch(2)
+    out["launch_shapes"] = {"two_waves_per_64_samples_ms": float(np.mean(roll_ms)),
+                            "one_wave_per_64_samples_ms": float(np.mean([a.elapsed_time(b) for a, b in ev1]))}
     if args.batch_ticks > 0:
         out["batch"] = batch_bench(B, inputs.load()["batch64"], torch, dev, args.batch_ticks)
     if not args.no_mlp:

@@ -161,6 +161,16 @@ int mppi_destroy(mppi_handle_t h);
  * otherwise).  Takes effect for later updates. */
 int mppi_set_cost(mppi_handle_t h, const mppi_cost_params* cost);
 
+/* Launch shape of the updates: 2 (the default) runs each group of 64
+ * samples on two waves where supported (FP32 rollouts of the
+ * articulated-body route): one wave integrates the dynamics while the
+ * other draws the next step's perturbations and evaluates the force
+ * estimate (Eq. 13) and the cost of the previous step, which shortens the
+ * per-step critical path; FP64 rollouts, the route of Eq. 8, and 1 use one
+ * wave per 64 samples.  Results are the same either way (the same
+ * arithmetic per sample).  Errors: MPPI_EINVAL (null, other values). */
+int mppi_set_launch(mppi_handle_t h, int waves_per_group);
+
 /* Synchronous update from host memory (Sec. II: one MPPI iteration).
  *   q, qd      [7] measured state x_0
  *   target     pose / wrench targets

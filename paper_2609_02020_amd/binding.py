@@ -177,6 +177,7 @@ def lib():
         L.mppi_weights_async.argtypes = [vp, P(DeviceIO), vp]
         L.mppi_plant_step_async.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int, vp]
         L.mppi_warm_start_async.argtypes = [vp, vp, vp, C.c_double, vp]
+        L.mppi_set_launch.argtypes = [vp, C.c_int]
         L.mppi_select_nominal_async.argtypes = [vp, P(DeviceIO), vp, vp, vp]
         L.mppi_strerror.argtypes = [C.c_int]
         L.mppi_strerror.restype = C.c_char_p
@@ -285,6 +286,12 @@ class Solver:
                                              int(substeps), _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_plant_step_async")
+
+    def set_launch(self, waves_per_group: int):
+        """1 or 2 waves per 64 samples (mppi_set_launch)."""
+        st = self._lib.mppi_set_launch(self._h, int(waves_per_group))
+        if st:
+            raise MppiError(st, "mppi_set_launch")
 
     def warm_start_async(self, U_new, U_out, shift_steps: float, stream=None):
         """U_out = U_new advanced by shift_steps horizon steps (mppi_warm_start_async)."""

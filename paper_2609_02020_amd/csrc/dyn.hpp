@@ -398,6 +398,22 @@ template <typename R> MPPI_HD void chol6_solve(const Sym6<R>& S, R* b)
 // (the uniform gravity pseudo-acceleration removed); x = Omega_n^-1 b is the
 // spatial force about p_n and the EE wrench is F = x_f,
 // N = x_n - (p_ee - p_n) x x_f.
+// What the force estimate needs from one articulated-body step: the joint
+// axes, the link translations r_1..r_6, the factors U_i and 1/D_i, the
+// zero-velocity response b = J_n M^-1 tau_F about p_n and the EE offset
+// from p_n (all world axes).  force_estimate() turns it into F_ee.
+template <typename R> struct ForceIn {
+    R z[NJ][3];
+    R rr[NJ][3];   // rr[0] unused
+    R U[NJ][6];
+    R iD[NJ];
+    R b[6];
+    R ree[3];
+};
+// Flat layout of a ForceIn for a handoff through memory (index of each
+// value; rr[0] is not stored): 97 values.
+constexpr int kFiZ = 0, kFiRr = 21, kFiU = 39, kFiD = 81, kFiB = 88, kFiRee = 94, kFiCount = 97;
+
 template <typename R> struct StepOut {
     R qdd[NJ];
     R pee[3];      // EE point, world
@@ -520,13 +536,50 @@ template <typename R> MPPI_HD void shift_motion(const R* r, Sym6<R>& M)
     for (int i = 0; i < 9; ++i) M.B[i] += W[i];
 }
 
+// EE wrench estimate of Eq. 13 from the factors of one step:
+//   Omega <- P (X Omega X^T) P^T + S S^T / D, link by link from the root
+//          = Y + S y^T + y S^T with Y = X Omega X^T, w = Y U,
+//            y = (beta/D^2 + 1/D)/2 S - w/D, beta = U.w,
+// then x = Omega_n^-1 b (6x6 Cholesky) is the spatial force about p_n and
+// F = (x_f, x_n - ree x x_f).
+template <typename R> MPPI_HD void force_estimate(const ForceIn<R>& fi, R* F)
+{
+    Sym6<R> Om;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) { Om.A[k] = R(0); Om.C[k] = R(0); }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Om.B[k] = R(0);
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        if (i > 0) shift_motion(fi.rr[i], Om);
+        R wv[6];
+        sym6_mv(Om, fi.U[i], wv);
+        const R dI = fi.iD[i];
+        const R g2 = R(0.5) * (dot6(fi.U[i], wv) * dI + R(1)) * dI;
+        R y[6];
+        y[0] = fma_(g2, fi.z[i][0], -wv[0] * dI); y[1] = fma_(g2, fi.z[i][1], -wv[1] * dI);
+        y[2] = fma_(g2, fi.z[i][2], -wv[2] * dI);
+        y[3] = -wv[3] * dI; y[4] = -wv[4] * dI; y[5] = -wv[5] * dI;
+        sym6_add_joint_rank2(Om, fi.z[i], y);
+    }
+    R b[6] = {fi.b[0], fi.b[1], fi.b[2], fi.b[3], fi.b[4], fi.b[5]};
+    chol6_solve(Om, b);   // x = Omega^-1 b: spatial force about p_n
+    R rf[3];
+    cross3(fi.ree, b + 3, rf);
+    F[0] = b[3]; F[1] = b[4]; F[2] = b[5];
+    F[3] = b[0] - rf[0]; F[4] = b[1] - rf[1]; F[5] = b[2] - rf[2];
+}
+
 // ext: EXTW_NONE, EXTW_CONST (world wrench F_ext at the EE point, current
 // configuration) or EXTW_WALL (the cost's wall model).  tau: joint torques
 // (sampled torque plus any joint-space external torque).  v: sampled torque
 // for the force estimate (FORCE only).
+// hand (FORCE only): when non-null, the inputs of the force estimate are
+// stored there in the flat ForceIn layout, value f at hand[f * hstride],
+// each as soon as the step no longer needs it, and out.F is left unset.
 template <typename R, bool FORCE>
 MPPI_HD void dyn_step(const ModelM<R>& M, const CostM<R>& Cst, int ext, const R* q, const R* qd,
-                      const R* tau, const R* v, StepOut<R>& out)
+                      const R* tau, const R* v, StepOut<R>& out, R* hand = nullptr, int hstride = 0)
 {
     R z[NJ][3];      // joint axes (world)
     R rr[NJ][3];     // p_i - p_{i-1} (r_0 = p_0)
@@ -676,13 +729,6 @@ MPPI_HD void dyn_step(const ModelM<R>& M, const CostM<R>& Cst, int ext, const R*
     R a[6] = {R(0), R(0), R(0), -M.g[0], -M.g[1], -M.g[2]};
     R aF[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     if (FORCE && Cst.force_mode == 0) { aF[3] = -M.g[0]; aF[4] = -M.g[1]; aF[5] = -M.g[2]; }
-    Sym6<R> Om;
-    if (FORCE) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) { Om.A[k] = R(0); Om.C[k] = R(0); }
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Om.B[k] = R(0);
-    }
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
         // a' = X a + c
@@ -699,31 +745,43 @@ MPPI_HD void dyn_step(const ModelM<R>& M, const CostM<R>& Cst, int ext, const R*
             aF[3] += wxr[0]; aF[4] += wxr[1]; aF[5] += wxr[2];
             const R qF = (uF[i] - dot6(U[i], aF)) * iD[i];
             aF[0] += z[i][0] * qF; aF[1] += z[i][1] * qF; aF[2] += z[i][2] * qF;
-            // Omega <- P (X Omega X^T) P^T + S S^T / D
-            //   = Y + S y^T + y S^T with Y = X Omega X^T, w = Y U,
-            //     y = (beta/D^2 + 1/D)/2 S - w/D, beta = U.w
-            if (i > 0) shift_motion(rr[i], Om);
-            R wv[6];
-            sym6_mv(Om, U[i], wv);
-            const R dI = iD[i];
-            const R g2 = R(0.5) * (dot6(U[i], wv) * dI + R(1)) * dI;
-            R y[6];
-            y[0] = fma_(g2, z[i][0], -wv[0] * dI); y[1] = fma_(g2, z[i][1], -wv[1] * dI);
-            y[2] = fma_(g2, z[i][2], -wv[2] * dI);
-            y[3] = -wv[3] * dI; y[4] = -wv[4] * dI; y[5] = -wv[5] * dI;
-            sym6_add_joint_rank2(Om, z[i], y);
+            if (hand) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    hand[(kFiZ + 3 * i + c) * hstride] = z[i][c];
+                    if (i > 0) hand[(kFiRr + 3 * (i - 1) + c) * hstride] = rr[i][c];
+                }
+#pragma unroll
+                for (int c = 0; c < 6; ++c) hand[(kFiU + 6 * i + c) * hstride] = U[i][c];
+                hand[(kFiD + i) * hstride] = iD[i];
+            }
         }
     }
 
-    if (FORCE) {
-        // b = J_n M^-1 tau_F about p_n (remove the uniform gravity term)
+    if (FORCE && hand) {
         R b[6] = {aF[0], aF[1], aF[2], aF[3], aF[4], aF[5]};
         if (Cst.force_mode == 0) { b[3] += M.g[0]; b[4] += M.g[1]; b[5] += M.g[2]; }
-        chol6_solve(Om, b);   // x = Omega^-1 b: spatial force about p_n
-        R rf[3];
-        cross3(ree_w, b + 3, rf);
-        out.F[0] = b[3]; out.F[1] = b[4]; out.F[2] = b[5];
-        out.F[3] = b[0] - rf[0]; out.F[4] = b[1] - rf[1]; out.F[5] = b[2] - rf[2];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) hand[(kFiB + c) * hstride] = b[c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) hand[(kFiRee + c) * hstride] = ree_w[c];
+    } else if (FORCE) {
+        ForceIn<R> fi;
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { fi.z[i][c] = z[i][c]; fi.rr[i][c] = rr[i][c]; }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) fi.U[i][c] = U[i][c];
+            fi.iD[i] = iD[i];
+        }
+        // b = J_n M^-1 tau_F about p_n (remove the uniform gravity term)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) fi.b[c] = aF[c];
+        if (Cst.force_mode == 0) { fi.b[3] += M.g[0]; fi.b[4] += M.g[1]; fi.b[5] += M.g[2]; }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fi.ree[c] = ree_w[c];
+        force_estimate(fi, out.F);
     }
 }
 

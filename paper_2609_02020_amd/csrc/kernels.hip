@@ -110,6 +110,199 @@ __global__ __launch_bounds__(kRolloutBlock) void update_kernel(
     if (lane == 0) *counter = 0u;
 }
 
+// The same update with two waves per 64 samples (FP32, articulated-body
+// dynamics): wave 0 runs the dynamics of every step (the sequential chain
+// of a sample), wave 1 draws the perturbations one step ahead and evaluates
+// the force estimate of Eq. 13 (FORCE) and the running cost one step
+// behind, from what wave 0 leaves in LDS.  With 64 waves for K = 4096
+// the single-wave update is bound by one wave's instruction stream per
+// SIMD; the split halves that stream's length on the critical path and
+// puts a second SIMD of each CU to work.  Per sample the arithmetic is the
+// single-wave update's (the same functions in the same order).
+//
+// Per step s (both waves meet at one barrier per step):
+//   wave 0: du_s from nb[s&1] -> v, tau; dyn_step (factors into hb[s&1]); Euler
+//   wave 1: noise of step s+1 -> nb[(s+1)&1]; step s-1 from hb[(s-1)&1]:
+//           F_ee (FORCE), l(x, v), S += l
+// The handoff is struct-of-arrays in LDS, [value][lane] (conflict-free): the flat ForceIn
+// (stored by dyn_step link by link, as soon as the step is done with each
+// value) followed by the pre-step q, qd, the sampled v and the EE pose.
+constexpr int kHoQ = kFiCount, kHoQd = kHoQ + NJ, kHoV = kHoQd + NJ, kHoPee = kHoV + NJ, kHoRn = kHoPee + 3,
+              kHandoff = kHoRn + 9;   // 130 values per sample
+
+template <bool FORCE>
+__device__ __forceinline__ void handoff_read(const float* h, ForceIn<float>& fi, float* q, float* qd, float* v,
+                                             float* pee, float* Rn)
+{
+    if constexpr (FORCE) {
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                fi.z[i][c] = h[(kFiZ + 3 * i + c) * 64];
+                fi.rr[i][c] = i > 0 ? h[(kFiRr + 3 * (i - 1) + c) * 64] : 0.0f;
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) fi.U[i][c] = h[(kFiU + 6 * i + c) * 64];
+            fi.iD[i] = h[(kFiD + i) * 64];
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) fi.b[c] = h[(kFiB + c) * 64];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fi.ree[c] = h[(kFiRee + c) * 64];
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) { q[j] = h[(kHoQ + j) * 64]; qd[j] = h[(kHoQd + j) * 64]; v[j] = h[(kHoV + j) * 64]; }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pee[c] = h[(kHoPee + c) * 64];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Rn[c] = h[(kHoRn + c) * 64];
+}
+
+template <typename A, bool FORCE, bool COLL>
+__global__ __launch_bounds__(128) void update_split_kernel(
+    const ModelM<float>* __restrict__ Mp, const CostM<float>* __restrict__ Cp, const double* __restrict__ q0,
+    const double* __restrict__ qd0, const double* __restrict__ target, const double* U_nom,
+    uint64_t seed, uint32_t tick, int K, int T, double lambda, float* __restrict__ noise,
+    float* __restrict__ S, int merge, int lds_noise, A* __restrict__ parts, unsigned int* __restrict__ counter,
+    double* U_new, double* __restrict__ U_shift, int* __restrict__ status)
+{
+    extern __shared__ char dyn_lds[];
+    __shared__ float hb[2][kHandoff * 64];
+    __shared__ float nb[2][NJ * 64];
+    __shared__ float Us[kMaxT * NJ];
+    __shared__ A wl[64];
+    __shared__ int last;
+    __shared__ CostM<float> Csh;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave == 0) wave_copy(&Csh, Cp, sizeof(CostM<float>), lane);
+    for (int i = threadIdx.x; i < T * NJ; i += blockDim.x) Us[i] = float(U_nom[i]);
+    const int k = blockIdx.x * 64 + lane;
+    float* tile = reinterpret_cast<float*>(dyn_lds);   // [rows][65] (noise) or [64][65] (regeneration)
+    float* noise_k = (noise && k < K) ? noise + k : nullptr;
+    float* tile_k = lds_noise ? tile + lane : nullptr;
+    const ModelM<float>& Mc = *Mp;
+    const CostM<float>& Cc = Csh;
+    __syncthreads();
+
+    float q[NJ], qd[NJ], te[NJ];   // wave 0: the trajectory
+    float du[NJ], Ssum = 0.0f;     // wave 1: the noise recursion and the cost
+    TargetM<float> tg;
+    if (wave == 0) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) { q[j] = float(q0[j]); qd[j] = float(qd0[j]); te[j] = 0.0f; }
+        if (Cc.ext_mode == EXTW_CONST) const_ext_torque(Mc, Cc, q, te);
+    } else {
+        make_target(target, tg);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) du[j] = 0.0f;
+        float z[8];
+        normals8<float>(seed, tick, (uint32_t)k, 0u, z);
+        noise_step(Cc, z, du, 0);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            nb[0][j * 64 + lane] = du[j];
+            if (noise_k) noise_k[(size_t)j * K] = du[j];
+            if (tile_k) tile_k[j * kLdsRowPad] = du[j];
+        }
+    }
+    __syncthreads();
+    const int ext = Cc.ext_mode == EXTW_WALL ? EXTW_WALL : EXTW_NONE;
+    for (int s = 0; s <= T; ++s) {
+        if (wave == 0) {
+            if (s < T) {
+                const ModelM<float>& M = *per_step(&Mc);
+                const CostM<float>& C = *per_step(&Cc);
+                float v[NJ], tau[NJ];
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    v[j] = Us[s * NJ + j] + nb[s & 1][j * 64 + lane];
+                    tau[j] = v[j] + te[j];
+                }
+                StepOut<float> o;
+                float* h = &hb[s & 1][lane];
+                dyn_step<float, FORCE>(M, C, ext, q, qd, tau, v, o, h, 64);
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    h[(kHoQ + j) * 64] = q[j];
+                    h[(kHoQd + j) * 64] = qd[j];
+                    h[(kHoV + j) * 64] = v[j];
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) h[(kHoPee + c) * 64] = o.pee[c];
+#pragma unroll
+                for (int c = 0; c < 9; ++c) h[(kHoRn + c) * 64] = o.Rn[c];
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    qd[j] += o.qdd[j] * C.dt;
+                    q[j] += qd[j] * C.dt;
+                }
+            }
+        } else {
+            const ModelM<float>& M = *per_step(&Mc);
+            const CostM<float>& C = *per_step(&Cc);
+            if (s + 1 < T) {
+                float z[8];
+                normals8<float>(seed, tick, (uint32_t)k, (uint32_t)(s + 1), z);
+                noise_step(C, z, du, s + 1);
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    nb[(s + 1) & 1][j * 64 + lane] = du[j];
+                    if (noise_k) noise_k[(size_t)((s + 1) * NJ + j) * K] = du[j];
+                    if (tile_k) tile_k[((s + 1) * NJ + j) * kLdsRowPad] = du[j];
+                }
+            }
+            if (s >= 1) {
+                ForceIn<float> fi;
+                float qs[NJ], qds[NJ], v[NJ], pee[3], Rn[9];
+                handoff_read<FORCE>(&hb[(s - 1) & 1][lane], fi, qs, qds, v, pee, Rn);
+                float l = motion_cost(M, C, tg, pee, Rn) + joint_cost(M, C, qs, qds) + torque_cost(M, C, v);
+                if constexpr (FORCE) {
+                    float F[6];
+                    force_estimate(fi, F);
+                    l += force_cost(C, tg, F);
+                }
+                if constexpr (COLL) l += collision_cost(M, C, qs);
+                Ssum += l;
+            }
+        }
+        __syncthreads();
+    }
+    // terminal cost phi(x_T): wave 0 hands over the final state
+    if (wave == 0) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) { nb[0][j * 64 + lane] = q[j]; nb[1][j * 64 + lane] = qd[j]; }
+    }
+    __syncthreads();
+    float s_lane = INFINITY;
+    if (wave == 1) {
+        float qT[NJ], qdT[NJ], pee[3], Rn[9];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) { qT[j] = nb[0][j * 64 + lane]; qdT[j] = nb[1][j * 64 + lane]; }
+        fk_ee(Mc, qT, pee, Rn, (float*)nullptr, (float*)nullptr);
+        Ssum += Cc.w_T * (motion_cost(Mc, Cc, tg, pee, Rn) + joint_cost(Mc, Cc, qT, qdT));
+        if (k < K) {
+            s_lane = finite_(Ssum) ? Ssum : INFINITY;
+            S[k] = s_lane;
+        }
+    }
+    if (!merge) return;
+
+    const int P = 2 + T * NJ;
+    if (wave == 1) {
+        wave_sync();
+        wave_partial<float, A>(s_lane, lane, T, lambda, lds_noise ? tile : nullptr, Cc, seed, tick, (uint32_t)k,
+                               tile, wl, parts + (size_t)blockIdx.x * P);
+        __threadfence();
+        if (lane == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last || wave == 0) return;
+    __threadfence();
+    wave_merge<A>(parts, gridDim.x, T, lambda, U_nom, U_new, U_shift, status, lane, wl);
+    if (lane == 0) *counter = 0u;
+}
+
 // Batched update (a13): many independent problems (own arm, cost, K, T,
 // seed) in one persistent launch.  Work items are 64-sample tiles, ordered
 // longest horizon first on the host; every wave pops items from a
@@ -501,9 +694,29 @@ static hipError_t update_t(const UpdateArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename A, bool FORCE, bool COLL> static hipError_t update_split_t(const UpdateArgs& a, hipStream_t s)
+{
+    dim3 grid((a.K + 63) / 64);
+    const size_t rows = (size_t)a.T * NJ;
+    const size_t tile = rows * kLdsRowPad * sizeof(float);
+    const int lds_noise = a.merge && tile <= (size_t)kMaxDynLds;
+    const size_t dyn = lds_noise ? tile : (a.merge ? 64 * kLdsRowPad * sizeof(float) : 0);
+    float* noise = (float*)a.noise;
+    if (a.merge && !a.want_noise) noise = nullptr;
+    hipLaunchKernelGGL((update_split_kernel<A, FORCE, COLL>), grid, dim3(128), dyn, s, (const ModelM<float>*)a.model,
+                       (const CostM<float>*)a.cost, a.q0, a.qd0, a.target, a.U_nom, a.seed, (uint32_t)a.tick, a.K,
+                       a.T, a.lambda, noise, (float*)a.costs, a.merge, lds_noise, (A*)a.parts, a.counter, a.U_new,
+                       a.U_shift, a.status);
+    return hipGetLastError();
+}
+
 template <bool EXPLICIT, bool COLL>
 static hipError_t update_dispatch(int precision, bool acc64, bool force, const UpdateArgs& a, hipStream_t s)
 {
+    if (!EXPLICIT && a.waves_per_group == 2 && precision == MPPI_FP32) {
+        if (force) return acc64 ? update_split_t<double, true, COLL>(a, s) : update_split_t<float, true, COLL>(a, s);
+        return acc64 ? update_split_t<double, false, COLL>(a, s) : update_split_t<float, false, COLL>(a, s);
+    }
     if (precision == MPPI_FP64)
         return force ? update_t<double, double, true, EXPLICIT, COLL>(a, s)
                      : update_t<double, double, false, EXPLICIT, COLL>(a, s);

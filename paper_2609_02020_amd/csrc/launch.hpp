@@ -41,6 +41,8 @@ struct UpdateArgs {
     int* status;
     int dynamics;           // mppi_dynamics
     int collision;          // the collision term is on (n_pairs > 0)
+    int waves_per_group;    // 2: the two-wave split update (FP32 articulated-body
+                            // rollouts), else 1
 };
 
 // One fused launch: rollouts, per-wave Eq. 4 partials, last-block merge.

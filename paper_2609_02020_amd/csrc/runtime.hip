@@ -34,6 +34,7 @@ struct mppi_solver {
     void* h_costs = nullptr;     // pinned R [K]
     int* h_status = nullptr;     // pinned
     hipStream_t stream = nullptr;
+    int waves_per_group = 2;     // mppi_set_launch
 };
 
 namespace {
@@ -211,6 +212,7 @@ int update_enqueue_one(mppi_solver* h, const mppi_device_io* io, hipStream_t s, 
     a.status = io->status;
     a.dynamics = h->cost.dynamics;
     a.collision = h->cost.n_pairs > 0 ? 1 : 0;
+    a.waves_per_group = h->waves_per_group;
     return launch_update(h->cost.precision, acc64_of(h->cost), has_force(h->cost), a, s) == hipSuccess
                ? MPPI_OK
                : MPPI_EDEVICE;
@@ -333,6 +335,13 @@ int mppi_set_cost(mppi_handle_t h, const mppi_cost_params* cost)
     if (hipDeviceSynchronize() != hipSuccess) return MPPI_EDEVICE;
     h->cost = *cost;
     return upload_cost(h);
+}
+
+int mppi_set_launch(mppi_handle_t h, int waves_per_group)
+{
+    if (!h || (waves_per_group != 1 && waves_per_group != 2)) return MPPI_EINVAL;
+    h->waves_per_group = waves_per_group;
+    return MPPI_OK;
 }
 
 int mppi_rollout_async(mppi_handle_t h, const mppi_device_io* io, void* stream)

@@ -51,6 +51,42 @@ extern "C" void hc_step(const mppi_robot_params* rp, const mppi_cost_params* cp,
     }
 }
 
+// The force-cost step with its force-estimate inputs handed over through a
+// flat buffer (stride 3, as the two-wave update hands them over through
+// LDS) and the estimate formed from the buffer: F_split.  The same step's
+// inline estimate goes to F; qdd must be the same in both runs.
+extern "C" void hc_step_handoff(const mppi_robot_params* rp, const mppi_cost_params* cp, const double* q,
+                                const double* qd, const double* tau, const double* v, double* F,
+                                double* F_split, double* qdd_diff)
+{
+    ModelM<double> M;
+    CostM<double> C;
+    prep_model(*rp, M);
+    prep_cost(*cp, C);
+    const int ext = C.ext_mode == EXTW_WALL ? EXTW_WALL : EXTW_NONE;
+    StepOut<double> a, b;
+    dyn_step<double, true>(M, C, ext, q, qd, tau, v, a);
+    double buf[kFiCount * 3];
+    for (int i = 0; i < kFiCount * 3; ++i) buf[i] = NAN;
+    dyn_step<double, true>(M, C, ext, q, qd, tau, v, b, buf, 3);
+    ForceIn<double> fi;
+    for (int i = 0; i < NJ; ++i) {
+        for (int c = 0; c < 3; ++c) {
+            fi.z[i][c] = buf[(kFiZ + 3 * i + c) * 3];
+            fi.rr[i][c] = i > 0 ? buf[(kFiRr + 3 * (i - 1) + c) * 3] : 0.0;
+        }
+        for (int c = 0; c < 6; ++c) fi.U[i][c] = buf[(kFiU + 6 * i + c) * 3];
+        fi.iD[i] = buf[(kFiD + i) * 3];
+    }
+    for (int c = 0; c < 6; ++c) fi.b[c] = buf[(kFiB + c) * 3];
+    for (int c = 0; c < 3; ++c) fi.ree[c] = buf[(kFiRee + c) * 3];
+    force_estimate(fi, F_split);
+    for (int c = 0; c < 6; ++c) F[c] = a.F[c];
+    double d = 0.0;
+    for (int j = 0; j < NJ; ++j) d = std::fmax(d, std::fabs(a.qdd[j] - b.qdd[j]));
+    *qdd_diff = d;
+}
+
 template <typename R>
 static double rollout_t(const mppi_robot_params* rp, const mppi_cost_params* cp, const double* target,
                         const double* q0, const double* qd0, const double* U, uint64_t seed,

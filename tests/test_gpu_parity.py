@@ -236,3 +236,37 @@ def test_maximum_horizon(ora, workloads, precision):
     note = check_update(ora, case, out, cost["lambda"], S_ref, U_ref, "T=256")
     if note:
         print(note)
+
+
+@pytest.mark.parametrize("which,i,K,T,extra", [("wall_k4096", 0, 4096, 18, {}), ("wall_k4096", 1, 4097, 3, {}),
+                                               ("wall_k4096", 2, 65, 1, {"noise_rho": 0.7}),
+                                               ("collision_k4096", 0, 4096, 18, {}),
+                                               ("wall_k4096", 3, 640, 40, {}),
+                                               ("single_k256", 0, 256, 18, {}),
+                                               ("single_k256", 1, 1000, 5, {"noise_rho": 0.5})])
+def test_two_wave_update_equals_one_wave(workloads, which, i, K, T, extra):
+    """The two-wave update (dynamics on one wave, noise, force estimate and
+    cost on the other) computes every sample as the one-wave update does:
+    the same costs, noise and U_new (the oracle parity of the default
+    launch is covered by the other tests)."""
+    base = workloads[which][i]
+    U = np.asarray(base["U_nom"])
+    U = np.concatenate([U] * (T // len(U) + 1))[:T]
+    cost = dict(base["cost"], K=K, T=T, **extra)
+    case = dict(base, cost=cost, U_nom=U.tolist())
+    outs = []
+    for w in (1, 2):
+        solver = B.Solver(case["robot"], cost, B.FP32)
+        solver.set_launch(w)
+        outs.append(device_update(solver, case, case["seed"], 12, B.FP32))
+        solver.close()
+    one, two = outs
+    assert one["status"] == two["status"] == B.OK
+    assert np.array_equal(one["noise"], two["noise"])
+    rel = cost_rel_err(two["costs"], one["costs"])
+    print("%s[%d] K=%d T=%d: max rel cost difference %.3g, bitwise equal %s"
+          % (which, i, K, T, rel.max(), np.array_equal(one["costs"], two["costs"])))
+    assert rel.max() <= 1e-6
+    assert np.abs(one["U_new"] - two["U_new"]).max() <= 1e-6
+    assert np.array_equal(one["U_shift"][:-1], two["U_shift"][:-1]) or \
+        np.abs(one["U_shift"] - two["U_shift"]).max() <= 1e-6

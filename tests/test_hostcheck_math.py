@@ -127,6 +127,27 @@ def test_rollout_cost_matches_oracle(hc, ora, workloads, which, prec, tol):
             assert np.abs(noise - n_ref).max() < (1e-12 if prec == B.FP64 else 1e-4)
 
 
+def test_force_estimate_through_the_handoff(hc, workloads):
+    """The two-wave update hands the force-estimate inputs over through a
+    flat buffer: every slot of the layout is written (no NaN left), and the
+    estimate formed from the buffer equals the inline one (FP64)."""
+    D = C.POINTER(C.c_double)
+    hc.hc_step_handoff.argtypes = [C.POINTER(B.RobotParams), C.POINTER(B.CostParams), D, D, D, D, D, D, D]
+    rng = np.random.default_rng(5)
+    for case in workloads["wall_k4096"][:4]:
+        rp = B.robot_params(case["robot"])
+        cp = B.cost_params(case["cost"], B.FP64)
+        for _ in range(3):
+            q = np.asarray(case["q0"]) + rng.uniform(-0.3, 0.3, 7)
+            qd = rng.uniform(-1, 1, 7)
+            tau = rng.normal(size=7) * 5
+            F, Fs, dq = np.zeros(6), np.zeros(6), np.zeros(1)
+            hc.hc_step_handoff(C.byref(rp), C.byref(cp), _d(q), _d(qd), _d(tau), _d(tau),
+                               F.ctypes.data_as(D), Fs.ctypes.data_as(D), dq.ctypes.data_as(D))
+            assert np.isfinite(Fs).all() and dq[0] == 0.0
+            assert np.array_equal(F, Fs)
+
+
 @pytest.mark.parametrize("rho", [0.5, 0.95])
 @pytest.mark.parametrize("prec,tol", [(B.FP64, 1e-9), (B.FP32, 1e-4)])
 def test_correlated_noise_rollout_matches_oracle(hc, ora, workloads, rho, prec, tol):
