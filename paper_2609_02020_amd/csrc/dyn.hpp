@@ -15,7 +15,8 @@
 //         the last link, by the outward recursion
 //           Omega_i = P_i X_i Omega_{i-1} X_i^T P_i^T + S D_i^-1 S^T,
 //           P_i = 1 - S D_i^-1 U_i^T,   Omega_{-1} = 0 (fixed base);
-//       - J_n M^-1 tau_F from one extra zero-velocity solve;
+//       - J_n M^-1 tau_F from one extra zero-velocity solve with the same
+//         factors (force_estimate, after the step);
 //     then x = Omega_n^-1 (J_n M^-1 tau_F) by a 6x6 Cholesky and
 //     F_ee = T^-T x (T: last-link origin -> EE point, world axes).
 //   * the running cost of Eqs. 9-14 and the semi-implicit Euler step of
@@ -399,20 +400,19 @@ template <typename R> MPPI_HD void chol6_solve(const Sym6<R>& S, R* b)
 // spatial force about p_n and the EE wrench is F = x_f,
 // N = x_n - (p_ee - p_n) x x_f.
 // What the force estimate needs from one articulated-body step: the joint
-// axes, the link translations r_1..r_6, the factors U_i and 1/D_i, the
-// zero-velocity response b = J_n M^-1 tau_F about p_n and the EE offset
-// from p_n (all world axes).  force_estimate() turns it into F_ee.
+// axes, the link translations r_0..r_6, the factors U_i and 1/D_i and the
+// EE offset from p_n (all world axes).  force_estimate() turns it, with the
+// sampled torques, into F_ee.
 template <typename R> struct ForceIn {
     R z[NJ][3];
-    R rr[NJ][3];   // rr[0] unused
+    R rr[NJ][3];
     R U[NJ][6];
     R iD[NJ];
-    R b[6];
     R ree[3];
 };
 // Flat layout of a ForceIn for a handoff through memory (index of each
-// value; rr[0] is not stored): 97 values.
-constexpr int kFiZ = 0, kFiRr = 21, kFiU = 39, kFiD = 81, kFiB = 88, kFiRee = 94, kFiCount = 97;
+// value): 94 values.
+constexpr int kFiZ = 0, kFiRr = 21, kFiU = 42, kFiD = 84, kFiRee = 91, kFiCount = 94;
 
 template <typename R> struct StepOut {
     R qdd[NJ];
@@ -536,14 +536,49 @@ template <typename R> MPPI_HD void shift_motion(const R* r, Sym6<R>& M)
     for (int i = 0; i < 9; ++i) M.B[i] += W[i];
 }
 
-// EE wrench estimate of Eq. 13 from the factors of one step:
+// EE wrench estimate of Eq. 13 from the factors of one step and the
+// sampled torques v:
+//   b = J_n M^-1 tau_F about p_n by a zero-velocity articulated-body solve
+//       with the same factors (tip to root: uF_i = tau_F,i - S_i.pF,
+//       pF += U_i uF_i / D_i shifted to the parent; root to tip:
+//       qF_i = (uF_i - U_i.aF) / D_i, aF += S_i qF_i), tau_F = v - g(q)
+//       through a uniform pseudo-acceleration -g when force_mode is 0;
 //   Omega <- P (X Omega X^T) P^T + S S^T / D, link by link from the root
 //          = Y + S y^T + y S^T with Y = X Omega X^T, w = Y U,
 //            y = (beta/D^2 + 1/D)/2 S - w/D, beta = U.w,
 // then x = Omega_n^-1 b (6x6 Cholesky) is the spatial force about p_n and
 // F = (x_f, x_n - ree x x_f).
-template <typename R> MPPI_HD void force_estimate(const ForceIn<R>& fi, R* F)
+template <typename R>
+MPPI_HD void force_estimate(const ForceIn<R>& fi, const R* v, const R* g, int force_mode, R* F)
 {
+    R uF[NJ];
+    R pF[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = NJ - 1; i >= 0; --i) {
+        uF[i] = v[i] - dot3(fi.z[i], pF);
+        if (i > 0) {
+            const R uFD = uF[i] * fi.iD[i];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) pF[a] += fi.U[i][a] * uFD;
+            R rf[3];
+            cross3(fi.rr[i], pF + 3, rf);
+            pF[0] += rf[0]; pF[1] += rf[1]; pF[2] += rf[2];
+        }
+    }
+    R aF[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    if (force_mode == 0) { aF[3] = -g[0]; aF[4] = -g[1]; aF[5] = -g[2]; }
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        R wxr[3];
+        cross3(aF, fi.rr[i], wxr);
+        aF[3] += wxr[0]; aF[4] += wxr[1]; aF[5] += wxr[2];
+        const R qF = (uF[i] - dot6(fi.U[i], aF)) * fi.iD[i];
+        aF[0] += fi.z[i][0] * qF; aF[1] += fi.z[i][1] * qF; aF[2] += fi.z[i][2] * qF;
+    }
+    // remove the uniform gravity term
+    R b[6] = {aF[0], aF[1], aF[2], aF[3], aF[4], aF[5]};
+    if (force_mode == 0) { b[3] += g[0]; b[4] += g[1]; b[5] += g[2]; }
+
     Sym6<R> Om;
 #pragma unroll
     for (int k = 0; k < 6; ++k) { Om.A[k] = R(0); Om.C[k] = R(0); }
@@ -562,7 +597,6 @@ template <typename R> MPPI_HD void force_estimate(const ForceIn<R>& fi, R* F)
         y[3] = -wv[3] * dI; y[4] = -wv[4] * dI; y[5] = -wv[5] * dI;
         sym6_add_joint_rank2(Om, fi.z[i], y);
     }
-    R b[6] = {fi.b[0], fi.b[1], fi.b[2], fi.b[3], fi.b[4], fi.b[5]};
     chol6_solve(Om, b);   // x = Omega^-1 b: spatial force about p_n
     R rf[3];
     cross3(fi.ree, b + 3, rf);
@@ -669,14 +703,13 @@ MPPI_HD void dyn_step(const ModelM<R>& M, const CostM<R>& Cst, int ext, const R*
     }
 
     // ---- pass 2 (tip -> root)
-    R U[NJ][6], iD[NJ], u[NJ], uF[NJ];
+    R U[NJ][6], iD[NJ], u[NJ];
     Sym6<R> IA;
 #pragma unroll
     for (int a = 0; a < 6; ++a) { IA.A[a] = R(0); IA.C[a] = R(0); }
 #pragma unroll
     for (int a = 0; a < 9; ++a) IA.B[a] = R(0);
     R pacc[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-    R pF[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
     for (int i = NJ - 1; i >= 0; --i) {
         const LinkM<R>& L = M.L[i];
@@ -699,7 +732,6 @@ MPPI_HD void dyn_step(const ModelM<R>& M, const CostM<R>& Cst, int ext, const R*
         }
         iD[i] = rcp_(dot3(zi, U[i]) + L.arm);
         u[i] = tau[i] - dot3(zi, p);
-        if (FORCE) uF[i] = v[i] - dot3(zi, pF);
         if (i > 0) {
             R UD[6];
 #pragma unroll
@@ -715,20 +747,11 @@ MPPI_HD void dyn_step(const ModelM<R>& M, const CostM<R>& Cst, int ext, const R*
             R rf[3];
             cross3(rr[i], pacc + 3, rf);
             pacc[0] += rf[0]; pacc[1] += rf[1]; pacc[2] += rf[2];
-            if (FORCE) {
-                const R uFD = uF[i] * iD[i];
-#pragma unroll
-                for (int a = 0; a < 6; ++a) pF[a] += U[i][a] * uFD;
-                cross3(rr[i], pF + 3, rf);
-                pF[0] += rf[0]; pF[1] += rf[1]; pF[2] += rf[2];
-            }
         }
     }
 
     // ---- pass 3 (root -> tip)
     R a[6] = {R(0), R(0), R(0), -M.g[0], -M.g[1], -M.g[2]};
-    R aF[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-    if (FORCE && Cst.force_mode == 0) { aF[3] = -M.g[0]; aF[4] = -M.g[1]; aF[5] = -M.g[2]; }
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
         // a' = X a + c
@@ -740,29 +763,19 @@ MPPI_HD void dyn_step(const ModelM<R>& M, const CostM<R>& Cst, int ext, const R*
         out.qdd[i] = qddi;
         a[0] = an[0] + z[i][0] * qddi; a[1] = an[1] + z[i][1] * qddi; a[2] = an[2] + z[i][2] * qddi;
         a[3] = an[3]; a[4] = an[4]; a[5] = an[5];
-        if (FORCE) {
-            cross3(aF, rr[i], wxr);
-            aF[3] += wxr[0]; aF[4] += wxr[1]; aF[5] += wxr[2];
-            const R qF = (uF[i] - dot6(U[i], aF)) * iD[i];
-            aF[0] += z[i][0] * qF; aF[1] += z[i][1] * qF; aF[2] += z[i][2] * qF;
-            if (hand) {
+        if (FORCE && hand) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    hand[(kFiZ + 3 * i + c) * hstride] = z[i][c];
-                    if (i > 0) hand[(kFiRr + 3 * (i - 1) + c) * hstride] = rr[i][c];
-                }
-#pragma unroll
-                for (int c = 0; c < 6; ++c) hand[(kFiU + 6 * i + c) * hstride] = U[i][c];
-                hand[(kFiD + i) * hstride] = iD[i];
+            for (int c = 0; c < 3; ++c) {
+                hand[(kFiZ + 3 * i + c) * hstride] = z[i][c];
+                hand[(kFiRr + 3 * i + c) * hstride] = rr[i][c];
             }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) hand[(kFiU + 6 * i + c) * hstride] = U[i][c];
+            hand[(kFiD + i) * hstride] = iD[i];
         }
     }
 
     if (FORCE && hand) {
-        R b[6] = {aF[0], aF[1], aF[2], aF[3], aF[4], aF[5]};
-        if (Cst.force_mode == 0) { b[3] += M.g[0]; b[4] += M.g[1]; b[5] += M.g[2]; }
-#pragma unroll
-        for (int c = 0; c < 6; ++c) hand[(kFiB + c) * hstride] = b[c];
 #pragma unroll
         for (int c = 0; c < 3; ++c) hand[(kFiRee + c) * hstride] = ree_w[c];
     } else if (FORCE) {
@@ -775,13 +788,9 @@ MPPI_HD void dyn_step(const ModelM<R>& M, const CostM<R>& Cst, int ext, const R*
             for (int c = 0; c < 6; ++c) fi.U[i][c] = U[i][c];
             fi.iD[i] = iD[i];
         }
-        // b = J_n M^-1 tau_F about p_n (remove the uniform gravity term)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) fi.b[c] = aF[c];
-        if (Cst.force_mode == 0) { fi.b[3] += M.g[0]; fi.b[4] += M.g[1]; fi.b[5] += M.g[2]; }
 #pragma unroll
         for (int c = 0; c < 3; ++c) fi.ree[c] = ree_w[c];
-        force_estimate(fi, out.F);
+        force_estimate(fi, v, M.g, Cst.force_mode, out.F);
     }
 }
 

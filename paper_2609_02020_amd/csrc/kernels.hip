@@ -127,8 +127,9 @@ __global__ __launch_bounds__(kRolloutBlock) void update_kernel(
 // The handoff is struct-of-arrays in LDS, [value][lane] (conflict-free): the flat ForceIn
 // (stored by dyn_step link by link, as soon as the step is done with each
 // value) followed by the pre-step q, qd, the sampled v and the EE pose.
+// The zero-velocity solve of the force estimate runs on wave 1 too.
 constexpr int kHoQ = kFiCount, kHoQd = kHoQ + NJ, kHoV = kHoQd + NJ, kHoPee = kHoV + NJ, kHoRn = kHoPee + 3,
-              kHandoff = kHoRn + 9;   // 130 values per sample
+              kHandoff = kHoRn + 9;   // 127 values per sample
 
 template <bool FORCE>
 __device__ __forceinline__ void handoff_read(const float* h, ForceIn<float>& fi, float* q, float* qd, float* v,
@@ -140,14 +141,12 @@ __device__ __forceinline__ void handoff_read(const float* h, ForceIn<float>& fi,
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 fi.z[i][c] = h[(kFiZ + 3 * i + c) * 64];
-                fi.rr[i][c] = i > 0 ? h[(kFiRr + 3 * (i - 1) + c) * 64] : 0.0f;
+                fi.rr[i][c] = h[(kFiRr + 3 * i + c) * 64];
             }
 #pragma unroll
             for (int c = 0; c < 6; ++c) fi.U[i][c] = h[(kFiU + 6 * i + c) * 64];
             fi.iD[i] = h[(kFiD + i) * 64];
         }
-#pragma unroll
-        for (int c = 0; c < 6; ++c) fi.b[c] = h[(kFiB + c) * 64];
 #pragma unroll
         for (int c = 0; c < 3; ++c) fi.ree[c] = h[(kFiRee + c) * 64];
     }
@@ -259,7 +258,7 @@ __global__ __launch_bounds__(128) void update_split_kernel(
                 float l = motion_cost(M, C, tg, pee, Rn) + joint_cost(M, C, qs, qds) + torque_cost(M, C, v);
                 if constexpr (FORCE) {
                     float F[6];
-                    force_estimate(fi, F);
+                    force_estimate(fi, v, M.g, C.force_mode, F);
                     l += force_cost(C, tg, F);
                 }
                 if constexpr (COLL) l += collision_cost(M, C, qs);

@@ -73,14 +73,13 @@ extern "C" void hc_step_handoff(const mppi_robot_params* rp, const mppi_cost_par
     for (int i = 0; i < NJ; ++i) {
         for (int c = 0; c < 3; ++c) {
             fi.z[i][c] = buf[(kFiZ + 3 * i + c) * 3];
-            fi.rr[i][c] = i > 0 ? buf[(kFiRr + 3 * (i - 1) + c) * 3] : 0.0;
+            fi.rr[i][c] = buf[(kFiRr + 3 * i + c) * 3];
         }
         for (int c = 0; c < 6; ++c) fi.U[i][c] = buf[(kFiU + 6 * i + c) * 3];
         fi.iD[i] = buf[(kFiD + i) * 3];
     }
-    for (int c = 0; c < 6; ++c) fi.b[c] = buf[(kFiB + c) * 3];
     for (int c = 0; c < 3; ++c) fi.ree[c] = buf[(kFiRee + c) * 3];
-    force_estimate(fi, F_split);
+    force_estimate(fi, v, M.g, C.force_mode, F_split);
     for (int c = 0; c < 6; ++c) F[c] = a.F[c];
     double d = 0.0;
     for (int j = 0; j < NJ; ++j) d = std::fmax(d, std::fabs(a.qdd[j] - b.qdd[j]));

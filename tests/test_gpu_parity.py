@@ -247,7 +247,7 @@ def test_maximum_horizon(ora, workloads, precision):
 def test_two_wave_update_equals_one_wave(workloads, which, i, K, T, extra):
     """The two-wave update (dynamics on one wave, noise, force estimate and
     cost on the other) computes every sample as the one-wave update does:
-    the same costs, noise and U_new (the oracle parity of the default
+    costs, noise and U_new equal to FP32 rounding (the oracle parity of the default
     launch is covered by the other tests)."""
     base = workloads[which][i]
     U = np.asarray(base["U_nom"])
