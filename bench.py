@@ -45,11 +45,11 @@ FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (AMD published)
 # known size (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 on gfx950), taken on the
 # kernel sources whose digest is recorded here; reported as null once the
 # sources differ.
-PROFILED_DIGEST = "d3f7e19c3d74f1b6"
-PROFILED_TRAFFIC = {"update_kernel": 685620 + 54145,        # K=4096, T=18 contact workload
-                    "batch_kernel": 6592875 + 6081307,      # 64-problem batch (W=2 x 1024; the
+PROFILED_DIGEST = "cc19d44ee1275468"
+PROFILED_TRAFFIC = {"update_split_kernel": 784384 + 56210,  # K=4096, T=18 contact workload
+                    "batch_kernel": 6966240 + 6076712,      # 64-problem batch (W=2 x 1024; the
                                                             # fastest shapes differ by < 1 %)
-                    "mlp_train": 15934686 + 3988256}        # forward/backward + weight gradients, 512 rows
+                    "mlp_train": 15934676 + 3988256}        # forward/backward + weight gradients, 512 rows
 
 
 def kernel_source_digest():
