@@ -82,6 +82,9 @@ def parse():
     p.add_argument("--batch-ticks", type=int, default=30,
                    help="graph replays of the 64-problem batched tick (0: skip)")
     p.add_argument("--no-mlp", action="store_true", help="skip the proposal-network timings")
+    p.add_argument("--cpu-study", type=float, default=0.0, metavar="SECONDS",
+                   help="only time the oracle (no GPU): the single-update, contact and precision "
+                        "workloads on one thread and on every core, SECONDS each, one JSON line")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="after the timed region, copy a MIB-sized buffer 5 times (a plain copy "
                         "kernel of known size, to calibrate HBM byte counters)")
@@ -105,7 +108,46 @@ def cpu_baseline(case, budget_s):
     return {"value": n / el, "unit": "Hz", "cores": ora.max_threads(), "kind": "oracle",
             "sample": "%d full oracle updates (K=%d, T=%d, FP64, OpenMP over samples) in %.1f s; "
                       "%.3g sample-steps/s" % (n, K, T, el, n * K * T / el),
-            "cpu": platform.processor() or platform.machine()}
+            "cpu": cpu_model()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_study(budget_s):
+    """The oracle's update rate and sample-steps/s on one thread and on all
+    cores for the single-update (K=256, T=18, position cost), contact
+    (K=4096, T=18) and precision (K=16384, T=36) workloads."""
+    from oracle import oracle as ora
+    from paper_2609_02020_amd import inputs
+    ora.build()
+    W = inputs.load()
+    rows = []
+    for name in ("single_k256", "wall_k4096", "precision_k16384"):
+        case = W[name][0]
+        K, T = case["cost"]["K"], case["cost"]["T"]
+        for threads in (1, ora.max_threads()):
+            n, t0 = 0, time.perf_counter()
+            while True:
+                ora.update(case["robot"], case["cost"], case["target"], case["q0"], case["qd0"], case["U_nom"],
+                           case["seed"], n, nthreads=threads, want_noise=False)
+                n += 1
+                el = time.perf_counter() - t0
+                if el >= budget_s:
+                    break
+            rows.append({"workload": "%s[0]" % name, "K": K, "T": T, "threads": threads, "updates": n,
+                         "seconds": el, "updates_per_s": n / el, "sample_steps_per_s": n * K * T / el})
+    return {"cpu": cpu_model(), "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "rows": rows}
 
 
 # Proposal network 21-256-256-256-126 (unpadded dimensions): a forward
@@ -331,6 +373,9 @@ def batch_bench(B, cases, torch, dev, ticks):
 
 def main():
     args = parse()
+    if args.cpu_study > 0:
+        print(json.dumps({"cpu_study": cpu_study(args.cpu_study)}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
@@ -399,9 +444,12 @@ def main():
     qh, qdh = q.cpu().numpy(), qd.cpu().numpy()
     for i in range(10):
         solver.update(qh, qdh, case["target"], Uh, case["seed"], 10**6 + i)
-    n_host, th = 100, time.perf_counter()
+    n_host, th = 200, time.perf_counter()
+    host_ms = []
     for i in range(n_host):
+        t1 = time.perf_counter()
         st, Uh2, _ = solver.update(qh, qdh, case["target"], Uh, case["seed"], 2 * 10**6 + i)
+        host_ms.append(1e3 * (time.perf_counter() - t1))
     host_rate = n_host / (time.perf_counter() - th)
 
     out = {
@@ -413,7 +461,9 @@ def main():
                    "K": K, "T": T, "dt": dt, "dof": 7, "precision": "fp32 rollouts"},
         "rollout_steps_per_s": K * T / roll_s,
         "update_kernel_ms": float(np.mean(roll_ms)),
+        "update_kernel_ms_p5_p50_p95": [float(np.percentile(roll_ms, x)) for x in (5, 50, 95)],
         "host_api_update_hz": host_rate,
+        "host_api_update_ms_p5_p50_p95": [float(np.percentile(host_ms, x)) for x in (5, 50, 95)],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                      "traffic": profiled_traffic("update_split_kernel"),
