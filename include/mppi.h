@@ -129,9 +129,9 @@ typedef struct {
      * runs that many MPPI iterations on the same state, each from the
      * previous one's U_new, iteration i drawing its noise with the Philox
      * tick word iterations * tick + i; costs, noise and status are the last
-     * iteration's.  Batches and the stage-isolated calls
-     * (mppi_rollout_async, mppi_weights_async) take one iteration only
-     * (MPPI_ENOTSUP otherwise). */
+     * iteration's.  The problems of a batch must share one iteration count;
+     * the stage-isolated calls (mppi_rollout_async, mppi_weights_async)
+     * take one iteration only (MPPI_ENOTSUP otherwise). */
     double noise_rho;
     int iterations;
 } mppi_cost_params;
@@ -236,8 +236,8 @@ typedef struct {
 /* Creates a batch of n >= 1 problems.  Copies every struct; validates each
  * problem as mppi_create does; builds the work list (64-sample tiles,
  * longest horizon first) and the device tables.  Errors: MPPI_EINVAL,
- * MPPI_ENOTSUP (FP64, T > 64, the explicit-M dynamics or more than one
- * iteration per update), MPPI_ENOMEM, MPPI_EDEVICE. */
+ * MPPI_ENOTSUP (FP64, T > 64, the explicit-M dynamics or iteration counts
+ * that differ between problems), MPPI_ENOMEM, MPPI_EDEVICE. */
 int mppi_batch_create(const mppi_problem_desc* descs, int n, mppi_batch_t* out);
 int mppi_batch_destroy(mppi_batch_t b);
 

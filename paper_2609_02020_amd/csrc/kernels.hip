@@ -333,14 +333,14 @@ __global__ __launch_bounds__(64 * W) void batch_kernel(
     const int2* __restrict__ items, int nitems, unsigned int* queue, unsigned int* done, unsigned int* counters, const double* __restrict__ q,
     const double* __restrict__ qd, const double* __restrict__ target, const double* U_nom, double* U_new,
     double* U_shift, float* __restrict__ costs, int* __restrict__ status, const uint64_t* __restrict__ seeds,
-    const uint64_t* __restrict__ tickp, double* __restrict__ parts)
+    const uint64_t* __restrict__ tickp, int iter, int niter, double* __restrict__ parts)
 {
     __shared__ CostM<float> Csh[W];
     __shared__ float Us[W][kMaxTBatch * NJ];
     __shared__ float tr[W][64 * kLdsRowPad];
     __shared__ double wl[W][64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const uint32_t tick = (uint32_t)*tickp;
+    const uint32_t tick = (uint32_t)(*tickp * (uint64_t)niter + (uint64_t)iter);
     // Queue pops, completion counts and the exit count are atomics that every
     // lane executes (adding 1 on lane 0 and 0 elsewhere) with the result
     // taken from lane 0, so the control flow around them stays uniform: a
@@ -760,7 +760,8 @@ template <int W, bool COLL> static hipError_t batch_t(const BatchArgs& a, int gr
 {
     hipLaunchKernelGGL((batch_kernel<W, COLL>), dim3(groups), dim3(64 * W), 0, s, (const BatchProblem*)a.probs,
                        (const ModelM<float>*)a.models, (const int2*)a.items, a.nitems, a.queue, a.done, a.counters,
-                       a.q, a.qd, a.target, a.U_nom, a.U_new, a.U_shift, a.costs, a.status, a.seeds, a.tick, a.parts);
+                       a.q, a.qd, a.target, a.U_nom, a.U_new, a.U_shift, a.costs, a.status, a.seeds, a.tick,
+                       a.iter, a.niter, a.parts);
     return hipGetLastError();
 }
 

@@ -69,6 +69,7 @@ struct BatchArgs {
     const uint64_t* tick;   // [1] (device)
     double* parts;          // partials, sized by the host
     int collision;          // some problem has the collision term
+    int iter, niter;        // iteration iter of niter: Philox tick word = *tick * niter + iter
 };
 
 // Persistent batched update: `groups` workgroups of `waves_per_group` waves.

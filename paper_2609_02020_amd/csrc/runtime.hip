@@ -493,6 +493,8 @@ struct mppi_batch {
     uint64_t* d_tick = nullptr;   // [0]: graph replays (advanced by the graph), [1]: eager launches
     int wpg = 1, groups = 1024;
     int collision = 0;            // some problem has the collision term
+    int iterations = 1;           // MPPI iterations per update (the same for every problem)
+    double* d_iter = nullptr;     // [2][u_total]: U of the intermediate iterations
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
 };
@@ -513,6 +515,7 @@ void batch_release(mppi_batch* b)
     (void)hipFree(b->d_items);
     (void)hipFree(b->d_sync);
     (void)hipFree(b->d_parts);
+    (void)hipFree(b->d_iter);
     (void)hipFree(b->d_tick);
     delete b;
 }
@@ -539,7 +542,31 @@ BatchArgs batch_args(mppi_batch* b, const mppi_batch_io* io, const uint64_t* tic
     a.tick = tick_slot;
     a.parts = b->d_parts;
     a.collision = b->collision;
+    a.iter = 0;
+    a.niter = 1;
     return a;
+}
+
+// The update as b->iterations chained launches: iteration i reads the
+// previous one's U_new (io->U_nominal for the first), writes one of two
+// intermediate buffers (io->U_new and io->U_shift for the last) and draws
+// with the Philox tick word iterations * tick + i (tick read from tick_slot
+// on the device, so a captured graph replays it).
+bool enqueue_batch_iterations(mppi_batch* b, const mppi_batch_io* io, const uint64_t* tick_slot, hipStream_t s)
+{
+    const int n = b->iterations;
+    for (int i = 0; i < n; ++i) {
+        BatchArgs a = batch_args(b, io, tick_slot);
+        a.iter = i;
+        a.niter = n;
+        if (i > 0) a.U_nom = b->d_iter + (size_t)((i - 1) & 1) * b->u_total;
+        if (i < n - 1) {
+            a.U_new = b->d_iter + (size_t)(i & 1) * b->u_total;
+            a.U_shift = nullptr;
+        }
+        if (launch_batch(a, b->wpg, b->groups, s) != hipSuccess) return false;
+    }
+    return true;
 }
 
 int check_batch_io(const mppi_batch* b, const mppi_batch_io* io)
@@ -563,7 +590,8 @@ int mppi_batch_create(const mppi_problem_desc* descs, int n, mppi_batch_t* out)
         if (!st) st = validate_cost(descs[p].cost);
         if (st) return st;
         if (descs[p].cost->precision != MPPI_FP32 || descs[p].cost->T > kMaxTBatch ||
-            descs[p].cost->dynamics != MPPI_DYN_ABA || iterations_of(*descs[p].cost) > 1)
+            descs[p].cost->dynamics != MPPI_DYN_ABA ||
+            iterations_of(*descs[p].cost) != iterations_of(*descs[0].cost))
             return MPPI_ENOTSUP;
     }
     int ndev = 0;
@@ -571,6 +599,7 @@ int mppi_batch_create(const mppi_problem_desc* descs, int n, mppi_batch_t* out)
     mppi_batch* b = new (std::nothrow) mppi_batch;
     if (!b) return MPPI_ENOMEM;
     b->n = n;
+    b->iterations = iterations_of(*descs[0].cost);
     b->robot.resize(n);
     b->cost.resize(n);
     b->u_off.resize(n);
@@ -611,6 +640,7 @@ int mppi_batch_create(const mppi_problem_desc* descs, int n, mppi_batch_t* out)
               hipMalloc(&b->d_items, sizeof(int2) * items.size()) == hipSuccess &&
               hipMalloc(&b->d_sync, sizeof(unsigned int) * (2 + n)) == hipSuccess &&
               hipMalloc(&b->d_parts, sizeof(double) * parts_total) == hipSuccess &&
+              hipMalloc(&b->d_iter, sizeof(double) * 2 * b->u_total) == hipSuccess &&
               hipMalloc(&b->d_tick, 2 * sizeof(uint64_t)) == hipSuccess;
     if (!ok) { batch_release(b); return MPPI_ENOMEM; }
     std::vector<CostM<float>> cf(n);
@@ -714,8 +744,7 @@ int mppi_batch_update_async(mppi_batch_t b, const mppi_batch_io* io, uint64_t ti
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     if (launch_set_tick(b->d_tick + 1, tick, s) != hipSuccess) return MPPI_EDEVICE;
-    BatchArgs a = batch_args(b, io, b->d_tick + 1);
-    return launch_batch(a, b->wpg, b->groups, s) == hipSuccess ? MPPI_OK : MPPI_EDEVICE;
+    return enqueue_batch_iterations(b, io, b->d_tick + 1, s) ? MPPI_OK : MPPI_EDEVICE;
 }
 
 int mppi_batch_autotune(mppi_batch_t b, const mppi_batch_io* io, int reps, void* stream, int* best_wpg,
@@ -767,9 +796,8 @@ int mppi_batch_graph_capture(mppi_batch_t b, const mppi_batch_io* io)
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     hipStream_t cs;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return MPPI_EDEVICE;
-    BatchArgs a = batch_args(b, io, b->d_tick);
     bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-    ok = ok && launch_batch(a, b->wpg, b->groups, cs) == hipSuccess;
+    ok = ok && enqueue_batch_iterations(b, io, b->d_tick, cs);
     ok = ok && launch_advance_tick(b->d_tick, cs) == hipSuccess;
     hipGraph_t g = nullptr;
     ok = (hipStreamEndCapture(cs, &g) == hipSuccess) && ok && g;

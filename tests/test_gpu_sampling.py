@@ -129,8 +129,8 @@ def test_one_iteration_is_the_plain_update(workloads):
 
 
 def test_multi_iteration_limits(workloads):
-    """Stage-isolated calls and batches take one iteration; a batch takes the
-    correlated noise."""
+    """Stage-isolated calls take one iteration; the problems of a batch share
+    one iteration count."""
     torch, dev = torch_dev()
     case = with_cost(workloads["wall_k4096"][0], iterations=2)
     solver = B.Solver(case["robot"], case["cost"], B.FP32)
@@ -145,8 +145,9 @@ def test_multi_iteration_limits(workloads):
         solver.rollout_async(io)
     assert e.value.status == B.ENOTSUP
     solver.close()
+    other = with_cost(workloads["wall_k4096"][1], iterations=3)
     with pytest.raises(B.MppiError) as e:
-        B.Batch([(case["robot"], case["cost"])])
+        B.Batch([(case["robot"], case["cost"]), (other["robot"], other["cost"])])
     assert e.value.status == B.ENOTSUP
 
 
@@ -176,4 +177,57 @@ def test_correlated_noise_in_a_batch_equals_single_problem(workloads):
         u0 = batch.u_off[p] // 7
         assert np.abs(io["U_new"][u0:u0 + c["cost"]["T"]].cpu().numpy() - out["U_new"]).max() <= U_ATOL
         assert int(io["status"][p].cpu()) == B.OK
+    batch.close()
+
+
+def batch_io(torch, dev, batch, cases):
+    f64 = dict(dtype=torch.float64, device=dev)
+    U = np.concatenate([np.asarray(c["U_nom"]) for c in cases])
+    return {"q": torch.tensor(np.array([c["q0"] for c in cases]), **f64),
+            "qd": torch.tensor(np.array([c["qd0"] for c in cases]), **f64),
+            "target": torch.tensor(np.array([B.target_vector(c["target"]) for c in cases]), **f64),
+            "U_nominal": torch.tensor(U, **f64), "U_new": torch.zeros(U.shape, **f64),
+            "U_shift": torch.zeros(U.shape, **f64),
+            "costs": torch.zeros(batch.k_total, dtype=torch.float32, device=dev),
+            "status": torch.full((len(cases),), -1, dtype=torch.int32, device=dev),
+            "seed": torch.tensor([c["seed"] for c in cases], dtype=torch.int64, device=dev)}
+
+
+def test_batch_iterations_equal_single_problem_iterations(workloads):
+    """A batch whose problems run three iterations per update gives each
+    problem the single-problem three-iteration update (same Philox ticks,
+    FP32 rounding of the two kernels), and a captured graph replays the
+    same iterations bit for bit."""
+    torch, dev = torch_dev()
+    cases = [with_cost(c, K=1024 + 448 * j, iterations=3, noise_rho=0.4 * (j % 2))
+             for j, c in enumerate(workloads["wall_k4096"][4:7] + workloads["single_k256"][2:4])]
+    batch = B.Batch([(c["robot"], c["cost"]) for c in cases])
+    io = batch_io(torch, dev, batch, cases)
+    batch.update_async(io, tick=4)
+    torch.cuda.synchronize()
+    for p, c in enumerate(cases):
+        solver = B.Solver(c["robot"], c["cost"], B.FP32)
+        out = device_update(solver, c, c["seed"], 4, B.FP32)
+        solver.close()
+        k0, K = batch.k_off[p], batch.K[p]
+        S_b = io["costs"][k0:k0 + K].double().cpu().numpy()
+        assert (np.abs(S_b - out["costs"]) / np.abs(out["costs"])).max() <= 1e-4, p
+        u0, T = batch.u_off[p] // 7, c["cost"]["T"]
+        assert np.abs(io["U_new"][u0:u0 + T].cpu().numpy() - out["U_new"]).max() <= U_ATOL, p
+        assert np.abs(io["U_shift"][u0:u0 + T].cpu().numpy() - out["U_shift"]).max() <= U_ATOL, p
+        assert int(io["status"][p].cpu()) == B.OK
+    # graph replays at ticks 7 and 8 against eager updates at the same ticks
+    eager = []
+    for t in (7, 8):
+        e = batch_io(torch, dev, batch, cases)
+        batch.update_async(e, tick=t)
+        torch.cuda.synchronize()
+        eager.append(e)
+    g = batch_io(torch, dev, batch, cases)
+    batch.graph_capture(g)
+    batch.set_tick(7)
+    for t, e in zip((7, 8), eager):
+        batch.graph_launch()
+        torch.cuda.synchronize()
+        assert torch.equal(g["U_new"], e["U_new"]) and torch.equal(g["costs"], e["costs"]), t
     batch.close()
