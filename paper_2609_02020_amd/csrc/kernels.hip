@@ -326,9 +326,14 @@ struct BatchProblem {
 };
 
 // COLL: some problem of the batch has the collision term (the collision
-// rollout variants are compiled in only then)
+// rollout variants are compiled in only then).  Without it the kernel is
+// built for two resident waves per SIMD (at most 256 registers per lane,
+// some spilled to scratch): the second wave fills the dependency stalls of
+// the first, 17 % faster on the 64-problem tick than one wave holding the
+// whole register file.  The collision variants spill too much at that size
+// and keep one wave per SIMD.
 template <int W, bool COLL>
-__global__ __launch_bounds__(64 * W) void batch_kernel(
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(COLL ? 1 : 2))) void batch_kernel(
     const BatchProblem* __restrict__ probs, const ModelM<float>* __restrict__ models,
     const int2* __restrict__ items, int nitems, unsigned int* queue, unsigned int* done, unsigned int* counters, const double* __restrict__ q,
     const double* __restrict__ qd, const double* __restrict__ target, const double* U_nom, double* U_new,
