@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -142,6 +143,14 @@ int validate_cost(const mppi_cost_params* c)
 }
 
 int iterations_of(const mppi_cost_params& c) { return c.iterations > 1 ? c.iterations : 1; }
+
+// do [a, a + n) and [b, b + n) (doubles) share an address?
+bool ranges_overlap(const double* a, const double* b, size_t n)
+{
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    const uintptr_t len = n * sizeof(double);
+    return x < y + len && y < x + len;
+}
 
 bool has_force(const mppi_cost_params& c)
 {
@@ -445,8 +454,7 @@ int mppi_warm_start_async(mppi_handle_t h, const double* U_new, double* U_out, d
 {
     if (!h || !U_new || !U_out || !std::isfinite(shift_steps) || shift_steps < 0 || shift_steps > h->cost.T)
         return MPPI_EINVAL;
-    const size_t TJ = (size_t)h->cost.T * MPPI_NJ;
-    if (U_out < U_new + TJ && U_new < U_out + TJ) return MPPI_EINVAL;
+    if (ranges_overlap(U_new, U_out, (size_t)h->cost.T * MPPI_NJ)) return MPPI_EINVAL;
     return launch_warm_start(U_new, U_out, h->cost.T, shift_steps, (hipStream_t)stream) == hipSuccess ? MPPI_OK
                                                                                                       : MPPI_EDEVICE;
 }
@@ -714,8 +722,7 @@ int mppi_batch_warm_start_async(mppi_batch_t b, const double* U_new, double* U_o
 {
     if (!b || !U_new || !U_out || !std::isfinite(shift_steps) || shift_steps < 0 || shift_steps > kMaxTBatch)
         return MPPI_EINVAL;
-    const size_t n = b->u_total;   // doubles
-    if (U_out < U_new + n && U_new < U_out + n) return MPPI_EINVAL;
+    if (ranges_overlap(U_new, U_out, b->u_total)) return MPPI_EINVAL;
     return launch_batch_warm_start(b->d_probs, b->n, U_new, U_out, shift_steps, (hipStream_t)stream) == hipSuccess
                ? MPPI_OK
                : MPPI_EDEVICE;
