@@ -270,3 +270,21 @@ def test_two_wave_update_equals_one_wave(workloads, which, i, K, T, extra):
     assert np.abs(one["U_new"] - two["U_new"]).max() <= 1e-6
     assert np.array_equal(one["U_shift"][:-1], two["U_shift"][:-1]) or \
         np.abs(one["U_shift"] - two["U_shift"]).max() <= 1e-6
+
+
+@pytest.mark.parametrize("waves", [1, 2])
+def test_fused_update_with_every_cost_non_finite(workloads, waves):
+    """Nominal torques of 1e30 N m overflow every sample's cost: the fused
+    update (one-wave and two-wave launches) reports MPPI_ENONFINITE and
+    passes the nominal sequence through unchanged, its shift included."""
+    case = workloads["wall_k4096"][2]
+    cost = dict(case["cost"], K=1000)
+    U = np.full((cost["T"], 7), 1e30)
+    solver = B.Solver(case["robot"], cost, B.FP32)
+    solver.set_launch(waves)
+    out = device_update(solver, dict(case, cost=cost), case["seed"], 1, B.FP32, U_nom=U)
+    solver.close()
+    assert out["status"] == B.ENONFINITE
+    assert not np.isfinite(out["costs"]).any()
+    assert np.array_equal(out["U_new"], U)
+    assert np.array_equal(out["U_shift"][:-1], U[1:]) and np.array_equal(out["U_shift"][-1], U[-1])

@@ -66,3 +66,14 @@ def test_rate_study(ora):
     rows = study(ora, 1024, [(10.0, 0), (6.0, 1), (1.0, 0)], 8, 1.5, 500.0)
     fast, paper = rows[(1.0, 0)], rows[(6.0, 1)]
     assert fast["cost"] <= paper["cost"]
+
+
+def test_closed_loop_is_deterministic():
+    """The same episodes, seeds and settings give the same plant trajectory
+    bit for bit (solver at 1 kHz with the fractional warm start, 0.3 s)."""
+    d = inputs.load_learned()
+    eps = d["eval"][:4]
+    a = rate.run(d["robot"], d["cost"], eps, 1024, 1.0, 0.3)
+    b = rate.run(d["robot"], d["cost"], eps, 1024, 1.0, 0.3)
+    assert np.isfinite(a["q"]).all()
+    assert np.array_equal(a["q"], b["q"]) and np.array_equal(a["u"], b["u"])
