@@ -1,9 +1,10 @@
 // mlp.hip -- the proposal network on gfx950: BF16 matrix-core products
 // (v_mfma_f32_16x16x16_bf16) with FP32 accumulation.
 //
-//   mlp_forward_kernel<TRAIN>  one workgroup (4 waves) per 64 states; the
-//                   layers run back to back with the activation tile in
-//                   LDS.  Training adds the MSE signal and the backward
+//   mlp_forward_kernel<TRAIN>  one workgroup (4 waves) per 16 states (one
+//                   matrix-core row tile, so a 512-row batch spreads over 32
+//                   workgroups); the layers run back to back with the
+//                   activation tile in LDS.  Training adds the MSE signal and the backward
 //                   products e_{l-1} = (e_l W_l) * gelu'(z_{l-1}) in the same
 //                   workgroup (the rows are independent), storing every
 //                   activation and signal transposed for the weight gradients.
@@ -75,13 +76,14 @@ __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// acc[i][j] = sum_k A[16 i + r][k] Bt[nb + 16 j + c][k] over the 64 rows of
-// the LDS tile A and CT column tiles of the global k-contiguous Bt [N][K].
-// Every B fragment of the layer is requested before the first product, so
-// the wave waits for one memory latency per layer instead of one per k-step.
-template <int K, int CT>
+// acc[i][j] = sum_k A[16 i + r][k] Bt[nb + 16 j + c][k] over the RT row
+// tiles of the LDS tile A and CT column tiles of the global k-contiguous
+// Bt [N][K].  Every B fragment of the layer is requested before the first
+// product, so the wave waits for one memory latency per layer instead of
+// one per k-step.
+template <int K, int CT, int RT = kMlpWgRows / 16>
 __device__ __forceinline__ void tile_mm(const uint16_t* A, const uint16_t* __restrict__ Bt, int nb,
-                                        v4f (&acc)[4][CT], int lane)
+                                        v4f (&acc)[RT][CT], int lane)
 {
     constexpr int KS = K / 16;
     const int r = lane & 15, kq = (lane >> 4) * 4;
@@ -94,27 +96,28 @@ __device__ __forceinline__ void tile_mm(const uint16_t* A, const uint16_t* __res
     // keep the scheduler from sinking the loads next to their products
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
         for (int j = 0; j < CT; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-        v4s a[4];
+        v4s a[RT];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const v4s*>(A + (16 * i + r) * kLda + 16 * s + kq);
+        for (int i = 0; i < RT; ++i) a[i] = *reinterpret_cast<const v4s*>(A + (16 * i + r) * kLda + 16 * s + kq);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < RT; ++i)
 #pragma unroll
             for (int j = 0; j < CT; ++j) acc[i][j] = mfma(a[i], b[s][j], acc[i][j]);
     }
 }
+constexpr int kRT = kMlpWgRows / 16;   // row tiles per workgroup
 
-// LDS tile columns [0, ncols) -> global [c][Bp] at rows b0..b0+63
+// LDS tile columns [0, ncols) -> global [c][Bp] at rows b0..b0+15
 __device__ __forceinline__ void store_transposed(const uint16_t* tile, int ncols, uint16_t* dst, int Bp, int b0,
                                                  int tid)
 {
-    for (int i = tid; i < ncols * kMlpRows; i += kThreads) {
-        const int c = i / kMlpRows, r = i % kMlpRows;
+    for (int i = tid; i < ncols * kMlpWgRows; i += kThreads) {
+        const int c = i / kMlpWgRows, r = i % kMlpWgRows;
         dst[(size_t)c * Bp + b0 + r] = tile[r * kLda + c];
     }
 }
@@ -127,10 +130,10 @@ __device__ __forceinline__ void hidden_forward(const uint16_t* A, const uint16_t
                                                const float* __restrict__ bias, float* z, uint16_t* out, int b0,
                                                int rows, int w, int lane)
 {
-    v4f acc[4][4];
+    v4f acc[kRT][4];
     tile_mm<K, 4>(A, W, w * 64, acc, lane);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kRT; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -148,10 +151,10 @@ template <int K>
 __device__ __forceinline__ void hidden_backward(const uint16_t* E, const uint16_t* __restrict__ Wt, const float* z,
                                                 uint16_t* out, int b0, int w, int lane)
 {
-    v4f acc[4][4];
+    v4f acc[kRT][4];
     tile_mm<K, 4>(E, Wt, w * 64, acc, lane);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kRT; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -166,14 +169,14 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
                                                                const float* __restrict__ Ytgt, float* __restrict__ Y,
                                                                double* __restrict__ U, int u_stride, float gscale)
 {
-    __shared__ __align__(16) uint16_t buf[2][kMlpRows * kLda];
+    __shared__ __align__(16) uint16_t buf[2][kMlpWgRows * kLda];
     __shared__ float red[kThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int b0 = blockIdx.x * kMlpRows;
+    const int b0 = blockIdx.x * kMlpWgRows;
     const float* th = d.theta;
 
     // a_0 = bf16(x); feature columns 21..31 and rows past B are zero
-    for (int i = tid; i < kMlpRows * kMlpInPad; i += kThreads) {
+    for (int i = tid; i < kMlpWgRows * kMlpInPad; i += kThreads) {
         const int r = i / kMlpInPad, c = i % kMlpInPad;
         const float x = (c < kMlpIn && b0 + r < B) ? X[(size_t)(b0 + r) * kMlpIn + c] : 0.0f;
         buf[0][r * kLda + c] = to_bf16(x);
@@ -182,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
     if (TRAIN) store_transposed(buf[0], kMlpInPad, d.aT0, d.Bp, b0, tid);
 
     // training keeps every row (the backward pass reads them all)
-    const int rows = TRAIN ? kMlpRows : min(kMlpRows, B - b0);
+    const int rows = TRAIN ? kMlpWgRows : min(kMlpWgRows, B - b0);
     hidden_forward<kMlpInPad>(buf[0], d.W1, th + kOffB1, TRAIN ? d.z1 : nullptr, buf[1], b0, rows, w, lane);
     __syncthreads();
     if (TRAIN) store_transposed(buf[1], kMlpHid, d.aT1, d.Bp, b0, tid);
@@ -195,11 +198,11 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
 
     // output layer; training: e_4 = bf16(2 (y - y*) / (B 126)) into buf[0]
     {
-        v4f acc[4][2];
+        v4f acc[kRT][2];
         tile_mm<kMlpHid, 2>(buf[1], d.W4, w * 32, acc, lane);
         float sq = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < kRT; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -344,7 +347,7 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
     }
     if (blockIdx.x == 0 && lane == 0 && loss) {
         float sl = 0.0f;
-        for (int i = 0; i < nb; ++i) sl += d.lossp[i];
+        for (int i = 0; i < Bb / kMlpWgRows; ++i) sl += d.lossp[i];
         *loss = sl / ((float)B * (float)kMlpOut);
     }
 }
@@ -418,7 +421,7 @@ size_t mlp_scratch_bytes(int Bp)
     b += align256((size_t)kMlpInPad * Bp * 2) + 3 * align256((size_t)kMlpHid * Bp * 2);   // aT0..aT3
     b += 3 * align256((size_t)kMlpHid * Bp * 2) + align256((size_t)kMlpOutPad * Bp * 2);  // eT1..eT4
     b += 3 * align256((size_t)Bp * kMlpHid * sizeof(float));                   // z1..z3
-    b += align256((size_t)(Bp / kMlpRows) * sizeof(float));                    // lossp
+    b += align256((size_t)(Bp / kMlpWgRows) * sizeof(float));                  // lossp
     b += align256((size_t)Bp * kMlpIn * sizeof(float));                        // X
     b += align256(21 * sizeof(double));                                        // scale
     return b;
@@ -451,7 +454,7 @@ void mlp_carve(MlpDev& d, void* base, int Bp)
     d.z1 = (float*)take((size_t)Bp * kMlpHid * 4);
     d.z2 = (float*)take((size_t)Bp * kMlpHid * 4);
     d.z3 = (float*)take((size_t)Bp * kMlpHid * 4);
-    d.lossp = (float*)take((size_t)(Bp / kMlpRows) * 4);
+    d.lossp = (float*)take((size_t)(Bp / kMlpWgRows) * 4);
     d.X = (float*)take((size_t)Bp * kMlpIn * 4);
     d.scale = (const double*)take(21 * sizeof(double));
     d.Bp = Bp;
@@ -461,13 +464,17 @@ hipError_t launch_mlp_forward(const MlpDev& d, const float* X, int B, const floa
                               int u_stride, hipStream_t s)
 {
     if (B < 1 || B > d.Bp) return hipErrorInvalidValue;
-    const dim3 grid((B + kMlpRows - 1) / kMlpRows);
     const float gscale = 2.0f / ((float)B * (float)kMlpOut);
-    if (Ytgt)
+    if (Ytgt) {
+        // training covers the batch rounded up to 64 rows (padding rows carry
+        // zero inputs and zero signals; the weight gradients split that range)
+        const dim3 grid((B + kMlpRows - 1) / kMlpRows * (kMlpRows / kMlpWgRows));
         hipLaunchKernelGGL(mlp_forward_kernel<true>, grid, dim3(kThreads), 0, s, d, X, B, Ytgt, Y, U, u_stride, gscale);
-    else
+    } else {
+        const dim3 grid((B + kMlpWgRows - 1) / kMlpWgRows);
         hipLaunchKernelGGL(mlp_forward_kernel<false>, grid, dim3(kThreads), 0, s, d, X, B, Ytgt, Y, U, u_stride,
                            gscale);
+    }
     return hipGetLastError();
 }
 

@@ -14,7 +14,8 @@
 namespace mppi {
 
 constexpr int kMlpIn = 21, kMlpInPad = 32, kMlpHid = 256, kMlpOut = 126, kMlpOutPad = 128;
-constexpr int kMlpRows = 64;      // states per workgroup
+constexpr int kMlpRows = 64;      // batch granularity: training buffers and batches padded to it
+constexpr int kMlpWgRows = 16;    // states per forward workgroup (one matrix-core row tile)
 constexpr int kOffW1 = 0;
 constexpr int kOffB1 = kOffW1 + kMlpHid * kMlpIn;
 constexpr int kOffW2 = kOffB1 + kMlpHid;
@@ -57,7 +58,7 @@ struct MlpDev {
     float* z1;        // [Bp][256]
     float* z2;
     float* z3;
-    float* lossp;     // [Bp / 64] per-workgroup sums of squared residuals
+    float* lossp;     // [Bp / 16] per-workgroup sums of squared residuals
     float* X;         // [Bp][21] feature scratch of the proposal path
     const double* scale;   // [21]: q_max[7], qd_max[7], then 7 torque limits
     int Bp;
