@@ -479,9 +479,17 @@ def main():
     for s in range(100):
         update(10**7 + 10 + s, ev1[s])
     torch.cuda.synchronize()
+    solver.set_launch(8)
+    ev8 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
+    for s in range(10):
+        update(10**7 + s)
+    for s in range(100):
+        update(10**7 + 10 + s, ev8[s])
+    torch.cuda.synchronize()
     solver.set_launch(2)
     out["launch_shapes"] = {"two_waves_per_64_samples_ms": float(np.mean(roll_ms)),
-                            "one_wave_per_64_samples_ms": float(np.mean([a.elapsed_time(b) for a, b in ev1]))}
+                            "one_wave_per_64_samples_ms": float(np.mean([a.elapsed_time(b) for a, b in ev1])),
+                            "eight_lanes_per_sample_ms": float(np.mean([a.elapsed_time(b) for a, b in ev8]))}
     if args.batch_ticks > 0:
         out["batch"] = batch_bench(B, inputs.load()["batch64"], torch, dev, args.batch_ticks)
     if not args.no_mlp:

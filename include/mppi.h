@@ -167,8 +167,16 @@ int mppi_set_cost(mppi_handle_t h, const mppi_cost_params* cost);
  * other draws the next step's perturbations and evaluates the force
  * estimate (Eq. 13) and the cost of the previous step, which shortens the
  * per-step critical path; FP64 rollouts, the route of Eq. 8, and 1 use one
- * wave per 64 samples.  Results are the same either way (the same
- * arithmetic per sample).  Errors: MPPI_EINVAL (null, other values). */
+ * wave per 64 samples (the same arithmetic per sample as 2).  8 gives
+ * every sample eight lanes of a wave, one per joint and one for the EE
+ * frame (FP32 rollouts of the articulated-body route without the
+ * collision term; elsewhere it acts as 2): kinematics, twists and bias
+ * forces by scans over the lanes, the inertia of Eq. 8 from
+ * composite-rigid-body inertias, Eq. 6 by an LDL^T solve, the force
+ * estimate of Eq. 13 with its right-hand sides split over the lanes; the
+ * forward dynamics are the same quantity by another factorisation, so
+ * results agree with the other shapes to FP32 rounding.
+ * Errors: MPPI_EINVAL (null, other values). */
 int mppi_set_launch(mppi_handle_t h, int waves_per_group);
 
 /* Synchronous update from host memory (Sec. II: one MPPI iteration).

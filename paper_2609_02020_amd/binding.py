@@ -288,7 +288,8 @@ class Solver:
             raise MppiError(st, "mppi_plant_step_async")
 
     def set_launch(self, waves_per_group: int):
-        """1 or 2 waves per 64 samples (mppi_set_launch)."""
+        """Launch shape of the updates (mppi_set_launch): 1 or 2 waves per 64
+        samples, or 8 lanes per sample."""
         st = self._lib.mppi_set_launch(self._h, int(waves_per_group))
         if st:
             raise MppiError(st, "mppi_set_launch")

@@ -1,0 +1,506 @@
+// group.hpp -- one MPPI sample on a group of eight lanes: lane j holds
+// joint j (j = 0..6) and lane 7 the end-effector frame.  The per-step work
+// of Sec. III-A/B is spread over the group so that the chain of one
+// sample's step is shorter than on one lane:
+//
+//   kinematics   every lane forms its joint transform Rp_j Rz(q_j), r_j
+//                (lane 7: the fixed EE transform) and an inclusive scan of
+//                transform compositions over the group gives every link
+//                frame (R_j, p_j) at once, the EE pose in lane 7;
+//   velocities   motion subspaces S_j = (z_j, p_j x z_j) in Pluecker
+//                coordinates about the world origin O, where moving between
+//                links needs no transform, so link twists are prefix sums
+//                V_j = sum_{i<=j} S_i qd_i and velocity-product
+//                accelerations prefix sums of V_i x S_i qd_i (gravity as
+//                the base acceleration);
+//   bias forces  f_j = I_j A_j + V_j x* I_j V_j (Newton-Euler per link,
+//                lane 7 carries the negated wall wrench) and suffix sums
+//                give h_j = S_j . sum_{i>=j} f_i, i.e. h(q, qd) of Eq. 5
+//                less the external torque;
+//   inertia      composite-rigid-body inertias Ic_j = sum_{i>=j} I_i
+//                (suffix sums of the ten inertia parameters about O) give
+//                the joint-space inertia M_ij = S_i . Ic_j S_j (i <= j),
+//                the matrix of Eq. 8 plus the armature diagonal, row j in
+//                lane j;
+//   solve        the rows are gathered through the group's LDS area and
+//                every lane factors M = L D L^T (no pivoting: M is SPD)
+//                and solves Eq. 6 for the whole qdd; lane j keeps qdd_j;
+//   force        (Eqs. 12-13) Omega = J M^-1 J^T and b = J M^-1 tau_F with
+//                J the EE Jacobian about the EE point (columns
+//                (z_j, (p_j - p_ee) x z_j), short moment arms where the
+//                estimate is taken): lane r (r < 6) solves L y = (row r of J)^T,
+//                lane 6 L y = tau_F, so Omega_rs = sum_i y^r_i y^s_i / d_i
+//                and b_r = sum_i y^r_i y^F_i / d_i are each one dot product
+//                per lane after a gather; every lane then solves the 6x6
+//                system (Cholesky) for the EE wrench;
+//   cost         lane 7 adds the pose and force terms of Eqs. 9-13, lanes
+//                0..6 their joint's limit and torque terms (Eq. 14); the
+//                group sums its lanes once, after the horizon.
+//
+// The code is written per lane against a group object G that provides the
+// cross-lane moves (shr<D>: value of lane j - D; shl<D>: of lane j + D;
+// invalid lanes are masked by the caller; bcast<K>: of lane K), sum (over
+// the group),
+// sync() (orders the group's LDS area) and shm (that area, kGxCount
+// values).  On the device G is eight consecutive lanes of a wave (DPP row
+// shifts; a row of 16 lanes holds two groups, so shifts never cross
+// groups unmasked); a host emulation runs the same code on eight threads
+// in lockstep at every cross-lane move.
+#pragma once
+
+#include "rollout.hpp"
+
+namespace mppi {
+
+constexpr int kGroup = 8;
+// group LDS area (values of the rollout type)
+constexpr int kGxS = 16;                   // slot: S_j (6), Ic_j S_j (6), (p_j - p_ee) x z_j (3)
+constexpr int kGxSF = 0;                   // [8][kGxS]
+constexpr int kGxRow = kGxSF + 8 * kGxS;   // [8][9]: M row j, tau - h, tau_F
+constexpr int kGxY = kGxRow + 8 * 9;       // [8][8]: y columns of the force solve
+constexpr int kGxOm = kGxY + 8 * 8;        // [8][8]: Omega row r, b_r
+constexpr int kGxCount = kGxOm + 8 * 8;    // 328
+
+// Per-lane constants of the group rollout (lane 7: the EE frame, massless).
+template <typename R> struct GroupLink {
+    R Rp[9], rp[3];   // joint frame in the parent frame (lane 7: R_ee, r_ee)
+    R Ic[6], com[3], m, arm;
+    R qmin, qmax, qdmax, taumax, qrest;
+    R sigma, sig_c;   // sampling scale of this joint (0 in lane 7)
+    R live;           // 1 for a joint, 0 for lane 7
+};
+
+template <typename R> MPPI_HD void group_link(const ModelM<R>& M, const CostM<R>& C, int j, GroupLink<R>& G)
+{
+    const bool live = j < NJ;
+    const LinkM<R>& L = M.L[live ? j : NJ - 1];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) G.Rp[a] = live ? L.Rp[a] : M.Ree[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        G.rp[a] = live ? L.rp[a] : M.ree[a];
+        G.com[a] = live ? L.com[a] : R(0);
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) G.Ic[a] = live ? L.Ic[a] : R(0);
+    G.m = live ? L.m : R(0);
+    G.arm = live ? L.arm : R(0);
+    G.qmin = L.qmin; G.qmax = L.qmax; G.qdmax = L.qdmax; G.taumax = L.taumax;
+    G.qrest = C.q_rest[live ? j : NJ - 1];
+    G.sigma = live ? C.sigma[j] : R(0);
+    G.sig_c = live ? C.sig_c[j] : R(0);
+    G.live = live ? R(1) : R(0);
+}
+
+// This lane's normal of step t: Philox call j / 4 of the counter (c, t, k,
+// tick), Box-Muller pair (j / 2) mod 2, cosine (even j) or sine branch --
+// the same u32 words and the same arithmetic as normals8, one normal per lane.
+template <typename R> MPPI_HD R group_normal(uint64_t seed, uint32_t tick, uint32_t k, uint32_t t, int j)
+{
+    uint32_t x0 = (uint32_t)(j >> 2), x1 = t, x2 = k, x3 = tick;
+    philox10(x0, x1, x2, x3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const bool hi = (j >> 1) & 1;
+    R z0, z1;
+    box_muller_pair<R>(hi ? x2 : x0, hi ? x3 : x1, z0, z1);
+    return (j & 1) ? z1 : z0;
+}
+
+// the perturbation recursion of noise_step for this lane's joint
+template <typename R> MPPI_HD R group_noise_step(const CostM<R>& C, const GroupLink<R>& L, R z, R du, int t)
+{
+    return (t == 0 || C.rho == R(0)) ? L.sigma * z : C.rho * du + L.sig_c * z;
+}
+
+// ---------------------------------------------------------------------------
+// scans over the group
+// ---------------------------------------------------------------------------
+// inclusive prefix composition of (Q, t) (child frame in the parent frame):
+// (Qa, ta) o (Qb, tb) = (Qa Qb, Qa tb + ta), earlier joints on the left
+template <int D, typename R, class G> MPPI_HD void scan_frames(const G& g, R* Q, R* t)
+{
+    R Qp[9], tp[3];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) Qp[a] = g.template shr<D>(Q[a]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) tp[a] = g.template shr<D>(t[a]);
+    if (g.j >= D) {
+        R nt[3];
+        mv3(Qp, t, nt);
+        t[0] = nt[0] + tp[0]; t[1] = nt[1] + tp[1]; t[2] = nt[2] + tp[2];
+        mm3(Qp, Q, Q);
+    }
+}
+template <int N, typename R, class G> MPPI_HD void prefix_sum(const G& g, R* x)
+{
+#pragma unroll
+    for (int d = 1; d < kGroup; d *= 2) {
+        R s[N];
+        if (d == 1) {
+#pragma unroll
+            for (int a = 0; a < N; ++a) s[a] = g.template shr<1>(x[a]);
+        } else if (d == 2) {
+#pragma unroll
+            for (int a = 0; a < N; ++a) s[a] = g.template shr<2>(x[a]);
+        } else {
+#pragma unroll
+            for (int a = 0; a < N; ++a) s[a] = g.template shr<4>(x[a]);
+        }
+        const bool on = g.j >= d;
+#pragma unroll
+        for (int a = 0; a < N; ++a) x[a] += on ? s[a] : R(0);
+    }
+}
+template <int N, typename R, class G> MPPI_HD void suffix_sum(const G& g, R* x)
+{
+#pragma unroll
+    for (int d = 1; d < kGroup; d *= 2) {
+        R s[N];
+        if (d == 1) {
+#pragma unroll
+            for (int a = 0; a < N; ++a) s[a] = g.template shl<1>(x[a]);
+        } else if (d == 2) {
+#pragma unroll
+            for (int a = 0; a < N; ++a) s[a] = g.template shl<2>(x[a]);
+        } else {
+#pragma unroll
+            for (int a = 0; a < N; ++a) s[a] = g.template shl<4>(x[a]);
+        }
+        const bool on = g.j + d < kGroup;
+#pragma unroll
+        for (int a = 0; a < N; ++a) x[a] += on ? s[a] : R(0);
+    }
+}
+
+// EE pose of the group: lane j gets its link frame (lane 7: R_ee, p_ee)
+template <typename R, class G> MPPI_HD void group_fk(const G& g, const GroupLink<R>& L, R q, R* Q, R* p)
+{
+    R c, s;
+    sincos_(q, &s, &c);
+    joint_rot(L.Rp, c, s, Q);
+    p[0] = L.rp[0]; p[1] = L.rp[1]; p[2] = L.rp[2];
+    scan_frames<1>(g, Q, p);
+    scan_frames<2>(g, Q, p);
+    scan_frames<4>(g, Q, p);
+}
+
+// pose terms of Eqs. 9-11 from the EE frame (R_ee = R_n R_ee,fixed)
+template <typename R> MPPI_HD R pose_cost(const CostM<R>& C, const TargetM<R>& tg, const R* pee, const R* Re)
+{
+    R s = C.W_pos[0] * sq(tg.p_des[0] - pee[0]) + C.W_pos[1] * sq(tg.p_des[1] - pee[1]) +
+          C.W_pos[2] * sq(tg.p_des[2] - pee[2]);
+    if (C.has_ori) {
+        R Rerr[9], rho[3];
+        mm3(tg.RdT, Re, Rerr);
+        so3_log(Rerr, rho);
+        s += C.W_ori[0] * rho[0] * rho[0] + C.W_ori[1] * rho[1] * rho[1] + C.W_ori[2] * rho[2] * rho[2];
+    }
+    return s;
+}
+// this lane's joint-limit, velocity-limit and posture terms (Eq. 14 C_joint)
+template <typename R> MPPI_HD R joint_cost1(const CostM<R>& C, const GroupLink<R>& L, R q, R qd)
+{
+    return C.w_q * (sq(hinge(q - L.qmax)) + sq(hinge(L.qmin - q))) + C.w_qd * sq(hinge(abs_(qd) - L.qdmax)) +
+           C.w_post * sq(q - L.qrest);
+}
+
+// What a group step leaves for inspection (host checks): lane 7's EE pose,
+// the force estimate (FORCE) and this lane's qdd.
+template <typename R> struct GroupStepOut {
+    R qdd;
+    R pee[3], Re[9];
+    R F[6];
+};
+
+// One step of Eqs. 5-7 and the running cost at the pre-step state (x_t,
+// v_t): returns this lane's share of l_t and sets qdd (0 in lane 7).
+// tau: this lane's joint torque (sampled torque plus any joint-space
+// external torque); v: the sampled torque (force estimate, torque terms).
+template <typename R, bool FORCE, class G>
+MPPI_HD R group_step(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg, const R* grav,
+                     int ext, R q, R qd, R tau, R v, R& qdd, GroupStepOut<R>* dbg = nullptr)
+{
+    const int j = g.j;
+    const bool ee = j == kGroup - 1;
+    R* X = g.shm;
+
+    // ---- kinematics: link frames (lane 7: the EE frame)
+    R Q[9], p[3];
+    group_fk(g, L, q, Q, p);
+    // motion subspace about O (lane 7: none)
+    R z[3] = {Q[2] * L.live, Q[5] * L.live, Q[8] * L.live}, pz[3];
+    cross3(p, z, pz);
+    // link inertia about O: mass m, first moment h = m c, rotational I_O
+    R cw[3], Ib[6];
+    mv3(Q, L.com, cw);
+    cw[0] += p[0]; cw[1] += p[1]; cw[2] += p[2];
+    congr_sym3<false>(Q, L.Ic, Ib);
+    R In[10];   // h[3], m, I_O[6]
+    In[0] = L.m * cw[0]; In[1] = L.m * cw[1]; In[2] = L.m * cw[2]; In[3] = L.m;
+    {
+        const R c00 = cw[0] * cw[0], c11 = cw[1] * cw[1], c22 = cw[2] * cw[2];
+        In[4] = Ib[0] + L.m * (c11 + c22);
+        In[5] = Ib[1] + L.m * (c00 + c22);
+        In[6] = Ib[2] + L.m * (c00 + c11);
+        In[7] = Ib[3] - In[0] * cw[1];
+        In[8] = Ib[4] - In[0] * cw[2];
+        In[9] = Ib[5] - In[1] * cw[2];
+    }
+
+    // ---- twists V_j = sum_{i<=j} S_i qd_i
+    R Sq[6] = {z[0] * qd, z[1] * qd, z[2] * qd, pz[0] * qd, pz[1] * qd, pz[2] * qd};
+    R V[6] = {Sq[0], Sq[1], Sq[2], Sq[3], Sq[4], Sq[5]};
+    prefix_sum<6>(g, V);
+    // velocity-product accelerations V_j x (S_j qd_j), prefix-summed, plus
+    // the base acceleration -g
+    R A[6];
+    {
+        R t1[3], t2[3], t3[3];
+        cross3(V, Sq, t1);
+        cross3(V, Sq + 3, t2);
+        cross3(V + 3, Sq, t3);
+        A[0] = t1[0]; A[1] = t1[1]; A[2] = t1[2];
+        A[3] = t2[0] + t3[0]; A[4] = t2[1] + t3[1]; A[5] = t2[2] + t3[2];
+    }
+    prefix_sum<6>(g, A);
+    A[3] -= grav[0]; A[4] -= grav[1]; A[5] -= grav[2];
+
+    // ---- link forces f = I A + V x* (I V)
+    auto inertia_mul = [&](const R* P, const R* x, R* y) {
+        // (I_O w + h x v, m v - h x w)
+        R hv[3], hw[3];
+        cross3(P, x + 3, hv);
+        cross3(P, x, hw);
+        y[0] = P[4] * x[0] + P[7] * x[1] + P[8] * x[2] + hv[0];
+        y[1] = P[7] * x[0] + P[5] * x[1] + P[9] * x[2] + hv[1];
+        y[2] = P[8] * x[0] + P[9] * x[1] + P[6] * x[2] + hv[2];
+        y[3] = P[3] * x[3] - hw[0];
+        y[4] = P[3] * x[4] - hw[1];
+        y[5] = P[3] * x[5] - hw[2];
+    };
+    R f[6];
+    {
+        R IV[6], t1[3], t2[3], t3[3];
+        inertia_mul(In, A, f);
+        inertia_mul(In, V, IV);
+        cross3(V, IV, t1);
+        cross3(V + 3, IV + 3, t2);
+        cross3(V, IV + 3, t3);
+        f[0] += t1[0] + t2[0]; f[1] += t1[1] + t2[1]; f[2] += t1[2] + t2[2];
+        f[3] += t3[0]; f[4] += t3[1]; f[5] += t3[2];
+    }
+    if (ext == EXTW_WALL) {
+        // unilateral spring-damper at the EE point (lane 7's frame origin)
+        R wxp[3];
+        cross3(V, p, wxp);
+        const R vee[3] = {V[3] + wxp[0], V[4] + wxp[1], V[5] + wxp[2]};
+        const R delta = C.wall_d0 - dot3(C.wall_n, p);
+        const R ddelta = -dot3(C.wall_n, vee);
+        const R mag = hinge(C.wall_k * delta + C.wall_c * ddelta);
+        const R Fw[3] = {C.wall_n[0] * mag, C.wall_n[1] * mag, C.wall_n[2] * mag};
+        R pf[3];
+        cross3(p, Fw, pf);
+        if (ee) {
+            f[0] -= pf[0]; f[1] -= pf[1]; f[2] -= pf[2];
+            f[3] -= Fw[0]; f[4] -= Fw[1]; f[5] -= Fw[2];
+        }
+    }
+
+    // ---- subtree sums: bias forces and composite inertias
+    suffix_sum<6>(g, f);
+    suffix_sum<10>(g, In);
+    const R hq = dot3(z, f) + dot3(pz, f + 3);
+    // Ic S and the gravity torque S . Ic (0, -g)
+    R Fm[6];
+    {
+        R Sv[6] = {z[0], z[1], z[2], pz[0], pz[1], pz[2]};
+        inertia_mul(In, Sv, Fm);
+    }
+    R tauF = v;
+    if (FORCE && C.force_mode == 0) {
+        const R ag[3] = {-grav[0], -grav[1], -grav[2]};
+        R ha[3];
+        cross3(In, ag, ha);
+        tauF = v - (dot3(z, ha) + In[3] * dot3(pz, ag));
+    }
+
+    // ---- gather S, Ic S and the EE Jacobian's linear rows (about p_ee)
+    R* slot = X + kGxSF + j * kGxS;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { slot[a] = z[a]; slot[3 + a] = pz[a]; }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) slot[6 + a] = Fm[a];
+    if (FORCE) {
+        const R pe[3] = {g.template bcast<kGroup - 1>(p[0]), g.template bcast<kGroup - 1>(p[1]),
+                         g.template bcast<kGroup - 1>(p[2])};
+        const R d[3] = {p[0] - pe[0], p[1] - pe[1], p[2] - pe[2]};
+        R jz[3];
+        cross3(d, z, jz);
+        slot[12] = jz[0]; slot[13] = jz[1]; slot[14] = jz[2];
+    }
+    g.sync();
+    // row j of M: M_jc = S_min(j,c) . (Ic S)_max(j,c), plus the armature
+    R row[NJ];
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) {
+        const int lo = j < c ? j : c, hi = j < c ? c : j;
+        const R* Sa = X + kGxSF + lo * kGxS;
+        const R* Fb = X + kGxSF + hi * kGxS + 6;
+        R s = Sa[0] * Fb[0] + Sa[1] * Fb[1] + Sa[2] * Fb[2] + Sa[3] * Fb[3] + Sa[4] * Fb[4] + Sa[5] * Fb[5];
+        row[c] = s + (c == j ? L.arm : R(0));
+    }
+    // the EE lane's slot holds no motion subspace: its rows are 0
+    if (ee) {
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) row[c] = R(0);
+    }
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) X[kGxRow + j * 9 + c] = row[c];
+    X[kGxRow + j * 9 + 7] = tau - hq;
+    X[kGxRow + j * 9 + 8] = tauF;
+    g.sync();
+
+    // ---- M = L D L^T in every lane (lower triangle, in place)
+    R Lm[NJ][NJ], b0[NJ], bF[NJ], id[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+#pragma unroll
+        for (int c = 0; c <= i; ++c) Lm[i][c] = X[kGxRow + i * 9 + c];
+        b0[i] = X[kGxRow + i * 9 + 7];
+        bF[i] = X[kGxRow + i * 9 + 8];
+    }
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) {
+        id[k] = rcp_(Lm[k][k]);
+        R u[NJ];
+#pragma unroll
+        for (int i = k + 1; i < NJ; ++i) { u[i] = Lm[i][k]; Lm[i][k] = u[i] * id[k]; }
+#pragma unroll
+        for (int i = k + 1; i < NJ; ++i)
+#pragma unroll
+            for (int c = k + 1; c <= i; ++c) Lm[i][c] = fma_(-Lm[i][k], u[c], Lm[i][c]);
+    }
+    // Eq. 6: qdd = L^-T D^-1 L^-1 (tau + tau_ext - h)
+    R x[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        R s = b0[i];
+#pragma unroll
+        for (int c = 0; c < i; ++c) s = fma_(-Lm[i][c], x[c], s);
+        x[i] = s;
+    }
+#pragma unroll
+    for (int i = NJ - 1; i >= 0; --i) {
+        R s = x[i] * id[i];
+#pragma unroll
+        for (int c = i + 1; c < NJ; ++c) s = fma_(-Lm[c][i], x[c], s);
+        x[i] = s;
+    }
+    R qj = R(0);
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) qj = (i == j) ? x[i] : qj;
+    qdd = qj;
+
+    R ell = R(0);
+    R F[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    if (FORCE) {
+        // ---- Eq. 13: lane r < 6 solves for row r of J (angular rows z, then
+        // the linear rows about p_ee), lane 6 (and 7) for tau_F
+        R y[NJ];
+        const int r = j < 3 ? j : (j < 6 ? j + 9 : 14);
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) {
+            const R Jri = X[kGxSF + i * kGxS + r];
+            R s = j < 6 ? Jri : bF[i];
+#pragma unroll
+            for (int c = 0; c < i; ++c) s = fma_(-Lm[i][c], y[c], s);
+            y[i] = s;
+        }
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) X[kGxY + j * 8 + i] = y[i];
+        g.sync();
+        // Omega_rs = sum_i y^r_i y^s_i / d_i (s < 6), b_r = sum_i y^r_i y^F_i / d_i
+        R w[NJ];
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) w[i] = y[i] * id[i];
+#pragma unroll
+        for (int s = 0; s < 7; ++s) {
+            R acc = R(0);
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) acc = fma_(w[i], X[kGxY + s * 8 + i], acc);
+            X[kGxOm + j * 8 + s] = acc;
+        }
+        g.sync();
+        Sym6<R> Om;
+        R bb[6];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int c = a; c < 3; ++c) {
+                Om.A[si(a, c)] = X[kGxOm + c * 8 + a];
+                Om.C[si(a, c)] = X[kGxOm + (3 + c) * 8 + 3 + a];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Om.B[a * 3 + c] = X[kGxOm + (3 + c) * 8 + a];
+        }
+#pragma unroll
+        for (int a = 0; a < 6; ++a) bb[a] = X[kGxOm + a * 8 + 6];
+        chol6_solve(Om, bb);   // EE wrench: (moment, force) about p_ee
+        F[0] = bb[3]; F[1] = bb[4]; F[2] = bb[5];
+        F[3] = bb[0]; F[4] = bb[1]; F[5] = bb[2];
+        if (ee) ell += force_cost(C, tg, F);
+    }
+
+    // ---- running cost of this lane at (x_t, v_t)
+    if (ee) ell += pose_cost(C, tg, p, Q);
+    else ell += joint_cost1(C, L, q, qd) + C.w_tau * sq(hinge(abs_(v) - L.taumax));
+    if (dbg) {
+        dbg->qdd = qdd;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dbg->pee[a] = p[a];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) dbg->Re[a] = Q[a];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) dbg->F[a] = F[a];
+    }
+    return ell;
+}
+
+// Terminal cost phi(x_T) = w_T (C_pos + C_ori + C_joint)(x_T): this lane's share.
+template <typename R, class G>
+MPPI_HD R group_terminal(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg, R q, R qd)
+{
+    R Q[9], p[3];
+    group_fk(g, L, q, Q, p);
+    const R s = g.j == kGroup - 1 ? pose_cost(C, tg, p, Q) : joint_cost1(C, L, q, qd);
+    return C.w_T * s;
+}
+
+// One sample's rollout on the group (Eq. 3 with the dynamics of Sec. III-A):
+// returns the sample's total cost S_k in every lane.  Us: [T][7] nominal
+// torques; te: this lane's joint-space external torque (constant mode);
+// noise_out (may be null): du[t][j] of this lane's joint at (7 t + j) *
+// noise_stride (lanes 0..6).
+template <typename R, bool FORCE, class G, typename UT>
+MPPI_HD R group_rollout(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg,
+                        const R* grav, R q, R qd, R te, const UT* Us, int T, uint64_t seed, uint32_t tick,
+                        uint32_t k, R* noise_out, size_t noise_stride)
+{
+    const int j = g.j;
+    const int jc = j < NJ ? j : NJ - 1;
+    const int ext = C.ext_mode == EXTW_WALL ? EXTW_WALL : EXTW_NONE;
+    R du = R(0), S = R(0);
+    for (int t = 0; t < T; ++t) {
+        const R z = group_normal<R>(seed, tick, k, (uint32_t)t, j);
+        du = group_noise_step(C, L, z, du, t);
+        if (noise_out && j < NJ) noise_out[(size_t)(t * NJ + j) * noise_stride] = du;
+        const R v = (R(Us[t * NJ + jc]) + du) * L.live;
+        R qdd;
+        S += group_step<R, FORCE>(g, L, C, tg, grav, ext, q, qd, v + te, v, qdd);
+        qd += qdd * C.dt;
+        q += qd * C.dt;
+    }
+    S += group_terminal(g, L, C, tg, q, qd);
+    return g.sum(S);
+}
+
+}  // namespace mppi

@@ -26,6 +26,7 @@
 #include "model_prep.hpp"
 #include "rollout.hpp"
 #include "wave.hpp"
+#include "group.hpp"
 
 namespace mppi {
 
@@ -297,6 +298,153 @@ __global__ __launch_bounds__(128) void update_split_kernel(
     }
     __syncthreads();
     if (!last || wave == 0) return;
+    __threadfence();
+    wave_merge<A>(parts, gridDim.x, T, lambda, U_nom, U_new, U_shift, status, lane, wl);
+    if (lane == 0) *counter = 0u;
+}
+
+// One MPPI update with eight lanes per sample (group.hpp): lane j of a
+// group holds joint j, lane 7 the EE frame, so a wave rolls out 8 samples
+// and a workgroup of kGroupWaves waves 8 kGroupWaves.  K = 4096 gives 512
+// waves, one per SIMD on half the chip, each running a step program
+// several times shorter than one lane's whole step.  After the horizon the
+// workgroup forms its Eq. 4 partial (wave.hpp convention) with the noise
+// regenerated from the Philox counters, and the last workgroup merges.
+// Every group of a wave runs through the rollout (samples past K too,
+// without storing anything), so the DPP moves always see a converged wave.
+constexpr int kGroupWaves = 4;
+constexpr int kGroupSamples = 8 * kGroupWaves;
+constexpr int kGroupSteps = 32;   // steps per chunk of the partial's row sums
+
+struct DevGroup {
+    int j;
+    float* shm;
+    template <int D> __device__ float shr(float x) const
+    {
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x110 + D, 0xF, 0xF, true));
+    }
+    template <int D> __device__ float shl(float x) const
+    {
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x100 + D, 0xF, 0xF, true));
+    }
+    // lane K of the group: broadcast within each quad, then the other
+    // half-group (banks of four lanes) takes it across with a row shift
+    template <int K> __device__ float bcast(float x) const
+    {
+        constexpr int q = K & 3;
+        int t = __builtin_amdgcn_mov_dpp(__float_as_int(x), q | (q << 2) | (q << 4) | (q << 6), 0xF, 0xF, true);
+        if (K < 4) t = __builtin_amdgcn_update_dpp(t, t, 0x114, 0xF, 0xA, false);
+        else t = __builtin_amdgcn_update_dpp(t, t, 0x104, 0xF, 0x5, false);
+        return __int_as_float(t);
+    }
+    __device__ float sum(float x) const
+    {
+        x += __shfl_xor(x, 1);
+        x += __shfl_xor(x, 2);
+        x += __shfl_xor(x, 4);
+        return x;
+    }
+    __device__ void sync() const { wave_sync(); }
+};
+
+template <typename A, bool FORCE>
+__global__ __launch_bounds__(64 * kGroupWaves) void update_group_kernel(
+    const ModelM<float>* __restrict__ Mp, const CostM<float>* __restrict__ Cp, const double* __restrict__ q0,
+    const double* __restrict__ qd0, const double* __restrict__ target, const double* U_nom,
+    uint64_t seed, uint32_t tick, int K, int T, double lambda, float* __restrict__ noise,
+    float* __restrict__ S, int merge, A* __restrict__ parts, unsigned int* __restrict__ counter,
+    double* U_new, double* __restrict__ U_shift, int* __restrict__ status)
+{
+    __shared__ float gx[kGroupSamples][kGxCount];
+    __shared__ float Us[kMaxT * NJ];
+    __shared__ CostM<float> Csh;
+    __shared__ A red_m[kGroupWaves], red_s[kGroupWaves];
+    __shared__ A vs[kGroupWaves][kGroupSteps * 8];
+    __shared__ A wl[64];
+    __shared__ int last;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j = lane & 7, grp = wave * 8 + (lane >> 3);
+    const int k = blockIdx.x * kGroupSamples + grp;
+    if (wave == 0) wave_copy(&Csh, Cp, sizeof(CostM<float>), lane);
+    for (int i = tid; i < T * NJ; i += blockDim.x) Us[i] = float(U_nom[i]);
+    __syncthreads();
+    const ModelM<float>& M = *Mp;
+    const CostM<float>& C = Csh;
+    GroupLink<float> L;
+    group_link(M, C, j, L);
+    TargetM<float> tg;
+    make_target(target, tg);
+    float q = 0.0f, qd = 0.0f, te = 0.0f;
+    {
+        float qa[NJ], qda[NJ], tea[NJ];
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) { qa[i] = float(q0[i]); qda[i] = float(qd0[i]); tea[i] = 0.0f; }
+        if (C.ext_mode == EXTW_CONST) const_ext_torque(M, C, qa, tea);
+#pragma unroll
+        for (int i = 0; i < NJ; ++i)
+            if (i == j) { q = qa[i]; qd = qda[i]; te = tea[i]; }
+    }
+    const float grav[3] = {M.g[0], M.g[1], M.g[2]};
+    const DevGroup g{j, gx[grp]};
+    const bool valid = k < K;
+    const float tot = group_rollout<float, FORCE>(g, L, C, tg, grav, q, qd, te, Us, T, seed, tick, (uint32_t)k,
+                                                  (valid && noise) ? noise + k : nullptr, (size_t)K);
+    float s = INFINITY;
+    if (valid) {
+        s = finite_(tot) ? tot : INFINITY;
+        if (j == 0) S[k] = s;
+    }
+    if (!merge) return;
+
+    // ---- this workgroup's partial of Eq. 4: m, sum of weights, V[7T]
+    const A inf = A(INFINITY), il = A(1) / A(lambda);
+    const bool fin = s < INFINITY;
+    const A mw = wave_min(fin ? A(s) : inf);
+    if (lane == 0) red_m[wave] = mw;
+    __syncthreads();
+    A m = red_m[0];
+#pragma unroll
+    for (int w = 1; w < kGroupWaves; ++w) m = fmin(m, red_m[w]);
+    const A wgt = fin ? exp((m - A(s)) * il) : A(0);
+    const A sw = wave_sum(j == 0 ? wgt : A(0));
+    if (lane == 0) red_s[wave] = sw;
+    A* part = parts + (size_t)blockIdx.x * (2 + T * NJ);
+    float du = 0.0f;
+    for (int t0 = 0; t0 < T; t0 += kGroupSteps) {
+        const int nt = min(kGroupSteps, T - t0);
+        for (int tt = 0; tt < nt; ++tt) {
+            const int t = t0 + tt;
+            du = group_noise_step(C, L, group_normal<float>(seed, tick, (uint32_t)k, (uint32_t)t, j), du, t);
+            A x = wgt * A(du);
+            x += __shfl_xor(x, 8);
+            x += __shfl_xor(x, 16);
+            x += __shfl_xor(x, 32);
+            if (lane < 8) vs[wave][tt * 8 + lane] = x;
+        }
+        __syncthreads();
+        for (int r = tid; r < nt * NJ; r += blockDim.x) {
+            const int tt = r / NJ, jj = r % NJ;
+            A acc = A(0);
+#pragma unroll
+            for (int w = 0; w < kGroupWaves; ++w) acc += vs[w][tt * 8 + jj];
+            part[2 + (t0 + tt) * NJ + jj] = acc;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        A st = A(0);
+#pragma unroll
+        for (int w = 0; w < kGroupWaves; ++w) st += red_s[w];
+        part[0] = m;
+        part[1] = st;
+    }
+
+    // the last workgroup merges all partials
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last || wave != 0) return;
     __threadfence();
     wave_merge<A>(parts, gridDim.x, T, lambda, U_nom, U_new, U_shift, status, lane, wl);
     if (lane == 0) *counter = 0u;
@@ -714,9 +862,30 @@ template <typename A, bool FORCE, bool COLL> static hipError_t update_split_t(co
     return hipGetLastError();
 }
 
+template <typename A, bool FORCE> static hipError_t update_group_t(const UpdateArgs& a, hipStream_t s)
+{
+    dim3 grid((a.K + kGroupSamples - 1) / kGroupSamples);
+    float* noise = (float*)a.noise;
+    if (a.merge && !a.want_noise) noise = nullptr;
+    hipLaunchKernelGGL((update_group_kernel<A, FORCE>), grid, dim3(64 * kGroupWaves), 0, s,
+                       (const ModelM<float>*)a.model, (const CostM<float>*)a.cost, a.q0, a.qd0, a.target, a.U_nom,
+                       a.seed, (uint32_t)a.tick, a.K, a.T, a.lambda, noise, (float*)a.costs, a.merge, (A*)a.parts,
+                       a.counter, a.U_new, a.U_shift, a.status);
+    return hipGetLastError();
+}
+
 template <bool EXPLICIT, bool COLL>
 static hipError_t update_dispatch(int precision, bool acc64, bool force, const UpdateArgs& a, hipStream_t s)
 {
+    if (!EXPLICIT && !COLL && a.waves_per_group == 8 && precision == MPPI_FP32) {
+        if (force) return acc64 ? update_group_t<double, true>(a, s) : update_group_t<float, true>(a, s);
+        return acc64 ? update_group_t<double, false>(a, s) : update_group_t<float, false>(a, s);
+    }
+    if (a.waves_per_group == 8) {   // the two-wave launch where groups do not apply
+        UpdateArgs b = a;
+        b.waves_per_group = 2;
+        return update_dispatch<EXPLICIT, COLL>(precision, acc64, force, b, s);
+    }
     if (!EXPLICIT && a.waves_per_group == 2 && precision == MPPI_FP32) {
         if (force) return acc64 ? update_split_t<double, true, COLL>(a, s) : update_split_t<float, true, COLL>(a, s);
         return acc64 ? update_split_t<double, false, COLL>(a, s) : update_split_t<float, false, COLL>(a, s);
@@ -743,7 +912,8 @@ hipError_t launch_update(int precision, bool acc64, bool force, const UpdateArgs
 
 size_t update_parts_bytes(int K, int T)
 {
-    return (size_t)((K + kRolloutBlock - 1) / kRolloutBlock) * (2 + (size_t)T * NJ) * sizeof(double);
+    // one partial per workgroup: 64 samples, or kGroupSamples with lane groups
+    return (size_t)((K + kGroupSamples - 1) / kGroupSamples) * (2 + (size_t)T * NJ) * sizeof(double);
 }
 
 template <typename R, typename A> static hipError_t weights_t(const WeightsArgs& a, hipStream_t s)

@@ -42,7 +42,8 @@ struct UpdateArgs {
     int dynamics;           // mppi_dynamics
     int collision;          // the collision term is on (n_pairs > 0)
     int waves_per_group;    // 2: the two-wave split update (FP32 articulated-body
-                            // rollouts), else 1
+                            // rollouts); 8: eight lanes per sample (FP32, no
+                            // collision term; otherwise as 2); else 1
 };
 
 // One fused launch: rollouts, per-wave Eq. 4 partials, last-block merge.

@@ -348,7 +348,7 @@ int mppi_set_cost(mppi_handle_t h, const mppi_cost_params* cost)
 
 int mppi_set_launch(mppi_handle_t h, int waves_per_group)
 {
-    if (!h || (waves_per_group != 1 && waves_per_group != 2)) return MPPI_EINVAL;
+    if (!h || (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 8)) return MPPI_EINVAL;
     h->waves_per_group = waves_per_group;
     return MPPI_OK;
 }

@@ -164,3 +164,172 @@ extern "C" double hc_collision(const mppi_robot_params* rp, const mppi_cost_para
 {
     return prec == MPPI_FP64 ? collision_t<double>(rp, cp, q) : collision_t<float>(rp, cp, q);
 }
+
+// ---------------------------------------------------------------------------
+// The eight-lane group rollout (group.hpp) on the host: eight threads run
+// the per-lane code and meet at every cross-lane move, which is what the
+// lanes of one group do in lockstep on the device.
+// ---------------------------------------------------------------------------
+#include <condition_variable>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "group.hpp"
+
+struct HostGroupSync {
+    std::mutex mu;
+    std::condition_variable cv;
+    int count = 0;
+    long phase = 0;
+    double slot[kGroup];
+    void barrier()
+    {
+        std::unique_lock<std::mutex> lk(mu);
+        const long ph = phase;
+        if (++count == kGroup) {
+            count = 0;
+            ++phase;
+            cv.notify_all();
+        } else {
+            cv.wait(lk, [&] { return phase != ph; });
+        }
+    }
+};
+
+template <typename R> struct HostGroup {
+    int j;
+    HostGroupSync* s;
+    R* shm;
+    template <int D> R shr(R x) const
+    {
+        s->slot[j] = double(x);
+        s->barrier();
+        const R r = j >= D ? R(s->slot[j - D]) : R(0);
+        s->barrier();
+        return r;
+    }
+    template <int D> R shl(R x) const
+    {
+        s->slot[j] = double(x);
+        s->barrier();
+        const R r = j + D < kGroup ? R(s->slot[j + D]) : R(0);
+        s->barrier();
+        return r;
+    }
+    template <int K> R bcast(R x) const
+    {
+        s->slot[j] = double(x);
+        s->barrier();
+        const R r = R(s->slot[K]);
+        s->barrier();
+        return r;
+    }
+    // the device's butterfly: x + x^1, then + ^2, then + ^4
+    R sum(R x) const
+    {
+        s->slot[j] = double(x);
+        s->barrier();
+        R a[kGroup], b[kGroup];
+        for (int i = 0; i < kGroup; ++i) a[i] = R(s->slot[i]) + R(s->slot[i ^ 1]);
+        for (int i = 0; i < kGroup; ++i) b[i] = a[i] + a[i ^ 2];
+        const R r = b[j] + b[j ^ 4];
+        s->barrier();
+        return r;
+    }
+    void sync() const { s->barrier(); }
+};
+
+template <typename R, typename F> static void run_group(F&& body)
+{
+    HostGroupSync sy;
+    std::vector<R> shm(kGxCount, R(NAN));
+    std::thread th[kGroup];
+    for (int j = 0; j < kGroup; ++j) {
+        th[j] = std::thread([&, j] {
+            HostGroup<R> g{j, &sy, shm.data()};
+            body(g);
+        });
+    }
+    for (auto& t : th) t.join();
+}
+
+template <typename R>
+static void group_step_t(const mppi_robot_params* rp, const mppi_cost_params* cp, int force, int ext,
+                         const double* q, const double* qd, const double* tau, const double* v,
+                         double* qdd, double* pee, double* Re, double* F)
+{
+    ModelM<R> M;
+    CostM<R> C;
+    prep_model(*rp, M);
+    prep_cost(*cp, C);
+    TargetM<R> tg;
+    const double tgt[13] = {0, 0, 0, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    make_target(tgt, tg);
+    GroupStepOut<R> out[kGroup];
+    run_group<R>([&](const HostGroup<R>& g) {
+        GroupLink<R> L;
+        group_link(M, C, g.j, L);
+        const int jc = g.j < NJ ? g.j : NJ - 1;
+        const R qj = g.j < NJ ? R(q[jc]) : R(0), qdj = g.j < NJ ? R(qd[jc]) : R(0);
+        const R tj = g.j < NJ ? R(tau[jc]) : R(0), vj = g.j < NJ ? R(v[jc]) : R(0);
+        R a;
+        if (force) group_step<R, true>(g, L, C, tg, M.g, ext, qj, qdj, tj, vj, a, &out[g.j]);
+        else group_step<R, false>(g, L, C, tg, M.g, ext, qj, qdj, tj, vj, a, &out[g.j]);
+    });
+    for (int j = 0; j < NJ; ++j) qdd[j] = double(out[j].qdd);
+    for (int a = 0; a < 3; ++a) pee[a] = double(out[NJ].pee[a]);
+    for (int a = 0; a < 9; ++a) Re[a] = double(out[NJ].Re[a]);
+    for (int a = 0; a < 6; ++a) F[a] = double(out[force ? 0 : NJ].F[a]);
+}
+
+// One step on the group: qdd[7], the EE point, R_ee (EE frame, not the
+// last link's) and the force estimate (from lane 0, force != 0).
+extern "C" void hc_group_step(const mppi_robot_params* rp, const mppi_cost_params* cp, int prec, int force,
+                              int ext, const double* q, const double* qd, const double* tau, const double* v,
+                              double* qdd, double* pee, double* Re, double* F)
+{
+    if (prec == MPPI_FP64) group_step_t<double>(rp, cp, force, ext, q, qd, tau, v, qdd, pee, Re, F);
+    else group_step_t<float>(rp, cp, force, ext, q, qd, tau, v, qdd, pee, Re, F);
+}
+
+template <typename R>
+static double group_rollout_t(const mppi_robot_params* rp, const mppi_cost_params* cp, const double* target,
+                              const double* q0, const double* qd0, const double* U, uint64_t seed,
+                              uint64_t tick, uint32_t k, double* noise)
+{
+    ModelM<R> M;
+    CostM<R> C;
+    TargetM<R> tg;
+    prep_model(*rp, M);
+    prep_cost(*cp, C);
+    make_target(target, tg);
+    R q[NJ], qd[NJ], te[NJ] = {};
+    for (int j = 0; j < NJ; ++j) { q[j] = R(q0[j]); qd[j] = R(qd0[j]); }
+    if (C.ext_mode == EXTW_CONST) const_ext_torque(M, C, q, te);
+    const int T = cp->T;
+    std::vector<R> nz((size_t)T * NJ, R(0));
+    R S[kGroup];
+    run_group<R>([&](const HostGroup<R>& g) {
+        GroupLink<R> L;
+        group_link(M, C, g.j, L);
+        const bool live = g.j < NJ;
+        const int jc = live ? g.j : NJ - 1;
+        const R qj = live ? q[jc] : R(0), qdj = live ? qd[jc] : R(0), tj = live ? te[jc] : R(0);
+        S[g.j] = C.has_force
+                     ? group_rollout<R, true>(g, L, C, tg, M.g, qj, qdj, tj, U, T, seed, (uint32_t)tick, k, nz.data(), 1)
+                     : group_rollout<R, false>(g, L, C, tg, M.g, qj, qdj, tj, U, T, seed, (uint32_t)tick, k, nz.data(), 1);
+    });
+    for (int i = 0; i < T * NJ; ++i) noise[i] = double(nz[i]);
+    for (int j = 1; j < kGroup; ++j)
+        if (!(S[j] == S[0])) return NAN;   // every lane must hold the same total
+    return double(S[0]);
+}
+
+extern "C" double hc_group_rollout(const mppi_robot_params* rp, const mppi_cost_params* cp, int prec,
+                                   const double* target, const double* q0, const double* qd0, const double* U,
+                                   uint64_t seed, uint64_t tick, uint32_t k, double* noise)
+{
+    if (prec == MPPI_FP64) return group_rollout_t<double>(rp, cp, target, q0, qd0, U, seed, tick, k, noise);
+    return group_rollout_t<float>(rp, cp, target, q0, qd0, U, seed, tick, k, noise);
+}
