@@ -46,7 +46,7 @@ FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (AMD published)
 # kernel sources whose digest is recorded here; reported as null once the
 # sources differ.
 PROFILED_DIGEST = "e3fb11e4386e5454"
-PROFILED_TRAFFIC = {"update_split_kernel": 777871 + 56153,  # K=4096, T=18 contact workload
+PROFILED_TRAFFIC = {"update_group_kernel": None,            # K=4096, T=18 contact workload
                     "batch_kernel": 39450538 + 352913512,   # 64-problem batch (W=2 x 1024); mostly
                                                             # register-spill stores of the
                                                             # two-waves-per-SIMD build
@@ -467,29 +467,26 @@ def main():
         "host_api_update_ms_p5_p50_p95": [float(np.percentile(host_ms, x)) for x in (5, 50, 95)],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-                     "traffic": profiled_traffic("update_split_kernel"),
-                     "kernel": "update_split_kernel<float, force> (two waves per 64 samples)",
+                     "traffic": profiled_traffic("update_group_kernel"),
+                     "kernel": "update_group_kernel<float, force> (eight lanes per sample)",
                      "flops_per_launch": flops},
     }
-    # the same update on one wave per 64 samples, for comparison
-    solver.set_launch(1)
-    ev1 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
-    for s in range(10):
-        update(10**7 + s)
-    for s in range(100):
-        update(10**7 + 10 + s, ev1[s])
-    torch.cuda.synchronize()
+
+    # the same update with the other launch shapes, for comparison
+    def shape_ms(waves):
+        solver.set_launch(waves)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
+        for s in range(10):
+            update(10**7 + s)
+        for s in range(100):
+            update(10**7 + 10 + s, ev[s])
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    out["launch_shapes"] = {"eight_lanes_per_sample_ms": float(np.mean(roll_ms)),
+                            "two_waves_per_64_samples_ms": shape_ms(2),
+                            "one_wave_per_64_samples_ms": shape_ms(1)}
     solver.set_launch(8)
-    ev8 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
-    for s in range(10):
-        update(10**7 + s)
-    for s in range(100):
-        update(10**7 + 10 + s, ev8[s])
-    torch.cuda.synchronize()
-    solver.set_launch(2)
-    out["launch_shapes"] = {"two_waves_per_64_samples_ms": float(np.mean(roll_ms)),
-                            "one_wave_per_64_samples_ms": float(np.mean([a.elapsed_time(b) for a, b in ev1])),
-                            "eight_lanes_per_sample_ms": float(np.mean([a.elapsed_time(b) for a, b in ev8]))}
     if args.batch_ticks > 0:
         out["batch"] = batch_bench(B, inputs.load()["batch64"], torch, dev, args.batch_ticks)
     if not args.no_mlp:

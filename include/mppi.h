@@ -161,7 +161,7 @@ int mppi_destroy(mppi_handle_t h);
  * otherwise).  Takes effect for later updates. */
 int mppi_set_cost(mppi_handle_t h, const mppi_cost_params* cost);
 
-/* Launch shape of the updates: 2 (the default) runs each group of 64
+/* Launch shape of the updates: 2 runs each group of 64
  * samples on two waves where supported (FP32 rollouts of the
  * articulated-body route): one wave integrates the dynamics while the
  * other draws the next step's perturbations and evaluates the force
@@ -169,8 +169,8 @@ int mppi_set_cost(mppi_handle_t h, const mppi_cost_params* cost);
  * per-step critical path; FP64 rollouts, the route of Eq. 8, and 1 use one
  * wave per 64 samples (the same arithmetic per sample as 2).  8 gives
  * every sample eight lanes of a wave, one per joint and one for the EE
- * frame (FP32 rollouts of the articulated-body route without the
- * collision term; elsewhere it acts as 2): kinematics, twists and bias
+ * frame (the default; FP32 rollouts of the articulated-body route without
+ * the collision term, elsewhere it acts as 2): kinematics, twists and bias
  * forces by scans over the lanes, the inertia of Eq. 8 from
  * composite-rigid-body inertias, Eq. 6 by an LDL^T solve, the force
  * estimate of Eq. 13 with its right-hand sides split over the lanes; the

@@ -478,12 +478,12 @@ MPPI_HD R group_terminal(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
 // One sample's rollout on the group (Eq. 3 with the dynamics of Sec. III-A):
 // returns the sample's total cost S_k in every lane.  Us: [T][7] nominal
 // torques; te: this lane's joint-space external torque (constant mode);
-// noise_out (may be null): du[t][j] of this lane's joint at (7 t + j) *
-// noise_stride (lanes 0..6).
+// noise_out, noise_lds (either may be null): du[t][j] of this lane's joint
+// at (7 t + j) * stride (lanes 0..6).
 template <typename R, bool FORCE, class G, typename UT>
 MPPI_HD R group_rollout(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg,
                         const R* grav, R q, R qd, R te, const UT* Us, int T, uint64_t seed, uint32_t tick,
-                        uint32_t k, R* noise_out, size_t noise_stride)
+                        uint32_t k, R* noise_out, size_t noise_stride, R* noise_lds = nullptr, int lds_stride = 0)
 {
     const int j = g.j;
     const int jc = j < NJ ? j : NJ - 1;
@@ -493,6 +493,7 @@ MPPI_HD R group_rollout(const G& g, const GroupLink<R>& L, const CostM<R>& C, co
         const R z = group_normal<R>(seed, tick, k, (uint32_t)t, j);
         du = group_noise_step(C, L, z, du, t);
         if (noise_out && j < NJ) noise_out[(size_t)(t * NJ + j) * noise_stride] = du;
+        if (noise_lds && j < NJ) noise_lds[(t * NJ + j) * lds_stride] = du;
         const R v = (R(Us[t * NJ + jc]) + du) * L.live;
         R qdd;
         S += group_step<R, FORCE>(g, L, C, tg, grav, ext, q, qd, v + te, v, qdd);

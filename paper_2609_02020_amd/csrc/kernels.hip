@@ -314,7 +314,98 @@ __global__ __launch_bounds__(128) void update_split_kernel(
 // without storing anything), so the DPP moves always see a converged wave.
 constexpr int kGroupWaves = 4;
 constexpr int kGroupSamples = 8 * kGroupWaves;
-constexpr int kGroupSteps = 32;   // steps per chunk of the partial's row sums
+constexpr int kGroupSteps = 32;   // steps per chunk of the partial's row sums (regenerated noise)
+constexpr int kGroupTile = kGroupSamples + 1;   // row stride of the workgroup's du tile
+
+// Merge of np partials [np][2 + rows] of one problem (Eq. 4 by the
+// log-sum-exp rule of wave.hpp) by one workgroup of NT threads: the
+// partials' (m, s) pairs are read NT at a time, and every row's weighted
+// sum is split over NT / rows threads that each read their partials'
+// values together, so the merge waits for about two memory round trips
+// instead of one per 64-partial block.  sh: LDS [NT] of A.
+template <typename A, int NT>
+__device__ void block_merge(const A* parts, int np, int T, double lambda, const double* U_nom, double* U_new,
+                            double* U_shift, int* status, int tid, A* sh)
+{
+    const int rows = T * NJ, P = 2 + rows;
+    const A inf = A(INFINITY), il = A(1) / A(lambda);
+    auto block_reduce = [&](A v, bool is_min) -> A {
+        v = is_min ? wave_min(v) : wave_sum(v);
+        __syncthreads();
+        if ((tid & 63) == 0) sh[tid >> 6] = v;
+        __syncthreads();
+        A r = sh[0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) r = is_min ? fmin(r, sh[w]) : r + sh[w];
+        return r;
+    };
+    A mp0 = inf, sp0 = A(0);
+    if (tid < np) { mp0 = parts[(size_t)tid * P]; sp0 = parts[(size_t)tid * P + 1]; }
+    A mg = mp0;
+    for (int p = tid + NT; p < np; p += NT) mg = fmin(mg, parts[(size_t)p * P]);
+    mg = block_reduce(mg, true);
+    if (!(mg < inf)) {
+        for (int r = tid; r < rows; r += NT) {
+            const int t = r / NJ, jj = r % NJ;
+            const double un = U_nom[r];
+            U_new[r] = un;
+            if (U_shift) {
+                if (t >= 1) U_shift[(t - 1) * NJ + jj] = un;
+                if (t == T - 1) U_shift[t * NJ + jj] = un;
+            }
+        }
+        if (status && tid == 0) *status = MPPI_ENONFINITE;
+        return;
+    }
+    const A f0 = mp0 < inf ? exp((mg - mp0) * il) : A(0);
+    A eta = f0 * sp0;
+    for (int p = tid + NT; p < np; p += NT) {
+        const A mp = parts[(size_t)p * P];
+        if (mp < inf) eta += exp((mg - mp) * il) * parts[(size_t)p * P + 1];
+    }
+    eta = block_reduce(eta, false);
+    // thread (slice, r): rows r, r + rows*nsl, ...; partials slice, slice + nsl, ...
+    const int nsl = rows < NT ? NT / rows : 1;
+    const int sl = tid / rows, r0 = tid % rows;
+    for (int rb = 0; rb < rows; rb += (rows < NT ? rows : NT)) {
+        const int r = rb + r0;
+        const bool act = sl < nsl && r < rows;
+        A acc = A(0);
+        for (int p0 = 0; p0 < np; p0 += NT) {
+            A f = f0;
+            if (p0 > 0) {
+                const int p = p0 + tid;
+                f = A(0);
+                if (p < np) {
+                    const A mp = parts[(size_t)p * P];
+                    f = mp < inf ? exp((mg - mp) * il) : A(0);
+                }
+            }
+            __syncthreads();
+            sh[tid] = f;
+            __syncthreads();
+            const int n = min(NT, np - p0);
+            if (act) {
+#pragma unroll 16
+                for (int i = sl; i < n; i += nsl) acc += sh[i] * parts[(size_t)(p0 + i) * P + 2 + r];
+            }
+        }
+        __syncthreads();
+        sh[tid] = acc;
+        __syncthreads();
+        if (act && sl == 0) {
+            for (int q = 1; q < nsl; ++q) acc += sh[q * rows + r0];
+            const int t = r / NJ, jj = r % NJ;
+            const double un = U_nom[r] + double(acc / eta);
+            U_new[r] = un;
+            if (U_shift) {
+                if (t >= 1) U_shift[(t - 1) * NJ + jj] = un;
+                if (t == T - 1) U_shift[t * NJ + jj] = un;
+            }
+        }
+    }
+    if (status && tid == 0) *status = MPPI_OK;
+}
 
 struct DevGroup {
     int j;
@@ -352,15 +443,16 @@ __global__ __launch_bounds__(64 * kGroupWaves) void update_group_kernel(
     const ModelM<float>* __restrict__ Mp, const CostM<float>* __restrict__ Cp, const double* __restrict__ q0,
     const double* __restrict__ qd0, const double* __restrict__ target, const double* U_nom,
     uint64_t seed, uint32_t tick, int K, int T, double lambda, float* __restrict__ noise,
-    float* __restrict__ S, int merge, A* __restrict__ parts, unsigned int* __restrict__ counter,
+    float* __restrict__ S, int merge, int lds_noise, A* __restrict__ parts, unsigned int* __restrict__ counter,
     double* U_new, double* __restrict__ U_shift, int* __restrict__ status)
 {
+    extern __shared__ char dyn_lds[];   // lds_noise: du tile [7T][kGroupTile]
     __shared__ float gx[kGroupSamples][kGxCount];
     __shared__ float Us[kMaxT * NJ];
     __shared__ CostM<float> Csh;
     __shared__ A red_m[kGroupWaves], red_s[kGroupWaves];
     __shared__ A vs[kGroupWaves][kGroupSteps * 8];
-    __shared__ A wl[64];
+    __shared__ A wsm[64 * kGroupWaves];
     __shared__ int last;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int j = lane & 7, grp = wave * 8 + (lane >> 3);
@@ -387,8 +479,10 @@ __global__ __launch_bounds__(64 * kGroupWaves) void update_group_kernel(
     const float grav[3] = {M.g[0], M.g[1], M.g[2]};
     const DevGroup g{j, gx[grp]};
     const bool valid = k < K;
+    float* tile = reinterpret_cast<float*>(dyn_lds);
     const float tot = group_rollout<float, FORCE>(g, L, C, tg, grav, q, qd, te, Us, T, seed, tick, (uint32_t)k,
-                                                  (valid && noise) ? noise + k : nullptr, (size_t)K);
+                                                  (valid && noise) ? noise + k : nullptr, (size_t)K,
+                                                  lds_noise ? tile + grp : nullptr, kGroupTile);
     float s = INFINITY;
     if (valid) {
         s = finite_(tot) ? tot : INFINITY;
@@ -410,7 +504,19 @@ __global__ __launch_bounds__(64 * kGroupWaves) void update_group_kernel(
     if (lane == 0) red_s[wave] = sw;
     A* part = parts + (size_t)blockIdx.x * (2 + T * NJ);
     float du = 0.0f;
-    for (int t0 = 0; t0 < T; t0 += kGroupSteps) {
+    if (lds_noise) {
+        // rows of the du tile weighted by the samples' weights
+        if (j == 0) wsm[grp] = wgt;
+        __syncthreads();
+        for (int r = tid; r < T * NJ; r += blockDim.x) {
+            const float* row = tile + r * kGroupTile;
+            A acc = A(0);
+#pragma unroll 8
+            for (int i = 0; i < kGroupSamples; ++i) acc += wsm[i] * A(row[i]);
+            part[2 + r] = acc;
+        }
+    }
+    for (int t0 = 0; t0 < (lds_noise ? 0 : T); t0 += kGroupSteps) {
         const int nt = min(kGroupSteps, T - t0);
         for (int tt = 0; tt < nt; ++tt) {
             const int t = t0 + tt;
@@ -444,10 +550,10 @@ __global__ __launch_bounds__(64 * kGroupWaves) void update_group_kernel(
     __syncthreads();
     if (tid == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
     __syncthreads();
-    if (!last || wave != 0) return;
+    if (!last) return;
     __threadfence();
-    wave_merge<A>(parts, gridDim.x, T, lambda, U_nom, U_new, U_shift, status, lane, wl);
-    if (lane == 0) *counter = 0u;
+    block_merge<A, 64 * kGroupWaves>(parts, gridDim.x, T, lambda, U_nom, U_new, U_shift, status, tid, wsm);
+    if (tid == 0) *counter = 0u;
 }
 
 // Batched update (a13): many independent problems (own arm, cost, K, T,
@@ -867,10 +973,12 @@ template <typename A, bool FORCE> static hipError_t update_group_t(const UpdateA
     dim3 grid((a.K + kGroupSamples - 1) / kGroupSamples);
     float* noise = (float*)a.noise;
     if (a.merge && !a.want_noise) noise = nullptr;
-    hipLaunchKernelGGL((update_group_kernel<A, FORCE>), grid, dim3(64 * kGroupWaves), 0, s,
+    const size_t tile = (size_t)a.T * NJ * kGroupTile * sizeof(float);
+    const int lds_noise = a.merge && tile <= (size_t)kMaxDynLds;
+    hipLaunchKernelGGL((update_group_kernel<A, FORCE>), grid, dim3(64 * kGroupWaves), lds_noise ? tile : 0, s,
                        (const ModelM<float>*)a.model, (const CostM<float>*)a.cost, a.q0, a.qd0, a.target, a.U_nom,
-                       a.seed, (uint32_t)a.tick, a.K, a.T, a.lambda, noise, (float*)a.costs, a.merge, (A*)a.parts,
-                       a.counter, a.U_new, a.U_shift, a.status);
+                       a.seed, (uint32_t)a.tick, a.K, a.T, a.lambda, noise, (float*)a.costs, a.merge, lds_noise,
+                       (A*)a.parts, a.counter, a.U_new, a.U_shift, a.status);
     return hipGetLastError();
 }
 

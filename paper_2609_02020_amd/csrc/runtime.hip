@@ -35,7 +35,7 @@ struct mppi_solver {
     void* h_costs = nullptr;     // pinned R [K]
     int* h_status = nullptr;     // pinned
     hipStream_t stream = nullptr;
-    int waves_per_group = 2;     // mppi_set_launch
+    int waves_per_group = 8;     // mppi_set_launch
 };
 
 namespace {

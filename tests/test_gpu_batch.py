@@ -1,7 +1,9 @@
 """GPU tests of the batched persistent launch (mppi_batch_*).
 
 Each problem of a batch must give the single-problem update's result for
-the same seed and tick (same noise and per-wave partials; the two kernels
+the same seed and tick, taken with the launch that shares the batch
+kernel's per-lane articulated-body arithmetic (mppi_set_launch 2; same
+noise and per-wave partials; the two kernels
 may fuse multiply-adds differently, so agreement is to FP32 rounding, not
 bitwise), and match the oracle on sampled problems; graph replays must be
 bitwise equal to eager launches of the same kernel; the autotuner must
@@ -71,6 +73,7 @@ def test_batch_equals_single_problem_updates(workloads):
         print("problem %d K=%d T=%d kind=%s" % (p, batch.K[p], batch.T[p], c["kind"]), flush=True)
         U_b, Us_b, S_b, st = pick(io, batch, p)
         solver = B.Solver(c["robot"], c["cost"], B.FP32)
+        solver.set_launch(2)   # the batch kernel's per-lane articulated-body arithmetic
         out = device_update(solver, c, c["seed"], 5, B.FP32)
         solver.close()
         assert st == B.OK
@@ -115,6 +118,7 @@ def test_batch_ragged_and_extreme_sizes(ora, workloads):
     for p, c in enumerate(cases):
         U_b, _, S_b, st = pick(io, batch, p)
         solver = B.Solver(c["robot"], c["cost"], B.FP32)
+        solver.set_launch(2)   # the batch kernel's per-lane articulated-body arithmetic
         out = device_update(solver, c, c["seed"], 2, B.FP32)
         solver.close()
         assert st == B.OK
@@ -157,6 +161,7 @@ def test_autotune_picks_a_shape(workloads):
     c = cases[0]
     U_b, _, S_b, _ = pick(io, batch, 0)
     solver = B.Solver(c["robot"], c["cost"], B.FP32)
+    solver.set_launch(2)   # the batch kernel's per-lane articulated-body arithmetic
     out = device_update(solver, c, c["seed"], 3, B.FP32)
     same_result(S_b, U_b, out, "after autotune")
     batch.close()

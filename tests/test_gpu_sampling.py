@@ -169,6 +169,7 @@ def test_correlated_noise_in_a_batch_equals_single_problem(workloads):
     torch.cuda.synchronize()
     for p, c in enumerate(cases):
         solver = B.Solver(c["robot"], c["cost"], B.FP32)
+        solver.set_launch(2)   # the batch kernel's per-lane articulated-body arithmetic
         out = device_update(solver, c, c["seed"], 6, B.FP32)
         solver.close()
         k0, K = batch.k_off[p], batch.K[p]
@@ -207,6 +208,7 @@ def test_batch_iterations_equal_single_problem_iterations(workloads):
     torch.cuda.synchronize()
     for p, c in enumerate(cases):
         solver = B.Solver(c["robot"], c["cost"], B.FP32)
+        solver.set_launch(2)   # the batch kernel's per-lane articulated-body arithmetic
         out = device_update(solver, c, c["seed"], 4, B.FP32)
         solver.close()
         k0, K = batch.k_off[p], batch.K[p]

@@ -24,7 +24,7 @@ def hc(tmp_path_factory):
     if shutil.which("g++") is None:
         pytest.skip("g++ not available")
     so = str(tmp_path_factory.mktemp("hc") / "libhostcheck.so")
-    subprocess.run(["g++", "-std=c++17", "-O2", "-fPIC", "-shared",
+    subprocess.run(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-pthread",
                     "-I", os.path.join(ROOT, "include"),
                     "-I", os.path.join(ROOT, "paper_2609_02020_amd", "csrc"),
                     os.path.join(ROOT, "tests", "hostcheck.cpp"), "-o", so], check=True)
@@ -40,6 +40,9 @@ def hc(tmp_path_factory):
     L.hc_seg_dist2.restype = C.c_double
     L.hc_collision.argtypes = [C.POINTER(B.RobotParams), C.POINTER(B.CostParams), C.c_int, D]
     L.hc_collision.restype = C.c_double
+    L.hc_group_step.argtypes = L.hc_step.argtypes
+    L.hc_group_rollout.argtypes = L.hc_rollout.argtypes
+    L.hc_group_rollout.restype = C.c_double
     return L
 
 
@@ -274,3 +277,92 @@ def test_explicit_m_rollout_matches_oracle(hc, ora, workloads):
             ref, _ = ora.rollout(case["robot"], case["cost"], case["target"], case["q0"], case["qd0"],
                                  case["U_nom"], case["seed"], 2, k)
             assert abs(S - ref) <= 1e-9 * abs(ref)
+
+
+# ---------------------------------------------------------------------------
+# the eight-lanes-per-sample rollout (group.hpp), run on eight host threads
+# ---------------------------------------------------------------------------
+def group_step(hc, case, prec, force, ext, q, qd, tau, v):
+    rp = B.robot_params(case["robot"])
+    cp = B.cost_params(case["cost"], prec)
+    qdd, pee, Re, F = np.zeros(7), np.zeros(3), np.zeros(9), np.zeros(6)
+    args = [np.ascontiguousarray(x, dtype=np.float64) for x in (q, qd, tau, v)]
+    hc.hc_group_step(C.byref(rp), C.byref(cp), prec, force, ext, *[_d(a) for a in args],
+                     qdd.ctypes.data_as(C.POINTER(C.c_double)), pee.ctypes.data_as(C.POINTER(C.c_double)),
+                     Re.ctypes.data_as(C.POINTER(C.c_double)), F.ctypes.data_as(C.POINTER(C.c_double)))
+    return qdd, pee, Re.reshape(3, 3), F
+
+
+@pytest.mark.parametrize("prec,tol", [(B.FP64, 1e-10), (B.FP32, 2e-4)])
+def test_group_step_matches_oracle(hc, ora, workloads, prec, tol):
+    """One step on the lane group (scans, composite-rigid-body M, LDL^T)
+    against the oracle's forward dynamics and kinematics (free motion), and
+    with the wall in contact against its dynamics and the force estimate of
+    Eq. 13 (taken about the EE point)."""
+    rng = np.random.default_rng(31)
+    for case in workloads["wall_k4096"][:5]:
+        rb = case["robot"]
+        q = np.array(case["q0"]) + rng.uniform(-0.5, 0.5, 7)
+        qd = rng.uniform(-2, 2, 7)
+        v = rng.uniform(-15, 15, 7)
+        R_ref, _, pe, _ = ora.fk(rb, q)
+        cost = dict(case["cost"], wall_d0=float(np.dot(case["cost"]["wall_n"], pe)) + 0.01)
+        case2 = dict(case, cost=cost)
+        qdd, pee, Re, _ = group_step(hc, case2, prec, 0, 0, q, qd, v, v)
+        ref = ora.forward_dynamics(rb, q, qd, v)
+        assert np.abs(qdd - ref).max() < tol * (np.abs(ref).max() + 1)
+        assert np.abs(pee - pe).max() < tol
+        Ree = np.asarray(rb["R_ee"]).reshape(3, 3)
+        assert np.abs(Re - R_ref[-1] @ Ree).max() < tol
+        qdd, _, _, F = group_step(hc, case2, prec, 1, 2, q, qd, v, v)
+        J = ora.ee_jacobian(rb, q)
+        fw = np.concatenate([ora.wall_force(cost, pe, J[:3] @ qd), np.zeros(3)])
+        assert np.linalg.norm(fw) > 1.0
+        ref = ora.forward_dynamics(rb, q, qd, v, fw)
+        assert np.abs(qdd - ref).max() < tol * (np.abs(ref).max() + 1)
+        g = ora.bias_jacobian(rb, q, np.zeros(7))
+        Fref = ora.force_estimate(rb, q, v - g)
+        assert np.abs(F - Fref).max() < tol * (np.abs(Fref).max() + 1)
+
+
+@pytest.mark.parametrize("which", ["single_k256", "wall_k4096"])
+@pytest.mark.parametrize("prec,tol", [(B.FP64, 1e-9), (B.FP32, 1e-4)])
+def test_group_rollout_cost_matches_oracle(hc, ora, workloads, which, prec, tol):
+    """Whole rollouts on the lane group: every lane ends with the same total
+    (the host function returns NaN otherwise), equal to the oracle's S_k;
+    the noise of every joint equals the oracle's."""
+    for case in workloads[which][:3]:
+        rp = B.robot_params(case["robot"])
+        cp = B.cost_params(case["cost"], prec)
+        tgt = B.target_vector(case["target"])
+        U = np.ascontiguousarray(case["U_nom"], dtype=np.float64)
+        for k in (0, 5, 1234):
+            noise = np.zeros((case["cost"]["T"], 7))
+            S = hc.hc_group_rollout(C.byref(rp), C.byref(cp), prec, _d(tgt), _d(case["q0"]),
+                                    _d(case["qd0"]), _d(U), case["seed"], 3, k,
+                                    noise.ctypes.data_as(C.POINTER(C.c_double)))
+            S_ref, n_ref = ora.rollout(case["robot"], case["cost"], case["target"], case["q0"],
+                                       case["qd0"], U, case["seed"], 3, k)
+            assert abs(S - S_ref) <= tol * abs(S_ref), (S, S_ref)
+            assert np.abs(noise - n_ref).max() < (1e-12 if prec == B.FP64 else 1e-4)
+
+
+def test_group_rollout_variants_match_oracle(hc, ora, workloads):
+    """FP64 group rollouts with correlated noise, the literal tau_F and the
+    constant external wrench."""
+    D = C.POINTER(C.c_double)
+    base = workloads["wall_k4096"][2]
+    for extra in ({"noise_rho": 0.7}, {"force_mode": 1},
+                  {"ext_mode": 1, "F_ext": [3.0, -2.0, 5.0, 0.2, -0.1, 0.3]}):
+        cost = dict(base["cost"], **extra)
+        rp, cp = B.robot_params(base["robot"]), B.cost_params(cost, B.FP64)
+        tgt = B.target_vector(base["target"])
+        U = np.ascontiguousarray(base["U_nom"], dtype=np.float64)
+        noise = np.zeros((cost["T"], 7))
+        for k in (0, 9):
+            S = hc.hc_group_rollout(C.byref(rp), C.byref(cp), B.FP64, tgt.ctypes.data_as(D), _d(base["q0"]),
+                                    _d(base["qd0"]), U.ctypes.data_as(D), base["seed"], 1, k,
+                                    noise.ctypes.data_as(D))
+            S_ref, _ = ora.rollout(base["robot"], cost, base["target"], base["q0"], base["qd0"], U,
+                                   base["seed"], 1, k)
+            assert abs(S - S_ref) <= 1e-9 * abs(S_ref), (extra, S, S_ref)
