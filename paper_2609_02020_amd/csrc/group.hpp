@@ -59,7 +59,9 @@ constexpr int kGxSF = 0;                   // [8][kGxS]
 constexpr int kGxRow = kGxSF + 8 * kGxS;   // [8][9]: M row j, tau - h, tau_F
 constexpr int kGxY = kGxRow + 8 * 9;       // [8][8]: y columns of the force solve
 constexpr int kGxOm = kGxY + 8 * 8;        // [8][8]: Omega row r, b_r
-constexpr int kGxCount = kGxOm + 8 * 8;    // 328
+constexpr int kGxH = kGxOm + 8 * 8;        // [8][12]: handoff to a cost wave: q, qd, v (lanes 0..6);
+                                           // lane 7: p_ee, R_ee
+constexpr int kGxCount = kGxH + 8 * 12;    // 424
 
 // Per-lane constants of the group rollout (lane 7: the EE frame, massless).
 template <typename R> struct GroupLink {
@@ -211,20 +213,49 @@ template <typename R> struct GroupStepOut {
     R F[6];
 };
 
-// One step of Eqs. 5-7 and the running cost at the pre-step state (x_t,
-// v_t): returns this lane's share of l_t and sets qdd (0 in lane 7).
-// tau: this lane's joint torque (sampled torque plus any joint-space
-// external torque); v: the sampled torque (force estimate, torque terms).
+// M = L D L^T (unit lower L, lower triangle in Lm, 1/d in id) of the rows
+// gathered in the group area, in every lane; b0, bF: the right-hand sides
+// tau - h and tau_F of the rows.
+template <typename R> struct GroupFactor {
+    R Lm[NJ][NJ];
+    R id[NJ];
+};
+template <typename R> MPPI_HD void group_factor(const R* X, GroupFactor<R>& f, R* b0, R* bF)
+{
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+#pragma unroll
+        for (int c = 0; c <= i; ++c) f.Lm[i][c] = X[kGxRow + i * 9 + c];
+        b0[i] = X[kGxRow + i * 9 + 7];
+        bF[i] = X[kGxRow + i * 9 + 8];
+    }
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) {
+        f.id[k] = rcp_(f.Lm[k][k]);
+        R u[NJ];
+#pragma unroll
+        for (int i = k + 1; i < NJ; ++i) { u[i] = f.Lm[i][k]; f.Lm[i][k] = u[i] * f.id[k]; }
+#pragma unroll
+        for (int i = k + 1; i < NJ; ++i)
+#pragma unroll
+            for (int c = k + 1; c <= i; ++c) f.Lm[i][c] = fma_(-f.Lm[i][k], u[c], f.Lm[i][c]);
+    }
+}
+
+// Dynamics part of one step (Eqs. 5-6): kinematics, twists, bias forces,
+// composite inertias, the rows of M and their right-hand sides in the group
+// area X, the factorisation (into *fac when given) and qdd.  Returns this
+// lane's qdd (0 in lane 7); p, Q receive this lane's frame (lane 7: the EE
+// pose).  tau: this lane's joint torque (sampled torque plus any
+// joint-space external torque); v: the sampled torque (tau_F).
 template <typename R, bool FORCE, class G>
-MPPI_HD R group_step(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg, const R* grav,
-                     int ext, R q, R qd, R tau, R v, R& qdd, GroupStepOut<R>* dbg = nullptr)
+MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, const R* grav, int ext, R q, R qd,
+                         R tau, R v, R* X, GroupFactor<R>* fac, R* p, R* Q)
 {
     const int j = g.j;
     const bool ee = j == kGroup - 1;
-    R* X = g.shm;
 
     // ---- kinematics: link frames (lane 7: the EE frame)
-    R Q[9], p[3];
     group_fk(g, L, q, Q, p);
     // motion subspace about O (lane 7: none)
     R z[3] = {Q[2] * L.live, Q[5] * L.live, Q[8] * L.live}, pz[3];
@@ -359,52 +390,54 @@ MPPI_HD R group_step(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
     X[kGxRow + j * 9 + 8] = tauF;
     g.sync();
 
-    // ---- M = L D L^T in every lane (lower triangle, in place)
-    R Lm[NJ][NJ], b0[NJ], bF[NJ], id[NJ];
-#pragma unroll
-    for (int i = 0; i < NJ; ++i) {
-#pragma unroll
-        for (int c = 0; c <= i; ++c) Lm[i][c] = X[kGxRow + i * 9 + c];
-        b0[i] = X[kGxRow + i * 9 + 7];
-        bF[i] = X[kGxRow + i * 9 + 8];
-    }
-#pragma unroll
-    for (int k = 0; k < NJ; ++k) {
-        id[k] = rcp_(Lm[k][k]);
-        R u[NJ];
-#pragma unroll
-        for (int i = k + 1; i < NJ; ++i) { u[i] = Lm[i][k]; Lm[i][k] = u[i] * id[k]; }
-#pragma unroll
-        for (int i = k + 1; i < NJ; ++i)
-#pragma unroll
-            for (int c = k + 1; c <= i; ++c) Lm[i][c] = fma_(-Lm[i][k], u[c], Lm[i][c]);
-    }
-    // Eq. 6: qdd = L^-T D^-1 L^-1 (tau + tau_ext - h)
-    R x[NJ];
+    // ---- Eq. 6: qdd = L^-T D^-1 L^-1 (tau + tau_ext - h)
+    GroupFactor<R> local;
+    GroupFactor<R>& F = fac ? *fac : local;
+    R b0[NJ], bF[NJ], x[NJ];
+    group_factor(X, F, b0, bF);
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
         R s = b0[i];
 #pragma unroll
-        for (int c = 0; c < i; ++c) s = fma_(-Lm[i][c], x[c], s);
+        for (int c = 0; c < i; ++c) s = fma_(-F.Lm[i][c], x[c], s);
         x[i] = s;
     }
 #pragma unroll
     for (int i = NJ - 1; i >= 0; --i) {
-        R s = x[i] * id[i];
+        R s = x[i] * F.id[i];
 #pragma unroll
-        for (int c = i + 1; c < NJ; ++c) s = fma_(-Lm[c][i], x[c], s);
+        for (int c = i + 1; c < NJ; ++c) s = fma_(-F.Lm[c][i], x[c], s);
         x[i] = s;
     }
     R qj = R(0);
 #pragma unroll
     for (int i = 0; i < NJ; ++i) qj = (i == j) ? x[i] : qj;
-    qdd = qj;
+    return qj;
+}
 
+// Cost part of one step: the force estimate of Eq. 13 (FORCE) from the
+// rows and Jacobian rows left in X by group_dynamics (factorised again
+// when fac is null) and this lane's running cost at (x_t, v_t): pose and
+// force terms in lane 7 (pee, Re: its EE pose), joint-limit and torque
+// terms in lanes 0..6.  Uses the kGxY and kGxOm parts of X.
+template <typename R, bool FORCE, class G>
+MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg, R* X,
+                     const GroupFactor<R>* fac, R q, R qd, R v, const R* pee, const R* Re, R* Fout = nullptr)
+{
+    const int j = g.j;
+    const bool ee = j == kGroup - 1;
     R ell = R(0);
-    R F[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     if (FORCE) {
-        // ---- Eq. 13: lane r < 6 solves for row r of J (angular rows z, then
-        // the linear rows about p_ee), lane 6 (and 7) for tau_F
+        GroupFactor<R> local;
+        R b0[NJ], bF[NJ];
+        if (!fac) group_factor(X, local, b0, bF);
+        else {
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) bF[i] = X[kGxRow + i * 9 + 8];
+        }
+        const GroupFactor<R>& Fc = fac ? *fac : local;
+        // ---- lane r < 6 solves for row r of J (angular rows z, then the
+        // linear rows about p_ee), lane 6 (and 7) for tau_F
         R y[NJ];
         const int r = j < 3 ? j : (j < 6 ? j + 9 : 14);
 #pragma unroll
@@ -412,7 +445,7 @@ MPPI_HD R group_step(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
             const R Jri = X[kGxSF + i * kGxS + r];
             R s = j < 6 ? Jri : bF[i];
 #pragma unroll
-            for (int c = 0; c < i; ++c) s = fma_(-Lm[i][c], y[c], s);
+            for (int c = 0; c < i; ++c) s = fma_(-Fc.Lm[i][c], y[c], s);
             y[i] = s;
         }
 #pragma unroll
@@ -421,7 +454,7 @@ MPPI_HD R group_step(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
         // Omega_rs = sum_i y^r_i y^s_i / d_i (s < 6), b_r = sum_i y^r_i y^F_i / d_i
         R w[NJ];
 #pragma unroll
-        for (int i = 0; i < NJ; ++i) w[i] = y[i] * id[i];
+        for (int i = 0; i < NJ; ++i) w[i] = y[i] * Fc.id[i];
 #pragma unroll
         for (int s = 0; s < 7; ++s) {
             R acc = R(0);
@@ -445,14 +478,29 @@ MPPI_HD R group_step(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
 #pragma unroll
         for (int a = 0; a < 6; ++a) bb[a] = X[kGxOm + a * 8 + 6];
         chol6_solve(Om, bb);   // EE wrench: (moment, force) about p_ee
-        F[0] = bb[3]; F[1] = bb[4]; F[2] = bb[5];
-        F[3] = bb[0]; F[4] = bb[1]; F[5] = bb[2];
+        const R F[6] = {bb[3], bb[4], bb[5], bb[0], bb[1], bb[2]};
         if (ee) ell += force_cost(C, tg, F);
+        if (Fout) {
+#pragma unroll
+            for (int a = 0; a < 6; ++a) Fout[a] = F[a];
+        }
     }
-
-    // ---- running cost of this lane at (x_t, v_t)
-    if (ee) ell += pose_cost(C, tg, p, Q);
+    if (ee) ell += pose_cost(C, tg, pee, Re);
     else ell += joint_cost1(C, L, q, qd) + C.w_tau * sq(hinge(abs_(v) - L.taumax));
+    return ell;
+}
+
+// One step of Eqs. 5-7 and the running cost at the pre-step state (x_t,
+// v_t) on one group of lanes: returns this lane's share of l_t and sets
+// qdd (0 in lane 7).
+template <typename R, bool FORCE, class G>
+MPPI_HD R group_step(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg, const R* grav,
+                     int ext, R q, R qd, R tau, R v, R& qdd, GroupStepOut<R>* dbg = nullptr)
+{
+    GroupFactor<R> fac;
+    R p[3], Q[9], F[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    qdd = group_dynamics<R, FORCE>(g, L, C, grav, ext, q, qd, tau, v, g.shm, &fac, p, Q);
+    const R ell = group_cost<R, FORCE>(g, L, C, tg, g.shm, &fac, q, qd, v, p, Q, F);
     if (dbg) {
         dbg->qdd = qdd;
 #pragma unroll
@@ -483,7 +531,8 @@ MPPI_HD R group_terminal(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
 template <typename R, bool FORCE, class G, typename UT>
 MPPI_HD R group_rollout(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg,
                         const R* grav, R q, R qd, R te, const UT* Us, int T, uint64_t seed, uint32_t tick,
-                        uint32_t k, R* noise_out, size_t noise_stride, R* noise_lds = nullptr, int lds_stride = 0)
+                        uint32_t k, R* noise_out, size_t noise_stride, R* noise_lds = nullptr, int lds_stride = 0,
+                        bool split = false)
 {
     const int j = g.j;
     const int jc = j < NJ ? j : NJ - 1;
@@ -496,7 +545,15 @@ MPPI_HD R group_rollout(const G& g, const GroupLink<R>& L, const CostM<R>& C, co
         if (noise_lds && j < NJ) noise_lds[(t * NJ + j) * lds_stride] = du;
         const R v = (R(Us[t * NJ + jc]) + du) * L.live;
         R qdd;
-        S += group_step<R, FORCE>(g, L, C, tg, grav, ext, q, qd, v + te, v, qdd);
+        if (split) {
+            // as a dynamics wave and a cost wave share the step: the cost part
+            // factorises the gathered rows again
+            R p[3], Q[9];
+            qdd = group_dynamics<R, FORCE>(g, L, C, grav, ext, q, qd, v + te, v, g.shm, nullptr, p, Q);
+            S += group_cost<R, FORCE>(g, L, C, tg, g.shm, nullptr, q, qd, v, p, Q);
+        } else {
+            S += group_step<R, FORCE>(g, L, C, tg, grav, ext, q, qd, v + te, v, qdd);
+        }
         qd += qdd * C.dt;
         q += qd * C.dt;
     }

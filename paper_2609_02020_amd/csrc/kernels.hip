@@ -304,25 +304,30 @@ __global__ __launch_bounds__(128) void update_split_kernel(
 }
 
 // One MPPI update with eight lanes per sample (group.hpp): lane j of a
-// group holds joint j, lane 7 the EE frame, so a wave rolls out 8 samples
-// and a workgroup of kGroupWaves waves 8 kGroupWaves.  K = 4096 gives 512
-// waves, one per SIMD on half the chip, each running a step program
-// several times shorter than one lane's whole step.  After the horizon the
-// workgroup forms its Eq. 4 partial (wave.hpp convention) with the noise
-// regenerated from the Philox counters, and the last workgroup merges.
-// Every group of a wave runs through the rollout (samples past K too,
-// without storing anything), so the DPP moves always see a converged wave.
-constexpr int kGroupWaves = 4;
-constexpr int kGroupSamples = 8 * kGroupWaves;
+// group holds joint j, lane 7 the EE frame, and every group of samples is
+// served by two waves: a dynamics wave (kinematics, inertias, the rows of M,
+// the LDL^T solve of Eq. 6 and the Euler step: the sequential chain of a
+// sample) and a cost wave, which draws the perturbations one step ahead and
+// evaluates the force estimate of Eq. 13 and the running cost one step
+// behind from what the dynamics wave leaves in LDS (double-buffered group
+// areas, one barrier per step).  A workgroup holds kGroupPairs such pairs
+// (8 kGroupPairs samples, one wave per SIMD); K = 4096 gives 1024 waves.
+// After the horizon the workgroup forms its Eq. 4 partial (wave.hpp
+// convention) from the du tile in LDS (or from regenerated noise when the
+// tile does not fit); group_merge_kernel, launched next, merges them.  Every
+// group runs through the rollout (samples past K too, storing nothing), so
+// the DPP moves always see a converged wave.
+constexpr int kGroupPairs = 2;
+constexpr int kGroupSamples = 8 * kGroupPairs;
+constexpr int kGroupThreads = 128 * kGroupPairs;
 constexpr int kGroupSteps = 32;   // steps per chunk of the partial's row sums (regenerated noise)
 constexpr int kGroupTile = kGroupSamples + 1;   // row stride of the workgroup's du tile
 
 // Merge of np partials [np][2 + rows] of one problem (Eq. 4 by the
 // log-sum-exp rule of wave.hpp) by one workgroup of NT threads: the
 // partials' (m, s) pairs are read NT at a time, and every row's weighted
-// sum is split over NT / rows threads that each read their partials'
-// values together, so the merge waits for about two memory round trips
-// instead of one per 64-partial block.  sh: LDS [NT] of A.
+// sum is split over NT / rows threads whose loads are issued 32 at a time,
+// so the merge waits for a few memory round trips.  sh: LDS [NT] of A.
 template <typename A, int NT>
 __device__ void block_merge(const A* parts, int np, int T, double lambda, const double* U_nom, double* U_new,
                             double* U_shift, int* status, int tid, A* sh)
@@ -364,7 +369,7 @@ __device__ void block_merge(const A* parts, int np, int T, double lambda, const 
         if (mp < inf) eta += exp((mg - mp) * il) * parts[(size_t)p * P + 1];
     }
     eta = block_reduce(eta, false);
-    // thread (slice, r): rows r, r + rows*nsl, ...; partials slice, slice + nsl, ...
+    // thread (slice, r): rows r, r + NT, ...; partials slice, slice + nsl, ...
     const int nsl = rows < NT ? NT / rows : 1;
     const int sl = tid / rows, r0 = tid % rows;
     for (int rb = 0; rb < rows; rb += (rows < NT ? rows : NT)) {
@@ -386,8 +391,17 @@ __device__ void block_merge(const A* parts, int np, int T, double lambda, const 
             __syncthreads();
             const int n = min(NT, np - p0);
             if (act) {
-#pragma unroll 16
-                for (int i = sl; i < n; i += nsl) acc += sh[i] * parts[(size_t)(p0 + i) * P + 2 + r];
+                // 32 loads in flight per thread, then their products
+                const A* col = parts + (size_t)p0 * P + 2 + r;
+                int i = sl;
+                for (; i + 31 * nsl < n; i += 32 * nsl) {
+                    A v[32];
+#pragma unroll
+                    for (int u = 0; u < 32; ++u) v[u] = col[(size_t)(i + u * nsl) * P];
+#pragma unroll
+                    for (int u = 0; u < 32; ++u) acc += sh[i + u * nsl] * v[u];
+                }
+                for (; i < n; i += nsl) acc += sh[i] * col[(size_t)i * P];
             }
         }
         __syncthreads();
@@ -439,121 +453,191 @@ struct DevGroup {
 };
 
 template <typename A, bool FORCE>
-__global__ __launch_bounds__(64 * kGroupWaves) void update_group_kernel(
+__global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
     const ModelM<float>* __restrict__ Mp, const CostM<float>* __restrict__ Cp, const double* __restrict__ q0,
     const double* __restrict__ qd0, const double* __restrict__ target, const double* U_nom,
     uint64_t seed, uint32_t tick, int K, int T, double lambda, float* __restrict__ noise,
-    float* __restrict__ S, int merge, int lds_noise, A* __restrict__ parts, unsigned int* __restrict__ counter,
-    double* U_new, double* __restrict__ U_shift, int* __restrict__ status)
+    float* __restrict__ S, int merge, int lds_noise, A* __restrict__ parts)
 {
     extern __shared__ char dyn_lds[];   // lds_noise: du tile [7T][kGroupTile]
-    __shared__ float gx[kGroupSamples][kGxCount];
+    __shared__ float gx[2][kGroupSamples][kGxCount];
+    __shared__ float nb[2][kGroupSamples][8];
     __shared__ float Us[kMaxT * NJ];
     __shared__ CostM<float> Csh;
-    __shared__ A red_m[kGroupWaves], red_s[kGroupWaves];
-    __shared__ A vs[kGroupWaves][kGroupSteps * 8];
-    __shared__ A wsm[64 * kGroupWaves];
-    __shared__ int last;
+    __shared__ float sS[kGroupSamples];
+    __shared__ A vs[kGroupPairs][kGroupSteps * 8];
+    __shared__ A wsm[kGroupSamples];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int j = lane & 7, grp = wave * 8 + (lane >> 3);
+    const bool dyn = wave < kGroupPairs;   // waves 0.. P-1: dynamics, P.. 2P-1: cost
+    const int pw = dyn ? wave : wave - kGroupPairs;
+    const int j = lane & 7, grp = pw * 8 + (lane >> 3), jc = j < NJ ? j : NJ - 1;
     const int k = blockIdx.x * kGroupSamples + grp;
-    if (wave == 0) wave_copy(&Csh, Cp, sizeof(CostM<float>), lane);
-    for (int i = tid; i < T * NJ; i += blockDim.x) Us[i] = float(U_nom[i]);
-    __syncthreads();
+    const bool valid = k < K;
+    // set-up from global memory (the cost constants from Cp directly, so that
+    // every load is issued before the first barrier)
     const ModelM<float>& M = *Mp;
-    const CostM<float>& C = Csh;
     GroupLink<float> L;
-    group_link(M, C, j, L);
+    group_link(M, *Cp, j, L);
+    const float grav[3] = {M.g[0], M.g[1], M.g[2]};
     TargetM<float> tg;
-    make_target(target, tg);
     float q = 0.0f, qd = 0.0f, te = 0.0f;
-    {
+    if (dyn) {
         float qa[NJ], qda[NJ], tea[NJ];
 #pragma unroll
         for (int i = 0; i < NJ; ++i) { qa[i] = float(q0[i]); qda[i] = float(qd0[i]); tea[i] = 0.0f; }
-        if (C.ext_mode == EXTW_CONST) const_ext_torque(M, C, qa, tea);
+        if (Cp->ext_mode == EXTW_CONST) const_ext_torque(M, *Cp, qa, tea);
 #pragma unroll
         for (int i = 0; i < NJ; ++i)
             if (i == j) { q = qa[i]; qd = qda[i]; te = tea[i]; }
+    } else {
+        make_target(target, tg);
     }
-    const float grav[3] = {M.g[0], M.g[1], M.g[2]};
-    const DevGroup g{j, gx[grp]};
-    const bool valid = k < K;
+    if (wave == 0) wave_copy(&Csh, Cp, sizeof(CostM<float>), lane);
+    for (int i = tid; i < T * NJ; i += blockDim.x) Us[i] = float(U_nom[i]);
+    const CostM<float>& C = Csh;
     float* tile = reinterpret_cast<float*>(dyn_lds);
-    const float tot = group_rollout<float, FORCE>(g, L, C, tg, grav, q, qd, te, Us, T, seed, tick, (uint32_t)k,
-                                                  (valid && noise) ? noise + k : nullptr, (size_t)K,
-                                                  lds_noise ? tile + grp : nullptr, kGroupTile);
-    float s = INFINITY;
-    if (valid) {
-        s = finite_(tot) ? tot : INFINITY;
-        if (j == 0) S[k] = s;
+    float* nz_out = (valid && noise && j < NJ) ? noise + k : nullptr;
+    float* nz_lds = (lds_noise && j < NJ) ? tile + grp : nullptr;
+    const int ext = Cp->ext_mode == EXTW_WALL ? EXTW_WALL : EXTW_NONE;
+
+    // the cost wave draws du of step t; du carries the AR(1) recursion
+    float du = 0.0f, Sl = 0.0f;
+    auto draw = [&](int t) {
+        du = group_noise_step(C, L, group_normal<float>(seed, tick, (uint32_t)k, (uint32_t)t, j), du, t);
+        nb[t & 1][grp][j] = du;
+        if (nz_out) nz_out[(size_t)(t * NJ + j) * K] = du;
+        if (nz_lds) nz_lds[(t * NJ + j) * kGroupTile] = du;
+    };
+    __syncthreads();
+    if (!dyn) draw(0);
+    __syncthreads();
+    for (int s = 0; s <= T; ++s) {
+        if (dyn) {
+            if (s < T) {
+                float* X = gx[s & 1][grp];
+                const DevGroup g{j, X};
+                const float v = (Us[s * NJ + jc] + nb[s & 1][grp][j]) * L.live;
+                float p[3], Q[9];
+                const float qdd = group_dynamics<float, FORCE>(g, L, C, grav, ext, q, qd, v + te, v, X, nullptr, p, Q);
+                // hand the pre-step state, v and the EE pose to the cost wave
+                float* h = X + kGxH + j * 12;
+                if (j < NJ) {
+                    h[0] = q; h[1] = qd; h[2] = v;
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) h[a] = p[a];
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) h[3 + a] = Q[a];
+                }
+                qd += qdd * C.dt;
+                q += qd * C.dt;
+            }
+        } else {
+            if (s + 1 < T) draw(s + 1);
+            if (s >= 1) {
+                float* X = gx[(s - 1) & 1][grp];
+                const DevGroup g{j, X};
+                const float* h = X + kGxH + j * 12;
+                float pe[3], Re[9];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) pe[a] = h[a];
+#pragma unroll
+                for (int a = 0; a < 9; ++a) Re[a] = h[3 + a];
+                Sl += group_cost<float, FORCE>(g, L, C, tg, X, nullptr, h[0], h[1], h[2], pe, Re);
+            }
+        }
+        __syncthreads();
+    }
+    // terminal cost phi(x_T) on the cost wave, from the final state
+    if (dyn) {
+        float* h = gx[T & 1][grp] + kGxH + j * 12;
+        h[0] = q;
+        h[1] = qd;
+    }
+    __syncthreads();
+    if (!dyn) {
+        const float* h = gx[T & 1][grp] + kGxH + j * 12;
+        const DevGroup g{j, gx[T & 1][grp]};
+        Sl += group_terminal(g, L, C, tg, j < NJ ? h[0] : 0.0f, j < NJ ? h[1] : 0.0f);
+        const float tot = g.sum(Sl);
+        float sv = INFINITY;
+        if (valid) {
+            sv = finite_(tot) ? tot : INFINITY;
+            if (j == 0) S[k] = sv;
+        }
+        if (j == 0) sS[grp] = sv;
     }
     if (!merge) return;
+    __syncthreads();
 
     // ---- this workgroup's partial of Eq. 4: m, sum of weights, V[7T]
     const A inf = A(INFINITY), il = A(1) / A(lambda);
-    const bool fin = s < INFINITY;
-    const A mw = wave_min(fin ? A(s) : inf);
-    if (lane == 0) red_m[wave] = mw;
-    __syncthreads();
-    A m = red_m[0];
+    A m = inf;
 #pragma unroll
-    for (int w = 1; w < kGroupWaves; ++w) m = fmin(m, red_m[w]);
-    const A wgt = fin ? exp((m - A(s)) * il) : A(0);
-    const A sw = wave_sum(j == 0 ? wgt : A(0));
-    if (lane == 0) red_s[wave] = sw;
+    for (int i = 0; i < kGroupSamples; ++i) m = fmin(m, sS[i] < INFINITY ? A(sS[i]) : inf);
+    if (tid < kGroupSamples) wsm[tid] = sS[tid] < INFINITY ? exp((m - A(sS[tid])) * il) : A(0);
+    __syncthreads();
     A* part = parts + (size_t)blockIdx.x * (2 + T * NJ);
-    float du = 0.0f;
     if (lds_noise) {
-        // rows of the du tile weighted by the samples' weights
-        if (j == 0) wsm[grp] = wgt;
-        __syncthreads();
         for (int r = tid; r < T * NJ; r += blockDim.x) {
             const float* row = tile + r * kGroupTile;
             A acc = A(0);
-#pragma unroll 8
+#pragma unroll
             for (int i = 0; i < kGroupSamples; ++i) acc += wsm[i] * A(row[i]);
             part[2 + r] = acc;
         }
-    }
-    for (int t0 = 0; t0 < (lds_noise ? 0 : T); t0 += kGroupSteps) {
-        const int nt = min(kGroupSteps, T - t0);
-        for (int tt = 0; tt < nt; ++tt) {
-            const int t = t0 + tt;
-            du = group_noise_step(C, L, group_normal<float>(seed, tick, (uint32_t)k, (uint32_t)t, j), du, t);
-            A x = wgt * A(du);
-            x += __shfl_xor(x, 8);
-            x += __shfl_xor(x, 16);
-            x += __shfl_xor(x, 32);
-            if (lane < 8) vs[wave][tt * 8 + lane] = x;
-        }
-        __syncthreads();
-        for (int r = tid; r < nt * NJ; r += blockDim.x) {
-            const int tt = r / NJ, jj = r % NJ;
-            A acc = A(0);
+    } else {
+        // regenerated noise: the cost waves' lanes reduce w du over their
+        // wave's 8 samples of each joint, then the pairs are summed
+        const A wgt = wsm[grp];
+        float dr = 0.0f;
+        for (int t0 = 0; t0 < T; t0 += kGroupSteps) {
+            const int nt = min(kGroupSteps, T - t0);
+            if (!dyn) {
+                for (int tt = 0; tt < nt; ++tt) {
+                    const int t = t0 + tt;
+                    dr = group_noise_step(C, L, group_normal<float>(seed, tick, (uint32_t)k, (uint32_t)t, j), dr, t);
+                    A x = wgt * A(dr);
+                    x += __shfl_xor(x, 8);
+                    x += __shfl_xor(x, 16);
+                    x += __shfl_xor(x, 32);
+                    if (lane < 8) vs[pw][tt * 8 + lane] = x;
+                }
+            }
+            __syncthreads();
+            for (int r = tid; r < nt * NJ; r += blockDim.x) {
+                const int tt = r / NJ, jj = r % NJ;
+                A acc = A(0);
 #pragma unroll
-            for (int w = 0; w < kGroupWaves; ++w) acc += vs[w][tt * 8 + jj];
-            part[2 + (t0 + tt) * NJ + jj] = acc;
+                for (int w = 0; w < kGroupPairs; ++w) acc += vs[w][tt * 8 + jj];
+                part[2 + (t0 + tt) * NJ + jj] = acc;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     if (tid == 0) {
         A st = A(0);
 #pragma unroll
-        for (int w = 0; w < kGroupWaves; ++w) st += red_s[w];
+        for (int i = 0; i < kGroupSamples; ++i) st += wsm[i];
         part[0] = m;
         part[1] = st;
     }
 
-    // the last workgroup merges all partials
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    block_merge<A, 64 * kGroupWaves>(parts, gridDim.x, T, lambda, U_nom, U_new, U_shift, status, tid, wsm);
-    if (tid == 0) *counter = 0u;
+    // the partials are merged by group_merge_kernel, launched next on the
+    // same stream: the kernel boundary orders them, with no per-workgroup
+    // fence (an agent-scope release writes back the XCD's L2, and hundreds
+    // of them cost more than the merge)
+}
+
+// Eq. 4 from the np workgroup partials of update_group_kernel (one workgroup).
+template <typename A>
+__global__ __launch_bounds__(kGroupThreads) void group_merge_kernel(const A* __restrict__ parts, int np, int T,
+                                                                    double lambda, const double* U_nom,
+                                                                    double* U_new, double* __restrict__ U_shift,
+                                                                    int* __restrict__ status)
+{
+    __shared__ A sh[kGroupThreads];
+    block_merge<A, kGroupThreads>(parts, np, T, lambda, U_nom, U_new, U_shift, status, threadIdx.x, sh);
 }
 
 // Batched update (a13): many independent problems (own arm, cost, K, T,
@@ -975,10 +1059,13 @@ template <typename A, bool FORCE> static hipError_t update_group_t(const UpdateA
     if (a.merge && !a.want_noise) noise = nullptr;
     const size_t tile = (size_t)a.T * NJ * kGroupTile * sizeof(float);
     const int lds_noise = a.merge && tile <= (size_t)kMaxDynLds;
-    hipLaunchKernelGGL((update_group_kernel<A, FORCE>), grid, dim3(64 * kGroupWaves), lds_noise ? tile : 0, s,
+    hipLaunchKernelGGL((update_group_kernel<A, FORCE>), grid, dim3(kGroupThreads), lds_noise ? tile : 0, s,
                        (const ModelM<float>*)a.model, (const CostM<float>*)a.cost, a.q0, a.qd0, a.target, a.U_nom,
                        a.seed, (uint32_t)a.tick, a.K, a.T, a.lambda, noise, (float*)a.costs, a.merge, lds_noise,
-                       (A*)a.parts, a.counter, a.U_new, a.U_shift, a.status);
+                       (A*)a.parts);
+    if (a.merge)
+        hipLaunchKernelGGL((group_merge_kernel<A>), dim3(1), dim3(kGroupThreads), 0, s, (const A*)a.parts,
+                           (int)grid.x, a.T, a.lambda, a.U_nom, a.U_new, a.U_shift, a.status);
     return hipGetLastError();
 }
 

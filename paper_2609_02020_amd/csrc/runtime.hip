@@ -27,7 +27,7 @@ struct mppi_solver {
     void* d_noise = nullptr;     // R [T][7][K]
     void* d_costs = nullptr;     // R [K]
     void* d_parts = nullptr;     // per-wave Eq. 4 partials (FP64-sized)
-    unsigned int* d_counter = nullptr;  // last-block counter of the fused update
+    unsigned int* d_counter = nullptr;  // last-block counter of the fused one-/two-wave updates
     int* d_status = nullptr;
     double* d_iter = nullptr;    // [2][T][7]: U of the intermediate iterations
     double* d_io = nullptr;      // q 7 | qd 7 | target 13 | U_nom T*7 | U_new T*7

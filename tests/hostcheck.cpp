@@ -296,7 +296,7 @@ extern "C" void hc_group_step(const mppi_robot_params* rp, const mppi_cost_param
 template <typename R>
 static double group_rollout_t(const mppi_robot_params* rp, const mppi_cost_params* cp, const double* target,
                               const double* q0, const double* qd0, const double* U, uint64_t seed,
-                              uint64_t tick, uint32_t k, double* noise)
+                              uint64_t tick, uint32_t k, double* noise, bool split = false)
 {
     ModelM<R> M;
     CostM<R> C;
@@ -317,8 +317,10 @@ static double group_rollout_t(const mppi_robot_params* rp, const mppi_cost_param
         const int jc = live ? g.j : NJ - 1;
         const R qj = live ? q[jc] : R(0), qdj = live ? qd[jc] : R(0), tj = live ? te[jc] : R(0);
         S[g.j] = C.has_force
-                     ? group_rollout<R, true>(g, L, C, tg, M.g, qj, qdj, tj, U, T, seed, (uint32_t)tick, k, nz.data(), 1)
-                     : group_rollout<R, false>(g, L, C, tg, M.g, qj, qdj, tj, U, T, seed, (uint32_t)tick, k, nz.data(), 1);
+                     ? group_rollout<R, true>(g, L, C, tg, M.g, qj, qdj, tj, U, T, seed, (uint32_t)tick, k, nz.data(), 1,
+                                              nullptr, 0, split)
+                     : group_rollout<R, false>(g, L, C, tg, M.g, qj, qdj, tj, U, T, seed, (uint32_t)tick, k, nz.data(), 1,
+                                               nullptr, 0, split);
     });
     for (int i = 0; i < T * NJ; ++i) noise[i] = double(nz[i]);
     for (int j = 1; j < kGroup; ++j)
@@ -332,4 +334,14 @@ extern "C" double hc_group_rollout(const mppi_robot_params* rp, const mppi_cost_
 {
     if (prec == MPPI_FP64) return group_rollout_t<double>(rp, cp, target, q0, qd0, U, seed, tick, k, noise);
     return group_rollout_t<float>(rp, cp, target, q0, qd0, U, seed, tick, k, noise);
+}
+
+// The same rollout with each step split as between a dynamics wave and a
+// cost wave (the cost part factorises the gathered rows again).
+extern "C" double hc_group_rollout_split(const mppi_robot_params* rp, const mppi_cost_params* cp, int prec,
+                                         const double* target, const double* q0, const double* qd0,
+                                         const double* U, uint64_t seed, uint64_t tick, uint32_t k, double* noise)
+{
+    if (prec == MPPI_FP64) return group_rollout_t<double>(rp, cp, target, q0, qd0, U, seed, tick, k, noise, true);
+    return group_rollout_t<float>(rp, cp, target, q0, qd0, U, seed, tick, k, noise, true);
 }

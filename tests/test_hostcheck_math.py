@@ -43,6 +43,8 @@ def hc(tmp_path_factory):
     L.hc_group_step.argtypes = L.hc_step.argtypes
     L.hc_group_rollout.argtypes = L.hc_rollout.argtypes
     L.hc_group_rollout.restype = C.c_double
+    L.hc_group_rollout_split.argtypes = L.hc_rollout.argtypes
+    L.hc_group_rollout_split.restype = C.c_double
     return L
 
 
@@ -325,12 +327,16 @@ def test_group_step_matches_oracle(hc, ora, workloads, prec, tol):
         assert np.abs(F - Fref).max() < tol * (np.abs(Fref).max() + 1)
 
 
+@pytest.mark.parametrize("split", [False, True])
 @pytest.mark.parametrize("which", ["single_k256", "wall_k4096"])
 @pytest.mark.parametrize("prec,tol", [(B.FP64, 1e-9), (B.FP32, 1e-4)])
-def test_group_rollout_cost_matches_oracle(hc, ora, workloads, which, prec, tol):
+def test_group_rollout_cost_matches_oracle(hc, ora, workloads, which, prec, tol, split):
     """Whole rollouts on the lane group: every lane ends with the same total
     (the host function returns NaN otherwise), equal to the oracle's S_k;
-    the noise of every joint equals the oracle's."""
+    the noise of every joint equals the oracle's.  split: each step as a
+    dynamics wave and a cost wave run it (the cost part factorises the
+    gathered rows again)."""
+    fn = hc.hc_group_rollout_split if split else hc.hc_group_rollout
     for case in workloads[which][:3]:
         rp = B.robot_params(case["robot"])
         cp = B.cost_params(case["cost"], prec)
@@ -338,9 +344,8 @@ def test_group_rollout_cost_matches_oracle(hc, ora, workloads, which, prec, tol)
         U = np.ascontiguousarray(case["U_nom"], dtype=np.float64)
         for k in (0, 5, 1234):
             noise = np.zeros((case["cost"]["T"], 7))
-            S = hc.hc_group_rollout(C.byref(rp), C.byref(cp), prec, _d(tgt), _d(case["q0"]),
-                                    _d(case["qd0"]), _d(U), case["seed"], 3, k,
-                                    noise.ctypes.data_as(C.POINTER(C.c_double)))
+            S = fn(C.byref(rp), C.byref(cp), prec, _d(tgt), _d(case["q0"]), _d(case["qd0"]), _d(U),
+                   case["seed"], 3, k, noise.ctypes.data_as(C.POINTER(C.c_double)))
             S_ref, n_ref = ora.rollout(case["robot"], case["cost"], case["target"], case["q0"],
                                        case["qd0"], U, case["seed"], 3, k)
             assert abs(S - S_ref) <= tol * abs(S_ref), (S, S_ref)
