@@ -468,7 +468,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                      "traffic": profiled_traffic("update_group_kernel"),
-                     "kernel": "update_group_kernel<float, force> (eight lanes per sample)",
+                     "kernel": "update_group_kernel<float, force> + group_merge_kernel (eight lanes per "
+                               "sample; the two launches of one update, timed together)",
                      "flops_per_launch": flops},
     }
 

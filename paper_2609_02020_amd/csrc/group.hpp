@@ -59,8 +59,8 @@ constexpr int kGxSF = 0;                   // [8][kGxS]
 constexpr int kGxRow = kGxSF + 8 * kGxS;   // [8][9]: M row j, tau - h, tau_F
 constexpr int kGxY = kGxRow + 8 * 9;       // [8][8]: y columns of the force solve
 constexpr int kGxOm = kGxY + 8 * 8;        // [8][8]: Omega row r, b_r
-constexpr int kGxH = kGxOm + 8 * 8;        // [8][12]: handoff to a cost wave: q, qd, v (lanes 0..6);
-                                           // lane 7: p_ee, R_ee
+constexpr int kGxH = kGxOm + 8 * 8;        // [8][12]: handoff to the cost part: q, qd, v, p_j (lanes
+                                           // 0..6); lane 7: p_ee, R_ee
 constexpr int kGxCount = kGxH + 8 * 12;    // 424
 
 // Per-lane constants of the group rollout (lane 7: the EE frame, massless).
@@ -388,6 +388,18 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
     for (int c = 0; c < NJ; ++c) X[kGxRow + j * 9 + c] = row[c];
     X[kGxRow + j * 9 + 7] = tau - hq;
     X[kGxRow + j * 9 + 8] = tauF;
+    // handoff to the cost part: pre-step q, qd, v and the joint origin
+    // (lanes 0..6), the EE pose (lane 7)
+    R* h = X + kGxH + j * 12;
+    if (ee) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) h[a] = p[a];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) h[3 + a] = Q[a];
+    } else {
+        h[0] = q; h[1] = qd; h[2] = v;
+        h[3] = p[0]; h[4] = p[1]; h[5] = p[2];
+    }
     g.sync();
 
     // ---- Eq. 6: qdd = L^-T D^-1 L^-1 (tau + tau_ext - h)
@@ -419,14 +431,40 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
 // rows and Jacobian rows left in X by group_dynamics (factorised again
 // when fac is null) and this lane's running cost at (x_t, v_t): pose and
 // force terms in lane 7 (pee, Re: its EE pose), joint-limit and torque
-// terms in lanes 0..6.  Uses the kGxY and kGxOm parts of X.
-template <typename R, bool FORCE, class G>
+// terms in lanes 0..6, and with COLL the collision term of Eqs. 14-15 with
+// the pairs dealt over the lanes (pair i to lane i mod 8; link segments
+// from the joint origins and the EE point in the handoff).  Uses the kGxY
+// and kGxOm parts of X.
+template <typename R, bool FORCE, bool COLL, class G>
 MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg, R* X,
                      const GroupFactor<R>* fac, R q, R qd, R v, const R* pee, const R* Re, R* Fout = nullptr)
 {
     const int j = g.j;
     const bool ee = j == kGroup - 1;
     R ell = R(0);
+    if (COLL) {
+        // segment id s: link s from P[s] to P[s + 1] (P[7] = EE point), or
+        // obstacle s - 7
+        auto ends = [&](int sid, R* e0, R* e1) {
+            if (sid < NJ) {
+                const R* a = X + kGxH + sid * 12 + 3;
+                const R* b = X + kGxH + (sid + 1) * 12 + (sid + 1 < NJ ? 3 : 0);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { e0[c] = a[c]; e1[c] = b[c]; }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { e0[c] = C.obs[sid - NJ][c]; e1[c] = C.obs[sid - NJ][3 + c]; }
+            }
+        };
+        R hits = R(0);
+        for (int i = j; i < C.n_pairs; i += kGroup) {
+            R a0[3], a1[3], b0[3], b1[3];
+            ends(C.pa[i], a0, a1);
+            ends(C.pb[i], b0, b1);
+            if (seg_dist2(a0, a1, b0, b1) < C.dth2[i]) hits += R(1);
+        }
+        ell += C.w_coll * hits;
+    }
     if (FORCE) {
         GroupFactor<R> local;
         R b0[NJ], bF[NJ];
@@ -493,14 +531,14 @@ MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
 // One step of Eqs. 5-7 and the running cost at the pre-step state (x_t,
 // v_t) on one group of lanes: returns this lane's share of l_t and sets
 // qdd (0 in lane 7).
-template <typename R, bool FORCE, class G>
+template <typename R, bool FORCE, class G, bool COLL = false>
 MPPI_HD R group_step(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg, const R* grav,
                      int ext, R q, R qd, R tau, R v, R& qdd, GroupStepOut<R>* dbg = nullptr)
 {
     GroupFactor<R> fac;
     R p[3], Q[9], F[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     qdd = group_dynamics<R, FORCE>(g, L, C, grav, ext, q, qd, tau, v, g.shm, &fac, p, Q);
-    const R ell = group_cost<R, FORCE>(g, L, C, tg, g.shm, &fac, q, qd, v, p, Q, F);
+    const R ell = group_cost<R, FORCE, COLL>(g, L, C, tg, g.shm, &fac, q, qd, v, p, Q, F);
     if (dbg) {
         dbg->qdd = qdd;
 #pragma unroll
@@ -528,7 +566,7 @@ MPPI_HD R group_terminal(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
 // torques; te: this lane's joint-space external torque (constant mode);
 // noise_out, noise_lds (either may be null): du[t][j] of this lane's joint
 // at (7 t + j) * stride (lanes 0..6).
-template <typename R, bool FORCE, class G, typename UT>
+template <typename R, bool FORCE, class G, typename UT, bool COLL = false>
 MPPI_HD R group_rollout(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg,
                         const R* grav, R q, R qd, R te, const UT* Us, int T, uint64_t seed, uint32_t tick,
                         uint32_t k, R* noise_out, size_t noise_stride, R* noise_lds = nullptr, int lds_stride = 0,
@@ -550,9 +588,9 @@ MPPI_HD R group_rollout(const G& g, const GroupLink<R>& L, const CostM<R>& C, co
             // factorises the gathered rows again
             R p[3], Q[9];
             qdd = group_dynamics<R, FORCE>(g, L, C, grav, ext, q, qd, v + te, v, g.shm, nullptr, p, Q);
-            S += group_cost<R, FORCE>(g, L, C, tg, g.shm, nullptr, q, qd, v, p, Q);
+            S += group_cost<R, FORCE, COLL>(g, L, C, tg, g.shm, nullptr, q, qd, v, p, Q);
         } else {
-            S += group_step<R, FORCE>(g, L, C, tg, grav, ext, q, qd, v + te, v, qdd);
+            S += group_step<R, FORCE, G, COLL>(g, L, C, tg, grav, ext, q, qd, v + te, v, qdd);
         }
         qd += qdd * C.dt;
         q += qd * C.dt;

@@ -452,7 +452,7 @@ struct DevGroup {
     __device__ void sync() const { wave_sync(); }
 };
 
-template <typename A, bool FORCE>
+template <typename A, bool FORCE, bool COLL>
 __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
     const ModelM<float>* __restrict__ Mp, const CostM<float>* __restrict__ Cp, const double* __restrict__ q0,
     const double* __restrict__ qd0, const double* __restrict__ target, const double* U_nom,
@@ -519,16 +519,6 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
                 const float v = (Us[s * NJ + jc] + nb[s & 1][grp][j]) * L.live;
                 float p[3], Q[9];
                 const float qdd = group_dynamics<float, FORCE>(g, L, C, grav, ext, q, qd, v + te, v, X, nullptr, p, Q);
-                // hand the pre-step state, v and the EE pose to the cost wave
-                float* h = X + kGxH + j * 12;
-                if (j < NJ) {
-                    h[0] = q; h[1] = qd; h[2] = v;
-                } else {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) h[a] = p[a];
-#pragma unroll
-                    for (int a = 0; a < 9; ++a) h[3 + a] = Q[a];
-                }
                 qd += qdd * C.dt;
                 q += qd * C.dt;
             }
@@ -543,7 +533,7 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
                 for (int a = 0; a < 3; ++a) pe[a] = h[a];
 #pragma unroll
                 for (int a = 0; a < 9; ++a) Re[a] = h[3 + a];
-                Sl += group_cost<float, FORCE>(g, L, C, tg, X, nullptr, h[0], h[1], h[2], pe, Re);
+                Sl += group_cost<float, FORCE, COLL>(g, L, C, tg, X, nullptr, h[0], h[1], h[2], pe, Re);
             }
         }
         __syncthreads();
@@ -1052,14 +1042,14 @@ template <typename A, bool FORCE, bool COLL> static hipError_t update_split_t(co
     return hipGetLastError();
 }
 
-template <typename A, bool FORCE> static hipError_t update_group_t(const UpdateArgs& a, hipStream_t s)
+template <typename A, bool FORCE, bool COLL> static hipError_t update_group_t(const UpdateArgs& a, hipStream_t s)
 {
     dim3 grid((a.K + kGroupSamples - 1) / kGroupSamples);
     float* noise = (float*)a.noise;
     if (a.merge && !a.want_noise) noise = nullptr;
     const size_t tile = (size_t)a.T * NJ * kGroupTile * sizeof(float);
     const int lds_noise = a.merge && tile <= (size_t)kMaxDynLds;
-    hipLaunchKernelGGL((update_group_kernel<A, FORCE>), grid, dim3(kGroupThreads), lds_noise ? tile : 0, s,
+    hipLaunchKernelGGL((update_group_kernel<A, FORCE, COLL>), grid, dim3(kGroupThreads), lds_noise ? tile : 0, s,
                        (const ModelM<float>*)a.model, (const CostM<float>*)a.cost, a.q0, a.qd0, a.target, a.U_nom,
                        a.seed, (uint32_t)a.tick, a.K, a.T, a.lambda, noise, (float*)a.costs, a.merge, lds_noise,
                        (A*)a.parts);
@@ -1072,9 +1062,9 @@ template <typename A, bool FORCE> static hipError_t update_group_t(const UpdateA
 template <bool EXPLICIT, bool COLL>
 static hipError_t update_dispatch(int precision, bool acc64, bool force, const UpdateArgs& a, hipStream_t s)
 {
-    if (!EXPLICIT && !COLL && a.waves_per_group == 8 && precision == MPPI_FP32) {
-        if (force) return acc64 ? update_group_t<double, true>(a, s) : update_group_t<float, true>(a, s);
-        return acc64 ? update_group_t<double, false>(a, s) : update_group_t<float, false>(a, s);
+    if (!EXPLICIT && a.waves_per_group == 8 && precision == MPPI_FP32) {
+        if (force) return acc64 ? update_group_t<double, true, COLL>(a, s) : update_group_t<float, true, COLL>(a, s);
+        return acc64 ? update_group_t<double, false, COLL>(a, s) : update_group_t<float, false, COLL>(a, s);
     }
     if (a.waves_per_group == 8) {   // the two-wave launch where groups do not apply
         UpdateArgs b = a;

@@ -316,11 +316,20 @@ static double group_rollout_t(const mppi_robot_params* rp, const mppi_cost_param
         const bool live = g.j < NJ;
         const int jc = live ? g.j : NJ - 1;
         const R qj = live ? q[jc] : R(0), qdj = live ? qd[jc] : R(0), tj = live ? te[jc] : R(0);
-        S[g.j] = C.has_force
-                     ? group_rollout<R, true>(g, L, C, tg, M.g, qj, qdj, tj, U, T, seed, (uint32_t)tick, k, nz.data(), 1,
-                                              nullptr, 0, split)
-                     : group_rollout<R, false>(g, L, C, tg, M.g, qj, qdj, tj, U, T, seed, (uint32_t)tick, k, nz.data(), 1,
-                                               nullptr, 0, split);
+        using HG = HostGroup<R>;
+        const uint32_t tk = (uint32_t)tick;
+        if (cp->n_pairs > 0)
+            S[g.j] = C.has_force
+                         ? group_rollout<R, true, HG, double, true>(g, L, C, tg, M.g, qj, qdj, tj, U, T, seed, tk, k,
+                                                                    nz.data(), 1, nullptr, 0, split)
+                         : group_rollout<R, false, HG, double, true>(g, L, C, tg, M.g, qj, qdj, tj, U, T, seed, tk, k,
+                                                                     nz.data(), 1, nullptr, 0, split);
+        else
+            S[g.j] = C.has_force
+                         ? group_rollout<R, true>(g, L, C, tg, M.g, qj, qdj, tj, U, T, seed, tk, k, nz.data(), 1,
+                                                  nullptr, 0, split)
+                         : group_rollout<R, false>(g, L, C, tg, M.g, qj, qdj, tj, U, T, seed, tk, k, nz.data(), 1,
+                                                   nullptr, 0, split);
     });
     for (int i = 0; i < T * NJ; ++i) noise[i] = double(nz[i]);
     for (int j = 1; j < kGroup; ++j)

@@ -371,3 +371,23 @@ def test_group_rollout_variants_match_oracle(hc, ora, workloads):
             S_ref, _ = ora.rollout(base["robot"], cost, base["target"], base["q0"], base["qd0"], U,
                                    base["seed"], 1, k)
             assert abs(S - S_ref) <= 1e-9 * abs(S_ref), (extra, S, S_ref)
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_group_rollout_with_collision_term_matches_oracle(hc, ora, workloads, split):
+    """FP64 group rollouts of the collision workload (Eqs. 14-15, pairs dealt
+    over the lanes) against the oracle's rollouts."""
+    D = C.POINTER(C.c_double)
+    fn = hc.hc_group_rollout_split if split else hc.hc_group_rollout
+    for case in workloads["collision_k4096"][:2]:
+        rp, cp = B.robot_params(case["robot"]), B.cost_params(case["cost"], B.FP64)
+        assert cp.n_pairs > 8   # more pairs than lanes
+        tgt = B.target_vector(case["target"])
+        U = np.ascontiguousarray(case["U_nom"], dtype=np.float64)
+        noise = np.zeros((case["cost"]["T"], 7))
+        for k in (0, 3, 100):
+            S = fn(C.byref(rp), C.byref(cp), B.FP64, tgt.ctypes.data_as(D), _d(case["q0"]), _d(case["qd0"]),
+                   U.ctypes.data_as(D), case["seed"], 2, k, noise.ctypes.data_as(D))
+            S_ref, _ = ora.rollout(case["robot"], case["cost"], case["target"], case["q0"], case["qd0"], U,
+                                   case["seed"], 2, k)
+            assert abs(S - S_ref) <= 1e-9 * abs(S_ref), (k, S, S_ref)
