@@ -324,15 +324,17 @@ constexpr int kGroupSteps = 32;   // steps per chunk of the partial's row sums (
 constexpr int kGroupTile = kGroupSamples + 1;   // row stride of the workgroup's du tile
 
 // Merge of np partials [np][2 + rows] of one problem (Eq. 4 by the
-// log-sum-exp rule of wave.hpp) by one workgroup of NT threads: the
-// partials' (m, s) pairs are read NT at a time, and every row's weighted
-// sum is split over NT / rows threads whose loads are issued 32 at a time,
-// so the merge waits for a few memory round trips.  sh: LDS [NT] of A.
+// log-sum-exp rule of wave.hpp), rows [r_lo, r_hi) of U_new (and U_shift)
+// by one workgroup of NT threads: every workgroup reads the partials'
+// (m, s) pairs for the global minimum and the normaliser eta, then splits
+// its rows' weighted sums over NT / (r_hi - r_lo) threads each, whose loads
+// are issued in batches (64 FP32 or 32 FP64 values).  Workgroup 0 writes
+// the status.  sh: LDS [NT] of A.
 template <typename A, int NT>
 __device__ void block_merge(const A* parts, int np, int T, double lambda, const double* U_nom, double* U_new,
-                            double* U_shift, int* status, int tid, A* sh)
+                            double* U_shift, int* status, int tid, A* sh, int r_lo, int r_hi, bool first)
 {
-    const int rows = T * NJ, P = 2 + rows;
+    const int P = 2 + T * NJ, rows = r_hi - r_lo;
     const A inf = A(INFINITY), il = A(1) / A(lambda);
     auto block_reduce = [&](A v, bool is_min) -> A {
         v = is_min ? wave_min(v) : wave_sum(v);
@@ -344,22 +346,22 @@ __device__ void block_merge(const A* parts, int np, int T, double lambda, const 
         for (int w = 1; w < NT / 64; ++w) r = is_min ? fmin(r, sh[w]) : r + sh[w];
         return r;
     };
+    auto write_row = [&](int r, double un) {
+        const int t = r / NJ, jj = r % NJ;
+        U_new[r] = un;
+        if (U_shift) {
+            if (t >= 1) U_shift[(t - 1) * NJ + jj] = un;
+            if (t == T - 1) U_shift[t * NJ + jj] = un;
+        }
+    };
     A mp0 = inf, sp0 = A(0);
     if (tid < np) { mp0 = parts[(size_t)tid * P]; sp0 = parts[(size_t)tid * P + 1]; }
     A mg = mp0;
     for (int p = tid + NT; p < np; p += NT) mg = fmin(mg, parts[(size_t)p * P]);
     mg = block_reduce(mg, true);
     if (!(mg < inf)) {
-        for (int r = tid; r < rows; r += NT) {
-            const int t = r / NJ, jj = r % NJ;
-            const double un = U_nom[r];
-            U_new[r] = un;
-            if (U_shift) {
-                if (t >= 1) U_shift[(t - 1) * NJ + jj] = un;
-                if (t == T - 1) U_shift[t * NJ + jj] = un;
-            }
-        }
-        if (status && tid == 0) *status = MPPI_ENONFINITE;
+        for (int r = r_lo + tid; r < r_hi; r += NT) write_row(r, U_nom[r]);
+        if (status && first && tid == 0) *status = MPPI_ENONFINITE;
         return;
     }
     const A f0 = mp0 < inf ? exp((mg - mp0) * il) : A(0);
@@ -369,12 +371,12 @@ __device__ void block_merge(const A* parts, int np, int T, double lambda, const 
         if (mp < inf) eta += exp((mg - mp) * il) * parts[(size_t)p * P + 1];
     }
     eta = block_reduce(eta, false);
-    // thread (slice, r): rows r, r + NT, ...; partials slice, slice + nsl, ...
+    // thread (slice, r): rows r_lo + r, + NT, ...; partials slice, slice + nsl, ...
     const int nsl = rows < NT ? NT / rows : 1;
     const int sl = tid / rows, r0 = tid % rows;
     for (int rb = 0; rb < rows; rb += (rows < NT ? rows : NT)) {
-        const int r = rb + r0;
-        const bool act = sl < nsl && r < rows;
+        const int r = r_lo + rb + r0;
+        const bool act = sl < nsl && r < r_hi;
         A acc = A(0);
         for (int p0 = 0; p0 < np; p0 += NT) {
             A f = f0;
@@ -391,15 +393,15 @@ __device__ void block_merge(const A* parts, int np, int T, double lambda, const 
             __syncthreads();
             const int n = min(NT, np - p0);
             if (act) {
-                // 32 loads in flight per thread, then their products
+                constexpr int NB = sizeof(A) == 4 ? 64 : 32;
                 const A* col = parts + (size_t)p0 * P + 2 + r;
                 int i = sl;
-                for (; i + 31 * nsl < n; i += 32 * nsl) {
-                    A v[32];
+                for (; i + (NB - 1) * nsl < n; i += NB * nsl) {
+                    A v[NB];
 #pragma unroll
-                    for (int u = 0; u < 32; ++u) v[u] = col[(size_t)(i + u * nsl) * P];
+                    for (int u = 0; u < NB; ++u) v[u] = col[(size_t)(i + u * nsl) * P];
 #pragma unroll
-                    for (int u = 0; u < 32; ++u) acc += sh[i + u * nsl] * v[u];
+                    for (int u = 0; u < NB; ++u) acc += sh[i + u * nsl] * v[u];
                 }
                 for (; i < n; i += nsl) acc += sh[i] * col[(size_t)i * P];
             }
@@ -409,16 +411,10 @@ __device__ void block_merge(const A* parts, int np, int T, double lambda, const 
         __syncthreads();
         if (act && sl == 0) {
             for (int q = 1; q < nsl; ++q) acc += sh[q * rows + r0];
-            const int t = r / NJ, jj = r % NJ;
-            const double un = U_nom[r] + double(acc / eta);
-            U_new[r] = un;
-            if (U_shift) {
-                if (t >= 1) U_shift[(t - 1) * NJ + jj] = un;
-                if (t == T - 1) U_shift[t * NJ + jj] = un;
-            }
+            write_row(r, U_nom[r] + double(acc / eta));
         }
     }
-    if (status && tid == 0) *status = MPPI_OK;
+    if (status && first && tid == 0) *status = MPPI_OK;
 }
 
 struct DevGroup {
@@ -619,7 +615,9 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
     // of them cost more than the merge)
 }
 
-// Eq. 4 from the np workgroup partials of update_group_kernel (one workgroup).
+// Eq. 4 from the np workgroup partials of update_group_kernel: workgroup b
+// writes rows [kMergeRows b, kMergeRows (b + 1)) of U_new.
+constexpr int kMergeRows = 16;
 template <typename A>
 __global__ __launch_bounds__(kGroupThreads) void group_merge_kernel(const A* __restrict__ parts, int np, int T,
                                                                     double lambda, const double* U_nom,
@@ -627,7 +625,9 @@ __global__ __launch_bounds__(kGroupThreads) void group_merge_kernel(const A* __r
                                                                     int* __restrict__ status)
 {
     __shared__ A sh[kGroupThreads];
-    block_merge<A, kGroupThreads>(parts, np, T, lambda, U_nom, U_new, U_shift, status, threadIdx.x, sh);
+    const int r_lo = blockIdx.x * kMergeRows, r_hi = min(T * NJ, r_lo + kMergeRows);
+    block_merge<A, kGroupThreads>(parts, np, T, lambda, U_nom, U_new, U_shift, status, threadIdx.x, sh, r_lo, r_hi,
+                                  blockIdx.x == 0);
 }
 
 // Batched update (a13): many independent problems (own arm, cost, K, T,
@@ -1054,7 +1054,8 @@ template <typename A, bool FORCE, bool COLL> static hipError_t update_group_t(co
                        a.seed, (uint32_t)a.tick, a.K, a.T, a.lambda, noise, (float*)a.costs, a.merge, lds_noise,
                        (A*)a.parts);
     if (a.merge)
-        hipLaunchKernelGGL((group_merge_kernel<A>), dim3(1), dim3(kGroupThreads), 0, s, (const A*)a.parts,
+        hipLaunchKernelGGL((group_merge_kernel<A>), dim3((a.T * NJ + kMergeRows - 1) / kMergeRows),
+                           dim3(kGroupThreads), 0, s, (const A*)a.parts,
                            (int)grid.x, a.T, a.lambda, a.U_nom, a.U_new, a.U_shift, a.status);
     return hipGetLastError();
 }
