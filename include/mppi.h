@@ -211,7 +211,9 @@ typedef struct {
 } mppi_device_io;
 
 /* Enqueues one update on `stream` (a hipStream_t; NULL = default stream):
- * the rollout kernel (noise, dynamics, cost) then the weighting kernel.
+ * the rollout kernel (noise, dynamics, cost, per-workgroup partials of
+ * Eq. 4) and the merge of the partials, fused into the rollout launch for
+ * the per-lane launch shapes and a second launch for the eight-lane one.
  * The caller synchronises.  Errors: MPPI_EINVAL, MPPI_EDEVICE. */
 int mppi_update_async(mppi_handle_t h, const mppi_device_io* io, void* stream);
 

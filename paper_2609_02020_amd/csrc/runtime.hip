@@ -228,7 +228,8 @@ int update_enqueue_one(mppi_solver* h, const mppi_device_io* io, hipStream_t s, 
 }
 
 // merge = false: rollouts only (costs, noise); merge = true: the full update,
-// one fused launch per MPPI iteration.  Iteration i of n reads the previous
+// per MPPI iteration one fused launch (per-lane shapes) or the eight-lane
+// launch and its merge launch.  Iteration i of n reads the previous
 // iteration's U_new (io->U_nominal for the first), writes it to one of the
 // two intermediate buffers (io->U_new and io->U_shift for the last) and
 // draws with the Philox tick word n * tick + i; the global noise, when
