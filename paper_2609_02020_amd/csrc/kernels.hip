@@ -323,100 +323,6 @@ constexpr int kGroupThreads = 128 * kGroupPairs;
 constexpr int kGroupSteps = 32;   // steps per chunk of the partial's row sums (regenerated noise)
 constexpr int kGroupTile = kGroupSamples + 1;   // row stride of the workgroup's du tile
 
-// Merge of np partials [np][2 + rows] of one problem (Eq. 4 by the
-// log-sum-exp rule of wave.hpp), rows [r_lo, r_hi) of U_new (and U_shift)
-// by one workgroup of NT threads: every workgroup reads the partials'
-// (m, s) pairs for the global minimum and the normaliser eta, then splits
-// its rows' weighted sums over NT / (r_hi - r_lo) threads each, whose loads
-// are issued in batches (64 FP32 or 32 FP64 values).  Workgroup 0 writes
-// the status.  sh: LDS [NT] of A.
-template <typename A, int NT>
-__device__ void block_merge(const A* parts, int np, int T, double lambda, const double* U_nom, double* U_new,
-                            double* U_shift, int* status, int tid, A* sh, int r_lo, int r_hi, bool first)
-{
-    const int P = 2 + T * NJ, rows = r_hi - r_lo;
-    const A inf = A(INFINITY), il = A(1) / A(lambda);
-    auto block_reduce = [&](A v, bool is_min) -> A {
-        v = is_min ? wave_min(v) : wave_sum(v);
-        __syncthreads();
-        if ((tid & 63) == 0) sh[tid >> 6] = v;
-        __syncthreads();
-        A r = sh[0];
-#pragma unroll
-        for (int w = 1; w < NT / 64; ++w) r = is_min ? fmin(r, sh[w]) : r + sh[w];
-        return r;
-    };
-    auto write_row = [&](int r, double un) {
-        const int t = r / NJ, jj = r % NJ;
-        U_new[r] = un;
-        if (U_shift) {
-            if (t >= 1) U_shift[(t - 1) * NJ + jj] = un;
-            if (t == T - 1) U_shift[t * NJ + jj] = un;
-        }
-    };
-    A mp0 = inf, sp0 = A(0);
-    if (tid < np) { mp0 = parts[(size_t)tid * P]; sp0 = parts[(size_t)tid * P + 1]; }
-    A mg = mp0;
-    for (int p = tid + NT; p < np; p += NT) mg = fmin(mg, parts[(size_t)p * P]);
-    mg = block_reduce(mg, true);
-    if (!(mg < inf)) {
-        for (int r = r_lo + tid; r < r_hi; r += NT) write_row(r, U_nom[r]);
-        if (status && first && tid == 0) *status = MPPI_ENONFINITE;
-        return;
-    }
-    const A f0 = mp0 < inf ? exp((mg - mp0) * il) : A(0);
-    A eta = f0 * sp0;
-    for (int p = tid + NT; p < np; p += NT) {
-        const A mp = parts[(size_t)p * P];
-        if (mp < inf) eta += exp((mg - mp) * il) * parts[(size_t)p * P + 1];
-    }
-    eta = block_reduce(eta, false);
-    // thread (slice, r): rows r_lo + r, + NT, ...; partials slice, slice + nsl, ...
-    const int nsl = rows < NT ? NT / rows : 1;
-    const int sl = tid / rows, r0 = tid % rows;
-    for (int rb = 0; rb < rows; rb += (rows < NT ? rows : NT)) {
-        const int r = r_lo + rb + r0;
-        const bool act = sl < nsl && r < r_hi;
-        A acc = A(0);
-        for (int p0 = 0; p0 < np; p0 += NT) {
-            A f = f0;
-            if (p0 > 0) {
-                const int p = p0 + tid;
-                f = A(0);
-                if (p < np) {
-                    const A mp = parts[(size_t)p * P];
-                    f = mp < inf ? exp((mg - mp) * il) : A(0);
-                }
-            }
-            __syncthreads();
-            sh[tid] = f;
-            __syncthreads();
-            const int n = min(NT, np - p0);
-            if (act) {
-                constexpr int NB = sizeof(A) == 4 ? 64 : 32;
-                const A* col = parts + (size_t)p0 * P + 2 + r;
-                int i = sl;
-                for (; i + (NB - 1) * nsl < n; i += NB * nsl) {
-                    A v[NB];
-#pragma unroll
-                    for (int u = 0; u < NB; ++u) v[u] = col[(size_t)(i + u * nsl) * P];
-#pragma unroll
-                    for (int u = 0; u < NB; ++u) acc += sh[i + u * nsl] * v[u];
-                }
-                for (; i < n; i += nsl) acc += sh[i] * col[(size_t)i * P];
-            }
-        }
-        __syncthreads();
-        sh[tid] = acc;
-        __syncthreads();
-        if (act && sl == 0) {
-            for (int q = 1; q < nsl; ++q) acc += sh[q * rows + r0];
-            write_row(r, U_nom[r] + double(acc / eta));
-        }
-    }
-    if (status && first && tid == 0) *status = MPPI_OK;
-}
-
 struct DevGroup {
     int j;
     float* shm;
@@ -427,6 +333,20 @@ struct DevGroup {
     template <int D> __device__ float shl(float x) const
     {
         return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x100 + D, 0xF, 0xF, true));
+    }
+    template <int S> __device__ float qperm(float x) const
+    {
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), S, 0xF, 0xF, true));
+    }
+    // banks (quads) 1 and 3 of each row of 16 lanes take the quad before them
+    __device__ float lo_to_hi(float x) const
+    {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x114, 0xF, 0xA, false));
+    }
+    // banks 0 and 2 take the quad after them
+    __device__ float hi_to_lo(float x) const
+    {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x104, 0xF, 0x5, false));
     }
     // lane K of the group: broadcast within each quad, then the other
     // half-group (banks of four lanes) takes it across with a row shift
@@ -616,18 +536,70 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
 }
 
 // Eq. 4 from the np workgroup partials of update_group_kernel: workgroup b
-// writes rows [kMergeRows b, kMergeRows (b + 1)) of U_new.
+// writes rows [kMergeRows b, kMergeRows (b + 1)) of U_new.  Thread
+// (slice, row) folds the partials slice, slice + kMergeSlices, ... into a
+// running (m, s, V) by the log-sum-exp rule of wave.hpp (a new minimum
+// rescales what it has), with each batch's loads issued together, so the
+// merge waits for one memory round trip per batch; the slices of a row
+// are then folded the same way through LDS.  Every row's slices cover all
+// partials, so each row has the full normaliser.
 constexpr int kMergeRows = 16;
+constexpr int kMergeSlices = kGroupThreads / kMergeRows;
 template <typename A>
 __global__ __launch_bounds__(kGroupThreads) void group_merge_kernel(const A* __restrict__ parts, int np, int T,
                                                                     double lambda, const double* U_nom,
                                                                     double* U_new, double* __restrict__ U_shift,
                                                                     int* __restrict__ status)
 {
-    __shared__ A sh[kGroupThreads];
-    const int r_lo = blockIdx.x * kMergeRows, r_hi = min(T * NJ, r_lo + kMergeRows);
-    block_merge<A, kGroupThreads>(parts, np, T, lambda, U_nom, U_new, U_shift, status, threadIdx.x, sh, r_lo, r_hi,
-                                  blockIdx.x == 0);
+    __shared__ A shm[kGroupThreads], shs[kGroupThreads], shv[kGroupThreads];
+    const int tid = threadIdx.x, rl = tid % kMergeRows, sl = tid / kMergeRows;
+    const int rows = T * NJ, P = 2 + rows;
+    const int r = blockIdx.x * kMergeRows + rl;
+    const bool act = r < rows;
+    const int rr = act ? r : 0;
+    const A inf = A(INFINITY), il = A(1) / A(lambda);
+    A m = inf, sw = A(0), acc = A(0);
+    // fold (mp, sp, vp) into (m, sw, acc)
+    auto fold = [&](A mp, A sp, A vp) {
+        if (!(mp < inf)) return;
+        if (mp < m) {
+            const A f = exp((mp - m) * il);   // 0 while m is still +inf
+            sw *= f;
+            acc *= f;
+            m = mp;
+        }
+        const A f = exp((m - mp) * il);
+        sw += f * sp;
+        acc += f * vp;
+    };
+    constexpr int NB = 16;
+    for (int p0 = sl; p0 < np; p0 += NB * kMergeSlices) {
+        A mv[NB], sv[NB], vv[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int p = p0 + u * kMergeSlices;
+            const A* pp = parts + (size_t)(p < np ? p : 0) * P;
+            mv[u] = p < np ? pp[0] : inf;
+            sv[u] = pp[1];
+            vv[u] = pp[2 + rr];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) fold(mv[u], sv[u], vv[u]);
+    }
+    shm[tid] = m;
+    shs[tid] = sw;
+    shv[tid] = acc;
+    __syncthreads();
+    if (sl != 0 || !act) return;
+    for (int q = 1; q < kMergeSlices; ++q) fold(shm[q * kMergeRows + rl], shs[q * kMergeRows + rl], shv[q * kMergeRows + rl]);
+    const int t = r / NJ, jj = r % NJ;
+    const double un = m < inf ? U_nom[r] + double(acc / sw) : U_nom[r];
+    U_new[r] = un;
+    if (U_shift) {
+        if (t >= 1) U_shift[(t - 1) * NJ + jj] = un;
+        if (t == T - 1) U_shift[t * NJ + jj] = un;
+    }
+    if (status && r == 0) *status = m < inf ? MPPI_OK : MPPI_ENONFINITE;
 }
 
 // Batched update (a13): many independent problems (own arm, cost, K, T,
