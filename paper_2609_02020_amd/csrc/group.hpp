@@ -39,8 +39,8 @@
 //
 // The code is written per lane against a group object G that provides the
 // cross-lane moves (shr<D>: value of lane j - D; shl<D>: of lane j + D;
-// invalid lanes are masked by the caller; bcast<K>: of lane K; qperm<S>:
-// the lane of its quad that S selects; lo_to_hi / hi_to_lo: lane j - 4 in
+// invalid lanes are masked by the caller; qperm<S>: the lane of its quad
+// that S selects; lo_to_hi / hi_to_lo: lane j - 4 in
 // lanes 4..7 / lane j + 4 in lanes 0..3, 0 elsewhere), sum (over the group),
 // sync() (orders the group's LDS area) and shm (that area, kGxCount
 // values).  On the device G is eight consecutive lanes of a wave (DPP row
@@ -55,13 +55,13 @@ namespace mppi {
 
 constexpr int kGroup = 8;
 // group LDS area (values of the rollout type)
-constexpr int kGxS = 16;                   // slot: S_j (6), Ic_j S_j (6), (p_j - p_ee) x z_j (3)
+constexpr int kGxS = 16;                   // slot: S_j (6), Ic_j S_j (6)
 constexpr int kGxSF = 0;                   // [8][kGxS]
 constexpr int kGxRow = kGxSF + 8 * kGxS;   // [8][9]: M row j, tau - h, tau_F
 constexpr int kGxY = kGxRow + 8 * 9;       // [8][8]: y columns of the force solve
 constexpr int kGxOm = kGxY + 8 * 8;        // [8][8]: Omega row r, b_r
-constexpr int kGxH = kGxOm + 8 * 8;        // [8][12]: handoff to the cost part: q, qd, v, p_j (lanes
-                                           // 0..6); lane 7: p_ee, R_ee
+constexpr int kGxH = kGxOm + 8 * 8;        // [8][12]: handoff to the cost part: q, qd, v, p_j, h_c, m_c
+                                           // (lanes 0..6); lane 7: p_ee, R_ee
 constexpr int kGxCount = kGxH + 8 * 12;    // 424
 
 // Per-lane constants of the group rollout (lane 7: the EE frame, massless).
@@ -203,20 +203,19 @@ template <typename R> struct GroupStepOut {
 };
 
 // M = L D L^T (unit lower L, lower triangle in Lm, 1/d in id) of the rows
-// gathered in the group area, in every lane; b0, bF: the right-hand sides
-// tau - h and tau_F of the rows.
+// gathered in the group area, in every lane; b0 (may be null): the
+// right-hand side tau - h of the rows.
 template <typename R> struct GroupFactor {
     R Lm[NJ][NJ];
     R id[NJ];
 };
-template <typename R> MPPI_HD void group_factor(const R* X, GroupFactor<R>& f, R* b0, R* bF)
+template <typename R> MPPI_HD void group_factor(const R* X, GroupFactor<R>& f, R* b0)
 {
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
 #pragma unroll
         for (int c = 0; c <= i; ++c) f.Lm[i][c] = X[kGxRow + i * 9 + c];
-        b0[i] = X[kGxRow + i * 9 + 7];
-        bF[i] = X[kGxRow + i * 9 + 8];
+        if (b0) b0[i] = X[kGxRow + i * 9 + 7];
     }
 #pragma unroll
     for (int k = 0; k < NJ; ++k) {
@@ -335,28 +334,13 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
         R Sv[6] = {z[0], z[1], z[2], pz[0], pz[1], pz[2]};
         inertia_mul(In, Sv, Fm);
     }
-    R tauF = v;
-    if (FORCE && C.force_mode == 0) {
-        const R ag[3] = {-grav[0], -grav[1], -grav[2]};
-        R ha[3];
-        cross3(In, ag, ha);
-        tauF = v - (dot3(z, ha) + In[3] * dot3(pz, ag));
-    }
 
-    // ---- gather S, Ic S and the EE Jacobian's linear rows (about p_ee)
+    // ---- gather S and Ic S
     R* slot = X + kGxSF + j * kGxS;
 #pragma unroll
     for (int a = 0; a < 3; ++a) { slot[a] = z[a]; slot[3 + a] = pz[a]; }
 #pragma unroll
     for (int a = 0; a < 6; ++a) slot[6 + a] = Fm[a];
-    if (FORCE) {
-        const R pe[3] = {g.template bcast<kGroup - 1>(p[0]), g.template bcast<kGroup - 1>(p[1]),
-                         g.template bcast<kGroup - 1>(p[2])};
-        const R d[3] = {p[0] - pe[0], p[1] - pe[1], p[2] - pe[2]};
-        R jz[3];
-        cross3(d, z, jz);
-        slot[12] = jz[0]; slot[13] = jz[1]; slot[14] = jz[2];
-    }
     g.sync();
     // row j of M: M_jc = S_min(j,c) . (Ic S)_max(j,c), plus the armature
     R row[NJ];
@@ -376,9 +360,8 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
 #pragma unroll
     for (int c = 0; c < NJ; ++c) X[kGxRow + j * 9 + c] = row[c];
     X[kGxRow + j * 9 + 7] = tau - hq;
-    X[kGxRow + j * 9 + 8] = tauF;
-    // handoff to the cost part: pre-step q, qd, v and the joint origin
-    // (lanes 0..6), the EE pose (lane 7)
+    // handoff to the cost part: pre-step q, qd, v, the joint origin and the
+    // subtree's mass and first moment (lanes 0..6), the EE pose (lane 7)
     R* h = X + kGxH + j * 12;
     if (ee) {
 #pragma unroll
@@ -388,14 +371,15 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
     } else {
         h[0] = q; h[1] = qd; h[2] = v;
         h[3] = p[0]; h[4] = p[1]; h[5] = p[2];
+        if (FORCE) { h[6] = In[0]; h[7] = In[1]; h[8] = In[2]; h[9] = In[3]; }
     }
     g.sync();
 
     // ---- Eq. 6: qdd = L^-T D^-1 L^-1 (tau + tau_ext - h)
     GroupFactor<R> local;
     GroupFactor<R>& F = fac ? *fac : local;
-    R b0[NJ], bF[NJ], x[NJ];
-    group_factor(X, F, b0, bF);
+    R b0[NJ], x[NJ];
+    group_factor(X, F, b0);
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
         R s = b0[i];
@@ -425,8 +409,9 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
 // from the joint origins and the EE point in the handoff).  Uses the kGxY
 // and kGxOm parts of X.
 template <typename R, bool FORCE, bool COLL, class G>
-MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg, R* X,
-                     const GroupFactor<R>* fac, R q, R qd, R v, const R* pee, const R* Re, R* Fout = nullptr)
+MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg, const R* grav,
+                     R* X, const GroupFactor<R>* fac, R q, R qd, R v, const R* pee, const R* Re,
+                     R* Fout = nullptr)
 {
     const int j = g.j;
     const bool ee = j == kGroup - 1;
@@ -455,22 +440,47 @@ MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
         ell += C.w_coll * hits;
     }
     if (FORCE) {
-        GroupFactor<R> local;
-        R b0[NJ], bF[NJ];
-        if (!fac) group_factor(X, local, b0, bF);
-        else {
-#pragma unroll
-            for (int i = 0; i < NJ; ++i) bF[i] = X[kGxRow + i * 9 + 8];
+        // tau_F of this lane's joint: v, less the gravity torque
+        // S . Ic (0, -g) of the subtree when force_mode is 0
+        {
+            const R* sj = X + kGxSF + j * kGxS;
+            const R* hj = X + kGxH + j * 12;
+            R tf = v;
+            if (C.force_mode == 0) {
+                const R ag[3] = {-grav[0], -grav[1], -grav[2]};
+                R ha[3];
+                cross3(hj + 6, ag, ha);
+                tf = v - (dot3(sj, ha) + hj[9] * dot3(sj + 3, ag));
+            }
+            X[kGxRow + j * 9 + 8] = ee ? R(0) : tf;
         }
+        // row r of the EE Jacobian about p_ee at joint i: z_i (r < 3), then
+        // (p_i - p_ee) x z_i
+        const int r = j < 6 ? j : 5;
+        R Jr[NJ];
+        {
+            const R* pe = X + kGxH + (kGroup - 1) * 12;
+            const int c = r < 3 ? 0 : r - 3, c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) {
+                const R* zi = X + kGxSF + i * kGxS;
+                const R* pi = X + kGxH + i * 12 + 3;
+                const R d1 = pi[c1] - pe[c1], d2 = pi[c2] - pe[c2];
+                Jr[i] = r < 3 ? zi[r] : d1 * zi[c2] - d2 * zi[c1];
+            }
+        }
+        g.sync();
+        GroupFactor<R> local;
+        if (!fac) group_factor(X, local, (R*)nullptr);
         const GroupFactor<R>& Fc = fac ? *fac : local;
-        // ---- lane r < 6 solves for row r of J (angular rows z, then the
-        // linear rows about p_ee), lane 6 (and 7) for tau_F
+        R bF[NJ];
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) bF[i] = X[kGxRow + i * 9 + 8];
+        // ---- lane r < 6 solves for row r of J, lane 6 (and 7) for tau_F
         R y[NJ];
-        const int r = j < 3 ? j : (j < 6 ? j + 9 : 14);
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
-            const R Jri = X[kGxSF + i * kGxS + r];
-            R s = j < 6 ? Jri : bF[i];
+            R s = j < 6 ? Jr[i] : bF[i];
 #pragma unroll
             for (int c = 0; c < i; ++c) s = fma_(-Fc.Lm[i][c], y[c], s);
             y[i] = s;
@@ -527,7 +537,7 @@ MPPI_HD R group_step(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
     GroupFactor<R> fac;
     R p[3], Q[9], F[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     qdd = group_dynamics<R, FORCE>(g, L, C, grav, ext, q, qd, tau, v, g.shm, &fac, p, Q);
-    const R ell = group_cost<R, FORCE, COLL>(g, L, C, tg, g.shm, &fac, q, qd, v, p, Q, F);
+    const R ell = group_cost<R, FORCE, COLL>(g, L, C, tg, grav, g.shm, &fac, q, qd, v, p, Q, F);
     if (dbg) {
         dbg->qdd = qdd;
 #pragma unroll
@@ -577,7 +587,7 @@ MPPI_HD R group_rollout(const G& g, const GroupLink<R>& L, const CostM<R>& C, co
             // factorises the gathered rows again
             R p[3], Q[9];
             qdd = group_dynamics<R, FORCE>(g, L, C, grav, ext, q, qd, v + te, v, g.shm, nullptr, p, Q);
-            S += group_cost<R, FORCE, COLL>(g, L, C, tg, g.shm, nullptr, q, qd, v, p, Q);
+            S += group_cost<R, FORCE, COLL>(g, L, C, tg, grav, g.shm, nullptr, q, qd, v, p, Q);
         } else {
             S += group_step<R, FORCE, G, COLL>(g, L, C, tg, grav, ext, q, qd, v + te, v, qdd);
         }
