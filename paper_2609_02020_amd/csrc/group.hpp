@@ -39,8 +39,8 @@
 //
 // The code is written per lane against a group object G that provides the
 // cross-lane moves (shr<D>: value of lane j - D; shl<D>: of lane j + D;
-// invalid lanes are masked by the caller; qperm<S>: the lane of its quad
-// that S selects; lo_to_hi / hi_to_lo: lane j - 4 in
+// invalid lanes are masked by the caller; bcast<K>: of lane K; qperm<S>:
+// the lane of its quad that S selects; lo_to_hi / hi_to_lo: lane j - 4 in
 // lanes 4..7 / lane j + 4 in lanes 0..3, 0 elsewhere), sum (over the group),
 // sync() (orders the group's LDS area) and shm (that area, kGxCount
 // values).  On the device G is eight consecutive lanes of a wave (DPP row
@@ -55,7 +55,7 @@ namespace mppi {
 
 constexpr int kGroup = 8;
 // group LDS area (values of the rollout type)
-constexpr int kGxS = 16;                   // slot: S_j (6), Ic_j S_j (6)
+constexpr int kGxS = 16;                   // slot: S_j (6), Ic_j S_j (6), (p_j - p_ee) x z_j (3)
 constexpr int kGxSF = 0;                   // [8][kGxS]
 constexpr int kGxRow = kGxSF + 8 * kGxS;   // [8][9]: M row j, tau - h, tau_F
 constexpr int kGxY = kGxRow + 8 * 9;       // [8][8]: y columns of the force solve
@@ -236,7 +236,12 @@ template <typename R> MPPI_HD void group_factor(const R* X, GroupFactor<R>& f, R
 // lane's qdd (0 in lane 7); p, Q receive this lane's frame (lane 7: the EE
 // pose).  tau: this lane's joint torque (sampled torque plus any
 // joint-space external torque); v: the sampled torque (tau_F).
-template <typename R, bool FORCE, class G>
+// FDYN: the inputs of the force estimate (tau_F in column 8 of the rows,
+// the EE Jacobian's linear rows in slots 12..14) are formed here, on the
+// dynamics chain; otherwise group_cost forms them from the handoff.  The
+// update kernel chooses FDYN when the cost part also carries the collision
+// pairs, so that neither part runs both.
+template <typename R, bool FORCE, class G, bool FDYN = false>
 MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, const R* grav, int ext, R q, R qd,
                          R tau, R v, R* X, GroupFactor<R>* fac, R* p, R* Q)
 {
@@ -341,6 +346,24 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
     for (int a = 0; a < 3; ++a) { slot[a] = z[a]; slot[3 + a] = pz[a]; }
 #pragma unroll
     for (int a = 0; a < 6; ++a) slot[6 + a] = Fm[a];
+    if (FORCE && FDYN) {
+        // tau_F (less the gravity torque S . Ic (0, -g) when force_mode is 0)
+        R tf = v;
+        if (C.force_mode == 0) {
+            const R ag[3] = {-grav[0], -grav[1], -grav[2]};
+            R ha[3];
+            cross3(In, ag, ha);
+            tf = v - (dot3(z, ha) + In[3] * dot3(pz, ag));
+        }
+        X[kGxRow + j * 9 + 8] = ee ? R(0) : tf;
+        // (p_j - p_ee) x z_j
+        const R pe[3] = {g.template bcast<kGroup - 1>(p[0]), g.template bcast<kGroup - 1>(p[1]),
+                         g.template bcast<kGroup - 1>(p[2])};
+        const R d[3] = {p[0] - pe[0], p[1] - pe[1], p[2] - pe[2]};
+        R jz[3];
+        cross3(d, z, jz);
+        slot[12] = jz[0]; slot[13] = jz[1]; slot[14] = jz[2];
+    }
     g.sync();
     // row j of M: M_jc = S_min(j,c) . (Ic S)_max(j,c), plus the armature
     R row[NJ];
@@ -371,7 +394,7 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
     } else {
         h[0] = q; h[1] = qd; h[2] = v;
         h[3] = p[0]; h[4] = p[1]; h[5] = p[2];
-        if (FORCE) { h[6] = In[0]; h[7] = In[1]; h[8] = In[2]; h[9] = In[3]; }
+        if (FORCE && !FDYN) { h[6] = In[0]; h[7] = In[1]; h[8] = In[2]; h[9] = In[3]; }
     }
     g.sync();
 
@@ -408,7 +431,7 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
 // the pairs dealt over the lanes (pair i to lane i mod 8; link segments
 // from the joint origins and the EE point in the handoff).  Uses the kGxY
 // and kGxOm parts of X.
-template <typename R, bool FORCE, bool COLL, class G>
+template <typename R, bool FORCE, bool COLL, class G, bool FDYN = false>
 MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg, const R* grav,
                      R* X, const GroupFactor<R>* fac, R q, R qd, R v, const R* pee, const R* Re,
                      R* Fout = nullptr)
@@ -442,7 +465,7 @@ MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
     if (FORCE) {
         // tau_F of this lane's joint: v, less the gravity torque
         // S . Ic (0, -g) of the subtree when force_mode is 0
-        {
+        if (!FDYN) {
             const R* sj = X + kGxSF + j * kGxS;
             const R* hj = X + kGxH + j * 12;
             R tf = v;
@@ -458,7 +481,10 @@ MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
         // (p_i - p_ee) x z_i
         const int r = j < 6 ? j : 5;
         R Jr[NJ];
-        {
+        if (FDYN) {
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) Jr[i] = X[kGxSF + i * kGxS + (r < 3 ? r : r + 9)];
+        } else {
             const R* pe = X + kGxH + (kGroup - 1) * 12;
             const int c = r < 3 ? 0 : r - 3, c1 = (c + 1) % 3, c2 = (c + 2) % 3;
 #pragma unroll
@@ -536,8 +562,8 @@ MPPI_HD R group_step(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
 {
     GroupFactor<R> fac;
     R p[3], Q[9], F[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-    qdd = group_dynamics<R, FORCE>(g, L, C, grav, ext, q, qd, tau, v, g.shm, &fac, p, Q);
-    const R ell = group_cost<R, FORCE, COLL>(g, L, C, tg, grav, g.shm, &fac, q, qd, v, p, Q, F);
+    qdd = group_dynamics<R, FORCE, G, COLL>(g, L, C, grav, ext, q, qd, tau, v, g.shm, &fac, p, Q);
+    const R ell = group_cost<R, FORCE, COLL, G, COLL>(g, L, C, tg, grav, g.shm, &fac, q, qd, v, p, Q, F);
     if (dbg) {
         dbg->qdd = qdd;
 #pragma unroll
@@ -586,8 +612,8 @@ MPPI_HD R group_rollout(const G& g, const GroupLink<R>& L, const CostM<R>& C, co
             // as a dynamics wave and a cost wave share the step: the cost part
             // factorises the gathered rows again
             R p[3], Q[9];
-            qdd = group_dynamics<R, FORCE>(g, L, C, grav, ext, q, qd, v + te, v, g.shm, nullptr, p, Q);
-            S += group_cost<R, FORCE, COLL>(g, L, C, tg, grav, g.shm, nullptr, q, qd, v, p, Q);
+            qdd = group_dynamics<R, FORCE, G, COLL>(g, L, C, grav, ext, q, qd, v + te, v, g.shm, nullptr, p, Q);
+            S += group_cost<R, FORCE, COLL, G, COLL>(g, L, C, tg, grav, g.shm, nullptr, q, qd, v, p, Q);
         } else {
             S += group_step<R, FORCE, G, COLL>(g, L, C, tg, grav, ext, q, qd, v + te, v, qdd);
         }

@@ -348,6 +348,16 @@ struct DevGroup {
     {
         return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x104, 0xF, 0x5, false));
     }
+    // lane K of the group: broadcast within each quad, then the other
+    // half-group (banks of four lanes) takes it across with a row shift
+    template <int K> __device__ float bcast(float x) const
+    {
+        constexpr int q = K & 3;
+        int t = __builtin_amdgcn_mov_dpp(__float_as_int(x), q | (q << 2) | (q << 4) | (q << 6), 0xF, 0xF, true);
+        if (K < 4) t = __builtin_amdgcn_update_dpp(t, t, 0x114, 0xF, 0xA, false);
+        else t = __builtin_amdgcn_update_dpp(t, t, 0x104, 0xF, 0x5, false);
+        return __int_as_float(t);
+    }
     __device__ float sum(float x) const
     {
         x += __shfl_xor(x, 1);
@@ -424,7 +434,8 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
                 const DevGroup g{j, X};
                 const float v = (Us[s * NJ + jc] + nb[s & 1][grp][j]) * L.live;
                 float p[3], Q[9];
-                const float qdd = group_dynamics<float, FORCE>(g, L, C, grav, ext, q, qd, v + te, v, X, nullptr, p, Q);
+                const float qdd = group_dynamics<float, FORCE, DevGroup, COLL>(g, L, C, grav, ext, q, qd, v + te, v, X,
+                                                                               nullptr, p, Q);
                 qd += qdd * C.dt;
                 q += qd * C.dt;
             }
@@ -439,7 +450,8 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
                 for (int a = 0; a < 3; ++a) pe[a] = h[a];
 #pragma unroll
                 for (int a = 0; a < 9; ++a) Re[a] = h[3 + a];
-                Sl += group_cost<float, FORCE, COLL>(g, L, C, tg, grav, X, nullptr, h[0], h[1], h[2], pe, Re);
+                Sl += group_cost<float, FORCE, COLL, DevGroup, COLL>(g, L, C, tg, grav, X, nullptr, h[0], h[1], h[2], pe,
+                                                                     Re);
             }
         }
         __syncthreads();

@@ -241,6 +241,14 @@ template <typename R> struct HostGroup {
         s->barrier();
         return r;
     }
+    template <int K> R bcast(R x) const
+    {
+        s->slot[j] = double(x);
+        s->barrier();
+        const R r = R(s->slot[K]);
+        s->barrier();
+        return r;
+    }
     // the device's butterfly: x + x^1, then + ^2, then + ^4
     R sum(R x) const
     {
