@@ -45,7 +45,7 @@ FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (AMD published)
 # known size (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 on gfx950), taken on the
 # kernel sources whose digest is recorded here; reported as null once the
 # sources differ.
-PROFILED_DIGEST = "d78ece581757821d"
+PROFILED_DIGEST = "f0bff8576b3a92a0"
 PROFILED_TRAFFIC = {"update_group_kernel": 511573 + 740471,    # K=4096, T=18 contact workload: the
                                                             # group kernel and its merge launch
                     "batch_kernel": 39295840 + 354172760,   # 64-problem batch (W=2 x 1024); mostly

@@ -34,14 +34,15 @@
 //                per lane after a gather; every lane then solves the 6x6
 //                system (Cholesky) for the EE wrench;
 //   cost         lane 7 adds the pose and force terms of Eqs. 9-13, lanes
-//                0..6 their joint's limit and torque terms (Eq. 14); the
-//                group sums its lanes once, after the horizon.
+//                0..6 their joint's limit and torque terms (Eq. 14), and
+//                the collision pairs of Eq. 15 are dealt over the eight
+//                lanes; the group sums its lanes once, after the horizon.
 //
 // The code is written per lane against a group object G that provides the
-// cross-lane moves (shr<D>: value of lane j - D; shl<D>: of lane j + D;
-// invalid lanes are masked by the caller; bcast<K>: of lane K; qperm<S>:
-// the lane of its quad that S selects; lo_to_hi / hi_to_lo: lane j - 4 in
-// lanes 4..7 / lane j + 4 in lanes 0..3, 0 elsewhere), sum (over the group),
+// cross-lane moves (shr<D>: value of lane j - D, invalid lanes masked by the
+// caller; bcast<K>: of lane K; qperm<S>: the lane of its quad that S
+// selects; lo_to_hi / hi_to_lo: lane j - 4 in lanes 4..7 / lane j + 4 in
+// lanes 0..3, 0 elsewhere), sum (over the group),
 // sync() (orders the group's LDS area) and shm (that area, kGxCount
 // values).  On the device G is eight consecutive lanes of a wave (DPP row
 // shifts; a row of 16 lanes holds two groups, so shifts never cross

@@ -1,11 +1,18 @@
 // kernels.hip -- the MPPI hot path on gfx950.
 //
+//   update_group_kernel + group_merge_kernel (a1-a12, the default for FP32
+//                   rollouts): eight lanes per sample (group.hpp) on
+//                   dynamics/cost wave pairs, workgroup partials of Eq. 4,
+//                   merged by a second launch.
+//   update_split_kernel (two waves per 64 samples) and
 //   update_kernel   (a1-a12): one sample per lane.  Noise from in-register
 //                   Philox, the per-step dynamics/cost of dyn.hpp, FP32 (or
 //                   FP64) cost accumulation; writes S_k and du[t][j][k]
 //                   (k fastest, so a wave's stores are coalesced); then the
 //                   Eq. 4 weighting as per-wave partials merged by the last
 //                   block (one launch per update).
+//   batch_kernel    (a13): one persistent launch over the 64-sample tiles of
+//                   many problems, one sample per lane.
 //   weights_kernel  (a10-a12 alone, on given costs and noise).  Every
 //                   block recomputes S_min and eta = sum_k omega_k over the
 //                   K costs (L2-resident) and reduces omega_k du[row][k] for
@@ -329,10 +336,6 @@ struct DevGroup {
     template <int D> __device__ float shr(float x) const
     {
         return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x110 + D, 0xF, 0xF, true));
-    }
-    template <int D> __device__ float shl(float x) const
-    {
-        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x100 + D, 0xF, 0xF, true));
     }
     template <int S> __device__ float qperm(float x) const
     {

@@ -209,14 +209,6 @@ template <typename R> struct HostGroup {
         s->barrier();
         return r;
     }
-    template <int D> R shl(R x) const
-    {
-        s->slot[j] = double(x);
-        s->barrier();
-        const R r = j + D < kGroup ? R(s->slot[j + D]) : R(0);
-        s->barrier();
-        return r;
-    }
     template <int S> R qperm(R x) const
     {
         s->slot[j] = double(x);
