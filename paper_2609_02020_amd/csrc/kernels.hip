@@ -488,14 +488,16 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
     for (int i = 0; i < kGroupSamples; ++i) m = fmin(m, sS[i] < INFINITY ? A(sS[i]) : inf);
     if (tid < kGroupSamples) wsm[tid] = sS[tid] < INFINITY ? exp((m - A(sS[tid])) * il) : A(0);
     __syncthreads();
-    A* part = parts + (size_t)blockIdx.x * (2 + T * NJ);
+    // partials: (m, s) of every workgroup in [nb][2], then V in [nb][7T]
+    A* part_ms = parts + (size_t)blockIdx.x * 2;
+    A* part = parts + (size_t)gridDim.x * 2 + (size_t)blockIdx.x * (T * NJ);
     if (lds_noise) {
         for (int r = tid; r < T * NJ; r += blockDim.x) {
             const float* row = tile + r * kGroupTile;
             A acc = A(0);
 #pragma unroll
             for (int i = 0; i < kGroupSamples; ++i) acc += wsm[i] * A(row[i]);
-            part[2 + r] = acc;
+            part[r] = acc;
         }
     } else {
         // regenerated noise: the cost waves' lanes reduce w du over their
@@ -521,7 +523,7 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
                 A acc = A(0);
 #pragma unroll
                 for (int w = 0; w < kGroupPairs; ++w) acc += vs[w][tt * 8 + jj];
-                part[2 + (t0 + tt) * NJ + jj] = acc;
+                part[(t0 + tt) * NJ + jj] = acc;
             }
             __syncthreads();
         }
@@ -530,8 +532,8 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
         A st = A(0);
 #pragma unroll
         for (int i = 0; i < kGroupSamples; ++i) st += wsm[i];
-        part[0] = m;
-        part[1] = st;
+        part_ms[0] = m;
+        part_ms[1] = st;
     }
 
     // the partials are merged by group_merge_kernel, launched next on the
@@ -540,8 +542,9 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
     // of them cost more than the merge)
 }
 
-// Eq. 4 from the np workgroup partials of update_group_kernel: workgroup b
-// writes rows [kMergeRows b, kMergeRows (b + 1)) of U_new.  Thread
+// Eq. 4 from the np workgroup partials of update_group_kernel ((m, s) pairs
+// [np][2], then the row sums [np][7T]): workgroup b writes rows
+// [kMergeRows b, kMergeRows (b + 1)) of U_new.  Thread
 // (slice, row) folds the partials slice, slice + kMergeSlices, ... into a
 // running (m, s, V) by the log-sum-exp rule of wave.hpp (a new minimum
 // rescales what it has), with each batch's loads issued together, so the
@@ -558,7 +561,8 @@ __global__ __launch_bounds__(kGroupThreads) void group_merge_kernel(const A* __r
 {
     __shared__ A shm[kGroupThreads], shs[kGroupThreads], shv[kGroupThreads];
     const int tid = threadIdx.x, rl = tid % kMergeRows, sl = tid / kMergeRows;
-    const int rows = T * NJ, P = 2 + rows;
+    const int rows = T * NJ;
+    const A* vparts = parts + (size_t)np * 2;   // [np][rows] after the (m, s) pairs
     const int r = blockIdx.x * kMergeRows + rl;
     const bool act = r < rows;
     const int rr = act ? r : 0;
@@ -582,11 +586,10 @@ __global__ __launch_bounds__(kGroupThreads) void group_merge_kernel(const A* __r
         A mv[NB], sv[NB], vv[NB];
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
-            const int p = p0 + u * kMergeSlices;
-            const A* pp = parts + (size_t)(p < np ? p : 0) * P;
-            mv[u] = p < np ? pp[0] : inf;
-            sv[u] = pp[1];
-            vv[u] = pp[2 + rr];
+            const int p = p0 + u * kMergeSlices, pc = p < np ? p : 0;
+            mv[u] = p < np ? parts[2 * pc] : inf;
+            sv[u] = parts[2 * pc + 1];
+            vv[u] = vparts[(size_t)pc * rows + rr];
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) fold(mv[u], sv[u], vv[u]);
