@@ -373,6 +373,37 @@ def batch_bench(B, cases, torch, dev, ticks):
                          "kernel": "batch_kernel", "flops_per_launch": flops}}
 
 
+def graph_update_bench(solver, io, torch, reps=200):
+    """The device-resident update replayed from a captured HIP graph: the
+    launches of one mppi_update_async (with this io's tick) captured on a
+    torch capture stream, each replay bracketed by HIP events."""
+    import numpy as np
+    gio = dict(io)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        solver.update_async(gio, side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        solver.update_async(gio, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    for _ in range(20):
+        graph.replay()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for i in range(reps):
+        ev[i][0].record(stream)
+        graph.replay()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    graph.reset()
+    return {"update_ms": float(np.mean(ms)),
+            "update_ms_p5_p50_p95": [float(np.percentile(ms, x)) for x in (5, 50, 95)],
+            "update_hz": 1e3 / float(np.mean(ms))}
+
+
 def main():
     args = parse()
     if args.cpu_study > 0:
@@ -489,6 +520,11 @@ def main():
                             "two_waves_per_64_samples_ms": shape_ms(2),
                             "one_wave_per_64_samples_ms": shape_ms(1)}
     solver.set_launch(8)
+    out["graph_update"] = graph_update_bench(solver, io, torch)
+    # latency-bound at this K: one resident wave per SIMD, T + 1 dependent
+    # steps (T rollout steps, then the terminal cost)
+    out["roofline"]["waves_resident"] = 4 * ((K + 15) // 16)
+    out["roofline"]["per_step_us_upper"] = 1e3 * float(np.mean(roll_ms)) / (T + 1)
     if args.batch_ticks > 0:
         out["batch"] = batch_bench(B, inputs.load()["batch64"], torch, dev, args.batch_ticks)
     if not args.no_mlp:
