@@ -391,7 +391,8 @@ int mppi_mlp_train_step_async(mppi_mlp_t m, const float* x, const float* y_targe
                               const mppi_adam_params* p, float* loss, void* stream);
 /* Mean torque sequences of n states (1 <= n <= max_batch): q, qd [n][7],
  * target [n][13] (the update's layout; F_des unused) in, U [n][u_stride]
- * doubles out (the first 126 of each row: [18][7]); all device memory. */
+ * doubles out (the first 126 of each row: [18][7]); all device memory.
+ * One kernel launch: the input features are encoded in its input load. */
 int mppi_mlp_propose_async(mppi_mlp_t m, int n, const double* q, const double* qd, const double* target,
                            double* U, int u_stride, void* stream);
 

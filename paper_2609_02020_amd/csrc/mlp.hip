@@ -4,7 +4,9 @@
 //   mlp_forward_kernel<TRAIN>  one workgroup (4 waves) per 16 states (one
 //                   matrix-core row tile, so a 512-row batch spreads over 32
 //                   workgroups); the layers run back to back with the
-//                   activation tile in LDS.  Training adds the MSE signal and the backward
+//                   activation tile in LDS.  A proposal encodes the input
+//                   features from the states in the same launch (one
+//                   launch per proposal).  Training adds the MSE signal and the backward
 //                   products e_{l-1} = (e_l W_l) * gelu'(z_{l-1}) in the same
 //                   workgroup (the rows are independent), storing every
 //                   activation and signal transposed for the weight gradients.
@@ -13,17 +15,20 @@
 //                   splitting the batch; db_l = sum of e_l.
 //   mlp_adam_kernel    Adam on the FP32 master weights, then the BF16 copies
 //                   (row-major and transposed).
-//   mlp_features_kernel  (q/q_max, qd/qd_max, p_des, quat_des with w >= 0),
-//                   and optionally the normalised targets U* / tau_max.
+//   mlp_features_kernel  (q/q_max, qd/qd_max, p_des, quat_des with w >= 0)
+//                   of recorded states for training rows, and optionally
+//                   the normalised targets U* / tau_max.
 //
 // Matrix-core fragments (16 x 16 x 16): lane l holds row (l mod 16) of A and
-// column (l mod 16) of B, each with the four k values 4 (l div 16) + 0..3;
-// the FP32 result holds column (l mod 16), rows 4 (l div 16) + 0..3.
-// Every operand is read with k contiguous: A from the LDS tile [row][k]
-// (row stride 264 BF16, so the 64 lanes of a fragment read hit distinct
-// banks), B^T from the row-major weights [n][k] (forward) or from their
-// stored transposes (backward), and both operands of the weight gradient
-// from the transposed [feature][batch] buffers.
+// column (l mod 16) of B, each with four of the step's 16 k values, the same
+// four for both operands (slots 4 (l div 16) + 0..3); the FP32 result holds
+// column (l mod 16), rows 4 (l div 16) + 0..3.  Every operand is read with
+// k contiguous: in the layer products a lane's k values of two consecutive
+// steps are 8 contiguous k, one 16-byte read per operand, A from the LDS
+// tile [row][k] (row stride 264 BF16: the 16 rows of a lane group start on
+// distinct banks), B^T from the row-major weights [n][k] (forward) or from
+// their stored transposes (backward); both operands of the weight gradient
+// come from the transposed [feature][batch] buffers, four k per step.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -35,6 +40,7 @@ namespace mppi {
 namespace {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
@@ -78,21 +84,27 @@ __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
 
 // acc[i][j] = sum_k A[16 i + r][k] Bt[nb + 16 j + c][k] over the RT row
 // tiles of the LDS tile A and CT column tiles of the global k-contiguous
-// Bt [N][K].  Every B fragment of the layer is requested before the first
-// product, so the wave waits for one memory latency per layer instead of
-// one per k-step.
+// Bt [N][K].  The contraction runs over k in chunks of 32 as two
+// matrix-core steps whose k sets are interleaved by lane group: lanes
+// 16 g .. 16 g + 15 supply k = 32 t + 8 g + 0..3 to the first step and
+// 32 t + 8 g + 4..7 to the second, the same k for both operands, so every
+// lane reads 16 contiguous bytes of each operand per chunk (half the load
+// instructions of one 8-byte read per step).  Every B fragment of the
+// layer is requested before the first product, so the wave waits for one
+// memory latency per layer instead of one per k-step.
 template <int K, int CT, int RT = kMlpWgRows / 16>
 __device__ __forceinline__ void tile_mm(const uint16_t* A, const uint16_t* __restrict__ Bt, int nb,
                                         v4f (&acc)[RT][CT], int lane)
 {
-    constexpr int KS = K / 16;
-    const int r = lane & 15, kq = (lane >> 4) * 4;
-    v4s b[KS][CT];
+    static_assert(K % 32 == 0, "the contraction runs in chunks of 32");
+    constexpr int KC = K / 32;
+    const int r = lane & 15, kg = (lane >> 4) * 8;
+    v8s b[KC][CT];
 #pragma unroll
-    for (int s = 0; s < KS; ++s)
+    for (int t = 0; t < KC; ++t)
 #pragma unroll
         for (int j = 0; j < CT; ++j)
-            b[s][j] = *reinterpret_cast<const v4s*>(Bt + (size_t)(nb + 16 * j + r) * K + 16 * s + kq);
+            b[t][j] = *reinterpret_cast<const v8s*>(Bt + (size_t)(nb + 16 * j + r) * K + 32 * t + kg);
     // keep the scheduler from sinking the loads next to their products
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -100,14 +112,17 @@ __device__ __forceinline__ void tile_mm(const uint16_t* A, const uint16_t* __res
 #pragma unroll
         for (int j = 0; j < CT; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-        v4s a[RT];
+    for (int t = 0; t < KC; ++t) {
+        v8s a[RT];
 #pragma unroll
-        for (int i = 0; i < RT; ++i) a[i] = *reinterpret_cast<const v4s*>(A + (16 * i + r) * kLda + 16 * s + kq);
+        for (int i = 0; i < RT; ++i) a[i] = *reinterpret_cast<const v8s*>(A + (16 * i + r) * kLda + 32 * t + kg);
 #pragma unroll
         for (int i = 0; i < RT; ++i)
 #pragma unroll
-            for (int j = 0; j < CT; ++j) acc[i][j] = mfma(a[i], b[s][j], acc[i][j]);
+            for (int j = 0; j < CT; ++j) {
+                acc[i][j] = mfma(a[i].lo, b[t][j].lo, acc[i][j]);
+                acc[i][j] = mfma(a[i].hi, b[t][j].hi, acc[i][j]);
+            }
     }
 }
 constexpr int kRT = kMlpWgRows / 16;   // row tiles per workgroup
@@ -130,6 +145,10 @@ __device__ __forceinline__ void hidden_forward(const uint16_t* A, const uint16_t
                                                const float* __restrict__ bias, float* z, uint16_t* out, int b0,
                                                int rows, int w, int lane)
 {
+    // the epilogue's global operands are requested before the products
+    float bv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bv[j] = bias[w * 64 + 16 * j + (lane & 15)];
     v4f acc[kRT][4];
     tile_mm<K, 4>(A, W, w * 64, acc, lane);
 #pragma unroll
@@ -139,18 +158,31 @@ __device__ __forceinline__ void hidden_forward(const uint16_t* A, const uint16_t
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = 16 * i + 4 * (lane >> 4) + e, col = w * 64 + 16 * j + (lane & 15);
-                const float zz = acc[i][j][e] + bias[col];
+                const float zz = acc[i][j][e] + bv[j];
                 if (z) z[(size_t)(b0 + row) * kMlpHid + col] = zz;
-                out[row * kLda + col] = row < rows ? to_bf16(gelu_f(zz)) : (uint16_t)0;
+                // 16 i + e is the wave's smallest row of this element: past
+                // `rows` no lane evaluates GELU (a uniform branch)
+                uint16_t o = 0;
+                if (16 * i + e < rows) o = row < rows ? to_bf16(gelu_f(zz)) : (uint16_t)0;
+                out[row * kLda + col] = o;
             }
 }
 
 // hidden layer backward: out = bf16((E Wt^T) * gelu'(z)); each thread reads
-// back only the z values it stored in the forward pass (same fragment map)
+// back only the z values it stored in the forward pass (same fragment map),
+// requested before the products
 template <int K>
 __device__ __forceinline__ void hidden_backward(const uint16_t* E, const uint16_t* __restrict__ Wt, const float* z,
                                                 uint16_t* out, int b0, int w, int lane)
 {
+    float zv[kRT][4][4];
+#pragma unroll
+    for (int i = 0; i < kRT; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                zv[i][j][e] = z[(size_t)(b0 + 16 * i + 4 * (lane >> 4) + e) * kMlpHid + w * 64 + 16 * j + (lane & 15)];
     v4f acc[kRT][4];
     tile_mm<K, 4>(E, Wt, w * 64, acc, lane);
 #pragma unroll
@@ -160,14 +192,32 @@ __device__ __forceinline__ void hidden_backward(const uint16_t* E, const uint16_
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = 16 * i + 4 * (lane >> 4) + e, col = w * 64 + 16 * j + (lane & 15);
-                out[row * kLda + col] = to_bf16(acc[i][j][e] * gelu_d(z[(size_t)(b0 + row) * kMlpHid + col]));
+                out[row * kLda + col] = to_bf16(acc[i][j][e] * gelu_d(zv[i][j][e]));
             }
+}
+
+// Feature c (0..20) of state p: q / q_max, qd / qd_max, p_des, then the
+// unit target quaternion with w >= 0 (the proposal's input encoding).
+__device__ __forceinline__ float state_feature(const MlpDev& d, const double* __restrict__ q,
+                                               const double* __restrict__ qd, const double* __restrict__ target,
+                                               int p, int c)
+{
+    if (c < 7) return (float)(q[p * 7 + c] / d.scale[c]);
+    if (c < 14) return (float)(qd[p * 7 + c - 7] / d.scale[c]);
+    const double* tg = target + (size_t)p * 13;
+    if (c < 17) return (float)tg[c - 14];
+    const double nrm = sqrt(tg[3] * tg[3] + tg[4] * tg[4] + tg[5] * tg[5] + tg[6] * tg[6]);
+    const double sg = (tg[3] < 0.0 ? -1.0 : 1.0) / nrm;
+    return (float)(tg[c - 14] * sg);
 }
 
 template <bool TRAIN>
 __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const float* __restrict__ X, int B,
                                                                const float* __restrict__ Ytgt, float* __restrict__ Y,
-                                                               double* __restrict__ U, int u_stride, float gscale)
+                                                               double* __restrict__ U, int u_stride, float gscale,
+                                                               const double* __restrict__ sq,
+                                                               const double* __restrict__ sqd,
+                                                               const double* __restrict__ stg)
 {
     __shared__ __align__(16) uint16_t buf[2][kMlpWgRows * kLda];
     __shared__ float red[kThreads / 64];
@@ -175,10 +225,13 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
     const int b0 = blockIdx.x * kMlpWgRows;
     const float* th = d.theta;
 
-    // a_0 = bf16(x); feature columns 21..31 and rows past B are zero
+    // a_0 = bf16(x), x from X or (X null) encoded here from the states;
+    // feature columns 21..31 and rows past B are zero
     for (int i = tid; i < kMlpWgRows * kMlpInPad; i += kThreads) {
         const int r = i / kMlpInPad, c = i % kMlpInPad;
-        const float x = (c < kMlpIn && b0 + r < B) ? X[(size_t)(b0 + r) * kMlpIn + c] : 0.0f;
+        float x = 0.0f;
+        if (c < kMlpIn && b0 + r < B)
+            x = X ? X[(size_t)(b0 + r) * kMlpIn + c] : state_feature(d, sq, sqd, stg, b0 + r, c);
         buf[0][r * kLda + c] = to_bf16(x);
     }
     __syncthreads();
@@ -198,6 +251,20 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
 
     // output layer; training: e_4 = bf16(2 (y - y*) / (B 126)) into buf[0]
     {
+        float b4[2], yt[kRT][2][4];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = w * 32 + 16 * j + (lane & 15);
+            b4[j] = col < kMlpOut ? th[kOffB4 + col] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < kRT; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = 16 * i + 4 * (lane >> 4) + e;
+                    yt[i][j][e] = (TRAIN && col < kMlpOut && b0 + row < B) ? Ytgt[(size_t)(b0 + row) * kMlpOut + col]
+                                                                          : 0.0f;
+                }
+        }
         v4f acc[kRT][2];
         tile_mm<kMlpHid, 2>(buf[1], d.W4, w * 32, acc, lane);
         float sq = 0.0f;
@@ -209,13 +276,13 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
                 for (int e = 0; e < 4; ++e) {
                     const int row = 16 * i + 4 * (lane >> 4) + e, col = w * 32 + 16 * j + (lane & 15);
                     const bool valid = col < kMlpOut && b0 + row < B;
-                    const float y = acc[i][j][e] + (col < kMlpOut ? th[kOffB4 + col] : 0.0f);
+                    const float y = acc[i][j][e] + b4[j];
                     if (valid) {
                         if (Y) Y[(size_t)(b0 + row) * kMlpOut + col] = y;
                         if (U) U[(size_t)(b0 + row) * u_stride + col] = d.scale[14 + col % 7] * (double)y;
                     }
                     if (TRAIN) {
-                        const float res = valid ? y - Ytgt[(size_t)(b0 + row) * kMlpOut + col] : 0.0f;
+                        const float res = valid ? y - yt[i][j][e] : 0.0f;
                         sq += res * res;
                         buf[0][row * kLda + col] = to_bf16(res * gscale);
                     }
@@ -395,15 +462,7 @@ __global__ void mlp_features_kernel(MlpDev d, int n, const double* __restrict__ 
     if (U && Y)   // normalised training targets y* = U* / tau_max
         for (int c = 0; c < kMlpOut; ++c) Y[(size_t)p * kMlpOut + c] = (float)(U[(size_t)p * u_stride + c] / d.scale[14 + c % 7]);
     float* x = X + (size_t)p * kMlpIn;
-    for (int j = 0; j < 7; ++j) {
-        x[j] = (float)(q[p * 7 + j] / d.scale[j]);
-        x[7 + j] = (float)(qd[p * 7 + j] / d.scale[7 + j]);
-    }
-    const double* tg = target + (size_t)p * 13;
-    for (int c = 0; c < 3; ++c) x[14 + c] = (float)tg[c];
-    const double nrm = sqrt(tg[3] * tg[3] + tg[4] * tg[4] + tg[5] * tg[5] + tg[6] * tg[6]);
-    const double sg = (tg[3] < 0.0 ? -1.0 : 1.0) / nrm;
-    for (int c = 0; c < 4; ++c) x[17 + c] = (float)(tg[3 + c] * sg);
+    for (int c = 0; c < kMlpIn; ++c) x[c] = state_feature(d, q, qd, target, p, c);
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -422,7 +481,6 @@ size_t mlp_scratch_bytes(int Bp)
     b += 3 * align256((size_t)kMlpHid * Bp * 2) + align256((size_t)kMlpOutPad * Bp * 2);  // eT1..eT4
     b += 3 * align256((size_t)Bp * kMlpHid * sizeof(float));                   // z1..z3
     b += align256((size_t)(Bp / kMlpWgRows) * sizeof(float));                  // lossp
-    b += align256((size_t)Bp * kMlpIn * sizeof(float));                        // X
     b += align256(21 * sizeof(double));                                        // scale
     return b;
 }
@@ -455,25 +513,25 @@ void mlp_carve(MlpDev& d, void* base, int Bp)
     d.z2 = (float*)take((size_t)Bp * kMlpHid * 4);
     d.z3 = (float*)take((size_t)Bp * kMlpHid * 4);
     d.lossp = (float*)take((size_t)(Bp / kMlpWgRows) * 4);
-    d.X = (float*)take((size_t)Bp * kMlpIn * 4);
     d.scale = (const double*)take(21 * sizeof(double));
     d.Bp = Bp;
 }
 
 hipError_t launch_mlp_forward(const MlpDev& d, const float* X, int B, const float* Ytgt, float* Y, double* U,
-                              int u_stride, hipStream_t s)
+                              int u_stride, hipStream_t s, const double* q, const double* qd, const double* target)
 {
-    if (B < 1 || B > d.Bp) return hipErrorInvalidValue;
+    if (B < 1 || B > d.Bp || (!X && (Ytgt || !q || !qd || !target))) return hipErrorInvalidValue;
     const float gscale = 2.0f / ((float)B * (float)kMlpOut);
     if (Ytgt) {
         // training covers the batch rounded up to 64 rows (padding rows carry
         // zero inputs and zero signals; the weight gradients split that range)
         const dim3 grid((B + kMlpRows - 1) / kMlpRows * (kMlpRows / kMlpWgRows));
-        hipLaunchKernelGGL(mlp_forward_kernel<true>, grid, dim3(kThreads), 0, s, d, X, B, Ytgt, Y, U, u_stride, gscale);
+        hipLaunchKernelGGL(mlp_forward_kernel<true>, grid, dim3(kThreads), 0, s, d, X, B, Ytgt, Y, U, u_stride, gscale,
+                           q, qd, target);
     } else {
         const dim3 grid((B + kMlpWgRows - 1) / kMlpWgRows);
         hipLaunchKernelGGL(mlp_forward_kernel<false>, grid, dim3(kThreads), 0, s, d, X, B, Ytgt, Y, U, u_stride,
-                           gscale);
+                           gscale, q, qd, target);
     }
     return hipGetLastError();
 }

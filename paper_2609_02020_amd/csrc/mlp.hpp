@@ -59,7 +59,6 @@ struct MlpDev {
     float* z2;
     float* z3;
     float* lossp;     // [Bp / 16] per-workgroup sums of squared residuals
-    float* X;         // [Bp][21] feature scratch of the proposal path
     const double* scale;   // [21]: q_max[7], qd_max[7], then 7 torque limits
     int Bp;
 };
@@ -69,13 +68,16 @@ size_t mlp_scratch_bytes(int Bp);
 // Lays the buffers out in one allocation of mlp_scratch_bytes(Bp) bytes.
 void mlp_carve(MlpDev& d, void* base, int Bp);
 
-// Forward for B rows (B <= d.Bp).  Inference: Ytgt == nullptr; writes Y
-// [B][126] and/or U [B][u_stride] = tau_max * y (either may be null).
-// Training: Ytgt [B][126] given; also stores the activations, the
+// Forward for B rows (B <= d.Bp) of the features X [B][21], or (X null,
+// inference only) of the features of the states q [B][7], qd [B][7],
+// target [B][13], encoded in the same launch.  Inference: Ytgt == nullptr;
+// writes Y [B][126] and/or U [B][u_stride] = tau_max * y (either may be
+// null).  Training: Ytgt [B][126] given; also stores the activations, the
 // pre-activations and the backward signals of the MSE loss, and the
 // per-workgroup loss sums.
 hipError_t launch_mlp_forward(const MlpDev& d, const float* X, int B, const float* Ytgt, float* Y, double* U,
-                              int u_stride, hipStream_t s);
+                              int u_stride, hipStream_t s, const double* q = nullptr, const double* qd = nullptr,
+                              const double* target = nullptr);
 // Weight and bias gradients from the stored signals (after a training
 // forward of the same B), and the loss into *loss (may be null).
 hipError_t launch_mlp_wgrad(const MlpDev& d, int B, float* loss, hipStream_t s);

@@ -160,11 +160,11 @@ int mppi_mlp_propose_async(mppi_mlp_t m, int n, const double* q, const double* q
                            double* U, int u_stride, void* stream)
 {
     if (!m || !q || !qd || !target || !U || n < 1 || n > m->max_batch || u_stride < kMlpOut) return MPPI_EINVAL;
-    const hipStream_t s = (hipStream_t)stream;
-    if (launch_mlp_features(m->d, n, q, qd, target, m->d.X, nullptr, 0, nullptr, s) != hipSuccess ||
-        launch_mlp_forward(m->d, m->d.X, n, nullptr, nullptr, U, u_stride, s) != hipSuccess)
-        return MPPI_EDEVICE;
-    return MPPI_OK;
+    // one launch: the features are encoded in the forward kernel's input load
+    return launch_mlp_forward(m->d, nullptr, n, nullptr, nullptr, U, u_stride, (hipStream_t)stream, q, qd, target) ==
+                   hipSuccess
+               ? MPPI_OK
+               : MPPI_EDEVICE;
 }
 
 int mppi_mlp_encode_async(mppi_mlp_t m, int n, const double* q, const double* qd, const double* target,

@@ -180,6 +180,34 @@ def test_propose_matches_oracle(workloads):
     net.close()
 
 
+@pytest.mark.parametrize("n", [1, 16, 17, 64])
+def test_propose_equals_forward_of_encoded_rows(workloads, n):
+    """The proposal (features encoded inside its one forward launch) and the
+    two-step path (encode the rows, forward them, scale by tau_max) give the
+    same torques bit for bit, over whole and ragged workgroups of 16 rows."""
+    torch, dev = torch_dev()
+    cases = workloads["wall_k4096"][:4]
+    rb = cases[0]["robot"]
+    net = B.Mlp(rb, 64)
+    net.set_params(f32(inputs.draw_mlp_params(9)))
+    rng = np.random.default_rng(20 + n)
+    q = to_dev(torch, dev, rng.uniform(-2, 2, (n, 7)), torch.float64)
+    qd = to_dev(torch, dev, rng.uniform(-2, 2, (n, 7)), torch.float64)
+    tg = np.array([B.target_vector(cases[i % 4]["target"]) for i in range(n)])
+    tg[::3, 3:7] *= -1.5   # unnormalised, w < 0
+    tg = to_dev(torch, dev, tg, torch.float64)
+    U = torch.full((n, 126), float("nan"), dtype=torch.float64, device=dev)
+    net.propose_async(q, qd, tg, U)
+    x = torch.zeros((n, 21), dtype=torch.float32, device=dev)
+    y = torch.zeros((n, 126), dtype=torch.float32, device=dev)
+    net.encode_async(q, qd, tg, x)
+    net.forward_async(x, y)
+    torch.cuda.synchronize()
+    expect = y.cpu().numpy().astype(np.float64) * np.tile(om.torque_scale(rb), 18)
+    assert np.array_equal(U.cpu().numpy(), expect)
+    net.close()
+
+
 def test_select_nominal_keeps_the_cheaper_sequence(ora, workloads):
     """Noise-free rollout costs of the warm start and of a candidate against
     the oracle's rollout with sigma = 0; the candidate replaces the nominal
