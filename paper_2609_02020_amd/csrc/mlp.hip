@@ -1,5 +1,5 @@
 // mlp.hip -- the proposal network on gfx950: BF16 matrix-core products
-// (v_mfma_f32_16x16x16_bf16) with FP32 accumulation.
+// (v_mfma_f32_16x16x32_bf16 and 16x16x16) with FP32 accumulation.
 //
 //   mlp_forward_kernel<TRAIN>  one workgroup (4 waves) per 16 states (one
 //                   matrix-core row tile, so a 512-row batch spreads over 32
@@ -19,16 +19,15 @@
 //                   of recorded states for training rows, and optionally
 //                   the normalised targets U* / tau_max.
 //
-// Matrix-core fragments (16 x 16 x 16): lane l holds row (l mod 16) of A and
-// column (l mod 16) of B, each with four of the step's 16 k values, the same
-// four for both operands (slots 4 (l div 16) + 0..3); the FP32 result holds
-// column (l mod 16), rows 4 (l div 16) + 0..3.  Every operand is read with
-// k contiguous: in the layer products a lane's k values of two consecutive
-// steps are 8 contiguous k, one 16-byte read per operand, A from the LDS
-// tile [row][k] (row stride 264 BF16: the 16 rows of a lane group start on
-// distinct banks), B^T from the row-major weights [n][k] (forward) or from
-// their stored transposes (backward); both operands of the weight gradient
-// come from the transposed [feature][batch] buffers, four k per step.
+// Matrix-core fragments: lane l holds row (l mod 16) of A and column
+// (l mod 16) of B with the k values 8 (l div 16) + 0..7 of a 32-step (16 x 16
+// x 32, the layer products) or 4 (l div 16) + 0..3 of a 16-step (16 x 16 x
+// 16, the weight gradients); the FP32 result holds column (l mod 16), rows
+// 4 (l div 16) + 0..3.  Every operand is read with k contiguous: A from
+// the LDS tile [row][k] (row stride 264 BF16: the 16 rows of a lane group
+// start on distinct banks), B^T from the row-major weights [n][k] (forward)
+// or from their stored transposes (backward), both operands of the weight
+// gradient from the transposed [feature][batch] buffers.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -41,6 +40,7 @@ namespace {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
@@ -81,15 +81,18 @@ __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
+// 16 x 16 x 32: lane l holds row (l mod 16) of A and column (l mod 16) of
+// B, each with the eight k values 8 (l div 16) + 0..7
+__device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0,
+                                                   0, 0);
+}
 
 // acc[i][j] = sum_k A[16 i + r][k] Bt[nb + 16 j + c][k] over the RT row
 // tiles of the LDS tile A and CT column tiles of the global k-contiguous
-// Bt [N][K].  The contraction runs over k in chunks of 32 as two
-// matrix-core steps whose k sets are interleaved by lane group: lanes
-// 16 g .. 16 g + 15 supply k = 32 t + 8 g + 0..3 to the first step and
-// 32 t + 8 g + 4..7 to the second, the same k for both operands, so every
-// lane reads 16 contiguous bytes of each operand per chunk (half the load
-// instructions of one 8-byte read per step).  Every B fragment of the
+// Bt [N][K], in k-steps of 32 (16 x 16 x 32 products): every lane reads 16
+// contiguous bytes of each operand per step.  Every B fragment of the
 // layer is requested before the first product, so the wave waits for one
 // memory latency per layer instead of one per k-step.
 template <int K, int CT, int RT = kMlpWgRows / 16>
@@ -119,10 +122,7 @@ __device__ __forceinline__ void tile_mm(const uint16_t* A, const uint16_t* __res
 #pragma unroll
         for (int i = 0; i < RT; ++i)
 #pragma unroll
-            for (int j = 0; j < CT; ++j) {
-                acc[i][j] = mfma(a[i].lo, b[t][j].lo, acc[i][j]);
-                acc[i][j] = mfma(a[i].hi, b[t][j].hi, acc[i][j]);
-            }
+            for (int j = 0; j < CT; ++j) acc[i][j] = mfma32(a[i], b[t][j], acc[i][j]);
     }
 }
 constexpr int kRT = kMlpWgRows / 16;   // row tiles per workgroup
