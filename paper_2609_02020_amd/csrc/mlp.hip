@@ -1,5 +1,5 @@
 // mlp.hip -- the proposal network on gfx950: BF16 matrix-core products
-// (v_mfma_f32_16x16x32_bf16 and 16x16x16) with FP32 accumulation.
+// (v_mfma_f32_16x16x32_bf16) with FP32 accumulation.
 //
 //   mlp_forward_kernel<TRAIN>  one workgroup (4 waves) per 16 states (one
 //                   matrix-core row tile, so a 512-row batch spreads over 32
@@ -19,15 +19,15 @@
 //                   of recorded states for training rows, and optionally
 //                   the normalised targets U* / tau_max.
 //
-// Matrix-core fragments: lane l holds row (l mod 16) of A and column
-// (l mod 16) of B with the k values 8 (l div 16) + 0..7 of a 32-step (16 x 16
-// x 32, the layer products) or 4 (l div 16) + 0..3 of a 16-step (16 x 16 x
-// 16, the weight gradients); the FP32 result holds column (l mod 16), rows
-// 4 (l div 16) + 0..3.  Every operand is read with k contiguous: A from
-// the LDS tile [row][k] (row stride 264 BF16: the 16 rows of a lane group
-// start on distinct banks), B^T from the row-major weights [n][k] (forward)
-// or from their stored transposes (backward), both operands of the weight
-// gradient from the transposed [feature][batch] buffers.
+// Matrix-core fragments (16 x 16 x 32): lane l holds row (l mod 16) of A
+// and column (l mod 16) of B with the k values 8 (l div 16) + 0..7 of the
+// step, one 16-byte read per operand; the FP32 result holds column
+// (l mod 16), rows 4 (l div 16) + 0..3.  Every operand is read with k
+// contiguous: A from the LDS tile [row][k] (row stride 264 BF16: the 16
+// rows of a lane group start on distinct banks), B^T from the row-major
+// weights [n][k] (forward) or from their stored transposes (backward),
+// both operands of the weight gradient from the transposed
+// [feature][batch] buffers.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -38,7 +38,6 @@
 namespace mppi {
 namespace {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
 typedef short v8s __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -77,10 +76,6 @@ __device__ __forceinline__ float gelu_d(float z)
     return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * c * (1.0f + 3.0f * a * z * z);
 }
 
-__device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
 // 16 x 16 x 32: lane l holds row (l mod 16) of A and column (l mod 16) of
 // B, each with the eight k values 8 (l div 16) + 0..7
 __device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c)
@@ -309,10 +304,11 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
 
 // Tiles of 32 x 32: layer 1 8 (256 x 32 padded), layers 2, 3 64 each,
 // layer 4 32 (128 padded x 256).  Each workgroup's 4 waves split the batch
-// (the contraction index) in quarters and add their partial tiles in LDS.
+// (the contraction index, in k-steps of 32 rows) and add their partial
+// tiles in LDS.
 constexpr int kWgradTiles = 8 + 64 + 64 + 32;
 constexpr int kWgradWaves = 4;
-constexpr int kWgradChunk = 8;    // k-steps of 16 rows requested together
+constexpr int kWgradChunk = 4;    // k-steps of 32 rows requested together
 
 __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, int B, float* loss)
 {
@@ -338,25 +334,28 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
     // (rows past B carry e = 0); later rows of the buffers are stale
     const int m0 = tm * 32, n0 = tn * 32, Bp = d.Bp;
     const int nb = (B + kMlpRows - 1) / kMlpRows, Bb = nb * kMlpRows;
-    const int quarter = Bb / kWgradWaves, kb = w * quarter;   // a multiple of 16
-    const int r = lane & 15, kq = (lane >> 4) * 4;
-    const uint16_t* ea[2] = {E + (size_t)(m0 + r) * Bp + kq, E + (size_t)(m0 + 16 + r) * Bp + kq};
-    const uint16_t* ab[2] = {Act + (size_t)(n0 + r) * Bp + kq, Act + (size_t)(n0 + 16 + r) * Bp + kq};
+    const int quarter = Bb / kWgradWaves, kb = w * quarter;   // the bias sums' split, a multiple of 16
+    // this wave's k-steps of 32 rows: [s0, s1) of Bb / 32
+    const int P = Bb / 32, per = (P + kWgradWaves - 1) / kWgradWaves;
+    const int s0 = min(P, w * per), s1 = min(P, s0 + per);
+    const int r = lane & 15, kg = (lane >> 4) * 8;
+    const uint16_t* ea[2] = {E + (size_t)(m0 + r) * Bp + kg, E + (size_t)(m0 + 16 + r) * Bp + kg};
+    const uint16_t* ab[2] = {Act + (size_t)(n0 + r) * Bp + kg, Act + (size_t)(n0 + 16 + r) * Bp + kg};
     v4f acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = kb; k0 < kb + quarter; k0 += 16 * kWgradChunk) {
-        const int ns = min(kWgradChunk, (kb + quarter - k0) / 16);
-        v4s a[kWgradChunk][2], b[kWgradChunk][2];
+    for (int st = s0; st < s1; st += kWgradChunk) {
+        const int ns = min(kWgradChunk, s1 - st);
+        v8s a[kWgradChunk][2], b[kWgradChunk][2];
 #pragma unroll
         for (int s = 0; s < kWgradChunk; ++s)
             if (s < ns)
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                    a[s][i] = *reinterpret_cast<const v4s*>(ea[i] + k0 + 16 * s);
-                    b[s][i] = *reinterpret_cast<const v4s*>(ab[i] + k0 + 16 * s);
+                    a[s][i] = *reinterpret_cast<const v8s*>(ea[i] + 32 * (st + s));
+                    b[s][i] = *reinterpret_cast<const v8s*>(ab[i] + 32 * (st + s));
                 }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -365,7 +364,7 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) acc[i][j] = mfma(a[s][i], b[s][j], acc[i][j]);
+                    for (int j = 0; j < 2; ++j) acc[i][j] = mfma32(a[s][i], b[s][j], acc[i][j]);
     }
     // db: lanes 0-31 and 32-63 sum the two halves of this wave's quarter
     const bool bias = tn == 0;
