@@ -45,13 +45,14 @@ FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (AMD published)
 # known size (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 on gfx950), taken on the
 # kernel sources whose digest is recorded here; reported as null once the
 # sources differ.
-PROFILED_DIGEST = "c0a1018db6a22640"
-PROFILED_TRAFFIC = {"update_group_kernel": 540798 + 582775,    # K=4096, T=18 contact workload: the
+PROFILED_DIGEST = "2170d10a60a62b66"
+PROFILED_TRAFFIC = {"update_group_kernel": 540778 + 582800,    # K=4096, T=18 contact workload: the
                                                             # group kernel and its merge launch
-                    "batch_kernel": 39430837 + 352391525,   # 64-problem batch (W=2 x 1024); mostly
-                                                            # register-spill stores of the
-                                                            # two-waves-per-SIMD build
-                    "mlp_train": 14585019 + 3989024}        # forward/backward + weight gradients, 512 rows
+                    # 64-problem batch, per launch shape the autotuner may pick (waves per
+                    # group x groups); mostly register-spill stores of the resident waves
+                    "batch_kernel_w2x1024": 39398432 + 353274605,
+                    "batch_kernel_w1x2048": 36178016 + 310906192,
+                    "mlp_train": 14507136 + 3989024}        # forward/backward + weight gradients, 512 rows
 
 
 def kernel_source_digest():
@@ -369,7 +370,7 @@ def batch_bench(B, cases, torch, dev, ticks):
             "roofline": {"bound": "alu", "achieved": flops / (tick_ms * 1e-3) / 1e12,
                          "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": flops / (tick_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
-                         "traffic": profiled_traffic("batch_kernel"),
+                         "traffic": profiled_traffic("batch_kernel_w%dx%d" % (wpg, groups)),
                          "kernel": "batch_kernel", "flops_per_launch": flops}}
 
 
