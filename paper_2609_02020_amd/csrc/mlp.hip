@@ -1,7 +1,8 @@
 // mlp.hip -- the proposal network on gfx950: BF16 matrix-core products
 // (v_mfma_f32_16x16x32_bf16) with FP32 accumulation.
 //
-//   mlp_forward_kernel<TRAIN>  one workgroup (4 waves) per 16 states (one
+//   mlp_forward_kernel<TRAIN>  one workgroup (16 waves, each holding 16 of a
+//                   layer's output columns) per 16 states (one
 //                   matrix-core row tile, so a 512-row batch spreads over 32
 //                   workgroups); the layers run back to back with the
 //                   activation tile in LDS.  A proposal encodes the input
@@ -42,7 +43,12 @@ typedef short v8s __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;
+constexpr int kFwdWaves = 16;                         // waves of a forward workgroup
+constexpr int kThreads = 64 * kFwdWaves;
+constexpr int kHidCT = kMlpHid / 16 / kFwdWaves;      // column tiles per wave: hidden layers
+// the output layer's 8 column tiles go to its first kOutWaves waves
+constexpr int kOutWaves = kMlpOutPad / 16 < kFwdWaves ? kMlpOutPad / 16 : kFwdWaves;
+constexpr int kOutCT = kMlpOutPad / 16 / kOutWaves;
 constexpr int kLda = 264;
 
 // FP32 -> BF16, round to nearest, ties to even (NaN stays NaN)
@@ -141,18 +147,19 @@ __device__ __forceinline__ void hidden_forward(const uint16_t* A, const uint16_t
                                                int rows, int w, int lane)
 {
     // the epilogue's global operands are requested before the products
-    float bv[4];
+    constexpr int NC = 16 * kHidCT;
+    float bv[kHidCT];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bv[j] = bias[w * 64 + 16 * j + (lane & 15)];
-    v4f acc[kRT][4];
-    tile_mm<K, 4>(A, W, w * 64, acc, lane);
+    for (int j = 0; j < kHidCT; ++j) bv[j] = bias[w * NC + 16 * j + (lane & 15)];
+    v4f acc[kRT][kHidCT];
+    tile_mm<K, kHidCT>(A, W, w * NC, acc, lane);
 #pragma unroll
     for (int i = 0; i < kRT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < kHidCT; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = 16 * i + 4 * (lane >> 4) + e, col = w * 64 + 16 * j + (lane & 15);
+                const int row = 16 * i + 4 * (lane >> 4) + e, col = w * NC + 16 * j + (lane & 15);
                 const float zz = acc[i][j][e] + bv[j];
                 if (z) z[(size_t)(b0 + row) * kMlpHid + col] = zz;
                 // 16 i + e is the wave's smallest row of this element: past
@@ -170,23 +177,24 @@ template <int K>
 __device__ __forceinline__ void hidden_backward(const uint16_t* E, const uint16_t* __restrict__ Wt, const float* z,
                                                 uint16_t* out, int b0, int w, int lane)
 {
-    float zv[kRT][4][4];
+    constexpr int NC = 16 * kHidCT;
+    float zv[kRT][kHidCT][4];
 #pragma unroll
     for (int i = 0; i < kRT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < kHidCT; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                zv[i][j][e] = z[(size_t)(b0 + 16 * i + 4 * (lane >> 4) + e) * kMlpHid + w * 64 + 16 * j + (lane & 15)];
-    v4f acc[kRT][4];
-    tile_mm<K, 4>(E, Wt, w * 64, acc, lane);
+                zv[i][j][e] = z[(size_t)(b0 + 16 * i + 4 * (lane >> 4) + e) * kMlpHid + w * NC + 16 * j + (lane & 15)];
+    v4f acc[kRT][kHidCT];
+    tile_mm<K, kHidCT>(E, Wt, w * NC, acc, lane);
 #pragma unroll
     for (int i = 0; i < kRT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < kHidCT; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = 16 * i + 4 * (lane >> 4) + e, col = w * 64 + 16 * j + (lane & 15);
+                const int row = 16 * i + 4 * (lane >> 4) + e, col = w * NC + 16 * j + (lane & 15);
                 out[row * kLda + col] = to_bf16(acc[i][j][e] * gelu_d(zv[i][j][e]));
             }
 }
@@ -246,10 +254,13 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
 
     // output layer; training: e_4 = bf16(2 (y - y*) / (B 126)) into buf[0]
     {
-        float b4[2], yt[kRT][2][4];
+        float sq = 0.0f;
+        if (w < kOutWaves) {
+        constexpr int NC = 16 * kOutCT;
+        float b4[kOutCT], yt[kRT][kOutCT][4];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int col = w * 32 + 16 * j + (lane & 15);
+        for (int j = 0; j < kOutCT; ++j) {
+            const int col = w * NC + 16 * j + (lane & 15);
             b4[j] = col < kMlpOut ? th[kOffB4 + col] : 0.0f;
 #pragma unroll
             for (int i = 0; i < kRT; ++i)
@@ -260,16 +271,15 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
                                                                           : 0.0f;
                 }
         }
-        v4f acc[kRT][2];
-        tile_mm<kMlpHid, 2>(buf[1], d.W4, w * 32, acc, lane);
-        float sq = 0.0f;
+        v4f acc[kRT][kOutCT];
+        tile_mm<kMlpHid, kOutCT>(buf[1], d.W4, w * NC, acc, lane);
 #pragma unroll
         for (int i = 0; i < kRT; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < kOutCT; ++j)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int row = 16 * i + 4 * (lane >> 4) + e, col = w * 32 + 16 * j + (lane & 15);
+                    const int row = 16 * i + 4 * (lane >> 4) + e, col = w * NC + 16 * j + (lane & 15);
                     const bool valid = col < kMlpOut && b0 + row < B;
                     const float y = acc[i][j][e] + b4[j];
                     if (valid) {
@@ -282,13 +292,19 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
                         buf[0][row * kLda + col] = to_bf16(res * gscale);
                     }
                 }
+        }
         if (!TRAIN) return;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
         if (lane == 0) red[w] = sq;
     }
     __syncthreads();
-    if (tid == 0) d.lossp[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (tid == 0) {
+        float sl = 0.0f;
+#pragma unroll
+        for (int q = 0; q < kFwdWaves; ++q) sl += red[q];
+        d.lossp[blockIdx.x] = sl;
+    }
     store_transposed(buf[0], kMlpOutPad, d.eT4, d.Bp, b0, tid);
 
     hidden_backward<kMlpOutPad>(buf[0], d.W4t, d.z3, buf[1], b0, w, lane);
