@@ -197,8 +197,22 @@ def mlp_bench(B, inputs, robot, torch, dev, reps=50, rows=512):
         U = torch.empty((n, 126), dtype=torch.float64, device=dev)
         prop[n] = timed(lambda: net.propose_async(q, q, tg, U, stream=stream))
     net.close()
+    # the same training step on a batch that gives every CU a workgroup
+    big = 4096
+    net = B.Mlp(robot, big)
+    net.set_params(inputs.draw_mlp_params(1).astype(np.float32))
+    Xb, Yb = inputs.draw_mlp_batch(3, big)
+    Xbd = torch.tensor(Xb, dtype=torch.float32, device=dev)
+    Ybd = torch.tensor(Yb, dtype=torch.float32, device=dev)
+    big_grad = timed(lambda: net.grad_async(Xbd, Ybd, loss=loss, stream=stream))
+    big_train = timed(lambda: net.train_step_async(Xbd, Ybd, loss, lr=1e-4, stream=stream))
+    net.close()
+    big_tf = MLP_TRAIN_FLOPS_PER_ROW * big / (big_grad * 1e-3) / 1e12
     tf = MLP_TRAIN_FLOPS_PER_ROW * rows / (grad_ms * 1e-3) / 1e12
     return {"rows": rows, "train_step_ms": train_ms, "train_rows_per_s": rows / (train_ms * 1e-3),
+            "batch_4096": {"grad_ms": big_grad, "train_step_ms": big_train,
+                           "train_rows_per_s": big / (big_train * 1e-3), "grad_tflops": big_tf,
+                           "grad_frac_of_bf16_peak": big_tf / BF16_MFMA_PEAK_TFLOPS},
             "grad_ms": grad_ms, "forward_ms": fwd_ms, "propose_us": {"1": 1e3 * prop[1], "64": 1e3 * prop[64]},
             "flops_per_row": {"forward": MLP_FWD_FLOPS_PER_ROW, "train": MLP_TRAIN_FLOPS_PER_ROW},
             "roofline": {"bound": "mfma", "achieved": tf, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
