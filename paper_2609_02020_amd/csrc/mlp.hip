@@ -321,7 +321,9 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
 // Tiles of 32 x 32: layer 1 8 (256 x 32 padded), layers 2, 3 64 each,
 // layer 4 32 (128 padded x 256).  Each workgroup's 4 waves split the batch
 // (the contraction index, in k-steps of 32 rows) and add their partial
-// tiles in LDS.
+// tiles in LDS.  The tiles of the first column also form the bias
+// gradients db = e 1 on the matrix cores, from the same e fragments times
+// a fragment of ones (every column of that product is db).
 constexpr int kWgradTiles = 8 + 64 + 64 + 32;
 constexpr int kWgradWaves = 4;
 constexpr int kWgradChunk = 4;    // k-steps of 32 rows requested together
@@ -329,7 +331,7 @@ constexpr int kWgradChunk = 4;    // k-steps of 32 rows requested together
 __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, int B, float* loss)
 {
     __shared__ float part[kWgradWaves - 1][32 * 32];
-    __shared__ float bpart[kWgradWaves * 2][32];
+    __shared__ float bpart[kWgradWaves - 1][32];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     int t = blockIdx.x;
     const uint16_t *E, *Act;
@@ -350,18 +352,22 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
     // (rows past B carry e = 0); later rows of the buffers are stale
     const int m0 = tm * 32, n0 = tn * 32, Bp = d.Bp;
     const int nb = (B + kMlpRows - 1) / kMlpRows, Bb = nb * kMlpRows;
-    const int quarter = Bb / kWgradWaves, kb = w * quarter;   // the bias sums' split, a multiple of 16
     // this wave's k-steps of 32 rows: [s0, s1) of Bb / 32
     const int P = Bb / 32, per = (P + kWgradWaves - 1) / kWgradWaves;
     const int s0 = min(P, w * per), s1 = min(P, s0 + per);
     const int r = lane & 15, kg = (lane >> 4) * 8;
     const uint16_t* ea[2] = {E + (size_t)(m0 + r) * Bp + kg, E + (size_t)(m0 + 16 + r) * Bp + kg};
     const uint16_t* ab[2] = {Act + (size_t)(n0 + r) * Bp + kg, Act + (size_t)(n0 + 16 + r) * Bp + kg};
-    v4f acc[2][2];
+    const bool bias = tn == 0;
+    v4f acc[2][2], accb[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
+        accb[i] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    const short one = 0x3f80;   // BF16 1.0
+    const v8s ones = {one, one, one, one, one, one, one, one};
     for (int st = s0; st < s1; st += kWgradChunk) {
         const int ns = min(kWgradChunk, s1 - st);
         v8s a[kWgradChunk][2], b[kWgradChunk][2];
@@ -378,25 +384,11 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
         for (int s = 0; s < kWgradChunk; ++s)
             if (s < ns)
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < 2; ++i) {
 #pragma unroll
                     for (int j = 0; j < 2; ++j) acc[i][j] = mfma32(a[s][i], b[s][j], acc[i][j]);
-    }
-    // db: lanes 0-31 and 32-63 sum the two halves of this wave's quarter
-    const bool bias = tn == 0;
-    if (bias) {
-        const int row = m0 + (lane & 31), h = quarter / 2, k1 = kb + (lane >> 5) * h;
-        float sb = 0.0f;
-        if (row < nreal) {
-            const uint16_t* er = E + (size_t)row * Bp;
-            for (int k = k1; k < k1 + h; k += 8) {
-                const uint4 v = *reinterpret_cast<const uint4*>(er + k);
-                const uint32_t u[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int c = 0; c < 4; ++c) sb += __uint_as_float(u[c] << 16) + __uint_as_float(u[c] & 0xffff0000u);
-            }
-        }
-        bpart[w * 2 + (lane >> 5)][lane & 31] = sb;
+                    if (bias) accb[i] = mfma32(a[s][i], ones, accb[i]);
+                }
     }
     if (w > 0) {
 #pragma unroll
@@ -406,6 +398,12 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
                     part[w - 1][(16 * i + 4 * (lane >> 4) + e) * 32 + 16 * j + r] = acc[i][j][e];
+        // column 0 of the db product: rows 16 i + 4 (lane div 16) + e
+        if (bias && r == 0)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) bpart[w - 1][16 * i + 4 * (lane >> 4) + e] = accb[i][e];
     }
     __syncthreads();
     if (w != 0) return;
@@ -421,12 +419,17 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
                 for (int q = 0; q < kWgradWaves - 1; ++q) v += part[q][rl * 32 + cl];
                 if (m0 + rl < nreal && n0 + cl < kreal) d.grad[woff + (m0 + rl) * kreal + n0 + cl] = v;
             }
-    if (bias && lane < 32 && m0 + lane < nreal) {
-        float sb = 0.0f;
+    if (bias && r == 0)
 #pragma unroll
-        for (int q = 0; q < 2 * kWgradWaves; ++q) sb += bpart[q][lane];
-        d.grad[boff + m0 + lane] = sb;
-    }
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int rl = 16 * i + 4 * (lane >> 4) + e;
+                float sb = accb[i][e];
+#pragma unroll
+                for (int q = 0; q < kWgradWaves - 1; ++q) sb += bpart[q][rl];
+                if (m0 + rl < nreal) d.grad[boff + m0 + rl] = sb;
+            }
     if (blockIdx.x == 0 && lane == 0 && loss) {
         float sl = 0.0f;
         for (int i = 0; i < Bb / kMlpWgRows; ++i) sl += d.lossp[i];
