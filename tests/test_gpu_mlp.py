@@ -59,10 +59,12 @@ def test_forward_matches_oracle(workloads, rows):
     net.close()
 
 
-@pytest.mark.parametrize("rows", [37, 256, 300])
+@pytest.mark.parametrize("rows", [37, 256, 300, 2000])
 def test_gradient_matches_oracle(workloads, rows):
+    """2000 rows: 16 k-steps of 32 rows per weight-gradient wave (four load
+    chunks) for the weight and bias gradients."""
     torch, dev = torch_dev()
-    net, theta = make(workloads, 512, seed=2)
+    net, theta = make(workloads, max(512, rows), seed=2)
     X, Y = inputs.draw_mlp_batch(100 + rows, rows)
     X, Y = f32(X), f32(Y)
     g = torch.full((B.MLP_PARAMS,), float("nan"), device=dev)
