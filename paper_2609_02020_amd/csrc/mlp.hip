@@ -5,11 +5,13 @@
 //                   layer's output columns) per 16 states (one
 //                   matrix-core row tile, so a 512-row batch spreads over 32
 //                   workgroups); the layers run back to back with the
-//                   activation tile in LDS.  A proposal encodes the input
-//                   features from the states in the same launch (one
+//                   activation tile in LDS; each layer's weight fragments
+//                   are requested one layer ahead.  A proposal encodes the
+//                   input features from the states in the same launch (one
 //                   launch per proposal).  Training adds the MSE signal and the backward
 //                   products e_{l-1} = (e_l W_l) * gelu'(z_{l-1}) in the same
-//                   workgroup (the rows are independent), storing every
+//                   workgroup (the rows are independent; the
+//                   pre-activations stay in registers), storing every
 //                   activation and signal transposed for the weight gradients.
 //   mlp_wgrad_kernel   dW_l = e_l^T a_{l-1} (a contraction over the batch),
 //                   one workgroup per 32 x 32 tile of one layer, its 4 waves
@@ -90,43 +92,50 @@ __device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c)
                                                    0, 0);
 }
 
-// acc[i][j] = sum_k A[16 i + r][k] Bt[nb + 16 j + c][k] over the RT row
-// tiles of the LDS tile A and CT column tiles of the global k-contiguous
-// Bt [N][K], in k-steps of 32 (16 x 16 x 32 products): every lane reads 16
-// contiguous bytes of each operand per step.  Every B fragment of the
-// layer is requested before the first product, so the wave waits for one
-// memory latency per layer instead of one per k-step.
-template <int K, int CT, int RT = kMlpWgRows / 16>
-__device__ __forceinline__ void tile_mm(const uint16_t* A, const uint16_t* __restrict__ Bt, int nb,
-                                        v4f (&acc)[RT][CT], int lane)
-{
+constexpr int kRT = kMlpWgRows / 16;   // row tiles per workgroup
+
+// The B fragments of one layer product held by one wave: CT column tiles
+// from output column nb of the global k-contiguous Bt [N][K], in k-steps of
+// 32 (16 x 16 x 32 products); every lane reads 16 contiguous bytes per
+// fragment.  The kernels request a layer's fragments one layer ahead, so
+// their memory latency overlaps the previous layer's products.
+template <int K, int CT> struct BFrag {
     static_assert(K % 32 == 0, "the contraction runs in chunks of 32");
-    constexpr int KC = K / 32;
+    v8s b[K / 32][CT];
+};
+template <int K, int CT>
+__device__ __forceinline__ void load_frag(const uint16_t* __restrict__ Bt, int nb, BFrag<K, CT>& f, int lane)
+{
     const int r = lane & 15, kg = (lane >> 4) * 8;
-    v8s b[KC][CT];
 #pragma unroll
-    for (int t = 0; t < KC; ++t)
+    for (int t = 0; t < K / 32; ++t)
 #pragma unroll
         for (int j = 0; j < CT; ++j)
-            b[t][j] = *reinterpret_cast<const v8s*>(Bt + (size_t)(nb + 16 * j + r) * K + 32 * t + kg);
-    // keep the scheduler from sinking the loads next to their products
+            f.b[t][j] = *reinterpret_cast<const v8s*>(Bt + (size_t)(nb + 16 * j + r) * K + 32 * t + kg);
+    // issue the loads here, not next to their products
     __builtin_amdgcn_sched_barrier(0);
+}
+// acc[i][j] = sum_k A[16 i + r][k] B[16 j + c][k] over the RT row tiles of
+// the LDS tile A and the CT column tiles of f
+template <int K, int CT>
+__device__ __forceinline__ void frag_mm(const uint16_t* A, const BFrag<K, CT>& f, v4f (&acc)[kRT][CT], int lane)
+{
+    const int r = lane & 15, kg = (lane >> 4) * 8;
 #pragma unroll
-    for (int i = 0; i < RT; ++i)
+    for (int i = 0; i < kRT; ++i)
 #pragma unroll
         for (int j = 0; j < CT; ++j) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int t = 0; t < KC; ++t) {
-        v8s a[RT];
+    for (int t = 0; t < K / 32; ++t) {
+        v8s a[kRT];
 #pragma unroll
-        for (int i = 0; i < RT; ++i) a[i] = *reinterpret_cast<const v8s*>(A + (16 * i + r) * kLda + 32 * t + kg);
+        for (int i = 0; i < kRT; ++i) a[i] = *reinterpret_cast<const v8s*>(A + (16 * i + r) * kLda + 32 * t + kg);
 #pragma unroll
-        for (int i = 0; i < RT; ++i)
+        for (int i = 0; i < kRT; ++i)
 #pragma unroll
-            for (int j = 0; j < CT; ++j) acc[i][j] = mfma32(a[i], b[t][j], acc[i][j]);
+            for (int j = 0; j < CT; ++j) acc[i][j] = mfma32(a[i], f.b[t][j], acc[i][j]);
     }
 }
-constexpr int kRT = kMlpWgRows / 16;   // row tiles per workgroup
 
 // LDS tile columns [0, ncols) -> global [c][Bp] at rows b0..b0+15
 __device__ __forceinline__ void store_transposed(const uint16_t* tile, int ncols, uint16_t* dst, int Bp, int b0,
@@ -138,21 +147,27 @@ __device__ __forceinline__ void store_transposed(const uint16_t* tile, int ncols
     }
 }
 
-// hidden layer forward: out = bf16(gelu(A W^T + b)); z stored when given.
-// Rows past `rows` (padding of the last workgroup) are set to zero without
-// evaluating GELU (rows never mix, so they cannot reach a valid output).
-template <int K>
-__device__ __forceinline__ void hidden_forward(const uint16_t* A, const uint16_t* __restrict__ W,
-                                               const float* __restrict__ bias, float* z, uint16_t* out, int b0,
-                                               int rows, int w, int lane)
+// this wave's bias values of a hidden layer (columns nb + 16 j + lane mod 16)
+__device__ __forceinline__ void load_bias(const float* __restrict__ bias, int nb, float (&bv)[kHidCT], int lane)
 {
-    // the epilogue's global operands are requested before the products
-    constexpr int NC = 16 * kHidCT;
-    float bv[kHidCT];
 #pragma unroll
-    for (int j = 0; j < kHidCT; ++j) bv[j] = bias[w * NC + 16 * j + (lane & 15)];
+    for (int j = 0; j < kHidCT; ++j) bv[j] = bias[nb + 16 * j + (lane & 15)];
+}
+
+// hidden layer forward: out = bf16(gelu(A W^T + b)) from the wave's
+// fragments f of W and bias values bv; the pre-activations go to zo (kept
+// in registers for the backward pass, which needs exactly the values each
+// thread computed here).  Rows past `rows` (padding of the last workgroup)
+// are set to zero without evaluating GELU (rows never mix, so they cannot
+// reach a valid output).
+template <int K>
+__device__ __forceinline__ void hidden_forward(const uint16_t* A, const BFrag<K, kHidCT>& f, const float (&bv)[kHidCT],
+                                               float (&zo)[kRT][kHidCT][4], uint16_t* out, int rows, int w,
+                                               int lane)
+{
+    constexpr int NC = 16 * kHidCT;
     v4f acc[kRT][kHidCT];
-    tile_mm<K, kHidCT>(A, W, w * NC, acc, lane);
+    frag_mm(A, f, acc, lane);
 #pragma unroll
     for (int i = 0; i < kRT; ++i)
 #pragma unroll
@@ -161,7 +176,7 @@ __device__ __forceinline__ void hidden_forward(const uint16_t* A, const uint16_t
             for (int e = 0; e < 4; ++e) {
                 const int row = 16 * i + 4 * (lane >> 4) + e, col = w * NC + 16 * j + (lane & 15);
                 const float zz = acc[i][j][e] + bv[j];
-                if (z) z[(size_t)(b0 + row) * kMlpHid + col] = zz;
+                zo[i][j][e] = zz;
                 // 16 i + e is the wave's smallest row of this element: past
                 // `rows` no lane evaluates GELU (a uniform branch)
                 uint16_t o = 0;
@@ -170,24 +185,16 @@ __device__ __forceinline__ void hidden_forward(const uint16_t* A, const uint16_t
             }
 }
 
-// hidden layer backward: out = bf16((E Wt^T) * gelu'(z)); each thread reads
-// back only the z values it stored in the forward pass (same fragment map),
-// requested before the products
+// hidden layer backward: out = bf16((E Wt^T) * gelu'(z)) from the wave's
+// fragments f of Wt and the pre-activations zv this thread computed in the
+// forward pass (same fragment map)
 template <int K>
-__device__ __forceinline__ void hidden_backward(const uint16_t* E, const uint16_t* __restrict__ Wt, const float* z,
-                                                uint16_t* out, int b0, int w, int lane)
+__device__ __forceinline__ void hidden_backward(const uint16_t* E, const BFrag<K, kHidCT>& f,
+                                                const float (&zv)[kRT][kHidCT][4], uint16_t* out, int w, int lane)
 {
     constexpr int NC = 16 * kHidCT;
-    float zv[kRT][kHidCT][4];
-#pragma unroll
-    for (int i = 0; i < kRT; ++i)
-#pragma unroll
-        for (int j = 0; j < kHidCT; ++j)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                zv[i][j][e] = z[(size_t)(b0 + 16 * i + 4 * (lane >> 4) + e) * kMlpHid + w * NC + 16 * j + (lane & 15)];
     v4f acc[kRT][kHidCT];
-    tile_mm<K, kHidCT>(E, Wt, w * NC, acc, lane);
+    frag_mm(E, f, acc, lane);
 #pragma unroll
     for (int i = 0; i < kRT; ++i)
 #pragma unroll
@@ -228,6 +235,16 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
     const int b0 = blockIdx.x * kMlpWgRows;
     const float* th = d.theta;
 
+    const int nh = w * 16 * kHidCT;   // this wave's first column of a hidden layer
+    // the first two layers' operands, requested before the input tile
+    BFrag<kMlpInPad, kHidCT> f1;
+    BFrag<kMlpHid, kHidCT> f2;
+    float bv1[kHidCT], bv2[kHidCT];
+    load_frag(d.W1, nh, f1, lane);
+    load_bias(th + kOffB1, nh, bv1, lane);
+    load_frag(d.W2, nh, f2, lane);
+    load_bias(th + kOffB2, nh, bv2, lane);
+
     // a_0 = bf16(x), x from X or (X null) encoded here from the states;
     // feature columns 21..31 and rows past B are zero
     for (int i = tid; i < kMlpWgRows * kMlpInPad; i += kThreads) {
@@ -242,25 +259,27 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
 
     // training keeps every row (the backward pass reads them all)
     const int rows = TRAIN ? kMlpWgRows : min(kMlpWgRows, B - b0);
-    hidden_forward<kMlpInPad>(buf[0], d.W1, th + kOffB1, TRAIN ? d.z1 : nullptr, buf[1], b0, rows, w, lane);
+    float z1[kRT][kHidCT][4], z2[kRT][kHidCT][4], z3[kRT][kHidCT][4];
+    hidden_forward<kMlpInPad>(buf[0], f1, bv1, z1, buf[1], rows, w, lane);
     __syncthreads();
     if (TRAIN) store_transposed(buf[1], kMlpHid, d.aT1, d.Bp, b0, tid);
-    hidden_forward<kMlpHid>(buf[1], d.W2, th + kOffB2, TRAIN ? d.z2 : nullptr, buf[0], b0, rows, w, lane);
+    BFrag<kMlpHid, kHidCT> f3;
+    float bv3[kHidCT];
+    load_frag(d.W3, nh, f3, lane);
+    load_bias(th + kOffB3, nh, bv3, lane);
+    hidden_forward<kMlpHid>(buf[1], f2, bv2, z2, buf[0], rows, w, lane);
     __syncthreads();
     if (TRAIN) store_transposed(buf[0], kMlpHid, d.aT2, d.Bp, b0, tid);
-    hidden_forward<kMlpHid>(buf[0], d.W3, th + kOffB3, TRAIN ? d.z3 : nullptr, buf[1], b0, rows, w, lane);
-    __syncthreads();
-    if (TRAIN) store_transposed(buf[1], kMlpHid, d.aT3, d.Bp, b0, tid);
 
-    // output layer; training: e_4 = bf16(2 (y - y*) / (B 126)) into buf[0]
-    {
-        float sq = 0.0f;
-        if (w < kOutWaves) {
-        constexpr int NC = 16 * kOutCT;
-        float b4[kOutCT], yt[kRT][kOutCT][4];
+    // the output layer's operands (its 8 column tiles on the first waves)
+    constexpr int NO = 16 * kOutCT;
+    BFrag<kMlpHid, kOutCT> f4;
+    float b4[kOutCT], yt[kRT][kOutCT][4];
+    if (w < kOutWaves) {
+        load_frag(d.W4, w * NO, f4, lane);
 #pragma unroll
         for (int j = 0; j < kOutCT; ++j) {
-            const int col = w * NC + 16 * j + (lane & 15);
+            const int col = w * NO + 16 * j + (lane & 15);
             b4[j] = col < kMlpOut ? th[kOffB4 + col] : 0.0f;
 #pragma unroll
             for (int i = 0; i < kRT; ++i)
@@ -271,29 +290,40 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
                                                                           : 0.0f;
                 }
         }
-        v4f acc[kRT][kOutCT];
-        tile_mm<kMlpHid, kOutCT>(buf[1], d.W4, w * NC, acc, lane);
+    }
+    hidden_forward<kMlpHid>(buf[0], f3, bv3, z3, buf[1], rows, w, lane);
+    __syncthreads();
+    if (TRAIN) store_transposed(buf[1], kMlpHid, d.aT3, d.Bp, b0, tid);
+
+    // output layer; training: e_4 = bf16(2 (y - y*) / (B 126)) into buf[0]
+    BFrag<kMlpOutPad, kHidCT> g4;
+    {
+        float sq = 0.0f;
+        if (w < kOutWaves) {
+            v4f acc[kRT][kOutCT];
+            frag_mm(buf[1], f4, acc, lane);
 #pragma unroll
-        for (int i = 0; i < kRT; ++i)
+            for (int i = 0; i < kRT; ++i)
 #pragma unroll
-            for (int j = 0; j < kOutCT; ++j)
+                for (int j = 0; j < kOutCT; ++j)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = 16 * i + 4 * (lane >> 4) + e, col = w * NC + 16 * j + (lane & 15);
-                    const bool valid = col < kMlpOut && b0 + row < B;
-                    const float y = acc[i][j][e] + b4[j];
-                    if (valid) {
-                        if (Y) Y[(size_t)(b0 + row) * kMlpOut + col] = y;
-                        if (U) U[(size_t)(b0 + row) * u_stride + col] = d.scale[14 + col % 7] * (double)y;
+                    for (int e = 0; e < 4; ++e) {
+                        const int row = 16 * i + 4 * (lane >> 4) + e, col = w * NO + 16 * j + (lane & 15);
+                        const bool valid = col < kMlpOut && b0 + row < B;
+                        const float y = acc[i][j][e] + b4[j];
+                        if (valid) {
+                            if (Y) Y[(size_t)(b0 + row) * kMlpOut + col] = y;
+                            if (U) U[(size_t)(b0 + row) * u_stride + col] = d.scale[14 + col % 7] * (double)y;
+                        }
+                        if (TRAIN) {
+                            const float res = valid ? y - yt[i][j][e] : 0.0f;
+                            sq += res * res;
+                            buf[0][row * kLda + col] = to_bf16(res * gscale);
+                        }
                     }
-                    if (TRAIN) {
-                        const float res = valid ? y - yt[i][j][e] : 0.0f;
-                        sq += res * res;
-                        buf[0][row * kLda + col] = to_bf16(res * gscale);
-                    }
-                }
         }
         if (!TRAIN) return;
+        load_frag(d.W4t, nh, g4, lane);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
         if (lane == 0) red[w] = sq;
@@ -307,13 +337,17 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
     }
     store_transposed(buf[0], kMlpOutPad, d.eT4, d.Bp, b0, tid);
 
-    hidden_backward<kMlpOutPad>(buf[0], d.W4t, d.z3, buf[1], b0, w, lane);
+    BFrag<kMlpHid, kHidCT> g3;
+    load_frag(d.W3t, nh, g3, lane);
+    hidden_backward<kMlpOutPad>(buf[0], g4, z3, buf[1], w, lane);
     __syncthreads();
     store_transposed(buf[1], kMlpHid, d.eT3, d.Bp, b0, tid);
-    hidden_backward<kMlpHid>(buf[1], d.W3t, d.z2, buf[0], b0, w, lane);
+    BFrag<kMlpHid, kHidCT> g2;
+    load_frag(d.W2t, nh, g2, lane);
+    hidden_backward<kMlpHid>(buf[1], g3, z2, buf[0], w, lane);
     __syncthreads();
     store_transposed(buf[0], kMlpHid, d.eT2, d.Bp, b0, tid);
-    hidden_backward<kMlpHid>(buf[0], d.W2t, d.z1, buf[1], b0, w, lane);
+    hidden_backward<kMlpHid>(buf[0], g2, z1, buf[1], w, lane);
     __syncthreads();
     store_transposed(buf[1], kMlpHid, d.eT1, d.Bp, b0, tid);
 }
@@ -497,7 +531,6 @@ size_t mlp_scratch_bytes(int Bp)
     b += 2 * align256((size_t)kMlpHid * kMlpHid * 2) + align256((size_t)kMlpHid * kMlpOutPad * 2);   // W2t..W4t
     b += align256((size_t)kMlpInPad * Bp * 2) + 3 * align256((size_t)kMlpHid * Bp * 2);   // aT0..aT3
     b += 3 * align256((size_t)kMlpHid * Bp * 2) + align256((size_t)kMlpOutPad * Bp * 2);  // eT1..eT4
-    b += 3 * align256((size_t)Bp * kMlpHid * sizeof(float));                   // z1..z3
     b += align256((size_t)(Bp / kMlpWgRows) * sizeof(float));                  // lossp
     b += align256(21 * sizeof(double));                                        // scale
     return b;
@@ -527,9 +560,6 @@ void mlp_carve(MlpDev& d, void* base, int Bp)
     d.eT2 = (uint16_t*)take((size_t)kMlpHid * Bp * 2);
     d.eT3 = (uint16_t*)take((size_t)kMlpHid * Bp * 2);
     d.eT4 = (uint16_t*)take((size_t)kMlpOutPad * Bp * 2);
-    d.z1 = (float*)take((size_t)Bp * kMlpHid * 4);
-    d.z2 = (float*)take((size_t)Bp * kMlpHid * 4);
-    d.z3 = (float*)take((size_t)Bp * kMlpHid * 4);
     d.lossp = (float*)take((size_t)(Bp / kMlpWgRows) * 4);
     d.scale = (const double*)take(21 * sizeof(double));
     d.Bp = Bp;

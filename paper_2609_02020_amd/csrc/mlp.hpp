@@ -33,8 +33,9 @@ static_assert(kMlpParams == 169598, "parameter count");
 // [256][128] (columns 126, 127 zero) feed the backward products.
 // Training scratch holds one batch of up to Bp rows (a multiple of 64):
 // activations a_l and backward signals e_l stored transposed ([features][Bp],
-// BF16) for the weight-gradient contraction over the batch, and the FP32
-// pre-activations z_l [Bp][256] for GELU'.
+// BF16) for the weight-gradient contraction over the batch (the
+// pre-activations that GELU' needs stay in the registers of the thread that
+// computed them).
 struct MlpDev {
     float* theta;     // [P] FP32 master parameters
     float* m;         // [P] Adam first moment
@@ -55,9 +56,6 @@ struct MlpDev {
     uint16_t* eT2;
     uint16_t* eT3;
     uint16_t* eT4;    // [128][Bp]
-    float* z1;        // [Bp][256]
-    float* z2;
-    float* z3;
     float* lossp;     // [Bp / 16] per-workgroup sums of squared residuals
     const double* scale;   // [21]: q_max[7], qd_max[7], then 7 torque limits
     int Bp;
