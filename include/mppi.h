@@ -386,7 +386,9 @@ int mppi_mlp_grad_async(mppi_mlp_t m, const float* x, const float* y_target, int
 /* One Adam step with the last gradient (the step count t advances on the
  * host with every call). */
 int mppi_mlp_adam_async(mppi_mlp_t m, const mppi_adam_params* p, void* stream);
-/* mppi_mlp_grad_async (no gradient copy) followed by mppi_mlp_adam_async. */
+/* The same result as mppi_mlp_grad_async (no gradient copy) followed by
+ * mppi_mlp_adam_async, in two kernel launches: the Adam step of each
+ * parameter is applied as its gradient tile completes. */
 int mppi_mlp_train_step_async(mppi_mlp_t m, const float* x, const float* y_target, int B,
                               const mppi_adam_params* p, float* loss, void* stream);
 /* Mean torque sequences of n states (1 <= n <= max_batch): q, qd [n][7],

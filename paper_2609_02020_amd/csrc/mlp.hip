@@ -17,7 +17,8 @@
 //                   one workgroup per 32 x 32 tile of one layer, its 4 waves
 //                   splitting the batch; db_l = sum of e_l.
 //   mlp_adam_kernel    Adam on the FP32 master weights, then the BF16 copies
-//                   (row-major and transposed).
+//                   (row-major and transposed); a training step applies the
+//                   same update in mlp_wgrad_kernel as each tile completes.
 //   mlp_features_kernel  (q/q_max, qd/qd_max, p_des, quat_des with w >= 0)
 //                   of recorded states for training rows, and optionally
 //                   the normalised targets U* / tau_max.
@@ -352,6 +353,38 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
     store_transposed(buf[1], kMlpHid, d.eT1, d.Bp, b0, tid);
 }
 
+// Adam step of parameter i with gradient g (a.update != 0), then its BF16
+// copies: W row-major and, for layers 2-4, the transposes
+__device__ __forceinline__ void adam_param(const MlpDev& d, int i, float g, const MlpAdam& a)
+{
+    float th = d.theta[i];
+    if (a.update) {
+        const float m = a.beta1 * d.m[i] + (1.0f - a.beta1) * g;
+        const float v = a.beta2 * d.v[i] + (1.0f - a.beta2) * g * g;
+        th -= a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
+        d.m[i] = m;
+        d.v[i] = v;
+        d.theta[i] = th;
+    }
+    const uint16_t h = to_bf16(th);
+    if (i < kOffB1) {
+        const int n = i / kMlpIn, k = i % kMlpIn;
+        d.W1[n * kMlpInPad + k] = h;
+    } else if (i >= kOffW2 && i < kOffB2) {
+        const int j = i - kOffW2, n = j / kMlpHid, k = j % kMlpHid;
+        d.W2[n * kMlpHid + k] = h;
+        d.W2t[k * kMlpHid + n] = h;
+    } else if (i >= kOffW3 && i < kOffB3) {
+        const int j = i - kOffW3, n = j / kMlpHid, k = j % kMlpHid;
+        d.W3[n * kMlpHid + k] = h;
+        d.W3t[k * kMlpHid + n] = h;
+    } else if (i >= kOffW4 && i < kOffB4) {
+        const int j = i - kOffW4, n = j / kMlpHid, k = j % kMlpHid;
+        d.W4[n * kMlpHid + k] = h;
+        d.W4t[k * kMlpOutPad + n] = h;
+    }
+}
+
 // Tiles of 32 x 32: layer 1 8 (256 x 32 padded), layers 2, 3 64 each,
 // layer 4 32 (128 padded x 256).  Each workgroup's 4 waves split the batch
 // (the contraction index, in k-steps of 32 rows) and add their partial
@@ -362,10 +395,11 @@ constexpr int kWgradTiles = 8 + 64 + 64 + 32;
 constexpr int kWgradWaves = 4;
 constexpr int kWgradChunk = 4;    // k-steps of 32 rows requested together
 
-__global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, int B, float* loss)
+__global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, int B, float* loss, int fuse,
+                                                                     MlpAdam adam)
 {
-    __shared__ float part[kWgradWaves - 1][32 * 32];
-    __shared__ float bpart[kWgradWaves - 1][32];
+    __shared__ float part[kWgradWaves][32 * 32];
+    __shared__ float bpart[kWgradWaves][32];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     int t = blockIdx.x;
     const uint16_t *E, *Act;
@@ -424,46 +458,44 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
                     if (bias) accb[i] = mfma32(a[s][i], ones, accb[i]);
                 }
     }
-    if (w > 0) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    part[w - 1][(16 * i + 4 * (lane >> 4) + e) * 32 + 16 * j + r] = acc[i][j][e];
-        // column 0 of the db product: rows 16 i + 4 (lane div 16) + e
-        if (bias && r == 0)
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) bpart[w - 1][16 * i + 4 * (lane >> 4) + e] = accb[i][e];
-    }
-    __syncthreads();
-    if (w != 0) return;
+    // every wave's partial tile (and db column) into LDS; then wave w
+    // finishes fragment (w div 2, w mod 2) of the tile: the sum over the
+    // waves in wave order, the gradient and, fused, its Adam step
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int rl = 16 * i + 4 * (lane >> 4) + e, cl = 16 * j + r;
-                float v = acc[i][j][e];
-#pragma unroll
-                for (int q = 0; q < kWgradWaves - 1; ++q) v += part[q][rl * 32 + cl];
-                if (m0 + rl < nreal && n0 + cl < kreal) d.grad[woff + (m0 + rl) * kreal + n0 + cl] = v;
-            }
+            for (int e = 0; e < 4; ++e) part[w][(16 * i + 4 * (lane >> 4) + e) * 32 + 16 * j + r] = acc[i][j][e];
+    // column 0 of the db product: rows 16 i + 4 (lane div 16) + e
     if (bias && r == 0)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int rl = 16 * i + 4 * (lane >> 4) + e;
-                float sb = accb[i][e];
+            for (int e = 0; e < 4; ++e) bpart[w][16 * i + 4 * (lane >> 4) + e] = accb[i][e];
+    __syncthreads();
+    {
+        const int fi = w >> 1, fj = w & 1;
 #pragma unroll
-                for (int q = 0; q < kWgradWaves - 1; ++q) sb += bpart[q][rl];
-                if (m0 + rl < nreal) d.grad[boff + m0 + rl] = sb;
+        for (int e = 0; e < 4; ++e) {
+            const int rl = 16 * fi + 4 * (lane >> 4) + e, cl = 16 * fj + r;
+            float v = part[0][rl * 32 + cl];
+#pragma unroll
+            for (int q = 1; q < kWgradWaves; ++q) v += part[q][rl * 32 + cl];
+            if (m0 + rl < nreal && n0 + cl < kreal) {
+                const int p = woff + (m0 + rl) * kreal + n0 + cl;
+                d.grad[p] = v;
+                if (fuse) adam_param(d, p, v, adam);
             }
+        }
+    }
+    if (bias && w == kWgradWaves - 1 && lane < 32 && m0 + lane < nreal) {
+        float sb = bpart[0][lane];
+#pragma unroll
+        for (int q = 1; q < kWgradWaves; ++q) sb += bpart[q][lane];
+        d.grad[boff + m0 + lane] = sb;
+        if (fuse) adam_param(d, boff + m0 + lane, sb, adam);
+    }
     if (blockIdx.x == 0 && lane == 0 && loss) {
         float sl = 0.0f;
         for (int i = 0; i < Bb / kMlpWgRows; ++i) sl += d.lossp[i];
@@ -471,38 +503,11 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
     }
 }
 
-__global__ void mlp_adam_kernel(MlpDev d, int update, float lr, float beta1, float beta2, float eps, float c1,
-                                float c2)
+__global__ void mlp_adam_kernel(MlpDev d, MlpAdam a)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kMlpParams) return;
-    float th = d.theta[i];
-    if (update) {
-        const float g = d.grad[i];
-        const float m = beta1 * d.m[i] + (1.0f - beta1) * g;
-        const float v = beta2 * d.v[i] + (1.0f - beta2) * g * g;
-        th -= lr * (m * c1) / (sqrtf(v * c2) + eps);
-        d.m[i] = m;
-        d.v[i] = v;
-        d.theta[i] = th;
-    }
-    const uint16_t h = to_bf16(th);
-    if (i < kOffB1) {
-        const int n = i / kMlpIn, k = i % kMlpIn;
-        d.W1[n * kMlpInPad + k] = h;
-    } else if (i >= kOffW2 && i < kOffB2) {
-        const int j = i - kOffW2, n = j / kMlpHid, k = j % kMlpHid;
-        d.W2[n * kMlpHid + k] = h;
-        d.W2t[k * kMlpHid + n] = h;
-    } else if (i >= kOffW3 && i < kOffB3) {
-        const int j = i - kOffW3, n = j / kMlpHid, k = j % kMlpHid;
-        d.W3[n * kMlpHid + k] = h;
-        d.W3t[k * kMlpHid + n] = h;
-    } else if (i >= kOffW4 && i < kOffB4) {
-        const int j = i - kOffW4, n = j / kMlpHid, k = j % kMlpHid;
-        d.W4[n * kMlpHid + k] = h;
-        d.W4t[k * kMlpOutPad + n] = h;
-    }
+    adam_param(d, i, a.update ? d.grad[i] : 0.0f, a);
 }
 
 __global__ void mlp_features_kernel(MlpDev d, int n, const double* __restrict__ q, const double* __restrict__ qd,
@@ -584,18 +589,18 @@ hipError_t launch_mlp_forward(const MlpDev& d, const float* X, int B, const floa
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_wgrad(const MlpDev& d, int B, float* loss, hipStream_t s)
+hipError_t launch_mlp_wgrad(const MlpDev& d, int B, float* loss, hipStream_t s, const MlpAdam* adam)
 {
     if (B < 1 || B > d.Bp) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(mlp_wgrad_kernel, dim3(kWgradTiles), dim3(64 * kWgradWaves), 0, s, d, B, loss);
+    const MlpAdam a = adam ? *adam : MlpAdam{0, 0.f, 0.f, 0.f, 1.f, 1.f, 1.f};
+    hipLaunchKernelGGL(mlp_wgrad_kernel, dim3(kWgradTiles), dim3(64 * kWgradWaves), 0, s, d, B, loss,
+                       adam ? 1 : 0, a);
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_adam(const MlpDev& d, int update, float lr, float beta1, float beta2, float eps, float c1,
-                           float c2, hipStream_t s)
+hipError_t launch_mlp_adam(const MlpDev& d, const MlpAdam& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, d, update, lr, beta1,
-                       beta2, eps, c1, c2);
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, d, a);
     return hipGetLastError();
 }
 

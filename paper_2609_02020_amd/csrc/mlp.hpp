@@ -76,13 +76,19 @@ void mlp_carve(MlpDev& d, void* base, int Bp);
 hipError_t launch_mlp_forward(const MlpDev& d, const float* X, int B, const float* Ytgt, float* Y, double* U,
                               int u_stride, hipStream_t s, const double* q = nullptr, const double* qd = nullptr,
                               const double* target = nullptr);
+// One Adam step (update != 0) with c1 = 1 / (1 - beta1^t), c2 = 1 / (1 -
+// beta2^t); update == 0 only rewrites the BF16 weight copies.
+struct MlpAdam {
+    int update;
+    float lr, beta1, beta2, eps, c1, c2;
+};
 // Weight and bias gradients from the stored signals (after a training
-// forward of the same B), and the loss into *loss (may be null).
-hipError_t launch_mlp_wgrad(const MlpDev& d, int B, float* loss, hipStream_t s);
-// One Adam step on d.grad (update != 0), then the BF16 weight copies.
-// c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t).
-hipError_t launch_mlp_adam(const MlpDev& d, int update, float lr, float beta1, float beta2, float eps, float c1,
-                           float c2, hipStream_t s);
+// forward of the same B) into d.grad, and the loss into *loss (may be
+// null); with adam (may be null) also the Adam step of every parameter and
+// its BF16 copies, as each gradient tile completes.
+hipError_t launch_mlp_wgrad(const MlpDev& d, int B, float* loss, hipStream_t s, const MlpAdam* adam = nullptr);
+// Adam on d.grad (a.update != 0), then the BF16 weight copies.
+hipError_t launch_mlp_adam(const MlpDev& d, const MlpAdam& a, hipStream_t s);
 // Features of n states into X [n][21]; with U and Y also the normalised
 // targets Y [n][126] = U [n][u_stride] / tau_max.
 hipError_t launch_mlp_features(const MlpDev& d, int n, const double* q, const double* qd, const double* target,

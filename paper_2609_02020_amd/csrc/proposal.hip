@@ -21,7 +21,8 @@ struct mppi_mlp {
 
 namespace {
 
-int adam_enqueue(mppi_mlp* m, const mppi_adam_params* p, hipStream_t s)
+// the Adam arguments of the next step (step count m->step + 1)
+int adam_args(const mppi_mlp* m, const mppi_adam_params* p, MlpAdam& a)
 {
     if (!p || !(p->lr > 0) || !(p->beta1 >= 0 && p->beta1 < 1) || !(p->beta2 >= 0 && p->beta2 < 1) ||
         !(p->eps > 0))
@@ -29,10 +30,17 @@ int adam_enqueue(mppi_mlp* m, const mppi_adam_params* p, hipStream_t s)
     const long long t = m->step + 1;
     const double c1 = 1.0 / (1.0 - std::pow(p->beta1, (double)t));
     const double c2 = 1.0 / (1.0 - std::pow(p->beta2, (double)t));
-    if (launch_mlp_adam(m->d, 1, (float)p->lr, (float)p->beta1, (float)p->beta2, (float)p->eps, (float)c1,
-                        (float)c2, s) != hipSuccess)
-        return MPPI_EDEVICE;
-    m->step = t;
+    a = MlpAdam{1, (float)p->lr, (float)p->beta1, (float)p->beta2, (float)p->eps, (float)c1, (float)c2};
+    return MPPI_OK;
+}
+
+int adam_enqueue(mppi_mlp* m, const mppi_adam_params* p, hipStream_t s)
+{
+    MlpAdam a;
+    const int st = adam_args(m, p, a);
+    if (st) return st;
+    if (launch_mlp_adam(m->d, a, s) != hipSuccess) return MPPI_EDEVICE;
+    m->step += 1;
     return MPPI_OK;
 }
 
@@ -105,7 +113,7 @@ int mppi_mlp_set_params(mppi_mlp_t m, const float* params, size_t n)
     const size_t b = n * sizeof(float);
     if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(m->d.theta, params, b, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(m->d.m, 0, b) != hipSuccess || hipMemset(m->d.v, 0, b) != hipSuccess ||
-        launch_mlp_adam(m->d, 0, 0.f, 0.f, 0.f, 1.f, 1.f, 1.f, nullptr) != hipSuccess ||
+        launch_mlp_adam(m->d, MlpAdam{0, 0.f, 0.f, 0.f, 1.f, 1.f, 1.f}, nullptr) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess)
         return MPPI_EDEVICE;
     m->step = 0;
@@ -151,9 +159,18 @@ int mppi_mlp_train_step_async(mppi_mlp_t m, const float* x, const float* y_targe
                               const mppi_adam_params* p, float* loss, void* stream)
 {
     if (!m || !p) return MPPI_EINVAL;
+    if (!x || !y_target || B < 1 || B > m->max_batch) return MPPI_EINVAL;
+    MlpAdam a;
+    const int st = adam_args(m, p, a);
+    if (st) return st;
+    // two launches: the forward/backward pass, then the weight gradients
+    // with the Adam step applied as each gradient tile completes
     const hipStream_t s = (hipStream_t)stream;
-    int st = grad_enqueue(m, x, y_target, B, loss, s);
-    return st ? st : adam_enqueue(m, p, s);
+    if (launch_mlp_forward(m->d, x, B, y_target, nullptr, nullptr, 0, s) != hipSuccess ||
+        launch_mlp_wgrad(m->d, B, loss, s, &a) != hipSuccess)
+        return MPPI_EDEVICE;
+    m->step += 1;
+    return MPPI_OK;
 }
 
 int mppi_mlp_propose_async(mppi_mlp_t m, int n, const double* q, const double* qd, const double* target,

@@ -117,6 +117,37 @@ def test_adam_steps_match_oracle(workloads):
     net.close()
 
 
+@pytest.mark.parametrize("rows", [128, 2000])
+def test_train_step_equals_grad_then_adam(workloads, rows):
+    """The one-call training step (Adam applied inside the weight-gradient
+    launch as each tile completes) leaves the same master weights, BF16
+    copies, loss and step count as separate gradient and Adam calls: bit
+    for bit over three steps, and the next forward agrees bit for bit."""
+    torch, dev = torch_dev()
+    a, _ = make(workloads, rows, seed=8)
+    b, _ = make(workloads, rows, seed=8)
+    la = torch.zeros(1, device=dev)
+    lb = torch.zeros(1, device=dev)
+    for t in range(3):
+        X, Y = inputs.draw_mlp_batch(60 + t, rows)
+        Xd, Yd = to_dev(torch, dev, f32(X)), to_dev(torch, dev, f32(Y))
+        a.train_step_async(Xd, Yd, la, lr=2e-3)
+        b.grad_async(Xd, Yd, loss=lb)
+        b.adam_async(lr=2e-3)
+        torch.cuda.synchronize()
+        assert la.item() == lb.item(), t
+        assert np.array_equal(a.get_params(), b.get_params()), t
+    X, _ = inputs.draw_mlp_batch(70, rows)
+    ya = torch.zeros((rows, 126), device=dev)
+    yb = torch.zeros((rows, 126), device=dev)
+    a.forward_async(to_dev(torch, dev, f32(X)), ya)
+    b.forward_async(to_dev(torch, dev, f32(X)), yb)
+    torch.cuda.synchronize()
+    assert torch.equal(ya, yb)
+    a.close()
+    b.close()
+
+
 def test_training_reduces_loss_and_keeps_weight_copies_consistent(workloads):
     """300 Adam steps on a smooth synthetic regression; afterwards the GPU
     forward and gradient (which read the BF16 copies and their transposes
