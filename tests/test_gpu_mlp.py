@@ -148,6 +148,46 @@ def test_train_step_equals_grad_then_adam(workloads, rows):
     b.close()
 
 
+def test_network_entry_points_reject_bad_sizes_and_adam_parameters(workloads):
+    """Batches beyond the network's capacity and invalid Adam parameters are
+    refused on the host before any launch; a refused training step leaves
+    the parameters and the Adam step count unchanged."""
+    torch, dev = torch_dev()
+    net, theta = make(workloads, 64, seed=9)
+    x = torch.zeros((65, 21), device=dev)
+    y = torch.zeros((65, 126), device=dev)
+    with pytest.raises(B.MppiError):
+        net.grad_async(x, y)
+    with pytest.raises(B.MppiError):
+        net.train_step_async(x, y)
+    with pytest.raises(B.MppiError):
+        net.forward_async(x, torch.zeros((65, 126), device=dev))
+    q = torch.zeros((65, 7), dtype=torch.float64, device=dev)
+    tg = torch.zeros((65, 13), dtype=torch.float64, device=dev)
+    tg[:, 3] = 1.0
+    with pytest.raises(B.MppiError):
+        net.propose_async(q, q, tg, torch.zeros((65, 126), dtype=torch.float64, device=dev))
+    x64, y64 = x[:64].contiguous(), y[:64].contiguous()
+    for bad in (dict(lr=-1.0), dict(beta1=1.0), dict(beta2=-0.1), dict(eps=0.0)):
+        with pytest.raises(B.MppiError):
+            net.train_step_async(x64, y64, **bad)
+        with pytest.raises(B.MppiError):
+            net.adam_async(**bad)
+    torch.cuda.synchronize()
+    assert np.array_equal(net.get_params(), theta)
+    # the first accepted step is Adam step 1 (bias corrections of t = 1)
+    X, Y = inputs.draw_mlp_batch(80, 64)
+    g = torch.zeros(B.MLP_PARAMS, device=dev)
+    net.grad_async(to_dev(torch, dev, f32(X)), to_dev(torch, dev, f32(Y)), g)
+    net.adam_async(lr=2e-3)
+    torch.cuda.synchronize()
+    ref, _, _ = om.adam(theta.astype(np.float64), np.zeros(theta.size), np.zeros(theta.size),
+                        g.cpu().numpy().astype(np.float64), 1, lr=2e-3)
+    got = net.get_params().astype(np.float64)
+    assert np.abs(got - ref).max() <= 4e-7 * (np.abs(ref).max() + 2e-3)
+    net.close()
+
+
 def test_training_reduces_loss_and_keeps_weight_copies_consistent(workloads):
     """300 Adam steps on a smooth synthetic regression; afterwards the GPU
     forward and gradient (which read the BF16 copies and their transposes
