@@ -24,18 +24,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "MPPI update rate (Hz) + ABA rollout steps/s, K=4096 T=18 7-DoF, FP32"
-# Floating-point operations of one sample-step and of the per-sample
-# terminal cost in the rollout kernel's own formulation, counted by running
-# its per-sample code with an op-counting scalar (tests/opcount.cpp; add,
-# mul, div, sqrt = 1 flop each, a fused multiply-add = 2).  Contact workload
+# Algorithmic floating-point operations of one sample-step and of the
+# per-sample terminal cost: the work of the method on the articulated-body
+# route (forward kinematics, articulated-body dynamics, the force estimate
+# in its least-squares form, the cost and the Euler step), counted by
+# running the per-lane kernels' per-sample code with an op-counting scalar
+# (tests/opcount.cpp; add, mul, div, sqrt = 1 flop each, a fused
+# multiply-add = 2).  Every launch shape and route is credited with this
+# same work per sample-step; the eight-lane default computes the same
+# quantities by the composite-rigid-body route and executes more
+# instructions for them (every lane factorises M).  Contact workload
 # (force estimate, wall, orientation cost on).
-FLOPS_PER_SAMPLE_STEP = 6967
+FLOPS_PER_SAMPLE_STEP = 6475
 FLOPS_PER_SAMPLE_TERMINAL = 822
 # Free-space problems (no wall, no force term, no orientation cost).
 FLOPS_PER_SAMPLE_STEP_FREE = 4573
 FLOPS_PER_SAMPLE_TERMINAL_FREE = 704
 # The paper's own dynamics route (M by Eq. 8, Cholesky), contact workload.
-FLOPS_PER_SAMPLE_STEP_EXPLICIT = 6709
+FLOPS_PER_SAMPLE_STEP_EXPLICIT = 6581
 # Eq. 4b: one multiply-add per sample and output row (weighted noise sum).
 FLOPS_PER_SAMPLE_ROW_WEIGHT = 2
 FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (AMD published)

@@ -9,15 +9,13 @@
 //     without forming M by the articulated-body algorithm (Featherstone),
 //     in link-local spatial coordinates [angular; linear];
 //   * when the force cost is on, the EE wrench estimate of Eq. 13,
-//     F_ee = Lambda J M^-1 tau_F, from two extra quantities that reuse the
-//     articulated-body factors (U_i, D_i) of the same step:
-//       - Omega_n = J_n M^-1 J_n^T, the inverse articulated inertia seen at
-//         the last link, by the outward recursion
-//           Omega_i = P_i X_i Omega_{i-1} X_i^T P_i^T + S D_i^-1 S^T,
-//           P_i = 1 - S D_i^-1 U_i^T,   Omega_{-1} = 0 (fixed base);
-//       - J_n M^-1 tau_F from one extra zero-velocity solve with the same
-//         factors (force_estimate, after the step);
-//     then x = Omega_n^-1 (J_n M^-1 tau_F) by a 6x6 Cholesky and
+//     F_ee = Lambda J M^-1 tau_F, from the articulated-body factors
+//     (U_i, D_i) of the same step: J_n M^-1 J_n^T = A A^T with one column
+//     of A per joint, carried outward link by link, and J_n M^-1 tau_F =
+//     A y from one extra zero-velocity pass with the same factors; the
+//     wrench is the least-squares solution of A^T x = y (lsq_wrench,
+//     modified Gram-Schmidt), which keeps FP32 accurate near kinematic
+//     singularities where forming Lambda^-1 would not, and
 //     F_ee = T^-T x (T: last-link origin -> EE point, world axes).
 //   * the running cost of Eqs. 9-14 and the semi-implicit Euler step of
 //     Eq. 7 are applied by the caller.
@@ -325,48 +323,52 @@ template <typename R> MPPI_HD void so3_log(const R* M, R* rho)
     rho[0] = f * vx; rho[1] = f * vy; rho[2] = f * vz;
 }
 
-// 6x6 SPD solve (Cholesky), M given as Sym6, b overwritten by the solution.
-template <typename R> MPPI_HD void chol6_solve(const Sym6<R>& S, R* b)
+// Least-squares form of the wrench solve of Eq. 13.  With the inverse
+// operational-space inertia factored as Omega = A A^T (A: 6 x 7, one column
+// per joint) and J M^-1 tau_F = A y, the wrench x = Omega^-1 A y is the
+// minimiser of |A^T x - y|.  Modified Gram-Schmidt on the columns of
+// [A^T | y] (the right-hand side taken through the same projections, the
+// augmented form that Bjorck showed backward stable for least squares)
+// gives A^T = Q Rm and Q^T y, then x = Rm^-1 Q^T y.  Its rounding error
+// grows with cond(A) = cond(Omega)^(1/2), where forming Omega and solving
+// it (the normal equations) grows with cond(Omega), which near a kinematic
+// singularity exceeds 1 / u in FP32.  At: rows = joints, columns = the six
+// wrench components; At and y are overwritten.
+template <typename R> MPPI_HD void lsq_wrench(R (&At)[NJ][6], R (&y)[NJ], R* x)
 {
-    R F[36];
+    R Rm[6][6], z[6], id[6];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int s = 0; s < 6; ++s) {
+        R n2 = R(0);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            F[i * 6 + j] = S.A[si(i, j)];
-            F[i * 6 + 3 + j] = S.B[i * 3 + j];
-            F[(3 + i) * 6 + j] = S.B[j * 3 + i];
-            F[(3 + i) * 6 + 3 + j] = S.C[si(i, j)];
+        for (int i = 0; i < NJ; ++i) n2 = fma_(At[i][s], At[i][s], n2);
+        const R r = rsqrt_sqrt_(n2);
+        id[s] = rcp_(r);
+        R qv[NJ];
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) qv[i] = At[i][s] * id[s];
+#pragma unroll
+        for (int c = s + 1; c < 6; ++c) {
+            R d = R(0);
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) d = fma_(qv[i], At[i][c], d);
+            Rm[s][c] = d;
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) At[i][c] = fma_(-d, qv[i], At[i][c]);
         }
-    R L[21], inv[6];
+        R d = R(0);
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
+        for (int i = 0; i < NJ; ++i) d = fma_(qv[i], y[i], d);
+        z[s] = d;
 #pragma unroll
-        for (int j = 0; j <= i; ++j) {
-            R s = F[i * 6 + j];
-#pragma unroll
-            for (int k = 0; k < j; ++k) s -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
-            if (i == j) {
-                R d = rsqrt_sqrt_(s);
-                L[i * (i + 1) / 2 + i] = d;
-                inv[i] = rcp_(d);
-            } else {
-                L[i * (i + 1) / 2 + j] = s * inv[j];
-            }
-        }
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        R s = b[i];
-#pragma unroll
-        for (int k = 0; k < i; ++k) s -= L[i * (i + 1) / 2 + k] * b[k];
-        b[i] = s * inv[i];
+        for (int i = 0; i < NJ; ++i) y[i] = fma_(-d, qv[i], y[i]);
     }
 #pragma unroll
-    for (int i = 5; i >= 0; --i) {
-        R s = b[i];
+    for (int s = 5; s >= 0; --s) {
+        R t = z[s];
 #pragma unroll
-        for (int k = i + 1; k < 6; ++k) s -= L[k * (k + 1) / 2 + i] * b[k];
-        b[i] = s * inv[i];
+        for (int c = s + 1; c < 6; ++c) t = fma_(-Rm[s][c], x[c], t);
+        x[s] = t * id[s];
     }
 }
 
@@ -395,10 +397,10 @@ template <typename R> MPPI_HD void chol6_solve(const Sym6<R>& S, R* b)
 //                       a_i = a'_i + S_i qdd_i, a_{-1} = (0, -g)
 // Force path (Eq. 13): Omega_i = P_i X_i Omega_{i-1} X_i^T P_i^T + S_i S_i^T / D_i,
 // P_i = 1 - S_i U_i^T / D_i, Omega_{-1} = 0, gives Omega_n = J_n M^-1 J_n^T
-// about p_n; a zero-velocity solve with torques tau_F gives b = J_n M^-1 tau_F
-// (the uniform gravity pseudo-acceleration removed); x = Omega_n^-1 b is the
-// spatial force about p_n and the EE wrench is F = x_f,
-// N = x_n - (p_ee - p_n) x x_f.
+// about p_n, a sum of one rank-one term per joint (force_estimate carries
+// its factor A instead of Omega); a zero-velocity solve with torques tau_F
+// gives b = J_n M^-1 tau_F; x = Omega_n^-1 b is the spatial force about p_n
+// and the EE wrench is F = x_f, N = x_n - (p_ee - p_n) x x_f.
 // What the force estimate needs from one articulated-body step: the joint
 // axes, the link translations r_0..r_6, the factors U_i and 1/D_i and the
 // EE offset from p_n (all world axes).  force_estimate() turns it, with the
@@ -451,30 +453,6 @@ template <typename R> MPPI_HD void sym6_sub_outer(Sym6<R>& M, const R* U, const 
 #pragma unroll
         for (int b = 0; b < 3; ++b) M.B[a * 3 + b] = fma_(-U[a], W[3 + b], M.B[a * 3 + b]);
 }
-// M += S y^T + y S^T for a revolute joint, S = (z, 0): the C block is
-// unchanged and B gets z_a y_lin,b only
-template <typename R> MPPI_HD void sym6_add_joint_rank2(Sym6<R>& M, const R* z, const R* y)
-{
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = a; b < 3; ++b) M.A[si(a, b)] = fma_(z[a], y[b], fma_(y[a], z[b], M.A[si(a, b)]));
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) M.B[a * 3 + b] = fma_(z[a], y[3 + b], M.B[a * 3 + b]);
-}
-// rx M for a general 3x3 M (row-major): P_ij = sum_k rx_ik M_kj
-template <typename R> MPPI_HD void rx_mul(const R* r, const R* M, R* P)
-{
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        R m0 = M[j], m1 = M[3 + j], m2 = M[6 + j];
-        P[j] = r[1] * m2 - r[2] * m1;
-        P[3 + j] = r[2] * m0 - r[0] * m2;
-        P[6 + j] = r[0] * m1 - r[1] * m0;
-    }
-}
 // Force-side shift of a symmetric spatial matrix from a reference point p'
 // to p = p' - r (r = p' - p): out = X^T M X with X = [1 0; -rx 1]:
 //   C' = C, B' = B + rx C, A' = A + rx B^T + (rx B^T)^T - rx C rx.
@@ -508,46 +486,22 @@ template <typename R> MPPI_HD void shift_force(const R* r, Sym6<R>& M)
 #pragma unroll
     for (int i = 0; i < 9; ++i) M.B[i] += P[i];
 }
-// Motion-side shift from p' to p = p' + r: out = X M X^T, X = [1 0; -rx 1]:
-//   A' = A, B' = B + A rx, C' = C - rx B - (rx B)^T - rx A rx.
-template <typename R> MPPI_HD void shift_motion(const R* r, Sym6<R>& M)
-{
-    R Af[9], W[9], G[9], H[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) Af[i * 3 + j] = M.A[si(i, j)];
-    // W = A rx: W_ij = sum_k A_ik rx_kj
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        R a0 = Af[i * 3], a1 = Af[i * 3 + 1], a2 = Af[i * 3 + 2];
-        W[i * 3 + 0] = a1 * r[2] - a2 * r[1];
-        W[i * 3 + 1] = a2 * r[0] - a0 * r[2];
-        W[i * 3 + 2] = a0 * r[1] - a1 * r[0];
-    }
-    rx_mul(r, M.B, G);  // rx B
-    rx_mul(r, W, H);    // rx A rx
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j)
-            M.C[si(i, j)] += -G[i * 3 + j] - G[j * 3 + i] - H[i * 3 + j];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) M.B[i] += W[i];
-}
-
 // EE wrench estimate of Eq. 13 from the factors of one step and the
-// sampled torques v:
-//   b = J_n M^-1 tau_F about p_n by a zero-velocity articulated-body solve
-//       with the same factors (tip to root: uF_i = tau_F,i - S_i.pF,
-//       pF += U_i uF_i / D_i shifted to the parent; root to tip:
-//       qF_i = (uF_i - U_i.aF) / D_i, aF += S_i qF_i), tau_F = v - g(q)
-//       through a uniform pseudo-acceleration -g when force_mode is 0;
-//   Omega <- P (X Omega X^T) P^T + S S^T / D, link by link from the root
-//          = Y + S y^T + y S^T with Y = X Omega X^T, w = Y U,
-//            y = (beta/D^2 + 1/D)/2 S - w/D, beta = U.w,
-// then x = Omega_n^-1 b (6x6 Cholesky) is the spatial force about p_n and
-// F = (x_f, x_n - ree x x_f).
+// sampled torques v, as the least-squares problem of lsq_wrench:
+//   uF_i = tau_F,i - S_i.pF by the tip-to-root pass of a zero-velocity
+//       articulated-body solve with the same factors (pF += U_i uF_i / D_i,
+//       shifted to the parent);
+//   the columns c_i = T_i S_i of the factorisation
+//       Omega_n = J_n M^-1 J_n^T = sum_i c_i c_i^T / D_i,
+//       T_i = P_n X_n ... P_{i+1} X_{i+1},  P_k = 1 - S_k U_k^T / D_k,
+//       carried link by link from the root (every earlier column shifted to
+//       p_k and projected by P_k, then c_k = S_k appended);
+//   J_n M^-1 tau_F = sum_i c_i (uF_i - U_i.a_b) / D_i, where a_b = (0, -g)
+//       when tau_F = v - g(q) (force_mode 0: the gravity torque enters as the
+//       rigid base acceleration -g, whose projections telescope into the
+//       U_i.a_b terms) and a_b = 0 for tau_F = v;
+// so A = [c_i / sqrt(D_i)] and y_i = (uF_i - U_i.a_b) / sqrt(D_i).  The
+// solution x is the spatial force about p_n and F = (x_f, x_n - ree x x_f).
 template <typename R>
 MPPI_HD void force_estimate(const ForceIn<R>& fi, const R* v, const R* g, int force_mode, R* F)
 {
@@ -565,43 +519,39 @@ MPPI_HD void force_estimate(const ForceIn<R>& fi, const R* v, const R* g, int fo
             pF[0] += rf[0]; pF[1] += rf[1]; pF[2] += rf[2];
         }
     }
-    R aF[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-    if (force_mode == 0) { aF[3] = -g[0]; aF[4] = -g[1]; aF[5] = -g[2]; }
+    R At[NJ][6], y[NJ];
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
-        R wxr[3];
-        cross3(aF, fi.rr[i], wxr);
-        aF[3] += wxr[0]; aF[4] += wxr[1]; aF[5] += wxr[2];
-        const R qF = (uF[i] - dot6(fi.U[i], aF)) * fi.iD[i];
-        aF[0] += fi.z[i][0] * qF; aF[1] += fi.z[i][1] * qF; aF[2] += fi.z[i][2] * qF;
+        // earlier columns: shift from p_{i-1} to p_i, then project by P_i
+#pragma unroll
+        for (int l = 0; l < i; ++l) {
+            R wxr[3];
+            cross3(At[l], fi.rr[i], wxr);
+            At[l][3] += wxr[0]; At[l][4] += wxr[1]; At[l][5] += wxr[2];
+            const R pr = dot6(fi.U[i], At[l]) * fi.iD[i];
+            At[l][0] = fma_(-fi.z[i][0], pr, At[l][0]);
+            At[l][1] = fma_(-fi.z[i][1], pr, At[l][1]);
+            At[l][2] = fma_(-fi.z[i][2], pr, At[l][2]);
+        }
+        At[i][0] = fi.z[i][0]; At[i][1] = fi.z[i][1]; At[i][2] = fi.z[i][2];
+        At[i][3] = R(0); At[i][4] = R(0); At[i][5] = R(0);
+        R ub = uF[i];
+        if (force_mode == 0) ub += fi.U[i][3] * g[0] + fi.U[i][4] * g[1] + fi.U[i][5] * g[2];
+        y[i] = ub;
     }
-    // remove the uniform gravity term
-    R b[6] = {aF[0], aF[1], aF[2], aF[3], aF[4], aF[5]};
-    if (force_mode == 0) { b[3] += g[0]; b[4] += g[1]; b[5] += g[2]; }
-
-    Sym6<R> Om;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) { Om.A[k] = R(0); Om.C[k] = R(0); }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Om.B[k] = R(0);
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
-        if (i > 0) shift_motion(fi.rr[i], Om);
-        R wv[6];
-        sym6_mv(Om, fi.U[i], wv);
-        const R dI = fi.iD[i];
-        const R g2 = R(0.5) * (dot6(fi.U[i], wv) * dI + R(1)) * dI;
-        R y[6];
-        y[0] = fma_(g2, fi.z[i][0], -wv[0] * dI); y[1] = fma_(g2, fi.z[i][1], -wv[1] * dI);
-        y[2] = fma_(g2, fi.z[i][2], -wv[2] * dI);
-        y[3] = -wv[3] * dI; y[4] = -wv[4] * dI; y[5] = -wv[5] * dI;
-        sym6_add_joint_rank2(Om, fi.z[i], y);
+        const R sD = rsqrt_sqrt_(fi.iD[i]);
+#pragma unroll
+        for (int a = 0; a < 6; ++a) At[i][a] *= sD;
+        y[i] *= sD;
     }
-    chol6_solve(Om, b);   // x = Omega^-1 b: spatial force about p_n
+    R x[6];
+    lsq_wrench(At, y, x);   // spatial force about p_n
     R rf[3];
-    cross3(fi.ree, b + 3, rf);
-    F[0] = b[3]; F[1] = b[4]; F[2] = b[5];
-    F[3] = b[0] - rf[0]; F[4] = b[1] - rf[1]; F[5] = b[2] - rf[2];
+    cross3(fi.ree, x + 3, rf);
+    F[0] = x[3]; F[1] = x[4]; F[2] = x[5];
+    F[3] = x[0] - rf[0]; F[4] = x[1] - rf[1]; F[5] = x[2] - rf[2];
 }
 
 // ext: EXTW_NONE, EXTW_CONST (world wrench F_ext at the EE point, current

@@ -10,8 +10,10 @@
 //     the J^T products are accumulated from the tip;
 //   * qdd = M^-1 (tau + tau_ext - h) (Eq. 6) by a 7x7 Cholesky solve;
 //   * when the force cost is on, F_ee = (J M^-1 J^T)^-1 J M^-1 tau_F
-//     (Eq. 13) with J the EE Jacobian [J_v; J_w] at the EE point: six
-//     solves for M^-1 J^T, one for M^-1 tau_F, and a 6x6 Cholesky.
+//     (Eq. 13) with J the EE Jacobian [J_v; J_w] at the EE point: with the
+//     Cholesky factor M = L L^T, seven forward substitutions give
+//     A^T = L^-1 J^T and y = L^-1 tau_F, and F_ee is the least-squares
+//     solution of A^T x = y (lsq_wrench of dyn.hpp).
 // Same inputs and outputs as dyn_step (StepOut: qdd, EE pose, F_ee).
 #pragma once
 
@@ -231,33 +233,25 @@ MPPI_HD void dyn_step_m(const ModelM<R>& Mdl, const CostM<R>& Cst, int ext, cons
             J[0][j] = jv[0]; J[1][j] = jv[1]; J[2][j] = jv[2];
             J[3][j] = z[j][0]; J[4][j] = z[j][1]; J[5][j] = z[j][2];
         }
-        // X = M^-1 J^T (six solves), y = M^-1 tau_F
-        R X[6][NJ];
+        // with M = L L^T: A^T = L^-1 J^T (J M^-1 J^T = A A^T) and
+        // y = L^-1 tau_F (J M^-1 tau_F = A y); the wrench is the
+        // least-squares solution of A^T x = y (lsq_wrench)
+        R At[NJ][6], y[NJ], b[6];
 #pragma unroll
-        for (int r = 0; r < 6; ++r) {
+        for (int i = 0; i < NJ; ++i) {
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) X[r][j] = J[r][j];
-            chol_solve<NJ>(Mm, idg, X[r]);
-        }
-        chol_solve<NJ>(Mm, idg, tF);
-        // Lambda^-1 = J M^-1 J^T, b = J M^-1 tau_F, F = Lambda b
-        R Li[6][6], b[6], id6[6];
+            for (int r = 0; r < 6; ++r) {
+                R s = J[r][i];
 #pragma unroll
-        for (int r = 0; r < 6; ++r) {
-            R s = R(0);
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) s += J[r][j] * tF[j];
-            b[r] = s;
-#pragma unroll
-            for (int c = 0; c <= r; ++c) {
-                R t = R(0);
-#pragma unroll
-                for (int j = 0; j < NJ; ++j) t += J[r][j] * X[c][j];
-                Li[r][c] = t;
+                for (int k = 0; k < i; ++k) s -= Mm[i][k] * At[k][r];
+                At[i][r] = s * idg[i];
             }
+            R s = tF[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) s -= Mm[i][k] * y[k];
+            y[i] = s * idg[i];
         }
-        chol_lower<6>(Li, id6);
-        chol_solve<6>(Li, id6, b);
+        lsq_wrench(At, y, b);
 #pragma unroll
         for (int a = 0; a < 6; ++a) out.F[a] = b[a];
     }

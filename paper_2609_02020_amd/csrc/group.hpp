@@ -7,9 +7,11 @@
 //                (lane 7: the fixed EE transform) and an inclusive scan of
 //                transform compositions over the group gives every link
 //                frame (R_j, p_j) at once, the EE pose in lane 7;
-//   velocities   motion subspaces S_j = (z_j, p_j x z_j) in Pluecker
-//                coordinates about the world origin O, where moving between
-//                links needs no transform, so link twists are prefix sums
+//   velocities   motion subspaces S_j = (z_j, (p_j - O) x z_j) in Pluecker
+//                coordinates about one point O for all links (the step's
+//                EE point, so that the distal links keep short moment
+//                arms), where moving between links needs no transform, so
+//                link twists are prefix sums
 //                V_j = sum_{i<=j} S_i qd_i and velocity-product
 //                accelerations prefix sums of V_i x S_i qd_i (gravity as
 //                the base acceleration);
@@ -25,14 +27,17 @@
 //   solve        the rows are gathered through the group's LDS area and
 //                every lane factors M = L D L^T (no pivoting: M is SPD)
 //                and solves Eq. 6 for the whole qdd; lane j keeps qdd_j;
-//   force        (Eqs. 12-13) Omega = J M^-1 J^T and b = J M^-1 tau_F with
-//                J the EE Jacobian about the EE point (columns
-//                (z_j, (p_j - p_ee) x z_j), short moment arms where the
-//                estimate is taken): lane r (r < 6) solves L y = (row r of J)^T,
-//                lane 6 L y = tau_F, so Omega_rs = sum_i y^r_i y^s_i / d_i
-//                and b_r = sum_i y^r_i y^F_i / d_i are each one dot product
-//                per lane after a gather; every lane then solves the 6x6
-//                system (Cholesky) for the EE wrench;
+//   force        (Eqs. 12-13) with J the EE Jacobian about the EE point
+//                (columns (z_j, (p_j - p_ee) x z_j), short moment arms
+//                where the estimate is taken) and M = L D L^T:
+//                lane r (r < 6) solves L y = (row r of J)^T, lane 6
+//                L y = tau_F, and D^-1/2 y is column j of [A^T | y'] with
+//                J M^-1 J^T = A A^T and J M^-1 tau_F = A y'; the wrench is
+//                the least-squares solution of A^T x = y' by modified
+//                Gram-Schmidt with column j in lane j (six broadcast
+//                steps) and a back substitution in every lane -- without
+//                forming J M^-1 J^T, whose condition number (the square of
+//                A's) exceeds 1 / u32 near kinematic singularities;
 //   cost         lane 7 adds the pose and force terms of Eqs. 9-13, lanes
 //                0..6 their joint's limit and torque terms (Eq. 14), and
 //                the collision pairs of Eq. 15 are dealt over the eight
@@ -56,11 +61,10 @@ namespace mppi {
 
 constexpr int kGroup = 8;
 // group LDS area (values of the rollout type)
-constexpr int kGxS = 16;                   // slot: S_j (6), Ic_j S_j (6), (p_j - p_ee) x z_j (3)
+constexpr int kGxS = 16;                   // slot: S_j (6), Ic_j S_j (6), 4 unused
 constexpr int kGxSF = 0;                   // [8][kGxS]
 constexpr int kGxRow = kGxSF + 8 * kGxS;   // [8][9]: M row j, tau - h, tau_F
-constexpr int kGxY = kGxRow + 8 * 9;       // [8][8]: y columns of the force solve
-constexpr int kGxOm = kGxY + 8 * 8;        // [8][8]: Omega row r, b_r
+constexpr int kGxOm = kGxRow + 8 * 9;      // [8][8]: lane j's column of the force solve's triangular factor
 constexpr int kGxH = kGxOm + 8 * 8;        // [8][12]: handoff to the cost part: q, qd, v, p_j, h_c, m_c
                                            // (lanes 0..6); lane 7: p_ee, R_ee
 constexpr int kGxCount = kGxH + 8 * 12;    // 424
@@ -195,6 +199,30 @@ template <typename R> MPPI_HD R joint_cost1(const CostM<R>& C, const GroupLink<R
            C.w_post * sq(q - L.qrest);
 }
 
+// One modified Gram-Schmidt step of lsq_wrench on the group: column S of
+// [A^T | y] (lane S) is broadcast; every lane takes its entry of row S of
+// the triangular factor, Rc[S] = q_S . col (q_S the normalised column S),
+// and lanes j > S remove the q_S component from their column.  idg[S] =
+// 1 / |column S| in every lane.
+template <int S, typename R, class G> MPPI_HD void group_mgs_step(const G& g, R* col, R* Rc, R* idg)
+{
+    R u[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) u[i] = g.template bcast<S>(col[i]);
+    R n2 = R(0), d = R(0);
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        n2 = fma_(u[i], u[i], n2);
+        d = fma_(u[i], col[i], d);
+    }
+    const R r = rsqrt_sqrt_(n2);
+    idg[S] = rcp_(r);
+    Rc[S] = d * idg[S];
+    const R coef = g.j > S ? d * idg[S] * idg[S] : R(0);
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) col[i] = fma_(-coef, u[i], col[i]);
+}
+
 // What a group step leaves for inspection (host checks): lane 7's EE pose,
 // the force estimate (FORCE) and this lane's qdd.
 template <typename R> struct GroupStepOut {
@@ -237,9 +265,9 @@ template <typename R> MPPI_HD void group_factor(const R* X, GroupFactor<R>& f, R
 // lane's qdd (0 in lane 7); p, Q receive this lane's frame (lane 7: the EE
 // pose).  tau: this lane's joint torque (sampled torque plus any
 // joint-space external torque); v: the sampled torque (tau_F).
-// FDYN: the inputs of the force estimate (tau_F in column 8 of the rows,
-// the EE Jacobian's linear rows in slots 12..14) are formed here, on the
-// dynamics chain; otherwise group_cost forms them from the handoff.  The
+// FDYN: the input of the force estimate that the rows do not hold (tau_F
+// in column 8 of the rows) is formed here, on the
+// dynamics chain; otherwise group_cost forms it from the handoff.  The
 // update kernel chooses FDYN when the cost part also carries the collision
 // pairs, so that neither part runs both.
 template <typename R, bool FORCE, class G, bool FDYN = false>
@@ -251,13 +279,21 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
 
     // ---- kinematics: link frames (lane 7: the EE frame)
     group_fk(g, L, q, Q, p);
-    // motion subspace about O (lane 7: none)
+    // spatial quantities are taken about the EE point O = p_ee of this
+    // step (a fixed point in space for the step): the moment arms of the
+    // distal links, whose small inertias set the small entries of M, stay
+    // at link length, where arms about the world origin would be the reach
+    const R pe[3] = {g.template bcast<kGroup - 1>(p[0]), g.template bcast<kGroup - 1>(p[1]),
+                     g.template bcast<kGroup - 1>(p[2])};
+    const R pr[3] = {p[0] - pe[0], p[1] - pe[1], p[2] - pe[2]};
+    // motion subspace about O (lane 7: none); its linear part (p_j - p_ee)
+    // x z_j is also the EE Jacobian's linear column about the EE point
     R z[3] = {Q[2] * L.live, Q[5] * L.live, Q[8] * L.live}, pz[3];
-    cross3(p, z, pz);
+    cross3(pr, z, pz);
     // link inertia about O: mass m, first moment h = m c, rotational I_O
     R cw[3], Ib[6];
     mv3(Q, L.com, cw);
-    cw[0] += p[0]; cw[1] += p[1]; cw[2] += p[2];
+    cw[0] += pr[0]; cw[1] += pr[1]; cw[2] += pr[2];
     congr_sym3<false>(Q, L.Ic, Ib);
     R In[10];   // h[3], m, I_O[6]
     In[0] = L.m * cw[0]; In[1] = L.m * cw[1]; In[2] = L.m * cw[2]; In[3] = L.m;
@@ -314,19 +350,14 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
         f[3] += t3[0]; f[4] += t3[1]; f[5] += t3[2];
     }
     if (ext == EXTW_WALL) {
-        // unilateral spring-damper at the EE point (lane 7's frame origin)
-        R wxp[3];
-        cross3(V, p, wxp);
-        const R vee[3] = {V[3] + wxp[0], V[4] + wxp[1], V[5] + wxp[2]};
+        // unilateral spring-damper at the EE point (lane 7's frame origin,
+        // the reference point O: the EE point velocity is V's linear part
+        // and the wall force has no moment about O)
         const R delta = C.wall_d0 - dot3(C.wall_n, p);
-        const R ddelta = -dot3(C.wall_n, vee);
+        const R ddelta = -dot3(C.wall_n, V + 3);
         const R mag = hinge(C.wall_k * delta + C.wall_c * ddelta);
-        const R Fw[3] = {C.wall_n[0] * mag, C.wall_n[1] * mag, C.wall_n[2] * mag};
-        R pf[3];
-        cross3(p, Fw, pf);
         if (ee) {
-            f[0] -= pf[0]; f[1] -= pf[1]; f[2] -= pf[2];
-            f[3] -= Fw[0]; f[4] -= Fw[1]; f[5] -= Fw[2];
+            f[3] -= C.wall_n[0] * mag; f[4] -= C.wall_n[1] * mag; f[5] -= C.wall_n[2] * mag;
         }
     }
 
@@ -357,13 +388,6 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
             tf = v - (dot3(z, ha) + In[3] * dot3(pz, ag));
         }
         X[kGxRow + j * 9 + 8] = ee ? R(0) : tf;
-        // (p_j - p_ee) x z_j
-        const R pe[3] = {g.template bcast<kGroup - 1>(p[0]), g.template bcast<kGroup - 1>(p[1]),
-                         g.template bcast<kGroup - 1>(p[2])};
-        const R d[3] = {p[0] - pe[0], p[1] - pe[1], p[2] - pe[2]};
-        R jz[3];
-        cross3(d, z, jz);
-        slot[12] = jz[0]; slot[13] = jz[1]; slot[14] = jz[2];
     }
     g.sync();
     // row j of M: M_jc = S_min(j,c) . (Ic S)_max(j,c), plus the armature
@@ -430,8 +454,8 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
 // force terms in lane 7 (pee, Re: its EE pose), joint-limit and torque
 // terms in lanes 0..6, and with COLL the collision term of Eqs. 14-15 with
 // the pairs dealt over the lanes (pair i to lane i mod 8; link segments
-// from the joint origins and the EE point in the handoff).  Uses the kGxY
-// and kGxOm parts of X.
+// from the joint origins and the EE point in the handoff).  Uses the kGxOm
+// part of X.
 template <typename R, bool FORCE, bool COLL, class G, bool FDYN = false>
 MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg, const R* grav,
                      R* X, const GroupFactor<R>* fac, R q, R qd, R v, const R* pee, const R* Re,
@@ -479,23 +503,12 @@ MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
             X[kGxRow + j * 9 + 8] = ee ? R(0) : tf;
         }
         // row r of the EE Jacobian about p_ee at joint i: z_i (r < 3), then
-        // (p_i - p_ee) x z_i
+        // (p_i - p_ee) x z_i, i.e. component r of the motion subspace S_i
+        // about the EE point
         const int r = j < 6 ? j : 5;
         R Jr[NJ];
-        if (FDYN) {
 #pragma unroll
-            for (int i = 0; i < NJ; ++i) Jr[i] = X[kGxSF + i * kGxS + (r < 3 ? r : r + 9)];
-        } else {
-            const R* pe = X + kGxH + (kGroup - 1) * 12;
-            const int c = r < 3 ? 0 : r - 3, c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-#pragma unroll
-            for (int i = 0; i < NJ; ++i) {
-                const R* zi = X + kGxSF + i * kGxS;
-                const R* pi = X + kGxH + i * 12 + 3;
-                const R d1 = pi[c1] - pe[c1], d2 = pi[c2] - pe[c2];
-                Jr[i] = r < 3 ? zi[r] : d1 * zi[c2] - d2 * zi[c1];
-            }
-        }
+        for (int i = 0; i < NJ; ++i) Jr[i] = X[kGxSF + i * kGxS + r];
         g.sync();
         GroupFactor<R> local;
         if (!fac) group_factor(X, local, (R*)nullptr);
@@ -503,45 +516,41 @@ MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
         R bF[NJ];
 #pragma unroll
         for (int i = 0; i < NJ; ++i) bF[i] = X[kGxRow + i * 9 + 8];
-        // ---- lane r < 6 solves for row r of J, lane 6 (and 7) for tau_F
-        R y[NJ];
+        // ---- lane r < 6 solves for row r of J, lane 6 (and 7) for tau_F;
+        // scaled by D^-1/2 that is column j of [A^T | y] with Omega = A A^T
+        // and J M^-1 tau_F = A y (M = L D L^T, A^T = D^-1/2 L^-1 J^T)
+        R col[NJ];
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
             R s = j < 6 ? Jr[i] : bF[i];
 #pragma unroll
-            for (int c = 0; c < i; ++c) s = fma_(-Fc.Lm[i][c], y[c], s);
-            y[i] = s;
+            for (int c = 0; c < i; ++c) s = fma_(-Fc.Lm[i][c], col[c], s);
+            col[i] = s;
         }
 #pragma unroll
-        for (int i = 0; i < NJ; ++i) X[kGxY + j * 8 + i] = y[i];
+        for (int i = 0; i < NJ; ++i) col[i] *= rsqrt_sqrt_(Fc.id[i]);
+        // least squares A^T x = y by modified Gram-Schmidt over the lanes
+        // (lsq_wrench's arithmetic with column j in lane j): this lane's
+        // column of the triangular factor (Rc[s], s < j; lane 6: Q^T y)
+        R Rc[6], idg[6];
+        group_mgs_step<0>(g, col, Rc, idg);
+        group_mgs_step<1>(g, col, Rc, idg);
+        group_mgs_step<2>(g, col, Rc, idg);
+        group_mgs_step<3>(g, col, Rc, idg);
+        group_mgs_step<4>(g, col, Rc, idg);
+        group_mgs_step<5>(g, col, Rc, idg);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) X[kGxOm + j * 8 + s] = Rc[s];
         g.sync();
-        // Omega_rs = sum_i y^r_i y^s_i / d_i (s < 6), b_r = sum_i y^r_i y^F_i / d_i
-        R w[NJ];
-#pragma unroll
-        for (int i = 0; i < NJ; ++i) w[i] = y[i] * Fc.id[i];
-#pragma unroll
-        for (int s = 0; s < 7; ++s) {
-            R acc = R(0);
-#pragma unroll
-            for (int i = 0; i < NJ; ++i) acc = fma_(w[i], X[kGxY + s * 8 + i], acc);
-            X[kGxOm + j * 8 + s] = acc;
-        }
-        g.sync();
-        Sym6<R> Om;
+        // x = Rm^-1 Q^T y in every lane: (moment, force) about p_ee
         R bb[6];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
+        for (int s = 5; s >= 0; --s) {
+            R t = X[kGxOm + 6 * 8 + s];
 #pragma unroll
-            for (int c = a; c < 3; ++c) {
-                Om.A[si(a, c)] = X[kGxOm + c * 8 + a];
-                Om.C[si(a, c)] = X[kGxOm + (3 + c) * 8 + 3 + a];
-            }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Om.B[a * 3 + c] = X[kGxOm + (3 + c) * 8 + a];
+            for (int c = s + 1; c < 6; ++c) t = fma_(-X[kGxOm + c * 8 + s], bb[c], t);
+            bb[s] = t * idg[s];
         }
-#pragma unroll
-        for (int a = 0; a < 6; ++a) bb[a] = X[kGxOm + a * 8 + 6];
-        chol6_solve(Om, bb);   // EE wrench: (moment, force) about p_ee
         const R F[6] = {bb[3], bb[4], bb[5], bb[0], bb[1], bb[2]};
         if (ee) ell += force_cost(C, tg, F);
         if (Fout) {

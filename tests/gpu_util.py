@@ -7,6 +7,7 @@ from paper_2609_02020_amd import binding as B
 COST_RTOL = 1e-4      # per-sample cost, relative to the FP64 oracle
 U_ATOL = 1e-3         # U_new, N m
 U32 = 2.0 ** -24      # FP32 unit roundoff
+KAPPA_CAP = 1e-2      # the largest per-sample cost error allowed anywhere (FP32)
 
 
 def torch_dev():
@@ -95,15 +96,20 @@ def force_condition(ora, case, seed, tick, k):
 def check_costs_fp32(ora, case, S_gpu, S_ref, seed, tick, label=""):
     """Per-sample cost parity for FP32 rollouts: relative error <= 1e-4, or,
     for a sample whose force estimate inverts an ill-conditioned matrix
-    (condition number kappa along its trajectory), <= kappa * u32, the
-    forward-error scale of a backward-stable FP32 solve.  Returns the list of
-    such samples (k, error, kappa) for the report."""
+    (condition number kappa of J M^-1 J^T along its trajectory), <=
+    min(kappa * u32, KAPPA_CAP): kappa u32 is the forward-error scale of a
+    backward-stable FP32 solve of that matrix (the least-squares solve the
+    kernels use stays well inside it), and no sample may be further than
+    KAPPA_CAP from the oracle however ill-conditioned.  Prints and returns
+    every such sample (k, error, kappa)."""
     err = cost_rel_err(S_gpu, S_ref)
     flagged = []
     has_force = any(w != 0 for w in case["cost"]["W_force"]) or any(w != 0 for w in case["cost"]["W_reg"])
     for k in np.nonzero(err > COST_RTOL)[0]:
         assert has_force, "%s: sample %d rel err %.3g without the force term" % (label, k, err[k])
         kappa = force_condition(ora, case, seed, tick, int(k))
-        assert err[k] <= kappa * U32, "%s: sample %d rel err %.3g, kappa %.3g" % (label, k, err[k], kappa)
+        bound = min(kappa * U32, KAPPA_CAP)
+        print("%s: flagged sample k=%d rel err %.3g kappa %.3g bound %.3g" % (label, k, err[k], kappa, bound))
+        assert err[k] <= bound, "%s: sample %d rel err %.3g, kappa %.3g" % (label, k, err[k], kappa)
         flagged.append((int(k), float(err[k]), float(kappa)))
     return flagged

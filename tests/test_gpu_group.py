@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from paper_2609_02020_amd import binding as B
-from gpu_util import (U32, U_ATOL, check_costs_fp32, check_update, cost_rel_err, device_update,
+from gpu_util import (KAPPA_CAP, U32, U_ATOL, check_costs_fp32, check_update, cost_rel_err, device_update,
                       force_condition)
 
 pytestmark = pytest.mark.gpu
@@ -92,7 +92,7 @@ def test_group_matches_two_wave_update(ora, workloads, which, i):
     bitwise the same (the same Philox words and arithmetic per normal); the
     costs agree to FP32 rounding of two factorisations, except for samples
     whose force estimate inverts an ill-conditioned J M^-1 J^T, where both
-    sides carry up to kappa u32 each; U_new agrees to 1e-3 N m."""
+    sides carry up to min(kappa u32, 1e-2) each; U_new agrees to 1e-3 N m."""
     case = workloads[which][i]
     outs = []
     for w in (2, GROUP):
@@ -110,7 +110,7 @@ def test_group_matches_two_wave_update(ora, workloads, which, i):
     for k in np.nonzero(rel > 2e-4)[0]:
         kappa = force_condition(ora, case, case["seed"], 12, int(k))
         flagged.append((int(k), float(rel[k]), kappa))
-        assert rel[k] <= 2 * kappa * U32, (k, rel[k], kappa)
+        assert rel[k] <= min(2 * kappa * U32, 2 * KAPPA_CAP), (k, rel[k], kappa)
     print("ill-conditioned samples (k, rel difference, kappa):", flagged)
     assert len(flagged) <= K_FLAG_MAX
     assert np.abs(two["U_new"] - grp["U_new"]).max() <= U_ATOL
