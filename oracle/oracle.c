@@ -1080,9 +1080,11 @@ int ora_update(const ora_robot* rb, const ora_cost* cp, const ora_target* tg,
     return st;
 }
 
-/* Plant for the closed loop: the command is held (zero-order hold) over
-   one control period, split into semi-implicit Euler substeps, with the
-   torque clamped to the joint limits. */
+/* Warm start after s horizon steps of elapsed time (the receding horizon
+   at the end of Sec. II, for a solver period that differs from dt): the
+   plan U is read as piecewise constant (row i held over [i, i + 1) in
+   steps, the last row held past the horizon) and row t of out is its mean
+   over [t + s, t + s + 1). */
 void ora_warm_start(int T, int n, const double* U, double s, double* out)
 {
     for (int t = 0; t < T; ++t) {
@@ -1100,6 +1102,9 @@ void ora_warm_start(int T, int n, const double* U, double s, double* out)
     }
 }
 
+/* Plant for the closed loop: the command is held (zero-order hold) over
+   one control period, split into semi-implicit Euler substeps, with the
+   torque clamped to the joint limits. */
 void ora_plant_step(const ora_robot* rb, const ora_cost* cp, double* q,
                     double* qd, const double* u, double dt, int substeps)
 {

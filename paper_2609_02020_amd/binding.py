@@ -197,8 +197,24 @@ def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def _ptr(t):
-    return None if t is None else C.c_void_p(t.data_ptr())
+def _dev(t, dtype: str, n: int, name: str):
+    """Device pointer of a torch tensor that a kernel reads or writes n
+    elements of, after checking what the C ABI cannot check on a raw
+    pointer: a CUDA (HIP) tensor, contiguous, of the element type the
+    kernels use, with at least n elements.  None passes through (the
+    library decides whether the argument is optional)."""
+    if t is None:
+        return None
+    import torch
+    if not getattr(t, "is_cuda", False):
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.dtype != getattr(torch, dtype):
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if t.numel() < n:
+        raise ValueError("%s needs %d elements, got %d" % (name, n, t.numel()))
+    return C.c_void_p(t.data_ptr())
 
 
 def _stream_ptr(stream):
@@ -256,8 +272,13 @@ class Solver:
 
     def _io(self, io: dict) -> DeviceIO:
         d = DeviceIO()
-        for key in ("q", "qd", "target", "U_nominal", "U_new", "U_shift", "costs", "noise", "status"):
-            setattr(d, key, _ptr(io.get(key)))
+        rdt = "float64" if self.precision == FP64 else "float32"
+        TJ = self.T * NJ
+        spec = {"q": ("float64", NJ), "qd": ("float64", NJ), "target": ("float64", 13),
+                "U_nominal": ("float64", TJ), "U_new": ("float64", TJ), "U_shift": ("float64", TJ),
+                "costs": (rdt, self.K), "noise": (rdt, TJ * self.K), "status": ("int32", 1)}
+        for key, (dt, n) in spec.items():
+            setattr(d, key, _dev(io.get(key), dt, n, key))
         d.seed = int(io.get("seed", 0))
         d.tick = int(io.get("tick", 0))
         return d
@@ -282,8 +303,9 @@ class Solver:
             raise MppiError(st, "mppi_weights_async")
 
     def plant_step_async(self, q, qd, u, dt: float, substeps: int, stream=None):
-        st = self._lib.mppi_plant_step_async(self._h, _ptr(q), _ptr(qd), _ptr(u), float(dt),
-                                             int(substeps), _stream_ptr(stream))
+        st = self._lib.mppi_plant_step_async(self._h, _dev(q, "float64", NJ, "q"), _dev(qd, "float64", NJ, "qd"),
+                                             _dev(u, "float64", NJ, "u"), float(dt), int(substeps),
+                                             _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_plant_step_async")
 
@@ -296,7 +318,9 @@ class Solver:
 
     def warm_start_async(self, U_new, U_out, shift_steps: float, stream=None):
         """U_out = U_new advanced by shift_steps horizon steps (mppi_warm_start_async)."""
-        st = self._lib.mppi_warm_start_async(self._h, _ptr(U_new), _ptr(U_out), float(shift_steps),
+        TJ = self.T * NJ
+        st = self._lib.mppi_warm_start_async(self._h, _dev(U_new, "float64", TJ, "U_new"),
+                                             _dev(U_out, "float64", TJ, "U_out"), float(shift_steps),
                                              _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_warm_start_async")
@@ -305,8 +329,9 @@ class Solver:
         """Keeps io["U_nominal"] or replaces it with U_candidate, whichever
         has the lower noise-free rollout cost (mppi_select_nominal_async)."""
         d = self._io(io)
-        st = self._lib.mppi_select_nominal_async(self._h, C.byref(d), _ptr(U_candidate), _ptr(costs),
-                                                 _stream_ptr(stream))
+        st = self._lib.mppi_select_nominal_async(self._h, C.byref(d), _dev(U_candidate, "float64", self.T * NJ,
+                                                                           "U_candidate"),
+                                                 _dev(costs, "float64", 2, "costs"), _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_select_nominal_async")
 
@@ -382,8 +407,13 @@ class Batch:
 
     def _io(self, io: dict) -> BatchIO:
         d = BatchIO()
-        for key in ("q", "qd", "target", "U_nominal", "U_new", "U_shift", "costs", "status", "seed"):
-            setattr(d, key, _ptr(io.get(key)))
+        n = self.n
+        spec = {"q": ("float64", n * NJ), "qd": ("float64", n * NJ), "target": ("float64", n * 13),
+                "U_nominal": ("float64", self.u_total), "U_new": ("float64", self.u_total),
+                "U_shift": ("float64", self.u_total), "costs": ("float32", self.k_total),
+                "status": ("int32", n), "seed": ("int64", n)}
+        for key, (dt, cnt) in spec.items():
+            setattr(d, key, _dev(io.get(key), dt, cnt, key))
         return d
 
     def update_async(self, io: dict, tick: int, stream=None):
@@ -434,14 +464,17 @@ class Batch:
 
     def warm_start_async(self, U_new, U_out, shift_steps: float, stream=None):
         """Packed U_out = U_new advanced by shift_steps horizon steps."""
-        st = self._lib.mppi_batch_warm_start_async(self._h, _ptr(U_new), _ptr(U_out), float(shift_steps),
-                                                   _stream_ptr(stream))
+        st = self._lib.mppi_batch_warm_start_async(self._h, _dev(U_new, "float64", self.u_total, "U_new"),
+                                                   _dev(U_out, "float64", self.u_total, "U_out"),
+                                                   float(shift_steps), _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_batch_warm_start_async")
 
     def select_nominal_async(self, io: dict, U_candidates, costs=None, stream=None):
         d = self._io(io)
-        st = self._lib.mppi_batch_select_nominal_async(self._h, C.byref(d), _ptr(U_candidates), _ptr(costs),
+        st = self._lib.mppi_batch_select_nominal_async(self._h, C.byref(d),
+                                                       _dev(U_candidates, "float64", self.u_total, "U_candidates"),
+                                                       _dev(costs, "float64", 2 * self.n, "costs"),
                                                        _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_batch_select_nominal_async")
@@ -509,14 +542,25 @@ class Mlp:
             raise MppiError(st, "mppi_mlp_get_params")
         return a
 
+    def _rows(self, x):
+        B = int(x.shape[0])
+        if x.dim() != 2 or x.shape[1] != MLP_INPUTS:
+            raise ValueError("x must be [B][%d]" % MLP_INPUTS)
+        return B
+
     def forward_async(self, x, y, stream=None):
-        st = self._lib.mppi_mlp_forward_async(self._h, _ptr(x), int(x.shape[0]), _ptr(y), _stream_ptr(stream))
+        B = self._rows(x)
+        st = self._lib.mppi_mlp_forward_async(self._h, _dev(x, "float32", B * MLP_INPUTS, "x"), B,
+                                              _dev(y, "float32", B * MLP_OUTPUTS, "y"), _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_mlp_forward_async")
 
     def grad_async(self, x, y_target, grad=None, loss=None, stream=None):
-        st = self._lib.mppi_mlp_grad_async(self._h, _ptr(x), _ptr(y_target), int(x.shape[0]), _ptr(grad),
-                                           _ptr(loss), _stream_ptr(stream))
+        B = self._rows(x)
+        st = self._lib.mppi_mlp_grad_async(self._h, _dev(x, "float32", B * MLP_INPUTS, "x"),
+                                           _dev(y_target, "float32", B * MLP_OUTPUTS, "y_target"), B,
+                                           _dev(grad, "float32", MLP_PARAMS, "grad"), _dev(loss, "float32", 1, "loss"),
+                                           _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_mlp_grad_async")
 
@@ -532,13 +576,21 @@ class Mlp:
 
     def train_step_async(self, x, y_target, loss=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         p = self._adam(lr, beta1, beta2, eps)
-        st = self._lib.mppi_mlp_train_step_async(self._h, _ptr(x), _ptr(y_target), int(x.shape[0]), C.byref(p),
-                                                 _ptr(loss), _stream_ptr(stream))
+        B = self._rows(x)
+        st = self._lib.mppi_mlp_train_step_async(self._h, _dev(x, "float32", B * MLP_INPUTS, "x"),
+                                                 _dev(y_target, "float32", B * MLP_OUTPUTS, "y_target"), B,
+                                                 C.byref(p), _dev(loss, "float32", 1, "loss"), _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_mlp_train_step_async")
 
     def propose_async(self, q, qd, target, U, u_stride=MLP_OUTPUTS, stream=None):
-        st = self._lib.mppi_mlp_propose_async(self._h, int(q.shape[0]), _ptr(q), _ptr(qd), _ptr(target), _ptr(U),
+        n = int(q.shape[0])
+        if u_stride < MLP_OUTPUTS:
+            raise ValueError("u_stride must be at least %d" % MLP_OUTPUTS)
+        st = self._lib.mppi_mlp_propose_async(self._h, n, _dev(q, "float64", n * NJ, "q"),
+                                              _dev(qd, "float64", n * NJ, "qd"),
+                                              _dev(target, "float64", n * 13, "target"),
+                                              _dev(U, "float64", (n - 1) * u_stride + MLP_OUTPUTS, "U"),
                                               int(u_stride), _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_mlp_propose_async")
@@ -546,7 +598,14 @@ class Mlp:
     def encode_async(self, q, qd, target, x, U=None, y=None, u_stride=MLP_OUTPUTS, stream=None):
         """Training rows: features x [n][21] and, with U and y, the
         normalised targets y [n][126] = U / tau_max."""
-        st = self._lib.mppi_mlp_encode_async(self._h, int(q.shape[0]), _ptr(q), _ptr(qd), _ptr(target), _ptr(U),
-                                             int(u_stride), _ptr(x), _ptr(y), _stream_ptr(stream))
+        n = int(q.shape[0])
+        if u_stride < MLP_OUTPUTS:
+            raise ValueError("u_stride must be at least %d" % MLP_OUTPUTS)
+        st = self._lib.mppi_mlp_encode_async(self._h, n, _dev(q, "float64", n * NJ, "q"),
+                                             _dev(qd, "float64", n * NJ, "qd"),
+                                             _dev(target, "float64", n * 13, "target"),
+                                             _dev(U, "float64", (n - 1) * u_stride + MLP_OUTPUTS, "U"),
+                                             int(u_stride), _dev(x, "float32", n * MLP_INPUTS, "x"),
+                                             _dev(y, "float32", n * MLP_OUTPUTS, "y"), _stream_ptr(stream))
         if st:
             raise MppiError(st, "mppi_mlp_encode_async")

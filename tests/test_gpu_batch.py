@@ -51,6 +51,15 @@ def pick(io, batch, p):
             io["costs"][k0:k0 + K].double().cpu().numpy(), int(io["status"][p].cpu()))
 
 
+def gpu_noise(c, tick):
+    """[K, T, 7] perturbations of a problem as the per-lane kernels draw them."""
+    solver = B.Solver(c["robot"], c["cost"], B.FP32)
+    solver.set_launch(2)
+    out = device_update(solver, c, c["seed"], tick, B.FP32)
+    solver.close()
+    return out["noise"]
+
+
 def small_cases(workloads, n=12, tmax=None):
     cases = []
     for i, c in enumerate(workloads["batch64"][:n]):
@@ -94,7 +103,12 @@ def test_batch_matches_oracle(ora, workloads):
         stt, U_ref, S_ref, E_ref = ora.update(c["robot"], c["cost"], c["target"], c["q0"], c["qd0"],
                                               c["U_nom"], c["seed"], 11)
         check_costs_fp32(ora, c, S_b, S_ref, c["seed"], 11, "batch %d" % p)
-        out = {"U_new": U_b, "costs": S_b, "noise": E_ref}
+        # the GPU's own noise for the stage-isolated check: the batch kernel
+        # regenerates it from the Philox counters with the per-lane kernels'
+        # arithmetic, which a single update (launch 2) writes out
+        E_gpu = gpu_noise(c, 11)
+        assert np.abs(E_gpu - E_ref).max() <= 5e-5
+        out = {"U_new": U_b, "costs": S_b, "noise": E_gpu}
         note = check_update(ora, c, out, c["cost"]["lambda"], S_ref, U_ref, "batch %d" % p)
         if note:
             print(note)

@@ -28,9 +28,12 @@ def test_warm_start_matches_oracle(ora, workloads):
         with pytest.raises(B.MppiError) as e:
             solver.warm_start_async(Ud, out, bad)
         assert e.value.status == B.EINVAL
+    big = torch.zeros((19, 7), dtype=torch.float64, device=dev)
     with pytest.raises(B.MppiError) as e:
-        solver.warm_start_async(Ud, Ud[1:], 0.5)   # overlapping buffers
+        solver.warm_start_async(big[:18], big[1:], 0.5)   # overlapping buffers of full size
     assert e.value.status == B.EINVAL
+    with pytest.raises(ValueError):
+        solver.warm_start_async(Ud, Ud[1:], 0.5)   # one row short: refused before the library
     solver.close()
 
 

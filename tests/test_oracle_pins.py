@@ -405,6 +405,46 @@ def test_joint_and_torque_penalties(ora):
     assert parts["pos"] == 0 and parts["ori"] == 0 and parts["force"] == 0
 
 
+def test_posture_term_closed_form(ora):
+    """The posture part of C_joint (Eq. 14; the paper says it regularises
+    redundant motion toward balanced postures) on constructed states: a
+    quadratic well at q_rest, separable over joints, linear in w_post.
+    Every other weight is zero, so the joint part is the posture term alone:
+    zero at q_rest (a sign or index slip moves the well), w_post * d^2 for
+    a single-joint offset d (a dropped or doubled factor), the sum of
+    single-joint offsets for a combined one, and four times the value for
+    twice the offset."""
+    rb = arm7(0)
+    cost = inputs.position_cost(1, 1)
+    cost.update({"W_pos": [0.0] * 3, "w_q": 0.0, "w_tau": 0.0, "w_post": 0.5,
+                 "q_rest": [0.3, -0.7, 1.1, 0.05, -1.9, 2.2, -0.4]})
+    tg = {"p_des": [0, 0, 0]}
+    z = np.zeros(7)
+    rest = np.array(cost["q_rest"])
+
+    def joint(q):
+        _, parts = ora.running_cost(rb, cost, tg, q, z, z)
+        assert parts["pos"] == 0 and parts["torque"] == 0
+        return parts["joint"]
+
+    assert joint(rest) == 0.0
+    singles = []
+    for j, d in enumerate([0.3, -0.1, 0.25, 0.2, -0.6, 0.15, 0.4]):
+        q = rest.copy()
+        q[j] += d
+        singles.append(joint(q))
+        assert singles[-1] == pytest.approx(0.5 * d * d, rel=1e-13)
+        q[j] += d
+        assert joint(q) == pytest.approx(4 * singles[-1], rel=1e-13)
+    d = np.array([0.3, -0.1, 0.25, 0.2, -0.6, 0.15, 0.4])
+    assert joint(rest + d) == pytest.approx(sum(singles), rel=1e-13)
+    assert joint(rest + d) == pytest.approx(0.5 * 0.745, rel=1e-13)   # 0.5 * sum(d^2)
+    # with the limit weights on and every joint inside its limits the
+    # hinges add nothing
+    cost["w_q"], cost["w_qd"] = 1e4, 3.0
+    assert joint(rest + d) == pytest.approx(0.5 * 0.745, rel=1e-13)
+
+
 # ---------------------------------------------------------------------------
 # rollout and Eq. (4)
 # ---------------------------------------------------------------------------
@@ -437,6 +477,55 @@ def test_rollout_pendulum_hand_recurrence(ora):
         th += thd * dt
     ref += 2.5 * pos_cost(th)
     assert S == pytest.approx(ref, rel=1e-12)
+
+
+def test_rollout_pendulum_posture_and_constant_wrench(ora):
+    """The one-link pendulum with a constant EE wrench and the posture term:
+    the external torque is J(q_0)^T F_ext, evaluated once at the measured
+    state and held over the horizon (Sec. III-A: tau_ext assumed constant
+    over the prediction horizon; Eq. 5), and the posture term w_post (q -
+    q_rest)^2 enters every running cost and the terminal cost.  Hand
+    recurrence: joint axis -y, EE at (0.5 cos th, 0, 0.5 sin th), so
+    J_v = (-0.5 sin th, 0, 0.5 cos th) and J_w = (0, -1, 0).  The same
+    recurrence with J taken at the current state instead is far from the
+    oracle's, so the test tells the two apart."""
+    rb = pendulum()
+    m, com, arm, g, Izz = 1.7, (0.31, 0.05, 0.02), 0.05, 9.81, 0.04
+    Mc = Izz + m * (com[0] ** 2 + com[1] ** 2) + arm
+    T, dt = 15, 0.01
+    F = [3.0, 1.0, -12.0, 0.2, 0.5, -0.1]
+    cost = inputs.position_cost(1, T, dt)
+    cost.update({"sigma": [0.0] * 7, "w_q": 0.0, "w_tau": 0.0, "w_terminal": 2.5,
+                 "W_pos": [1.0, 3.0, 7.0], "w_post": 4.0, "q_rest": [0.7] + [0.0] * 6,
+                 "ext_mode": 1, "F_ext": F})
+    tg = {"p_des": [0.1, 0.05, -0.2]}
+    U = np.linspace(-1.0, 2.0, T).reshape(T, 1)
+    S, _ = ora.rollout(rb, cost, tg, [0.4], [0.3], U, 7, 0, 0)
+
+    def stage(th):
+        p = np.array([0.5 * math.cos(th), 0.0, 0.5 * math.sin(th)])
+        e = np.array(tg["p_des"]) - p
+        return float(np.sum(np.array([1.0, 3.0, 7.0]) * e * e)) + 4.0 * (th - 0.7) ** 2
+
+    def tau_ext(th):
+        return -0.5 * math.sin(th) * F[0] + 0.5 * math.cos(th) * F[2] - F[4]
+
+    def run(held):
+        th, thd, ref = 0.4, 0.3, 0.0
+        te0 = tau_ext(th)
+        for t in range(T):
+            ref += stage(th)
+            te = te0 if held else tau_ext(th)
+            acc = (U[t, 0] + te - m * g * (com[0] * math.cos(th) - com[1] * math.sin(th))) / Mc
+            thd += acc * dt
+            th += thd * dt
+        return ref + 2.5 * stage(th)
+
+    assert S == pytest.approx(run(True), rel=1e-12)
+    assert abs(S - run(False)) > 1e-5 * abs(S)   # 1e7 times the tolerance above
+    # the posture term is in: without it the cost drops by its share
+    S0, _ = ora.rollout(rb, dict(cost, w_post=0.0), tg, [0.4], [0.3], U, 7, 0, 0)
+    assert S - S0 > 1e-2 * S
 
 
 def test_rollout_composes_step_functions(ora, workloads):
