@@ -47,7 +47,8 @@ typedef enum {
     MPPI_ENONFINITE = 2,  /* every sample cost was non-finite: U_new = U_nominal */
     MPPI_ENOMEM = 3,      /* device or pinned host allocation failed */
     MPPI_EDEVICE = 4,     /* a HIP runtime call or kernel launch failed */
-    MPPI_ENOTSUP = 5      /* valid request this build does not implement */
+    MPPI_ENOTSUP = 5,     /* valid request this build does not implement */
+    MPPI_ESCRATCH = 6     /* mppi_update_noalloc: needs more than its static workspace */
 } mppi_status;
 
 typedef enum { MPPI_FP32 = 0, MPPI_FP64 = 1 } mppi_precision;
@@ -216,6 +217,28 @@ typedef struct {
  * the per-lane launch shapes and a second launch for the eight-lane one.
  * The caller synchronises.  Errors: MPPI_EINVAL, MPPI_EDEVICE. */
 int mppi_update_async(mppi_handle_t h, const mppi_device_io* io, void* stream);
+
+/* The update of mppi_update_async without allocating anything, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  No handle: robot
+ * and cost are validated as mppi_create validates them (host structs, read
+ * during the call only), and io is as for mppi_update_async (device
+ * pointers in the element type of cost->precision; io->costs and io->noise
+ * may be NULL).  Runs the default launch shape.  What the update needs
+ * beyond io lives in a static device workspace of 8 MiB per GPU (held
+ * until the process ends): the prepared model and cost, written by a
+ * set-up kernel whose arguments carry them by value, a cleared counter,
+ * the intermediate sequences of several iterations (34 KB in all), the
+ * Eq. 4 partials (ceil(K / 16) (2 + 7 T) doubles) and, when io->costs is
+ * NULL, the costs (K values).  Enqueues the set-up kernel and the update
+ * on `stream`; the caller synchronises.  Every call on a GPU uses that
+ * GPU's one workspace, so calls that overlap in time on one GPU race
+ * (serialise them, e.g. on one stream).
+ * Errors: MPPI_EINVAL (as mppi_create and mppi_update_async),
+ * MPPI_ESCRATCH (the sizes above exceed 8 MiB, e.g. K > 32768 at T = 64;
+ * nothing is launched), MPPI_EDEVICE. */
+int mppi_update_noalloc(const mppi_robot_params* robot, const mppi_cost_params* cost,
+                        const mppi_device_io* io, void* stream);
 
 /* Stage entry points (the two halves of mppi_update_async, same io):
  * rollout only writes costs and noise; weights reads them (Eq. 4) and

@@ -16,7 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmppi.so")
 NJ = 7
 
-OK, EINVAL, ENONFINITE, ENOMEM, EDEVICE, ENOTSUP = range(6)
+OK, EINVAL, ENONFINITE, ENOMEM, EDEVICE, ENOTSUP, ESCRATCH = range(7)
 FP32, FP64 = 0, 1
 EXT_NONE, EXT_CONST, EXT_WALL = 0, 1, 2
 
@@ -173,6 +173,7 @@ def lib():
         L.mppi_update.argtypes = [vp, P(C.c_double), P(C.c_double), P(Target), P(C.c_double),
                                   C.c_uint64, C.c_uint64, P(C.c_double), P(C.c_double)]
         L.mppi_update_async.argtypes = [vp, P(DeviceIO), vp]
+        L.mppi_update_noalloc.argtypes = [P(RobotParams), P(CostParams), P(DeviceIO), vp]
         L.mppi_rollout_async.argtypes = [vp, P(DeviceIO), vp]
         L.mppi_weights_async.argtypes = [vp, P(DeviceIO), vp]
         L.mppi_plant_step_async.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int, vp]
@@ -223,6 +224,35 @@ def _stream_ptr(stream):
     return C.c_void_p(int(stream.cuda_stream))
 
 
+def _device_io(io: dict, K: int, T: int, precision: int) -> DeviceIO:
+    """mppi_device_io of one update from a dict of torch device tensors,
+    each checked against what the kernels read and write."""
+    d = DeviceIO()
+    rdt = "float64" if precision == FP64 else "float32"
+    TJ = T * NJ
+    spec = {"q": ("float64", NJ), "qd": ("float64", NJ), "target": ("float64", 13),
+            "U_nominal": ("float64", TJ), "U_new": ("float64", TJ), "U_shift": ("float64", TJ),
+            "costs": (rdt, K), "noise": (rdt, TJ * K), "status": ("int32", 1)}
+    for key, (dt, n) in spec.items():
+        setattr(d, key, _dev(io.get(key), dt, n, key))
+    d.seed = int(io.get("seed", 0))
+    d.tick = int(io.get("tick", 0))
+    return d
+
+
+def update_noalloc(robot: dict, cost: dict, io: dict, precision: int = FP32,
+                   lambda_fp64_threshold: float = 0.05, stream=None):
+    """One update without a handle and without any allocation
+    (mppi_update_noalloc): io as for Solver.update_async."""
+    L = lib()
+    rp = robot_params(robot)
+    cp = cost_params(cost, precision, lambda_fp64_threshold)
+    d = _device_io(io, cp.K, cp.T, precision)
+    st = L.mppi_update_noalloc(C.byref(rp), C.byref(cp), C.byref(d), _stream_ptr(stream))
+    if st:
+        raise MppiError(st, "mppi_update_noalloc")
+
+
 class Solver:
     """One MPPI problem: mppi_create / mppi_update / mppi_destroy."""
 
@@ -271,17 +301,7 @@ class Solver:
         return st, out, costs
 
     def _io(self, io: dict) -> DeviceIO:
-        d = DeviceIO()
-        rdt = "float64" if self.precision == FP64 else "float32"
-        TJ = self.T * NJ
-        spec = {"q": ("float64", NJ), "qd": ("float64", NJ), "target": ("float64", 13),
-                "U_nominal": ("float64", TJ), "U_new": ("float64", TJ), "U_shift": ("float64", TJ),
-                "costs": (rdt, self.K), "noise": (rdt, TJ * self.K), "status": ("int32", 1)}
-        for key, (dt, n) in spec.items():
-            setattr(d, key, _dev(io.get(key), dt, n, key))
-        d.seed = int(io.get("seed", 0))
-        d.tick = int(io.get("tick", 0))
-        return d
+        return _device_io(io, self.K, self.T, self.precision)
 
     def update_async(self, io: dict, stream=None):
         """Device update; io holds torch CUDA tensors (see mppi_device_io)."""

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "launch.hpp"
@@ -280,6 +281,70 @@ int check_io(const mppi_solver* h, const mppi_device_io* io, bool need_out)
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// mppi_update_noalloc: the update of mppi_update_async for callers that
+// cannot allocate device memory.  Everything the update needs beyond the
+// caller's inputs and outputs (the prepared model and cost, the fused
+// launches' counter, the Eq. 4 partials, the intermediate sequences of
+// several iterations, the costs when the caller passes none) lives in this
+// file-scope array: one copy per GPU, held until the process ends, and
+// shared by every call on that GPU (calls that overlap on one GPU race).
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// layout of the scratch array (byte offsets, each region 256-aligned)
+constexpr size_t kSxModelF = 0, kSxModelD = 1024, kSxCostF = 3072, kSxCostD = 4096, kSxCounter = 5376,
+                 kSxIter = 5632, kSxVar = kSxIter + 2 * 256 * 7 * sizeof(double);
+static_assert(sizeof(ModelM<float>) <= kSxModelD - kSxModelF, "scratch layout");
+static_assert(sizeof(ModelM<double>) <= kSxCostF - kSxModelD, "scratch layout");
+static_assert(sizeof(CostM<float>) <= kSxCostD - kSxCostF, "scratch layout");
+static_assert(sizeof(CostM<double>) <= kSxCounter - kSxCostD, "scratch layout");
+static_assert(kSxVar % 256 == 0, "scratch layout");
+// the prepared structs travel as kernel arguments (captured by value)
+static_assert(sizeof(mppi_robot_params) + sizeof(CostM<float>) + sizeof(CostM<double>) + sizeof(void*) <= 4000,
+              "kernel argument space");
+
+// The model prepared on the device (as mppi_create does), the cost structs
+// prepared on the host copied in, the fused launches' counter cleared.
+__global__ void noalloc_setup_kernel(mppi_robot_params P, CostM<float> cf, CostM<double> cd,
+                                     unsigned char* __restrict__ base)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        prep_model(P, *reinterpret_cast<ModelM<float>*>(base + kSxModelF));
+        prep_model(P, *reinterpret_cast<ModelM<double>*>(base + kSxModelD));
+        *reinterpret_cast<CostM<float>*>(base + kSxCostF) = cf;
+        *reinterpret_cast<CostM<double>*>(base + kSxCostD) = cd;
+        *reinterpret_cast<unsigned int*>(base + kSxCounter) = 0u;
+    }
+}
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kScratchDevices] = {};
+
+size_t round256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// the scratch array's device address on the current device, looked up
+// once per device (each GPU holds its own copy at its own address)
+int scratch_base(unsigned char** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return MPPI_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MPPI_EDEVICE;
+        g_scratch[dev] = static_cast<unsigned char*>(ptr);
+    }
+    *out = g_scratch[dev];
+    return MPPI_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int mppi_create(const mppi_robot_params* robot, const mppi_cost_params* cost, mppi_handle_t* out)
@@ -379,6 +444,43 @@ int mppi_update_async(mppi_handle_t h, const mppi_device_io* io, void* stream)
                           io->costs ? io->costs : h->d_costs, true, io->noise != nullptr);
 }
 
+int mppi_update_noalloc(const mppi_robot_params* robot, const mppi_cost_params* cost, const mppi_device_io* io,
+                        void* stream)
+{
+    int st = validate_robot(robot);
+    if (st) return st;
+    st = validate_cost(cost);
+    if (st) return st;
+    if (!io || !io->q || !io->qd || !io->target || !io->U_nominal || !io->U_new) return MPPI_EINVAL;
+    const size_t costs_bytes = io->costs ? 0 : round256((size_t)cost->K * rsize(*cost));
+    const size_t need = kSxVar + costs_bytes + round256(update_parts_bytes(cost->K, cost->T));
+    if (need > kScratchBytes) return MPPI_ESCRATCH;
+    unsigned char* base = nullptr;
+    st = scratch_base(&base);
+    if (st) return st;
+    CostM<float> cf;
+    CostM<double> cd;
+    prep_cost(*cost, cf);
+    prep_cost(*cost, cd);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(noalloc_setup_kernel, dim3(1), dim3(64), 0, s, *robot, cf, cd, base);
+    if (hipGetLastError() != hipSuccess) return MPPI_EDEVICE;
+    // a solver view whose buffers are regions of the scratch array (no
+    // allocation; the default launch shape)
+    mppi_solver h;
+    h.robot = *robot;
+    h.cost = *cost;
+    h.d_mf = reinterpret_cast<ModelM<float>*>(base + kSxModelF);
+    h.d_md = reinterpret_cast<ModelM<double>*>(base + kSxModelD);
+    h.d_cf = reinterpret_cast<CostM<float>*>(base + kSxCostF);
+    h.d_cd = reinterpret_cast<CostM<double>*>(base + kSxCostD);
+    h.d_counter = reinterpret_cast<unsigned int*>(base + kSxCounter);
+    h.d_iter = reinterpret_cast<double*>(base + kSxIter);
+    h.d_costs = io->costs ? io->costs : (void*)(base + kSxVar);
+    h.d_parts = base + kSxVar + costs_bytes;
+    return update_enqueue(&h, io, s, io->noise, h.d_costs, true, io->noise != nullptr);
+}
+
 int mppi_update(mppi_handle_t h, const double* q, const double* qd, const mppi_target* target,
                 const double* U_nominal, uint64_t seed, uint64_t tick, double* U_new, double* costs)
 {
@@ -469,6 +571,7 @@ const char* mppi_strerror(int status)
     case MPPI_ENOMEM: return "out of memory";
     case MPPI_EDEVICE: return "device error";
     case MPPI_ENOTSUP: return "not supported";
+    case MPPI_ESCRATCH: return "request exceeds the static workspace of mppi_update_noalloc";
     default: return "unknown status";
     }
 }

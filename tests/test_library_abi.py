@@ -121,3 +121,23 @@ def test_proposal_and_selection_entry_points_reject_bad_arguments(lib, workloads
     bio = B.BatchIO()
     assert lib.mppi_batch_select_nominal_async(None, C.byref(bio), None, None, None) == B.EINVAL
     assert lib.mppi_batch_plant_step_async(None, C.byref(bio), 0.01, 10, None) == B.EINVAL
+
+
+def test_noalloc_update_validates_on_the_host(lib, workloads):
+    """mppi_update_noalloc checks its structs, its io and the workspace size
+    before any device call (the io pointers below are never dereferenced)."""
+    case = workloads["single_k256"][0]
+    rp = B.robot_params(case["robot"])
+    io = B.DeviceIO()
+    for key in ("q", "qd", "target", "U_nominal", "U_new"):
+        setattr(io, key, C.c_void_p(256))
+    bad = dict(case["cost"], K=0)
+    assert lib.mppi_update_noalloc(C.byref(rp), C.byref(B.cost_params(bad)), C.byref(io), None) == B.EINVAL
+    r = {**case["robot"], "links": [dict(L) for L in case["robot"]["links"]]}
+    r["links"][2]["mass"] = -1.0
+    assert lib.mppi_update_noalloc(C.byref(B.robot_params(r)), C.byref(B.cost_params(case["cost"])),
+                                   C.byref(io), None) == B.EINVAL
+    assert lib.mppi_update_noalloc(C.byref(rp), C.byref(B.cost_params(case["cost"])), None, None) == B.EINVAL
+    big = dict(case["cost"], K=65536, T=64)
+    assert lib.mppi_update_noalloc(C.byref(rp), C.byref(B.cost_params(big)), C.byref(io), None) == B.ESCRATCH
+    assert "workspace" in B.strerror(B.ESCRATCH)
