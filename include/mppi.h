@@ -8,9 +8,11 @@
  *   - K perturbed torque sequences v_k,t = u_t + du_k,t (Eq. 2, Sec. III-A
  *     "torque-level sampling"), du drawn per (tick, sample, step, joint)
  *     from Philox4x32-10 + Box-Muller;
- *   - each rolled out for T steps through 7-DoF forward dynamics (Eqs. 5-6,
- *     computed with the articulated-body algorithm) and the semi-implicit
- *     Euler step written in Eq. 7;
+ *   - each rolled out for T steps through 7-DoF forward dynamics (Eqs. 5-6;
+ *     on the default launch shape from composite-rigid-body inertias and an
+ *     LDL^T solve with eight lanes per sample, on the per-lane shapes and in
+ *     batches by the articulated-body algorithm, see mppi_set_launch) and
+ *     the semi-implicit Euler step written in Eq. 7;
  *   - the running cost of Eqs. 9-14 (EE position/orientation, dynamically
  *     consistent EE force, joint/torque limit penalties) at every step and
  *     a terminal cost phi(x_T) (Eq. 3);
@@ -52,9 +54,12 @@ typedef enum {
 } mppi_status;
 
 typedef enum { MPPI_FP32 = 0, MPPI_FP64 = 1 } mppi_precision;
-/* Forward dynamics of the rollouts: the articulated-body algorithm
- * (default), or the paper's own route, M formed by the Jacobian sum of
- * Eq. 8 and h from the Jacobian time derivatives, solved by Cholesky. */
+/* Forward dynamics of the rollouts: MPPI_DYN_ABA (default) is the
+ * recursive route (the articulated-body algorithm on the per-lane launch
+ * shapes and in batches; on the eight-lane launch shape the same
+ * quantities from composite-rigid-body inertias and an LDL^T solve), or
+ * the paper's own route, M formed by the Jacobian sum of Eq. 8 and h from
+ * the Jacobian time derivatives, solved by Cholesky. */
 typedef enum { MPPI_DYN_ABA = 0, MPPI_DYN_EXPLICIT_M = 1 } mppi_dynamics;
 typedef enum { MPPI_EXT_NONE = 0, MPPI_EXT_CONST = 1, MPPI_EXT_WALL = 2 } mppi_ext_mode;
 
