@@ -48,6 +48,26 @@ def device_update(solver, case, seed, tick, precision=B.FP32, stage=False, costs
             "status": int(io["status"].cpu().numpy()[0]), "io": io}
 
 
+def check_noise_fp32(E_gpu, E_ref, sigma, label=""):
+    """FP32 perturbations [K, T, 7] of i.i.d. sampling against the oracle's
+    FP64 ones from the same Philox bits, element by element.  The kernels
+    form the radius uniform u = (x + 1) 2^-32 in FP32, which near u = 1 is
+    resolved to 2^-24 only, so the Box-Muller radius r = sqrt(-2 ln u)
+    carries an absolute error of about 2^-24 / r (at most sqrt(2^-23),
+    when u rounds to 1); with |z| <= r that is at most 2^-24 / |z|.  A
+    normal z of the oracle may therefore differ by min(2^-22 / |z|, 4e-4)
+    (twice the estimate) plus 2e-5 for the rest of the FP32 arithmetic
+    (hardware log2, sin and cos), scaled by sigma_j."""
+    sig = np.asarray(sigma, dtype=float)[:E_ref.shape[-1]]
+    z = np.abs(E_ref) / np.where(sig > 0, sig, 1.0)
+    tol = 2e-5 + sig * np.minimum(2.0 ** -22 / np.maximum(z, 1e-30), 4e-4)
+    diff = np.abs(E_gpu - E_ref)
+    i = np.unravel_index(int(np.argmax(diff / tol)), diff.shape)
+    print("%s: noise max |d| %.3g; tightest element |d| %.3g at |du| %.3g (bound %.3g)"
+          % (label, diff.max(), diff[i], abs(E_ref[i]), tol[i]))
+    assert diff[i] <= tol[i], (label, diff[i], tol[i])
+
+
 def cost_rel_err(S_gpu, S_ref):
     return np.abs(S_gpu - S_ref) / np.maximum(np.abs(S_ref), 1e-9)
 

@@ -9,8 +9,8 @@ Score: the realised closed-loop cost, the running cost of Eqs. 9-14 of the
 commanded torque at every tick's measured state (FP64 oracle), summed over
 the 200 ticks, per episode; mean and median over the episodes.  The test
 requires the proposal to lower the median at K=256 (the gain over the
-method without it) and reports every ratio, including learned@K /
-plain@4096.
+method without it) and the mean at K=256 and K=1024 to come within 2 % of
+plain MPPI at K=4096 (or below it), and reports every ratio.
 """
 import time
 
@@ -75,4 +75,8 @@ def test_learned_proposal_gain(ora):
     # (median over the held-out episodes: a few diverging episodes dominate
     # the mean of every variant)
     assert np.median(scores["learned256"]) < np.median(scores["plain256"])
+    # the target: with the proposal, K <= 1024 samples reach the realised
+    # cost of plain MPPI at K = 4096 within 2 % (mean over the episodes)
+    for name in ("learned1024", "learned256"):
+        assert scores[name].mean() <= 1.02 * ref, (name, scores[name].mean() / ref)
     net.close()

@@ -2,9 +2,10 @@
 accumulation) against the FP64 oracle with the same BF16 rounding points
 (oracle/mlp.py, mirror=True), through the C ABI.
 
-Bars: outputs within 1e-3 of the output scale (max |y|); gradients within
-1e-2 relative (norm of the error over the norm of the oracle gradient, per
-weight matrix and per bias vector); Adam steps on the GPU's own gradient
+Bars: outputs within 1e-3 of the output scale (max |y|); gradient entries
+within 5e-3 of their block's largest oracle entry (per weight matrix and
+per bias vector), and each block's error norm within 1e-2 of the oracle
+gradient's norm; Adam steps on the GPU's own gradient
 within FP32 rounding of the oracle's.  Rows past the batch, padded features
 and ragged batch sizes are covered.
 """
@@ -18,7 +19,8 @@ from gpu_util import torch_dev
 
 pytestmark = pytest.mark.gpu
 Y_TOL = 1e-3
-G_TOL = 1e-2
+G_TOL = 1e-2          # relative norm of each block's gradient error
+G_ELEM_TOL = 5e-3     # each gradient entry, relative to its block's largest (observed <= 1e-3)
 
 
 def f32(a):
@@ -37,8 +39,19 @@ def make(workloads, max_batch, seed=1):
 
 
 def check_grad(g_gpu, g_ref, label):
-    for w, _, b in om.layer_slices():
-        for sl, name in ((w, "W"), (b, "b")):
+    """Element by element: every entry of each weight matrix and bias
+    vector within G_ELEM_TOL of that block's largest oracle entry (a wrong
+    tile, lane or padded-edge mapping shows up in single entries); the worst
+    entry is printed with its (layer, row, column).  Then the relative norm
+    of each block's error as a second bar."""
+    for layer, (w, shape, b) in enumerate(om.layer_slices()):
+        for sl, name, shp in ((w, "W", shape), (b, "b", (shape[0],))):
+            d = np.abs(g_gpu[sl] - g_ref[sl])
+            scale = np.abs(g_ref[sl]).max()
+            worst = np.unravel_index(int(np.argmax(d)), shp)
+            print("%s: layer %d %s worst entry %s |dg| = %.3g of max |g| %.3g (%.2g)"
+                  % (label, layer + 1, name, tuple(int(x) for x in worst), d.max(), scale, d.max() / scale))
+            assert d.max() <= G_ELEM_TOL * scale, (label, layer + 1, name, worst, d.max() / scale)
             err = np.linalg.norm(g_gpu[sl] - g_ref[sl]) / np.linalg.norm(g_ref[sl])
             assert err <= G_TOL, (label, name, sl, err)
 
