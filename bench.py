@@ -361,7 +361,7 @@ def batch_bench(B, cases, torch, dev, ticks):
           "status": torch.zeros(len(cases), dtype=torch.int32, device=dev),
           "seed": torch.tensor([c["seed"] for c in cases], dtype=torch.int64, device=dev)}
     stream = torch.cuda.current_stream()
-    wpg, groups, _ = batch.autotune(io, reps=3, stream=stream)
+    wpg, groups, tune_ms = batch.autotune(io, reps=3, stream=stream)
     batch.graph_capture(io)
     batch.set_tick(0)
     for _ in range(3):
@@ -390,12 +390,45 @@ def batch_bench(B, cases, torch, dev, ticks):
             "ticks_per_s": ticks / elapsed, "tick_ms": tick_ms, "ticks": ticks,
             "problem_updates_per_s": len(cases) * ticks / elapsed,
             "rollout_steps_per_s": sample_steps / (tick_ms * 1e-3),
-            "launch": {"waves_per_group": wpg, "groups": groups, "graph": True},
+            "launch": {"waves_per_group": wpg, "groups": groups, "graph": True,
+                       "lanes_per_sample": 8 if wpg == 8 else 1},
+            "autotune_ms": {"%s_waves%d" % ("lanes8" if w == 8 else "wpg%d" % w, v): round(t, 4)
+                            for (w, v), t in zip([(w, v) for w in (1, 2, 4, 8) for v in (256, 512, 1024, 2048)],
+                                                 tune_ms)},
             "roofline": {"bound": "alu", "achieved": flops / (tick_ms * 1e-3) / 1e12,
                          "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": flops / (tick_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
                          "traffic": profiled_traffic("batch_kernel_w%dx%d" % (wpg, groups)),
-                         "kernel": "batch_kernel", "flops_per_launch": flops}}
+                         "kernel": "batch_group_kernel" if wpg == 8 else "batch_kernel",
+                         "flops_per_launch": flops}}
+
+
+def small_batch_bench(B, cases, torch, dev, reps=50):
+    """A latency-bound batch (the first 8 problems of batch64 with K capped
+    at 1024): the tick at one and at eight lanes per sample, each at the
+    autotuner's best workgroup count for that lane count."""
+    import numpy as np
+    cases = [dict(c, cost=dict(c["cost"], K=min(c["cost"]["K"], 1024))) for c in cases[:8]]
+    batch = B.Batch([(c["robot"], c["cost"]) for c in cases])
+    f64 = dict(dtype=torch.float64, device=dev)
+    U = np.zeros((batch.u_total // 7, 7))
+    for p, c in enumerate(cases):
+        U[batch.u_off[p] // 7: batch.u_off[p] // 7 + batch.T[p]] = np.asarray(c["U_nom"])[:batch.T[p]]
+    io = {"q": torch.tensor(np.array([c["q0"] for c in cases]), **f64),
+          "qd": torch.tensor(np.array([c["qd0"] for c in cases]), **f64),
+          "target": torch.tensor(np.array([B.target_vector(c["target"]) for c in cases]), **f64),
+          "U_nominal": torch.tensor(U, **f64), "U_new": torch.empty(U.shape, **f64),
+          "costs": torch.empty(batch.k_total, dtype=torch.float32, device=dev),
+          "seed": torch.tensor([c["seed"] for c in cases], dtype=torch.int64, device=dev)}
+    stream = torch.cuda.current_stream()
+    wpg, groups, tune_ms = batch.autotune(io, reps=5, stream=stream)
+    one = min(tune_ms[:12])
+    eight = min(tune_ms[12:])
+    batch.close()
+    return {"workload": "batch64[0:8] with K <= 1024: %d sample-steps per tick"
+                        % sum(c["cost"]["K"] * c["cost"]["T"] for c in cases),
+            "tick_ms_one_lane_per_sample": one, "tick_ms_eight_lanes_per_sample": eight,
+            "autotuned": {"waves_per_group": wpg, "groups": groups}}
 
 
 def graph_update_bench(solver, io, torch, reps=200):
@@ -562,6 +595,7 @@ def main():
     out["roofline"]["per_step_us_upper"] = 1e3 * float(np.mean(roll_ms)) / (T + 1)
     if args.batch_ticks > 0:
         out["batch"] = batch_bench(B, inputs.load()["batch64"], torch, dev, args.batch_ticks)
+        out["batch_small"] = small_batch_bench(B, inputs.load()["batch64"], torch, dev)
     if not args.no_mlp:
         out["mlp"] = mlp_bench(B, inputs, case["robot"], torch, dev)
     out["collision"] = collision_bench(B, inputs.load()["collision_k4096"][0], torch, dev)

@@ -223,6 +223,26 @@ typedef struct {
  * The caller synchronises.  Errors: MPPI_EINVAL, MPPI_EDEVICE. */
 int mppi_update_async(mppi_handle_t h, const mppi_device_io* io, void* stream);
 
+/* Picks the launch shape of mppi_set_launch (8, 2 or 1) by timing updates
+ * of this problem on `stream` with the caller's io (device pointers as for
+ * mppi_update_async; its outputs are written by the timing runs; a
+ * representative state gives representative times): per shape one untimed
+ * update, then about budget_ms / 3 of timed ones.  Sets the handle's shape,
+ * returns it in *best_launch (may be NULL) and the mean update times in
+ * times_ms[3] (launch 8, 2, 1; may be NULL).  With an autotune cache the
+ * choice is stored under (architecture, K, T, precision, dynamics route,
+ * cost terms, iterations) and reused without timing (times_ms set to -1).
+ * Errors: MPPI_EINVAL (null, budget_ms < 1), MPPI_EDEVICE. */
+int mppi_autotune(mppi_handle_t h, const mppi_device_io* io, int budget_ms, void* stream,
+                  int* best_launch, float* times_ms);
+
+/* Autotune cache of mppi_autotune and mppi_batch_autotune: a JSON file at
+ * `path` (one object, one entry per key: the chosen shape and its time),
+ * read when a tuner starts and rewritten (via a temporary file and a
+ * rename) when it stores a new choice.  NULL or "" turns the cache off (the
+ * default).  Process-wide; the string is copied. */
+int mppi_set_autotune_cache(const char* path);
+
 /* The update of mppi_update_async without allocating anything, for
  * callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc).  No handle: robot
@@ -302,14 +322,26 @@ typedef struct {
 /* Enqueues one batched update with Philox tick `tick` on `stream`. */
 int mppi_batch_update_async(mppi_batch_t b, const mppi_batch_io* io, uint64_t tick, void* stream);
 
-/* Launch shape: waves per workgroup (1, 2 or 4) and workgroup count. */
+/* Launch shape: waves per workgroup and workgroup count.  1, 2 or 4: one
+ * lane per sample, every wave takes 64-sample tiles from the work list (the
+ * articulated-body rollouts); 8: eight lanes per sample, a workgroup of
+ * eight waves takes a 64-sample tile together (eight samples per wave, the
+ * eight-lane arithmetic of mppi_set_launch(h, 8) with each step's dynamics
+ * and cost on one wave).  Both write the same partials of Eq. 4, so they
+ * give the same U_new to FP32 rounding. */
 int mppi_batch_set_launch(mppi_batch_t b, int waves_per_group, int groups);
 
 /* Times every launch shape of the built-in search space (waves per
- * workgroup {1, 2, 4} x resident waves {256, 512, 1024, 2048}) with `reps`
- * updates each on `stream`, keeps the fastest and returns it.  times_ms
- * (may be NULL) receives the 12 mean times in search order.  The io buffers
- * are written by the timing runs. */
+ * workgroup {1, 2, 4, 8}, i.e. one lane per sample in workgroups of 1, 2 or
+ * 4 waves, or eight lanes per sample, x resident waves {256, 512, 1024,
+ * 2048}) with `reps` updates each on `stream`, keeps the fastest and
+ * returns it.  times_ms (may be NULL) receives the 16 mean times in search
+ * order.  The io buffers are written by the timing runs.  With an autotune
+ * cache (mppi_set_autotune_cache) the choice is stored under a key of the
+ * device architecture, the batch's total sample-steps (power-of-two
+ * bucket), its horizon range, the precision, the union of its cost terms
+ * and the iteration count; a later call with the same key takes the stored
+ * shape without timing and sets every times_ms entry to -1. */
 int mppi_batch_autotune(mppi_batch_t b, const mppi_batch_io* io, int reps, void* stream,
                         int* best_waves_per_group, int* best_groups, float* times_ms);
 

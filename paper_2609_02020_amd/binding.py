@@ -179,12 +179,21 @@ def lib():
         L.mppi_plant_step_async.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int, vp]
         L.mppi_warm_start_async.argtypes = [vp, vp, vp, C.c_double, vp]
         L.mppi_set_launch.argtypes = [vp, C.c_int]
+        L.mppi_autotune.argtypes = [vp, P(DeviceIO), C.c_int, vp, P(C.c_int), P(C.c_float)]
+        L.mppi_set_autotune_cache.argtypes = [C.c_char_p]
         L.mppi_select_nominal_async.argtypes = [vp, P(DeviceIO), vp, vp, vp]
         L.mppi_strerror.argtypes = [C.c_int]
         L.mppi_strerror.restype = C.c_char_p
         L.mppi_version.restype = C.c_char_p
         _lib = L
     return _lib
+
+
+def set_autotune_cache(path):
+    """Autotune cache file of both tuners (mppi_set_autotune_cache); None: off."""
+    st = lib().mppi_set_autotune_cache(None if path is None else str(path).encode())
+    if st:
+        raise MppiError(st, "mppi_set_autotune_cache")
 
 
 def strerror(status: int) -> str:
@@ -329,6 +338,17 @@ class Solver:
         if st:
             raise MppiError(st, "mppi_plant_step_async")
 
+    def autotune(self, io: dict, budget_ms: int = 30, stream=None):
+        """Times launch shapes 8, 2 and 1 on io (mppi_autotune), keeps the
+        fastest; returns (shape, [times in ms, -1 when taken from the cache])."""
+        d = self._io(io)
+        best = C.c_int()
+        times = (C.c_float * 3)()
+        st = self._lib.mppi_autotune(self._h, C.byref(d), int(budget_ms), _stream_ptr(stream), C.byref(best), times)
+        if st:
+            raise MppiError(st, "mppi_autotune")
+        return best.value, list(times)
+
     def set_launch(self, waves_per_group: int):
         """Launch shape of the updates (mppi_set_launch): 1 or 2 waves per 64
         samples, or 8 lanes per sample."""
@@ -450,7 +470,7 @@ class Batch:
     def autotune(self, io: dict, reps: int = 3, stream=None):
         d = self._io(io)
         w, g = C.c_int(), C.c_int()
-        times = (C.c_float * 12)()
+        times = (C.c_float * 16)()
         st = self._lib.mppi_batch_autotune(self._h, C.byref(d), int(reps), _stream_ptr(stream),
                                            C.byref(w), C.byref(g), times)
         if st:

@@ -741,6 +741,179 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(COLL ? 1
     }
 }
 
+// Batched update with eight lanes per sample (mppi_batch_set_launch(b, 8,
+// groups)): a workgroup of eight waves takes one 64-sample tile of the work
+// list at a time, wave w the samples 8 w .. 8 w + 7 of the tile, each on a
+// group of eight lanes running group_rollout (group.hpp; the dynamics and
+// the cost of a step on one wave, the single-problem eight-lane update's
+// arithmetic without its two-wave split).  The tile's Eq. 4 partial (noise
+// regenerated per lane from the Philox counters, reduced over the eight
+// samples of a wave by shuffles and over the waves through LDS), the
+// problem counters, the merge by the workgroup that completes a problem and
+// the queue reset by the last workgroup out follow batch_kernel at
+// workgroup granularity: both kernels write the same partials and share
+// the queue and counters (they never run concurrently on one batch).
+constexpr int kBatchGroupWaves = 8;
+
+template <typename A>
+__device__ void group_tile_partial(const float* sS, A* wsm, A (*vs)[kGroupSteps * 8], int tid, int lane, int wave,
+                                   int j, int grp, int T, double lambda, const CostM<float>& C,
+                                   const GroupLink<float>& L, uint64_t seed, uint32_t tick, uint32_t k, A* part)
+{
+    const A inf = A(INFINITY), il = A(1) / A(lambda);
+    A m = inf;
+    for (int i = 0; i < 64; ++i) m = fmin(m, sS[i] < INFINITY ? A(sS[i]) : inf);
+    if (tid < 64) wsm[tid] = sS[tid] < INFINITY ? exp((m - A(sS[tid])) * il) : A(0);
+    __syncthreads();
+    const A wgt = wsm[grp];
+    float dr = 0.0f;
+    for (int t0 = 0; t0 < T; t0 += kGroupSteps) {
+        const int nt = min(kGroupSteps, T - t0);
+        for (int tt = 0; tt < nt; ++tt) {
+            const int t = t0 + tt;
+            dr = group_noise_step(C, L, group_normal<float>(seed, tick, k, (uint32_t)t, j), dr, t);
+            A x = wgt * A(dr);
+            x += __shfl_xor(x, 8);
+            x += __shfl_xor(x, 16);
+            x += __shfl_xor(x, 32);
+            if (lane < 8) vs[wave][tt * 8 + lane] = x;
+        }
+        __syncthreads();
+        for (int r = tid; r < nt * NJ; r += 64 * kBatchGroupWaves) {
+            const int tt = r / NJ, jj = r % NJ;
+            A acc = A(0);
+#pragma unroll
+            for (int w = 0; w < kBatchGroupWaves; ++w) acc += vs[w][tt * 8 + jj];
+            part[2 + (t0 + tt) * NJ + jj] = acc;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        A st = A(0);
+        for (int i = 0; i < 64; ++i) st += wsm[i];
+        part[0] = m;
+        part[1] = st;
+    }
+}
+
+template <bool COLL>
+__global__ __launch_bounds__(64 * kBatchGroupWaves) void batch_group_kernel(
+    const BatchProblem* __restrict__ probs, const ModelM<float>* __restrict__ models,
+    const int2* __restrict__ items, int nitems, unsigned int* queue, unsigned int* done, unsigned int* counters,
+    const double* __restrict__ q, const double* __restrict__ qd, const double* __restrict__ target,
+    const double* U_nom, double* U_new, double* U_shift, float* __restrict__ costs, int* __restrict__ status,
+    const uint64_t* __restrict__ seeds, const uint64_t* __restrict__ tickp, int iter, int niter,
+    double* __restrict__ parts)
+{
+    __shared__ float gx[kBatchGroupWaves * 8][kGxCount];
+    __shared__ float Us[kMaxTBatch * NJ];
+    __shared__ CostM<float> Csh;
+    __shared__ float sS[64];
+    __shared__ double wsm[64];
+    __shared__ double vs[kBatchGroupWaves][kGroupSteps * 8];
+    __shared__ int sItem, sDone;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j = lane & 7, grp = wave * 8 + (lane >> 3);   // sample grp of the tile
+    const uint32_t tick = (uint32_t)(*tickp * (uint64_t)niter + (uint64_t)iter);
+    for (;;) {
+        if (tid == 0) sItem = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int item = sItem;
+        if (item >= nitems) break;
+        const int2 it = items[item];
+        const BatchProblem& Pb = probs[it.x];
+        const int T = Pb.T, K = Pb.K;
+        if (wave == 0) wave_copy(&Csh, Pb.cost, sizeof(CostM<float>), lane);
+        for (int i = tid; i < T * NJ; i += 64 * kBatchGroupWaves) Us[i] = float(U_nom[Pb.u_off + i]);
+        __syncthreads();
+        // problem p's model through the restrict-qualified argument at a
+        // uniform index (scalar loads), as in batch_kernel
+        const ModelM<float>& M = models[it.x];
+        const CostM<float>& C = Csh;
+        const int k = it.y * 64 + grp;
+        const uint64_t seed = seeds[it.x];
+        GroupLink<float> L;
+        group_link(M, C, j, L);
+        const float grav[3] = {M.g[0], M.g[1], M.g[2]};
+        TargetM<float> tg;
+        make_target(target + (size_t)it.x * 13, tg);
+        float q0 = 0.0f, qd0 = 0.0f, te = 0.0f;
+        {
+            float qa[NJ], qda[NJ], tea[NJ];
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) {
+                qa[i] = float(q[it.x * NJ + i]);
+                qda[i] = float(qd[it.x * NJ + i]);
+                tea[i] = 0.0f;
+            }
+            if (C.ext_mode == EXTW_CONST) const_ext_torque(M, C, qa, tea);
+#pragma unroll
+            for (int i = 0; i < NJ; ++i)
+                if (i == j) { q0 = qa[i]; qd0 = qda[i]; te = tea[i]; }
+        }
+        // every group rolls out (samples past K too, storing nothing), so
+        // the DPP moves always see a converged wave
+        const DevGroup g{j, gx[grp]};
+        float S;
+        if (COLL && Pb.coll)
+            S = Pb.force ? group_rollout<float, true, DevGroup, float, true>(g, L, C, tg, grav, q0, qd0, te, Us, T,
+                                                                              seed, tick, (uint32_t)k, nullptr, 0, nullptr, 0, true)
+                         : group_rollout<float, false, DevGroup, float, true>(g, L, C, tg, grav, q0, qd0, te, Us, T,
+                                                                               seed, tick, (uint32_t)k, nullptr, 0, nullptr, 0, true);
+        else
+            S = Pb.force ? group_rollout<float, true, DevGroup, float>(g, L, C, tg, grav, q0, qd0, te, Us, T, seed,
+                                                                       tick, (uint32_t)k, nullptr, 0, nullptr, 0, true)
+                         : group_rollout<float, false, DevGroup, float>(g, L, C, tg, grav, q0, qd0, te, Us, T, seed,
+                                                                        tick, (uint32_t)k, nullptr, 0, nullptr, 0, true);
+        float sv = INFINITY;
+        if (k < K) {
+            sv = finite_(S) ? S : INFINITY;
+            if (j == 0 && costs) costs[Pb.k_off + k] = sv;
+        }
+        if (j == 0) sS[grp] = sv;
+        __syncthreads();
+        double* pbase = parts + Pb.part_off;
+        const int P = 2 + T * NJ;
+        if (Pb.acc64)
+            group_tile_partial<double>(sS, wsm, vs, tid, lane, wave, j, grp, T, Pb.lambda, C, L, seed, tick,
+                                       (uint32_t)k, pbase + (size_t)it.y * P);
+        else
+            group_tile_partial<float>(sS, reinterpret_cast<float*>(wsm),
+                                      reinterpret_cast<float (*)[kGroupSteps * 8]>(vs), tid, lane, wave, j, grp, T,
+                                      Pb.lambda, C, L, seed, tick, (uint32_t)k,
+                                      reinterpret_cast<float*>(pbase) + (size_t)it.y * P);
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) sDone = (int)atomicAdd(&counters[it.x], 1u);
+        __syncthreads();
+        if (sDone == Pb.ntiles - 1) {
+            __threadfence();
+            if (wave == 0) {
+                const double* un = U_nom + Pb.u_off;
+                double* uw = U_new + Pb.u_off;
+                double* us = U_shift ? U_shift + Pb.u_off : nullptr;
+                int* st = status ? status + it.x : nullptr;
+                if (Pb.acc64) wave_merge<double>(pbase, Pb.ntiles, T, Pb.lambda, un, uw, us, st, lane, wsm);
+                else
+                    wave_merge<float>(reinterpret_cast<const float*>(pbase), Pb.ntiles, T, Pb.lambda, un, uw, us,
+                                      st, lane, reinterpret_cast<float*>(wsm));
+                if (lane == 0) counters[it.x] = 0u;
+            }
+        }
+        __syncthreads();
+    }
+    // the last workgroup out resets the queue for the next launch
+    if (tid == 0) {
+        __threadfence();
+        const unsigned out = atomicAdd(done, 1u);
+        if (out == gridDim.x - 1) {
+            *queue = 0u;
+            *done = 0u;
+            __threadfence();
+        }
+    }
+}
+
 __global__ void advance_tick_kernel(uint64_t* tick)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) *tick += 1;
@@ -1106,10 +1279,20 @@ template <int W, bool COLL> static hipError_t batch_t(const BatchArgs& a, int gr
     return hipGetLastError();
 }
 
+template <bool COLL> static hipError_t batch_group_t(const BatchArgs& a, int groups, hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_group_kernel<COLL>), dim3(groups), dim3(64 * kBatchGroupWaves), 0, s,
+                       (const BatchProblem*)a.probs, (const ModelM<float>*)a.models, (const int2*)a.items, a.nitems,
+                       a.queue, a.done, a.counters, a.q, a.qd, a.target, a.U_nom, a.U_new, a.U_shift, a.costs,
+                       a.status, a.seeds, a.tick, a.iter, a.niter, a.parts);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch(const BatchArgs& a, int waves_per_group, int groups, hipStream_t s)
 {
     if (groups < 1 || a.nitems < 1) return hipErrorInvalidValue;
     switch (waves_per_group) {
+    case 8: return a.collision ? batch_group_t<true>(a, groups, s) : batch_group_t<false>(a, groups, s);
     case 1: return a.collision ? batch_t<1, true>(a, groups, s) : batch_t<1, false>(a, groups, s);
     case 2: return a.collision ? batch_t<2, true>(a, groups, s) : batch_t<2, false>(a, groups, s);
     case 4: return a.collision ? batch_t<4, true>(a, groups, s) : batch_t<4, false>(a, groups, s);

@@ -3,12 +3,17 @@
 // All arithmetic of the method runs in the kernels of kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
+#include <string>
+#include <unistd.h>
 
 #include "launch.hpp"
 #include "model_prep.hpp"
@@ -279,6 +284,92 @@ int check_io(const mppi_solver* h, const mppi_device_io* io, bool need_out)
     return MPPI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// autotune cache: a JSON object in a file, one entry per line,
+//   "<key>": {"waves_per_group": w, "groups": g, "ms": t},
+// keyed by the device architecture, the problem sizes, the precision and
+// the cost terms; read and rewritten whole (write to a temporary, rename)
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+    int wpg = 0, groups = 0;
+    double ms = 0;
+};
+std::mutex g_tune_mu;
+std::string g_tune_path;   // empty: no cache
+
+std::string arch_name()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// cost terms of a problem as bits: force, orientation, wall, constant
+// wrench, collision, correlated noise
+unsigned cost_mask(const mppi_cost_params& c)
+{
+    unsigned m = has_force(c) ? 1u : 0u;
+    if (c.W_ori[0] != 0.0 || c.W_ori[1] != 0.0 || c.W_ori[2] != 0.0) m |= 2u;
+    if (c.ext_mode == MPPI_EXT_WALL) m |= 4u;
+    if (c.ext_mode == MPPI_EXT_CONST) m |= 8u;
+    if (c.n_pairs > 0) m |= 16u;
+    if (c.noise_rho > 0.0) m |= 32u;
+    return m;
+}
+
+std::map<std::string, TuneEntry> tune_read(const std::string& path)
+{
+    std::map<std::string, TuneEntry> out;
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return out;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        const char* a = std::strchr(line, '"');
+        const char* b = a ? std::strchr(a + 1, '"') : nullptr;
+        if (!a || !b) continue;
+        TuneEntry e;
+        if (std::sscanf(b + 1, " : {\"waves_per_group\": %d, \"groups\": %d, \"ms\": %lf", &e.wpg, &e.groups,
+                        &e.ms) == 3)
+            out[std::string(a + 1, b)] = e;
+    }
+    std::fclose(f);
+    return out;
+}
+
+bool tune_lookup(const std::string& key, TuneEntry* e)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_tune_path.empty()) return false;
+    const auto m = tune_read(g_tune_path);
+    const auto it = m.find(key);
+    if (it == m.end()) return false;
+    *e = it->second;
+    return true;
+}
+
+void tune_store(const std::string& key, const TuneEntry& e)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_tune_path.empty()) return;
+    auto m = tune_read(g_tune_path);
+    m[key] = e;
+    const std::string tmp = g_tune_path + ".tmp" + std::to_string((long)getpid());
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto& kv : m)
+        std::fprintf(f, "\"%s\": {\"waves_per_group\": %d, \"groups\": %d, \"ms\": %.6f}%s\n", kv.first.c_str(),
+                     kv.second.wpg, kv.second.groups, kv.second.ms, ++i < m.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    const bool ok = std::fclose(f) == 0;
+    if (ok) std::rename(tmp.c_str(), g_tune_path.c_str());
+    else std::remove(tmp.c_str());
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -416,6 +507,71 @@ int mppi_set_launch(mppi_handle_t h, int waves_per_group)
 {
     if (!h || (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 8)) return MPPI_EINVAL;
     h->waves_per_group = waves_per_group;
+    return MPPI_OK;
+}
+
+int mppi_set_autotune_cache(const char* path)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_path = path ? path : "";
+    return MPPI_OK;
+}
+
+int mppi_autotune(mppi_handle_t h, const mppi_device_io* io, int budget_ms, void* stream, int* best_launch,
+                  float* times_ms)
+{
+    int st = check_io(h, io, true);
+    if (st) return st;
+    if (budget_ms < 1) return MPPI_EINVAL;
+    const int shapes[3] = {8, 2, 1};
+    char key[256];
+    std::snprintf(key, sizeof key, "solver|%s|K%d|T%d|%s|dyn%d|mask%02x|it%d", arch_name().c_str(), h->cost.K,
+                  h->cost.T, h->cost.precision == MPPI_FP64 ? "fp64" : "fp32", h->cost.dynamics, cost_mask(h->cost),
+                  iterations_of(h->cost));
+    TuneEntry e;
+    if (tune_lookup(key, &e) && (e.wpg == 1 || e.wpg == 2 || e.wpg == 8)) {
+        h->waves_per_group = e.wpg;
+        if (best_launch) *best_launch = e.wpg;
+        if (times_ms)
+            for (int i = 0; i < 3; ++i) times_ms[i] = -1.0f;
+        return MPPI_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MPPI_EDEVICE;
+    void* noise = io->noise ? io->noise : h->d_noise;
+    void* costs = io->costs ? io->costs : h->d_costs;
+    const int keep = h->waves_per_group;
+    float best = 1e30f;
+    int bw = keep;
+    for (int i = 0; i < 3 && !st; ++i) {
+        h->waves_per_group = shapes[i];
+        // one untimed update, one timed to size the repetitions, then the
+        // shape's share of the budget
+        float ms = 0;
+        if (update_enqueue(h, io, s, noise, costs, true, io->noise != nullptr) ||
+            hipEventRecord(e0, s) != hipSuccess || update_enqueue(h, io, s, noise, costs, true, io->noise != nullptr) ||
+            hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = MPPI_EDEVICE; break; }
+        const int reps = std::max(1, std::min(1000, (int)(budget_ms / 3.0f / std::max(ms, 1e-3f))));
+        if (hipEventRecord(e0, s) != hipSuccess) { st = MPPI_EDEVICE; break; }
+        for (int r = 0; r < reps && !st; ++r)
+            if (update_enqueue(h, io, s, noise, costs, true, io->noise != nullptr)) st = MPPI_EDEVICE;
+        if (st || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = MPPI_EDEVICE; break; }
+        ms /= reps;
+        if (times_ms) times_ms[i] = ms;
+        if (ms < best) { best = ms; bw = shapes[i]; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->waves_per_group = st ? keep : bw;
+    if (st) return st;
+    if (best_launch) *best_launch = bw;
+    e.wpg = bw;
+    e.groups = 0;
+    e.ms = best;
+    tune_store(key, e);
     return MPPI_OK;
 }
 
@@ -583,8 +739,8 @@ const char* mppi_version(void) { return "mppi-gfx950 0.1"; }
 // ---------------------------------------------------------------------------
 // batched problems
 // ---------------------------------------------------------------------------
-#include <algorithm>
 #include <vector>
+
 
 struct mppi_batch {
     int n = 0;
@@ -834,8 +990,8 @@ int mppi_batch_warm_start_async(mppi_batch_t b, const double* U_new, double* U_o
 
 int mppi_batch_set_launch(mppi_batch_t b, int waves_per_group, int groups)
 {
-    if (!b || (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4) || groups < 1 ||
-        groups > (1 << 16))
+    if (!b || (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4 && waves_per_group != 8) ||
+        groups < 1 || groups > (1 << 16))
         return MPPI_EINVAL;
     b->wpg = waves_per_group;
     b->groups = groups;
@@ -865,15 +1021,43 @@ int mppi_batch_autotune(mppi_batch_t b, const mppi_batch_io* io, int reps, void*
     if (st) return st;
     if (reps < 1) return MPPI_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    const int wpgs[3] = {1, 2, 4};
+    constexpr int kShapes = 16;
+    const int wpgs[4] = {1, 2, 4, 8};
     const int waves[4] = {256, 512, 1024, 2048};
+    // cache key: architecture, total sample-steps (power-of-two bucket),
+    // horizon range, precision, union of the problems' cost terms, iterations
+    long long kt = 0;
+    int tmin = 1 << 30, tmax = 0;
+    unsigned mask = 0;
+    for (int p = 0; p < b->n; ++p) {
+        kt += (long long)b->cost[p].K * b->cost[p].T;
+        tmin = std::min(tmin, b->cost[p].T);
+        tmax = std::max(tmax, b->cost[p].T);
+        mask |= cost_mask(b->cost[p]);
+    }
+    int lg = 0;
+    while ((2LL << lg) <= kt) ++lg;
+    char key[256];
+    std::snprintf(key, sizeof key, "batch|%s|kt2^%d|T%d-%d|fp32|mask%02x|it%d", arch_name().c_str(), lg, tmin, tmax,
+                  mask, b->iterations);
+    TuneEntry e;
+    if (tune_lookup(key, &e) && (e.wpg == 1 || e.wpg == 2 || e.wpg == 4 || e.wpg == 8) && e.groups >= 1 &&
+        e.groups <= (1 << 16)) {
+        b->wpg = e.wpg;
+        b->groups = e.groups;
+        if (best_wpg) *best_wpg = e.wpg;
+        if (best_groups) *best_groups = e.groups;
+        if (times_ms)
+            for (int i = 0; i < kShapes; ++i) times_ms[i] = -1.0f;
+        return MPPI_OK;
+    }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MPPI_EDEVICE;
     BatchArgs a = batch_args(b, io, b->d_tick + 1);
     float best = 1e30f;
     int bw = b->wpg, bg = b->groups, idx = 0;
     st = MPPI_OK;
-    for (int wi = 0; wi < 3 && !st; ++wi)
+    for (int wi = 0; wi < 4 && !st; ++wi)
         for (int vi = 0; vi < 4 && !st; ++vi, ++idx) {
             const int w = wpgs[wi], g = waves[vi] / w;
             // one untimed launch, then `reps` timed ones
@@ -896,6 +1080,10 @@ int mppi_batch_autotune(mppi_batch_t b, const mppi_batch_io* io, int reps, void*
     b->groups = bg;
     if (best_wpg) *best_wpg = bw;
     if (best_groups) *best_groups = bg;
+    e.wpg = bw;
+    e.groups = bg;
+    e.ms = best;
+    tune_store(key, e);
     return MPPI_OK;
 }
 

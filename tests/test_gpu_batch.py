@@ -167,8 +167,9 @@ def test_autotune_picks_a_shape(workloads):
     io = batch_io(batch, cases, torch, dev)
     w, g, times = batch.autotune(io, reps=2)
     print("autotune: waves/group %d, groups %d, times %s" % (w, g, np.round(times, 3)))
-    assert w in (1, 2, 4) and g * w in (256, 512, 1024, 2048)
-    assert all(t > 0 for t in times) and min(times) == pytest.approx(times[[1, 2, 4].index(w) * 4 + [256, 512, 1024, 2048].index(g * w)])
+    assert w in (1, 2, 4, 8) and g * w in (256, 512, 1024, 2048)
+    assert len(times) == 16 and all(t > 0 for t in times)
+    assert min(times) == pytest.approx(times[[1, 2, 4, 8].index(w) * 4 + [256, 512, 1024, 2048].index(g * w)])
     # still correct after the timing runs, with the chosen shape
     batch.update_async(io, tick=3)
     torch.cuda.synchronize()
@@ -228,6 +229,39 @@ def test_full_batch64_parity(ora, workloads):
                                 c["cost"]["lambda"], S_ref, U_ref, "batch64 %d" % p)
             if note:
                 print(note)
+    # eight lanes per sample (a workgroup of eight waves per tile): the same
+    # update by the eight-lane arithmetic; it agrees with the one-lane result
+    # to FP32 rounding (costs: median 1e-6, every sample within 1e-4 or, for
+    # the ill-conditioned force estimates, within twice the capped
+    # allowance), U_new within 1e-3 N m, and the sampled problems meet the
+    # oracle criteria
+    io8 = batch_io(batch, cases, torch, dev)
+    batch.set_launch(8, 256)
+    batch.update_async(io8, tick=7)
+    torch.cuda.synchronize()
+    assert (io8["status"] == B.OK).all()
+    S1, S8 = io["costs"].double().cpu().numpy(), io8["costs"].double().cpu().numpy()
+    rel = np.abs(S8 - S1) / np.abs(S1)
+    print("eight lanes vs one lane per sample: cost rel difference median %.3g, p99.9 %.3g, max %.3g"
+          % (np.median(rel), np.percentile(rel, 99.9), rel.max()), flush=True)
+    assert np.median(rel) <= 1e-6 and np.percentile(rel, 99.9) <= 1e-4 and rel.max() <= 2e-2
+    # U_new agrees wherever the cost differences cannot move the weights
+    # (max |dS| / lambda <= 1e-3, as for the end-to-end oracle criterion)
+    for p, c in enumerate(cases):
+        U1, _, Sa, _ = pick(io, batch, p)
+        U8, _, Sb, _ = pick(io8, batch, p)
+        dS = np.abs(Sa - Sb).max() / c["cost"]["lambda"]
+        dU = np.abs(U1 - U8).max()
+        if dS <= 1e-3:
+            assert dU <= 1e-3, (p, dU)
+        else:
+            print("problem %d: max |dS| / lambda = %.3g between the shapes, |dU| = %.3g N m" % (p, dS, dU))
+    for p in range(3, 64, 8):
+        c = cases[p]
+        U_b, _, S_b, _ = pick(io8, batch, p)
+        st_o, U_ref, S_ref, E_ref = ora.update(c["robot"], c["cost"], c["target"], c["q0"], c["qd0"],
+                                               c["U_nom"], c["seed"], 7)
+        check_costs_fp32(ora, c, S_b, S_ref, c["seed"], 7, "batch64 lanes 8 %d" % p)
     # a captured graph at the autotuned shape replays the eager bits
     batch.set_launch(w, g)
     io_g = batch_io(batch, cases, torch, dev)
@@ -241,4 +275,40 @@ def test_full_batch64_parity(ora, workloads):
         torch.cuda.synchronize()
         assert torch.equal(io_g["U_new"], ref["U_new"]), r
         assert torch.equal(io_g["costs"], ref["costs"]), r
+    batch.close()
+
+
+@pytest.mark.parametrize("with_collision", [False, True])
+def test_eight_lane_batch_equals_single_problem_updates(ora, workloads, with_collision):
+    """Eight lanes per sample (mppi_batch_set_launch(b, 8, groups)): every
+    problem equals its single-problem update on the eight-lane launch
+    (mppi_set_launch(h, 8); the same per-lane group arithmetic, with the
+    step's dynamics and cost on one wave instead of two) to FP32 rounding,
+    ragged K included; with a collision problem in the batch the collision
+    rollout variants are compiled in."""
+    torch, dev = torch_dev()
+    cases = small_cases(workloads, 8)
+    cases[1] = dict(cases[1], cost=dict(cases[1]["cost"], K=63))
+    cases[2] = dict(cases[2], cost=dict(cases[2]["cost"], K=65))
+    if with_collision:
+        c = workloads["collision_k4096"][0]
+        cases.append(dict(c, cost=dict(c["cost"], K=777)))
+    batch = B.Batch([(c["robot"], c["cost"]) for c in cases])
+    batch.set_launch(8, 128)
+    io = batch_io(batch, cases, torch, dev)
+    batch.update_async(io, tick=9)
+    torch.cuda.synchronize()
+    for p, c in enumerate(cases):
+        U_b, Us_b, S_b, st = pick(io, batch, p)
+        assert st == B.OK
+        solver = B.Solver(c["robot"], c["cost"], B.FP32)
+        solver.set_launch(8)
+        out = device_update(solver, c, c["seed"], 9, B.FP32)
+        solver.close()
+        same_result(S_b, U_b, out, "lanes 8 problem %d" % p)
+        assert np.array_equal(Us_b[:-1], U_b[1:]) and np.array_equal(Us_b[-1], U_b[-1])
+    c = cases[0]
+    st_o, U_ref, S_ref, E_ref = ora.update(c["robot"], c["cost"], c["target"], c["q0"], c["qd0"], c["U_nom"],
+                                           c["seed"], 9)
+    check_costs_fp32(ora, c, pick(io, batch, 0)[2], S_ref, c["seed"], 9, "lanes 8 problem 0")
     batch.close()
