@@ -385,12 +385,17 @@ __device__ __forceinline__ void adam_param(const MlpDev& d, int i, float g, cons
     }
 }
 
-// Tiles of 32 x 32: layer 1 8 (256 x 32 padded), layers 2, 3 64 each,
-// layer 4 32 (128 padded x 256).  Each workgroup's 4 waves split the batch
-// (the contraction index, in k-steps of 32 rows) and add their partial
-// tiles in LDS.  The tiles of the first column also form the bias
-// gradients db = e 1 on the matrix cores, from the same e fragments times
-// a fragment of ones (every column of that product is db).
+// Weight and bias gradients dW_l = e_l^T a_{l-1}, db_l = e_l^T 1 (a
+// contraction over the batch).  Tiles of 32 x 32 of the gradient matrices:
+// layer 1 8 (256 x 32 padded), layers 2, 3 64 each, layer 4 32 (128 padded
+// x 256).  A workgroup takes one tile; its 4 waves split the batch (in
+// k-steps of 32 rows, kWgradChunk requested together) and add their
+// partial tiles in LDS, in wave order.  The tiles of the first column also
+// form the bias gradients on the matrix cores, from the same e fragments
+// times a fragment of ones (every column of that product is db).  The
+// workgroup writes the gradient (and, fused, its Adam step) as its tile
+// completes.  (Splitting the batch over workgroups as well, with a second
+// launch summing the slices, measured no faster at 512 or 4096 rows.)
 constexpr int kWgradTiles = 8 + 64 + 64 + 32;
 constexpr int kWgradWaves = 4;
 constexpr int kWgradChunk = 4;    // k-steps of 32 rows requested together
@@ -417,10 +422,10 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
         E = d.eT4; Act = d.aT3; nreal = kMlpOut; kreal = kMlpHid; woff = kOffW4; boff = kOffB4; tm = t / 8; tn = t % 8;
     }
     // rows of this batch: the forward workgroups covered ceil(B / 64) * 64
-    // (rows past B carry e = 0); later rows of the buffers are stale
+    // (rows past B carry e = 0); later rows of the buffers are stale.  This
+    // wave's k-steps of 32 rows: [s0, s1) of Bb / 32
     const int m0 = tm * 32, n0 = tn * 32, Bp = d.Bp;
     const int nb = (B + kMlpRows - 1) / kMlpRows, Bb = nb * kMlpRows;
-    // this wave's k-steps of 32 rows: [s0, s1) of Bb / 32
     const int P = Bb / 32, per = (P + kWgradWaves - 1) / kWgradWaves;
     const int s0 = min(P, w * per), s1 = min(P, s0 + per);
     const int r = lane & 15, kg = (lane >> 4) * 8;
@@ -440,22 +445,22 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
         const int ns = min(kWgradChunk, s1 - st);
         v8s a[kWgradChunk][2], b[kWgradChunk][2];
 #pragma unroll
-        for (int s = 0; s < kWgradChunk; ++s)
-            if (s < ns)
+        for (int q = 0; q < kWgradChunk; ++q)
+            if (q < ns)
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                    a[s][i] = *reinterpret_cast<const v8s*>(ea[i] + 32 * (st + s));
-                    b[s][i] = *reinterpret_cast<const v8s*>(ab[i] + 32 * (st + s));
+                    a[q][i] = *reinterpret_cast<const v8s*>(ea[i] + 32 * (st + q));
+                    b[q][i] = *reinterpret_cast<const v8s*>(ab[i] + 32 * (st + q));
                 }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int s = 0; s < kWgradChunk; ++s)
-            if (s < ns)
+        for (int q = 0; q < kWgradChunk; ++q)
+            if (q < ns)
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) acc[i][j] = mfma32(a[s][i], b[s][j], acc[i][j]);
-                    if (bias) accb[i] = mfma32(a[s][i], ones, accb[i]);
+                    for (int j = 0; j < 2; ++j) acc[i][j] = mfma32(a[q][i], b[q][j], acc[i][j]);
+                    if (bias) accb[i] = mfma32(a[q][i], ones, accb[i]);
                 }
     }
     // every wave's partial tile (and db column) into LDS; then wave w
@@ -496,10 +501,23 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
         d.grad[boff + m0 + lane] = sb;
         if (fuse) adam_param(d, boff + m0 + lane, sb, adam);
     }
-    if (blockIdx.x == 0 && lane == 0 && loss) {
+    // the loss: the forward workgroups' sums reduced by workgroup 0 (every
+    // thread a strided share, then the waves' shuffles and LDS), not by one
+    // thread's chain of dependent loads
+    if (blockIdx.x == 0 && loss) {
+        __shared__ float lred[kWgradWaves];
         float sl = 0.0f;
-        for (int i = 0; i < Bb / kMlpWgRows; ++i) sl += d.lossp[i];
-        *loss = sl / ((float)B * (float)kMlpOut);
+        for (int i = tid; i < Bb / kMlpWgRows; i += 64 * kWgradWaves) sl += d.lossp[i];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sl += __shfl_xor(sl, o);
+        if (lane == 0) lred[w] = sl;
+        __syncthreads();
+        if (tid == 0) {
+            float tot = 0.0f;
+#pragma unroll
+            for (int q = 0; q < kWgradWaves; ++q) tot += lred[q];
+            *loss = tot / ((float)B * (float)kMlpOut);
+        }
     }
 }
 
