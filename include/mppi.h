@@ -280,6 +280,24 @@ int mppi_plant_step_async(mppi_handle_t h, double* q, double* qd,
                           const double* u, double dt, int substeps,
                           void* stream);
 
+/* mppi_plant_step_async with a further world wrench [force; moment] (N,
+ * N m) acting at the EE point, e.g. a push on the end effector that the
+ * controller does not model (the external perturbations of the free-space
+ * experiment, Sec. IV-B): J(q)^T wrench is added to the clamped torque at
+ * every substep, at that substep's state.  wrench: device [6], or NULL
+ * (then exactly mppi_plant_step_async).  Errors as mppi_plant_step_async. */
+int mppi_plant_step_wrench_async(mppi_handle_t h, double* q, double* qd,
+                                 const double* u, const double* wrench,
+                                 double dt, int substeps, void* stream);
+
+/* EE pose of n states of the handle's arm, FP64 forward kinematics (the
+ * EE frame of Sec. III-A, Fig. 1 caption): q device [n][7]; pose device
+ * [n][7] = position [3] (m, world) then the unit quaternion (w, x, y, z)
+ * of the EE frame with w >= 0.  Enqueued on `stream`.  Errors: MPPI_EINVAL
+ * (null pointer, n < 1), MPPI_EDEVICE. */
+int mppi_ee_pose_async(mppi_handle_t h, const double* q, int n, double* pose,
+                       void* stream);
+
 /* ---- batched problems (one persistent launch per control tick) ---- */
 
 typedef struct mppi_batch* mppi_batch_t;

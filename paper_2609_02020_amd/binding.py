@@ -177,6 +177,8 @@ def lib():
         L.mppi_rollout_async.argtypes = [vp, P(DeviceIO), vp]
         L.mppi_weights_async.argtypes = [vp, P(DeviceIO), vp]
         L.mppi_plant_step_async.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int, vp]
+        L.mppi_plant_step_wrench_async.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_int, vp]
+        L.mppi_ee_pose_async.argtypes = [vp, vp, C.c_int, vp, vp]
         L.mppi_warm_start_async.argtypes = [vp, vp, vp, C.c_double, vp]
         L.mppi_set_launch.argtypes = [vp, C.c_int]
         L.mppi_autotune.argtypes = [vp, P(DeviceIO), C.c_int, vp, P(C.c_int), P(C.c_float)]
@@ -331,12 +333,25 @@ class Solver:
         if st:
             raise MppiError(st, "mppi_weights_async")
 
-    def plant_step_async(self, q, qd, u, dt: float, substeps: int, stream=None):
-        st = self._lib.mppi_plant_step_async(self._h, _dev(q, "float64", NJ, "q"), _dev(qd, "float64", NJ, "qd"),
-                                             _dev(u, "float64", NJ, "u"), float(dt), int(substeps),
-                                             _stream_ptr(stream))
+    def plant_step_async(self, q, qd, u, dt: float, substeps: int, stream=None, wrench=None):
+        """FP64 plant step (mppi_plant_step_async); with `wrench` (device
+        [6] float64) a further world wrench at the EE point
+        (mppi_plant_step_wrench_async)."""
+        st = self._lib.mppi_plant_step_wrench_async(self._h, _dev(q, "float64", NJ, "q"),
+                                                    _dev(qd, "float64", NJ, "qd"), _dev(u, "float64", NJ, "u"),
+                                                    _dev(wrench, "float64", 6, "wrench"), float(dt), int(substeps),
+                                                    _stream_ptr(stream))
         if st:
-            raise MppiError(st, "mppi_plant_step_async")
+            raise MppiError(st, "mppi_plant_step_wrench_async")
+
+    def ee_pose_async(self, q, pose, stream=None):
+        """EE position and quaternion (w >= 0) of the states q [n][7] into
+        pose [n][7] (mppi_ee_pose_async); device float64 tensors."""
+        n = q.numel() // NJ
+        st = self._lib.mppi_ee_pose_async(self._h, _dev(q, "float64", n * NJ, "q"), int(n),
+                                          _dev(pose, "float64", n * 7, "pose"), _stream_ptr(stream))
+        if st:
+            raise MppiError(st, "mppi_ee_pose_async")
 
     def autotune(self, io: dict, budget_ms: int = 30, stream=None):
         """Times launch shapes 8, 2 and 1 on io (mppi_autotune), keeps the

@@ -928,16 +928,22 @@ template <typename R> MPPI_HD void make_target(const double* tgt, TargetM<R>& tg
 
 // tau_ext = J(q0)^T F_ext for the constant external wrench (Sec. III-A:
 // held over the whole horizon).  (J^T F)_j = (z_j x (p_ee - p_j)).F + z_j.N
-template <typename R> MPPI_HD void const_ext_torque(const ModelM<R>& M, const CostM<R>& C, const R* q0, R* tau_ext)
+// Joint torques J(q)^T W of a world wrench W = [force; moment] acting at
+// the EE point (Eq. 5's tau_ext for a wrench at the EE).
+template <typename R> MPPI_HD void ee_wrench_torque(const ModelM<R>& M, const R* q, const R* W, R* tau)
 {
     R pee[3], Rn[9], P[NJ * 3], Z[NJ * 3];
-    fk_ee(M, q0, pee, Rn, P, Z);
+    fk_ee(M, q, pee, Rn, P, Z);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         R d[3] = {pee[0] - P[j * 3], pee[1] - P[j * 3 + 1], pee[2] - P[j * 3 + 2]}, c[3];
         cross3(Z + j * 3, d, c);
-        tau_ext[j] = dot3(c, C.F_ext) + dot3(Z + j * 3, C.F_ext + 3);
+        tau[j] = dot3(c, W) + dot3(Z + j * 3, W + 3);
     }
+}
+template <typename R> MPPI_HD void const_ext_torque(const ModelM<R>& M, const CostM<R>& C, const R* q0, R* tau_ext)
+{
+    ee_wrench_torque(M, q0, C.F_ext, tau_ext);
 }
 
 }  // namespace mppi

@@ -1001,22 +1001,33 @@ __global__ __launch_bounds__(kWeightsBlock) void weights_kernel(
 }
 
 // zero-order hold of u (clamped to the torque limits) over dt in
-// `substeps` semi-implicit Euler steps of the FP64 dynamics
+// `substeps` semi-implicit Euler steps of the FP64 dynamics, with the cost's
+// external-wrench model and, when `wrench` is non-null, a further world
+// wrench [force; moment] at the EE point (a disturbance the controller does
+// not model), J(q)^T wrench at the state of every substep
 __device__ void plant_advance(const ModelM<double>& M, const CostM<double>& C, double* q, double* qd,
-                              const double* u, double dt, int substeps)
+                              const double* u, double dt, int substeps, const double* wrench)
 {
-    double tau[NJ], qq[NJ], qv[NJ];
+    double tau[NJ], qq[NJ], qv[NJ], W[6];
     for (int j = 0; j < NJ; ++j) {
         double lim = M.L[j].taumax;
         tau[j] = fmin(fmax(u[j], -lim), lim);
         qq[j] = q[j];
         qv[j] = qd[j];
     }
+    for (int c = 0; c < 6; ++c) W[c] = wrench ? wrench[c] : 0.0;
     const int ext = C.ext_mode == EXTW_WALL ? EXTW_WALL : (C.ext_mode == EXTW_CONST ? EXTW_CONST : EXTW_NONE);
     const double h = dt / substeps;
     for (int s = 0; s < substeps; ++s) {
+        double ts[NJ];
+        if (wrench) {
+            ee_wrench_torque(M, qq, W, ts);
+            for (int j = 0; j < NJ; ++j) ts[j] += tau[j];
+        } else {
+            for (int j = 0; j < NJ; ++j) ts[j] = tau[j];
+        }
         StepOut<double> o;
-        dyn_step<double, false>(M, C, ext, qq, qv, tau, tau, o);
+        dyn_step<double, false>(M, C, ext, qq, qv, ts, ts, o);
         for (int j = 0; j < NJ; ++j) {
             qv[j] += o.qdd[j] * h;
             qq[j] += qv[j] * h;
@@ -1026,10 +1037,47 @@ __device__ void plant_advance(const ModelM<double>& M, const CostM<double>& C, d
 }
 
 __global__ void plant_kernel(const ModelM<double>* __restrict__ Mp, const CostM<double>* __restrict__ Cp,
-                             double* q, double* qd, const double* __restrict__ u, double dt, int substeps)
+                             double* q, double* qd, const double* __restrict__ u, double dt, int substeps,
+                             const double* __restrict__ wrench)
 {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    plant_advance(*Mp, *Cp, q, qd, u, dt, substeps);
+    plant_advance(*Mp, *Cp, q, qd, u, dt, substeps, wrench);
+}
+
+// EE pose of n states (FP64): position and the unit quaternion (w, x, y, z)
+// of the EE frame, w >= 0; one thread per state.  The quaternion is taken
+// from the rotation matrix by its largest diagonal combination (Shepperd's
+// method), which keeps the square root away from zero.
+__global__ void ee_pose_kernel(const ModelM<double>* __restrict__ Mp, const double* __restrict__ q, int n,
+                               double* __restrict__ pose)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const ModelM<double>& M = *Mp;
+    double qi[NJ], p[3], Rn[9];
+    for (int j = 0; j < NJ; ++j) qi[j] = q[i * NJ + j];
+    fk_ee(M, qi, p, Rn, (double*)nullptr, (double*)nullptr);
+    double Re[9];
+    mm3(Rn, M.Ree, Re);
+    const double tr = Re[0] + Re[4] + Re[8];
+    double w, x, y, z;
+    if (tr >= Re[0] && tr >= Re[4] && tr >= Re[8]) {
+        const double r = sqrt(1.0 + tr), s = 0.5 / r;
+        w = 0.5 * r; x = (Re[7] - Re[5]) * s; y = (Re[2] - Re[6]) * s; z = (Re[3] - Re[1]) * s;
+    } else if (Re[0] >= Re[4] && Re[0] >= Re[8]) {
+        const double r = sqrt(1.0 + Re[0] - Re[4] - Re[8]), s = 0.5 / r;
+        x = 0.5 * r; w = (Re[7] - Re[5]) * s; y = (Re[1] + Re[3]) * s; z = (Re[2] + Re[6]) * s;
+    } else if (Re[4] >= Re[8]) {
+        const double r = sqrt(1.0 - Re[0] + Re[4] - Re[8]), s = 0.5 / r;
+        y = 0.5 * r; w = (Re[2] - Re[6]) * s; x = (Re[1] + Re[3]) * s; z = (Re[5] + Re[7]) * s;
+    } else {
+        const double r = sqrt(1.0 - Re[0] - Re[4] + Re[8]), s = 0.5 / r;
+        z = 0.5 * r; w = (Re[3] - Re[1]) * s; x = (Re[2] + Re[6]) * s; y = (Re[5] + Re[7]) * s;
+    }
+    const double sg = w < 0.0 ? -1.0 : 1.0;
+    double* o = pose + (size_t)i * 7;
+    o[0] = p[0]; o[1] = p[1]; o[2] = p[2];
+    o[3] = sg * w; o[4] = sg * x; o[5] = sg * y; o[6] = sg * z;
 }
 
 // one workgroup per problem of a batch: the first row of its U_new
@@ -1039,7 +1087,7 @@ __global__ void batch_plant_kernel(const BatchProblem* __restrict__ probs, int n
     const int p = blockIdx.x;
     if (p >= n || threadIdx.x != 0) return;
     const BatchProblem& Pb = probs[p];
-    plant_advance(*Pb.model64, *Pb.cost64, q + p * NJ, qd + p * NJ, U_new + Pb.u_off, dt, substeps);
+    plant_advance(*Pb.model64, *Pb.cost64, q + p * NJ, qd + p * NJ, U_new + Pb.u_off, dt, substeps, nullptr);
 }
 
 // Warm start after s horizon steps of elapsed time (solver period != dt):
@@ -1330,9 +1378,15 @@ void fill_batch_problem(void* dst, const void* model, const void* cost, const vo
 }
 
 hipError_t launch_plant(const ModelM<double>* M, const CostM<double>* C, double* q, double* qd,
-                        const double* u, double dt, int substeps, hipStream_t s)
+                        const double* u, double dt, int substeps, const double* wrench, hipStream_t s)
 {
-    hipLaunchKernelGGL(plant_kernel, dim3(1), dim3(64), 0, s, M, C, q, qd, u, dt, substeps);
+    hipLaunchKernelGGL(plant_kernel, dim3(1), dim3(64), 0, s, M, C, q, qd, u, dt, substeps, wrench);
+    return hipGetLastError();
+}
+
+hipError_t launch_ee_pose(const ModelM<double>* M, const double* q, int n, double* pose, hipStream_t s)
+{
+    hipLaunchKernelGGL(ee_pose_kernel, dim3((n + 63) / 64), dim3(64), 0, s, M, q, n, pose);
     return hipGetLastError();
 }
 

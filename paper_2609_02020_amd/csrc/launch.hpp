@@ -98,8 +98,12 @@ hipError_t launch_prep_model(const mppi_robot_params* d_raw, ModelM<float>* d_mf
                              hipStream_t s);
 // acc64: accumulate the weights and sums in FP64
 hipError_t launch_weights(int precision, bool acc64, const WeightsArgs& a, hipStream_t s);
+// wrench: device [6] world wrench at the EE point added to the plant's
+// external model, or null
 hipError_t launch_plant(const ModelM<double>* M, const CostM<double>* C, double* q, double* qd,
-                        const double* u, double dt, int substeps, hipStream_t s);
+                        const double* u, double dt, int substeps, const double* wrench, hipStream_t s);
+// EE position and quaternion (w >= 0) of n states: pose [n][7]
+hipError_t launch_ee_pose(const ModelM<double>* M, const double* q, int n, double* pose, hipStream_t s);
 
 constexpr int kRolloutBlock = 64;
 constexpr int kWeightsBlock = 256;

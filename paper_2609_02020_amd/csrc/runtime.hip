@@ -686,13 +686,25 @@ int mppi_update(mppi_handle_t h, const double* q, const double* qd, const mppi_t
     return *h->h_status;
 }
 
+int mppi_plant_step_wrench_async(mppi_handle_t h, double* q, double* qd, const double* u, const double* wrench,
+                                 double dt, int substeps, void* stream)
+{
+    if (!h || !q || !qd || !u || !(dt > 0) || substeps < 1) return MPPI_EINVAL;
+    return launch_plant(h->d_md, h->d_cd, q, qd, u, dt, substeps, wrench, (hipStream_t)stream) == hipSuccess
+               ? MPPI_OK
+               : MPPI_EDEVICE;
+}
+
 int mppi_plant_step_async(mppi_handle_t h, double* q, double* qd, const double* u, double dt, int substeps,
                           void* stream)
 {
-    if (!h || !q || !qd || !u || !(dt > 0) || substeps < 1) return MPPI_EINVAL;
-    return launch_plant(h->d_md, h->d_cd, q, qd, u, dt, substeps, (hipStream_t)stream) == hipSuccess
-               ? MPPI_OK
-               : MPPI_EDEVICE;
+    return mppi_plant_step_wrench_async(h, q, qd, u, nullptr, dt, substeps, stream);
+}
+
+int mppi_ee_pose_async(mppi_handle_t h, const double* q, int n, double* pose, void* stream)
+{
+    if (!h || !q || !pose || n < 1) return MPPI_EINVAL;
+    return launch_ee_pose(h->d_md, q, n, pose, (hipStream_t)stream) == hipSuccess ? MPPI_OK : MPPI_EDEVICE;
 }
 
 int mppi_select_nominal_async(mppi_handle_t h, const mppi_device_io* io, const double* U_candidate, double* costs,

@@ -130,6 +130,23 @@ def wall_cost(K: int, T: int, normal, axis: int, d0: float, dt: float = 0.01,
     return c
 
 
+def free_space_cost(K: int, T: int, dt: float = 0.01, lam: float = 1.0) -> dict:
+    """Hybrid motion/force task in free space: Table I's free-space weights
+    (W_pos diag(0, 5e6, 5e6), W_ori 5e5 I, W_force diag(30, 0, ...), W_reg I)
+    scaled by 1e3 / 5e6 to the position weight of the other workloads
+    (W_pos = 1e3 on y and z), so W_ori = 100, W_force = 0.006 on the x
+    force, W_reg = 2e-4 on all six; joint-limit (1e4), velocity-limit (1e4)
+    and torque-limit (10) penalties; the posture term of C_joint on
+    (w_post = 10; its rest posture q_rest is set per episode to the start
+    configuration); no contact model in the controller."""
+    c = position_cost(K, T, dt, lam)
+    s = 1e3 / 5e6
+    c.update({"W_pos": [0.0, 5e6 * s, 5e6 * s], "W_ori": [5e5 * s] * 3,
+              "W_force": [30.0 * s, 0.0, 0.0, 0.0, 0.0, 0.0], "W_reg": [1.0 * s] * 6,
+              "w_qd": 1e4, "w_post": 10.0})
+    return c
+
+
 def draw_perturbation(seed: int, n: int = NJ, start_width: float = 0.2, goal_width: float = 0.3):
     """Offsets of a start and a goal configuration, uniform in +-start_width
     and +-goal_width rad per joint."""
@@ -172,6 +189,21 @@ def draw_mlp_batch(seed: int, rows: int, scale: float = 1.0):
     rng = np.random.default_rng(seed)
     return (rng.uniform(-scale, scale, size=(rows, MLP_DIMS[0])),
             rng.uniform(-0.5, 0.5, size=(rows, MLP_DIMS[-1])))
+
+
+FREE_SPACE_JSON = os.path.join(os.path.dirname(WORKLOADS_JSON), "free_space.json")
+
+
+def load_free_space(path: str = FREE_SPACE_JSON) -> dict:
+    """Episodes of the free-space hybrid task (written by
+    tests/golden/make_workloads.py): {"robot", "cost", "episodes": [...]},
+    each episode {"q0", "qd0", "target", "U_nom", "seed"}."""
+    with open(path) as f:
+        d = json.load(f)
+    T = d["cost"]["T"]
+    for e in d["episodes"]:
+        e["U_nom"] = [list(e["g0"])] * T
+    return d
 
 
 def load_learned(path: str = LEARNED_JSON) -> dict:

@@ -18,6 +18,8 @@ Recipe (all seeds fixed):
   * collision_k4096: wall_k4096[0..3] with the collision term (see
     with_collision()).
   * learned_wall.json: the learned-proposal task (see learned_wall()).
+  * free_space.json: the free-space hybrid task (see free_space());
+    `python tests/golden/make_workloads.py free_space` writes only it.
 """
 from __future__ import annotations
 
@@ -133,6 +135,46 @@ def learned_wall(n_train=1000, n_eval=50):
     return {"robot": arm, "cost": cost, "q_base": qb.tolist(), "train": eps[:n_train], "eval": eps[n_train:]}
 
 
+def free_space(n=8, learned_path=None):
+    """The free-space hybrid task of Sec. IV-B: the arm and base posture of
+    the learned-proposal task (read from learned_wall.json); episode e
+    starts at base + the start offset of draw_perturbation(8000 + e +
+    100000 a) (+-0.2 rad) for the first attempt a whose gravity torques are
+    within 0.6 tau_max and sigma_min(J(q0)) >= 0.05, at rest, with
+    U_nom = g(q0); the target is a step reference from the start pose: the
+    EE point raised 0.03 m along z (the position-controlled axes are y and
+    z), the initial orientation, and 10 N along +x (F_des = (10, 0, 0, 0,
+    0, 0)); the posture term's rest posture is the start configuration
+    (q_rest = q0, stored with the episode).  Cost: inputs.free_space_cost
+    (K = 4096, T = 18, dt = 0.01 s, lambda = 1)."""
+    lw = inputs.load_learned(learned_path) if learned_path else inputs.load_learned()
+    arm, qb = lw["robot"], np.array(lw["q_base"])
+    lim = np.array([L["tau_max"] for L in arm["links"]])
+    eps = []
+    for e in range(n):
+        for attempt in range(200):
+            dq0, _ = inputs.draw_perturbation(8000 + e + 100000 * attempt)
+            q0 = qb + dq0
+            g0 = ora.bias_jacobian(arm, q0, np.zeros(7))
+            smin = np.linalg.svd(ora.ee_jacobian(arm, q0), compute_uv=False).min()
+            if (np.abs(g0) <= 0.6 * lim).all() and smin >= 0.05:
+                break
+        else:
+            raise RuntimeError("no acceptable free-space episode %d" % e)
+        tg = target_of(arm, q0, [10.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+        tg["p_des"][2] += 0.03
+        eps.append({"q0": q0.tolist(), "qd0": [0.0] * 7, "target": tg, "g0": g0.tolist(), "q_rest": q0.tolist(),
+                    "seed": 9000 + e})
+    return {"robot": arm, "cost": inputs.free_space_cost(4096, 18, 0.01, 1.0), "episodes": eps}
+
+
+def write_free_space():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "free_space.json")
+    with open(path, "w") as f:
+        json.dump(free_space(), f, indent=None, separators=(",", ":"))
+    print("wrote", path, os.path.getsize(path), "bytes")
+
+
 def with_collision(case):
     """The contact case plus the collision term of Eqs. 14-15: two vertical
     obstacle segments beside the target point (0.15 m along +x, 0.25 m
@@ -172,7 +214,11 @@ def main():
     with open(path, "w") as f:
         json.dump(learned_wall(), f, indent=None, separators=(",", ":"))
     print("wrote", path, os.path.getsize(path), "bytes")
+    write_free_space()
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "free_space":
+        write_free_space()
+    else:
+        main()

@@ -1,0 +1,154 @@
+"""Free-space hybrid motion/force task (Sec. IV-B, Table I free-space
+column) on the simulated arm: a 10 N force target along x through the
+torque-based force estimate of Eq. 13, pose tracking on y, z and the
+orientation, motion blocking along x and pushes along +z, +y and -y
+(paper_2609_02020_amd/hybrid.py).  The analysis of the recorded states
+(force estimate of the applied torque, orientation error, wall force) uses
+the CPU oracle; the closed loop itself runs in the library.
+
+Also checks the two library calls the scenario adds: the EE pose of many
+states against the oracle's forward kinematics, and the plant step with an
+extra EE wrench against the oracle's plant under the same constant wrench.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return torch.device("cuda:0")
+
+
+def test_ee_pose_matches_oracle_fk(ora):
+    from paper_2609_02020_amd import binding as B, inputs
+    dev = _dev()
+    d = inputs.load_free_space()
+    robot = d["robot"]
+    rng = np.random.default_rng(5)
+    Q = rng.uniform(-2.5, 2.5, size=(300, 7))
+    s = B.Solver(robot, dict(d["cost"], K=1, T=1))
+    q = torch.tensor(Q, dtype=torch.float64, device=dev)
+    pose = torch.empty((300, 7), dtype=torch.float64, device=dev)
+    s.ee_pose_async(q, pose)
+    torch.cuda.synchronize()
+    P = pose.cpu().numpy()
+    s.close()
+    for i in range(300):
+        _, _, pe, Re = ora.fk(robot, Q[i])
+        assert np.abs(P[i, :3] - pe).max() < 1e-12
+        assert abs(np.linalg.norm(P[i, 3:]) - 1.0) < 1e-12 and P[i, 3] >= 0.0
+        assert np.abs(ora.quat_to_R(P[i, 3:]) - Re).max() < 1e-12
+
+
+def test_plant_wrench_matches_oracle_constant_wrench(ora):
+    """A wrench at the EE point passed to the plant step equals the oracle
+    plant with the same world wrench as its constant external model (J(q)^T W
+    at every substep's state), and zero wrench equals the plain step."""
+    from paper_2609_02020_amd import binding as B, inputs
+    dev = _dev()
+    d = inputs.load_free_space()
+    robot = d["robot"]
+    pc = dict(d["cost"], K=1, T=1)
+    s = B.Solver(robot, pc)
+    f64 = dict(dtype=torch.float64, device=dev)
+    for i, e in enumerate(d["episodes"][:4]):
+        W = [0.0, 15.0 * (i % 2), 12.0, 0.5, -0.3, 0.2 * i]
+        u = np.asarray(e["g0"]) + 0.5
+        q = torch.tensor(e["q0"], **f64)
+        qd = torch.tensor([0.1] * 7, **f64)
+        s.plant_step_async(q, qd, torch.tensor(u, **f64), 0.01, 10, wrench=torch.tensor(W, **f64))
+        q0 = torch.tensor(e["q0"], **f64)
+        qd0 = torch.tensor([0.1] * 7, **f64)
+        s.plant_step_async(q0, qd0, torch.tensor(u, **f64), 0.01, 10, wrench=torch.zeros(6, **f64))
+        q1 = torch.tensor(e["q0"], **f64)
+        qd1 = torch.tensor([0.1] * 7, **f64)
+        s.plant_step_async(q1, qd1, torch.tensor(u, **f64), 0.01, 10)
+        torch.cuda.synchronize()
+        qr, qdr = ora.plant_step(robot, dict(pc, ext_mode=B.EXT_CONST, F_ext=W), e["q0"], [0.1] * 7, u, 0.01, 10)
+        assert np.abs(q.cpu().numpy() - qr).max() < 1e-10
+        assert np.abs(qd.cpu().numpy() - qdr).max() < 1e-8
+        assert torch.equal(q0, q1) and torch.equal(qd0, qd1)
+        # the wrench moved the arm
+        assert np.abs(q.cpu().numpy() - q1.cpu().numpy()).max() > 1e-6
+    s.close()
+
+
+def _analyse(ora, robot, cost, episode, out, schedule):
+    dt = out["dt"]
+    n = len(out["u"])
+    p_des = np.asarray(episode["target"]["p_des"])
+    Rd = ora.quat_to_R(episode["target"]["quat_des"])
+    P = out["pose"][:n, :3]
+    eyz = np.linalg.norm(P[:, 1:] - p_des[1:], axis=1)
+    ori = np.array([np.linalg.norm(ora.so3_log(Rd.T @ ora.quat_to_R(out["pose"][t, 3:]))) for t in range(n)])
+    Fx = np.zeros(n)
+    Fw = np.zeros(n)
+    for t in range(n):
+        q = out["q"][t]
+        g = ora.rnea(robot, q, np.zeros(7), np.zeros(7))
+        Fx[t] = ora.force_estimate(robot, q, out["u"][t] - g)[0]
+        b = out["blocked"][t]
+        if b >= 0:
+            nrm, d0 = out["walls"][b, :3], out["walls"][b, 3]
+            v = ora.ee_jacobian(robot, q)[:3] @ out["qd"][t]
+            Fw[t] = max(0.0, schedule["wall_k"] * (d0 - nrm @ P[t]) - schedule["wall_c"] * (nrm @ v))
+    i0, i1 = (int(round(x / dt)) for x in schedule["window"])
+    w = slice(i0, i1)
+    m = {"window_eyz": eyz[w].mean(), "window_ori": ori[w].mean(), "window_Fx_mae": np.abs(Fx[w] - 10.0).mean(),
+         "window_Fx": Fx[w].mean()}
+    # the last 0.4 s of the first block: force estimate and the wall's force
+    b0 = schedule["blocks"][0]
+    bl = slice(int(round((b0[1] - 0.4) / dt)), int(round(b0[1] / dt)))
+    m["block_Fx"] = Fx[bl].mean()
+    m["block_Fwall"] = Fw[bl].mean()
+    m["block_eyz"] = eyz[bl].mean()
+    # pushes: largest EE displacement along the push from its start point,
+    # and the y/z error 0.4 s after the push ends
+    for k, (a, b, axis) in enumerate(schedule["pushes"]):
+        ia, ib = int(round(a / dt)), int(round(b / dt))
+        ax = np.asarray(axis)
+        m["push%d_disp" % k] = ((P[ia:ib] - P[ia]) @ ax).max()
+        m["push%d_after_eyz" % k] = eyz[min(ib + int(round(0.4 / dt)), n - 1)]
+    m["qd_max"] = np.abs(out["qd"]).max()
+    return m
+
+
+def test_free_space_hybrid_task(ora):
+    from paper_2609_02020_amd import hybrid, inputs
+    _dev()
+    d = inputs.load_free_space()
+    robot, cost = d["robot"], d["cost"]
+    sched = hybrid.SCHEDULE
+    rows = []
+    for i, e in enumerate(d["episodes"]):
+        print("free-space episode %d" % i, flush=True)
+        out = hybrid.run_episode(robot, cost, e, sched)
+        assert out["status"] == 0
+        for key in ("q", "qd", "u", "pose"):
+            assert np.isfinite(out[key]).all(), (i, key)
+        m = _analyse(ora, robot, cost, e, out, sched)
+        rows.append(m)
+        print("  " + " ".join("%s=%.4g" % kv for kv in m.items()), flush=True)
+    med = {k: float(np.median([r[k] for r in rows])) for k in rows[0]}
+    print("median " + " ".join("%s=%.4g" % kv for kv in med.items()), flush=True)
+    mx = {k: float(np.max([r[k] for r in rows])) for k in rows[0]}
+    # bounded episodes: every joint rate stays under 3 rad/s
+    assert mx["qd_max"] < 3.0
+    # the converged free interval (the experiment's error window): pose
+    # errors on y, z and the orientation, and the force estimate on x
+    assert med["window_eyz"] < 0.03 and mx["window_eyz"] < 0.06
+    assert med["window_ori"] < 0.06 and mx["window_ori"] < 0.1
+    assert med["window_Fx"] > 2.0 and med["window_Fx_mae"] < 8.0
+    # blocked: the arm pushes against the block along the force target
+    assert 3.0 < med["block_Fx"] < 12.0
+    assert med["block_Fwall"] > 2.0
+    # pushes: the EE yields along each push and returns afterwards
+    for k in range(len(sched["pushes"])):
+        assert med["push%d_disp" % k] > 0.0005
+        assert med["push%d_after_eyz" % k] < 0.05 and mx["push%d_after_eyz" % k] < 0.15
+    assert med["push1_disp"] > 0.01 and med["push2_disp"] > 0.01
