@@ -14,8 +14,8 @@
 //                   pre-activations stay in registers), storing every
 //                   activation and signal transposed for the weight gradients.
 //   mlp_wgrad_kernel   dW_l = e_l^T a_{l-1} (a contraction over the batch),
-//                   one workgroup per 32 x 32 tile of one layer, its 4 waves
-//                   splitting the batch; db_l = sum of e_l.
+//                   one workgroup per 32 x 32 tile of one layer, its 16
+//                   waves splitting the batch; db_l = sum of e_l.
 //   mlp_adam_kernel    Adam on the FP32 master weights, then the BF16 copies
 //                   (row-major and transposed); a training step applies the
 //                   same update in mlp_wgrad_kernel as each tile completes.
@@ -138,7 +138,8 @@ __device__ __forceinline__ void frag_mm(const uint16_t* A, const BFrag<K, CT>& f
     }
 }
 
-// LDS tile columns [0, ncols) -> global [c][Bp] at rows b0..b0+15
+// LDS tile columns [0, ncols) -> global [c][Bp] at rows b0..b0+15 (the
+// input tile only; the layers' outputs go out from their result registers)
 __device__ __forceinline__ void store_transposed(const uint16_t* tile, int ncols, uint16_t* dst, int Bp, int b0,
                                                  int tid)
 {
@@ -146,6 +147,17 @@ __device__ __forceinline__ void store_transposed(const uint16_t* tile, int ncols
         const int c = i / kMlpWgRows, r = i % kMlpWgRows;
         dst[(size_t)c * Bp + b0 + r] = tile[r * kLda + c];
     }
+}
+
+// One result fragment's four BF16 values (column col, rows row0 + 0..3 of
+// the workgroup's 16) into the transposed global buffer [feature][Bp]: the
+// four rows are contiguous there, so one 8-byte store per lane.
+__device__ __forceinline__ void store_frag_T(uint16_t* dstT, int Bp, int b0, int row0, int col, const uint16_t (&o)[4])
+{
+    uint2 v;
+    v.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
+    v.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
+    *reinterpret_cast<uint2*>(dstT + (size_t)col * Bp + b0 + row0) = v;
 }
 
 // this wave's bias values of a hidden layer (columns nb + 16 j + lane mod 16)
@@ -161,10 +173,12 @@ __device__ __forceinline__ void load_bias(const float* __restrict__ bias, int nb
 // thread computed here).  Rows past `rows` (padding of the last workgroup)
 // are set to zero without evaluating GELU (rows never mix, so they cannot
 // reach a valid output).
+// Training (dstT non-null) also stores the activations transposed from the
+// result registers (store_frag_T).
 template <int K>
 __device__ __forceinline__ void hidden_forward(const uint16_t* A, const BFrag<K, kHidCT>& f, const float (&bv)[kHidCT],
                                                float (&zo)[kRT][kHidCT][4], uint16_t* out, int rows, int w,
-                                               int lane)
+                                               int lane, uint16_t* dstT, int Bp, int b0)
 {
     constexpr int NC = 16 * kHidCT;
     v4f acc[kRT][kHidCT];
@@ -172,26 +186,33 @@ __device__ __forceinline__ void hidden_forward(const uint16_t* A, const BFrag<K,
 #pragma unroll
     for (int i = 0; i < kRT; ++i)
 #pragma unroll
-        for (int j = 0; j < kHidCT; ++j)
+        for (int j = 0; j < kHidCT; ++j) {
+            const int col = w * NC + 16 * j + (lane & 15);
+            uint16_t o[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = 16 * i + 4 * (lane >> 4) + e, col = w * NC + 16 * j + (lane & 15);
+                const int row = 16 * i + 4 * (lane >> 4) + e;
                 const float zz = acc[i][j][e] + bv[j];
                 zo[i][j][e] = zz;
                 // 16 i + e is the wave's smallest row of this element: past
                 // `rows` no lane evaluates GELU (a uniform branch)
-                uint16_t o = 0;
-                if (16 * i + e < rows) o = row < rows ? to_bf16(gelu_f(zz)) : (uint16_t)0;
-                out[row * kLda + col] = o;
+                o[e] = 0;
+                if (16 * i + e < rows) o[e] = row < rows ? to_bf16(gelu_f(zz)) : (uint16_t)0;
+                out[row * kLda + col] = o[e];
             }
+            if (dstT) store_frag_T(dstT, Bp, b0, 16 * i + 4 * (lane >> 4), col, o);
+        }
 }
 
-// hidden layer backward: out = bf16((E Wt^T) * gelu'(z)) from the wave's
+// hidden layer backward: bf16((E Wt^T) * gelu'(z)) from the wave's
 // fragments f of Wt and the pre-activations zv this thread computed in the
-// forward pass (same fragment map)
+// forward pass (same fragment map), into the LDS tile out (null for the
+// first layer's signal, which no later product reads) and, transposed,
+// into dstT
 template <int K>
 __device__ __forceinline__ void hidden_backward(const uint16_t* E, const BFrag<K, kHidCT>& f,
-                                                const float (&zv)[kRT][kHidCT][4], uint16_t* out, int w, int lane)
+                                                const float (&zv)[kRT][kHidCT][4], uint16_t* out, int w, int lane,
+                                                uint16_t* dstT, int Bp, int b0)
 {
     constexpr int NC = 16 * kHidCT;
     v4f acc[kRT][kHidCT];
@@ -199,12 +220,17 @@ __device__ __forceinline__ void hidden_backward(const uint16_t* E, const BFrag<K
 #pragma unroll
     for (int i = 0; i < kRT; ++i)
 #pragma unroll
-        for (int j = 0; j < kHidCT; ++j)
+        for (int j = 0; j < kHidCT; ++j) {
+            const int col = w * NC + 16 * j + (lane & 15);
+            uint16_t o[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = 16 * i + 4 * (lane >> 4) + e, col = w * NC + 16 * j + (lane & 15);
-                out[row * kLda + col] = to_bf16(acc[i][j][e] * gelu_d(zv[i][j][e]));
+                const int row = 16 * i + 4 * (lane >> 4) + e;
+                o[e] = to_bf16(acc[i][j][e] * gelu_d(zv[i][j][e]));
+                if (out) out[row * kLda + col] = o[e];
             }
+            store_frag_T(dstT, Bp, b0, 16 * i + 4 * (lane >> 4), col, o);
+        }
 }
 
 // Feature c (0..20) of state p: q / q_max, qd / qd_max, p_des, then the
@@ -261,16 +287,14 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
     // training keeps every row (the backward pass reads them all)
     const int rows = TRAIN ? kMlpWgRows : min(kMlpWgRows, B - b0);
     float z1[kRT][kHidCT][4], z2[kRT][kHidCT][4], z3[kRT][kHidCT][4];
-    hidden_forward<kMlpInPad>(buf[0], f1, bv1, z1, buf[1], rows, w, lane);
+    hidden_forward<kMlpInPad>(buf[0], f1, bv1, z1, buf[1], rows, w, lane, TRAIN ? d.aT1 : nullptr, d.Bp, b0);
     __syncthreads();
-    if (TRAIN) store_transposed(buf[1], kMlpHid, d.aT1, d.Bp, b0, tid);
     BFrag<kMlpHid, kHidCT> f3;
     float bv3[kHidCT];
     load_frag(d.W3, nh, f3, lane);
     load_bias(th + kOffB3, nh, bv3, lane);
-    hidden_forward<kMlpHid>(buf[1], f2, bv2, z2, buf[0], rows, w, lane);
+    hidden_forward<kMlpHid>(buf[1], f2, bv2, z2, buf[0], rows, w, lane, TRAIN ? d.aT2 : nullptr, d.Bp, b0);
     __syncthreads();
-    if (TRAIN) store_transposed(buf[0], kMlpHid, d.aT2, d.Bp, b0, tid);
 
     // the output layer's operands (its 8 column tiles on the first waves)
     constexpr int NO = 16 * kOutCT;
@@ -292,9 +316,8 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
                 }
         }
     }
-    hidden_forward<kMlpHid>(buf[0], f3, bv3, z3, buf[1], rows, w, lane);
+    hidden_forward<kMlpHid>(buf[0], f3, bv3, z3, buf[1], rows, w, lane, TRAIN ? d.aT3 : nullptr, d.Bp, b0);
     __syncthreads();
-    if (TRAIN) store_transposed(buf[1], kMlpHid, d.aT3, d.Bp, b0, tid);
 
     // output layer; training: e_4 = bf16(2 (y - y*) / (B 126)) into buf[0]
     BFrag<kMlpOutPad, kHidCT> g4;
@@ -306,10 +329,12 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
 #pragma unroll
             for (int i = 0; i < kRT; ++i)
 #pragma unroll
-                for (int j = 0; j < kOutCT; ++j)
+                for (int j = 0; j < kOutCT; ++j) {
+                    const int col = w * NO + 16 * j + (lane & 15);
+                    uint16_t o[4];
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const int row = 16 * i + 4 * (lane >> 4) + e, col = w * NO + 16 * j + (lane & 15);
+                        const int row = 16 * i + 4 * (lane >> 4) + e;
                         const bool valid = col < kMlpOut && b0 + row < B;
                         const float y = acc[i][j][e] + b4[j];
                         if (valid) {
@@ -319,9 +344,12 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
                         if (TRAIN) {
                             const float res = valid ? y - yt[i][j][e] : 0.0f;
                             sq += res * res;
-                            buf[0][row * kLda + col] = to_bf16(res * gscale);
+                            o[e] = to_bf16(res * gscale);
+                            buf[0][row * kLda + col] = o[e];
                         }
                     }
+                    if (TRAIN) store_frag_T(d.eT4, d.Bp, b0, 16 * i + 4 * (lane >> 4), col, o);
+                }
         }
         if (!TRAIN) return;
         load_frag(d.W4t, nh, g4, lane);
@@ -336,31 +364,43 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
         for (int q = 0; q < kFwdWaves; ++q) sl += red[q];
         d.lossp[blockIdx.x] = sl;
     }
-    store_transposed(buf[0], kMlpOutPad, d.eT4, d.Bp, b0, tid);
 
     BFrag<kMlpHid, kHidCT> g3;
     load_frag(d.W3t, nh, g3, lane);
-    hidden_backward<kMlpOutPad>(buf[0], g4, z3, buf[1], w, lane);
+    hidden_backward<kMlpOutPad>(buf[0], g4, z3, buf[1], w, lane, d.eT3, d.Bp, b0);
     __syncthreads();
-    store_transposed(buf[1], kMlpHid, d.eT3, d.Bp, b0, tid);
     BFrag<kMlpHid, kHidCT> g2;
     load_frag(d.W2t, nh, g2, lane);
-    hidden_backward<kMlpHid>(buf[1], g3, z2, buf[0], w, lane);
+    hidden_backward<kMlpHid>(buf[1], g3, z2, buf[0], w, lane, d.eT2, d.Bp, b0);
     __syncthreads();
-    store_transposed(buf[0], kMlpHid, d.eT2, d.Bp, b0, tid);
-    hidden_backward<kMlpHid>(buf[0], g2, z1, buf[1], w, lane);
-    __syncthreads();
-    store_transposed(buf[1], kMlpHid, d.eT1, d.Bp, b0, tid);
+    hidden_backward<kMlpHid>(buf[0], g2, z1, nullptr, w, lane, d.eT1, d.Bp, b0);
 }
 
-// Adam step of parameter i with gradient g (a.update != 0), then its BF16
-// copies: W row-major and, for layers 2-4, the transposes
-__device__ __forceinline__ void adam_param(const MlpDev& d, int i, float g, const MlpAdam& a)
+// Adam state of one parameter, read before its gradient is known
+struct AdamState {
+    float th, m, v;
+};
+__device__ __forceinline__ AdamState adam_load(const MlpDev& d, int i, const MlpAdam& a)
 {
-    float th = d.theta[i];
+    AdamState s{d.theta[i], 0.0f, 0.0f};
     if (a.update) {
-        const float m = a.beta1 * d.m[i] + (1.0f - a.beta1) * g;
-        const float v = a.beta2 * d.v[i] + (1.0f - a.beta2) * g * g;
+        s.m = d.m[i];
+        s.v = d.v[i];
+    }
+    return s;
+}
+
+// Adam step of parameter i with gradient g (a.update != 0) from its state
+// s, then its BF16 copies: W row-major and, for layers 2-4, the transposes.
+// No multiply-add contraction, so that the fused step in the
+// weight-gradient launch and the separate Adam launch round alike.
+__device__ __forceinline__ void adam_apply(const MlpDev& d, int i, float g, const MlpAdam& a, AdamState s)
+{
+#pragma clang fp contract(off)
+    float th = s.th;
+    if (a.update) {
+        const float m = a.beta1 * s.m + (1.0f - a.beta1) * g;
+        const float v = a.beta2 * s.v + (1.0f - a.beta2) * g * g;
         th -= a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
         d.m[i] = m;
         d.v[i] = v;
@@ -388,21 +428,22 @@ __device__ __forceinline__ void adam_param(const MlpDev& d, int i, float g, cons
 // Weight and bias gradients dW_l = e_l^T a_{l-1}, db_l = e_l^T 1 (a
 // contraction over the batch).  Tiles of 32 x 32 of the gradient matrices:
 // layer 1 8 (256 x 32 padded), layers 2, 3 64 each, layer 4 32 (128 padded
-// x 256).  A workgroup takes one tile; its 4 waves split the batch (in
-// k-steps of 32 rows, kWgradChunk requested together) and add their
-// partial tiles in LDS, in wave order.  The tiles of the first column also
-// form the bias gradients on the matrix cores, from the same e fragments
-// times a fragment of ones (every column of that product is db).  The
-// workgroup writes the gradient (and, fused, its Adam step) as its tile
-// completes.  (Splitting the batch over workgroups as well, with a second
-// launch summing the slices, measured no faster at 512 or 4096 rows.)
+// x 256).  A workgroup takes one tile; its 16 waves split the batch (in
+// k-steps of 32 rows, kWgradChunk requested together), so that a CU has
+// sixteen waves' loads in flight, and add their partial tiles in LDS, in
+// wave order.  The tiles of the first column also form the bias gradients
+// on the matrix cores, from the same e fragments times a fragment of ones
+// (every column of that product is db).  Every thread then finishes one
+// element of the tile: the gradient and, fused, its Adam step, whose state
+// it requested at the start (that latency overlaps the contraction).
 constexpr int kWgradTiles = 8 + 64 + 64 + 32;
-constexpr int kWgradWaves = 4;
+constexpr int kWgradWaves = 16;
 constexpr int kWgradChunk = 4;    // k-steps of 32 rows requested together
 
 __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, int B, float* loss, int fuse,
                                                                      MlpAdam adam)
 {
+    static_assert(64 * kWgradWaves == 32 * 32, "one thread per element of a tile");
     __shared__ float part[kWgradWaves][32 * 32];
     __shared__ float bpart[kWgradWaves][32];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -421,17 +462,28 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
         t -= 136;
         E = d.eT4; Act = d.aT3; nreal = kMlpOut; kreal = kMlpHid; woff = kOffW4; boff = kOffB4; tm = t / 8; tn = t % 8;
     }
+    const int m0 = tm * 32, n0 = tn * 32, Bp = d.Bp;
+    const bool bias = tn == 0;
+    // the element this thread finishes (row rl, column cl of the tile) and,
+    // on bias tiles, threads 0..31 also bias m0 + tid: their Adam state now
+    const int rl = tid >> 5, cl = tid & 31;
+    const bool own = m0 + rl < nreal && n0 + cl < kreal;
+    const int pw = woff + (m0 + rl) * kreal + n0 + cl;
+    const bool ownb = bias && tid < 32 && m0 + tid < nreal;
+    const int pb = boff + m0 + tid;
+    AdamState sw{0.0f, 0.0f, 0.0f}, sb{0.0f, 0.0f, 0.0f};
+    if (fuse && own) sw = adam_load(d, pw, adam);
+    if (fuse && ownb) sb = adam_load(d, pb, adam);
+
     // rows of this batch: the forward workgroups covered ceil(B / 64) * 64
     // (rows past B carry e = 0); later rows of the buffers are stale.  This
     // wave's k-steps of 32 rows: [s0, s1) of Bb / 32
-    const int m0 = tm * 32, n0 = tn * 32, Bp = d.Bp;
     const int nb = (B + kMlpRows - 1) / kMlpRows, Bb = nb * kMlpRows;
     const int P = Bb / 32, per = (P + kWgradWaves - 1) / kWgradWaves;
     const int s0 = min(P, w * per), s1 = min(P, s0 + per);
     const int r = lane & 15, kg = (lane >> 4) * 8;
     const uint16_t* ea[2] = {E + (size_t)(m0 + r) * Bp + kg, E + (size_t)(m0 + 16 + r) * Bp + kg};
     const uint16_t* ab[2] = {Act + (size_t)(n0 + r) * Bp + kg, Act + (size_t)(n0 + 16 + r) * Bp + kg};
-    const bool bias = tn == 0;
     v4f acc[2][2], accb[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -463,9 +515,8 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
                     if (bias) accb[i] = mfma32(a[q][i], ones, accb[i]);
                 }
     }
-    // every wave's partial tile (and db column) into LDS; then wave w
-    // finishes fragment (w div 2, w mod 2) of the tile: the sum over the
-    // waves in wave order, the gradient and, fused, its Adam step
+    // every wave's partial tile (and db column) into LDS; then every
+    // thread sums its element over the waves in wave order
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -479,27 +530,19 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
 #pragma unroll
             for (int e = 0; e < 4; ++e) bpart[w][16 * i + 4 * (lane >> 4) + e] = accb[i][e];
     __syncthreads();
-    {
-        const int fi = w >> 1, fj = w & 1;
+    if (own) {
+        float v = part[0][tid];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int rl = 16 * fi + 4 * (lane >> 4) + e, cl = 16 * fj + r;
-            float v = part[0][rl * 32 + cl];
-#pragma unroll
-            for (int q = 1; q < kWgradWaves; ++q) v += part[q][rl * 32 + cl];
-            if (m0 + rl < nreal && n0 + cl < kreal) {
-                const int p = woff + (m0 + rl) * kreal + n0 + cl;
-                d.grad[p] = v;
-                if (fuse) adam_param(d, p, v, adam);
-            }
-        }
+        for (int q = 1; q < kWgradWaves; ++q) v += part[q][tid];
+        d.grad[pw] = v;
+        if (fuse) adam_apply(d, pw, v, adam, sw);
     }
-    if (bias && w == kWgradWaves - 1 && lane < 32 && m0 + lane < nreal) {
-        float sb = bpart[0][lane];
+    if (ownb) {
+        float v = bpart[0][tid];
 #pragma unroll
-        for (int q = 1; q < kWgradWaves; ++q) sb += bpart[q][lane];
-        d.grad[boff + m0 + lane] = sb;
-        if (fuse) adam_param(d, boff + m0 + lane, sb, adam);
+        for (int q = 1; q < kWgradWaves; ++q) v += bpart[q][tid];
+        d.grad[pb] = v;
+        if (fuse) adam_apply(d, pb, v, adam, sb);
     }
     // the loss: the forward workgroups' sums reduced by workgroup 0 (every
     // thread a strided share, then the waves' shuffles and LDS), not by one
@@ -525,7 +568,7 @@ __global__ void mlp_adam_kernel(MlpDev d, MlpAdam a)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kMlpParams) return;
-    adam_param(d, i, a.update ? d.grad[i] : 0.0f, a);
+    adam_apply(d, i, a.update ? d.grad[i] : 0.0f, a, adam_load(d, i, a));
 }
 
 __global__ void mlp_features_kernel(MlpDev d, int n, const double* __restrict__ q, const double* __restrict__ qd,
