@@ -28,10 +28,11 @@
 // step, one 16-byte read per operand; the FP32 result holds column
 // (l mod 16), rows 4 (l div 16) + 0..3.  Every operand is read with k
 // contiguous: A from the LDS tile [row][k] (row stride 264 BF16: the 16
-// rows of a lane group start on distinct banks), B^T from the row-major
-// weights [n][k] (forward) or from their stored transposes (backward),
-// both operands of the weight gradient from the transposed
-// [feature][batch] buffers.
+// rows of a lane group start on distinct banks), B^T from the weights
+// [n][k] (forward) or from their stored transposes (backward), both
+// operands of the weight gradient from the transposed [feature][batch]
+// buffers; the global ones are kept in operand order (frag_index), one
+// contiguous 1 KB read per fragment.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -95,10 +96,23 @@ __device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c)
 
 constexpr int kRT = kMlpWgRows / 16;   // row tiles per workgroup
 
+// Matrix-core operand order of a BF16 matrix [N][K] read as k-contiguous
+// 16 x 32 fragments (the weights, their transposes, and the transposed
+// activations and signals [feature][batch]): element (n, k) sits at
+// ((n div 16) (K / 32) + k div 32) 512 + (n mod 16 + 16 ((k mod 32) div 8)) 8
+// + k mod 8, so the fragment of column tile n div 16 and k-step k div 32 is
+// 1 KB contiguous and lane l reads its 16 bytes at 16 l (a row-major layout
+// spreads the same fragment over 16 half-used cache lines, which measured
+// 2.3 times slower to fetch).  K is a multiple of 32.
+__device__ __forceinline__ size_t frag_index(int n, int k, int K)
+{
+    return ((size_t)(n >> 4) * (K >> 5) + (k >> 5)) * 512 + ((n & 15) + 16 * ((k & 31) >> 3)) * 8 + (k & 7);
+}
+
 // The B fragments of one layer product held by one wave: CT column tiles
-// from output column nb of the global k-contiguous Bt [N][K], in k-steps of
-// 32 (16 x 16 x 32 products); every lane reads 16 contiguous bytes per
-// fragment.  The kernels request a layer's fragments one layer ahead, so
+// from output column nb of Bt [N][K] in operand order (frag_index), in
+// k-steps of 32 (16 x 16 x 32 products); each fragment is one contiguous
+// 1 KB read.  The kernels request a layer's fragments one layer ahead, so
 // their memory latency overlaps the previous layer's products.
 template <int K, int CT> struct BFrag {
     static_assert(K % 32 == 0, "the contraction runs in chunks of 32");
@@ -107,12 +121,11 @@ template <int K, int CT> struct BFrag {
 template <int K, int CT>
 __device__ __forceinline__ void load_frag(const uint16_t* __restrict__ Bt, int nb, BFrag<K, CT>& f, int lane)
 {
-    const int r = lane & 15, kg = (lane >> 4) * 8;
 #pragma unroll
     for (int t = 0; t < K / 32; ++t)
 #pragma unroll
         for (int j = 0; j < CT; ++j)
-            f.b[t][j] = *reinterpret_cast<const v8s*>(Bt + (size_t)(nb + 16 * j + r) * K + 32 * t + kg);
+            f.b[t][j] = *reinterpret_cast<const v8s*>(Bt + ((size_t)((nb >> 4) + j) * (K / 32) + t) * 512 + lane * 8);
     // issue the loads here, not next to their products
     __builtin_amdgcn_sched_barrier(0);
 }
@@ -145,19 +158,20 @@ __device__ __forceinline__ void store_transposed(const uint16_t* tile, int ncols
 {
     for (int i = tid; i < ncols * kMlpWgRows; i += kThreads) {
         const int c = i / kMlpWgRows, r = i % kMlpWgRows;
-        dst[(size_t)c * Bp + b0 + r] = tile[r * kLda + c];
+        dst[frag_index(c, b0 + r, Bp)] = tile[r * kLda + c];
     }
 }
 
 // One result fragment's four BF16 values (column col, rows row0 + 0..3 of
-// the workgroup's 16) into the transposed global buffer [feature][Bp]: the
-// four rows are contiguous there, so one 8-byte store per lane.
+// the workgroup's 16, row0 a multiple of 4) into the transposed global
+// buffer [feature][Bp] in operand order: the four rows are contiguous there,
+// so one 8-byte store per lane.
 __device__ __forceinline__ void store_frag_T(uint16_t* dstT, int Bp, int b0, int row0, int col, const uint16_t (&o)[4])
 {
     uint2 v;
     v.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
     v.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
-    *reinterpret_cast<uint2*>(dstT + (size_t)col * Bp + b0 + row0) = v;
+    *reinterpret_cast<uint2*>(dstT + frag_index(col, b0 + row0, Bp)) = v;
 }
 
 // this wave's bias values of a hidden layer (columns nb + 16 j + lane mod 16)
@@ -234,18 +248,33 @@ __device__ __forceinline__ void hidden_backward(const uint16_t* E, const BFrag<K
 }
 
 // Feature c (0..20) of state p: q / q_max, qd / qd_max, p_des, then the
-// unit target quaternion with w >= 0 (the proposal's input encoding).
-__device__ __forceinline__ float state_feature(const MlpDev& d, const double* __restrict__ q,
+// unit target quaternion with w >= 0 (the proposal's input encoding), in
+// two halves: feature_load issues the loads, feature_value forms the value
+// once they have arrived (so a kernel can request other operands between).
+struct FeatIn {
+    double v, s, qw, qx, qy, qz;
+};
+__device__ __forceinline__ FeatIn feature_load(const MlpDev& d, const double* __restrict__ q,
                                                const double* __restrict__ qd, const double* __restrict__ target,
                                                int p, int c)
 {
-    if (c < 7) return (float)(q[p * 7 + c] / d.scale[c]);
-    if (c < 14) return (float)(qd[p * 7 + c - 7] / d.scale[c]);
+    // every load unconditional (a select of the address), so that no
+    // branch has to wait for them
     const double* tg = target + (size_t)p * 13;
-    if (c < 17) return (float)tg[c - 14];
-    const double nrm = sqrt(tg[3] * tg[3] + tg[4] * tg[4] + tg[5] * tg[5] + tg[6] * tg[6]);
-    const double sg = (tg[3] < 0.0 ? -1.0 : 1.0) / nrm;
-    return (float)(tg[c - 14] * sg);
+    const double* src = c < 7 ? q + p * 7 + c : (c < 14 ? qd + p * 7 + (c - 7) : tg + (c - 14));
+    FeatIn f;
+    f.v = *src;
+    f.s = d.scale[c < 14 ? c : 0];
+    f.qw = tg[3]; f.qx = tg[4]; f.qy = tg[5]; f.qz = tg[6];
+    return f;
+}
+__device__ __forceinline__ float feature_value(const FeatIn& f, int c)
+{
+    if (c < 14) return (float)(f.v / f.s);
+    if (c < 17) return (float)f.v;
+    const double nrm = sqrt(f.qw * f.qw + f.qx * f.qx + f.qy * f.qy + f.qz * f.qz);
+    const double sg = (f.qw < 0.0 ? -1.0 : 1.0) / nrm;
+    return (float)(f.v * sg);
 }
 
 template <bool TRAIN>
@@ -263,7 +292,21 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
     const float* th = d.theta;
 
     const int nh = w * 16 * kHidCT;   // this wave's first column of a hidden layer
-    // the first two layers' operands, requested before the input tile
+    // a_0 = bf16(x), x from X or (X null) encoded here from the states
+    // (one element per thread; feature columns 21..31 and rows past B are
+    // zero): its loads first, then the first two layers' operands, and only
+    // then the input tile's values (the loads return in order)
+    static_assert(kMlpWgRows * kMlpInPad <= kThreads, "one input element per thread");
+    const int ir = tid / kMlpInPad, ic = tid % kMlpInPad;
+    const bool has_x = tid < kMlpWgRows * kMlpInPad && ic < kMlpIn && b0 + ir < B;
+    // the element's indices clamped to a valid one, so that the loads need
+    // no branch (has_x decides below whether the value is used)
+    const int pr = min(b0 + ir, B - 1), pc = min(ic, kMlpIn - 1);
+    float xv = 0.0f;
+    FeatIn fin{0.0, 1.0, 0.0, 0.0, 0.0, 0.0};
+    if (TRAIN || X) xv = X[(size_t)pr * kMlpIn + pc];   // training always has X
+    else fin = feature_load(d, sq, sqd, stg, pr, pc);
+    __builtin_amdgcn_sched_barrier(0);
     BFrag<kMlpInPad, kHidCT> f1;
     BFrag<kMlpHid, kHidCT> f2;
     float bv1[kHidCT], bv2[kHidCT];
@@ -271,15 +314,11 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
     load_bias(th + kOffB1, nh, bv1, lane);
     load_frag(d.W2, nh, f2, lane);
     load_bias(th + kOffB2, nh, bv2, lane);
-
-    // a_0 = bf16(x), x from X or (X null) encoded here from the states;
-    // feature columns 21..31 and rows past B are zero
-    for (int i = tid; i < kMlpWgRows * kMlpInPad; i += kThreads) {
-        const int r = i / kMlpInPad, c = i % kMlpInPad;
+    __builtin_amdgcn_sched_barrier(0);
+    if (tid < kMlpWgRows * kMlpInPad) {
         float x = 0.0f;
-        if (c < kMlpIn && b0 + r < B)
-            x = X ? X[(size_t)(b0 + r) * kMlpIn + c] : state_feature(d, sq, sqd, stg, b0 + r, c);
-        buf[0][r * kLda + c] = to_bf16(x);
+        if (has_x) x = (TRAIN || X) ? xv : feature_value(fin, pc);
+        buf[0][ir * kLda + ic] = to_bf16(x);
     }
     __syncthreads();
     if (TRAIN) store_transposed(buf[0], kMlpInPad, d.aT0, d.Bp, b0, tid);
@@ -300,12 +339,14 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
     constexpr int NO = 16 * kOutCT;
     BFrag<kMlpHid, kOutCT> f4;
     float b4[kOutCT], yt[kRT][kOutCT][4];
+    double us[kOutCT];   // inference into U: the torque limit of the column's joint
     if (w < kOutWaves) {
         load_frag(d.W4, w * NO, f4, lane);
 #pragma unroll
         for (int j = 0; j < kOutCT; ++j) {
             const int col = w * NO + 16 * j + (lane & 15);
             b4[j] = col < kMlpOut ? th[kOffB4 + col] : 0.0f;
+            us[j] = (!TRAIN && U) ? d.scale[14 + col % 7] : 0.0;
 #pragma unroll
             for (int i = 0; i < kRT; ++i)
 #pragma unroll
@@ -337,9 +378,9 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(MlpDev d, const f
                         const int row = 16 * i + 4 * (lane >> 4) + e;
                         const bool valid = col < kMlpOut && b0 + row < B;
                         const float y = acc[i][j][e] + b4[j];
-                        if (valid) {
+                        if (!TRAIN && valid) {   // training writes neither
                             if (Y) Y[(size_t)(b0 + row) * kMlpOut + col] = y;
-                            if (U) U[(size_t)(b0 + row) * u_stride + col] = d.scale[14 + col % 7] * (double)y;
+                            if (U) U[(size_t)(b0 + row) * u_stride + col] = us[j] * (double)y;
                         }
                         if (TRAIN) {
                             const float res = valid ? y - yt[i][j][e] : 0.0f;
@@ -409,19 +450,19 @@ __device__ __forceinline__ void adam_apply(const MlpDev& d, int i, float g, cons
     const uint16_t h = to_bf16(th);
     if (i < kOffB1) {
         const int n = i / kMlpIn, k = i % kMlpIn;
-        d.W1[n * kMlpInPad + k] = h;
+        d.W1[frag_index(n, k, kMlpInPad)] = h;
     } else if (i >= kOffW2 && i < kOffB2) {
         const int j = i - kOffW2, n = j / kMlpHid, k = j % kMlpHid;
-        d.W2[n * kMlpHid + k] = h;
-        d.W2t[k * kMlpHid + n] = h;
+        d.W2[frag_index(n, k, kMlpHid)] = h;
+        d.W2t[frag_index(k, n, kMlpHid)] = h;
     } else if (i >= kOffW3 && i < kOffB3) {
         const int j = i - kOffW3, n = j / kMlpHid, k = j % kMlpHid;
-        d.W3[n * kMlpHid + k] = h;
-        d.W3t[k * kMlpHid + n] = h;
+        d.W3[frag_index(n, k, kMlpHid)] = h;
+        d.W3t[frag_index(k, n, kMlpHid)] = h;
     } else if (i >= kOffW4 && i < kOffB4) {
         const int j = i - kOffW4, n = j / kMlpHid, k = j % kMlpHid;
-        d.W4[n * kMlpHid + k] = h;
-        d.W4t[k * kMlpOutPad + n] = h;
+        d.W4[frag_index(n, k, kMlpHid)] = h;
+        d.W4t[frag_index(k, n, kMlpOutPad)] = h;
     }
 }
 
@@ -481,9 +522,11 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
     const int nb = (B + kMlpRows - 1) / kMlpRows, Bb = nb * kMlpRows;
     const int P = Bb / 32, per = (P + kWgradWaves - 1) / kWgradWaves;
     const int s0 = min(P, w * per), s1 = min(P, s0 + per);
-    const int r = lane & 15, kg = (lane >> 4) * 8;
-    const uint16_t* ea[2] = {E + (size_t)(m0 + r) * Bp + kg, E + (size_t)(m0 + 16 + r) * Bp + kg};
-    const uint16_t* ab[2] = {Act + (size_t)(n0 + r) * Bp + kg, Act + (size_t)(n0 + 16 + r) * Bp + kg};
+    // operand order (frag_index): row tile m, k-step s at (m (Bp / 32) + s) 512
+    const int r = lane & 15;
+    const size_t ts = (size_t)(Bp / 32) * 512;
+    const uint16_t* ea[2] = {E + (size_t)(m0 >> 4) * ts + lane * 8, E + (size_t)((m0 >> 4) + 1) * ts + lane * 8};
+    const uint16_t* ab[2] = {Act + (size_t)(n0 >> 4) * ts + lane * 8, Act + (size_t)((n0 >> 4) + 1) * ts + lane * 8};
     v4f acc[2][2], accb[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -501,8 +544,8 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
             if (q < ns)
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                    a[q][i] = *reinterpret_cast<const v8s*>(ea[i] + 32 * (st + q));
-                    b[q][i] = *reinterpret_cast<const v8s*>(ab[i] + 32 * (st + q));
+                    a[q][i] = *reinterpret_cast<const v8s*>(ea[i] + (size_t)(st + q) * 512);
+                    b[q][i] = *reinterpret_cast<const v8s*>(ab[i] + (size_t)(st + q) * 512);
                 }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -580,7 +623,7 @@ __global__ void mlp_features_kernel(MlpDev d, int n, const double* __restrict__ 
     if (U && Y)   // normalised training targets y* = U* / tau_max
         for (int c = 0; c < kMlpOut; ++c) Y[(size_t)p * kMlpOut + c] = (float)(U[(size_t)p * u_stride + c] / d.scale[14 + c % 7]);
     float* x = X + (size_t)p * kMlpIn;
-    for (int c = 0; c < kMlpIn; ++c) x[c] = state_feature(d, q, qd, target, p, c);
+    for (int c = 0; c < kMlpIn; ++c) x[c] = feature_value(feature_load(d, q, qd, target, p, c), c);
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }

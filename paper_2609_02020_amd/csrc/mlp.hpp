@@ -33,9 +33,11 @@ static_assert(kMlpParams == 169598, "parameter count");
 // [256][128] (columns 126, 127 zero) feed the backward products.
 // Training scratch holds one batch of up to Bp rows (a multiple of 64):
 // activations a_l and backward signals e_l stored transposed ([features][Bp],
-// BF16) for the weight-gradient contraction over the batch (the
+// BF16) for the weight-gradient contraction over the batch.  Every one of
+// these [N][K] matrices is stored in matrix-core operand order (16 x 32
+// fragments of 1 KB, mlp.hip frag_index), not row-major.  The
 // pre-activations that GELU' needs stay in the registers of the thread that
-// computed them).
+// computed them.
 struct MlpDev {
     float* theta;     // [P] FP32 master parameters
     float* m;         // [P] Adam first moment
