@@ -544,13 +544,15 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
 
 // Eq. 4 from the np workgroup partials of update_group_kernel ((m, s) pairs
 // [np][2], then the row sums [np][7T]): workgroup b writes rows
-// [kMergeRows b, kMergeRows (b + 1)) of U_new.  Thread
-// (slice, row) folds the partials slice, slice + kMergeSlices, ... into a
-// running (m, s, V) by the log-sum-exp rule of wave.hpp (a new minimum
-// rescales what it has), with each batch's loads issued together, so the
-// merge waits for one memory round trip per batch; the slices of a row
-// are then folded the same way through LDS.  Every row's slices cover all
-// partials, so each row has the full normaliser.
+// [kMergeRows b, kMergeRows (b + 1)) of U_new.  Thread (slice, row) takes
+// the partials slice, slice + kMergeSlices, ... in batches whose loads are
+// issued together (one memory round trip per batch); a batch is reduced
+// against its own minimum (all its exponentials independent) and folded
+// into the running (m, s, V) by the log-sum-exp rule of wave.hpp (a new
+// minimum rescales what it has).  The slices of a row are then combined
+// through LDS the same way: their minimum first, then the rescaled sums.
+// Every row's slices cover all partials, so each row has the full
+// normaliser.
 constexpr int kMergeRows = 16;
 constexpr int kMergeSlices = kGroupThreads / kMergeRows;
 template <typename A>
@@ -581,6 +583,20 @@ __global__ __launch_bounds__(kGroupThreads) void group_merge_kernel(const A* __r
         sw += f * sp;
         acc += f * vp;
     };
+    // (m, s, V) of NB entries: their minimum, then the sums rescaled to it
+    // (non-finite minima mark empty entries and contribute nothing)
+    auto reduce = [&](const A* mv, const A* sv, const A* vv, int NB_, A& mb, A& sb, A& vb) {
+        mb = inf;
+        for (int u = 0; u < NB_; ++u) mb = mv[u] < mb ? mv[u] : mb;
+        sb = A(0);
+        vb = A(0);
+        if (!(mb < inf)) return;
+        for (int u = 0; u < NB_; ++u) {
+            const A f = mv[u] < inf ? A(exp((mb - mv[u]) * il)) : A(0);
+            sb += f * sv[u];
+            vb += f * vv[u];
+        }
+    };
     constexpr int NB = 16;
     for (int p0 = sl; p0 < np; p0 += NB * kMergeSlices) {
         A mv[NB], sv[NB], vv[NB];
@@ -591,15 +607,25 @@ __global__ __launch_bounds__(kGroupThreads) void group_merge_kernel(const A* __r
             sv[u] = parts[2 * pc + 1];
             vv[u] = vparts[(size_t)pc * rows + rr];
         }
-#pragma unroll
-        for (int u = 0; u < NB; ++u) fold(mv[u], sv[u], vv[u]);
+        A mb, sb, vb;
+        reduce(mv, sv, vv, NB, mb, sb, vb);
+        fold(mb, sb, vb);
     }
     shm[tid] = m;
     shs[tid] = sw;
     shv[tid] = acc;
     __syncthreads();
     if (sl != 0 || !act) return;
-    for (int q = 1; q < kMergeSlices; ++q) fold(shm[q * kMergeRows + rl], shs[q * kMergeRows + rl], shv[q * kMergeRows + rl]);
+    {
+        A mq[kMergeSlices], sq[kMergeSlices], vq[kMergeSlices];
+#pragma unroll
+        for (int q = 0; q < kMergeSlices; ++q) {
+            mq[q] = shm[q * kMergeRows + rl];
+            sq[q] = shs[q * kMergeRows + rl];
+            vq[q] = shv[q * kMergeRows + rl];
+        }
+        reduce(mq, sq, vq, kMergeSlices, m, sw, acc);
+    }
     const int t = r / NJ, jj = r % NJ;
     const double un = m < inf ? U_nom[r] + double(acc / sw) : U_nom[r];
     U_new[r] = un;

@@ -69,8 +69,8 @@ def run(ora, d, ep, with_collision):
 def test_moving_obstacle_is_avoided(ora):
     """Eight held-out episodes with and without the term.  Every closed loop
     stays bounded (finite state, some finite sampled cost at the last
-    tick) in both runs, and in every episode the links spend less time
-    inside the 0.2 m zone with the term than without it; over the episodes
+    tick) in both runs, and in every episode that enters the 0.2 m zone
+    the links spend less time inside it with the term than without; over the episodes
     the zone time with the term is under 0.6 of that without, and the
     closest approach is larger on average.  (The indicator of Eq. 15
     carries no preference once every sampled trajectory is inside a pair's
@@ -87,7 +87,10 @@ def test_moving_obstacle_is_avoided(ora):
               flush=True)
     for e in range(8):
         assert on[e][2] and off[e][2], "episode %d diverged" % e
-        assert on[e][1] < off[e][1], (e, on[e][1], off[e][1])
+        # equal only where neither run enters the zone (the closed loops
+        # are chaotic: a rounding-level change in the update can send an
+        # episode's arm away from the obstacle's path)
+        assert on[e][1] < off[e][1] or on[e][1] == off[e][1] == 0, (e, on[e][1], off[e][1])
     zone_on, zone_off = sum(r[1] for r in on), sum(r[1] for r in off)
     assert zone_on <= 0.6 * zone_off, (zone_on, zone_off)
     assert np.mean([r[0] for r in on]) >= np.mean([r[0] for r in off]) + 0.02
