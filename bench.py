@@ -55,14 +55,17 @@ FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (AMD published)
 # known size (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 on gfx950), taken on the
 # kernel sources whose digest is recorded here; reported as null once the
 # sources differ.
-PROFILED_DIGEST = "a3e2c33ac5101ff5"
-PROFILED_TRAFFIC = {"update_group_kernel": 540775 + 582802,    # K=4096, T=18 contact workload: the
-                                                            # group kernel and its merge launch
+PROFILED_DIGEST = "741248ad8d4c247d"
+PROFILED_TRAFFIC = {"update_group_kernel": 368753 + 159744 + 529676 + 1925,   # K=4096, T=18 contact workload:
+                                                            # the group kernel and its merge launch
                     # 64-problem batch, per launch shape the autotuner may pick (waves per
-                    # group x groups); mostly register-spill stores of the resident waves
-                    "batch_kernel_w2x1024": 39506304 + 353603621,
-                    "batch_kernel_w1x2048": 36323680 + 312411208,
-                    "mlp_train": 12573897 + 2416160}        # forward/backward + weight gradients, 512 rows
+                    # group x groups); the one-lane shapes mostly register-spill stores
+                    "batch_kernel_w1x2048": 98897306 + 322193920,
+                    "batch_kernel_w2x1024": 122571162 + 366253056,
+                    "batch_kernel_w4x512": 107749990 + 336444672,
+                    "batch_kernel_w8x256": 6292275 + 8601242,    # eight lanes per sample
+                    "mlp_train": 5864448 + 1737728 + 6668288 + 678400}   # forward/backward + weight
+                                                                          # gradients, 512 rows
 
 
 def kernel_source_digest():
