@@ -488,20 +488,31 @@ __global__ __launch_bounds__(64 * kWgradWaves) void mlp_wgrad_kernel(MlpDev d, i
     __shared__ float part[kWgradWaves][32 * 32];
     __shared__ float bpart[kWgradWaves][32];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // Tile of this workgroup.  Workgroup b runs on XCD b mod 8 and every
+    // layer's range starts at a multiple of 8, so within a layer x = t mod
+    // 8 is the XCD: the tiles of a layer are laid out 2 x 4 over the XCDs
+    // (a layer of 8 x 8 tiles gives each XCD 4 row blocks of E by 2 of the
+    // activations, the 4 x 8 layer 2 x 2), so that an XCD's L2 fetches
+    // half of E and a quarter of the activations instead of all of one.
     int t = blockIdx.x;
     const uint16_t *E, *Act;
     int nreal, kreal, woff, boff, tm, tn;
+    auto place = [&](int tt, int rows_per) {   // rows_per: row blocks of E per XCD row
+        const int x = tt % 8, slot = tt / 8;
+        tm = (x / 4) * rows_per + slot / 2;
+        tn = (x % 4) * 2 + slot % 2;
+    };
     if (t < 8) {
         E = d.eT1; Act = d.aT0; nreal = kMlpHid; kreal = kMlpIn; woff = kOffW1; boff = kOffB1; tm = t; tn = 0;
     } else if (t < 72) {
-        t -= 8;
-        E = d.eT2; Act = d.aT1; nreal = kMlpHid; kreal = kMlpHid; woff = kOffW2; boff = kOffB2; tm = t / 8; tn = t % 8;
+        E = d.eT2; Act = d.aT1; nreal = kMlpHid; kreal = kMlpHid; woff = kOffW2; boff = kOffB2;
+        place(t - 8, 4);
     } else if (t < 136) {
-        t -= 72;
-        E = d.eT3; Act = d.aT2; nreal = kMlpHid; kreal = kMlpHid; woff = kOffW3; boff = kOffB3; tm = t / 8; tn = t % 8;
+        E = d.eT3; Act = d.aT2; nreal = kMlpHid; kreal = kMlpHid; woff = kOffW3; boff = kOffB3;
+        place(t - 72, 4);
     } else {
-        t -= 136;
-        E = d.eT4; Act = d.aT3; nreal = kMlpOut; kreal = kMlpHid; woff = kOffW4; boff = kOffB4; tm = t / 8; tn = t % 8;
+        E = d.eT4; Act = d.aT3; nreal = kMlpOut; kreal = kMlpHid; woff = kOffW4; boff = kOffB4;
+        place(t - 136, 2);
     }
     const int m0 = tm * 32, n0 = tn * 32, Bp = d.Bp;
     const bool bias = tn == 0;
