@@ -55,16 +55,16 @@ FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (AMD published)
 # known size (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 on gfx950), taken on the
 # kernel sources whose digest is recorded here; reported as null once the
 # sources differ.
-PROFILED_DIGEST = "741248ad8d4c247d"
-PROFILED_TRAFFIC = {"update_group_kernel": 368753 + 159744 + 529676 + 1925,   # K=4096, T=18 contact workload:
+PROFILED_DIGEST = "2331721c2a097cd6"
+PROFILED_TRAFFIC = {"update_group_kernel": 368713 + 159744 + 529624 + 1925,   # K=4096, T=18 contact workload:
                                                             # the group kernel and its merge launch
                     # 64-problem batch, per launch shape the autotuner may pick (waves per
                     # group x groups); the one-lane shapes mostly register-spill stores
-                    "batch_kernel_w1x2048": 98897306 + 322193920,
-                    "batch_kernel_w2x1024": 122571162 + 366253056,
-                    "batch_kernel_w4x512": 107749990 + 336444672,
-                    "batch_kernel_w8x256": 6292275 + 8601242,    # eight lanes per sample
-                    "mlp_train": 5864448 + 1737728 + 6668288 + 678400}   # forward/backward + weight
+                    "batch_kernel_w1x2048": 99764555 + 323942912,
+                    "batch_kernel_w2x1024": 120688807 + 367947264,
+                    "batch_kernel_w4x512": 106755045 + 335721216,
+                    "batch_kernel_w8x256": 6326924 + 8616545,    # eight lanes per sample
+                    "mlp_train": 5863875 + 1737728 + 4833890 + 678432}   # forward/backward + weight
                                                                           # gradients, 512 rows
 
 
@@ -268,13 +268,16 @@ def collision_bench(B, case, torch, dev, steps=100):
 
 def explicit_bench(B, case, torch, dev, steps=100):
     """The contact workload on both dynamics routes (articulated-body vs M
-    by Eq. 8 with a Cholesky solve): update-kernel time with HIP events."""
+    by Eq. 8 with a Cholesky solve), both on the per-lane launch with one
+    wave per 64 samples (the route of Eq. 8 has no eight-lane form):
+    update-kernel time with HIP events."""
     import numpy as np
     f64 = dict(dtype=torch.float64, device=dev)
     K, T = case["cost"]["K"], case["cost"]["T"]
     res = {}
     for name, dyn in (("aba", B.DYN_ABA), ("explicit_m", B.DYN_EXPLICIT_M)):
         solver = B.Solver(case["robot"], dict(case["cost"], dynamics=dyn), B.FP32)
+        solver.set_launch(1)
         io = {"q": torch.tensor(case["q0"], **f64), "qd": torch.tensor(case["qd0"], **f64),
               "target": torch.tensor(B.target_vector(case["target"]), **f64),
               "U_nominal": torch.tensor(case["U_nom"], **f64), "U_new": torch.empty((T, 7), **f64),
@@ -296,6 +299,7 @@ def explicit_bench(B, case, torch, dev, steps=100):
         solver.close()
     res["flops_per_sample_step"] = {"aba": FLOPS_PER_SAMPLE_STEP, "explicit_m": FLOPS_PER_SAMPLE_STEP_EXPLICIT}
     res["workload"] = "wall_k4096[0], K=%d, T=%d, FP32" % (K, T)
+    res["launch"] = "one wave per 64 samples (per-lane kernels), both routes"
     return res
 
 

@@ -56,10 +56,12 @@ def check_grad(g_gpu, g_ref, label):
             assert err <= G_TOL, (label, name, sl, err)
 
 
-@pytest.mark.parametrize("rows", [1, 63, 64, 200, 512])
+@pytest.mark.parametrize("rows", [1, 63, 64, 200, 512, 2100])
 def test_forward_matches_oracle(workloads, rows):
+    """2100 rows: 132 workgroups of 16 rows, the last one ragged (4
+    rows)."""
     torch, dev = torch_dev()
-    net, theta = make(workloads, 512)
+    net, theta = make(workloads, max(512, rows))
     X, _ = inputs.draw_mlp_batch(rows, rows, scale=1.5)
     X = f32(X)
     y = torch.full((rows, 126), float("nan"), device=dev)
@@ -72,10 +74,12 @@ def test_forward_matches_oracle(workloads, rows):
     net.close()
 
 
-@pytest.mark.parametrize("rows", [37, 256, 300, 2000])
+@pytest.mark.parametrize("rows", [37, 256, 300, 2000, 2100])
 def test_gradient_matches_oracle(workloads, rows):
     """2000 rows: 16 k-steps of 32 rows per weight-gradient wave (four load
-    chunks) for the weight and bias gradients."""
+    chunks) for the weight and bias gradients; 2100 rows: a batch that is
+    not a multiple of 64 (padding rows in the last forward workgroups and
+    the last k-step)."""
     torch, dev = torch_dev()
     net, theta = make(workloads, max(512, rows), seed=2)
     X, Y = inputs.draw_mlp_batch(100 + rows, rows)
@@ -91,6 +95,22 @@ def test_gradient_matches_oracle(workloads, rows):
     # and the exact FP64 gradient of the unrounded network points the same way
     _, g_exact = om.loss_and_grad(theta, X, Y, mirror=False)
     assert g_gpu @ g_exact / np.linalg.norm(g_gpu) / np.linalg.norm(g_exact) > 0.999
+    net.close()
+
+
+def test_forward_rows_independent_of_batch(workloads):
+    """Rows never mix in the forward pass, so the first 500 rows of a
+    2100-row batch get the bits that a 500-row batch gives them."""
+    torch, dev = torch_dev()
+    net, _ = make(workloads, 2100, seed=4)
+    X, Y = inputs.draw_mlp_batch(77, 2100)
+    Xd = to_dev(torch, dev, X)
+    y_big = torch.zeros((2100, 126), device=dev)
+    y_small = torch.zeros((500, 126), device=dev)
+    net.forward_async(Xd, y_big)
+    net.forward_async(Xd[:500].contiguous(), y_small)
+    torch.cuda.synchronize()
+    assert torch.equal(y_big[:500], y_small)
     net.close()
 
 
