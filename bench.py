@@ -85,6 +85,20 @@ def profiled_traffic(kernel):
     return PROFILED_TRAFFIC.get(kernel) if kernel_source_digest() == PROFILED_DIGEST else None
 
 
+def span_ms(torch, stream, fn, n):
+    """Mean GPU time per call of fn(i), i = 0..n-1, launched back to back:
+    one pair of HIP events around all n calls (events around each call put
+    their own packets between the launches, ~2 us of queue time per pair)."""
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for i in range(n):
+        fn(i)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / n
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -237,7 +251,6 @@ def mlp_bench(B, inputs, robot, torch, dev, reps=50, rows=512):
 def collision_bench(B, case, torch, dev, steps=100):
     """The contact workload with the collision term of Eqs. 14-15 (two
     obstacles, 20 pairs): device-resident updates timed with HIP events."""
-    import numpy as np
     solver = B.Solver(case["robot"], case["cost"], B.FP32)
     f64 = dict(dtype=torch.float64, device=dev)
     K, T = case["cost"]["K"], case["cost"]["T"]
@@ -250,15 +263,11 @@ def collision_bench(B, case, torch, dev, steps=100):
     for i in range(10):
         io["tick"] = i
         solver.update_async(io, stream)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    torch.cuda.synchronize()
-    for i, (a, b) in enumerate(evs):
+
+    def one(i):
         io["tick"] = 10 + i
-        a.record(stream)
         solver.update_async(io, stream)
-        b.record(stream)
-    torch.cuda.synchronize()
-    ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    ms = span_ms(torch, stream, one, steps)
     solver.close()
     return {"workload": "collision_k4096[0]: the contact workload plus %d obstacles and %d collision pairs "
                         "(w_collision = %g), K=%d, T=%d" % (len(case["cost"]["obstacles"]), len(case["cost"]["pairs"]),
@@ -271,7 +280,6 @@ def explicit_bench(B, case, torch, dev, steps=100):
     by Eq. 8 with a Cholesky solve), both on the per-lane launch with one
     wave per 64 samples (the route of Eq. 8 has no eight-lane form):
     update-kernel time with HIP events."""
-    import numpy as np
     f64 = dict(dtype=torch.float64, device=dev)
     K, T = case["cost"]["K"], case["cost"]["T"]
     res = {}
@@ -287,15 +295,11 @@ def explicit_bench(B, case, torch, dev, steps=100):
         for i in range(10):
             io["tick"] = i
             solver.update_async(io, stream)
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        torch.cuda.synchronize()
-        for i, (a, b) in enumerate(evs):
+
+        def one(i):
             io["tick"] = 10 + i
-            a.record(stream)
             solver.update_async(io, stream)
-            b.record(stream)
-        torch.cuda.synchronize()
-        res[name + "_kernel_ms"] = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        res[name + "_kernel_ms"] = span_ms(torch, stream, one, steps)
         solver.close()
     res["flops_per_sample_step"] = {"aba": FLOPS_PER_SAMPLE_STEP, "explicit_m": FLOPS_PER_SAMPLE_STEP_EXPLICIT}
     res["workload"] = "wall_k4096[0], K=%d, T=%d, FP32" % (K, T)
@@ -307,7 +311,6 @@ def sampling_bench(B, case, torch, dev, steps=100):
     """The contact workload with the sampling variants: independent draws,
     perturbations correlated in time (rho = 0.8) and three MPPI iterations
     per update (three fused launches): GPU time per update with HIP events."""
-    import numpy as np
     f64 = dict(dtype=torch.float64, device=dev)
     K, T = case["cost"]["K"], case["cost"]["T"]
     res = {}
@@ -322,15 +325,11 @@ def sampling_bench(B, case, torch, dev, steps=100):
         for i in range(10):
             io["tick"] = i
             solver.update_async(io, stream)
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        torch.cuda.synchronize()
-        for i, (a, b) in enumerate(evs):
+
+        def one(i):
             io["tick"] = 10 + i
-            a.record(stream)
             solver.update_async(io, stream)
-            b.record(stream)
-        torch.cuda.synchronize()
-        res[name + "_update_ms"] = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        res[name + "_update_ms"] = span_ms(torch, stream, one, steps)
         solver.close()
     res["workload"] = "wall_k4096[0], K=%d, T=%d, FP32" % (K, T)
     return res
@@ -374,18 +373,17 @@ def batch_bench(B, cases, torch, dev, ticks):
     for _ in range(3):
         batch.graph_launch(stream)
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(ticks)]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    for a, b in evs:
-        a.record(stream)
+    a.record(stream)
+    for _ in range(ticks):
         batch.graph_launch(stream)
-        b.record(stream)
+    b.record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = io["status"].cpu().numpy()
     assert (st == B.OK).all(), st
-    tick_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    tick_ms = a.elapsed_time(b) / ticks
     sample_steps = sum(c["cost"]["K"] * c["cost"]["T"] for c in cases)
     flops = sum(problem_flops(c["cost"]) for c in cases)
     batch.close()
@@ -441,7 +439,8 @@ def small_batch_bench(B, cases, torch, dev, reps=50):
 def graph_update_bench(solver, io, torch, reps=200):
     """The device-resident update replayed from a captured HIP graph: the
     launches of one mppi_update_async (with this io's tick) captured on a
-    torch capture stream, each replay bracketed by HIP events."""
+    torch capture stream; the mean from HIP events around all replays, the
+    percentiles from events around each."""
     import numpy as np
     gio = dict(io)
     side = torch.cuda.Stream()
@@ -456,6 +455,7 @@ def graph_update_bench(solver, io, torch, reps=200):
     stream = torch.cuda.current_stream()
     for _ in range(20):
         graph.replay()
+    mean = span_ms(torch, stream, lambda i: graph.replay(), reps)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     for i in range(reps):
         ev[i][0].record(stream)
@@ -464,9 +464,8 @@ def graph_update_bench(solver, io, torch, reps=200):
     torch.cuda.synchronize()
     ms = np.array([a.elapsed_time(b) for a, b in ev])
     graph.reset()
-    return {"update_ms": float(np.mean(ms)),
-            "update_ms_p5_p50_p95": [float(np.percentile(ms, x)) for x in (5, 50, 95)],
-            "update_hz": 1e3 / float(np.mean(ms))}
+    return {"update_ms": mean, "update_hz": 1e3 / mean,
+            "update_ms_p5_p50_p95_events_per_replay": [float(np.percentile(ms, x)) for x in (5, 50, 95)]}
 
 
 def main():
@@ -518,21 +517,31 @@ def main():
         solver.plant_step_async(q, qd, U_new[0], dt, max(1, int(round(dt / 1e-3))), stream)
     torch.cuda.synchronize()
 
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
+    # the timed region: K updates back to back, one pair of HIP events
+    # around all of them on the launch stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record(stream)
     for s in range(args.steps):
-        update(args.warmup + s, evs[s])
+        update(args.warmup + s)
+    ev1.record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    roll_ms = np.array([a.elapsed_time(b) for a, b in evs])
+    update_ms = ev0.elapsed_time(ev1) / args.steps
     status = int(io["status"].cpu()[0])
     assert status == B.OK, status
+    # after it, the spread of single updates, each between its own events
+    nd = min(args.steps, 200)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nd)]
+    for s in range(nd):
+        update(10**6 + s, evs[s])
+    torch.cuda.synchronize()
+    roll_ms = np.array([a.elapsed_time(b) for a, b in evs])
 
     ms_per_step = 1e3 * elapsed / args.steps
     rate = args.steps / elapsed
-    roll_s = float(np.mean(roll_ms)) * 1e-3
+    roll_s = update_ms * 1e-3
     flops = (FLOPS_PER_SAMPLE_STEP * K * T + FLOPS_PER_SAMPLE_TERMINAL * K
              + FLOPS_PER_SAMPLE_ROW_WEIGHT * K * T * 7)
     achieved = flops / roll_s / 1e12
@@ -560,8 +569,8 @@ def main():
                    "dynamics_route": "composite-rigid-body inertia + LDL^T, eight lanes per sample "
                                      "(default launch); the articulated-body route in aba_rollout_steps_per_s"},
         "rollout_steps_per_s": K * T / roll_s,
-        "update_kernel_ms": float(np.mean(roll_ms)),
-        "update_kernel_ms_p5_p50_p95": [float(np.percentile(roll_ms, x)) for x in (5, 50, 95)],
+        "update_kernel_ms": update_ms,
+        "update_kernel_ms_p5_p50_p95_events_per_update": [float(np.percentile(roll_ms, x)) for x in (5, 50, 95)],
         "host_api_update_hz": host_rate,
         "host_api_update_ms_p5_p50_p95": [float(np.percentile(host_ms, x)) for x in (5, 50, 95)],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
@@ -578,15 +587,11 @@ def main():
     # the same update with the other launch shapes, for comparison
     def shape_ms(waves):
         solver.set_launch(waves)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
         for s in range(10):
             update(10**7 + s)
-        for s in range(100):
-            update(10**7 + 10 + s, ev[s])
-        torch.cuda.synchronize()
-        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        return span_ms(torch, stream, lambda i: update(10**7 + 10 + i), 100)
 
-    out["launch_shapes"] = {"eight_lanes_per_sample_ms": float(np.mean(roll_ms)),
+    out["launch_shapes"] = {"eight_lanes_per_sample_ms": update_ms,
                             "two_waves_per_64_samples_ms": shape_ms(2),
                             "one_wave_per_64_samples_ms": shape_ms(1)}
     # the articulated-body route (the per-lane kernels): its fastest shape
@@ -599,7 +604,7 @@ def main():
     # latency-bound at this K: one resident wave per SIMD, T + 1 dependent
     # steps (T rollout steps, then the terminal cost)
     out["roofline"]["waves_resident"] = 4 * ((K + 15) // 16)
-    out["roofline"]["per_step_us_upper"] = 1e3 * float(np.mean(roll_ms)) / (T + 1)
+    out["roofline"]["per_step_us_upper"] = 1e3 * update_ms / (T + 1)
     if args.batch_ticks > 0:
         out["batch"] = batch_bench(B, inputs.load()["batch64"], torch, dev, args.batch_ticks)
         out["batch_small"] = small_batch_bench(B, inputs.load()["batch64"], torch, dev)
