@@ -44,15 +44,15 @@
 //                lanes; the group sums its lanes once, after the horizon.
 //
 // The code is written per lane against a group object G that provides the
-// cross-lane moves (shr<D>: value of lane j - D, invalid lanes masked by the
-// caller; bcast<K>: of lane K; qperm<S>: the lane of its quad that S
-// selects; lo_to_hi / hi_to_lo: lane j - 4 in lanes 4..7 / lane j + 4 in
-// lanes 0..3, 0 elsewhere), sum (over the group),
-// sync() (orders the group's LDS area) and shm (that area, kGxCount
-// values).  On the device G is eight consecutive lanes of a wave (DPP row
-// shifts; a row of 16 lanes holds two groups, so shifts never cross
-// groups unmasked); a host emulation runs the same code on eight threads
-// in lockstep at every cross-lane move.
+// cross-lane moves (shr<D>: value of lane j - D, 0 for j < D; add_shr<D> /
+// add_shl<D>: x plus the value of lane j - D / j + D, plus 0 where there
+// is none; bcast<K>: of lane K), sum (over the group), sync() (orders the
+// group's LDS area) and shm (that area, kGxCount values).  On the device G
+// is eight lanes of a row of 16, two groups interleaved (joint j in lane
+// 2 j + p), so that DPP row shifts by 2 D stay within a group and fill the
+// lanes without a source with 0, and a shift-and-add is one instruction; a
+// host emulation runs the same code on eight threads in lockstep at every
+// cross-lane move.
 #pragma once
 
 #include "rollout.hpp"
@@ -138,33 +138,25 @@ template <int D, typename R, class G> MPPI_HD void scan_frames(const G& g, R* Q,
         mm3(Qp, Q, Q);
     }
 }
-// Sums over the group in two levels: inclusive scans within each quad of
-// lanes (quad permutations; a lane with no source in its quad reads itself
-// and adds it times 0, so nothing crosses into another sample's lanes),
-// then one quad's total added to the other quad (a row shift by four
-// lanes restricted to the receiving quad).
-constexpr int quad_sel(int a, int b, int c, int d) { return a | (b << 2) | (c << 4) | (d << 6); }
+// Inclusive prefix and suffix sums over the group (Hillis-Steele: three
+// shift-and-add rounds, lanes past the ends adding 0)
 template <int N, typename R, class G> MPPI_HD void prefix_sum(const G& g, R* x)
 {
-    const int q = g.j & 3;
-    const R m1 = q >= 1 ? R(1) : R(0), m2 = q >= 2 ? R(1) : R(0);
 #pragma unroll
-    for (int a = 0; a < N; ++a) x[a] = fma_(g.template qperm<quad_sel(0, 0, 1, 2)>(x[a]), m1, x[a]);
+    for (int a = 0; a < N; ++a) x[a] = g.template add_shr<1>(x[a]);
 #pragma unroll
-    for (int a = 0; a < N; ++a) x[a] = fma_(g.template qperm<quad_sel(0, 1, 0, 1)>(x[a]), m2, x[a]);
+    for (int a = 0; a < N; ++a) x[a] = g.template add_shr<2>(x[a]);
 #pragma unroll
-    for (int a = 0; a < N; ++a) x[a] += g.lo_to_hi(g.template qperm<quad_sel(3, 3, 3, 3)>(x[a]));
+    for (int a = 0; a < N; ++a) x[a] = g.template add_shr<4>(x[a]);
 }
 template <int N, typename R, class G> MPPI_HD void suffix_sum(const G& g, R* x)
 {
-    const int q = g.j & 3;
-    const R m1 = q <= 2 ? R(1) : R(0), m2 = q <= 1 ? R(1) : R(0);
 #pragma unroll
-    for (int a = 0; a < N; ++a) x[a] = fma_(g.template qperm<quad_sel(1, 2, 3, 3)>(x[a]), m1, x[a]);
+    for (int a = 0; a < N; ++a) x[a] = g.template add_shl<1>(x[a]);
 #pragma unroll
-    for (int a = 0; a < N; ++a) x[a] = fma_(g.template qperm<quad_sel(2, 3, 2, 3)>(x[a]), m2, x[a]);
+    for (int a = 0; a < N; ++a) x[a] = g.template add_shl<2>(x[a]);
 #pragma unroll
-    for (int a = 0; a < N; ++a) x[a] += g.hi_to_lo(g.template qperm<quad_sel(0, 0, 0, 0)>(x[a]));
+    for (int a = 0; a < N; ++a) x[a] = g.template add_shl<4>(x[a]);
 }
 
 // EE pose of the group: lane j gets its link frame (lane 7: R_ee, p_ee)

@@ -330,42 +330,60 @@ constexpr int kGroupThreads = 128 * kGroupPairs;
 constexpr int kGroupSteps = 32;   // steps per chunk of the partial's row sums (regenerated noise)
 constexpr int kGroupTile = kGroupSamples + 1;   // row stride of the workgroup's du tile
 
+// Lane layout of a wave's eight groups: a row of 16 lanes holds two
+// samples interleaved, joint j of sample s in lane 2 j + (s & 1) + 16 (s >> 1),
+// so that a row shift by 2 D lanes moves every joint's value D joints along
+// its own sample, and lanes with no source (the first or last D joints) read
+// 0 from the shift itself.
+__device__ __forceinline__ int group_joint(int lane) { return (lane >> 1) & 7; }
+__device__ __forceinline__ int group_sample(int lane) { return (lane & 1) | ((lane >> 4) << 1); }
+
 struct DevGroup {
     int j;
     float* shm;
+    // joint j - D's value (0 for j < D)
     template <int D> __device__ float shr(float x) const
     {
-        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x110 + D, 0xF, 0xF, true));
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x110 + 2 * D, 0xF, 0xF, true));
     }
-    template <int S> __device__ float qperm(float x) const
+    // x plus joint j - D's value (j < D: plus 0), one DPP add
+    template <int D> __device__ float add_shr(float x) const { return x + shr<D>(x); }
+    // x plus joint j + D's value (j + D > 7: plus 0), one DPP add
+    template <int D> __device__ float add_shl(float x) const
     {
-        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), S, 0xF, 0xF, true));
+        return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x100 + 2 * D, 0xF, 0xF, true));
     }
-    // banks (quads) 1 and 3 of each row of 16 lanes take the quad before them
-    __device__ float lo_to_hi(float x) const
-    {
-        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x114, 0xF, 0xA, false));
-    }
-    // banks 0 and 2 take the quad after them
-    __device__ float hi_to_lo(float x) const
-    {
-        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x104, 0xF, 0x5, false));
-    }
-    // lane K of the group: broadcast within each quad, then the other
-    // half-group (banks of four lanes) takes it across with a row shift
+    // joint K's value: within every bank of four lanes (joints 2 m, 2 m + 1
+    // of both samples) the lanes of joint 2 m + (K & 1) spread over the
+    // bank, then bank K / 2 is copied into the other three by two masked
+    // row shifts
     template <int K> __device__ float bcast(float x) const
     {
-        constexpr int q = K & 3;
-        int t = __builtin_amdgcn_mov_dpp(__float_as_int(x), q | (q << 2) | (q << 4) | (q << 6), 0xF, 0xF, true);
-        if (K < 4) t = __builtin_amdgcn_update_dpp(t, t, 0x114, 0xF, 0xA, false);
-        else t = __builtin_amdgcn_update_dpp(t, t, 0x104, 0xF, 0x5, false);
+        constexpr int h = 2 * (K & 1);
+        int t = __builtin_amdgcn_mov_dpp(__float_as_int(x), h | ((h + 1) << 2) | (h << 4) | ((h + 1) << 6), 0xF, 0xF,
+                                         true);
+        constexpr int b = K >> 1;
+        if (b == 0) {
+            t = __builtin_amdgcn_update_dpp(t, t, 0x114, 0xF, 0x2, false);   // bank 1 <- 0
+            t = __builtin_amdgcn_update_dpp(t, t, 0x118, 0xF, 0xC, false);   // banks 2, 3 <- 0, 1
+        } else if (b == 1) {
+            t = __builtin_amdgcn_update_dpp(t, t, 0x104, 0xF, 0x1, false);   // bank 0 <- 1
+            t = __builtin_amdgcn_update_dpp(t, t, 0x118, 0xF, 0xC, false);   // banks 2, 3 <- 0, 1
+        } else if (b == 2) {
+            t = __builtin_amdgcn_update_dpp(t, t, 0x114, 0xF, 0x8, false);   // bank 3 <- 2
+            t = __builtin_amdgcn_update_dpp(t, t, 0x108, 0xF, 0x3, false);   // banks 0, 1 <- 2, 3
+        } else {
+            t = __builtin_amdgcn_update_dpp(t, t, 0x104, 0xF, 0x4, false);   // bank 2 <- 3
+            t = __builtin_amdgcn_update_dpp(t, t, 0x108, 0xF, 0x3, false);   // banks 0, 1 <- 2, 3
+        }
         return __int_as_float(t);
     }
+    // over the group: joints j ^ 1, ^ 2, ^ 4 are lanes ^ 2, ^ 4, ^ 8
     __device__ float sum(float x) const
     {
-        x += __shfl_xor(x, 1);
         x += __shfl_xor(x, 2);
         x += __shfl_xor(x, 4);
+        x += __shfl_xor(x, 8);
         return x;
     }
     __device__ void sync() const { wave_sync(); }
@@ -389,7 +407,7 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool dyn = wave < kGroupPairs;   // waves 0.. P-1: dynamics, P.. 2P-1: cost
     const int pw = dyn ? wave : wave - kGroupPairs;
-    const int j = lane & 7, grp = pw * 8 + (lane >> 3), jc = j < NJ ? j : NJ - 1;
+    const int j = group_joint(lane), grp = pw * 8 + group_sample(lane), jc = j < NJ ? j : NJ - 1;
     const int k = blockIdx.x * kGroupSamples + grp;
     const bool valid = k < K;
     // set-up from global memory (the cost constants from Cp directly, so that
@@ -510,11 +528,12 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
                 for (int tt = 0; tt < nt; ++tt) {
                     const int t = t0 + tt;
                     dr = group_noise_step(C, L, group_normal<float>(seed, tick, (uint32_t)k, (uint32_t)t, j), dr, t);
+                    // over the wave's 8 samples (lane bits 0, 4, 5)
                     A x = wgt * A(dr);
-                    x += __shfl_xor(x, 8);
+                    x += __shfl_xor(x, 1);
                     x += __shfl_xor(x, 16);
                     x += __shfl_xor(x, 32);
-                    if (lane < 8) vs[pw][tt * 8 + lane] = x;
+                    if ((lane & 0x31) == 0) vs[pw][tt * 8 + j] = x;
                 }
             }
             __syncthreads();
@@ -798,11 +817,12 @@ __device__ void group_tile_partial(const float* sS, A* wsm, A (*vs)[kGroupSteps 
         for (int tt = 0; tt < nt; ++tt) {
             const int t = t0 + tt;
             dr = group_noise_step(C, L, group_normal<float>(seed, tick, k, (uint32_t)t, j), dr, t);
+            // over the wave's 8 samples (lane bits 0, 4, 5)
             A x = wgt * A(dr);
-            x += __shfl_xor(x, 8);
+            x += __shfl_xor(x, 1);
             x += __shfl_xor(x, 16);
             x += __shfl_xor(x, 32);
-            if (lane < 8) vs[wave][tt * 8 + lane] = x;
+            if ((lane & 0x31) == 0) vs[wave][tt * 8 + j] = x;
         }
         __syncthreads();
         for (int r = tid; r < nt * NJ; r += 64 * kBatchGroupWaves) {
@@ -839,7 +859,7 @@ __global__ __launch_bounds__(64 * kBatchGroupWaves) void batch_group_kernel(
     __shared__ double vs[kBatchGroupWaves][kGroupSteps * 8];
     __shared__ int sItem, sDone;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int j = lane & 7, grp = wave * 8 + (lane >> 3);   // sample grp of the tile
+    const int j = group_joint(lane), grp = wave * 8 + group_sample(lane);   // sample grp of the tile
     const uint32_t tick = (uint32_t)(*tickp * (uint64_t)niter + (uint64_t)iter);
     for (;;) {
         if (tid == 0) sItem = (int)atomicAdd(queue, 1u);

@@ -209,29 +209,14 @@ template <typename R> struct HostGroup {
         s->barrier();
         return r;
     }
-    template <int S> R qperm(R x) const
+    template <int D> R add_shr(R x) const { return x + shr<D>(x); }
+    template <int D> R add_shl(R x) const
     {
         s->slot[j] = double(x);
         s->barrier();
-        const R r = R(s->slot[(j & ~3) + ((S >> (2 * (j & 3))) & 3)]);
+        const R r = j + D < kGroup ? R(s->slot[j + D]) : R(0);
         s->barrier();
-        return r;
-    }
-    R lo_to_hi(R x) const
-    {
-        s->slot[j] = double(x);
-        s->barrier();
-        const R r = j >= 4 ? R(s->slot[j - 4]) : R(0);
-        s->barrier();
-        return r;
-    }
-    R hi_to_lo(R x) const
-    {
-        s->slot[j] = double(x);
-        s->barrier();
-        const R r = j < 4 ? R(s->slot[j + 4]) : R(0);
-        s->barrier();
-        return r;
+        return x + r;
     }
     template <int K> R bcast(R x) const
     {
