@@ -44,7 +44,8 @@
 //                lanes; the group sums its lanes once, after the horizon.
 //
 // The code is written per lane against a group object G that provides the
-// cross-lane moves (shr<D>: value of lane j - D, 0 for j < D; add_shr<D> /
+// cross-lane moves (shr<D>: value of lane j - D, 0 for j < D; shr_one<D>:
+// the same with 1 for j < D; add_shr<D> /
 // add_shl<D>: x plus the value of lane j - D / j + D, plus 0 where there
 // is none; bcast<K>: of lane K), sum (over the group), sync() (orders the
 // group's LDS area) and shm (that area, kGxCount values).  On the device G
@@ -123,20 +124,20 @@ template <typename R> MPPI_HD R group_noise_step(const CostM<R>& C, const GroupL
 // scans over the group
 // ---------------------------------------------------------------------------
 // inclusive prefix composition of (Q, t) (child frame in the parent frame):
-// (Qa, ta) o (Qb, tb) = (Qa Qb, Qa tb + ta), earlier joints on the left
+// (Qa, ta) o (Qb, tb) = (Qa Qb, Qa tb + ta), earlier joints on the left;
+// lanes j < D compose with the identity (I, 0) that the shift leaves them
 template <int D, typename R, class G> MPPI_HD void scan_frames(const G& g, R* Q, R* t)
 {
     R Qp[9], tp[3];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) Qp[a] = g.template shr<D>(Q[a]);
+    for (int a = 0; a < 9; ++a)
+        Qp[a] = (a % 4 == 0) ? g.template shr_one<D>(Q[a]) : g.template shr<D>(Q[a]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) tp[a] = g.template shr<D>(t[a]);
-    if (g.j >= D) {
-        R nt[3];
-        mv3(Qp, t, nt);
-        t[0] = nt[0] + tp[0]; t[1] = nt[1] + tp[1]; t[2] = nt[2] + tp[2];
-        mm3(Qp, Q, Q);
-    }
+    R nt[3];
+    mv3(Qp, t, nt);
+    t[0] = nt[0] + tp[0]; t[1] = nt[1] + tp[1]; t[2] = nt[2] + tp[2];
+    mm3(Qp, Q, Q);
 }
 // Inclusive prefix and suffix sums over the group (Hillis-Steele: three
 // shift-and-add rounds, lanes past the ends adding 0)

@@ -346,6 +346,12 @@ struct DevGroup {
     {
         return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x110 + 2 * D, 0xF, 0xF, true));
     }
+    // joint j - D's value (1 for j < D: the shift leaves the old value)
+    template <int D> __device__ float shr_one(float x) const
+    {
+        return __int_as_float(
+            __builtin_amdgcn_update_dpp(__float_as_int(1.0f), __float_as_int(x), 0x110 + 2 * D, 0xF, 0xF, false));
+    }
     // x plus joint j - D's value (j < D: plus 0), one DPP add
     template <int D> __device__ float add_shr(float x) const { return x + shr<D>(x); }
     // x plus joint j + D's value (j + D > 7: plus 0), one DPP add

@@ -209,6 +209,14 @@ template <typename R> struct HostGroup {
         s->barrier();
         return r;
     }
+    template <int D> R shr_one(R x) const
+    {
+        s->slot[j] = double(x);
+        s->barrier();
+        const R r = j >= D ? R(s->slot[j - D]) : R(1);
+        s->barrier();
+        return r;
+    }
     template <int D> R add_shr(R x) const { return x + shr<D>(x); }
     template <int D> R add_shl(R x) const
     {
