@@ -65,7 +65,9 @@ constexpr int kGroup = 8;
 constexpr int kGxS = 16;                   // slot: S_j (6), Ic_j S_j (6), 4 unused
 constexpr int kGxSF = 0;                   // [8][kGxS]
 constexpr int kGxRow = kGxSF + 8 * kGxS;   // [8][9]: M row j, tau - h, tau_F
-constexpr int kGxOm = kGxRow + 8 * 9;      // [8][8]: lane j's column of the force solve's triangular factor
+constexpr int kGxOm = kGxRow + 8 * 9;      // [8][8]: the LDL^T factor of M (row i: L below the diagonal,
+                                           // 1 / d_i on it), then lane j's column of the force solve's
+                                           // triangular factor
 constexpr int kGxH = kGxOm + 8 * 8;        // [8][12]: handoff to the cost part: q, qd, v, p_j, h_c, m_c
                                            // (lanes 0..6); lane 7: p_ee, R_ee
 constexpr int kGxCount = kGxH + 8 * 12;    // 424
@@ -263,7 +265,7 @@ template <typename R> MPPI_HD void group_factor(const R* X, GroupFactor<R>& f, R
 // dynamics chain; otherwise group_cost forms it from the handoff.  The
 // update kernel chooses FDYN when the cost part also carries the collision
 // pairs, so that neither part runs both.
-template <typename R, bool FORCE, class G, bool FDYN = false>
+template <typename R, bool FORCE, class G, bool FDYN = false, bool HANDOFF = false>
 MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, const R* grav, int ext, R q, R qd,
                          R tau, R v, R* X, GroupFactor<R>* fac, R* p, R* Q)
 {
@@ -421,6 +423,20 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
     GroupFactor<R>& F = fac ? *fac : local;
     R b0[NJ], x[NJ];
     group_factor(X, F, b0);
+    if (FORCE && HANDOFF && j == 0) {
+        // for the cost part that follows on the same lanes (HANDOFF): row
+        // i of L below the diagonal and 1 / d_i on it, in the kGxOm rows,
+        // so that it does not factorise M again (one lane writes; the
+        // other lanes have read M).  A cost part on another wave
+        // factorises M itself: there the writes would lengthen the
+        // dynamics chain, which sets the step.
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) {
+#pragma unroll
+            for (int c = 0; c < i; ++c) X[kGxOm + i * 8 + c] = F.Lm[i][c];
+            X[kGxOm + i * 8 + i] = F.id[i];
+        }
+    }
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
         R s = b0[i];
@@ -442,14 +458,15 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
 }
 
 // Cost part of one step: the force estimate of Eq. 13 (FORCE) from the
-// rows and Jacobian rows left in X by group_dynamics (factorised again
-// when fac is null) and this lane's running cost at (x_t, v_t): pose and
+// factor of M (fac; when null, the one group_dynamics left in X with
+// HANDOFF, else M's rows in X factorised again) and the Jacobian rows left
+// in X, and this lane's running cost at (x_t, v_t): pose and
 // force terms in lane 7 (pee, Re: its EE pose), joint-limit and torque
 // terms in lanes 0..6, and with COLL the collision term of Eqs. 14-15 with
 // the pairs dealt over the lanes (pair i to lane i mod 8; link segments
 // from the joint origins and the EE point in the handoff).  Uses the kGxOm
 // part of X.
-template <typename R, bool FORCE, bool COLL, class G, bool FDYN = false>
+template <typename R, bool FORCE, bool COLL, class G, bool FDYN = false, bool HANDOFF = false>
 MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg, const R* grav,
                      R* X, const GroupFactor<R>* fac, R q, R qd, R v, const R* pee, const R* Re,
                      R* Fout = nullptr)
@@ -504,7 +521,17 @@ MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
         for (int i = 0; i < NJ; ++i) Jr[i] = X[kGxSF + i * kGxS + r];
         g.sync();
         GroupFactor<R> local;
-        if (!fac) group_factor(X, local, (R*)nullptr);
+        if (!fac && HANDOFF) {
+            // the factor that group_dynamics left in the kGxOm rows
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) {
+#pragma unroll
+                for (int c = 0; c < i; ++c) local.Lm[i][c] = X[kGxOm + i * 8 + c];
+                local.id[i] = X[kGxOm + i * 8 + i];
+            }
+        } else if (!fac) {
+            group_factor(X, local, (R*)nullptr);
+        }
         const GroupFactor<R>& Fc = fac ? *fac : local;
         R bF[NJ];
 #pragma unroll
@@ -593,7 +620,9 @@ MPPI_HD R group_terminal(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
 // returns the sample's total cost S_k in every lane.  Us: [T][7] nominal
 // torques; te: this lane's joint-space external torque (constant mode);
 // noise_out, noise_lds (either may be null): du[t][j] of this lane's joint
-// at (7 t + j) * stride (lanes 0..6).
+// at (7 t + j) * stride (lanes 0..6).  split: each step as its dynamics
+// part and then its cost part (group_dynamics, group_cost with the factor
+// of M handed over in the group area) instead of group_step.
 template <typename R, bool FORCE, class G, typename UT, bool COLL = false>
 MPPI_HD R group_rollout(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg,
                         const R* grav, R q, R qd, R te, const UT* Us, int T, uint64_t seed, uint32_t tick,
@@ -612,11 +641,12 @@ MPPI_HD R group_rollout(const G& g, const GroupLink<R>& L, const CostM<R>& C, co
         const R v = (R(Us[t * NJ + jc]) + du) * L.live;
         R qdd;
         if (split) {
-            // as a dynamics wave and a cost wave share the step: the cost part
-            // factorises the gathered rows again
+            // the dynamics and cost parts in sequence, the factor of M
+            // handed over through the group area instead of held in
+            // registers across the cost part
             R p[3], Q[9];
-            qdd = group_dynamics<R, FORCE, G, COLL>(g, L, C, grav, ext, q, qd, v + te, v, g.shm, nullptr, p, Q);
-            S += group_cost<R, FORCE, COLL, G, COLL>(g, L, C, tg, grav, g.shm, nullptr, q, qd, v, p, Q);
+            qdd = group_dynamics<R, FORCE, G, COLL, true>(g, L, C, grav, ext, q, qd, v + te, v, g.shm, nullptr, p, Q);
+            S += group_cost<R, FORCE, COLL, G, COLL, true>(g, L, C, tg, grav, g.shm, nullptr, q, qd, v, p, Q);
         } else {
             S += group_step<R, FORCE, G, COLL>(g, L, C, tg, grav, ext, q, qd, v + te, v, qdd);
         }

@@ -354,8 +354,9 @@ extern "C" double hc_group_rollout(const mppi_robot_params* rp, const mppi_cost_
     return group_rollout_t<float>(rp, cp, target, q0, qd0, U, seed, tick, k, noise);
 }
 
-// The same rollout with each step split as between a dynamics wave and a
-// cost wave (the cost part factorises the gathered rows again).
+// The same rollout with each step split into its dynamics and cost parts,
+// as the eight-lane batch kernel runs it (the factor of M handed over
+// through the group area).
 extern "C" double hc_group_rollout_split(const mppi_robot_params* rp, const mppi_cost_params* cp, int prec,
                                          const double* target, const double* q0, const double* qd0,
                                          const double* U, uint64_t seed, uint64_t tick, uint32_t k, double* noise)

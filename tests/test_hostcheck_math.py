@@ -333,9 +333,9 @@ def test_group_step_matches_oracle(hc, ora, workloads, prec, tol):
 def test_group_rollout_cost_matches_oracle(hc, ora, workloads, which, prec, tol, split):
     """Whole rollouts on the lane group: every lane ends with the same total
     (the host function returns NaN otherwise), equal to the oracle's S_k;
-    the noise of every joint equals the oracle's.  split: each step as a
-    dynamics wave and a cost wave run it (the cost part factorises the
-    gathered rows again)."""
+    the noise of every joint equals the oracle's.  split: each step as its
+    dynamics part and then its cost part, the factor of M handed over in
+    the group area (the eight-lane batch kernel's path)."""
     fn = hc.hc_group_rollout_split if split else hc.hc_group_rollout
     for case in workloads[which][:3]:
         rp = B.robot_params(case["robot"])
