@@ -317,7 +317,9 @@ __global__ __launch_bounds__(128) void update_split_kernel(
 // sample) and a cost wave, which draws the perturbations one step ahead and
 // evaluates the force estimate of Eq. 13 and the running cost one step
 // behind from what the dynamics wave leaves in LDS (double-buffered group
-// areas, one barrier per step).  A workgroup holds kGroupPairs such pairs
+// areas, one barrier per step); in the last step, while the cost wave
+// evaluates step T - 1, the dynamics wave evaluates the terminal cost of
+// x_T.  A workgroup holds kGroupPairs such pairs
 // (8 kGroupPairs samples, one wave per SIMD); K = 4096 gives 1024 waves.
 // After the horizon the workgroup forms its Eq. 4 partial (wave.hpp
 // convention) from the du tile in LDS (or from regenerated noise when the
@@ -410,6 +412,7 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
     __shared__ float sS[kGroupSamples];
     __shared__ A vs[kGroupPairs][kGroupSteps * 8];
     __shared__ A wsm[kGroupSamples];
+    __shared__ float tS[kGroupSamples][8];   // the terminal cost's lane shares
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool dyn = wave < kGroupPairs;   // waves 0.. P-1: dynamics, P.. 2P-1: cost
     const int pw = dyn ? wave : wave - kGroupPairs;
@@ -423,6 +426,7 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
     group_link(M, *Cp, j, L);
     const float grav[3] = {M.g[0], M.g[1], M.g[2]};
     TargetM<float> tg;
+    make_target(target, tg);   // the cost wave's running cost, the dynamics wave's terminal cost
     float q = 0.0f, qd = 0.0f, te = 0.0f;
     if (dyn) {
         float qa[NJ], qda[NJ], tea[NJ];
@@ -432,8 +436,6 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
 #pragma unroll
         for (int i = 0; i < NJ; ++i)
             if (i == j) { q = qa[i]; qd = qda[i]; te = tea[i]; }
-    } else {
-        make_target(target, tg);
     }
     if (wave == 0) wave_copy(&Csh, Cp, sizeof(CostM<float>), lane);
     for (int i = tid; i < T * NJ; i += blockDim.x) Us[i] = float(U_nom[i]);
@@ -465,6 +467,11 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
                                                                                nullptr, p, Q);
                 qd += qdd * C.dt;
                 q += qd * C.dt;
+            } else {
+                // phi(x_T) (lane 7: q = qd = 0), while the cost wave
+                // evaluates step T - 1
+                const DevGroup g{j, gx[s & 1][grp]};
+                tS[grp][j] = group_terminal(g, L, C, tg, q, qd);
             }
         } else {
             if (s + 1 < T) draw(s + 1);
@@ -483,17 +490,10 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
         }
         __syncthreads();
     }
-    // terminal cost phi(x_T) on the cost wave, from the final state
-    if (dyn) {
-        float* h = gx[T & 1][grp] + kGxH + j * 12;
-        h[0] = q;
-        h[1] = qd;
-    }
-    __syncthreads();
+    // the terminal cost from the dynamics wave (ordered by the last barrier)
     if (!dyn) {
-        const float* h = gx[T & 1][grp] + kGxH + j * 12;
         const DevGroup g{j, gx[T & 1][grp]};
-        Sl += group_terminal(g, L, C, tg, j < NJ ? h[0] : 0.0f, j < NJ ? h[1] : 0.0f);
+        Sl += tS[grp][j];
         const float tot = g.sum(Sl);
         float sv = INFINITY;
         if (valid) {
