@@ -785,29 +785,30 @@ template <typename R> MPPI_HD R clamp01_(R x) { return x < R(0) ? R(0) : (x > R(
 // Squared minimum distance between segments [a0, a1] and [b0, b1] (the
 // closest-point construction of Lumelsky's method): the line-line optimum
 // s clamped to [0, 1] (0 for parallel lines), t optimal for that s, and if
-// t leaves [0, 1] it is clamped and s re-optimised for it.
+// t leaves [0, 1] it is clamped and s re-optimised for it.  Every candidate
+// is formed and the case picked by selects, with one reciprocal per
+// denominator (the lanes of a wave take different cases; branches would
+// run them one after another).
 template <typename R> MPPI_HD R seg_dist2(const R* a0, const R* a1, const R* b0, const R* b1)
 {
     R da[3], db[3], r[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) { da[c] = a1[c] - a0[c]; db[c] = b1[c] - b0[c]; r[c] = a0[c] - b0[c]; }
     const R A = dot3(da, da), B = dot3(da, db), E = dot3(db, db), Cr = dot3(da, r), F = dot3(db, r);
-    R s, t;
-    if (E <= R(0)) {            // b is a point
-        t = R(0);
-        s = A > R(0) ? clamp01_(-Cr / A) : R(0);
-    } else {
-        const R den = A * E - B * B;
-        s = den > R(0) ? clamp01_((B * F - Cr * E) / den) : R(0);
-        t = (B * s + F) / E;
-        if (t < R(0)) {
-            t = R(0);
-            s = A > R(0) ? clamp01_(-Cr / A) : R(0);
-        } else if (t > R(1)) {
-            t = R(1);
-            s = A > R(0) ? clamp01_((B - Cr) / A) : R(0);
-        }
-    }
+    const R den = A * E - B * B;
+    // 1 / A, 1 / E, 1 / den, or 0 where the denominator vanishes (a point
+    // segment, parallel lines): the candidates that divide by it become 0
+    const R rA = A > R(0) ? rcp_(A) : R(0);
+    const R rE = E > R(0) ? rcp_(E) : R(0);
+    const R rD = den > R(0) ? rcp_(den) : R(0);
+    const R s_lo = clamp01_(-Cr * rA);        // s re-optimised for t = 0
+    const R s_hi = clamp01_((B - Cr) * rA);   // for t = 1
+    const R s_in = clamp01_((B * F - Cr * E) * rD);
+    const R t_in = (B * s_in + F) * rE;
+    const bool pt = !(E > R(0));              // b is a point: t = 0
+    const bool lo = pt || t_in < R(0), hi = !pt && t_in > R(1);
+    const R t = lo ? R(0) : (hi ? R(1) : t_in);
+    const R s = lo ? s_lo : (hi ? s_hi : s_in);
     R e[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) e[c] = r[c] + s * da[c] - t * db[c];
