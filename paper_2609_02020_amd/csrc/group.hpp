@@ -403,8 +403,17 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
 #pragma unroll
     for (int c = 0; c < NJ; ++c) X[kGxRow + j * 9 + c] = row[c];
     X[kGxRow + j * 9 + 7] = tau - hq;
+    g.sync();
+
+    // ---- Eq. 6: qdd = L^-T D^-1 L^-1 (tau + tau_ext - h)
+    GroupFactor<R> local;
+    GroupFactor<R>& F = fac ? *fac : local;
+    R b0[NJ], x[NJ];
+    group_factor(X, F, b0);
     // handoff to the cost part: pre-step q, qd, v, the joint origin and the
-    // subtree's mass and first moment (lanes 0..6), the EE pose (lane 7)
+    // subtree's mass and first moment (lanes 0..6), the EE pose (lane 7);
+    // written once the rows are read, so that the row reads do not queue
+    // behind these writes
     R* h = X + kGxH + j * 12;
     if (ee) {
 #pragma unroll
@@ -416,13 +425,6 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
         h[3] = p[0]; h[4] = p[1]; h[5] = p[2];
         if (FORCE && !FDYN) { h[6] = In[0]; h[7] = In[1]; h[8] = In[2]; h[9] = In[3]; }
     }
-    g.sync();
-
-    // ---- Eq. 6: qdd = L^-T D^-1 L^-1 (tau + tau_ext - h)
-    GroupFactor<R> local;
-    GroupFactor<R>& F = fac ? *fac : local;
-    R b0[NJ], x[NJ];
-    group_factor(X, F, b0);
     if (FORCE && HANDOFF && j == 0) {
         // for the cost part that follows on the same lanes (HANDOFF): row
         // i of L below the diagonal and 1 / d_i on it, in the kGxOm rows,
@@ -489,6 +491,7 @@ MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
             }
         };
         R hits = R(0);
+        g.sync();   // the other lanes' handoff (written at the end of the dynamics part)
         for (int i = j; i < C.n_pairs; i += kGroup) {
             R a0[3], a1[3], b0[3], b1[3];
             ends(C.pa[i], a0, a1);
