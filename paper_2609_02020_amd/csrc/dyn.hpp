@@ -120,6 +120,15 @@ MPPI_HD float rsqrt_sqrt_(float x)
 #endif
 }
 MPPI_HD double rsqrt_sqrt_(double x) { return std::sqrt(x); }
+// keeps the instruction scheduler from moving code across this point (on
+// the device; nothing on the host): placed after a batch of LDS or memory
+// reads, it keeps the batch issued together ahead of its uses
+MPPI_HD void sched_fence()
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+}
 MPPI_HD float max0_(float x) { return std::fmax(x, 0.0f); }
 MPPI_HD double max0_(double x) { return std::fmax(x, 0.0); }
 

@@ -62,7 +62,7 @@ namespace mppi {
 
 constexpr int kGroup = 8;
 // group LDS area (values of the rollout type)
-constexpr int kGxS = 16;                   // slot: S_j (6), Ic_j S_j (6), 4 unused
+constexpr int kGxS = 16;                   // slot: S_j (6), 10 unused
 constexpr int kGxSF = 0;                   // [8][kGxS]
 constexpr int kGxRow = kGxSF + 8 * kGxS;   // [8][9]: M row j, tau - h, tau_F
 constexpr int kGxOm = kGxRow + 8 * 9;      // [8][8]: the LDL^T factor of M (row i: L below the diagonal,
@@ -174,24 +174,51 @@ template <typename R, class G> MPPI_HD void group_fk(const G& g, const GroupLink
     scan_frames<4>(g, Q, p);
 }
 
-// pose terms of Eqs. 9-11 from the EE frame (R_ee = R_n R_ee,fixed)
-template <typename R> MPPI_HD R pose_cost(const CostM<R>& C, const TargetM<R>& tg, const R* pee, const R* Re)
+// The cost weights that the group's running and terminal costs read at
+// every step, held in registers: read once with the other reads of a
+// step, where reads from the cost copy in LDS inside the EE lane's branch
+// would each wait for their own round trip.
+template <typename R> struct GroupCostW {
+    R W_pos[3], W_ori[3], W_force[6], W_reg[6];
+    R w_q, w_qd, w_post, w_tau;
+    int has_ori;
+};
+template <typename R> MPPI_HD void group_cost_w(const CostM<R>& C, GroupCostW<R>& w)
 {
-    R s = C.W_pos[0] * sq(tg.p_des[0] - pee[0]) + C.W_pos[1] * sq(tg.p_des[1] - pee[1]) +
-          C.W_pos[2] * sq(tg.p_des[2] - pee[2]);
-    if (C.has_ori) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { w.W_pos[a] = C.W_pos[a]; w.W_ori[a] = C.W_ori[a]; }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) { w.W_force[a] = C.W_force[a]; w.W_reg[a] = C.W_reg[a]; }
+    w.w_q = C.w_q; w.w_qd = C.w_qd; w.w_post = C.w_post; w.w_tau = C.w_tau;
+    w.has_ori = C.has_ori;
+}
+
+// pose terms of Eqs. 9-11 from the EE frame (R_ee = R_n R_ee,fixed)
+template <typename R> MPPI_HD R pose_cost(const GroupCostW<R>& W, const TargetM<R>& tg, const R* pee, const R* Re)
+{
+    R s = W.W_pos[0] * sq(tg.p_des[0] - pee[0]) + W.W_pos[1] * sq(tg.p_des[1] - pee[1]) +
+          W.W_pos[2] * sq(tg.p_des[2] - pee[2]);
+    if (W.has_ori) {
         R Rerr[9], rho[3];
         mm3(tg.RdT, Re, Rerr);
         so3_log(Rerr, rho);
-        s += C.W_ori[0] * rho[0] * rho[0] + C.W_ori[1] * rho[1] * rho[1] + C.W_ori[2] * rho[2] * rho[2];
+        s += W.W_ori[0] * rho[0] * rho[0] + W.W_ori[1] * rho[1] * rho[1] + W.W_ori[2] * rho[2] * rho[2];
     }
     return s;
 }
 // this lane's joint-limit, velocity-limit and posture terms (Eq. 14 C_joint)
-template <typename R> MPPI_HD R joint_cost1(const CostM<R>& C, const GroupLink<R>& L, R q, R qd)
+template <typename R> MPPI_HD R joint_cost1(const GroupCostW<R>& W, const GroupLink<R>& L, R q, R qd)
 {
-    return C.w_q * (sq(hinge(q - L.qmax)) + sq(hinge(L.qmin - q))) + C.w_qd * sq(hinge(abs_(qd) - L.qdmax)) +
-           C.w_post * sq(q - L.qrest);
+    return W.w_q * (sq(hinge(q - L.qmax)) + sq(hinge(L.qmin - q))) + W.w_qd * sq(hinge(abs_(qd) - L.qdmax)) +
+           W.w_post * sq(q - L.qrest);
+}
+// force terms of Eq. 12 (the arithmetic of force_cost)
+template <typename R> MPPI_HD R group_force_cost(const GroupCostW<R>& W, const TargetM<R>& tg, const R* F)
+{
+    R s = R(0);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) s += W.W_force[a] * sq(tg.F_des[a] - F[a]) + W.W_reg[a] * F[a] * F[a];
+    return s;
 }
 
 // One modified Gram-Schmidt step of lsq_wrench on the group: column S of
@@ -367,12 +394,10 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
         inertia_mul(In, Sv, Fm);
     }
 
-    // ---- gather S and Ic S
+    // ---- gather S (Ic S stays in this lane)
     R* slot = X + kGxSF + j * kGxS;
 #pragma unroll
     for (int a = 0; a < 3; ++a) { slot[a] = z[a]; slot[3 + a] = pz[a]; }
-#pragma unroll
-    for (int a = 0; a < 6; ++a) slot[6 + a] = Fm[a];
     if (FORCE && FDYN) {
         // tau_F (less the gravity torque S . Ic (0, -g) when force_mode is 0)
         R tf = v;
@@ -385,14 +410,20 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
         X[kGxRow + j * 9 + 8] = ee ? R(0) : tf;
     }
     g.sync();
-    // row j of M: M_jc = S_min(j,c) . (Ic S)_max(j,c), plus the armature
-    R row[NJ];
+    // row j of M up to the diagonal: M_jc = S_c . (Ic S)_j (c <= j), plus
+    // the armature; every lane reads the slots at the same offsets and
+    // multiplies by its own Ic S.  Above the diagonal the same products
+    // are not M (nothing reads that part of the rows).
+    R Sc[NJ][6], row[NJ];
+#pragma unroll
+    for (int c = 0; c < NJ; ++c)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) Sc[c][a] = X[kGxSF + c * kGxS + a];
+    sched_fence();   // the 42 reads in one round trip
 #pragma unroll
     for (int c = 0; c < NJ; ++c) {
-        const int lo = j < c ? j : c, hi = j < c ? c : j;
-        const R* Sa = X + kGxSF + lo * kGxS;
-        const R* Fb = X + kGxSF + hi * kGxS + 6;
-        R s = Sa[0] * Fb[0] + Sa[1] * Fb[1] + Sa[2] * Fb[2] + Sa[3] * Fb[3] + Sa[4] * Fb[4] + Sa[5] * Fb[5];
+        const R* S = Sc[c];
+        R s = S[0] * Fm[0] + S[1] * Fm[1] + S[2] * Fm[2] + S[3] * Fm[3] + S[4] * Fm[4] + S[5] * Fm[5];
         row[c] = s + (c == j ? L.arm : R(0));
     }
     // the EE lane's slot holds no motion subspace: its rows are 0
@@ -475,6 +506,12 @@ MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
 {
     const int j = g.j;
     const bool ee = j == kGroup - 1;
+    GroupCostW<R> W;
+    group_cost_w(C, W);
+    R sj[6];   // this lane's motion subspace (the gravity torque of tau_F)
+#pragma unroll
+    for (int a = 0; a < 6; ++a) sj[a] = X[kGxSF + j * kGxS + a];
+    sched_fence();   // with the handoff reads: one round trip
     R ell = R(0);
     if (COLL) {
         // segment id s: link s from P[s] to P[s + 1] (P[7] = EE point), or
@@ -504,15 +541,14 @@ MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
         // tau_F of this lane's joint: v, less the gravity torque
         // S . Ic (0, -g) of the subtree when force_mode is 0
         if (!FDYN) {
-            const R* sj = X + kGxSF + j * kGxS;
+            // the gravity torque is formed whatever force_mode says, so that
+            // its reads join the step's first batch instead of a branch
             const R* hj = X + kGxH + j * 12;
-            R tf = v;
-            if (C.force_mode == 0) {
-                const R ag[3] = {-grav[0], -grav[1], -grav[2]};
-                R ha[3];
-                cross3(hj + 6, ag, ha);
-                tf = v - (dot3(sj, ha) + hj[9] * dot3(sj + 3, ag));
-            }
+            const R ag[3] = {-grav[0], -grav[1], -grav[2]};
+            R ha[3];
+            cross3(hj + 6, ag, ha);
+            const R tg0 = v - (dot3(sj, ha) + hj[9] * dot3(sj + 3, ag));
+            const R tf = C.force_mode == 0 ? tg0 : v;
             X[kGxRow + j * 9 + 8] = ee ? R(0) : tf;
         }
         // row r of the EE Jacobian about p_ee at joint i: z_i (r < 3), then
@@ -565,24 +601,32 @@ MPPI_HD R group_cost(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
 #pragma unroll
         for (int s = 0; s < 6; ++s) X[kGxOm + j * 8 + s] = Rc[s];
         g.sync();
-        // x = Rm^-1 Q^T y in every lane: (moment, force) about p_ee
-        R bb[6];
+        // x = Rm^-1 Q^T y in every lane: (moment, force) about p_ee; the
+        // triangle and Q^T y are read in one round trip
+        R Rm[6][6], qy[6], bb[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            qy[s] = X[kGxOm + 6 * 8 + s];
+#pragma unroll
+            for (int c = s + 1; c < 6; ++c) Rm[c][s] = X[kGxOm + c * 8 + s];
+        }
+        sched_fence();
 #pragma unroll
         for (int s = 5; s >= 0; --s) {
-            R t = X[kGxOm + 6 * 8 + s];
+            R t = qy[s];
 #pragma unroll
-            for (int c = s + 1; c < 6; ++c) t = fma_(-X[kGxOm + c * 8 + s], bb[c], t);
+            for (int c = s + 1; c < 6; ++c) t = fma_(-Rm[c][s], bb[c], t);
             bb[s] = t * idg[s];
         }
         const R F[6] = {bb[3], bb[4], bb[5], bb[0], bb[1], bb[2]};
-        if (ee) ell += force_cost(C, tg, F);
+        if (ee) ell += group_force_cost(W, tg, F);
         if (Fout) {
 #pragma unroll
             for (int a = 0; a < 6; ++a) Fout[a] = F[a];
         }
     }
-    if (ee) ell += pose_cost(C, tg, pee, Re);
-    else ell += joint_cost1(C, L, q, qd) + C.w_tau * sq(hinge(abs_(v) - L.taumax));
+    if (ee) ell += pose_cost(W, tg, pee, Re);
+    else ell += joint_cost1(W, L, q, qd) + W.w_tau * sq(hinge(abs_(v) - L.taumax));
     return ell;
 }
 
@@ -613,9 +657,11 @@ MPPI_HD R group_step(const G& g, const GroupLink<R>& L, const CostM<R>& C, const
 template <typename R, class G>
 MPPI_HD R group_terminal(const G& g, const GroupLink<R>& L, const CostM<R>& C, const TargetM<R>& tg, R q, R qd)
 {
+    GroupCostW<R> W;
+    group_cost_w(C, W);
     R Q[9], p[3];
     group_fk(g, L, q, Q, p);
-    const R s = g.j == kGroup - 1 ? pose_cost(C, tg, p, Q) : joint_cost1(C, L, q, qd);
+    const R s = g.j == kGroup - 1 ? pose_cost(W, tg, p, Q) : joint_cost1(W, L, q, qd);
     return C.w_T * s;
 }
 

@@ -571,13 +571,16 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
 // [np][2], then the row sums [np][7T]): workgroup b writes rows
 // [kMergeRows b, kMergeRows (b + 1)) of U_new.  Thread (slice, row) takes
 // the partials slice, slice + kMergeSlices, ... in batches whose loads are
-// issued together (one memory round trip per batch); a batch is reduced
-// against its own minimum (all its exponentials independent) and folded
-// into the running (m, s, V) by the log-sum-exp rule of wave.hpp (a new
-// minimum rescales what it has).  The slices of a row are then combined
-// through LDS the same way: their minimum first, then the rescaled sums.
-// Every row's slices cover all partials, so each row has the full
-// normaliser.
+// issued together (one memory round trip per batch, with this row of U_nom
+// in the same trip); a batch is reduced against its own minimum (all its
+// exponentials independent) and folded into the running (m, s, V) by the
+// log-sum-exp rule of wave.hpp (a new minimum rescales what it has).  The
+// slices of a row are then combined through LDS the same way: their minimum
+// first, then the rescaled sums.  Every row's slices cover all partials, so
+// each row has the full normaliser.  Empty entries (a non-finite minimum,
+// or a slot past np, which reads partial 0) enter every step with weight
+// zero rather than through a branch: a branch lets the compiler defer the
+// loads of such entries past the first wait.
 constexpr int kMergeRows = 16;
 constexpr int kMergeSlices = kGroupThreads / kMergeRows;
 template <typename A>
@@ -589,53 +592,59 @@ __global__ __launch_bounds__(kGroupThreads) void group_merge_kernel(const A* __r
     __shared__ A shm[kGroupThreads], shs[kGroupThreads], shv[kGroupThreads];
     const int tid = threadIdx.x, rl = tid % kMergeRows, sl = tid / kMergeRows;
     const int rows = T * NJ;
-    const A* vparts = parts + (size_t)np * 2;   // [np][rows] after the (m, s) pairs
     const int r = blockIdx.x * kMergeRows + rl;
     const bool act = r < rows;
     const int rr = act ? r : 0;
+    const A* vrow = parts + (size_t)np * 2 + rr;   // [np][rows] after the (m, s) pairs
+    const double un0 = U_nom[rr];
     const A inf = A(INFINITY), il = A(1) / A(lambda);
     A m = inf, sw = A(0), acc = A(0);
-    // fold (mp, sp, vp) into (m, sw, acc)
+    // fold (mp, sp, vp) into (m, sw, acc): a lower finite minimum rescales
+    // what is held (by 0 while m is still +inf); an empty entry adds 0
     auto fold = [&](A mp, A sp, A vp) {
-        if (!(mp < inf)) return;
-        if (mp < m) {
-            const A f = exp((mp - m) * il);   // 0 while m is still +inf
-            sw *= f;
-            acc *= f;
-            m = mp;
-        }
-        const A f = exp((m - mp) * il);
+        const bool ok = mp < inf, lower = ok && mp < m;
+        const A fr = lower ? A(exp((mp - m) * il)) : A(1);
+        sw *= fr;
+        acc *= fr;
+        m = lower ? mp : m;
+        const A f = ok ? A(exp((m - mp) * il)) : A(0);
         sw += f * sp;
         acc += f * vp;
     };
     // (m, s, V) of NB entries: their minimum, then the sums rescaled to it
-    // (non-finite minima mark empty entries and contribute nothing)
     auto reduce = [&](const A* mv, const A* sv, const A* vv, int NB_, A& mb, A& sb, A& vb) {
         mb = inf;
         for (int u = 0; u < NB_; ++u) mb = mv[u] < mb ? mv[u] : mb;
         sb = A(0);
         vb = A(0);
-        if (!(mb < inf)) return;
         for (int u = 0; u < NB_; ++u) {
             const A f = mv[u] < inf ? A(exp((mb - mv[u]) * il)) : A(0);
             sb += f * sv[u];
             vb += f * vv[u];
         }
     };
+    // the first batch runs on every thread (a slice past np holds only
+    // empty entries), so the kernel arguments are all read up front
     constexpr int NB = 16;
-    for (int p0 = sl; p0 < np; p0 += NB * kMergeSlices) {
+    int p0 = sl;
+    do {
         A mv[NB], sv[NB], vv[NB];
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int p = p0 + u * kMergeSlices, pc = p < np ? p : 0;
-            mv[u] = p < np ? parts[2 * pc] : inf;
+            const A mp = parts[2 * pc];
+            mv[u] = p < np ? mp : inf;
             sv[u] = parts[2 * pc + 1];
-            vv[u] = vparts[(size_t)pc * rows + rr];
+            vv[u] = vrow[pc * rows];
         }
+        // keep the batch's loads ahead of its first use (the scheduler
+        // otherwise spreads them over the reduction, one wait each)
+        __builtin_amdgcn_sched_barrier(0);
         A mb, sb, vb;
         reduce(mv, sv, vv, NB, mb, sb, vb);
         fold(mb, sb, vb);
-    }
+        p0 += NB * kMergeSlices;
+    } while (p0 < np);
     shm[tid] = m;
     shs[tid] = sw;
     shv[tid] = acc;
@@ -652,7 +661,7 @@ __global__ __launch_bounds__(kGroupThreads) void group_merge_kernel(const A* __r
         reduce(mq, sq, vq, kMergeSlices, m, sw, acc);
     }
     const int t = r / NJ, jj = r % NJ;
-    const double un = m < inf ? U_nom[r] + double(acc / sw) : U_nom[r];
+    const double un = m < inf ? un0 + double(acc / sw) : un0;
     U_new[r] = un;
     if (U_shift) {
         if (t >= 1) U_shift[(t - 1) * NJ + jj] = un;
