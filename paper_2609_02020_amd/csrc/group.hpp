@@ -298,6 +298,16 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
 {
     const int j = g.j;
     const bool ee = j == kGroup - 1;
+    // the wall's constants, read ahead of the chain that uses them
+    R wn[3], wd0 = R(0), wk = R(0), wc = R(0);
+    if (ext == EXTW_WALL) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) wn[a] = C.wall_n[a];
+        wd0 = C.wall_d0;
+        wk = C.wall_k;
+        wc = C.wall_c;
+    }
+    sched_fence();
 
     // ---- kinematics: link frames (lane 7: the EE frame)
     group_fk(g, L, q, Q, p);
@@ -375,11 +385,11 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
         // unilateral spring-damper at the EE point (lane 7's frame origin,
         // the reference point O: the EE point velocity is V's linear part
         // and the wall force has no moment about O)
-        const R delta = C.wall_d0 - dot3(C.wall_n, p);
-        const R ddelta = -dot3(C.wall_n, V + 3);
-        const R mag = hinge(C.wall_k * delta + C.wall_c * ddelta);
+        const R delta = wd0 - dot3(wn, p);
+        const R ddelta = -dot3(wn, V + 3);
+        const R mag = hinge(wk * delta + wc * ddelta);
         if (ee) {
-            f[3] -= C.wall_n[0] * mag; f[4] -= C.wall_n[1] * mag; f[5] -= C.wall_n[2] * mag;
+            f[3] -= wn[0] * mag; f[4] -= wn[1] * mag; f[5] -= wn[2] * mag;
         }
     }
 
@@ -681,6 +691,7 @@ MPPI_HD R group_rollout(const G& g, const GroupLink<R>& L, const CostM<R>& C, co
     const int j = g.j;
     const int jc = j < NJ ? j : NJ - 1;
     const int ext = C.ext_mode == EXTW_WALL ? EXTW_WALL : EXTW_NONE;
+    const R dt = C.dt;
     R du = R(0), S = R(0);
     for (int t = 0; t < T; ++t) {
         const R z = group_normal<R>(seed, tick, k, (uint32_t)t, j);
@@ -699,8 +710,8 @@ MPPI_HD R group_rollout(const G& g, const GroupLink<R>& L, const CostM<R>& C, co
         } else {
             S += group_step<R, FORCE, G, COLL>(g, L, C, tg, grav, ext, q, qd, v + te, v, qdd);
         }
-        qd += qdd * C.dt;
-        q += qd * C.dt;
+        qd += qdd * dt;
+        q += qd * dt;
     }
     S += group_terminal(g, L, C, tg, q, qd);
     return g.sum(S);

@@ -455,6 +455,7 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
     };
     // step 0's draw needs only this lane's sigma (not the LDS cost copy)
     if (!dyn) draw(0);
+    const float dt = Cp->dt;   // in a register: the step's last operation reads it
     __syncthreads();
     for (int s = 0; s <= T; ++s) {
         if (dyn) {
@@ -465,8 +466,8 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
                 float p[3], Q[9];
                 const float qdd = group_dynamics<float, FORCE, DevGroup, COLL>(g, L, C, grav, ext, q, qd, v + te, v, X,
                                                                                nullptr, p, Q);
-                qd += qdd * C.dt;
-                q += qd * C.dt;
+                qd += qdd * dt;
+                q += qd * dt;
             } else {
                 // phi(x_T) (lane 7: q = qd = 0), while the cost wave
                 // evaluates step T - 1
