@@ -466,20 +466,6 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
         h[3] = p[0]; h[4] = p[1]; h[5] = p[2];
         if (FORCE && !FDYN) { h[6] = In[0]; h[7] = In[1]; h[8] = In[2]; h[9] = In[3]; }
     }
-    if (FORCE && HANDOFF && j == 0) {
-        // for the cost part that follows on the same lanes (HANDOFF): row
-        // i of L below the diagonal and 1 / d_i on it, in the kGxOm rows,
-        // so that it does not factorise M again (one lane writes; the
-        // other lanes have read M).  A cost part on another wave
-        // factorises M itself: there the writes would lengthen the
-        // dynamics chain, which sets the step.
-#pragma unroll
-        for (int i = 0; i < NJ; ++i) {
-#pragma unroll
-            for (int c = 0; c < i; ++c) X[kGxOm + i * 8 + c] = F.Lm[i][c];
-            X[kGxOm + i * 8 + i] = F.id[i];
-        }
-    }
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
         R s = b0[i];
@@ -493,6 +479,19 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
 #pragma unroll
         for (int c = i + 1; c < NJ; ++c) s = fma_(-F.Lm[c][i], x[c], s);
         x[i] = s;
+    }
+    if (FORCE && HANDOFF && j == 0) {
+        // for the cost part (HANDOFF): row i of L below the diagonal and
+        // 1 / d_i on it, in the kGxOm rows, so that it does not factorise
+        // M again (one lane writes; the other lanes have read M).  Written
+        // after the solve: written before it, the last write waits for the
+        // last reciprocal and holds up the solve behind it.
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) {
+#pragma unroll
+            for (int c = 0; c < i; ++c) X[kGxOm + i * 8 + c] = F.Lm[i][c];
+            X[kGxOm + i * 8 + i] = F.id[i];
+        }
     }
     R qj = R(0);
 #pragma unroll

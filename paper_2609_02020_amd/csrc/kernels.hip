@@ -316,8 +316,9 @@ __global__ __launch_bounds__(128) void update_split_kernel(
 // the LDL^T solve of Eq. 6 and the Euler step: the sequential chain of a
 // sample) and a cost wave, which draws the perturbations one step ahead and
 // evaluates the force estimate of Eq. 13 and the running cost one step
-// behind from what the dynamics wave leaves in LDS (double-buffered group
-// areas, one barrier per step); in the last step, while the cost wave
+// behind from what the dynamics wave leaves in LDS, the LDL^T factor of M
+// included (double-buffered group areas, one barrier per step); in the
+// last step, while the cost wave
 // evaluates step T - 1, the dynamics wave evaluates the terminal cost of
 // x_T.  A workgroup holds kGroupPairs such pairs
 // (8 kGroupPairs samples, one wave per SIMD); K = 4096 gives 1024 waves.
@@ -464,7 +465,7 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
                 const DevGroup g{j, X};
                 const float v = (Us[s * NJ + jc] + nb[s & 1][grp][j]) * L.live;
                 float p[3], Q[9];
-                const float qdd = group_dynamics<float, FORCE, DevGroup, COLL>(g, L, C, grav, ext, q, qd, v + te, v, X,
+                const float qdd = group_dynamics<float, FORCE, DevGroup, COLL, true>(g, L, C, grav, ext, q, qd, v + te, v, X,
                                                                                nullptr, p, Q);
                 qd += qdd * dt;
                 q += qd * dt;
@@ -485,7 +486,7 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
                 for (int a = 0; a < 3; ++a) pe[a] = h[a];
 #pragma unroll
                 for (int a = 0; a < 9; ++a) Re[a] = h[3 + a];
-                Sl += group_cost<float, FORCE, COLL, DevGroup, COLL>(g, L, C, tg, grav, X, nullptr, h[0], h[1], h[2], pe,
+                Sl += group_cost<float, FORCE, COLL, DevGroup, COLL, true>(g, L, C, tg, grav, X, nullptr, h[0], h[1], h[2], pe,
                                                                      Re);
             }
         }
