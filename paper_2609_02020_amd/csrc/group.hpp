@@ -483,9 +483,7 @@ MPPI_HD R group_dynamics(const G& g, const GroupLink<R>& L, const CostM<R>& C, c
     if (FORCE && HANDOFF && j == 0) {
         // for the cost part (HANDOFF): row i of L below the diagonal and
         // 1 / d_i on it, in the kGxOm rows, so that it does not factorise
-        // M again (one lane writes; the other lanes have read M).  Written
-        // after the solve: written before it, the last write waits for the
-        // last reciprocal and holds up the solve behind it.
+        // M again (one lane writes; the other lanes have read M)
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
 #pragma unroll
