@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kRolloutBlock) void update_kernel(
     // adding them to the scalar stream.
     __shared__ CostM<R> Csh;
     const int lane = threadIdx.x & 63;
-    wave_copy(&Csh, Cp, sizeof(CostM<R>), lane);
+    wave_copy(&Csh, Cp, lane);
     for (int i = threadIdx.x; i < T * NJ; i += blockDim.x) Us[i] = R(U_nom[i]);
     __syncthreads();
     const ModelM<R>& M = *Mp;
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(128) void update_split_kernel(
     __shared__ int last;
     __shared__ CostM<float> Csh;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (wave == 0) wave_copy(&Csh, Cp, sizeof(CostM<float>), lane);
+    if (wave == 0) wave_copy(&Csh, Cp, lane);
     for (int i = threadIdx.x; i < T * NJ; i += blockDim.x) Us[i] = float(U_nom[i]);
     const int k = blockIdx.x * 64 + lane;
     float* tile = reinterpret_cast<float*>(dyn_lds);   // [rows][65] (noise) or [64][65] (regeneration)
@@ -387,13 +387,18 @@ struct DevGroup {
         }
         return __int_as_float(t);
     }
-    // over the group: joints j ^ 1, ^ 2, ^ 4 are lanes ^ 2, ^ 4, ^ 8
+    // over the group: joints j ^ 1, ^ 2, ^ 4 are lanes ^ 2, ^ 4, ^ 8, each
+    // reached by DPP within the row (a quad permutation, then pairs of
+    // bank-masked row shifts by 4 and by 8)
     __device__ float sum(float x) const
     {
-        x += __shfl_xor(x, 2);
-        x += __shfl_xor(x, 4);
-        x += __shfl_xor(x, 8);
-        return x;
+        x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x4E, 0xF, 0xF, true));   // [2,3,0,1]
+        int t = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x104, 0xF, 0x5, false);   // banks 0, 2 <- +4
+        t = __builtin_amdgcn_update_dpp(t, __float_as_int(x), 0x114, 0xF, 0xA, false);       // banks 1, 3 <- -4
+        x += __int_as_float(t);
+        t = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x108, 0xF, 0x3, false);       // banks 0, 1 <- +8
+        t = __builtin_amdgcn_update_dpp(t, __float_as_int(x), 0x118, 0xF, 0xC, false);       // banks 2, 3 <- -8
+        return x + __int_as_float(t);
     }
     __device__ void sync() const { wave_sync(); }
 };
@@ -438,7 +443,7 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
         for (int i = 0; i < NJ; ++i)
             if (i == j) { q = qa[i]; qd = qda[i]; te = tea[i]; }
     }
-    if (wave == 0) wave_copy(&Csh, Cp, sizeof(CostM<float>), lane);
+    if (wave == 0) wave_copy(&Csh, Cp, lane);
     for (int i = tid; i < T * NJ; i += blockDim.x) Us[i] = float(U_nom[i]);
     const CostM<float>& C = Csh;
     float* tile = reinterpret_cast<float*>(dyn_lds);
@@ -728,7 +733,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(COLL ? 1
         const BatchProblem& Pb = probs[it.x];
         const int T = Pb.T, K = Pb.K;
         wave_sync();
-        wave_copy(&Csh[wid], Pb.cost, sizeof(CostM<float>), lane);
+        wave_copy(&Csh[wid], Pb.cost, lane);
         for (int i = lane; i < T * NJ; i += 64) Us[wid][i] = float(U_nom[Pb.u_off + i]);
         wave_sync();
         // problem p's model is models[p] (== *Pb.model); read through the
@@ -886,7 +891,7 @@ __global__ __launch_bounds__(64 * kBatchGroupWaves) void batch_group_kernel(
         const int2 it = items[item];
         const BatchProblem& Pb = probs[it.x];
         const int T = Pb.T, K = Pb.K;
-        if (wave == 0) wave_copy(&Csh, Pb.cost, sizeof(CostM<float>), lane);
+        if (wave == 0) wave_copy(&Csh, Pb.cost, lane);
         for (int i = tid; i < T * NJ; i += 64 * kBatchGroupWaves) Us[i] = float(U_nom[Pb.u_off + i]);
         __syncthreads();
         // problem p's model through the restrict-qualified argument at a
@@ -1196,8 +1201,8 @@ __device__ void select_two(const ModelM<R>& Mg, const CostM<R>& Cg, const double
                            ModelM<R>& Msh, CostM<R>& Csh, R* Us, R* sc)
 {
     const int lane = threadIdx.x & 63;
-    wave_copy(&Msh, &Mg, sizeof(ModelM<R>), lane);
-    wave_copy(&Csh, &Cg, sizeof(CostM<R>), lane);
+    wave_copy(&Msh, &Mg, lane);
+    wave_copy(&Csh, &Cg, lane);
     for (int i = lane; i < T * NJ; i += 64) {
         Us[i] = R(U_nom[i]);
         Us[kMaxT * NJ + i] = R(U_cand[i]);

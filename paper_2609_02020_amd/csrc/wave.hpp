@@ -43,11 +43,21 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // copies `bytes` (a multiple of 4) from global memory to LDS with one wave
-__device__ __forceinline__ void wave_copy(void* dst, const void* src, int bytes, int lane)
+// Copies an object of T by the 64 lanes of a wave, every load issued before
+// the first store (one memory round trip, where a loop of load-store pairs
+// waits for each load in turn).
+template <typename T> __device__ __forceinline__ void wave_copy(T* dst, const T* src, int lane)
 {
+    static_assert(sizeof(T) % 4 == 0, "copied as 32-bit words");
+    constexpr int W = sizeof(T) / 4, N = (W + 63) / 64;
     const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
     uint32_t* d = reinterpret_cast<uint32_t*>(dst);
-    for (int i = lane; i < bytes / 4; i += 64) d[i] = s[i];
+    uint32_t v[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] = (lane + 64 * n < W) ? s[lane + 64 * n] : 0u;
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+        if (lane + 64 * n < W) d[lane + 64 * n] = v[n];
 }
 
 // Per-wave partial.  s_lane: this lane's cost (+inf if invalid or
