@@ -588,6 +588,11 @@ __global__ __launch_bounds__(kGroupThreads) void update_group_kernel(
 // or a slot past np, which reads partial 0) enter every step with weight
 // zero rather than through a branch: a branch lets the compiler defer the
 // loads of such entries past the first wait.
+// e^x for the merge's shifted exponents (x <= 0): in FP32 the hardware
+// base-2 exponential of x log2(e) (about 1 ulp, plus |x| ulp from the
+// scaling, which only the negligible weights reach), libm in FP64
+__device__ __forceinline__ float merge_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504f); }
+__device__ __forceinline__ double merge_exp(double x) { return exp(x); }
 constexpr int kMergeRows = 16;
 constexpr int kMergeSlices = kGroupThreads / kMergeRows;
 template <typename A>
@@ -610,11 +615,11 @@ __global__ __launch_bounds__(kGroupThreads) void group_merge_kernel(const A* __r
     // what is held (by 0 while m is still +inf); an empty entry adds 0
     auto fold = [&](A mp, A sp, A vp) {
         const bool ok = mp < inf, lower = ok && mp < m;
-        const A fr = lower ? A(exp((mp - m) * il)) : A(1);
+        const A fr = lower ? merge_exp((mp - m) * il) : A(1);
         sw *= fr;
         acc *= fr;
         m = lower ? mp : m;
-        const A f = ok ? A(exp((m - mp) * il)) : A(0);
+        const A f = ok ? merge_exp((m - mp) * il) : A(0);
         sw += f * sp;
         acc += f * vp;
     };
@@ -625,7 +630,7 @@ __global__ __launch_bounds__(kGroupThreads) void group_merge_kernel(const A* __r
         sb = A(0);
         vb = A(0);
         for (int u = 0; u < NB_; ++u) {
-            const A f = mv[u] < inf ? A(exp((mb - mv[u]) * il)) : A(0);
+            const A f = mv[u] < inf ? merge_exp((mb - mv[u]) * il) : A(0);
             sb += f * sv[u];
             vb += f * vv[u];
         }
@@ -639,14 +644,16 @@ __global__ __launch_bounds__(kGroupThreads) void group_merge_kernel(const A* __r
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int p = p0 + u * kMergeSlices, pc = p < np ? p : 0;
-            const A mp = parts[2 * pc];
-            mv[u] = p < np ? mp : inf;
+            mv[u] = parts[2 * pc];
             sv[u] = parts[2 * pc + 1];
             vv[u] = vrow[pc * rows];
         }
-        // keep the batch's loads ahead of its first use (the scheduler
-        // otherwise spreads them over the reduction, one wait each)
+        // keep the batch's loads ahead of their first use (the scheduler
+        // otherwise spreads them over the reduction, one wait each); slots
+        // past np are marked empty only after it
         __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < NB; ++u) mv[u] = p0 + u * kMergeSlices < np ? mv[u] : inf;
         A mb, sb, vb;
         reduce(mv, sv, vv, NB, mb, sb, vb);
         fold(mb, sb, vb);
