@@ -55,16 +55,16 @@ FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32 (AMD published)
 # known size (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 on gfx950), taken on the
 # kernel sources whose digest is recorded here; reported as null once the
 # sources differ.
-PROFILED_DIGEST = "72930a56a6bf7105"
-PROFILED_TRAFFIC = {"update_group_kernel": 340437 + 159744 + 514371 + 1956,   # K=4096, T=18 contact workload:
+PROFILED_DIGEST = "9389df91679e6d76"
+PROFILED_TRAFFIC = {"update_group_kernel": 340034 + 159744 + 476486 + 1956,   # K=4096, T=18 contact workload:
                                                             # the group kernel and its merge launch
                     # 64-problem batch, per launch shape the autotuner may pick (waves per
                     # group x groups); the one-lane shapes mostly register-spill stores
-                    "batch_kernel_w1x2048": 99393272 + 324103168,
-                    "batch_kernel_w2x1024": 119262534 + 367537067,
-                    "batch_kernel_w4x512": 106344769 + 335760640,
-                    "batch_kernel_w8x256": 5997895 + 9581673,    # eight lanes per sample
-                    "mlp_train": 5863884 + 1737728 + 4833913 + 678432}   # forward/backward + weight
+                    "batch_kernel_w1x2048": 106361459 + 324806144,
+                    "batch_kernel_w2x1024": 118716882 + 352157440,
+                    "batch_kernel_w4x512": 104396139 + 333902592,
+                    "batch_kernel_w8x256": 5992043 + 10652006,    # eight lanes per sample
+                    "mlp_train": 5863884 + 1737728 + 4833908 + 678432}   # forward/backward + weight
                                                                           # gradients, 512 rows
 
 
